@@ -1,0 +1,122 @@
+/*
+ * oracle.h -- plain FP64 CPU oracle for the r-z implicit PIC/MCC step with
+ * equivalent-capacitance circuit coupling (arXiv 2310.04957, Sec. 2).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the
+ * benchmark's CPU-baseline leg load this library.  It shares no source with
+ * the HIP path; both consume the same plain-data configuration and seeded
+ * inputs.  Everything here is written for a reader to check against the
+ * paper by eye: no blocking, no fusion, single-threaded, FP64 throughout
+ * (the deposit is an exact integer definition).
+ *
+ * Readings of passages the paper leaves open are marked [Rn] in the sources;
+ * the list is kept with the design notes of the repository.
+ *
+ * Parity unpinned: conformance of Philox4x32-10 to the published
+ * known-answer vectors (not available); the 4x64 instantiation of the same
+ * round structure is pinned to numpy's Philox instead.
+ */
+#ifndef PIC_ORACLE_H
+#define PIC_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_MAX_REGIONS 32
+#define ORC_NCNT 4 /* absorption counter slots: 0 ground, 1 powered, 2 lost (Neumann edge), 3 dielectric */
+
+typedef struct {
+    double r0, r1, z0, z1;
+    int32_t kind;    /* 0 vacuum, 1 dielectric, 2 conductor */
+    int32_t cond_id; /* 0 ground, 1 RF-driven electrode */
+    double eps_r;
+} orc_region;
+
+typedef struct {
+    /* geometry: cells nr x nz on [0,R] x [0,Z] */
+    int32_t nr, nz;
+    double R, Z;
+    int32_t n_regions;
+    int32_t edge_bc[3]; /* r=R, z=0, z=Z: conductor id, or -1 Neumann */
+    orc_region regions[ORC_MAX_REGIONS];
+    /* circuit: 0 ideal source on the electrode, 1 series R_b L_b C_b (Eq. 9),
+       2 L-type matching network with stray branch (Eq. 10) */
+    int32_t circ_kind, substeps;
+    double freq, U_amp, U_dc, R_s, C_m1, C_m2, L_m, R_m, C_stray, L_stray, R_stray, C_b, R_b, L_b;
+    /* background argon */
+    double p_Pa, T_gas_K;
+    /* particles and run */
+    int64_t n_e, n_i, cap_e, cap_i;
+    double n0, Te_eV, Ti_eV;
+    int32_t steps_per_period, sort_every;
+    uint64_t seed;
+    double tol;
+    int32_t max_iter;
+    int32_t load; /* 1: Maxwellian uniform load at creation, 0: no particles */
+} orc_config;
+
+typedef struct {
+    double t, U_E, Q_E, C_eq, Q_P, I_ccp, dt, w_unit, n_gas;
+    double circ[5];
+    double nu_max[2];
+    uint32_t thresh[2];
+    int64_t step, periods_done;
+    int64_t n_slots[2], n_alive[2];
+    int64_t absorbed[2][ORC_NCNT];
+    int64_t born, coll[2][4], numax_violations;
+    int64_t solver_iters;
+    double solver_relres;
+    double harm_U_re[6], harm_U_im[6], harm_I_re[6], harm_I_im[6];
+} orc_diag;
+
+typedef struct orc_sim orc_sim;
+
+/* grid ids for orc_get_grid / orc_set_grid */
+enum {
+    ORC_G_DEP_E = 0, ORC_G_DEP_I = 1, /* int64 fixed-point node sums of the predicted positions */
+    ORC_G_PHI = 2, ORC_G_ER = 3, ORC_G_EZ = 4, ORC_G_CHI = 5,
+    ORC_G_WALLQ = 6,       /* int64 dielectric surface charge, signed */
+    ORC_G_NODE_KIND = 7,   /* int32: -1 unknown, >=0 conductor id */
+    ORC_G_CELL_KIND = 8,   /* int32: 0 vacuum, 1 dielectric, 2+id conductor */
+    ORC_G_VOL = 9, ORC_G_PHI_L = 10, ORC_G_Q = 11, ORC_G_AR = 12, ORC_G_AZ = 13,
+    ORC_G_NE_AVG = 14, ORC_G_NI_AVG = 15
+};
+
+int orc_create(const orc_config* cfg, orc_sim** out);
+void orc_destroy(orc_sim* s);
+int orc_step(orc_sim* s, int32_t nsteps);
+int orc_diag_get(orc_sim* s, orc_diag* d);
+int orc_series(orc_sim* s, int32_t last, double* U_out, double* I_out);
+
+/* particles as 9 field-major arrays of length n: r z vr vt vz ar at az w */
+int64_t orc_num_slots(orc_sim* s, int32_t species);
+int orc_get_particles(orc_sim* s, int32_t species, double* out9);
+int orc_set_particles(orc_sim* s, int32_t species, int64_t n, const double* in9);
+int orc_redeposit(orc_sim* s);
+int orc_get_grid(orc_sim* s, int32_t which, void* out);
+int orc_set_grid(orc_sim* s, int32_t which, const void* in);
+int orc_set_state(orc_sim* s, const double* st); /* t, Q_E, U_E, circ[5], C_eq */
+
+/* pure pieces, for pins */
+int orc_solve_q(orc_sim* s, const double* Q, const double* chi, double U_E, double tol,
+                double* phi_inout, int32_t* iters, double* relres);
+double orc_refresh_laplace(orc_sim* s); /* recompute phi_L and C_eq with the current chi */
+double orc_ceq_flux(orc_sim* s);         /* C_eq as the flux out of the electrode */
+int orc_deposit(orc_sim* s, int64_t n, const double* r, const double* z, const double* w, int64_t* grid);
+int orc_tile_keys(orc_sim* s, int64_t n, const double* r, const double* z, uint32_t* keys);
+int orc_stable_perm(int64_t n, const uint32_t* keys, int64_t* perm);
+int orc_predict(orc_sim* s, int64_t n, double* p9);
+int orc_correct(orc_sim* s, int32_t species, int64_t n, double* p9, const double* Er, const double* Ez);
+int orc_mcc(orc_sim* s, int32_t species, int64_t n, double* v3, uint32_t slot0, uint32_t step,
+            int32_t* proc, double* birth6);
+void orc_philox4x32(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+void orc_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
+void orc_xsec_e(double eps_eV, double out3[3]);
+int orc_circuit_vacuum(const orc_config* cfg, double C_eq, int64_t nsteps, double* U_out, double* I_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,586 @@
+/*
+ * orc_sim.c -- oracle (test infrastructure only): the external circuit
+ * (Eqs. 8-10) coupled by the equivalent capacitance (Eq. 5), the time step
+ * in the paper's order, sorting, diagnostics (Sec. 3: period-averaged
+ * densities, electrode voltage and current harmonics), and the C entry
+ * points used by the Python tests.
+ */
+#include "orc_internal.h"
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---------------------------------------------------------------- circuit */
+/* State y: L-match (Eq. 10) y0..y4 = Q1, Q2, I2, Q_ccp, I_stray;
+   series RLC (Eq. 9) y0, y1 = Q_b, I_b; y5 = Q_E, the electrode charge of
+   Eq. (8), dQ_E/dt = I_ccp + I_conv.  [R16] the electrode voltage is
+   U_E = (Q_E - Q_P)/C_eq, where Q_P = -sum phi_L Q is the charge the space
+   charge induces on the electrode (Green reciprocity); in vacuum this is
+   Eq. (5). */
+static void circ_rhs(const orc_config* c, double C_eq, double t, const double* y, double Q_P, double I_conv,
+                     double* dy) {
+    double U_E = (y[5] - Q_P) / C_eq;
+    double Us = c->U_amp * sin(2.0 * O_PI * c->freq * t) + c->U_dc;
+    for (int k = 0; k < 6; k++) dy[k] = 0.0;
+    if (c->circ_kind == 2) {
+        double Um1 = (y[0] - y[1]) / c->C_m1;
+        dy[0] = (Us - Um1) / c->R_s;
+        dy[1] = y[2];
+        dy[2] = (Um1 - U_E - y[1] / c->C_m2 - y[2] * c->R_m) / c->L_m;
+        dy[3] = y[2] - y[4];
+        dy[4] = (U_E - (y[1] - y[3]) / c->C_stray - y[4] * c->R_stray) / c->L_stray;
+        dy[5] = (y[2] - y[4]) + I_conv;
+    } else if (c->circ_kind == 1) {
+        dy[0] = y[1];
+        dy[1] = (Us - U_E - y[0] / c->C_b - y[1] * c->R_b) / c->L_b;
+        dy[5] = y[1] + I_conv;
+    }
+}
+
+/* [R17] classical RK4 with `substeps` substeps per PIC step; I_conv and Q_P
+   are held over the step.  Returns the step-averaged circuit current. */
+static double circ_integrate(const orc_config* c, double dt, double C_eq, double t0, double Q_P, double I_conv,
+                             double* y) {
+    int M = c->substeps > 0 ? c->substeps : 1;
+    double h = dt / M;
+    int qi = (c->circ_kind == 2) ? 3 : 0;
+    double q0 = y[qi];
+    for (int m = 0; m < M; m++) {
+        double t = t0 + m * h;
+        double k1[6], k2[6], k3[6], k4[6], yt[6];
+        circ_rhs(c, C_eq, t, y, Q_P, I_conv, k1);
+        for (int k = 0; k < 6; k++) yt[k] = y[k] + 0.5 * h * k1[k];
+        circ_rhs(c, C_eq, t + 0.5 * h, yt, Q_P, I_conv, k2);
+        for (int k = 0; k < 6; k++) yt[k] = y[k] + 0.5 * h * k2[k];
+        circ_rhs(c, C_eq, t + 0.5 * h, yt, Q_P, I_conv, k3);
+        for (int k = 0; k < 6; k++) yt[k] = y[k] + h * k3[k];
+        circ_rhs(c, C_eq, t + h, yt, Q_P, I_conv, k4);
+        for (int k = 0; k < 6; k++) y[k] += h / 6.0 * (k1[k] + 2.0 * k2[k] + 2.0 * k3[k] + k4[k]);
+    }
+    return (y[qi] - q0) / dt;
+}
+
+static double powered_count(const orc_sim* s) {
+    return (double)(s->sign[1] * s->cnt[1][1] + s->sign[0] * s->cnt[0][1]);
+}
+
+static double induced_charge(const orc_sim* s) {
+    double qp = 0.0;
+    for (int n = 0; n < s->nn; n++)
+        if (s->node_kind[n] < 0) qp -= s->phiL[n] * s->Q[n];
+    return qp;
+}
+
+void o_circuit_advance(orc_sim* s) {
+    double unit = O_QE * s->w_unit * ldexp(1.0, -O_KBITS);
+    double pc = powered_count(s);
+    double I_conv = (pc - (double)s->cnt_prev_pow) * unit / s->dt;
+    s->cnt_prev_pow = (int64_t)pc;
+    s->Q_P = induced_charge(s);
+    double t1 = s->t + s->dt;
+    const orc_config* c = &s->cfg;
+    if (c->circ_kind == 0) {
+        double U = c->U_amp * sin(2.0 * O_PI * c->freq * t1) + c->U_dc;
+        double QE = s->C_eq * U + s->Q_P;
+        s->I_ccp = (QE - s->Q_E) / s->dt - I_conv;
+        s->Q_E = QE;
+        s->U_E = U;
+    } else {
+        double y[6];
+        for (int k = 0; k < 5; k++) y[k] = s->circ[k];
+        y[5] = s->Q_E;
+        s->I_ccp = circ_integrate(c, s->dt, s->C_eq, s->t, s->Q_P, I_conv, y);
+        for (int k = 0; k < 5; k++) s->circ[k] = y[k];
+        s->Q_E = y[5];
+        s->U_E = (s->Q_E - s->Q_P) / s->C_eq;
+    }
+    s->t = t1;
+}
+
+int orc_circuit_vacuum(const orc_config* cfg, double C_eq, int64_t nsteps, double* U_out, double* I_out) {
+    double dt = 1.0 / (cfg->freq * cfg->steps_per_period);
+    double y[6] = {0, 0, 0, 0, 0, 0};
+    double t = 0.0;
+    for (int64_t n = 0; n < nsteps; n++) {
+        double I = circ_integrate(cfg, dt, C_eq, t, 0.0, 0.0, y);
+        t += dt;
+        U_out[n] = y[5] / C_eq;
+        I_out[n] = I;
+    }
+    return 0;
+}
+
+/* ---------------------------------------------------------------- helpers */
+static int parts_alloc(o_parts* P, int64_t cap) {
+    P->cap = cap;
+    P->n = 0;
+    double** f[9] = {&P->r, &P->z, &P->vr, &P->vt, &P->vz, &P->ar, &P->at, &P->az, &P->w};
+    for (int k = 0; k < 9; k++) {
+        *f[k] = calloc((size_t)(cap > 0 ? cap : 1), sizeof(double));
+        if (!*f[k]) return -1;
+    }
+    return 0;
+}
+
+static void parts_free(o_parts* P) {
+    free(P->r); free(P->z); free(P->vr); free(P->vt); free(P->vz);
+    free(P->ar); free(P->at); free(P->az); free(P->w);
+}
+
+static void get1(const o_parts* P, int64_t k, double* st) {
+    st[0] = P->r[k]; st[1] = P->z[k]; st[2] = P->vr[k]; st[3] = P->vt[k]; st[4] = P->vz[k];
+    st[5] = P->ar[k]; st[6] = P->at[k]; st[7] = P->az[k]; st[8] = P->w[k];
+}
+
+static void put1(o_parts* P, int64_t k, const double* st) {
+    P->r[k] = st[0]; P->z[k] = st[1]; P->vr[k] = st[2]; P->vt[k] = st[3]; P->vz[k] = st[4];
+    P->ar[k] = st[5]; P->at[k] = st[6]; P->az[k] = st[7]; P->w[k] = st[8];
+}
+
+static uint32_t tile_key(const orc_sim* s, double r, double z) {
+    if (r < 0.0) return 0xFFFFFFFFu;
+    o_loc L = o_locate(s, r, z);
+    if (!L.inside) return 0xFFFFFFFFu;
+    int ntr = (s->nr + (1 << O_TILE_SHIFT) - 1) >> O_TILE_SHIFT;
+    return (uint32_t)((L.j >> O_TILE_SHIFT) * ntr + (L.i >> O_TILE_SHIFT));
+}
+
+typedef struct { uint32_t key; int64_t idx; } kv;
+static int kv_cmp(const void* a, const void* b) {
+    const kv *x = a, *y = b;
+    if (x->key != y->key) return x->key < y->key ? -1 : 1;
+    return (x->idx > y->idx) - (x->idx < y->idx);
+}
+
+int orc_stable_perm(int64_t n, const uint32_t* keys, int64_t* perm) {
+    kv* a = malloc(sizeof(kv) * (size_t)(n > 0 ? n : 1));
+    for (int64_t k = 0; k < n; k++) { a[k].key = keys[k]; a[k].idx = k; }
+    qsort(a, (size_t)n, sizeof(kv), kv_cmp);
+    for (int64_t k = 0; k < n; k++) perm[k] = a[k].idx;
+    free(a);
+    return 0;
+}
+
+/* stable sort by tile key of the predicted position; dead slots dropped */
+static void sort_species(orc_sim* s, int sp) {
+    o_parts* P = &s->p[sp];
+    int64_t n = P->n;
+    uint32_t* keys = malloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
+    int64_t* perm = malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t k = 0; k < n; k++) keys[k] = tile_key(s, P->r[k], P->z[k]);
+    orc_stable_perm(n, keys, perm);
+    o_parts Q;
+    parts_alloc(&Q, P->cap);
+    int64_t m = 0;
+    double st[9];
+    for (int64_t k = 0; k < n; k++) {
+        if (keys[perm[k]] == 0xFFFFFFFFu) break;
+        get1(P, perm[k], st);
+        put1(&Q, m++, st);
+    }
+    Q.n = m;
+    parts_free(P);
+    *P = Q;
+    free(keys);
+    free(perm);
+}
+
+/* ------------------------------------------------------------------ step */
+typedef struct { double r, z, W, v[6]; } o_birth;
+
+static int particle_pass(orc_sim* s, int sp, o_birth** births, int64_t* nb, int64_t* capb, uint32_t step) {
+    o_parts* P = &s->p[sp];
+    double st[9];
+    for (int64_t k = 0; k < P->n; k++) {
+        if (P->r[k] < 0.0) continue;
+        get1(P, k, st);
+        double Er, Ez;
+        o_gather(s, st[0], st[1], &Er, &Ez);
+        o_correct1(s, sp, st, Er, Ez);
+        if (o_absorb_check(s, sp, st[0], st[1], st[8])) { P->r[k] = -1.0; continue; }
+        double v[3] = {st[2], st[3], st[4]}, b6[6];
+        int proc = o_mcc1(s, sp, v, (uint32_t)k, step, b6);
+        if (proc >= 0) s->coll[sp][proc]++;
+        st[2] = v[0]; st[3] = v[1]; st[4] = v[2];
+        if (proc == 2 && sp == 0) {
+            if (*nb == *capb) {
+                *capb = *capb * 2 + 16;
+                *births = realloc(*births, sizeof(o_birth) * (size_t)*capb);
+            }
+            o_birth* b = &(*births)[(*nb)++];
+            b->r = st[0]; b->z = st[1]; b->W = st[8];
+            memcpy(b->v, b6, sizeof(b6));
+        }
+        o_predict1(s, st);
+        if (o_absorb_check(s, sp, st[0], st[1], st[8])) { P->r[k] = -1.0; continue; }
+        put1(P, k, st);
+        o_deposit_one(s, st[0], st[1], st[8], s->dep[sp]);
+    }
+    return 0;
+}
+
+static int append_births(orc_sim* s, const o_birth* b, int64_t nb) {
+    if (s->p[0].n + nb > s->p[0].cap || s->p[1].n + nb > s->p[1].cap) return -2;
+    for (int64_t k = 0; k < nb; k++) {
+        for (int sp = 0; sp < 2; sp++) {
+            double st[9] = {b[k].r, b[k].z, b[k].v[3 * sp], b[k].v[3 * sp + 1], b[k].v[3 * sp + 2],
+                            0.0, 0.0, 0.0, b[k].W};
+            o_predict1(s, st);
+            o_parts* P = &s->p[sp];
+            int64_t slot = P->n++;
+            if (o_absorb_check(s, sp, st[0], st[1], st[8])) {
+                put1(P, slot, st);
+                P->r[slot] = -1.0;
+                continue;
+            }
+            put1(P, slot, st);
+            o_deposit_one(s, st[0], st[1], st[8], s->dep[sp]);
+        }
+        s->born++;
+    }
+    return 0;
+}
+
+/* One time step in the paper's order (Sec. 2): the susceptibility and the
+   predicted charge define Eq. (1); the electrode voltage comes from the
+   electrode charge and the equivalent capacitance (Eqs. 5, 8-10); the field
+   solve; then the particle loop (gather, implicit correction, absorption,
+   null-collision MCC, prediction and deposit of the next predicted
+   positions), births, the periodic sort and the once-per-period refresh of
+   the Laplace solution and C_eq. */
+static int step1(orc_sim* s) {
+    int spp = s->cfg.steps_per_period;
+    int k = (int)(s->step % spp);
+    o_assemble(s);
+    for (int sp = 0; sp < 2; sp++)
+        for (int n = 0; n < s->nn; n++) s->psum[sp][n] += s->dep[sp][n];
+    o_circuit_advance(s);
+    int it;
+    double rel;
+    int rc = o_solve(s, s->ar, s->az, s->Q, s->U_E, s->cfg.tol, s->phi, &it, &rel);
+    s->solver_iters = it;
+    s->solver_relres = rel;
+    if (rc) return rc;
+    o_efield(s);
+    s->serU[k] = s->U_E;
+    s->serI[k] = s->I_ccp;
+    for (int sp = 0; sp < 2; sp++) memset(s->dep[sp], 0, sizeof(int64_t) * s->nn);
+    uint32_t stepc = (uint32_t)(s->step + 1);
+    o_birth* births = NULL;
+    int64_t nb = 0, capb = 0;
+    particle_pass(s, 0, &births, &nb, &capb, stepc);
+    particle_pass(s, 1, &births, &nb, &capb, stepc);
+    rc = append_births(s, births, nb);
+    free(births);
+    if (rc) return rc;
+    s->step++;
+    if (s->cfg.sort_every > 0 && s->step % s->cfg.sort_every == 0) {
+        sort_species(s, 0);
+        sort_species(s, 1);
+    }
+    if (s->step % spp == 0) {
+        o_laplace(s);
+        memcpy(s->lastU, s->serU, sizeof(double) * spp);
+        memcpy(s->lastI, s->serI, sizeof(double) * spp);
+        for (int sp = 0; sp < 2; sp++) {
+            memcpy(s->plast[sp], s->psum[sp], sizeof(int64_t) * s->nn);
+            memset(s->psum[sp], 0, sizeof(int64_t) * s->nn);
+        }
+        s->periods_done++;
+        s->have_last = 1;
+    }
+    return 0;
+}
+
+int orc_step(orc_sim* s, int32_t nsteps) {
+    for (int32_t k = 0; k < nsteps; k++) {
+        int rc = step1(s);
+        if (rc) return rc;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------ create/free */
+int orc_create(const orc_config* cfg, orc_sim** out) {
+    if (cfg->nr < 2 || cfg->nz < 2 || cfg->R <= 0 || cfg->Z <= 0 || cfg->steps_per_period < 1 ||
+        cfg->n_regions < 0 || cfg->n_regions > ORC_MAX_REGIONS || cfg->freq <= 0)
+        return -1;
+    orc_sim* s = calloc(1, sizeof(orc_sim));
+    s->cfg = *cfg;
+    s->nr = cfg->nr;
+    s->nz = cfg->nz;
+    s->nn = (cfg->nr + 1) * (cfg->nz + 1);
+    s->dt = 1.0 / (cfg->freq * cfg->steps_per_period);
+    if (o_geometry(s)) { orc_destroy(s); return -1; }
+    s->Sr = ldexp(1.0, O_FBITS) / s->dr;
+    s->Sz = ldexp(1.0, O_FBITS) / s->dz;
+    s->invd = malloc(sizeof(double) * s->nr);
+    for (int i = 0; i < s->nr; i++) s->invd[i] = ldexp(1.0, -2 * O_FBITS) / (double)(2 * i + 1);
+    s->mass[0] = O_ME;
+    s->mass[1] = O_MAR;
+    s->qm[0] = -O_QE / O_ME;
+    s->qm[1] = O_QE / O_MAR;
+    s->sign[0] = -1;
+    s->sign[1] = 1;
+    o_set_collision_constants(s);
+    int64_t caps[2] = {cfg->cap_e, cfg->cap_i};
+    for (int sp = 0; sp < 2; sp++) {
+        if (parts_alloc(&s->p[sp], caps[sp])) { orc_destroy(s); return -1; }
+        s->dep[sp] = calloc(s->nn, sizeof(int64_t));
+        s->psum[sp] = calloc(s->nn, sizeof(int64_t));
+        s->plast[sp] = calloc(s->nn, sizeof(int64_t));
+    }
+    s->wallq = calloc(s->nn, sizeof(int64_t));
+    double** g[8] = {&s->phi, &s->phiL, &s->Er, &s->Ez, &s->chi, &s->Q, &s->ar, &s->az};
+    for (int k = 0; k < 8; k++) *g[k] = calloc(s->nn, sizeof(double));
+    int spp = cfg->steps_per_period;
+    s->serU = calloc(spp, sizeof(double));
+    s->serI = calloc(spp, sizeof(double));
+    s->lastU = calloc(spp, sizeof(double));
+    s->lastI = calloc(spp, sizeof(double));
+    /* particles: the load fixes w_unit; with load = 0 the slots stay empty */
+    orc_config save = s->cfg;
+    if (!cfg->load) { s->cfg.n_e = 0; s->cfg.n_i = 0; }
+    /* w_unit from the requested counts even when nothing is loaded */
+    {
+        double vv = 0.0;
+        for (int j = 0; j < s->nz; j++)
+            for (int i = 0; i < s->nr; i++)
+                if (s->cell_kind[j * s->nr + i] == 0) {
+                    double r0 = i * s->dr, r1 = (i + 1) * s->dr;
+                    vv += O_PI * (r1 * r1 - r0 * r0) * s->dz;
+                }
+        s->w_unit = cfg->n0 * vv / (double)(cfg->n_e > 0 ? cfg->n_e : 1);
+    }
+    int rc = o_load(s);
+    s->cfg = save;
+    if (rc) { orc_destroy(s); return rc; }
+    /* [R8] a_bar = 0 at start: the first prediction is a plain move */
+    for (int sp = 0; sp < 2; sp++) {
+        o_parts* P = &s->p[sp];
+        double st[9];
+        for (int64_t k = 0; k < P->n; k++) {
+            get1(P, k, st);
+            o_predict1(s, st);
+            if (o_absorb_check(s, sp, st[0], st[1], st[8])) { put1(P, k, st); P->r[k] = -1.0; continue; }
+            put1(P, k, st);
+            o_deposit_one(s, st[0], st[1], st[8], s->dep[sp]);
+        }
+    }
+    /* vacuum equivalent capacitance and Laplace solution at start [R21] */
+    o_faces_from_chi(s, s->chi, s->ar, s->az);
+    o_laplace(s);
+    o_assemble(s);
+    s->Q_P = induced_charge(s);
+    s->U_E = (cfg->circ_kind == 0) ? cfg->U_dc : 0.0;
+    s->Q_E = s->C_eq * s->U_E + s->Q_P;
+    s->cnt_prev_pow = (int64_t)powered_count(s);
+    *out = s;
+    return 0;
+}
+
+void orc_destroy(orc_sim* s) {
+    if (!s) return;
+    free(s->invd); free(s->cell_kind); free(s->node_kind); free(s->cell_eps);
+    free(s->vol); free(s->gr); free(s->gz);
+    for (int sp = 0; sp < 2; sp++) {
+        parts_free(&s->p[sp]);
+        free(s->dep[sp]); free(s->psum[sp]); free(s->plast[sp]);
+    }
+    free(s->wallq);
+    free(s->phi); free(s->phiL); free(s->Er); free(s->Ez); free(s->chi); free(s->Q);
+    free(s->ar); free(s->az);
+    free(s->serU); free(s->serI); free(s->lastU); free(s->lastI);
+    free(s);
+}
+
+/* ------------------------------------------------------------ diagnostics */
+/* [R23] harmonics over the last complete RF period of N = steps_per_period
+   samples: X_k = (2/N) sum_n x_n exp(-2 pi i k n / N), X_0 the mean (the DC
+   self-bias for the voltage). */
+static void harmonics(const double* x, int N, double* re, double* im) {
+    for (int k = 0; k < 6; k++) {
+        double a = 0.0, b = 0.0;
+        for (int n = 0; n < N; n++) {
+            double ph = 2.0 * O_PI * (double)k * (double)n / (double)N;
+            a += x[n] * cos(ph);
+            b -= x[n] * sin(ph);
+        }
+        double sc = (k == 0) ? 1.0 / N : 2.0 / N;
+        re[k] = a * sc;
+        im[k] = b * sc;
+    }
+}
+
+int orc_diag_get(orc_sim* s, orc_diag* d) {
+    memset(d, 0, sizeof(*d));
+    d->t = s->t; d->U_E = s->U_E; d->Q_E = s->Q_E; d->C_eq = s->C_eq; d->Q_P = s->Q_P;
+    d->I_ccp = s->I_ccp; d->dt = s->dt; d->w_unit = s->w_unit; d->n_gas = s->n_gas;
+    memcpy(d->circ, s->circ, sizeof(d->circ));
+    d->nu_max[0] = s->nu_max[0]; d->nu_max[1] = s->nu_max[1];
+    d->thresh[0] = s->thresh[0]; d->thresh[1] = s->thresh[1];
+    d->step = s->step; d->periods_done = s->periods_done;
+    for (int sp = 0; sp < 2; sp++) {
+        d->n_slots[sp] = s->p[sp].n;
+        int64_t a = 0;
+        for (int64_t k = 0; k < s->p[sp].n; k++) a += (s->p[sp].r[k] >= 0.0);
+        d->n_alive[sp] = a;
+        for (int c = 0; c < ORC_NCNT; c++) d->absorbed[sp][c] = s->cnt[sp][c];
+        for (int c = 0; c < 4; c++) d->coll[sp][c] = s->coll[sp][c];
+    }
+    d->born = s->born;
+    d->numax_violations = s->viol;
+    d->solver_iters = s->solver_iters;
+    d->solver_relres = s->solver_relres;
+    if (s->have_last) {
+        harmonics(s->lastU, s->cfg.steps_per_period, d->harm_U_re, d->harm_U_im);
+        harmonics(s->lastI, s->cfg.steps_per_period, d->harm_I_re, d->harm_I_im);
+    }
+    return 0;
+}
+
+int orc_series(orc_sim* s, int32_t last, double* U_out, double* I_out) {
+    int spp = s->cfg.steps_per_period;
+    memcpy(U_out, last ? s->lastU : s->serU, sizeof(double) * spp);
+    memcpy(I_out, last ? s->lastI : s->serI, sizeof(double) * spp);
+    return 0;
+}
+
+/* --------------------------------------------------------- introspection */
+int64_t orc_num_slots(orc_sim* s, int32_t sp) { return (sp == 0 || sp == 1) ? s->p[sp].n : -1; }
+
+int orc_get_particles(orc_sim* s, int32_t sp, double* out9) {
+    o_parts* P = &s->p[sp];
+    int64_t n = P->n;
+    double* f[9] = {P->r, P->z, P->vr, P->vt, P->vz, P->ar, P->at, P->az, P->w};
+    for (int k = 0; k < 9; k++) memcpy(out9 + (size_t)k * n, f[k], sizeof(double) * n);
+    return 0;
+}
+
+int orc_set_particles(orc_sim* s, int32_t sp, int64_t n, const double* in9) {
+    o_parts* P = &s->p[sp];
+    if (n > P->cap) return -2;
+    double* f[9] = {P->r, P->z, P->vr, P->vt, P->vz, P->ar, P->at, P->az, P->w};
+    for (int k = 0; k < 9; k++) memcpy(f[k], in9 + (size_t)k * n, sizeof(double) * n);
+    P->n = n;
+    return 0;
+}
+
+int orc_redeposit(orc_sim* s) {
+    for (int sp = 0; sp < 2; sp++) {
+        memset(s->dep[sp], 0, sizeof(int64_t) * s->nn);
+        o_parts* P = &s->p[sp];
+        for (int64_t k = 0; k < P->n; k++)
+            if (P->r[k] >= 0.0) o_deposit_one(s, P->r[k], P->z[k], P->w[k], s->dep[sp]);
+    }
+    return 0;
+}
+
+int orc_get_grid(orc_sim* s, int32_t which, void* out) {
+    size_t nn = (size_t)s->nn, nc = (size_t)s->nr * s->nz;
+    switch (which) {
+    case ORC_G_DEP_E: memcpy(out, s->dep[0], nn * 8); return 0;
+    case ORC_G_DEP_I: memcpy(out, s->dep[1], nn * 8); return 0;
+    case ORC_G_PHI: memcpy(out, s->phi, nn * 8); return 0;
+    case ORC_G_ER: memcpy(out, s->Er, nn * 8); return 0;
+    case ORC_G_EZ: memcpy(out, s->Ez, nn * 8); return 0;
+    case ORC_G_CHI: memcpy(out, s->chi, nn * 8); return 0;
+    case ORC_G_WALLQ: memcpy(out, s->wallq, nn * 8); return 0;
+    case ORC_G_NODE_KIND: memcpy(out, s->node_kind, nn * 4); return 0;
+    case ORC_G_CELL_KIND: memcpy(out, s->cell_kind, nc * 4); return 0;
+    case ORC_G_VOL: memcpy(out, s->vol, nn * 8); return 0;
+    case ORC_G_PHI_L: memcpy(out, s->phiL, nn * 8); return 0;
+    case ORC_G_Q: memcpy(out, s->Q, nn * 8); return 0;
+    case ORC_G_AR: memcpy(out, s->ar, nn * 8); return 0;
+    case ORC_G_AZ: memcpy(out, s->az, nn * 8); return 0;
+    case ORC_G_NE_AVG:
+    case ORC_G_NI_AVG: {
+        int sp = which - ORC_G_NE_AVG;
+        double* o = out;
+        double unit = s->w_unit * ldexp(1.0, -O_KBITS) / s->cfg.steps_per_period;
+        for (size_t n = 0; n < nn; n++) o[n] = (double)s->plast[sp][n] * unit / s->vol[n];
+        return 0;
+    }
+    }
+    return -1;
+}
+
+int orc_set_grid(orc_sim* s, int32_t which, const void* in) {
+    size_t nn = (size_t)s->nn;
+    switch (which) {
+    case ORC_G_DEP_E: memcpy(s->dep[0], in, nn * 8); return 0;
+    case ORC_G_DEP_I: memcpy(s->dep[1], in, nn * 8); return 0;
+    case ORC_G_PHI: memcpy(s->phi, in, nn * 8); return 0;
+    case ORC_G_WALLQ: memcpy(s->wallq, in, nn * 8); return 0;
+    case ORC_G_PHI_L: memcpy(s->phiL, in, nn * 8); return 0;
+    }
+    return -1;
+}
+
+int orc_set_state(orc_sim* s, const double* st) {
+    s->t = st[0]; s->Q_E = st[1]; s->U_E = st[2];
+    for (int k = 0; k < 5; k++) s->circ[k] = st[3 + k];
+    s->C_eq = st[8];
+    return 0;
+}
+
+/* ------------------------------------------------------------ pure pieces */
+int orc_solve_q(orc_sim* s, const double* Q, const double* chi, double U_E, double tol, double* phi_inout,
+                int32_t* iters, double* relres) {
+    double* ar = calloc(s->nn, sizeof(double));
+    double* az = calloc(s->nn, sizeof(double));
+    o_faces_from_chi(s, chi, ar, az);
+    int it;
+    double rel;
+    int rc = o_solve(s, ar, az, Q, U_E, tol, phi_inout, &it, &rel);
+    if (iters) *iters = it;
+    if (relres) *relres = rel;
+    free(ar);
+    free(az);
+    return rc;
+}
+
+double orc_refresh_laplace(orc_sim* s) { return o_laplace(s); }
+
+int orc_deposit(orc_sim* s, int64_t n, const double* r, const double* z, const double* w, int64_t* grid) {
+    memset(grid, 0, sizeof(int64_t) * s->nn);
+    for (int64_t k = 0; k < n; k++)
+        if (r[k] >= 0.0) o_deposit_one(s, r[k], z[k], w[k], grid);
+    return 0;
+}
+
+int orc_tile_keys(orc_sim* s, int64_t n, const double* r, const double* z, uint32_t* keys) {
+    for (int64_t k = 0; k < n; k++) keys[k] = tile_key(s, r[k], z[k]);
+    return 0;
+}
+
+int orc_predict(orc_sim* s, int64_t n, double* p9) {
+    double st[9];
+    for (int64_t k = 0; k < n; k++) {
+        for (int f = 0; f < 9; f++) st[f] = p9[(size_t)f * n + k];
+        o_predict1(s, st);
+        for (int f = 0; f < 9; f++) p9[(size_t)f * n + k] = st[f];
+    }
+    return 0;
+}
+
+int orc_correct(orc_sim* s, int32_t sp, int64_t n, double* p9, const double* Er, const double* Ez) {
+    double st[9];
+    for (int64_t k = 0; k < n; k++) {
+        for (int f = 0; f < 9; f++) st[f] = p9[(size_t)f * n + k];
+        o_correct1(s, sp, st, Er[k], Ez[k]);
+        for (int f = 0; f < 9; f++) p9[(size_t)f * n + k] = st[f];
+    }
+    return 0;
+}
+
+int orc_mcc(orc_sim* s, int32_t sp, int64_t n, double* v3, uint32_t slot0, uint32_t step, int32_t* proc,
+            double* birth6) {
+    for (int64_t k = 0; k < n; k++) {
+        double v[3] = {v3[3 * k], v3[3 * k + 1], v3[3 * k + 2]}, b6[6] = {0, 0, 0, 0, 0, 0};
+        proc[k] = o_mcc1(s, sp, v, slot0 + (uint32_t)k, step, b6);
+        for (int c = 0; c < 3; c++) v3[3 * k + c] = v[c];
+        if (birth6) for (int c = 0; c < 6; c++) birth6[6 * k + c] = b6[c];
+    }
+    return 0;
+}
