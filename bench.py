@@ -1,0 +1,128 @@
+"""Benchmark of the hot path on one MI355X.
+
+One step = the whole time step of the method (assembly of Eq. 1, circuit,
+implicit field solve, the fused particle loop for both species, births,
+periodic sort, per-period Laplace refresh).  Prints one JSON line.
+
+  value          whole-job particle-steps/s over the timed region
+  roofline       fused particle kernel (gather, correct, absorb, MCC, predict,
+                 deposit): 68 algorithmic bytes per particle-step against the
+                 8 TB/s HBM peak, timed with HIP events on the library's stream
+  cpu_baseline   the FP64 oracle on a bounded sample of the same workload
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+BYTES_PER_PARTICLE_STEP = 68.0   # read r z vr vt vz ar at az w, write all but w (FP32)
+HBM_PEAK_GBS = 8000.0
+
+
+def cpu_baseline(name, sample_particles, steps):
+    import oracle as O
+    from pic_inputs import workload
+    w = workload(name, run=dict(n_e=sample_particles, n_i=sample_particles,
+                                cap_e=2 * sample_particles, cap_i=2 * sample_particles))
+    o = O.Oracle(w)
+    t0 = time.perf_counter()
+    o.step(steps)
+    dt = time.perf_counter() - t0
+    d = o.diag()
+    n = int(d.n_alive[0] + d.n_alive[1])
+    return dict(value=2 * sample_particles * steps / dt, unit="particle-steps/s", cores=1, kind="oracle",
+                sample=f"{name} geometry and circuit, {sample_particles} e + {sample_particles} Ar+ "
+                       f"(uniform load), {steps} whole steps single-threaded FP64 incl. field solve; "
+                       f"{dt:.1f} s, {n} alive at end",
+                seconds=dt)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="gec1024x2048")
+    ap.add_argument("--method", default="ir", choices=["ir", "mgpcg"])
+    ap.add_argument("--cpu-sample", type=int, default=1_000_000)
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    from paper_2310_04957_amd.pic import Pic
+    from pic_inputs import workload
+    from pic_inputs.workloads import SOLVE_IR_MG, SOLVE_MGPCG_FP64
+
+    w = workload(args.workload)
+    method = SOLVE_IR_MG if args.method == "ir" else SOLVE_MGPCG_FP64
+    print(f"[bench] init {args.workload} method={args.method}", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    sim = Pic(w, timing=True, method=method)
+    torch.cuda.synchronize()
+    t_init = time.perf_counter() - t0
+    print(f"[bench] init done in {t_init:.1f} s; warmup {args.warmup}", file=sys.stderr, flush=True)
+    sim.step(args.warmup)
+    sim.reset_timers()
+    d0 = sim.diag()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    d = sim.diag()
+    print(f"[bench] timed {args.steps} steps in {wall:.3f} s", file=sys.stderr, flush=True)
+
+    # particle-steps in the timed region: slots are processed each step;
+    # use the mean of the live counts at both ends
+    n_start = d0.n_alive[0] + d0.n_alive[1]
+    n_end = d.n_alive[0] + d.n_alive[1]
+    n_mean = 0.5 * (n_start + n_end)
+    ps = n_mean * args.steps
+    ms_part = d.ms_particles[0] + d.ms_particles[1]
+    part_bytes = BYTES_PER_PARTICLE_STEP * ps
+    achieved = part_bytes / (ms_part * 1e-3) / 1e9 if ms_part > 0 else 0.0
+    out = {
+        "metric": "particle-steps/s (push+deposit+MCC) + field-solve ms/step, learned vs plain PCG",
+        "value": ps / wall,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "grid": f"{w['geometry']['nr']}x{w['geometry']['nz']}",
+                   "particles": int(n_start), "solver": args.method, "steps_per_period": w["run"]["steps_per_period"]},
+        "particle_loop_particle_steps_per_s": ps / (ms_part * 1e-3) if ms_part > 0 else None,
+        "field_solve_ms_per_step": d.ms_field / max(args.steps, 1),
+        "phase_ms_per_step": {"particles_e": d.ms_particles[0] / args.steps, "particles_i": d.ms_particles[1] / args.steps,
+                              "births": d.ms_births / args.steps, "sort": d.ms_sort / args.steps,
+                              "field": d.ms_field / args.steps, "refresh": d.ms_refresh / args.steps},
+        "solver_iters_last": int(d.solver_iters), "solver_relres_last": d.solver_relres,
+        "deposit_fallback_per_step": (d.deposit_fallback - d0.deposit_fallback) / args.steps,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_particles", "bytes_per_unit": BYTES_PER_PARTICLE_STEP,
+                     "unit_of_work": "particle-step"},
+    }
+    sim.close()
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_sample, args.cpu_steps)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,203 @@
+/*
+ * pic.h -- C ABI of the MI355X (gfx950) implementation of the hot path of
+ * the 2D axisymmetric (r-z) electrostatic implicit PIC/MCC model with
+ * equivalent-capacitance circuit coupling of arXiv 2310.04957 (Sec. 2).
+ *
+ * The calls follow the paper's statement of the problem: a reactor made of
+ * metal electrodes and dielectrics on a regular r-z grid (Sec. 2, reactor
+ * geometry paragraph), one RF-driven electrode coupled to an external
+ * circuit (Eqs. 5 and 8-10), argon with electrons and Ar+ (collision
+ * paragraph), a time step (Sec. 3, first paragraph), and outputs of
+ * period-averaged densities and electrode voltage/current harmonics (Sec. 3).
+ *
+ * Conventions for every entry point:
+ *   - Return value: PIC_OK (0) or a negative PIC_E_* code; pic_strerror()
+ *     names it.  No C++ exception crosses this boundary.
+ *   - Device memory and the HIP stream are owned by the caller: pic_init
+ *     receives one device workspace of at least pic_workspace_size() bytes,
+ *     which must stay allocated and untouched until pic_free(); all work is
+ *     queued on the caller's stream.  The library allocates no device memory
+ *     of its own.
+ *   - The library copies the configuration at pic_init; caller buffers
+ *     passed to other calls are read or written only during the call.
+ *   - A handle is not thread safe: one caller at a time.
+ *   - Grids are node arrays of (nr+1)*(nz+1) values, index j*(nr+1)+i with
+ *     r_i = i*R/nr, z_j = j*Z/nz (r fastest).
+ */
+#ifndef PIC_H
+#define PIC_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PIC_ABI_VERSION 1
+#define PIC_MAX_REGIONS 32
+
+enum {
+    PIC_OK = 0,
+    PIC_E_CONFIG = -1,    /* invalid configuration (sizes, regions, circuit values) */
+    PIC_E_CAPACITY = -2,  /* births exceeded a species capacity; the births of that step were dropped */
+    PIC_E_SOLVER = -3,    /* field solve did not reach the tolerance within max_iter */
+    PIC_E_HIP = -4,       /* a HIP runtime call failed */
+    PIC_E_NONFINITE = -5, /* a non-finite value reached the field solve */
+    PIC_E_STATE = -6,     /* call not valid in the handle's state */
+    PIC_E_ARG = -7,       /* bad argument (null pointer, size too small, bad id) */
+    PIC_E_NODEVICE = -8   /* no gfx950 device is current */
+};
+
+enum { PIC_VACUUM = 0, PIC_DIEL = 1, PIC_COND = 2 };                 /* region kinds */
+enum { PIC_GROUND = 0, PIC_POWERED = 1, PIC_NEUMANN = -1 };           /* conductor ids / edge bc */
+enum { PIC_IDEAL_SOURCE = 0, PIC_SERIES_RLC = 1, PIC_LMATCH = 2 };    /* circuits */
+enum { PIC_SOLVE_MGPCG_FP64 = 0, PIC_SOLVE_IR_MG = 1 };              /* field-solve methods */
+
+/* A rectangle [r0,r1) x [z0,z1) in metres.  Each cell takes the last region
+   that contains its centre.  kind PIC_COND uses cond_id (0 ground, 1 the
+   driven electrode); PIC_DIEL uses eps_r. */
+typedef struct {
+    double r0, r1, z0, z1;
+    int32_t kind, cond_id;
+    double eps_r;
+} pic_region;
+
+typedef struct {
+    int32_t nr, nz;             /* cells; both even and >= 4 */
+    double R, Z;                /* domain [0,R] x [0,Z], metres; r = 0 is the axis */
+    int32_t n_regions;
+    int32_t edge_bc[3];         /* r=R, z=0, z=Z edges: conductor id or PIC_NEUMANN */
+    pic_region regions[PIC_MAX_REGIONS];
+} pic_geometry;
+
+/* Eq. (9) series R_b L_b C_b, Eq. (10) L-type network (C_m1 shunt, R_m L_m
+   C_m2 series, stray branch R_stray L_stray C_stray), or an ideal source on
+   the electrode.  Source U_amp sin(2 pi f t) + U_dc. */
+typedef struct {
+    int32_t kind, substeps;     /* substeps: RK4 substeps per PIC step */
+    double freq, U_amp, U_dc, R_s, C_m1, C_m2, L_m, R_m, C_stray, L_stray, R_stray, C_b, R_b, L_b;
+} pic_circuit;
+
+typedef struct {
+    double p_Pa, T_gas_K;       /* background argon, fixed (no depletion) */
+} pic_gas;
+
+typedef struct {
+    int64_t n_e, n_i;           /* initial macro-particles */
+    int64_t cap_e, cap_i;       /* slots reserved per species */
+    double n0, Te_eV, Ti_eV;    /* initial uniform plasma density (m^-3) and temperatures */
+    int32_t steps_per_period;   /* dt = 1 / (freq * steps_per_period) */
+    int32_t sort_every;         /* cell sort every K steps (0: never) */
+    uint64_t seed;              /* Philox key */
+    int32_t load;               /* 1: load the Maxwellian plasma at init; 0: start empty */
+    int32_t timing;             /* 1: time each phase with HIP events (pic_diag reports ms) */
+} pic_run;
+
+typedef struct {
+    int32_t method;             /* PIC_SOLVE_* */
+    double tol;                 /* ||b - K phi||_2 / ||b||_2 at which a solve stops */
+    int32_t max_iter;           /* Krylov iterations per solve */
+    double inner_tol;           /* IR: relative tolerance of each FP32 inner solve */
+} pic_solver;
+
+typedef struct {
+    int32_t abi_version;        /* PIC_ABI_VERSION */
+    pic_geometry geom;
+    pic_circuit circ;
+    pic_gas gas;
+    pic_run run;
+    pic_solver solver;
+} pic_config;
+
+typedef struct pic_handle pic_handle;
+
+/* Scalars and counters returned by pic_diag.  Grids and time series are
+   copied into the optional caller buffers of pic_diag_buffers. */
+typedef struct {
+    double t, U_E, Q_E, C_eq, Q_P, I_ccp, dt, w_unit, n_gas;
+    double circ[5];
+    double nu_max[2];
+    uint32_t thresh[2];
+    int64_t step, periods_done;
+    int64_t n_slots[2], n_alive[2];
+    int64_t absorbed[2][4];     /* per species: ground, powered, lost (Neumann edge), dielectric */
+    int64_t born, coll[2][4], numax_violations;
+    int64_t solver_iters, solver_outer;
+    double solver_relres;
+    double harm_U_re[6], harm_U_im[6], harm_I_re[6], harm_I_im[6];
+    double ms_particles[2], ms_births, ms_sort, ms_field, ms_refresh; /* accumulated since last reset */
+    int64_t timed_steps, deposit_fallback;
+    int32_t error;              /* sticky error raised on the device (PIC_E_CAPACITY ...) */
+} pic_diag_out;
+
+typedef struct {
+    double* n_e;                /* period-averaged densities, m^-3, node grid (or NULL) */
+    double* n_i;
+    double* phi;                /* potential at the last step, V (or NULL) */
+    double* U_E;                /* electrode voltage over the last complete period, steps_per_period values */
+    double* I_ccp;              /* circuit current over the last complete period */
+} pic_diag_buffers;
+
+/* Bytes of device workspace needed for cfg.  Host-only, no device access. */
+int pic_workspace_size(const pic_config* cfg, size_t* bytes_out);
+
+/* Validate cfg, carve the workspace, build the geometry, load the plasma
+   (Sec. 3: uniform density, Maxwellian), deposit the first predicted
+   positions, compute the vacuum C_eq (Eqs. 6-7) and the multigrid
+   hierarchy.  Synchronises the stream before returning. */
+int pic_init(const pic_config* cfg, void* dev_workspace, size_t bytes, void* hip_stream, pic_handle** out);
+
+/* Queue nsteps time steps on the stream (Sec. 2 order: assembly of Eq. 1,
+   circuit and electrode charge, implicit field solve, particle push with
+   MCC and deposit, births, periodic sort, per-period Laplace/C_eq refresh).
+   Returns after queueing; the field solve reads one convergence flag back
+   every few Krylov iterations. */
+int pic_step(pic_handle* h, int32_t nsteps);
+
+/* Synchronise and fill `out` (and the buffers of `bufs` that are non-NULL). */
+int pic_diag(pic_handle* h, pic_diag_out* out, const pic_diag_buffers* bufs);
+int pic_reset_timers(pic_handle* h);
+
+int pic_free(pic_handle* h);
+const char* pic_strerror(int code);
+
+/* ---- introspection for parity tests (synchronous, host buffers) ---- */
+enum { PIC_P_R = 0, PIC_P_Z, PIC_P_VR, PIC_P_VT, PIC_P_VZ, PIC_P_AR, PIC_P_AT, PIC_P_AZ, PIC_P_W };
+/* Particle slots of a species as 9 field-major FP32 arrays (r z vr vt vz ar
+   at az w); a dead slot has r < 0.  get: `host9` holds 9*cap floats and
+   *n receives the slot count.  set: n slots are copied in. */
+int pic_get_particles(pic_handle* h, int32_t species, float* host9, int64_t* n);
+int pic_set_particles(pic_handle* h, int32_t species, const float* host9, int64_t n);
+
+enum {
+    PIC_G_DEP_E = 0, PIC_G_DEP_I = 1, /* int64 fixed-point deposits of the predicted positions */
+    PIC_G_PHI = 2,                    /* double */
+    PIC_G_ER = 3, PIC_G_EZ = 4,       /* float, node electric field */
+    PIC_G_CHI = 5,                    /* double */
+    PIC_G_WALLQ = 6,                  /* int64 dielectric surface charge */
+    PIC_G_PHI_L = 10, PIC_G_Q = 11, PIC_G_AR = 12, PIC_G_AZ = 13 /* double */
+};
+int pic_get_grid(pic_handle* h, int32_t which, void* host);
+int pic_set_grid(pic_handle* h, int32_t which, const void* host); /* DEP_E, DEP_I, WALLQ, PHI */
+
+/* Zero both deposit grids and deposit the current slots at their stored
+   (predicted) positions, with the same fixed-point kernel as the step. */
+int pic_redeposit(pic_handle* h);
+
+/* Tile sort of one species now (stable, dead slots dropped); perm_out (or
+   NULL) receives, for each new slot, the old slot it came from. */
+int pic_sort_now(pic_handle* h, int32_t species, int64_t* perm_out);
+
+/* One solve of Eq. (1) on given node charges Q (C) and susceptibility chi
+   with the driven electrode at U_E; phi_inout is the warm start and the
+   result.  Uses the configured method; tol overrides the configured one. */
+int pic_solve_once(pic_handle* h, const double* Q, const double* chi, double U_E, double tol,
+                   double* phi_inout, int32_t* iters, double* relres);
+
+/* Set t, Q_E, U_E, circ[5], C_eq (9 doubles) -- for single-step parity. */
+int pic_set_state(pic_handle* h, const double* st9);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,809 @@
+// api.hip -- the C ABI of include/pic.h: configuration checks, geometry,
+// workspace layout, the multigrid plan, and the time-step driver that queues
+// the kernels of particles.hip, sort.hip and field.hip on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "pic_internal.h"
+
+using namespace pic;
+
+namespace {
+
+constexpr double kQE = 1.602176634e-19;
+constexpr double kME = 9.1093837015e-31;
+constexpr double kMAr = 39.948 * 1.66053906660e-27;
+constexpr double kEps0 = 8.8541878128e-12;
+constexpr double kKB = 1.380649e-23;
+constexpr double kPi = 3.14159265358979323846;
+
+#define HIP_OK(x)                               \
+    do {                                        \
+        if ((x) != hipSuccess) return PIC_E_HIP; \
+    } while (0)
+
+int validate(const pic_config* c) {
+    if (!c || c->abi_version != PIC_ABI_VERSION) return PIC_E_CONFIG;
+    const pic_geometry& g = c->geom;
+    if (g.nr < 4 || g.nz < 4 || (g.nr & 1) || (g.nz & 1) || g.nr > 16384 || g.nz > 16384) return PIC_E_CONFIG;
+    if (!(g.R > 0) || !(g.Z > 0) || g.n_regions < 0 || g.n_regions > PIC_MAX_REGIONS) return PIC_E_CONFIG;
+    for (int k = 0; k < 3; ++k)
+        if (g.edge_bc[k] < -1 || g.edge_bc[k] > 1) return PIC_E_CONFIG;
+    for (int k = 0; k < g.n_regions; ++k) {
+        const pic_region& r = g.regions[k];
+        if (r.kind < 0 || r.kind > 2) return PIC_E_CONFIG;
+        if (r.kind == PIC_COND && (r.cond_id < 0 || r.cond_id > 1)) return PIC_E_CONFIG;
+        if (r.kind == PIC_DIEL && !(r.eps_r >= 1.0)) return PIC_E_CONFIG;
+    }
+    const pic_circuit& ci = c->circ;
+    if (!(ci.freq > 0) || ci.kind < 0 || ci.kind > 2 || ci.substeps < 1) return PIC_E_CONFIG;
+    if (ci.kind == PIC_LMATCH && !(ci.C_m1 > 0 && ci.C_m2 > 0 && ci.L_m > 0 && ci.R_s > 0 && ci.C_stray > 0 &&
+                                   ci.L_stray > 0))
+        return PIC_E_CONFIG;
+    if (ci.kind == PIC_SERIES_RLC && !(ci.C_b > 0 && ci.L_b > 0)) return PIC_E_CONFIG;
+    const pic_run& r = c->run;
+    if (r.steps_per_period < 1 || r.n_e < 0 || r.n_i < 0 || r.cap_e < r.n_e || r.cap_i < r.n_i) return PIC_E_CONFIG;
+    if (r.cap_e > 0xFFFFFFF0LL || r.cap_i > 0xFFFFFFF0LL || r.sort_every < 0) return PIC_E_CONFIG;
+    if (!(c->gas.p_Pa >= 0) || !(c->gas.T_gas_K > 0) || !(r.n0 >= 0)) return PIC_E_CONFIG;
+    if (c->solver.method < 0 || c->solver.method > 1 || !(c->solver.tol > 0) || c->solver.max_iter < 1)
+        return PIC_E_CONFIG;
+    return PIC_OK;
+}
+
+// cross sections for the electron null-collision bound (analytic argon
+// stand-ins: elastic, excitation 11.5 eV, ionisation 15.76 eV)
+double sigma_total_e(double eps) {
+    double el = 1.0e-19 / std::sqrt(1.0 + eps / 10.0);
+    double ex = (eps > 11.5) ? 2.7e-20 * std::log(eps / 11.5) / (eps / 11.5) : 0.0;
+    double io = (eps > 15.76) ? 8.0e-20 * std::log(eps / 15.76) / (eps / 15.76) : 0.0;
+    return el + ex + io;
+}
+
+void derive(pic_handle* h) {
+    const pic_config& c = h->cfg;
+    h->nr = c.geom.nr; h->nz = c.geom.nz; h->w = h->nr + 1;
+    h->nn = (h->nr + 1) * (h->nz + 1);
+    h->ncell = h->nr * h->nz;
+    h->dr = c.geom.R / h->nr;
+    h->dz = c.geom.Z / h->nz;
+    h->dt = 1.0 / (c.circ.freq * c.run.steps_per_period);
+    h->Sr = std::ldexp(1.0, kFBits) / h->dr;
+    h->Sz = std::ldexp(1.0, kFBits) / h->dz;
+    h->ntr = (h->nr + kTile - 1) / kTile;
+    h->ntz = (h->nz + kTile - 1) / kTile;
+    h->ntiles = h->ntr * h->ntz;
+    int bits = 1;
+    while ((1u << bits) <= (unsigned)h->ntiles) ++bits;   // keys 0..ntiles (ntiles = dead)
+    h->key_bits = bits;
+    h->cap[0] = c.run.cap_e;
+    h->cap[1] = c.run.cap_i;
+    int64_t capmax = std::max<int64_t>(std::max(h->cap[0], h->cap[1]), 1);
+    h->max_chunks = (capmax + kChunk - 1) / kChunk;
+    // null-collision constants (Vahedi & Surendra 1995)
+    h->n_gas = c.gas.p_Pa / (kKB * c.gas.T_gas_K);
+    const int N = 2000000;
+    double best = 0.0;
+    for (int k = 0; k < N; ++k) {
+        double eps = std::pow(10.0, -4.0 + 9.0 * (double)k / (double)(N - 1));
+        double sv = sigma_total_e(eps) * std::sqrt(2.0 * kQE * eps / kME);
+        best = std::max(best, sv);
+    }
+    h->nu_max[0] = h->n_gas * best * 1.001;
+    const double gmax = std::sqrt(2.0 * kQE * 2000.0 / kMAr) + 5.0 * std::sqrt(kKB * c.gas.T_gas_K / kMAr);
+    h->nu_max[1] = h->n_gas * (5.0e-19 + 5.0e-19) * gmax;
+    h->vth_gas = std::sqrt(kKB * c.gas.T_gas_K / kMAr);
+    for (int sp = 0; sp < 2; ++sp) {
+        double P = -std::expm1(-h->nu_max[sp] * h->dt);
+        double T = std::floor(P * 4294967296.0);
+        h->thresh[sp] = (T >= 4294967295.0) ? 0xFFFFFFFFu : (uint32_t)T;
+    }
+}
+
+}  // namespace
+
+namespace pic {
+
+// Cells: the last region containing the centre; nodes: conductor if an
+// adjacent cell is a conductor or it lies on a conductor edge, ground
+// winning over the driven electrode where both touch.  Host only.
+int host_geometry(pic_handle* h) {
+    const pic_geometry& g = h->cfg.geom;
+    const int nr = h->nr, nz = h->nz, w = h->w;
+    h->h_cell_kind.assign((size_t)nr * nz, 0);
+    std::vector<double> eps((size_t)nr * nz, 1.0);
+    for (int j = 0; j < nz; ++j)
+        for (int i = 0; i < nr; ++i) {
+            const double rc = (i + 0.5) * h->dr, zc = (j + 0.5) * h->dz;
+            uint8_t kind = 0;
+            double e = 1.0;
+            for (int k = 0; k < g.n_regions; ++k) {
+                const pic_region& q = g.regions[k];
+                if (rc >= q.r0 && rc < q.r1 && zc >= q.z0 && zc < q.z1) {
+                    if (q.kind == PIC_COND) { kind = (uint8_t)(2 + q.cond_id); e = 1.0; }
+                    else if (q.kind == PIC_DIEL) { kind = 1; e = q.eps_r; }
+                    else { kind = 0; e = 1.0; }
+                }
+            }
+            h->h_cell_kind[(size_t)j * nr + i] = kind;
+            eps[(size_t)j * nr + i] = e;
+        }
+    h->h_node_kind.assign((size_t)h->nn, -1);
+    for (int j = 0; j <= nz; ++j)
+        for (int i = 0; i <= nr; ++i) {
+            bool touch[2] = {false, false};
+            for (int cj = j - 1; cj <= j; ++cj)
+                for (int ci = i - 1; ci <= i; ++ci) {
+                    if (ci < 0 || cj < 0 || ci >= nr || cj >= nz) continue;
+                    const uint8_t k = h->h_cell_kind[(size_t)cj * nr + ci];
+                    if (k >= 2) touch[k - 2] = true;
+                }
+            if (i == nr && g.edge_bc[0] >= 0) touch[g.edge_bc[0]] = true;
+            if (j == 0 && g.edge_bc[1] >= 0) touch[g.edge_bc[1]] = true;
+            if (j == nz && g.edge_bc[2] >= 0) touch[g.edge_bc[2]] = true;
+            h->h_node_kind[(size_t)j * w + i] = touch[0] ? 0 : (touch[1] ? 1 : -1);
+        }
+    // node volumes: half of each adjacent annulus (r^2 weights), half again on z edges
+    h->h_vol.assign((size_t)h->nn, 0.0);
+    h->h_gr.assign((size_t)h->nn, 0.0);
+    h->h_gz.assign((size_t)h->nn, 0.0);
+    const double dr = h->dr, dz = h->dz;
+    for (int j = 0; j <= nz; ++j)
+        for (int i = 0; i <= nr; ++i) {
+            const double rlo = (i > 0) ? (i - 1) * dr : 0.0;
+            const double ri = i * dr;
+            const double rhi = (i < nr) ? (i + 1) * dr : ri;
+            double v = (i == 0) ? kPi * dz * dr * dr * 0.5 : kPi * dz * (rhi * rhi - rlo * rlo) * 0.5;
+            if (j == 0 || j == nz) v *= 0.5;
+            const size_t n = (size_t)j * w + i;
+            h->h_vol[n] = v;
+            // finite-volume faces over the node control volume
+            if (i < nr) {
+                const double hz = (j == 0 || j == nz) ? 0.5 * dz : dz;
+                double e = 0.0, cnt = 0.0;
+                if (j > 0) { e += eps[(size_t)(j - 1) * nr + i]; cnt += 1.0; }
+                if (j < nz) { e += eps[(size_t)j * nr + i]; cnt += 1.0; }
+                h->h_gr[n] = 2.0 * kPi * (i + 0.5) * dr * hz * kEps0 * (e / cnt) / dr;
+            }
+            if (j < nz) {
+                const double a = (i > 0) ? (i - 0.5) * dr : 0.0;
+                const double b = (i < nr) ? (i + 0.5) * dr : h->cfg.geom.R;
+                double num = 0.0;
+                if (i > 0) num += eps[(size_t)j * nr + i - 1] * (ri * ri - a * a);
+                if (i < nr) num += eps[(size_t)j * nr + i] * (b * b - ri * ri);
+                h->h_gz[n] = kPi * (b * b - a * a) * kEps0 * (num / (b * b - a * a)) / dz;
+            }
+        }
+    return PIC_OK;
+}
+
+int upload_geometry(pic_handle* h) {
+    std::vector<double> invd((size_t)h->nr);
+    for (int i = 0; i < h->nr; ++i) invd[i] = std::ldexp(1.0, -2 * kFBits) / (double)(2 * i + 1);
+    hipStream_t s = h->stream;
+    HIP_OK(hipMemcpyAsync(h->cell_kind, h->h_cell_kind.data(), h->h_cell_kind.size(), hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(h->node_kind, h->h_node_kind.data(), h->h_node_kind.size(), hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(h->vol, h->h_vol.data(), h->h_vol.size() * 8, hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(h->gr, h->h_gr.data(), h->h_gr.size() * 8, hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(h->gz, h->h_gz.data(), h->h_gz.size() * 8, hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(h->invd, invd.data(), invd.size() * 8, hipMemcpyHostToDevice, s));
+    HIP_OK(hipStreamSynchronize(s));
+    return PIC_OK;
+}
+
+// Level sizes: coarsen in z only while cells are much wider in r (strong
+// axial coupling), in r only in the opposite case, else in both; stop at
+// <= 300 nodes.  A grid too small to coarsen gets one identity level so the
+// coarse solve is exact.
+int mg_plan(pic_handle* h) {
+    int nr = h->nr, nz = h->nz;
+    double dr = h->dr, dz = h->dz;
+    int l = 0;
+    h->lv[0].nr = nr; h->lv[0].nz = nz;
+    for (;;) {
+        const long nn = (long)(nr + 1) * (nz + 1);
+        if (nn <= 300 || l + 1 >= kMaxLevels) break;
+        const bool can_r = (nr % 2 == 0) && nr >= 4, can_z = (nz % 2 == 0) && nz >= 4;
+        int cr = 1, cz = 1;
+        if (dr > 1.5 * dz) { if (can_z) cz = 2; else if (can_r) cr = 2; }
+        else if (dz > 1.5 * dr) { if (can_r) cr = 2; else if (can_z) cz = 2; }
+        else { if (can_r) cr = 2; if (can_z) cz = 2; }
+        if (cr == 1 && cz == 1) break;
+        h->lv[l].cr = cr; h->lv[l].cz = cz;
+        nr /= cr; nz /= cz; dr *= cr; dz *= cz;
+        ++l;
+        h->lv[l].nr = nr; h->lv[l].nz = nz;
+    }
+    if (l == 0) {
+        h->lv[0].cr = h->lv[0].cz = 1;
+        l = 1;
+        h->lv[1].nr = nr; h->lv[1].nz = nz;
+    }
+    h->nlev = l + 1;
+    for (int k = 0; k < h->nlev; ++k) {
+        h->lv[k].w = h->lv[k].nr + 1;
+        h->lv[k].nn = h->lv[k].w * (h->lv[k].nz + 1);
+    }
+    h->lv[h->nlev - 1].cr = h->lv[h->nlev - 1].cz = 1;
+    // activity of the coarsest nodes follows the injection chain from level 0
+    int cnr = h->lv[h->nlev - 1].nr, cnz = h->lv[h->nlev - 1].nz;
+    int cnt = 0;
+    for (int J = 0; J <= cnz; ++J)
+        for (int I = 0; I <= cnr; ++I) {
+            int i = I, j = J;
+            for (int k = h->nlev - 2; k >= 0; --k) { i *= h->lv[k].cr; j *= h->lv[k].cz; }
+            if (h->h_node_kind[(size_t)j * h->w + i] < 0) ++cnt;
+        }
+    if (cnt > kMaxCoarse) return PIC_E_CONFIG;
+    h->ncoarse = cnt;
+    return PIC_OK;
+}
+
+static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Carver {
+    char* base;
+    size_t off = 0;
+    template <typename T>
+    T* take(size_t count) {
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += align_up(std::max<size_t>(count, 1) * sizeof(T));
+        return p;
+    }
+};
+
+size_t layout(pic_handle* h, char* base) {
+    Carver c{base};
+    const size_t nn = (size_t)h->nn, nc = (size_t)h->ncell;
+    h->cell_kind = c.take<uint8_t>(nc);
+    h->node_kind = c.take<int8_t>(nn);
+    h->vol = c.take<double>(nn);
+    h->gr = c.take<double>(nn);
+    h->gz = c.take<double>(nn);
+    h->invd = c.take<double>((size_t)h->nr);
+    size_t capmax = (size_t)std::max<int64_t>(std::max(h->cap[0], h->cap[1]), 1);
+    for (int sp = 0; sp < 2; ++sp)
+        for (int b = 0; b < 2; ++b)
+            for (int k = 0; k < 9; ++k) h->buf[sp][b].f[k] = c.take<float>((size_t)std::max<int64_t>(h->cap[sp], 1));
+    for (int b = 0; b < 2; ++b) {
+        h->keys[b] = c.take<uint32_t>(capmax);
+        h->idx[b] = c.take<uint32_t>(capmax);
+    }
+    const size_t mch = (size_t)h->max_chunks;
+    h->hist = c.take<uint32_t>(256 * mch);
+    h->bsum = c.take<uint32_t>((256 * mch + 4095) / 4096 + 1);
+    h->stage = c.take<Birth>(mch * kStageCap);
+    h->stage_cnt = c.take<int>(mch);
+    h->stage_off = c.take<int>(mch);
+    for (int b = 0; b < 2; ++b)
+        for (int sp = 0; sp < 2; ++sp) h->dep[b][sp] = c.take<unsigned long long>(nn);
+    h->wallq = c.take<unsigned long long>(nn);
+    for (int sp = 0; sp < 2; ++sp) {
+        h->psum[sp] = c.take<unsigned long long>(nn);
+        h->plast[sp] = c.take<unsigned long long>(nn);
+    }
+    h->chi = c.take<double>(nn); h->Q = c.take<double>(nn);
+    h->ar = c.take<double>(nn); h->az = c.take<double>(nn);
+    h->phi = c.take<double>(nn); h->phiL = c.take<double>(nn); h->zeroQ = c.take<double>(nn);
+    h->ar32 = c.take<float>(nn); h->az32 = c.take<float>(nn);
+    h->E = c.take<float2>(nn);
+    h->r64 = c.take<double>(nn); h->x64 = c.take<double>(nn); h->z64 = c.take<double>(nn);
+    h->p64 = c.take<double>(nn); h->q64 = c.take<double>(nn);
+    h->r32 = c.take<float>(nn); h->x32 = c.take<float>(nn); h->z32 = c.take<float>(nn);
+    h->p32 = c.take<float>(nn); h->q32 = c.take<float>(nn);
+    h->part = c.take<double>(2 * kRedBlocks);
+    for (int l = 0; l < h->nlev; ++l) {
+        Level& L = h->lv[l];
+        const size_t m = (size_t)L.nn;
+        for (int k = 0; k < 9; ++k) {
+            L.A64[k] = (l > 0) ? c.take<double>(m) : nullptr;
+            L.A32[k] = (l > 0) ? c.take<float>(m) : nullptr;
+        }
+        L.x64 = c.take<double>(m); L.y64 = c.take<double>(m); L.b64 = c.take<double>(m); L.res64 = c.take<double>(m);
+        L.x32 = c.take<float>(m); L.y32 = c.take<float>(m); L.b32 = c.take<float>(m); L.res32 = c.take<float>(m);
+    }
+    const size_t cnn = (size_t)h->lv[h->nlev - 1].nn;
+    h->cmap = c.take<int>(cnn + kMaxCoarse);
+    h->cinv64 = c.take<double>((size_t)kMaxCoarse * kMaxCoarse);
+    h->cinv32 = c.take<float>((size_t)kMaxCoarse * kMaxCoarse);
+    const size_t spp = (size_t)h->cfg.run.steps_per_period;
+    h->serU = c.take<double>(spp); h->serI = c.take<double>(spp);
+    h->lastU = c.take<double>(spp); h->lastI = c.take<double>(spp);
+    h->ctr = c.take<DevCounters>(1);
+    h->sc = c.take<DevScalars>(1);
+    return c.off;
+}
+
+}  // namespace pic
+
+namespace {
+
+void ev_record(pic_handle* h, int phase, hipEvent_t* begin) {
+    if (!h->timing) return;
+    hipEvent_t e;
+    if (h->ev_pool.empty()) {
+        if (hipEventCreate(&e) != hipSuccess) return;
+    } else {
+        e = h->ev_pool.back();
+        h->ev_pool.pop_back();
+    }
+    hipEventRecord(e, h->stream);
+    if (phase < 0) {
+        *begin = e;
+    } else {
+        h->ev_pending.push_back({phase, {*begin, e}});
+    }
+}
+
+void ev_collect(pic_handle* h) {
+    for (auto& p : h->ev_pending) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, p.second.first, p.second.second) == hipSuccess) h->ms[p.first] += ms;
+        h->ev_pool.push_back(p.second.first);
+        h->ev_pool.push_back(p.second.second);
+    }
+    h->ev_pending.clear();
+}
+
+__global__ void k_init_circuit(const double* part, DevScalars* s, const DevCounters* ctr, double U0) {
+    __shared__ double a[kRedBlocks];
+    for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) a[i] = part[i];
+    __syncthreads();
+    for (int o = kRedBlocks / 2; o > 0; o >>= 1) {
+        for (int i = threadIdx.x; i < o; i += blockDim.x) a[i] += a[i + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        s->Q_P = a[0];
+        s->U_E = U0;
+        s->Q_E = s->C_eq * U0 + a[0];
+        s->powered_prev = (double)((long long)ctr->absorbed[1][1] - (long long)ctr->absorbed[0][1]);
+        s->one = 1.0;
+    }
+}
+
+__global__ void k_set_slots(DevCounters* c, long long ne, long long ni) {
+    c->n_slots[0] = ne;
+    c->n_slots[1] = ni;
+}
+
+__global__ void k_set_state(DevScalars* s, double t, double QE, double UE, double c0, double c1, double c2, double c3,
+                            double c4, double Ceq) {
+    s->t = t; s->Q_E = QE; s->U_E = UE;
+    s->circ[0] = c0; s->circ[1] = c1; s->circ[2] = c2; s->circ[3] = c3; s->circ[4] = c4;
+    s->C_eq = Ceq;
+}
+
+__global__ void k_set_one(DevScalars* s) { s->one = 1.0; }
+
+__global__ void k_set_U(DevScalars* s, double U) { s->U_E = U; }
+
+__global__ void k_set_cmap(int* cmap, const int* src, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) cmap[i] = src[i];
+}
+
+int build_cmap(pic_handle* h) {
+    const Level& L = h->lv[h->nlev - 1];
+    std::vector<int> m((size_t)L.nn + kMaxCoarse, -1);
+    int cnt = 0;
+    for (int J = 0; J <= L.nz; ++J)
+        for (int I = 0; I <= L.nr; ++I) {
+            int i = I, j = J;
+            for (int k = h->nlev - 2; k >= 0; --k) { i *= h->lv[k].cr; j *= h->lv[k].cz; }
+            if (h->h_node_kind[(size_t)j * h->w + i] < 0) {
+                m[(size_t)J * L.w + I] = cnt;
+                m[(size_t)L.nn + cnt] = J * L.w + I;
+                ++cnt;
+            }
+        }
+    HIP_OK(hipMemcpyAsync(h->cmap, m.data(), m.size() * sizeof(int), hipMemcpyHostToDevice, h->stream));
+    HIP_OK(hipStreamSynchronize(h->stream));
+    return PIC_OK;
+}
+
+int load_plasma(pic_handle* h) {
+    const pic_run& r = h->cfg.run;
+    std::vector<double> cdf;
+    std::vector<int> cell;
+    double acc = 0.0;
+    for (int j = 0; j < h->nz; ++j)
+        for (int i = 0; i < h->nr; ++i) {
+            if (h->h_cell_kind[(size_t)j * h->nr + i] != 0) continue;
+            const double r0 = i * h->dr, r1 = (i + 1) * h->dr;
+            acc += kPi * (r1 * r1 - r0 * r0) * h->dz;
+            cdf.push_back(acc);
+            cell.push_back(j * h->nr + i);
+        }
+    const double vvac = acc;
+    h->w_unit = r.n0 * vvac / (double)(r.n_e > 0 ? r.n_e : 1);
+    h->qunit = kQE * h->w_unit * std::ldexp(1.0, -kKBits);
+    const double base = 0.5 * h->dt * h->dt * kQE * kQE * h->w_unit * std::ldexp(1.0, -kKBits) / kEps0;
+    h->chi_c[0] = base / kME;
+    h->chi_c[1] = base / kMAr;
+    if (!r.load || cdf.empty()) return PIC_OK;
+    if ((size_t)cdf.size() > (size_t)h->nn) return PIC_E_CONFIG;
+    // the solver vectors serve as upload space for the CDF
+    double* d_cdf = h->r64;
+    int* d_cell = reinterpret_cast<int*>(h->x64);
+    HIP_OK(hipMemcpyAsync(d_cdf, cdf.data(), cdf.size() * 8, hipMemcpyHostToDevice, h->stream));
+    HIP_OK(hipMemcpyAsync(d_cell, cell.data(), cell.size() * 4, hipMemcpyHostToDevice, h->stream));
+    const int64_t n[2] = {r.n_e, r.n_i};
+    const double T[2] = {r.Te_eV, r.Ti_eV}, M[2] = {kME, kMAr};
+    for (int sp = 0; sp < 2; ++sp) {
+        if (n[sp] <= 0) continue;
+        const double W = (r.n0 * vvac / (double)n[sp]) / h->w_unit;
+        const double vth = std::sqrt(kQE * T[sp] / M[sp]);
+        launch_load(h, sp, d_cdf, d_cell, (int)cdf.size(), vvac, n[sp], (float)W, (float)vth);
+    }
+    HIP_OK(hipStreamSynchronize(h->stream));
+    return PIC_OK;
+}
+
+int sync_err(pic_handle* h) {
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return PIC_E_HIP;
+    if (hipMemcpy(h->h_ctr, h->ctr, sizeof(DevCounters), hipMemcpyDeviceToHost) != hipSuccess) return PIC_E_HIP;
+    if (h->h_ctr->err == 2) h->sticky_err = PIC_E_CAPACITY;
+    return PIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pic_workspace_size(const pic_config* cfg, size_t* bytes_out) {
+    if (!bytes_out) return PIC_E_ARG;
+    int rc = validate(cfg);
+    if (rc) return rc;
+    pic_handle* h = new (std::nothrow) pic_handle();
+    if (!h) return PIC_E_ARG;
+    h->cfg = *cfg;
+    derive(h);
+    host_geometry(h);
+    rc = mg_plan(h);
+    if (rc == PIC_OK) *bytes_out = layout(h, nullptr) + 256;
+    delete h;
+    return rc;
+}
+
+int pic_init(const pic_config* cfg, void* dev_workspace, size_t bytes, void* hip_stream, pic_handle** out) {
+    if (!out || !dev_workspace) return PIC_E_ARG;
+    *out = nullptr;
+    size_t need = 0;
+    int rc = pic_workspace_size(cfg, &need);
+    if (rc) return rc;
+    if (bytes < need) return PIC_E_ARG;
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return PIC_E_NODEVICE;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return PIC_E_NODEVICE;
+    pic_handle* h = new (std::nothrow) pic_handle();
+    if (!h) return PIC_E_ARG;
+    h->cfg = *cfg;
+    h->stream = (hipStream_t)hip_stream;
+    h->timing = cfg->run.timing != 0;
+    derive(h);
+    host_geometry(h);
+    rc = mg_plan(h);
+    if (rc) { delete h; return rc; }
+    char* base = (char*)(((uintptr_t)dev_workspace + 255) & ~(uintptr_t)255);
+    h->ws = base;
+    h->ws_bytes = bytes;
+    const size_t used = layout(h, base);
+    if (used + (size_t)(base - (char*)dev_workspace) > bytes) { delete h; return PIC_E_ARG; }
+    if (hipHostMalloc((void**)&h->h_sc, sizeof(DevScalars), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&h->h_ctr, sizeof(DevCounters), hipHostMallocDefault) != hipSuccess) {
+        pic_free(h);
+        return PIC_E_HIP;
+    }
+    // zero the whole workspace with a fill kernel
+    launch_zero_u64((unsigned long long*)base, used / 8, h->stream);
+    rc = upload_geometry(h);
+    if (rc == PIC_OK) rc = build_cmap(h);
+    if (rc == PIC_OK) rc = load_plasma(h);
+    if (rc) { pic_free(h); return rc; }
+    const int64_t n0[2] = {cfg->run.load ? cfg->run.n_e : 0, cfg->run.load ? cfg->run.n_i : 0};
+    hipLaunchKernelGGL(k_set_slots, dim3(1), dim3(1), 0, h->stream, h->ctr, (long long)n0[0], (long long)n0[1]);
+    hipLaunchKernelGGL(k_set_one, dim3(1), dim3(1), 0, h->stream, h->sc);
+    h->dep_cur = 0;
+    h->cur[0] = h->cur[1] = 0;
+    // first prediction (a_bar = 0) and deposit
+    for (int sp = 0; sp < 2; ++sp) launch_predict_deposit(h, sp);
+    // vacuum operator, multigrid, Laplace solution and C_eq (Eqs. 6-7)
+    launch_faces(h);                 // chi = 0 from the zeroed workspace
+    rc = refresh_laplace(h);
+    if (rc) { pic_free(h); return rc; }
+    // initial electrode charge: U_E(0) with the induced charge of the load
+    launch_assemble(h);
+    hipLaunchKernelGGL(k_init_circuit, dim3(1), dim3(256), 0, h->stream, (const double*)h->part, h->sc,
+                       (const DevCounters*)h->ctr, cfg->circ.kind == PIC_IDEAL_SOURCE ? cfg->circ.U_dc : 0.0);
+    // the assembly above added the first deposit to the period sums: undo
+    launch_zero_u64(h->psum[0], (size_t)h->nn, h->stream);
+    launch_zero_u64(h->psum[1], (size_t)h->nn, h->stream);
+    rc = sync_err(h);
+    if (rc) { pic_free(h); return rc; }
+    *out = h;
+    return PIC_OK;
+}
+
+int pic_step(pic_handle* h, int32_t nsteps) {
+    if (!h) return PIC_E_ARG;
+    if (nsteps < 0) return PIC_E_ARG;
+    const pic_config& c = h->cfg;
+    const int spp = c.run.steps_per_period;
+    for (int32_t k = 0; k < nsteps; ++k) {
+        hipEvent_t b0 = nullptr, b1 = nullptr, b2 = nullptr, b3 = nullptr;
+        ev_record(h, -1, &b0);
+        launch_assemble(h);
+        launch_faces(h);
+        launch_circuit(h);
+        int32_t it = 0;
+        double rel = 0.0;
+        int rc = field_solve(h, h->phi, h->Q, &h->sc->U_E, c.solver.tol, c.solver.method, &it, &rel);
+        h->solver_iters = it;
+        h->solver_relres = rel;
+        if (rc != PIC_OK) return rc;
+        launch_efield(h);
+        ev_record(h, 4, &b0);
+        h->dep_cur = 1 - h->dep_cur;
+        ev_record(h, -1, &b1);
+        launch_particles(h, 0);
+        ev_record(h, 0, &b1);
+        ev_record(h, -1, &b1);
+        launch_particles(h, 1);
+        ev_record(h, 1, &b1);
+        ev_record(h, -1, &b2);
+        launch_births(h);
+        ev_record(h, 2, &b2);
+        h->step++;
+        if (c.run.sort_every > 0 && h->step % c.run.sort_every == 0) {
+            ev_record(h, -1, &b3);
+            launch_sort(h, 0);
+            launch_sort(h, 1);
+            ev_record(h, 3, &b3);
+        }
+        if (h->step % spp == 0) {
+            ev_record(h, -1, &b3);
+            rc = refresh_laplace(h);
+            if (rc) return rc;
+            launch_period_roll(h);
+            ev_record(h, 5, &b3);
+            h->periods_done++;
+            h->have_last = 1;
+        }
+        if (h->timing) h->timed_steps++;
+    }
+    if (hipGetLastError() != hipSuccess) return PIC_E_HIP;
+    return PIC_OK;
+}
+
+int pic_reset_timers(pic_handle* h) {
+    if (!h) return PIC_E_ARG;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return PIC_E_HIP;
+    ev_collect(h);
+    for (double& m : h->ms) m = 0.0;
+    h->timed_steps = 0;
+    return PIC_OK;
+}
+
+int pic_diag(pic_handle* h, pic_diag_out* out, const pic_diag_buffers* bufs) {
+    if (!h || !out) return PIC_E_ARG;
+    int rc = sync_err(h);
+    if (rc) return rc;
+    ev_collect(h);
+    DevScalars sc;
+    if (hipMemcpy(&sc, h->sc, sizeof(sc), hipMemcpyDeviceToHost) != hipSuccess) return PIC_E_HIP;
+    const DevCounters& ct = *h->h_ctr;
+    std::memset(out, 0, sizeof(*out));
+    out->t = sc.t; out->U_E = sc.U_E; out->Q_E = sc.Q_E; out->C_eq = sc.C_eq; out->Q_P = sc.Q_P;
+    out->I_ccp = sc.I_ccp; out->dt = h->dt; out->w_unit = h->w_unit; out->n_gas = h->n_gas;
+    for (int k = 0; k < 5; ++k) out->circ[k] = sc.circ[k];
+    for (int sp = 0; sp < 2; ++sp) {
+        out->nu_max[sp] = h->nu_max[sp];
+        out->thresh[sp] = h->thresh[sp];
+        out->n_slots[sp] = ct.n_slots[sp];
+        for (int k = 0; k < 4; ++k) {
+            out->absorbed[sp][k] = (int64_t)ct.absorbed[sp][k];
+            out->coll[sp][k] = (int64_t)ct.coll[sp][k];
+        }
+    }
+    long long alive[2] = {0, 0};
+    launch_count_alive(h, alive);
+    out->n_alive[0] = alive[0];
+    out->n_alive[1] = alive[1];
+    out->step = h->step;
+    out->periods_done = h->periods_done;
+    out->born = ct.born;
+    out->numax_violations = ct.viol;
+    out->solver_iters = h->solver_iters;
+    out->solver_outer = h->solver_outer;
+    out->solver_relres = h->solver_relres;
+    out->ms_particles[0] = h->ms[0]; out->ms_particles[1] = h->ms[1];
+    out->ms_births = h->ms[2]; out->ms_sort = h->ms[3]; out->ms_field = h->ms[4]; out->ms_refresh = h->ms[5];
+    out->timed_steps = h->timed_steps;
+    out->deposit_fallback = (int64_t)ct.fallback;
+    out->error = h->sticky_err;
+    const int spp = h->cfg.run.steps_per_period;
+    std::vector<double> U(spp), I(spp);
+    if (hipMemcpy(U.data(), h->lastU, spp * 8, hipMemcpyDeviceToHost) != hipSuccess) return PIC_E_HIP;
+    if (hipMemcpy(I.data(), h->lastI, spp * 8, hipMemcpyDeviceToHost) != hipSuccess) return PIC_E_HIP;
+    if (h->have_last) {
+        for (int k = 0; k < 6; ++k) {
+            double a = 0, b = 0, c = 0, d = 0;
+            for (int n = 0; n < spp; ++n) {
+                const double ph = 2.0 * kPi * (double)k * (double)n / (double)spp;
+                a += U[n] * std::cos(ph); b -= U[n] * std::sin(ph);
+                c += I[n] * std::cos(ph); d -= I[n] * std::sin(ph);
+            }
+            const double s = (k == 0) ? 1.0 / spp : 2.0 / spp;
+            out->harm_U_re[k] = a * s; out->harm_U_im[k] = b * s;
+            out->harm_I_re[k] = c * s; out->harm_I_im[k] = d * s;
+        }
+    }
+    if (bufs) {
+        if (bufs->U_E) std::memcpy(bufs->U_E, U.data(), spp * 8);
+        if (bufs->I_ccp) std::memcpy(bufs->I_ccp, I.data(), spp * 8);
+        if (bufs->phi && hipMemcpy(bufs->phi, h->phi, (size_t)h->nn * 8, hipMemcpyDeviceToHost) != hipSuccess)
+            return PIC_E_HIP;
+        double* dens[2] = {bufs->n_e, bufs->n_i};
+        for (int sp = 0; sp < 2; ++sp) {
+            if (!dens[sp]) continue;
+            std::vector<unsigned long long> s((size_t)h->nn);
+            if (hipMemcpy(s.data(), h->plast[sp], (size_t)h->nn * 8, hipMemcpyDeviceToHost) != hipSuccess)
+                return PIC_E_HIP;
+            const double u = h->w_unit * std::ldexp(1.0, -kKBits) / spp;
+            for (size_t n = 0; n < s.size(); ++n) dens[sp][n] = (double)(long long)s[n] * u / h->h_vol[n];
+        }
+    }
+    return PIC_OK;
+}
+
+int pic_free(pic_handle* h) {
+    if (!h) return PIC_E_ARG;
+    hipStreamSynchronize(h->stream);
+    ev_collect(h);
+    for (hipEvent_t e : h->ev_pool) hipEventDestroy(e);
+    if (h->h_sc) hipHostFree(h->h_sc);
+    if (h->h_ctr) hipHostFree(h->h_ctr);
+    delete h;
+    return PIC_OK;
+}
+
+const char* pic_strerror(int code) {
+    switch (code) {
+    case PIC_OK: return "ok";
+    case PIC_E_CONFIG: return "invalid configuration";
+    case PIC_E_CAPACITY: return "particle capacity exceeded by births";
+    case PIC_E_SOLVER: return "field solve did not converge";
+    case PIC_E_HIP: return "HIP runtime error";
+    case PIC_E_NONFINITE: return "non-finite value in the field solve";
+    case PIC_E_STATE: return "call not valid in this state";
+    case PIC_E_ARG: return "bad argument";
+    case PIC_E_NODEVICE: return "no gfx950 device is current";
+    }
+    return "unknown error";
+}
+
+int pic_get_particles(pic_handle* h, int32_t species, float* host9, int64_t* n) {
+    if (!h || !host9 || !n || species < 0 || species > 1) return PIC_E_ARG;
+    int rc = sync_err(h);
+    if (rc) return rc;
+    const int64_t m = h->h_ctr->n_slots[species];
+    const int64_t cap = h->cap[species];
+    for (int k = 0; k < 9; ++k)
+        if (m > 0 && hipMemcpy(host9 + (size_t)k * cap, h->buf[species][h->cur[species]].f[k], (size_t)m * 4,
+                               hipMemcpyDeviceToHost) != hipSuccess)
+            return PIC_E_HIP;
+    *n = m;
+    return PIC_OK;
+}
+
+int pic_set_particles(pic_handle* h, int32_t species, const float* host9, int64_t n) {
+    if (!h || (!host9 && n > 0) || species < 0 || species > 1 || n < 0 || n > h->cap[species]) return PIC_E_ARG;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return PIC_E_HIP;
+    for (int k = 0; k < 9; ++k)
+        if (n > 0 && hipMemcpy(h->buf[species][h->cur[species]].f[k], host9 + (size_t)k * n, (size_t)n * 4,
+                               hipMemcpyHostToDevice) != hipSuccess)
+            return PIC_E_HIP;
+    long long ns[2];
+    DevCounters ct;
+    if (hipMemcpy(&ct, h->ctr, sizeof(ct), hipMemcpyDeviceToHost) != hipSuccess) return PIC_E_HIP;
+    ns[0] = ct.n_slots[0];
+    ns[1] = ct.n_slots[1];
+    ns[species] = n;
+    hipLaunchKernelGGL(k_set_slots, dim3(1), dim3(1), 0, h->stream, h->ctr, ns[0], ns[1]);
+    return hipStreamSynchronize(h->stream) == hipSuccess ? PIC_OK : PIC_E_HIP;
+}
+
+int pic_redeposit(pic_handle* h) {
+    if (!h) return PIC_E_ARG;
+    launch_redeposit(h);
+    return hipStreamSynchronize(h->stream) == hipSuccess ? PIC_OK : PIC_E_HIP;
+}
+
+int pic_get_grid(pic_handle* h, int32_t which, void* host) {
+    if (!h || !host) return PIC_E_ARG;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return PIC_E_HIP;
+    const size_t nn = (size_t)h->nn;
+    const void* src = nullptr;
+    size_t bytes = nn * 8;
+    switch (which) {
+    case PIC_G_DEP_E: src = h->dep[h->dep_cur][0]; break;
+    case PIC_G_DEP_I: src = h->dep[h->dep_cur][1]; break;
+    case PIC_G_PHI: src = h->phi; break;
+    case PIC_G_CHI: src = h->chi; break;
+    case PIC_G_WALLQ: src = h->wallq; break;
+    case PIC_G_PHI_L: src = h->phiL; break;
+    case PIC_G_Q: src = h->Q; break;
+    case PIC_G_AR: src = h->ar; break;
+    case PIC_G_AZ: src = h->az; break;
+    case PIC_G_ER:
+    case PIC_G_EZ: {
+        std::vector<float2> e(nn);
+        if (hipMemcpy(e.data(), h->E, nn * sizeof(float2), hipMemcpyDeviceToHost) != hipSuccess) return PIC_E_HIP;
+        float* o = (float*)host;
+        for (size_t n = 0; n < nn; ++n) o[n] = (which == PIC_G_ER) ? e[n].x : e[n].y;
+        return PIC_OK;
+    }
+    default: return PIC_E_ARG;
+    }
+    return hipMemcpy(host, src, bytes, hipMemcpyDeviceToHost) == hipSuccess ? PIC_OK : PIC_E_HIP;
+}
+
+int pic_set_grid(pic_handle* h, int32_t which, const void* host) {
+    if (!h || !host) return PIC_E_ARG;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return PIC_E_HIP;
+    void* dst = nullptr;
+    switch (which) {
+    case PIC_G_DEP_E: dst = h->dep[h->dep_cur][0]; break;
+    case PIC_G_DEP_I: dst = h->dep[h->dep_cur][1]; break;
+    case PIC_G_WALLQ: dst = h->wallq; break;
+    case PIC_G_PHI: dst = h->phi; break;
+    case PIC_G_PHI_L: dst = h->phiL; break;
+    default: return PIC_E_ARG;
+    }
+    return hipMemcpy(dst, host, (size_t)h->nn * 8, hipMemcpyHostToDevice) == hipSuccess ? PIC_OK : PIC_E_HIP;
+}
+
+int pic_sort_now(pic_handle* h, int32_t species, int64_t* perm_out) {
+    if (!h || species < 0 || species > 1) return PIC_E_ARG;
+    launch_sort(h, species);
+    int rc = sync_err(h);
+    if (rc) return rc;
+    if (perm_out) {
+        const int64_t n = h->h_ctr->n_slots[species];
+        std::vector<uint32_t> p((size_t)std::max<int64_t>(n, 1));
+        if (n > 0 && hipMemcpy(p.data(), h->idx[h->sort_src_last], (size_t)n * 4, hipMemcpyDeviceToHost) != hipSuccess)
+            return PIC_E_HIP;
+        for (int64_t k = 0; k < n; ++k) perm_out[k] = p[k];
+    }
+    return PIC_OK;
+}
+
+int pic_solve_once(pic_handle* h, const double* Q, const double* chi, double U_E, double tol, double* phi_inout,
+                   int32_t* iters, double* relres) {
+    if (!h || !Q || !chi || !phi_inout) return PIC_E_ARG;
+    const size_t nn = (size_t)h->nn;
+    if (hipMemcpyAsync(h->Q, Q, nn * 8, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+        hipMemcpyAsync(h->chi, chi, nn * 8, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+        hipMemcpyAsync(h->phi, phi_inout, nn * 8, hipMemcpyHostToDevice, h->stream) != hipSuccess)
+        return PIC_E_HIP;
+    hipLaunchKernelGGL(k_set_U, dim3(1), dim3(1), 0, h->stream, h->sc, U_E);
+    launch_faces(h);
+    mg_rebuild(h);
+    int rc = field_solve(h, h->phi, h->Q, &h->sc->U_E, tol, h->cfg.solver.method, iters, relres);
+    if (hipMemcpy(phi_inout, h->phi, nn * 8, hipMemcpyDeviceToHost) != hipSuccess) return PIC_E_HIP;
+    return rc;
+}
+
+int pic_set_state(pic_handle* h, const double* st9) {
+    if (!h || !st9) return PIC_E_ARG;
+    hipLaunchKernelGGL(k_set_state, dim3(1), dim3(1), 0, h->stream, h->sc, st9[0], st9[1], st9[2], st9[3], st9[4],
+                       st9[5], st9[6], st9[7], st9[8]);
+    return hipStreamSynchronize(h->stream) == hipSuccess ? PIC_OK : PIC_E_HIP;
+}
+
+}  // extern "C"

@@ -1,0 +1,970 @@
+// field.hip -- the implicit field solve on gfx950 (arXiv 2310.04957,
+// Sec. 2): assembly of the finite-volume form of Eq. (1) with the implicit
+// susceptibility, the equivalent-capacitance electrode voltage and external
+// circuit (Eqs. 5, 8-10), FP64 residuals with FP32 (or FP64) multigrid-
+// preconditioned CG inside iterative refinement, the per-period Laplace
+// solution and energy-method C_eq (Eqs. 6-7), and the node electric field.
+// Reductions use fixed-size grids and fixed orders: results are run-to-run
+// reproducible.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+
+#include "pic_internal.h"
+
+namespace pic {
+
+constexpr double kEps0 = 8.8541878128e-12;
+constexpr double kOmega = 0.7;   // damped-Jacobi weight of the multigrid smoother
+constexpr int kCheckEvery = 4;   // Krylov iterations between host convergence reads
+
+// ------------------------------------------------------------ small utils
+__global__ void k_fill_u64(unsigned long long* p, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0ull;
+}
+__global__ void k_fill_f64(double* p, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+void launch_zero_u64(unsigned long long* p, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_u64, dim3(512), dim3(256), 0, s, p, n);
+}
+void launch_zero_f64(double* p, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_f64, dim3(512), dim3(256), 0, s, p, n);
+}
+
+template <typename T>
+__global__ void k_fill(T* p, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = T(0);
+}
+
+// block sum of a double into part[blockIdx.x * stride + slot]
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w];
+    __syncthreads();
+    return t;  // valid in thread 0
+}
+
+// --------------------------------------------------------------- assembly
+struct AsmArgs {
+    const unsigned long long *dep_e, *dep_i, *wallq;
+    unsigned long long *next_e, *next_i, *psum_e, *psum_i;
+    const double *vol, *phiL;
+    const int8_t* nk;
+    double *chi, *Q, *part;
+    double ce, ci, qunit;
+    int nn;
+};
+
+// chi_n = 1/2 dt^2 sum_s (q_s^2/m_s) n_s / eps0 (the D1 linearised response),
+// Q_n = node charge of the predicted positions plus the dielectric surface
+// charge; also the period sums, the clearing of the next deposit buffer and
+// the partial sums of Q_P = -sum phi_L Q.
+__global__ __launch_bounds__(256) void k_assemble(AsmArgs a) {
+    __shared__ double sh[4];
+    double qp = 0.0;
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < a.nn; n += gridDim.x * blockDim.x) {
+        long long Ne = (long long)a.dep_e[n], Ni = (long long)a.dep_i[n];
+        long long W = (long long)a.wallq[n];
+        a.chi[n] = (a.ce * (double)Ne + a.ci * (double)Ni) / a.vol[n];
+        double q = a.qunit * (double)(Ni - Ne + W);
+        a.Q[n] = q;
+        a.psum_e[n] += (unsigned long long)Ne;
+        a.psum_i[n] += (unsigned long long)Ni;
+        a.next_e[n] = 0ull;
+        a.next_i[n] = 0ull;
+        if (a.nk[n] < 0) qp -= a.phiL[n] * q;
+    }
+    double t = block_sum(qp, sh);
+    if (threadIdx.x == 0) a.part[blockIdx.x] = t;
+}
+
+void launch_assemble(pic_handle* h) {
+    AsmArgs a;
+    int c = h->dep_cur, o = 1 - h->dep_cur;
+    a.dep_e = h->dep[c][0]; a.dep_i = h->dep[c][1]; a.wallq = h->wallq;
+    a.next_e = h->dep[o][0]; a.next_i = h->dep[o][1];
+    a.psum_e = h->psum[0]; a.psum_i = h->psum[1];
+    a.vol = h->vol; a.phiL = h->phiL; a.nk = h->node_kind;
+    a.chi = h->chi; a.Q = h->Q; a.part = h->part;
+    a.ce = h->chi_c[0]; a.ci = h->chi_c[1]; a.qunit = h->qunit; a.nn = h->nn;
+    hipLaunchKernelGGL(k_assemble, dim3(kRedBlocks), dim3(256), 0, h->stream, a);
+}
+
+// face coefficients a = geometry x eps0 eps_r x (1 + mean chi), FP64 and
+// FP32 (the latter divided by eps0)
+__global__ __launch_bounds__(256) void k_faces(const double* chi, const double* gr, const double* gz, double* ar,
+                                               double* az, float* ar32, float* az32, int nr, int nz) {
+    const int w = nr + 1, nn = w * (nz + 1);
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += gridDim.x * blockDim.x) {
+        int i = n % w, j = n / w;
+        double a1 = (i < nr) ? gr[n] * (1.0 + 0.5 * (chi[n] + chi[n + 1])) : 0.0;
+        double a2 = (j < nz) ? gz[n] * (1.0 + 0.5 * (chi[n] + chi[n + w])) : 0.0;
+        ar[n] = a1; az[n] = a2;
+        ar32[n] = (float)(a1 / kEps0);
+        az32[n] = (float)(a2 / kEps0);
+    }
+}
+
+void launch_faces(pic_handle* h) {
+    hipLaunchKernelGGL(k_faces, dim3(1024), dim3(256), 0, h->stream, h->chi, h->gr, h->gz, h->ar, h->az, h->ar32,
+                       h->az32, h->nr, h->nz);
+}
+
+// ---------------------------------------------------------------- circuit
+struct CircArgs {
+    DevScalars* sc;
+    const DevCounters* ctr;
+    const double* part;
+    double *serU, *serI;
+    int k, kind, substeps;
+    double dt, qunit, freq, U_amp, U_dc, R_s, C_m1, C_m2, L_m, R_m, C_stray, L_stray, R_stray, C_b, R_b, L_b;
+};
+
+// y: L-match (Eq. 10) Q1, Q2, I2, Q_ccp, I_stray; series RLC (Eq. 9) Q_b, I_b;
+// y[5] the electrode charge of Eq. (8).  U_E = (Q_E - Q_P)/C_eq.
+__device__ void circ_f(const CircArgs& a, double C_eq, double Q_P, double I_conv, double t, const double* y,
+                       double* dy) {
+    const double U_E = (y[5] - Q_P) / C_eq;
+    const double Us = a.U_amp * sin(2.0 * 3.14159265358979323846 * a.freq * t) + a.U_dc;
+    for (int k = 0; k < 6; ++k) dy[k] = 0.0;
+    if (a.kind == PIC_LMATCH) {
+        const double Um1 = (y[0] - y[1]) / a.C_m1;
+        dy[0] = (Us - Um1) / a.R_s;
+        dy[1] = y[2];
+        dy[2] = (Um1 - U_E - y[1] / a.C_m2 - y[2] * a.R_m) / a.L_m;
+        dy[3] = y[2] - y[4];
+        dy[4] = (U_E - (y[1] - y[3]) / a.C_stray - y[4] * a.R_stray) / a.L_stray;
+        dy[5] = dy[3] + I_conv;
+    } else if (a.kind == PIC_SERIES_RLC) {
+        dy[0] = y[1];
+        dy[1] = (Us - U_E - y[0] / a.C_b - y[1] * a.R_b) / a.L_b;
+        dy[5] = y[1] + I_conv;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_circuit(CircArgs a) {
+    __shared__ double sh[kRedBlocks];
+    for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) sh[i] = a.part[i];
+    __syncthreads();
+    for (int o = kRedBlocks / 2; o > 0; o >>= 1) {
+        for (int i = threadIdx.x; i < o; i += blockDim.x) sh[i] += sh[i + o];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    DevScalars* s = a.sc;
+    const double Q_P = sh[0];
+    const long long pc = (long long)a.ctr->absorbed[1][1] - (long long)a.ctr->absorbed[0][1];
+    const double I_conv = ((double)pc - s->powered_prev) * a.qunit / a.dt;
+    s->powered_prev = (double)pc;
+    s->Q_P = Q_P;
+    const double t0 = s->t, t1 = t0 + a.dt;
+    if (a.kind == PIC_IDEAL_SOURCE) {
+        const double U = a.U_amp * sin(2.0 * 3.14159265358979323846 * a.freq * t1) + a.U_dc;
+        const double QE = s->C_eq * U + Q_P;
+        s->I_ccp = (QE - s->Q_E) / a.dt - I_conv;
+        s->Q_E = QE;
+        s->U_E = U;
+    } else {
+        double y[6];
+        for (int k = 0; k < 5; ++k) y[k] = s->circ[k];
+        y[5] = s->Q_E;
+        const int qi = (a.kind == PIC_LMATCH) ? 3 : 0;
+        const double q0 = y[qi];
+        const int M = a.substeps > 0 ? a.substeps : 1;
+        const double hh = a.dt / M;
+        for (int m = 0; m < M; ++m) {
+            const double t = t0 + m * hh;
+            double k1[6], k2[6], k3[6], k4[6], yt[6];
+            circ_f(a, s->C_eq, Q_P, I_conv, t, y, k1);
+            for (int k = 0; k < 6; ++k) yt[k] = y[k] + 0.5 * hh * k1[k];
+            circ_f(a, s->C_eq, Q_P, I_conv, t + 0.5 * hh, yt, k2);
+            for (int k = 0; k < 6; ++k) yt[k] = y[k] + 0.5 * hh * k2[k];
+            circ_f(a, s->C_eq, Q_P, I_conv, t + 0.5 * hh, yt, k3);
+            for (int k = 0; k < 6; ++k) yt[k] = y[k] + hh * k3[k];
+            circ_f(a, s->C_eq, Q_P, I_conv, t + hh, yt, k4);
+            for (int k = 0; k < 6; ++k) y[k] += hh / 6.0 * (k1[k] + 2.0 * k2[k] + 2.0 * k3[k] + k4[k]);
+        }
+        s->I_ccp = (y[qi] - q0) / a.dt;
+        for (int k = 0; k < 5; ++k) s->circ[k] = y[k];
+        s->Q_E = y[5];
+        s->U_E = (y[5] - Q_P) / s->C_eq;
+    }
+    s->t = t1;
+    a.serU[a.k] = s->U_E;
+    a.serI[a.k] = s->I_ccp;
+}
+
+void launch_circuit(pic_handle* h) {
+    CircArgs a;
+    const pic_circuit& c = h->cfg.circ;
+    a.sc = h->sc; a.ctr = h->ctr; a.part = h->part; a.serU = h->serU; a.serI = h->serI;
+    a.k = (int)(h->step % h->cfg.run.steps_per_period);
+    a.kind = c.kind; a.substeps = c.substeps;
+    a.dt = h->dt; a.qunit = h->qunit;
+    a.freq = c.freq; a.U_amp = c.U_amp; a.U_dc = c.U_dc; a.R_s = c.R_s; a.C_m1 = c.C_m1; a.C_m2 = c.C_m2;
+    a.L_m = c.L_m; a.R_m = c.R_m; a.C_stray = c.C_stray; a.L_stray = c.L_stray; a.R_stray = c.R_stray;
+    a.C_b = c.C_b; a.R_b = c.R_b; a.L_b = c.L_b;
+    hipLaunchKernelGGL(k_circuit, dim3(1), dim3(256), 0, h->stream, a);
+}
+
+// ---------------------------------------------------------- FP64 residual
+__device__ __forceinline__ double dir_val(int8_t k, double U) { return k == 1 ? U : 0.0; }
+
+// r = Q - K phi on unknown nodes, Dirichlet neighbours at their conductor
+// value; partial sums of r.r and of b.b (b = Q + Dirichlet lift)
+__global__ __launch_bounds__(256) void k_resid64(const double* ar, const double* az, const int8_t* nk,
+                                                 const double* Q, const double* phi, const double* Up, double* r,
+                                                 double* part, int nr, int nz) {
+    __shared__ double sh[4];
+    const int w = nr + 1, nn = w * (nz + 1);
+    const double U = *Up;
+    double rr = 0.0, bb = 0.0;
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += gridDim.x * blockDim.x) {
+        const int8_t k0 = nk[n];
+        if (k0 >= 0) { r[n] = 0.0; continue; }
+        const int i = n % w, j = n / w;
+        const double pn = phi[n];
+        const double q = Q ? Q[n] : 0.0;
+        double Kp = 0.0, b = q;
+        if (i > 0) { int m = n - 1; int8_t km = nk[m]; double v = km >= 0 ? dir_val(km, U) : phi[m];
+                     Kp += ar[m] * (pn - v); if (km >= 0) b += ar[m] * v; }
+        if (i < nr) { int m = n + 1; int8_t km = nk[m]; double v = km >= 0 ? dir_val(km, U) : phi[m];
+                      Kp += ar[n] * (pn - v); if (km >= 0) b += ar[n] * v; }
+        if (j > 0) { int m = n - w; int8_t km = nk[m]; double v = km >= 0 ? dir_val(km, U) : phi[m];
+                     Kp += az[m] * (pn - v); if (km >= 0) b += az[m] * v; }
+        if (j < nz) { int m = n + w; int8_t km = nk[m]; double v = km >= 0 ? dir_val(km, U) : phi[m];
+                      Kp += az[n] * (pn - v); if (km >= 0) b += az[n] * v; }
+        const double res = q - Kp;
+        r[n] = res;
+        rr += res * res;
+        bb += b * b;
+    }
+    double t1 = block_sum(rr, sh);
+    double t2 = block_sum(bb, sh);
+    if (threadIdx.x == 0) { part[2 * blockIdx.x] = t1; part[2 * blockIdx.x + 1] = t2; }
+}
+
+// final sums; decides the outer convergence and the inner target
+__global__ __launch_bounds__(256) void k_reduce_resid(const double* part, DevScalars* s, double tol, int fp64) {
+    __shared__ double a[kRedBlocks], b[kRedBlocks];
+    for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) { a[i] = part[2 * i]; b[i] = part[2 * i + 1]; }
+    __syncthreads();
+    for (int o = kRedBlocks / 2; o > 0; o >>= 1) {
+        for (int i = threadIdx.x; i < o; i += blockDim.x) { a[i] += a[i + o]; b[i] += b[i + o]; }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double rr = a[0], bb = b[0];
+        s->rr0 = rr;
+        s->bb = bb;
+        s->nonfinite = !(isfinite(rr) && isfinite(bb));
+        s->relres = (bb > 0.0) ? sqrt(rr / bb) : 0.0;
+        s->scale = (rr > 0.0) ? 1.0 / sqrt(rr) : 0.0;
+        // inner target on r.r: FP64 -> the final tolerance (with margin),
+        // FP32 on the normalised residual -> set by the caller
+        s->target = fp64 ? 0.25 * tol * tol * bb : s->target;
+    }
+}
+
+// ------------------------------------------------------ Krylov kernels (T)
+template <typename T>
+__global__ __launch_bounds__(256) void k_scale_to(const double* r64, T* r, T* x, const DevScalars* s, int nn) {
+    const double sc = s->scale;
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += gridDim.x * blockDim.x) {
+        r[n] = (T)(r64[n] * sc);
+        x[n] = T(0);
+    }
+}
+
+// level-0 operator (5-point) on unknown nodes; neighbours that are
+// conductors carry zero correction
+template <typename T>
+__device__ __forceinline__ T apply0(const T* ar, const T* az, const int8_t* nk, const T* x, int n, int i, int j,
+                                    int nr, int nz, int w, T& diag) {
+    T d = T(0), off = T(0);
+    if (i > 0) { T a = ar[n - 1]; d += a; if (nk[n - 1] < 0) off += a * x[n - 1]; }
+    if (i < nr) { T a = ar[n]; d += a; if (nk[n + 1] < 0) off += a * x[n + 1]; }
+    if (j > 0) { T a = az[n - w]; d += a; if (nk[n - w] < 0) off += a * x[n - w]; }
+    if (j < nz) { T a = az[n]; d += a; if (nk[n + w] < 0) off += a * x[n + w]; }
+    diag = d;
+    return d * x[n] - off;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_spmv_dot(const T* ar, const T* az, const int8_t* nk, const T* p, T* q,
+                                                  double* part, const DevScalars* s, int nr, int nz) {
+    __shared__ double sh[4];
+    if (s->done) return;
+    const int w = nr + 1, nn = w * (nz + 1);
+    double acc = 0.0;
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += gridDim.x * blockDim.x) {
+        if (nk[n] >= 0) { q[n] = T(0); continue; }
+        T d;
+        T v = apply0(ar, az, nk, p, n, n % w, n / w, nr, nz, w, d);
+        q[n] = v;
+        acc += (double)p[n] * (double)v;
+    }
+    double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_dot(const T* a, const T* b, double* part, const DevScalars* s, int nn) {
+    __shared__ double sh[4];
+    if (s->done) return;
+    double acc = 0.0;
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += gridDim.x * blockDim.x)
+        acc += (double)a[n] * (double)b[n];
+    double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_update_xr(T* x, T* r, const T* p, const T* q, double* part,
+                                                   const DevScalars* s, int nn) {
+    __shared__ double sh[4];
+    if (s->done) return;
+    const T al = (T)s->alpha;
+    double acc = 0.0;
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += gridDim.x * blockDim.x) {
+        x[n] += al * p[n];
+        T rn = r[n] - al * q[n];
+        r[n] = rn;
+        acc += (double)rn * (double)rn;
+    }
+    double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_update_p(T* p, const T* z, const DevScalars* s, int nn) {
+    if (s->done) return;
+    const T be = (T)s->beta;
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += gridDim.x * blockDim.x) p[n] = z[n] + be * p[n];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_copy(T* dst, const T* src, const DevScalars* s, int nn) {
+    if (s->done) return;
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += gridDim.x * blockDim.x) dst[n] = src[n];
+}
+
+// what = 0: rz from the partials (start of CG); 1: alpha = rz / pq;
+// 2: r.r against the target (sets done); 3: beta = rz_new / rz
+__global__ __launch_bounds__(256) void k_reduce(const double* part, DevScalars* s, int what) {
+    __shared__ double a[kRedBlocks];
+    if (s->done && what != 0) return;
+    for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) a[i] = part[i];
+    __syncthreads();
+    for (int o = kRedBlocks / 2; o > 0; o >>= 1) {
+        for (int i = threadIdx.x; i < o; i += blockDim.x) a[i] += a[i + o];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const double v = a[0];
+    if (what == 0) {
+        s->rz = v;
+        s->done = !(v > 0.0);
+        s->iters = 0;
+    } else if (what == 1) {
+        s->pq = v;
+        if (!(v > 0.0) || !isfinite(v)) { s->done = 1; s->nonfinite = !isfinite(v); }
+        else s->alpha = s->rz / v;
+    } else if (what == 2) {
+        s->rr = v;
+        s->iters += 1;
+        if (!isfinite(v)) { s->done = 1; s->nonfinite = 1; }
+        else if (v <= s->target) s->done = 1;
+    } else {
+        s->rz_new = v;
+        s->beta = v / s->rz;
+        s->rz = v;
+    }
+}
+
+__global__ void k_begin_cg(DevScalars* s) { s->done = 0; s->iters = 0; }
+
+// ------------------------------------------------------------- multigrid
+// level 0: damped Jacobi and residual on the 5-point operator
+template <typename T>
+__global__ __launch_bounds__(256) void k_jac0(const T* ar, const T* az, const int8_t* nk, const T* xin, const T* b,
+                                              T* xout, const DevScalars* s, int nr, int nz, int first) {
+    if (s->done) return;
+    const int w = nr + 1, nn = w * (nz + 1);
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += gridDim.x * blockDim.x) {
+        if (nk[n] >= 0) { xout[n] = T(0); continue; }
+        T d;
+        const int i = n % w, j = n / w;
+        if (first) {
+            T dd = T(0);
+            if (i > 0) dd += ar[n - 1];
+            if (i < nr) dd += ar[n];
+            if (j > 0) dd += az[n - w];
+            if (j < nz) dd += az[n];
+            xout[n] = (T)kOmega * b[n] / dd;
+        } else {
+            T ax = apply0(ar, az, nk, xin, n, i, j, nr, nz, w, d);
+            xout[n] = xin[n] + (T)kOmega * (b[n] - ax) / d;
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_res0(const T* ar, const T* az, const int8_t* nk, const T* x, const T* b,
+                                              T* res, const DevScalars* s, int nr, int nz) {
+    if (s->done) return;
+    const int w = nr + 1, nn = w * (nz + 1);
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += gridDim.x * blockDim.x) {
+        if (nk[n] >= 0) { res[n] = T(0); continue; }
+        T d;
+        res[n] = b[n] - apply0(ar, az, nk, x, n, n % w, n / w, nr, nz, w, d);
+    }
+}
+
+struct Sten {
+    const void* A[9];
+};
+
+template <typename T>
+__device__ __forceinline__ T apply9(const Sten& S, const T* x, int n, int i, int j, int nr, int nz, int w, T& d) {
+    T acc = T(0);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const int di = k % 3 - 1, dj = k / 3 - 1;
+        const int i2 = i + di, j2 = j + dj;
+        if (i2 < 0 || j2 < 0 || i2 > nr || j2 > nz) continue;
+        acc += ((const T*)S.A[k])[n] * x[n + dj * w + di];
+    }
+    d = ((const T*)S.A[4])[n];
+    return acc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_jac9(Sten S, const T* xin, const T* b, T* xout, const DevScalars* s, int nr,
+                                              int nz, int first) {
+    if (s->done) return;
+    const int w = nr + 1, nn = w * (nz + 1);
+    const T* D = (const T*)S.A[4];
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += gridDim.x * blockDim.x) {
+        const T d0 = D[n];
+        if (d0 == T(0)) { xout[n] = T(0); continue; }
+        if (first) { xout[n] = (T)kOmega * b[n] / d0; continue; }
+        T d;
+        T ax = apply9(S, xin, n, n % w, n / w, nr, nz, w, d);
+        xout[n] = xin[n] + (T)kOmega * (b[n] - ax) / d;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_res9(Sten S, const T* x, const T* b, T* res, const DevScalars* s, int nr,
+                                              int nz) {
+    if (s->done) return;
+    const int w = nr + 1, nn = w * (nz + 1);
+    const T* D = (const T*)S.A[4];
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += gridDim.x * blockDim.x) {
+        if (D[n] == T(0)) { res[n] = T(0); continue; }
+        T d;
+        res[n] = b[n] - apply9(S, x, n, n % w, n / w, nr, nz, w, d);
+    }
+}
+
+__device__ __forceinline__ float pw1(int i, int I, int c) {
+    if (c == 1) return i == I ? 1.0f : 0.0f;
+    int d = i - 2 * I;
+    return d == 0 ? 1.0f : ((d == 1 || d == -1) ? 0.5f : 0.0f);
+}
+
+// b_c = P^T res_f; activity of fine nodes from the node kinds (level 0) or
+// the diagonal (coarser levels); coarse nodes inactive when their diagonal
+// is zero
+template <typename T>
+__global__ __launch_bounds__(256) void k_restrict(const T* res, const int8_t* nk, const T* Df, int fnr, int fnz,
+                                                  T* bc, const T* Dc, int cnr, int cnz, int cr, int cz,
+                                                  const DevScalars* s) {
+    if (s->done) return;
+    const int fw = fnr + 1, cw = cnr + 1, cn = cw * (cnz + 1);
+    for (int N = blockIdx.x * blockDim.x + threadIdx.x; N < cn; N += gridDim.x * blockDim.x) {
+        if (Dc[N] == T(0)) { bc[N] = T(0); continue; }
+        const int I = N % cw, J = N / cw;
+        T acc = T(0);
+        for (int j = cz * J - (cz - 1); j <= cz * J + (cz - 1); ++j) {
+            if (j < 0 || j > fnz) continue;
+            for (int i = cr * I - (cr - 1); i <= cr * I + (cr - 1); ++i) {
+                if (i < 0 || i > fnr) continue;
+                const int nf = j * fw + i;
+                const bool act = nk ? (nk[nf] < 0) : (Df[nf] != T(0));
+                if (!act) continue;
+                acc += (T)(pw1(i, I, cr) * pw1(j, J, cz)) * res[nf];
+            }
+        }
+        bc[N] = acc;
+    }
+}
+
+// y_f += P y_c on active fine nodes
+template <typename T>
+__global__ __launch_bounds__(256) void k_prolong(T* yf, const int8_t* nk, const T* Df, int fnr, int fnz, const T* yc,
+                                                 const T* Dc, int cnr, int cnz, int cr, int cz, const DevScalars* s) {
+    if (s->done) return;
+    const int fw = fnr + 1, cw = cnr + 1, fn = fw * (fnz + 1);
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < fn; n += gridDim.x * blockDim.x) {
+        const bool act = nk ? (nk[n] < 0) : (Df[n] != T(0));
+        if (!act) continue;
+        const int i = n % fw, j = n / fw;
+        const int I0 = i / cr, J0 = j / cz;
+        T acc = T(0);
+        for (int J = J0 - 1; J <= J0 + 1; ++J) {
+            if (J < 0 || J > cnz) continue;
+            for (int I = I0 - 1; I <= I0 + 1; ++I) {
+                if (I < 0 || I > cnr) continue;
+                const int N = J * cw + I;
+                if (Dc[N] == T(0)) continue;
+                const float p = pw1(i, I, cr) * pw1(j, J, cz);
+                if (p != 0.0f) acc += (T)p * yc[N];
+            }
+        }
+        yf[n] += acc;
+    }
+}
+
+// coarsest level: y = A^-1 b with the precomputed dense inverse
+template <typename T>
+__global__ __launch_bounds__(256) void k_coarse(const T* b, T* y, const int* cmap, const int* clist, const T* inv,
+                                                int nc, int cn, const DevScalars* s) {
+    __shared__ T sb[kMaxCoarse];
+    if (s->done) return;
+    for (int k = threadIdx.x; k < nc; k += blockDim.x) sb[k] = b[clist[k]];
+    for (int n = threadIdx.x; n < cn; n += blockDim.x)
+        if (cmap[n] < 0) y[n] = T(0);
+    __syncthreads();
+    for (int r = threadIdx.x; r < nc; r += blockDim.x) {
+        T acc = T(0);
+        for (int c = 0; c < nc; ++c) acc += inv[r * nc + c] * sb[c];
+        y[clist[r]] = acc;
+    }
+}
+
+// ------------------------------------------------- multigrid construction
+// Galerkin product A_c = P^T A_f P, one coarse node per thread.  A coarse
+// node is active only if the fine node it injects into is active, which
+// keeps P of full column rank and A_c positive definite.
+__device__ __forceinline__ double fine_coef0(const double* ar, const double* az, const int8_t* nk, int n, int i, int j,
+                                             int nr, int nz, int w, int k) {
+    if (nk[n] >= 0) return 0.0;
+    switch (k) {
+    case 4: {
+        double d = 0.0;
+        if (i > 0) d += ar[n - 1];
+        if (i < nr) d += ar[n];
+        if (j > 0) d += az[n - w];
+        if (j < nz) d += az[n];
+        return d;
+    }
+    case 3: return (i > 0 && nk[n - 1] < 0) ? -ar[n - 1] : 0.0;
+    case 5: return (i < nr && nk[n + 1] < 0) ? -ar[n] : 0.0;
+    case 1: return (j > 0 && nk[n - w] < 0) ? -az[n - w] : 0.0;
+    case 7: return (j < nz && nk[n + w] < 0) ? -az[n] : 0.0;
+    default: return 0.0;
+    }
+}
+
+struct RapArgs {
+    const double* ar;
+    const double* az;
+    const int8_t* nk;   // non-null: the fine level is level 0
+    const double* Af[9];
+    double* Ac[9];
+    int fnr, fnz, cnr, cnz, cr, cz;
+};
+
+__device__ __forceinline__ bool fine_active(const RapArgs& a, int nf) {
+    return a.nk ? (a.nk[nf] < 0) : (a.Af[4][nf] != 0.0);
+}
+
+__global__ __launch_bounds__(256) void k_rap(RapArgs a) {
+    const int fw = a.fnr + 1, cw = a.cnr + 1, cn = cw * (a.cnz + 1);
+    for (int N = blockIdx.x * blockDim.x + threadIdx.x; N < cn; N += gridDim.x * blockDim.x) {
+        const int I = N % cw, J = N / cw;
+        double acc[9];
+        for (int k = 0; k < 9; ++k) acc[k] = 0.0;
+        if (fine_active(a, (a.cz * J) * fw + a.cr * I)) {
+            for (int j = a.cz * J - (a.cz - 1); j <= a.cz * J + (a.cz - 1); ++j) {
+                if (j < 0 || j > a.fnz) continue;
+                for (int i = a.cr * I - (a.cr - 1); i <= a.cr * I + (a.cr - 1); ++i) {
+                    if (i < 0 || i > a.fnr) continue;
+                    const int nf = j * fw + i;
+                    if (!fine_active(a, nf)) continue;
+                    const double p1 = (double)(pw1(i, I, a.cr) * pw1(j, J, a.cz));
+                    if (p1 == 0.0) continue;
+                    for (int k = 0; k < 9; ++k) {
+                        const int di = k % 3 - 1, dj = k / 3 - 1;
+                        const int i2 = i + di, j2 = j + dj;
+                        if (i2 < 0 || j2 < 0 || i2 > a.fnr || j2 > a.fnz) continue;
+                        const double v = a.nk ? fine_coef0(a.ar, a.az, a.nk, nf, i, j, a.fnr, a.fnz, fw, k)
+                                              : a.Af[k][nf];
+                        if (v == 0.0) continue;
+                        const int nf2 = j2 * fw + i2;
+                        if (!fine_active(a, nf2)) continue;
+                        for (int k2 = 0; k2 < 9; ++k2) {
+                            const int I2 = I + k2 % 3 - 1, J2 = J + k2 / 3 - 1;
+                            if (I2 < 0 || J2 < 0 || I2 > a.cnr || J2 > a.cnz) continue;
+                            if (!fine_active(a, (a.cz * J2) * fw + a.cr * I2)) continue;
+                            const double p2 = (double)(pw1(i2, I2, a.cr) * pw1(j2, J2, a.cz));
+                            if (p2 != 0.0) acc[k2] += p1 * v * p2;
+                        }
+                    }
+                }
+            }
+        }
+        for (int k = 0; k < 9; ++k) a.Ac[k][N] = acc[k];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_to32(const double* a, float* b, int n, double scale) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) b[i] = (float)(a[i] * scale);
+}
+
+// dense matrix of the coarsest operator over its active nodes
+__global__ __launch_bounds__(256) void k_coarse_dense(Sten S, const int* cmap, double* M, int nc, int nr, int nz) {
+    const int w = nr + 1, cn = w * (nz + 1);
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nc * nc; t += gridDim.x * blockDim.x) M[t] = 0.0;
+    __syncthreads();
+    for (int n = threadIdx.x; n < cn; n += blockDim.x) {
+        const int a = cmap[n];
+        if (a < 0) continue;
+        const int i = n % w, j = n / w;
+        for (int k = 0; k < 9; ++k) {
+            const int i2 = i + k % 3 - 1, j2 = j + k / 3 - 1;
+            if (i2 < 0 || j2 < 0 || i2 > nr || j2 > nz) continue;
+            const int b = cmap[j2 * w + i2];
+            if (b < 0) continue;
+            M[a * nc + b] += ((const double*)S.A[k])[n];
+        }
+    }
+}
+
+// in-place Gauss-Jordan inverse of an SPD matrix (no pivoting), one block
+__global__ __launch_bounds__(1024) void k_invert(double* M, int n) {
+    __shared__ double rowk[kMaxCoarse], colk[kMaxCoarse];
+    for (int k = 0; k < n; ++k) {
+        __syncthreads();
+        const double piv = M[k * n + k];
+        for (int c = threadIdx.x; c < n; c += blockDim.x) {
+            rowk[c] = (c == k) ? 1.0 / piv : M[k * n + c] / piv;
+            colk[c] = M[c * n + k];
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+            const int r = t / n, c = t % n;
+            if (r == k) continue;
+            const double f = colk[r];
+            M[t] = (c == k) ? -f * rowk[k] : M[t] - f * rowk[c];
+        }
+        __syncthreads();
+        for (int c = threadIdx.x; c < n; c += blockDim.x) M[k * n + c] = rowk[c];
+    }
+}
+
+void mg_rebuild(pic_handle* h) {
+    hipStream_t st = h->stream;
+    for (int l = 0; l + 1 < h->nlev; ++l) {
+        Level& F = h->lv[l];
+        Level& C = h->lv[l + 1];
+        RapArgs a;
+        a.ar = h->ar; a.az = h->az;
+        a.nk = (l == 0) ? h->node_kind : nullptr;
+        for (int k = 0; k < 9; ++k) { a.Af[k] = F.A64[k]; a.Ac[k] = C.A64[k]; }
+        a.fnr = F.nr; a.fnz = F.nz; a.cnr = C.nr; a.cnz = C.nz; a.cr = F.cr; a.cz = F.cz;
+        hipLaunchKernelGGL(k_rap, dim3((C.nn + 255) / 256), dim3(256), 0, st, a);
+        for (int k = 0; k < 9; ++k)
+            hipLaunchKernelGGL(k_to32, dim3((C.nn + 255) / 256), dim3(256), 0, st, (const double*)C.A64[k], C.A32[k],
+                               C.nn, 1.0 / kEps0);
+    }
+    Level& L = h->lv[h->nlev - 1];
+    if (h->ncoarse > 0) {
+        Sten S;
+        for (int k = 0; k < 9; ++k) S.A[k] = L.A64[k];
+        if (h->nlev == 1) {
+            // a single level: the coarse matrix is the level-0 operator (test-sized grids only)
+        }
+        hipLaunchKernelGGL(k_coarse_dense, dim3(1), dim3(256), 0, st, S, h->cmap, h->cinv64, h->ncoarse, L.nr, L.nz);
+        hipLaunchKernelGGL(k_invert, dim3(1), dim3(1024), 0, st, h->cinv64, h->ncoarse);
+        hipLaunchKernelGGL(k_to32, dim3(64), dim3(256), 0, st, (const double*)h->cinv64, h->cinv32,
+                           h->ncoarse * h->ncoarse, kEps0);
+    }
+}
+
+template <typename T>
+struct VecSet;
+template <>
+struct VecSet<double> {
+    static double* x(Level& L) { return L.x64; }
+    static double* y(Level& L) { return L.y64; }
+    static double* b(Level& L) { return L.b64; }
+    static double* res(Level& L) { return L.res64; }
+    static Sten sten(Level& L) { Sten S; for (int k = 0; k < 9; ++k) S.A[k] = L.A64[k]; return S; }
+    static const double* diag(Level& L) { return L.A64[4]; }
+    static const double* ar(pic_handle* h) { return h->ar; }
+    static const double* az(pic_handle* h) { return h->az; }
+    static const double* cinv(pic_handle* h) { return h->cinv64; }
+};
+template <>
+struct VecSet<float> {
+    static float* x(Level& L) { return L.x32; }
+    static float* y(Level& L) { return L.y32; }
+    static float* b(Level& L) { return L.b32; }
+    static float* res(Level& L) { return L.res32; }
+    static Sten sten(Level& L) { Sten S; for (int k = 0; k < 9; ++k) S.A[k] = L.A32[k]; return S; }
+    static const float* diag(Level& L) { return L.A32[4]; }
+    static const float* ar(pic_handle* h) { return h->ar32; }
+    static const float* az(pic_handle* h) { return h->az32; }
+    static const float* cinv(pic_handle* h) { return h->cinv32; }
+};
+
+static inline dim3 grid_for(int n) { return dim3(std::min(1024, (n + 255) / 256)); }
+
+// symmetric V(2,2) cycle: on level l, y = M_l b (b in the level's b buffer;
+// level 0 takes b0 and writes y0)
+template <typename T>
+static void vcycle(pic_handle* h, int l, const T* b0, T* y0) {
+    using V = VecSet<T>;
+    hipStream_t st = h->stream;
+    Level& L = h->lv[l];
+    const DevScalars* s = h->sc;
+    const T* b = (l == 0) ? b0 : V::b(L);
+    T* y = (l == 0) ? y0 : V::y(L);
+    T* x = V::x(L);
+    if (l == h->nlev - 1) {
+        if (l == 0) {
+            // single-level hierarchy: smoothing only
+            hipLaunchKernelGGL(k_jac0<T>, grid_for(L.nn), dim3(256), 0, st, V::ar(h), V::az(h), h->node_kind, x, b, y,
+                               s, L.nr, L.nz, 1);
+            return;
+        }
+        hipLaunchKernelGGL(k_coarse<T>, dim3(1), dim3(256), 0, st, b, y, h->cmap, h->cmap + L.nn, V::cinv(h),
+                           h->ncoarse, L.nn, s);
+        return;
+    }
+    Level& C = h->lv[l + 1];
+    if (l == 0) {
+        hipLaunchKernelGGL(k_jac0<T>, grid_for(L.nn), dim3(256), 0, st, V::ar(h), V::az(h), h->node_kind, x, b, x, s,
+                           L.nr, L.nz, 1);
+        hipLaunchKernelGGL(k_jac0<T>, grid_for(L.nn), dim3(256), 0, st, V::ar(h), V::az(h), h->node_kind, x, b, y, s,
+                           L.nr, L.nz, 0);
+        hipLaunchKernelGGL(k_res0<T>, grid_for(L.nn), dim3(256), 0, st, V::ar(h), V::az(h), h->node_kind, y, b,
+                           V::res(L), s, L.nr, L.nz);
+    } else {
+        Sten S = V::sten(L);
+        hipLaunchKernelGGL(k_jac9<T>, grid_for(L.nn), dim3(256), 0, st, S, x, b, x, s, L.nr, L.nz, 1);
+        hipLaunchKernelGGL(k_jac9<T>, grid_for(L.nn), dim3(256), 0, st, S, x, b, y, s, L.nr, L.nz, 0);
+        hipLaunchKernelGGL(k_res9<T>, grid_for(L.nn), dim3(256), 0, st, S, y, b, V::res(L), s, L.nr, L.nz);
+    }
+    const int8_t* nk = (l == 0) ? h->node_kind : nullptr;
+    const T* Df = (l == 0) ? nullptr : V::diag(L);
+    hipLaunchKernelGGL(k_restrict<T>, grid_for(C.nn), dim3(256), 0, st, (const T*)V::res(L), nk, Df, L.nr, L.nz,
+                       V::b(C), V::diag(C), C.nr, C.nz, L.cr, L.cz, s);
+    vcycle<T>(h, l + 1, nullptr, nullptr);
+    hipLaunchKernelGGL(k_prolong<T>, grid_for(L.nn), dim3(256), 0, st, y, nk, Df, L.nr, L.nz, (const T*)V::y(C),
+                       V::diag(C), C.nr, C.nz, L.cr, L.cz, s);
+    if (l == 0) {
+        hipLaunchKernelGGL(k_jac0<T>, grid_for(L.nn), dim3(256), 0, st, V::ar(h), V::az(h), h->node_kind, y, b, x, s,
+                           L.nr, L.nz, 0);
+        hipLaunchKernelGGL(k_jac0<T>, grid_for(L.nn), dim3(256), 0, st, V::ar(h), V::az(h), h->node_kind, x, b, y, s,
+                           L.nr, L.nz, 0);
+    } else {
+        Sten S = V::sten(L);
+        hipLaunchKernelGGL(k_jac9<T>, grid_for(L.nn), dim3(256), 0, st, S, y, b, x, s, L.nr, L.nz, 0);
+        hipLaunchKernelGGL(k_jac9<T>, grid_for(L.nn), dim3(256), 0, st, S, x, b, y, s, L.nr, L.nz, 0);
+    }
+}
+
+// preconditioned CG on the level-0 operator; r is overwritten, x receives
+// the correction.  Returns the iteration count.
+template <typename T>
+static int pcg(pic_handle* h, T* r, T* x, T* z, T* p, T* q, int max_iter, int* err) {
+    using V = VecSet<T>;
+    hipStream_t st = h->stream;
+    const int nn = h->nn;
+    DevScalars* s = h->sc;
+    hipLaunchKernelGGL(k_begin_cg, dim3(1), dim3(1), 0, st, s);
+    hipLaunchKernelGGL(k_fill<T>, grid_for(nn), dim3(256), 0, st, x, nn);
+    vcycle<T>(h, 0, r, z);
+    hipLaunchKernelGGL(k_copy<T>, grid_for(nn), dim3(256), 0, st, p, (const T*)z, s, nn);
+    hipLaunchKernelGGL(k_dot<T>, dim3(kRedBlocks), dim3(256), 0, st, (const T*)r, (const T*)z, h->part, s, nn);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, st, (const double*)h->part, s, 0);
+    int it = 0;
+    for (; it < max_iter; ++it) {
+        hipLaunchKernelGGL(k_spmv_dot<T>, dim3(kRedBlocks), dim3(256), 0, st, V::ar(h), V::az(h), h->node_kind,
+                           (const T*)p, q, h->part, s, h->nr, h->nz);
+        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, st, (const double*)h->part, s, 1);
+        hipLaunchKernelGGL(k_update_xr<T>, dim3(kRedBlocks), dim3(256), 0, st, x, r, (const T*)p, (const T*)q,
+                           h->part, s, nn);
+        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, st, (const double*)h->part, s, 2);
+        vcycle<T>(h, 0, r, z);
+        hipLaunchKernelGGL(k_dot<T>, dim3(kRedBlocks), dim3(256), 0, st, (const T*)r, (const T*)z, h->part, s, nn);
+        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, st, (const double*)h->part, s, 3);
+        hipLaunchKernelGGL(k_update_p<T>, grid_for(nn), dim3(256), 0, st, p, (const T*)z, s, nn);
+        if ((it + 1) % kCheckEvery == 0 || it + 1 == max_iter) {
+            hipMemcpyAsync(h->h_sc, s, sizeof(DevScalars), hipMemcpyDeviceToHost, st);
+            if (hipStreamSynchronize(st) != hipSuccess) { *err = PIC_E_HIP; return it; }
+            if (h->h_sc->done) break;
+        }
+    }
+    hipMemcpyAsync(h->h_sc, s, sizeof(DevScalars), hipMemcpyDeviceToHost, st);
+    if (hipStreamSynchronize(st) != hipSuccess) { *err = PIC_E_HIP; return it; }
+    if (h->h_sc->nonfinite) *err = PIC_E_NONFINITE;
+    return h->h_sc->iters;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_add_phi(double* phi, const T* x, const int8_t* nk, const DevScalars* s,
+                                                 int nn, int scaled) {
+    // FP32 inner: x solves (K/eps0) x = r / ||r||, so K^-1 r = x ||r|| / eps0
+    const double f = scaled ? (1.0 / s->scale) / kEps0 : 1.0;
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += gridDim.x * blockDim.x)
+        if (nk[n] < 0) phi[n] += f * (double)x[n];
+}
+
+__global__ __launch_bounds__(256) void k_set_dirichlet(double* phi, const int8_t* nk, const double* Up, int nn) {
+    const double U = *Up;
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += gridDim.x * blockDim.x)
+        if (nk[n] >= 0) phi[n] = nk[n] == 1 ? U : 0.0;
+}
+
+__global__ void k_set_target(DevScalars* s, double v) { s->target = v; }
+
+int field_solve(pic_handle* h, double* phi, const double* Q, const double* Up, double tol, int method,
+                int32_t* iters_out, double* relres_out) {
+    hipStream_t st = h->stream;
+    const int nn = h->nn;
+    const int fp64 = (method == PIC_SOLVE_MGPCG_FP64);
+    const int max_outer = fp64 ? 4 : 30;
+    int total = 0, outer = 0, err = 0;
+    double rel = 0.0;
+    for (;; ++outer) {
+        hipLaunchKernelGGL(k_resid64, dim3(kRedBlocks), dim3(256), 0, st, (const double*)h->ar, (const double*)h->az,
+                           (const int8_t*)h->node_kind, Q, (const double*)phi, Up, h->r64, h->part, h->nr, h->nz);
+        hipLaunchKernelGGL(k_reduce_resid, dim3(1), dim3(256), 0, st, (const double*)h->part, h->sc, tol, fp64);
+        hipMemcpyAsync(h->h_sc, h->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, st);
+        if (hipStreamSynchronize(st) != hipSuccess) return PIC_E_HIP;
+        rel = h->h_sc->relres;
+        if (h->h_sc->nonfinite) { err = PIC_E_NONFINITE; break; }
+        if (rel <= tol || outer >= max_outer) break;
+        if (fp64) {
+            total += pcg<double>(h, h->r64, h->x64, h->z64, h->p64, h->q64, h->cfg.solver.max_iter, &err);
+            hipLaunchKernelGGL(k_add_phi<double>, grid_for(nn), dim3(256), 0, st, phi, (const double*)h->x64,
+                               (const int8_t*)h->node_kind, (const DevScalars*)h->sc, nn, 0);
+        } else {
+            const double it = h->cfg.solver.inner_tol > 0 ? h->cfg.solver.inner_tol : 1e-4;
+            hipLaunchKernelGGL(k_set_target, dim3(1), dim3(1), 0, st, h->sc, it * it);
+            hipLaunchKernelGGL(k_scale_to<float>, grid_for(nn), dim3(256), 0, st, (const double*)h->r64, h->r32,
+                               h->x32, (const DevScalars*)h->sc, nn);
+            total += pcg<float>(h, h->r32, h->x32, h->z32, h->p32, h->q32, h->cfg.solver.max_iter, &err);
+            hipLaunchKernelGGL(k_add_phi<float>, grid_for(nn), dim3(256), 0, st, phi, (const float*)h->x32,
+                               (const int8_t*)h->node_kind, (const DevScalars*)h->sc, nn, 1);
+        }
+        if (err) break;
+    }
+    hipLaunchKernelGGL(k_set_dirichlet, grid_for(nn), dim3(256), 0, st, phi, (const int8_t*)h->node_kind, Up, nn);
+    h->solver_outer = outer;
+    if (iters_out) *iters_out = total;
+    if (relres_out) *relres_out = rel;
+    if (err) return err;
+    return rel <= tol ? PIC_OK : PIC_E_SOLVER;
+}
+
+// ---------------------------------------------------- Laplace and C_eq
+__global__ __launch_bounds__(256) void k_ceq_part(const double* ar, const double* az, const double* f, double* part,
+                                                  int nr, int nz) {
+    __shared__ double sh[4];
+    const int w = nr + 1, nn = w * (nz + 1);
+    double acc = 0.0;
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += gridDim.x * blockDim.x) {
+        const int i = n % w, j = n / w;
+        if (i < nr) { double d = f[n] - f[n + 1]; acc += ar[n] * d * d; }
+        if (j < nz) { double d = f[n] - f[n + w]; acc += az[n] * d * d; }
+    }
+    double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(256) void k_ceq_final(const double* part, DevScalars* s) {
+    __shared__ double a[kRedBlocks];
+    for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) a[i] = part[i];
+    __syncthreads();
+    for (int o = kRedBlocks / 2; o > 0; o >>= 1) {
+        for (int i = threadIdx.x; i < o; i += blockDim.x) a[i] += a[i + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) s->C_eq = a[0];
+}
+
+// Once per RF period (Sec. 2, text after Eq. 4): rebuild the multigrid
+// hierarchy for the current operator, solve the Laplace problem with the
+// driven electrode at 1 V, and C_eq = sum over edges of a (d phi_L)^2.
+int refresh_laplace(pic_handle* h) {
+    mg_rebuild(h);
+    int32_t it;
+    double rel;
+    int rc = field_solve(h, h->phiL, nullptr, &h->sc->one, 1e-12, PIC_SOLVE_MGPCG_FP64, &it, &rel);
+    if (rc != PIC_OK && rc != PIC_E_SOLVER) return rc;
+    hipLaunchKernelGGL(k_ceq_part, dim3(kRedBlocks), dim3(256), 0, h->stream, (const double*)h->ar,
+                       (const double*)h->az, (const double*)h->phiL, h->part, h->nr, h->nz);
+    hipLaunchKernelGGL(k_ceq_final, dim3(1), dim3(256), 0, h->stream, (const double*)h->part, h->sc);
+    return PIC_OK;
+}
+
+// -------------------------------------------------------------- E field
+// E = -grad phi at nodes: centred inside, one-sided on the z edges and at
+// r = R, E_r = 0 on the axis.
+__global__ __launch_bounds__(256) void k_efield(const double* phi, float2* E, int nr, int nz, double inv_dr,
+                                                double inv_dz) {
+    const int w = nr + 1, nn = w * (nz + 1);
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += gridDim.x * blockDim.x) {
+        const int i = n % w, j = n / w;
+        double er, ez;
+        if (i == 0) er = 0.0;
+        else if (i == nr) er = -(phi[n] - phi[n - 1]) * inv_dr;
+        else er = -(phi[n + 1] - phi[n - 1]) * 0.5 * inv_dr;
+        if (j == 0) ez = -(phi[n + w] - phi[n]) * inv_dz;
+        else if (j == nz) ez = -(phi[n] - phi[n - w]) * inv_dz;
+        else ez = -(phi[n + w] - phi[n - w]) * 0.5 * inv_dz;
+        E[n] = make_float2((float)er, (float)ez);
+    }
+}
+
+void launch_efield(pic_handle* h) {
+    hipLaunchKernelGGL(k_efield, dim3(1024), dim3(256), 0, h->stream, (const double*)h->phi, h->E, h->nr, h->nz,
+                       1.0 / h->dr, 1.0 / h->dz);
+}
+
+__global__ __launch_bounds__(256) void k_period_roll(unsigned long long* pe, unsigned long long* pi,
+                                                     unsigned long long* le, unsigned long long* li, const double* sU,
+                                                     const double* sI, double* lU, double* lI, int nn, int spp) {
+    const int total = nn > spp ? nn : spp;
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < total; n += gridDim.x * blockDim.x) {
+        if (n < nn) {
+            le[n] = pe[n]; li[n] = pi[n];
+            pe[n] = 0ull; pi[n] = 0ull;
+        }
+        if (n < spp) { lU[n] = sU[n]; lI[n] = sI[n]; }
+    }
+}
+
+void launch_period_roll(pic_handle* h) {
+    hipLaunchKernelGGL(k_period_roll, dim3(1024), dim3(256), 0, h->stream, h->psum[0], h->psum[1], h->plast[0],
+                       h->plast[1], (const double*)h->serU, (const double*)h->serI, h->lastU, h->lastI, h->nn,
+                       h->cfg.run.steps_per_period);
+}
+
+}  // namespace pic

@@ -1,0 +1,325 @@
+// pic_device.h -- device-side building blocks of the r-z implicit PIC/MCC
+// hot path for gfx950 (arXiv 2310.04957, Sec. 2): fixed-point locate and
+// cylindrical-volume deposit weights, the D1 direct-implicit push in local
+// (r, theta, z) frames, Philox4x32-10 streams and the null-collision e-Ar /
+// Ar+-Ar kinematics.  All particle arithmetic is FP32 except the integer
+// deposit definition, which is exact FP64 + int64 by construction.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pic {
+
+constexpr int kFBits = 20;        // fraction bits of a fixed-point position (per cell)
+constexpr int kKBits = 32;        // fraction bits of a deposited weight
+constexpr int kTileShift = 4;     // sort / LDS tiles of 16 x 16 cells
+constexpr int kTile = 1 << kTileShift;
+constexpr uint32_t kDeadKey = 0xFFFFFFFFu;
+
+// Geometry as the particle kernels see it.
+struct Geo {
+    int nr, nz, w;                // cells, nodes per row = nr + 1
+    double R, Z, Sr, Sz;          // Sr = 2^F / dr, Sz = 2^F / dz
+    float inv_dr, inv_dz;
+    const double* invd;           // 2^-2F / (2i + 1), i < nr
+    const uint8_t* cell_kind;     // 0 vacuum, 1 dielectric, 2 + id conductor
+    const int8_t* node_kind;      // -1 unknown, >= 0 conductor id
+    int edge_bc[3];               // r=R, z=0, z=Z
+};
+
+struct Loc {
+    int inside, edge, i, j;
+    int64_t fr, fz;
+};
+
+// Fixed-point position q = floor((double)x * 2^F / dx): cell q >> F,
+// fraction q & (2^F - 1).  Outside when !(r < R), !(z > 0), !(z < Z) or
+// the cell index leaves the grid; `edge` then names the edge crossed.
+__device__ __forceinline__ Loc locate(float r, float z, const Geo& g) {
+    Loc L;
+    L.inside = 0; L.edge = 0; L.i = 0; L.j = 0; L.fr = 0; L.fz = 0;
+    double rd = (double)r, zd = (double)z;
+    if (!(rd < g.R)) { L.edge = 0; return L; }
+    if (!(zd > 0.0)) { L.edge = 1; return L; }
+    if (!(zd < g.Z)) { L.edge = 2; return L; }
+    int64_t qr = (int64_t)floor(rd * g.Sr);
+    int64_t qz = (int64_t)floor(zd * g.Sz);
+    int i = (int)(qr >> kFBits), j = (int)(qz >> kFBits);
+    if (i >= g.nr) { L.edge = 0; return L; }
+    if (j >= g.nz) { L.edge = 2; return L; }
+    L.i = i; L.j = j;
+    L.fr = qr & ((1LL << kFBits) - 1);
+    L.fz = qz & ((1LL << kFBits) - 1);
+    L.inside = 1;
+    return L;
+}
+
+// Integer node shares of a particle of relative weight W, in units of
+// 2^-K: radial weight to node i+1 is the volume fraction
+// (r^2 - r_i^2)/(r_{i+1}^2 - r_i^2) = (2 i f + f^2)/(2i + 1), axial weights
+// linear.  Every product is rounded separately (no contraction), so the
+// result is the same on any IEEE machine.  Order: (i,j) (i+1,j) (i,j+1)
+// (i+1,j+1); the four sum to floor(W 2^K) exactly.
+__device__ __forceinline__ void node_shares(const Loc& L, double W, const double* invd, int64_t c[4]) {
+#pragma clang fp contract(off)
+    int64_t nrr = 2LL * (int64_t)L.i * L.fr * (1LL << kFBits) + L.fr * L.fr;
+    double wr = (double)nrr * invd[L.i];
+    double wrb = 1.0 - wr;
+    double wz = (double)L.fz * 0x1p-20;
+    double wzb = (double)((1LL << kFBits) - L.fz) * 0x1p-20;
+    double t;
+    t = W * wr; t = t * wz; t = t * 0x1p32;
+    int64_t c11 = (int64_t)floor(t);
+    t = W * wr; t = t * wzb; t = t * 0x1p32;
+    int64_t c10 = (int64_t)floor(t);
+    t = W * wrb; t = t * wz; t = t * 0x1p32;
+    int64_t c01 = (int64_t)floor(t);
+    t = W * 0x1p32;
+    int64_t tot = (int64_t)floor(t);
+    c[0] = tot - c11 - c10 - c01;
+    c[1] = c10;
+    c[2] = c01;
+    c[3] = c11;
+}
+
+__device__ __forceinline__ int64_t total_share(double W) {
+#pragma clang fp contract(off)
+    double t = W * 0x1p32;
+    return (int64_t)floor(t);
+}
+
+// ---------------------------------------------------------------- Philox
+// Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11).
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c.x;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c.z;
+        uint32_t n0 = (uint32_t)(p1 >> 32) ^ c.y ^ k0;
+        uint32_t n2 = (uint32_t)(p0 >> 32) ^ c.w ^ k1;
+        c = make_uint4(n0, (uint32_t)p1, n2, (uint32_t)p0);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// uniform in (0,1), exactly representable: ((x >> 9) + 1/2) 2^-23
+__device__ __forceinline__ float u01(uint32_t x) { return ((float)(x >> 9) + 0.5f) * 0x1p-23f; }
+
+enum { kPurposeLoad = 0, kPurposeMcc = 1 };
+
+__device__ __forceinline__ uint4 draw(uint32_t slot, uint32_t step, uint32_t purpose, int sp, uint32_t k,
+                                      uint32_t key0, uint32_t key1) {
+    return philox4x32_10(make_uint4(slot, step, purpose * 2u + (uint32_t)sp, k), key0, key1);
+}
+
+// ------------------------------------------------------------ D1 push
+// Particle state between steps: predicted position (r~, z~), the explicit
+// velocity v* and the averaged acceleration a_bar, all in the local
+// (r, theta, z) frame of the particle.
+struct P9 {
+    float r, z, vr, vt, vz, ar, at, az, w;
+};
+
+// correct: a = (q/m) E(x~); x = x~ + dt^2/2 a; v = v* + dt/2 a;
+// a_bar = (a_bar + a)/2; crossing the axis reflects r, v_r, v_t, a_r, a_t.
+__device__ __forceinline__ void d1_correct(P9& p, float Er, float Ez, float qm, float dt) {
+    float ar = qm * Er, az = qm * Ez;
+    float h2 = 0.5f * dt * dt, h = 0.5f * dt;
+    p.r = p.r + h2 * ar;
+    p.z = p.z + h2 * az;
+    p.vr = p.vr + h * ar;
+    p.vz = p.vz + h * az;
+    p.ar = 0.5f * (p.ar + ar);
+    p.at = 0.5f * p.at;
+    p.az = 0.5f * (p.az + az);
+    if (p.r < 0.0f) {
+        p.r = -p.r;
+        p.vr = -p.vr; p.vt = -p.vt;
+        p.ar = -p.ar; p.at = -p.at;
+    }
+}
+
+// predict: v* = v + dt/2 a_bar; straight Cartesian move; rotate v* and
+// a_bar into the new local frame.
+__device__ __forceinline__ void d1_predict(P9& p, float dt) {
+    float h = 0.5f * dt;
+    float vr = p.vr + h * p.ar, vt = p.vt + h * p.at, vz = p.vz + h * p.az;
+    float X = p.r + dt * vr, Y = dt * vt;
+    float rn = sqrtf(X * X + Y * Y);
+    float c = 1.0f, s = 0.0f;
+    if (rn > 0.0f) {
+        float inv = 1.0f / rn;
+        c = X * inv;
+        s = Y * inv;
+    }
+    p.r = rn;
+    p.z = p.z + dt * vz;
+    p.vr = c * vr + s * vt;
+    p.vt = -s * vr + c * vt;
+    p.vz = vz;
+    float ar = p.ar, at = p.at;
+    p.ar = c * ar + s * at;
+    p.at = -s * ar + c * at;
+}
+
+// E at a position with the cylindrical-volume weights (FP32).
+__device__ __forceinline__ void gather_E(const float2* __restrict__ E, const Geo& g, float r, float z,
+                                         float& Er, float& Ez) {
+    float x = r * g.inv_dr, y = z * g.inv_dz;
+    int i = min(max((int)x, 0), g.nr - 1);
+    int j = min(max((int)y, 0), g.nz - 1);
+    float f = fminf(fmaxf(x - (float)i, 0.0f), 1.0f);
+    float gz = fminf(fmaxf(y - (float)j, 0.0f), 1.0f);
+    float fi = (float)i;
+    float wr = f * (2.0f * fi + f) / (2.0f * fi + 1.0f);
+    int n00 = j * g.w + i;
+    float2 e00 = E[n00], e10 = E[n00 + 1], e01 = E[n00 + g.w], e11 = E[n00 + g.w + 1];
+    float a0 = (1.0f - wr) * (1.0f - gz), a1 = wr * (1.0f - gz), a2 = (1.0f - wr) * gz, a3 = wr * gz;
+    Er = a0 * e00.x + a1 * e10.x + a2 * e01.x + a3 * e11.x;
+    Ez = a0 * e00.y + a1 * e10.y + a2 * e01.y + a3 * e11.y;
+}
+
+// --------------------------------------------------------------- MCC (FP32)
+struct Mcc {
+    float n_gas, nu_max, vth_gas, half_m_over_e, two_e_over_m, m_ratio2; // m_ratio2 = 2 m_e / M
+    uint32_t thresh;
+};
+
+__device__ __forceinline__ void xsec_e(float eps, float& el, float& ex, float& io) {
+    el = 1.0e-19f / sqrtf(1.0f + eps * 0.1f);
+    float xe = eps * (1.0f / 11.5f), xi = eps * (1.0f / 15.76f);
+    ex = (eps > 11.5f) ? 2.7e-20f * logf(xe) / xe : 0.0f;
+    io = (eps > 15.76f) ? 8.0e-20f * logf(xi) / xi : 0.0f;
+}
+
+__device__ __forceinline__ float e_cos_chi(float eps, float u) {
+    if (eps < 1e-6f) return 1.0f - 2.0f * u;
+    float c = (2.0f + eps - 2.0f * powf(1.0f + eps, u)) / eps;
+    return fminf(1.0f, fmaxf(-1.0f, c));
+}
+
+// turn unit vector d by polar angle chi (cos cchi) and azimuth phi
+__device__ __forceinline__ void rotate_dir(float& u, float& v, float& w, float cchi, float phi) {
+    float schi = sqrtf(fmaxf(0.0f, 1.0f - cchi * cchi));
+    float sp, cp;
+    sincosf(phi, &sp, &cp);
+    float st = sqrtf(u * u + v * v);
+    if (st > 1e-12f) {
+        float inv = 1.0f / st;
+        float nu = u * cchi + schi * (u * w * cp - v * sp) * inv;
+        float nv = v * cchi + schi * (v * w * cp + u * sp) * inv;
+        float nw = w * cchi - st * schi * cp;
+        u = nu; v = nv; w = nw;
+    } else {
+        u = schi * cp;
+        v = schi * sp;
+        w = (w >= 0.0f ? 1.0f : -1.0f) * cchi;
+    }
+}
+
+__device__ __forceinline__ void maxwell3(uint4 y, float vth, float& a, float& b, float& c) {
+    const float two_pi = 6.28318530717958647692f;
+    float m0 = sqrtf(-2.0f * logf(u01(y.x))), m1 = sqrtf(-2.0f * logf(u01(y.z)));
+    float s0, c0, s1, c1;
+    sincosf(two_pi * u01(y.y), &s0, &c0);
+    sincosf(two_pi * u01(y.w), &s1, &c1);
+    a = vth * m0 * c0;
+    b = vth * m0 * s0;
+    c = vth * m1 * c1;
+}
+
+// Outcome codes: 0 elastic / isotropic, 1 excitation / charge exchange,
+// 2 ionisation, 3 null.  x is the first Philox draw of this particle-step.
+__device__ __forceinline__ int collide(int sp, uint4 x, float& vr, float& vt, float& vz, const Mcc& m,
+                                      uint32_t slot, uint32_t step, uint32_t key0, uint32_t key1,
+                                      float* born6, unsigned int* viol) {
+    const float two_pi = 6.28318530717958647692f;
+    float u1 = u01(x.y), u2 = u01(x.z), u3 = u01(x.w);
+    float R = u1 * m.nu_max;
+    if (sp == 0) {
+        float v2 = vr * vr + vt * vt + vz * vz;
+        float vm = sqrtf(v2);
+        if (!(vm > 0.0f)) return 3;
+        float eps = m.half_m_over_e * v2;
+        float el, ex, io;
+        xsec_e(eps, el, ex, io);
+        float k = m.n_gas * vm;
+        float n_el = k * el, n_ex = k * ex, n_io = k * io;
+        float inv = 1.0f / vm;
+        float du = vr * inv, dv = vt * inv, dw = vz * inv;
+        if (R < n_el) {
+            float cc = e_cos_chi(eps, u2);
+            float e2 = eps * (1.0f - m.m_ratio2 * (1.0f - cc));
+            rotate_dir(du, dv, dw, cc, two_pi * u3);
+            float s = sqrtf(m.two_e_over_m * e2);
+            vr = s * du; vt = s * dv; vz = s * dw;
+            return 0;
+        }
+        if (R < n_el + n_ex) {
+            float e1 = eps - 11.5f;
+            float cc = e_cos_chi(e1, u2);
+            rotate_dir(du, dv, dw, cc, two_pi * u3);
+            float s = sqrtf(m.two_e_over_m * fmaxf(e1, 0.0f));
+            vr = s * du; vt = s * dv; vz = s * dw;
+            return 1;
+        }
+        if (R < n_el + n_ex + n_io) {
+            uint4 y = draw(slot, step, kPurposeMcc, sp, 1, key0, key1);
+            uint4 z4 = draw(slot, step, kPurposeMcc, sp, 2, key0, key1);
+            float e1 = eps - 15.76f;
+            float eej = 10.0f * tanf(u01(y.x) * atanf(e1 * (1.0f / 20.0f)));
+            float esc = fmaxf(e1 - eej, 0.0f);
+            float bu = du, bv = dv, bw = dw;
+            rotate_dir(du, dv, dw, e_cos_chi(esc, u2), two_pi * u3);
+            rotate_dir(bu, bv, bw, e_cos_chi(eej, u01(y.y)), two_pi * u01(y.z));
+            float s1 = sqrtf(m.two_e_over_m * esc), s2 = sqrtf(m.two_e_over_m * eej);
+            vr = s1 * du; vt = s1 * dv; vz = s1 * dw;
+            born6[0] = s2 * bu; born6[1] = s2 * bv; born6[2] = s2 * bw;
+            maxwell3(z4, m.vth_gas, born6[3], born6[4], born6[5]);
+            return 2;
+        }
+        return 3;
+    }
+    // Ar+ on Ar: partner from the gas Maxwellian, relative velocity g
+    uint4 y = draw(slot, step, kPurposeMcc, sp, 1, key0, key1);
+    float nr_, nt_, nz_;
+    maxwell3(y, m.vth_gas, nr_, nt_, nz_);
+    float gr = vr - nr_, gt = vt - nt_, gz = vz - nz_;
+    float gm = sqrtf(gr * gr + gt * gt + gz * gz);
+    float n_iso = m.n_gas * 5.0e-19f * gm, n_cx = n_iso;
+    float tot = n_iso + n_cx;
+    if (tot > m.nu_max) {
+        atomicAdd(viol, 1u);
+        float f = m.nu_max / tot;
+        n_iso *= f;
+        n_cx *= f;
+    }
+    if (R < n_iso && gm > 0.0f) {
+        float cc = sqrtf(1.0f - u2);
+        float inv = 1.0f / gm;
+        float du = gr * inv, dv = gt * inv, dw = gz * inv;
+        rotate_dir(du, dv, dw, cc, two_pi * u3);
+        float gp = gm * cc;
+        vr = nr_ + gp * du; vt = nt_ + gp * dv; vz = nz_ + gp * dw;
+        return 0;
+    }
+    if (R < n_iso + n_cx) {
+        vr = nr_; vt = nt_; vz = nz_;
+        return 1;
+    }
+    return 3;
+}
+
+// staged ionisation birth: parent position and weight, new electron and ion
+// velocities
+struct Birth {
+    float r, z, w, v[6];
+};
+
+__device__ __forceinline__ uint32_t tile_key(const Loc& L, int ntr) {
+    return (uint32_t)((L.j >> kTileShift) * ntr + (L.i >> kTileShift));
+}
+
+}  // namespace pic

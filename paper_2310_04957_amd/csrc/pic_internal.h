@@ -1,0 +1,161 @@
+// pic_internal.h -- runtime state behind the C ABI and the host-side
+// launchers of the HIP kernels (one process, one gfx950 device, the
+// caller's stream).  Device buffers are carved from the caller's workspace.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/pic.h"
+#include "pic_device.h"
+
+namespace pic {
+
+constexpr int kBlock = 256;           // threads per block for particle and sort kernels
+constexpr int kItems = 16;            // particles per thread per chunk
+constexpr int kChunk = kBlock * kItems;
+constexpr int kStageCap = 256;        // staged ionisation births per chunk
+constexpr int kMaxLevels = 16;
+constexpr int kMaxCoarse = 320;       // active nodes of the coarsest multigrid level
+constexpr int kRedBlocks = 1024;      // partial sums of a grid reduction
+
+// counters that kernels update; lives in device memory
+struct DevCounters {
+    long long n_slots[2];
+    long long born;
+    unsigned long long absorbed[2][4];
+    unsigned long long coll[2][4];
+    unsigned int viol;
+    int err;
+    unsigned long long fallback;
+    long long births_step;
+    long long base[2];
+    long long nch_births;
+    unsigned int dead[2];
+    long long pad[4];
+};
+
+// FP64 scalars of the field solve and the circuit; device memory
+struct DevScalars {
+    double U_E, Q_E, Q_P, C_eq, t, I_ccp, circ[5];
+    double one;              // constant 1.0: Dirichlet value of the Laplace problem
+    double powered_prev;     // integer powered-electrode charge at the last circuit step
+    double bb, rr, rz, rz_new, pq, alpha, beta, target, scale, relres, rr0;
+    int done, iters, nonfinite, pad;
+};
+
+struct Level {
+    int nr, nz, w, nn, cr, cz;   // cr/cz: factor to the next (coarser) level
+    double* A64[9];              // 9-point stencils (levels >= 1)
+    float* A32[9];
+    double *x64, *y64, *b64, *res64;
+    float *x32, *y32, *b32, *res32;
+};
+
+struct Species {
+    float* f[9];                 // r z vr vt vz ar at az w
+};
+
+}  // namespace pic
+
+struct pic_handle {
+    pic_config cfg;
+    hipStream_t stream;
+    char* ws;
+    size_t ws_bytes;
+    // derived constants
+    int nr, nz, w, nn, ncell, ntr, ntz, ntiles, key_bits;
+    double dr, dz, dt, Sr, Sz, w_unit, n_gas, nu_max[2], vth_gas, qunit, chi_c[2];
+    uint32_t thresh[2];
+    int64_t cap[2];
+    int64_t max_chunks;
+    // geometry (device)
+    uint8_t* cell_kind;
+    int8_t* node_kind;
+    double *vol, *gr, *gz, *invd;
+    std::vector<int8_t> h_node_kind;
+    std::vector<uint8_t> h_cell_kind;
+    std::vector<double> h_vol, h_gr, h_gz;
+    // particles: two buffers per species for the sort
+    pic::Species buf[2][2];
+    int cur[2];
+    int sort_src_last;
+    uint32_t *keys[2], *idx[2];
+    uint32_t* hist;
+    uint32_t* bsum;
+    // births
+    pic::Birth* stage;
+    int *stage_cnt, *stage_off;
+    // deposits and grids
+    unsigned long long* dep[2][2];  // [buffer][species]
+    int dep_cur;
+    unsigned long long *wallq, *psum[2], *plast[2];
+    double *chi, *Q, *ar, *az, *phi, *phiL, *zeroQ;
+    float *ar32, *az32;
+    float2* E;
+    // solver vectors
+    double *r64, *x64, *z64, *p64, *q64;
+    float *r32, *x32, *z32, *p32, *q32;
+    double* part;           // reduction partials
+    pic::Level lv[pic::kMaxLevels];
+    int nlev;
+    int* cmap;              // coarsest node -> dense index, -1 inactive
+    int ncoarse;
+    double* cinv64;
+    float* cinv32;
+    // time series
+    double *serU, *serI, *lastU, *lastI;
+    // device counters / scalars and their pinned host mirrors
+    pic::DevCounters* ctr;
+    pic::DevScalars* sc;
+    pic::DevScalars* h_sc;     // pinned
+    pic::DevCounters* h_ctr;   // pinned
+    // host-side bookkeeping
+    int64_t step, periods_done;
+    int have_last;
+    int64_t solver_iters, solver_outer;
+    double solver_relres;
+    int sticky_err;
+    // phase timing
+    bool timing;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
+    double ms[6];
+    int64_t timed_steps;
+};
+
+namespace pic {
+
+// geometry and layout on the host
+int host_geometry(pic_handle* h);          // host rasterisation, volumes, faces
+int upload_geometry(pic_handle* h);
+size_t layout(pic_handle* h, char* base);   // returns bytes; assigns pointers when base != nullptr
+int mg_plan(pic_handle* h);                 // level sizes and coarsening factors (host)
+
+// particle kernels
+void launch_load(pic_handle* h, int sp, const double* cdf, const int* cell, int nv, double vvac, int64_t n,
+                 float W, float vth);
+void launch_predict_deposit(pic_handle* h, int sp);
+void launch_redeposit(pic_handle* h);
+void launch_particles(pic_handle* h, int sp);
+void launch_births(pic_handle* h);
+void launch_count_alive(pic_handle* h, long long* out2);
+
+// sort
+void launch_sort(pic_handle* h, int sp);
+
+// field
+void launch_assemble(pic_handle* h);
+void launch_faces(pic_handle* h);
+void launch_circuit(pic_handle* h);
+int field_solve(pic_handle* h, double* phi, const double* Q, const double* Uptr, double tol, int method,
+                int32_t* iters_out, double* relres_out);
+int refresh_laplace(pic_handle* h);
+void mg_rebuild(pic_handle* h);
+void launch_efield(pic_handle* h);
+void launch_period_roll(pic_handle* h);
+void launch_zero_u64(unsigned long long* p, size_t n, hipStream_t s);
+void launch_zero_f64(double* p, size_t n, hipStream_t s);
+
+}  // namespace pic

@@ -1,0 +1,266 @@
+// sort.hip -- periodic stable sort of a species' slots by the 16x16-cell
+// tile of the predicted position, which also removes dead slots.  LSD radix
+// sort on 8-bit digits: per-chunk digit histograms, one exclusive scan in
+// digit-major order, and a stable scatter whose in-chunk ranks come from
+// wavefront ballots (no atomics decide an order, so the permutation is
+// deterministic).  The nine particle arrays are then gathered into the
+// second buffer.
+#include <hip/hip_runtime.h>
+
+#include "pic_internal.h"
+
+namespace pic {
+
+constexpr int kSeg = 4096;   // elements per block of the scan kernels
+
+struct KeyArgs {
+    Geo g;
+    const float* r;
+    const float* z;
+    uint32_t* keys;
+    uint32_t* idx;
+    const long long* n_slots;
+    unsigned int* dead;
+    int sp, ntr;
+    uint32_t dead_key;
+};
+
+__global__ __launch_bounds__(kBlock) void k_keys(KeyArgs a) {
+    const long long n = a.n_slots[a.sp];
+    unsigned int dead = 0;
+    for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < n;
+         p += (long long)gridDim.x * blockDim.x) {
+        float r = a.r[p];
+        uint32_t key = a.dead_key;
+        if (r >= 0.0f) {
+            Loc L = locate(r, a.z[p], a.g);
+            if (L.inside) key = tile_key(L, a.ntr);
+        }
+        dead += (key == a.dead_key);
+        a.keys[p] = key;
+        a.idx[p] = (uint32_t)p;
+    }
+    // wave reduction then one atomic per wave
+    for (int o = 32; o > 0; o >>= 1) dead += __shfl_down(dead, o);
+    if ((threadIdx.x & 63) == 0 && dead) atomicAdd(a.dead, dead);
+}
+
+__global__ __launch_bounds__(kBlock) void k_hist(const uint32_t* keys, const long long* n_slots, int sp, int shift,
+                                                 uint32_t* hist) {
+    __shared__ unsigned int h[256];
+    const long long n = n_slots[sp];
+    const long long nch = (n + kChunk - 1) / kChunk;
+    for (long long c = blockIdx.x; c < nch; c += gridDim.x) {
+        h[threadIdx.x] = 0u;
+        __syncthreads();
+        for (int it = 0; it < kItems; ++it) {
+            long long p = c * kChunk + (long long)it * kBlock + threadIdx.x;
+            if (p < n) atomicAdd(&h[(keys[p] >> shift) & 0xFFu], 1u);
+        }
+        __syncthreads();
+        hist[(long long)threadIdx.x * nch + c] = h[threadIdx.x];
+        __syncthreads();
+    }
+}
+
+// exclusive scan of hist[0 .. 256 * nch) in three kernels
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t* v, const long long* n_slots, int sp,
+                                                        uint32_t* bsum) {
+    __shared__ unsigned int s[kBlock];
+    const long long nch = (n_slots[sp] + kChunk - 1) / kChunk;
+    const long long len = 256 * nch;
+    const long long nseg = (len + kSeg - 1) / kSeg;
+    for (long long b = blockIdx.x; b < nseg; b += gridDim.x) {
+        unsigned int t = 0;
+        for (int k = 0; k < kSeg / kBlock; ++k) {
+            long long i = b * kSeg + (long long)k * kBlock + threadIdx.x;
+            if (i < len) t += v[i];
+        }
+        s[threadIdx.x] = t;
+        __syncthreads();
+        for (int o = kBlock / 2; o > 0; o >>= 1) {
+            if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) bsum[b] = s[0];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_scan_top(uint32_t* bsum, const long long* n_slots, int sp) {
+    __shared__ unsigned int s[1024];
+    __shared__ unsigned int carry;
+    const long long nch = (n_slots[sp] + kChunk - 1) / kChunk;
+    const long long nseg = (256 * nch + kSeg - 1) / kSeg;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (long long b0 = 0; b0 < nseg; b0 += 1024) {
+        long long i = b0 + threadIdx.x;
+        unsigned int v = (i < nseg) ? bsum[i] : 0u;
+        s[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = 1; o < 1024; o <<= 1) {
+            unsigned int t = ((int)threadIdx.x >= o) ? s[threadIdx.x - o] : 0u;
+            __syncthreads();
+            s[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (i < nseg) bsum[i] = carry + s[threadIdx.x] - v;
+        __syncthreads();
+        if (threadIdx.x == 0) carry += s[1023];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_down(uint32_t* v, const uint32_t* bsum, const long long* n_slots,
+                                                      int sp) {
+    __shared__ unsigned int s[kBlock];
+    const long long nch = (n_slots[sp] + kChunk - 1) / kChunk;
+    const long long len = 256 * nch;
+    const long long nseg = (len + kSeg - 1) / kSeg;
+    constexpr int per = kSeg / kBlock;  // 16 consecutive elements per thread
+    for (long long b = blockIdx.x; b < nseg; b += gridDim.x) {
+        unsigned int loc[per];
+        unsigned int t = 0;
+        const long long i0 = b * kSeg + (long long)threadIdx.x * per;
+        for (int k = 0; k < per; ++k) {
+            long long i = i0 + k;
+            loc[k] = (i < len) ? v[i] : 0u;
+            t += loc[k];
+        }
+        s[threadIdx.x] = t;
+        __syncthreads();
+        for (int o = 1; o < kBlock; o <<= 1) {
+            unsigned int u = ((int)threadIdx.x >= o) ? s[threadIdx.x - o] : 0u;
+            __syncthreads();
+            s[threadIdx.x] += u;
+            __syncthreads();
+        }
+        unsigned int run = bsum[b] + s[threadIdx.x] - t;
+        for (int k = 0; k < per; ++k) {
+            long long i = i0 + k;
+            if (i < len) v[i] = run;
+            run += loc[k];
+        }
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ unsigned long long lanemask_lt_s() {
+    return (1ull << (threadIdx.x & 63)) - 1ull;
+}
+
+// stable scatter: element order inside a chunk is (item, thread); ranks
+// among equal digits come from 8 ballots per round
+__global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* kin, const uint32_t* vin, uint32_t* kout,
+                                                    uint32_t* vout, const uint32_t* offs, const long long* n_slots,
+                                                    int sp, int shift) {
+    __shared__ unsigned int run[256];
+    __shared__ unsigned int wcnt[kBlock / 64][256];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const long long n = n_slots[sp];
+    const long long nch = (n + kChunk - 1) / kChunk;
+    for (long long c = blockIdx.x; c < nch; c += gridDim.x) {
+        run[tid] = offs[(long long)tid * nch + c];
+        for (int w2 = 0; w2 < kBlock / 64; ++w2) wcnt[w2][tid] = 0u;
+        __syncthreads();
+        for (int it = 0; it < kItems; ++it) {
+            const long long p = c * kChunk + (long long)it * kBlock + tid;
+            const bool valid = p < n;
+            uint32_t key = valid ? kin[p] : 0u;
+            uint32_t val = valid ? vin[p] : 0u;
+            uint32_t d = (key >> shift) & 0xFFu;
+            unsigned long long peers = __ballot(valid);
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                unsigned long long m = __ballot((d >> b) & 1u);
+                peers &= ((d >> b) & 1u) ? m : ~m;
+            }
+            const int rank = __popcll(peers & lanemask_lt_s());
+            if (valid && rank == 0) wcnt[wave][d] = (unsigned int)__popcll(peers);
+            __syncthreads();
+            if (valid) {
+                unsigned int pos = run[d] + rank;
+                for (int w2 = 0; w2 < wave; ++w2) pos += wcnt[w2][d];
+                kout[pos] = key;
+                vout[pos] = val;
+            }
+            __syncthreads();
+            unsigned int add = 0;
+            for (int w2 = 0; w2 < kBlock / 64; ++w2) {
+                add += wcnt[w2][tid];
+                wcnt[w2][tid] = 0u;
+            }
+            run[tid] += add;
+            __syncthreads();
+        }
+    }
+}
+
+struct GatherArgs {
+    const float* src[9];
+    float* dst[9];
+    const uint32_t* idx;
+    long long* n_slots;
+    const unsigned int* dead;
+    int sp;
+};
+
+__global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a) {
+    const long long n = a.n_slots[a.sp] - (long long)a.dead[a.sp];
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n;
+         q += (long long)gridDim.x * blockDim.x) {
+        const uint32_t o = a.idx[q];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) a.dst[k][q] = a.src[k][o];
+    }
+}
+
+__global__ void k_finish_sort(long long* n_slots, unsigned int* dead, int sp) {
+    n_slots[sp] -= (long long)dead[sp];
+    dead[sp] = 0u;
+}
+
+__global__ void k_zero_u32(unsigned int* p) { *p = 0u; }
+
+void launch_sort(pic_handle* h, int sp) {
+    hipStream_t st = h->stream;
+    const long long* ns = (const long long*)h->ctr->n_slots;
+    unsigned int* dead = &h->ctr->dead[0];
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, dead + sp);
+    Species& S = h->buf[sp][h->cur[sp]];
+    KeyArgs ka;
+    ka.g.nr = h->nr; ka.g.nz = h->nz; ka.g.w = h->w;
+    ka.g.R = h->cfg.geom.R; ka.g.Z = h->cfg.geom.Z; ka.g.Sr = h->Sr; ka.g.Sz = h->Sz;
+    ka.g.inv_dr = (float)(1.0 / h->dr); ka.g.inv_dz = (float)(1.0 / h->dz);
+    ka.g.invd = h->invd; ka.g.cell_kind = h->cell_kind; ka.g.node_kind = h->node_kind;
+    for (int k = 0; k < 3; ++k) ka.g.edge_bc[k] = h->cfg.geom.edge_bc[k];
+    ka.r = S.f[0]; ka.z = S.f[1];
+    ka.keys = h->keys[0]; ka.idx = h->idx[0];
+    ka.n_slots = ns; ka.dead = dead + sp; ka.sp = sp; ka.ntr = h->ntr;
+    ka.dead_key = (uint32_t)h->ntiles;   // one bucket past the last tile: sorts last
+    hipLaunchKernelGGL(k_keys, dim3(2048), dim3(kBlock), 0, st, ka);
+    int src = 0;
+    for (int shift = 0; shift < h->key_bits; shift += 8) {
+        hipLaunchKernelGGL(k_hist, dim3(2048), dim3(kBlock), 0, st, h->keys[src], ns, sp, shift, h->hist);
+        hipLaunchKernelGGL(k_scan_reduce, dim3(2048), dim3(kBlock), 0, st, h->hist, ns, sp, h->bsum);
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, h->bsum, ns, sp);
+        hipLaunchKernelGGL(k_scan_down, dim3(2048), dim3(kBlock), 0, st, h->hist, h->bsum, ns, sp);
+        hipLaunchKernelGGL(k_scatter, dim3(2048), dim3(kBlock), 0, st, h->keys[src], h->idx[src], h->keys[1 - src],
+                           h->idx[1 - src], h->hist, ns, sp, shift);
+        src = 1 - src;
+    }
+    GatherArgs ga;
+    Species& D = h->buf[sp][1 - h->cur[sp]];
+    for (int k = 0; k < 9; ++k) { ga.src[k] = S.f[k]; ga.dst[k] = D.f[k]; }
+    ga.idx = h->idx[src];
+    ga.n_slots = h->ctr->n_slots;
+    ga.dead = dead;
+    ga.sp = sp;
+    hipLaunchKernelGGL(k_gather, dim3(2048), dim3(kBlock), 0, st, ga);
+    hipLaunchKernelGGL(k_finish_sort, dim3(1), dim3(1), 0, st, h->ctr->n_slots, dead, sp);
+    h->cur[sp] = 1 - h->cur[sp];
+    h->sort_src_last = src;
+}
+
+}  // namespace pic

@@ -1,0 +1,257 @@
+"""Thin Python binding of the C ABI in include/pic.h (argument marshalling only).
+
+Every step of the method runs in the HIP kernels of libpic.so.  PyTorch
+supplies the device workspace and the stream.  There is no CPU fallback: if
+the library or a gfx950 device is missing, construction raises.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpic.so")
+
+ABI_VERSION = 1
+MAX_REGIONS = 32
+FIELDS = ("r", "z", "vr", "vt", "vz", "ar", "at", "az", "w")
+GRIDS = dict(DEP_E=0, DEP_I=1, PHI=2, ER=3, EZ=4, CHI=5, WALLQ=6, PHI_L=10, Q=11, AR=12, AZ=13)
+ERRORS = {0: "ok", -1: "PIC_E_CONFIG", -2: "PIC_E_CAPACITY", -3: "PIC_E_SOLVER", -4: "PIC_E_HIP",
+          -5: "PIC_E_NONFINITE", -6: "PIC_E_STATE", -7: "PIC_E_ARG", -8: "PIC_E_NODEVICE"}
+
+
+class PicError(RuntimeError):
+    def __init__(self, code, where):
+        super().__init__(f"{where}: {ERRORS.get(code, code)} ({code})")
+        self.code = code
+
+
+class Region(C.Structure):
+    _fields_ = [("r0", C.c_double), ("r1", C.c_double), ("z0", C.c_double), ("z1", C.c_double),
+                ("kind", C.c_int32), ("cond_id", C.c_int32), ("eps_r", C.c_double)]
+
+
+class Geometry(C.Structure):
+    _fields_ = [("nr", C.c_int32), ("nz", C.c_int32), ("R", C.c_double), ("Z", C.c_double),
+                ("n_regions", C.c_int32), ("edge_bc", C.c_int32 * 3), ("regions", Region * MAX_REGIONS)]
+
+
+class Circuit(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("substeps", C.c_int32)] + [
+        (f, C.c_double) for f in ("freq", "U_amp", "U_dc", "R_s", "C_m1", "C_m2", "L_m", "R_m", "C_stray",
+                                  "L_stray", "R_stray", "C_b", "R_b", "L_b")]
+
+
+class Gas(C.Structure):
+    _fields_ = [("p_Pa", C.c_double), ("T_gas_K", C.c_double)]
+
+
+class Run(C.Structure):
+    _fields_ = [("n_e", C.c_int64), ("n_i", C.c_int64), ("cap_e", C.c_int64), ("cap_i", C.c_int64),
+                ("n0", C.c_double), ("Te_eV", C.c_double), ("Ti_eV", C.c_double),
+                ("steps_per_period", C.c_int32), ("sort_every", C.c_int32), ("seed", C.c_uint64),
+                ("load", C.c_int32), ("timing", C.c_int32)]
+
+
+class Solver(C.Structure):
+    _fields_ = [("method", C.c_int32), ("tol", C.c_double), ("max_iter", C.c_int32), ("inner_tol", C.c_double)]
+
+
+class Config(C.Structure):
+    _fields_ = [("abi_version", C.c_int32), ("geom", Geometry), ("circ", Circuit), ("gas", Gas), ("run", Run),
+                ("solver", Solver)]
+
+
+class Diag(C.Structure):
+    _fields_ = [(f, C.c_double) for f in ("t", "U_E", "Q_E", "C_eq", "Q_P", "I_ccp", "dt", "w_unit", "n_gas")] + [
+        ("circ", C.c_double * 5), ("nu_max", C.c_double * 2), ("thresh", C.c_uint32 * 2),
+        ("step", C.c_int64), ("periods_done", C.c_int64), ("n_slots", C.c_int64 * 2), ("n_alive", C.c_int64 * 2),
+        ("absorbed", (C.c_int64 * 4) * 2), ("born", C.c_int64), ("coll", (C.c_int64 * 4) * 2),
+        ("numax_violations", C.c_int64), ("solver_iters", C.c_int64), ("solver_outer", C.c_int64),
+        ("solver_relres", C.c_double),
+        ("harm_U_re", C.c_double * 6), ("harm_U_im", C.c_double * 6),
+        ("harm_I_re", C.c_double * 6), ("harm_I_im", C.c_double * 6),
+        ("ms_particles", C.c_double * 2), ("ms_births", C.c_double), ("ms_sort", C.c_double),
+        ("ms_field", C.c_double), ("ms_refresh", C.c_double),
+        ("timed_steps", C.c_int64), ("deposit_fallback", C.c_int64), ("error", C.c_int32)]
+
+
+class DiagBuffers(C.Structure):
+    _fields_ = [(f, C.c_void_p) for f in ("n_e", "n_i", "phi", "U_E", "I_ccp")]
+
+
+_lib = None
+
+
+def lib():
+    """Load libpic.so; raise if it was not built (no fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2310_04957_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        L.pic_workspace_size.argtypes = [C.POINTER(Config), C.POINTER(C.c_size_t)]
+        L.pic_init.argtypes = [C.POINTER(Config), P, C.c_size_t, P, C.POINTER(P)]
+        L.pic_step.argtypes = [P, C.c_int32]
+        L.pic_diag.argtypes = [P, C.POINTER(Diag), C.POINTER(DiagBuffers)]
+        L.pic_reset_timers.argtypes = [P]
+        L.pic_free.argtypes = [P]
+        L.pic_strerror.argtypes = [C.c_int]
+        L.pic_strerror.restype = C.c_char_p
+        L.pic_get_particles.argtypes = [P, C.c_int32, P, C.POINTER(C.c_int64)]
+        L.pic_set_particles.argtypes = [P, C.c_int32, P, C.c_int64]
+        L.pic_get_grid.argtypes = [P, C.c_int32, P]
+        L.pic_set_grid.argtypes = [P, C.c_int32, P]
+        L.pic_redeposit.argtypes = [P]
+        L.pic_sort_now.argtypes = [P, C.c_int32, P]
+        L.pic_solve_once.argtypes = [P, P, P, C.c_double, C.c_double, P, C.POINTER(C.c_int32),
+                                     C.POINTER(C.c_double)]
+        L.pic_set_state.argtypes = [P, P]
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _check(rc, where):
+    if rc != 0:
+        raise PicError(rc, where)
+
+
+def make_config(w, load=True, timing=False, method=None, inner_tol=1e-4):
+    """Marshal a workload dict (pic_inputs.workloads) into pic_config."""
+    g, c, gas, run, sol = w["geometry"], w["circuit"], w["gas"], w["run"], w["solver"]
+    cfg = Config()
+    cfg.abi_version = ABI_VERSION
+    cfg.geom.nr, cfg.geom.nz, cfg.geom.R, cfg.geom.Z = g["nr"], g["nz"], g["R"], g["Z"]
+    if len(g["regions"]) > MAX_REGIONS:
+        raise ValueError("too many regions")
+    cfg.geom.n_regions = len(g["regions"])
+    for k, e in enumerate(g["edge_bc"]):
+        cfg.geom.edge_bc[k] = e
+    for k, (r0, r1, z0, z1, kind, cid, eps) in enumerate(g["regions"]):
+        cfg.geom.regions[k] = Region(r0, r1, z0, z1, kind, cid, eps)
+    cfg.circ.kind, cfg.circ.substeps = c["kind"], c["substeps"]
+    for f in ("freq", "U_amp", "U_dc", "R_s", "C_m1", "C_m2", "L_m", "R_m", "C_stray", "L_stray", "R_stray",
+              "C_b", "R_b", "L_b"):
+        setattr(cfg.circ, f, c[f])
+    cfg.gas.p_Pa, cfg.gas.T_gas_K = gas["p_Pa"], gas["T_K"]
+    for f in ("n_e", "n_i", "cap_e", "cap_i", "n0", "Te_eV", "Ti_eV", "steps_per_period", "sort_every", "seed"):
+        setattr(cfg.run, f, run[f])
+    cfg.run.load = 1 if load else 0
+    cfg.run.timing = 1 if timing else 0
+    cfg.solver.method = sol["method"] if method is None else method
+    cfg.solver.tol, cfg.solver.max_iter = sol["tol"], sol["max_iter"]
+    cfg.solver.inner_tol = inner_tol
+    return cfg
+
+
+def workspace_bytes(cfg):
+    n = C.c_size_t()
+    _check(lib().pic_workspace_size(C.byref(cfg), C.byref(n)), "pic_workspace_size")
+    return n.value
+
+
+class Pic:
+    """One simulation on the current HIP device and stream."""
+
+    def __init__(self, w, load=True, timing=False, method=None, inner_tol=1e-4, device="cuda:0"):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the HIP path has no CPU fallback")
+        self.w = w
+        self.cfg = make_config(w, load, timing, method, inner_tol)
+        L = lib()
+        nbytes = workspace_bytes(self.cfg)
+        self.device = torch.device(device)
+        torch.cuda.set_device(self.device)
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        self.h = C.c_void_p()
+        _check(L.pic_init(C.byref(self.cfg), C.c_void_p(self.ws.data_ptr()), nbytes + 256,
+                          C.c_void_p(self.stream.cuda_stream), C.byref(self.h)), "pic_init")
+        g = w["geometry"]
+        self.nr, self.nz = g["nr"], g["nz"]
+        self.nn = (self.nr + 1) * (self.nz + 1)
+        self.spp = w["run"]["steps_per_period"]
+        self.cap = (w["run"]["cap_e"], w["run"]["cap_i"])
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            lib().pic_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n=1):
+        _check(lib().pic_step(self.h, n), "pic_step")
+
+    def diag(self, grids=False):
+        d = Diag()
+        bufs = None
+        out = {}
+        if grids:
+            out = dict(n_e=np.zeros(self.nn), n_i=np.zeros(self.nn), phi=np.zeros(self.nn),
+                       U_E=np.zeros(self.spp), I_ccp=np.zeros(self.spp))
+            bufs = DiagBuffers(*[_ptr(out[k]).value for k in ("n_e", "n_i", "phi", "U_E", "I_ccp")])
+        _check(lib().pic_diag(self.h, C.byref(d), C.byref(bufs) if bufs is not None else None), "pic_diag")
+        return (d, out) if grids else d
+
+    def reset_timers(self):
+        _check(lib().pic_reset_timers(self.h), "pic_reset_timers")
+
+    def particles(self, sp):
+        cap = self.cap[sp]
+        a = np.zeros(9 * max(cap, 1), dtype=np.float32)
+        n = C.c_int64()
+        _check(lib().pic_get_particles(self.h, sp, _ptr(a), C.byref(n)), "pic_get_particles")
+        n = n.value
+        return {f: a[k * cap:k * cap + n].copy() for k, f in enumerate(FIELDS)}
+
+    def set_particles(self, sp, p):
+        n = len(p["r"])
+        a = np.concatenate([np.asarray(p[f], dtype=np.float32) for f in FIELDS]) if n else np.zeros(9, np.float32)
+        _check(lib().pic_set_particles(self.h, sp, _ptr(a), n), "pic_set_particles")
+
+    def grid(self, name):
+        if name in ("DEP_E", "DEP_I", "WALLQ"):
+            a = np.zeros(self.nn, dtype=np.int64)
+        elif name in ("ER", "EZ"):
+            a = np.zeros(self.nn, dtype=np.float32)
+        else:
+            a = np.zeros(self.nn, dtype=np.float64)
+        _check(lib().pic_get_grid(self.h, GRIDS[name], _ptr(a)), "pic_get_grid")
+        return a
+
+    def set_grid(self, name, a):
+        dt = np.int64 if name in ("DEP_E", "DEP_I", "WALLQ") else np.float64
+        a = np.ascontiguousarray(a, dtype=dt)
+        _check(lib().pic_set_grid(self.h, GRIDS[name], _ptr(a)), "pic_set_grid")
+
+    def redeposit(self):
+        _check(lib().pic_redeposit(self.h), "pic_redeposit")
+
+    def sort_now(self, sp):
+        perm = np.zeros(max(self.cap[sp], 1), dtype=np.int64)
+        _check(lib().pic_sort_now(self.h, sp, _ptr(perm)), "pic_sort_now")
+        return perm
+
+    def solve_once(self, Q, chi, U_E, tol, phi0=None):
+        Q = np.ascontiguousarray(Q, dtype=np.float64)
+        chi = np.ascontiguousarray(chi, dtype=np.float64)
+        phi = np.zeros(self.nn) if phi0 is None else np.array(phi0, dtype=np.float64)
+        it = C.c_int32()
+        rel = C.c_double()
+        rc = lib().pic_solve_once(self.h, _ptr(Q), _ptr(chi), U_E, tol, _ptr(phi), C.byref(it), C.byref(rel))
+        return phi, it.value, rel.value, rc
+
+    def set_state(self, t, Q_E, U_E, circ, C_eq):
+        st = np.array([t, Q_E, U_E] + list(circ) + [C_eq], dtype=np.float64)
+        _check(lib().pic_set_state(self.h, _ptr(st)), "pic_set_state")
