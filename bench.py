@@ -21,6 +21,11 @@ sys.path.insert(0, ROOT)
 
 BYTES_PER_PARTICLE_STEP = 68.0   # read r z vr vt vz ar at az w, write all but w (FP32)
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per particle-step of k_particles measured with rocprofv3 FETCH_SIZE
+# and WRITE_SIZE (scaled by a plain-copy calibration) on gec1024x2048; see
+# profiles/k_particles_gec1024x2048.md.  Set to None whenever the kernel
+# changes until it is measured again.
+MEASURED_BYTES_PER_PARTICLE_STEP = {"gec1024x2048": (7.27e9 + 8.55e9) / 199.4e6}
 
 
 def cpu_baseline(name, sample_particles, steps):
@@ -51,7 +56,20 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1_000_000)
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sort-every", type=int, default=None)
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="only run a plain FP32 copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy_mib:
+        import torch
+        n = args.calibrate_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.add(src, 0.0, out=dst)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "copy", "bytes_read": 4 * n, "bytes_written": 4 * n, "launches": 3}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
                           "n_gpus": args.gpus}))
@@ -63,6 +81,8 @@ def main():
     from pic_inputs.workloads import SOLVE_IR_MG, SOLVE_MGPCG_FP64
 
     w = workload(args.workload)
+    if args.sort_every is not None:
+        w["run"]["sort_every"] = args.sort_every
     method = SOLVE_IR_MG if args.method == "ir" else SOLVE_MGPCG_FP64
     print(f"[bench] init {args.workload} method={args.method}", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
@@ -104,7 +124,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "grid": f"{w['geometry']['nr']}x{w['geometry']['nz']}",
-                   "particles": int(n_start), "solver": args.method, "steps_per_period": w["run"]["steps_per_period"]},
+                   "particles": int(n_start), "solver": args.method, "sort_every": w["run"]["sort_every"], "steps_per_period": w["run"]["steps_per_period"]},
         "particle_loop_particle_steps_per_s": ps / (ms_part * 1e-3) if ms_part > 0 else None,
         "field_solve_ms_per_step": d.ms_field / max(args.steps, 1),
         "phase_ms_per_step": {"particles_e": d.ms_particles[0] / args.steps, "particles_i": d.ms_particles[1] / args.steps,
@@ -113,7 +133,11 @@ def main():
         "solver_iters_last": int(d.solver_iters), "solver_relres_last": d.solver_relres,
         "deposit_fallback_per_step": (d.deposit_fallback - d0.deposit_fallback) / args.steps,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": (MEASURED_BYTES_PER_PARTICLE_STEP[args.workload] * ps / (2 * args.steps) / 1e9
+                                 if args.workload in MEASURED_BYTES_PER_PARTICLE_STEP else None),
+                     "traffic_unit": "GB per launch (HBM, rocprofv3 counters)",
+                     "algorithmic_gb_per_launch": part_bytes / (2 * args.steps) / 1e9,
                      "kernel": "k_particles", "bytes_per_unit": BYTES_PER_PARTICLE_STEP,
                      "unit_of_work": "particle-step"},
     }

@@ -63,7 +63,7 @@ typedef struct {
 } pic_region;
 
 typedef struct {
-    int32_t nr, nz;             /* cells; both even and >= 4 */
+    int32_t nr, nz;             /* cells; both even, 4 <= n <= 4096 */
     double R, Z;                /* domain [0,R] x [0,Z], metres; r = 0 is the axis */
     int32_t n_regions;
     int32_t edge_bc[3];         /* r=R, z=0, z=Z edges: conductor id or PIC_NEUMANN */
@@ -87,7 +87,8 @@ typedef struct {
     int64_t cap_e, cap_i;       /* slots reserved per species */
     double n0, Te_eV, Ti_eV;    /* initial uniform plasma density (m^-3) and temperatures */
     int32_t steps_per_period;   /* dt = 1 / (freq * steps_per_period) */
-    int32_t sort_every;         /* cell sort every K steps (0: never) */
+    int32_t sort_every;         /* electron tile sort every K steps (0: never) */
+    int32_t sort_every_ion;     /* ion tile sort every K steps (0: never) */
     uint64_t seed;              /* Philox key */
     int32_t load;               /* 1: load the Maxwellian plasma at init; 0: start empty */
     int32_t timing;             /* 1: time each phase with HIP events (pic_diag reports ms) */

@@ -34,7 +34,7 @@ class Config(C.Structure):
                 ("p_Pa", C.c_double), ("T_gas_K", C.c_double),
                 ("n_e", C.c_int64), ("n_i", C.c_int64), ("cap_e", C.c_int64), ("cap_i", C.c_int64),
                 ("n0", C.c_double), ("Te_eV", C.c_double), ("Ti_eV", C.c_double),
-                ("steps_per_period", C.c_int32), ("sort_every", C.c_int32),
+                ("steps_per_period", C.c_int32), ("sort_every", C.c_int32), ("sort_every_ion", C.c_int32),
                 ("seed", C.c_uint64), ("tol", C.c_double), ("max_iter", C.c_int32),
                 ("load", C.c_int32)]
 
@@ -119,7 +119,7 @@ def make_config(w, load=True):
         setattr(cfg, f, c[f])
     cfg.p_Pa, cfg.T_gas_K = gas["p_Pa"], gas["T_K"]
     for f in ("n_e", "n_i", "cap_e", "cap_i", "n0", "Te_eV", "Ti_eV", "steps_per_period",
-              "sort_every", "seed"):
+              "sort_every", "sort_every_ion", "seed"):
         setattr(cfg, f, run[f])
     cfg.tol, cfg.max_iter = sol["tol"], sol["max_iter"]
     cfg.load = 1 if load else 0

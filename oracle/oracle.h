@@ -50,7 +50,7 @@ typedef struct {
     /* particles and run */
     int64_t n_e, n_i, cap_e, cap_i;
     double n0, Te_eV, Ti_eV;
-    int32_t steps_per_period, sort_every;
+    int32_t steps_per_period, sort_every, sort_every_ion;
     uint64_t seed;
     double tol;
     int32_t max_iter;

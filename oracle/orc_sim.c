@@ -274,10 +274,8 @@ static int step1(orc_sim* s) {
     free(births);
     if (rc) return rc;
     s->step++;
-    if (s->cfg.sort_every > 0 && s->step % s->cfg.sort_every == 0) {
-        sort_species(s, 0);
-        sort_species(s, 1);
-    }
+    if (s->cfg.sort_every > 0 && s->step % s->cfg.sort_every == 0) sort_species(s, 0);
+    if (s->cfg.sort_every_ion > 0 && s->step % s->cfg.sort_every_ion == 0) sort_species(s, 1);
     if (s->step % spp == 0) {
         o_laplace(s);
         memcpy(s->lastU, s->serU, sizeof(double) * spp);
@@ -367,6 +365,9 @@ int orc_create(const orc_config* cfg, orc_sim** out) {
             o_deposit_one(s, st[0], st[1], st[8], s->dep[sp]);
         }
     }
+    /* the loaded plasma starts tile-sorted, like every later sort */
+    sort_species(s, 0);
+    sort_species(s, 1);
     /* vacuum equivalent capacitance and Laplace solution at start [R21] */
     o_faces_from_chi(s, s->chi, s->ar, s->az);
     o_laplace(s);

@@ -30,7 +30,7 @@ constexpr double kPi = 3.14159265358979323846;
 int validate(const pic_config* c) {
     if (!c || c->abi_version != PIC_ABI_VERSION) return PIC_E_CONFIG;
     const pic_geometry& g = c->geom;
-    if (g.nr < 4 || g.nz < 4 || (g.nr & 1) || (g.nz & 1) || g.nr > 16384 || g.nz > 16384) return PIC_E_CONFIG;
+    if (g.nr < 4 || g.nz < 4 || (g.nr & 1) || (g.nz & 1) || g.nr > 4096 || g.nz > 4096) return PIC_E_CONFIG;
     if (!(g.R > 0) || !(g.Z > 0) || g.n_regions < 0 || g.n_regions > PIC_MAX_REGIONS) return PIC_E_CONFIG;
     for (int k = 0; k < 3; ++k)
         if (g.edge_bc[k] < -1 || g.edge_bc[k] > 1) return PIC_E_CONFIG;
@@ -48,7 +48,8 @@ int validate(const pic_config* c) {
     if (ci.kind == PIC_SERIES_RLC && !(ci.C_b > 0 && ci.L_b > 0)) return PIC_E_CONFIG;
     const pic_run& r = c->run;
     if (r.steps_per_period < 1 || r.n_e < 0 || r.n_i < 0 || r.cap_e < r.n_e || r.cap_i < r.n_i) return PIC_E_CONFIG;
-    if (r.cap_e > 0xFFFFFFF0LL || r.cap_i > 0xFFFFFFF0LL || r.sort_every < 0) return PIC_E_CONFIG;
+    if (r.cap_e > 0xFFFFFFF0LL || r.cap_i > 0xFFFFFFF0LL || r.sort_every < 0 || r.sort_every_ion < 0)
+        return PIC_E_CONFIG;
     if (!(c->gas.p_Pa >= 0) || !(c->gas.T_gas_K > 0) || !(r.n0 >= 0)) return PIC_E_CONFIG;
     if (c->solver.method < 0 || c->solver.method > 1 || !(c->solver.tol > 0) || c->solver.max_iter < 1)
         return PIC_E_CONFIG;
@@ -277,8 +278,9 @@ size_t layout(pic_handle* h, char* base) {
     h->hist = c.take<uint32_t>(256 * mch);
     h->bsum = c.take<uint32_t>((256 * mch + 4095) / 4096 + 1);
     h->stage = c.take<Birth>(mch * kStageCap);
-    h->stage_cnt = c.take<int>(mch);
-    h->stage_off = c.take<int>(mch);
+    h->stage_cnt = c.take<int>(mch * kWaves);
+    h->stage_off = c.take<int>(mch * kWaves / 1024 + 2);
+    h->stage_segoff = c.take<int>(mch * kWaves / 1024 + 2);
     for (int b = 0; b < 2; ++b)
         for (int sp = 0; sp < 2; ++sp) h->dep[b][sp] = c.take<unsigned long long>(nn);
     h->wallq = c.take<unsigned long long>(nn);
@@ -510,8 +512,10 @@ int pic_init(const pic_config* cfg, void* dev_workspace, size_t bytes, void* hip
     hipLaunchKernelGGL(k_set_one, dim3(1), dim3(1), 0, h->stream, h->sc);
     h->dep_cur = 0;
     h->cur[0] = h->cur[1] = 0;
-    // first prediction (a_bar = 0) and deposit
+    // first prediction (a_bar = 0) and deposit; the loaded plasma starts tile-sorted
     for (int sp = 0; sp < 2; ++sp) launch_predict_deposit(h, sp);
+    launch_sort(h, 0);
+    launch_sort(h, 1);
     // vacuum operator, multigrid, Laplace solution and C_eq (Eqs. 6-7)
     launch_faces(h);                 // chi = 0 from the zeroed workspace
     rc = refresh_laplace(h);
@@ -559,10 +563,12 @@ int pic_step(pic_handle* h, int32_t nsteps) {
         launch_births(h);
         ev_record(h, 2, &b2);
         h->step++;
-        if (c.run.sort_every > 0 && h->step % c.run.sort_every == 0) {
+        const bool se = c.run.sort_every > 0 && h->step % c.run.sort_every == 0;
+        const bool si = c.run.sort_every_ion > 0 && h->step % c.run.sort_every_ion == 0;
+        if (se || si) {
             ev_record(h, -1, &b3);
-            launch_sort(h, 0);
-            launch_sort(h, 1);
+            if (se) launch_sort(h, 0);
+            if (si) launch_sort(h, 1);
             ev_record(h, 3, &b3);
         }
         if (h->step % spp == 0) {

@@ -10,9 +10,11 @@
 
 namespace pic {
 
-constexpr int kHalo = 8;                      // cells of halo around a 16x16-cell tile
+constexpr int kHalo = 16;                     // cells of halo around a 16x16-cell tile
 constexpr int kWin = kTile + 2 * kHalo + 1;   // LDS window nodes per side
-constexpr int kQCap = 512;                    // deferred colliders per block
+constexpr int kSlice = kChunk / kWaves;       // consecutive slots owned by one wavefront
+constexpr int kRounds = kSlice / 64;
+constexpr int kQW = 128;                      // deferred colliders per wavefront
 
 struct PushArgs {
     Geo g;
@@ -70,25 +72,26 @@ __device__ __forceinline__ bool absorb(const Geo& g, const Loc& L, float w, int 
 
 // Deposit into the LDS window when all four nodes fall inside it, else
 // straight to the global grid (the result is identical: integer sums).
-__device__ __forceinline__ void deposit(const Geo& g, const Loc& L, float w, unsigned long long* win, int wi0,
-                                        int wj0, unsigned long long* dep, unsigned int* s_fallback) {
+// Returns 1 for a global-fallback deposit.
+__device__ __forceinline__ unsigned int deposit(const Geo& g, const Loc& L, float w, unsigned long long* win,
+                                                int wi0, int wj0, unsigned long long* dep) {
     int64_t c[4];
     node_shares(L, (double)w, g.invd, c);
-    int li = L.i - wi0, lj = L.j - wj0;
+    const int li = L.i - wi0, lj = L.j - wj0;
     if (li >= 0 && li + 1 < kWin && lj >= 0 && lj + 1 < kWin) {
-        int b = lj * kWin + li;
+        const int b = lj * kWin + li;
         atomicAdd(&win[b], (unsigned long long)c[0]);
         atomicAdd(&win[b + 1], (unsigned long long)c[1]);
         atomicAdd(&win[b + kWin], (unsigned long long)c[2]);
         atomicAdd(&win[b + kWin + 1], (unsigned long long)c[3]);
-    } else {
-        int n00 = L.j * g.w + L.i;
-        atomicAdd(&dep[n00], (unsigned long long)c[0]);
-        atomicAdd(&dep[n00 + 1], (unsigned long long)c[1]);
-        atomicAdd(&dep[n00 + g.w], (unsigned long long)c[2]);
-        atomicAdd(&dep[n00 + g.w + 1], (unsigned long long)c[3]);
-        atomicAdd(s_fallback, 1u);
+        return 0u;
     }
+    const int n00 = L.j * g.w + L.i;
+    atomicAdd(&dep[n00], (unsigned long long)c[0]);
+    atomicAdd(&dep[n00 + 1], (unsigned long long)c[1]);
+    atomicAdd(&dep[n00 + g.w], (unsigned long long)c[2]);
+    atomicAdd(&dep[n00 + g.w + 1], (unsigned long long)c[3]);
+    return 1u;
 }
 
 __device__ __forceinline__ P9 load9(float* const* f, long long p) {
@@ -103,17 +106,33 @@ __device__ __forceinline__ void store8(float* const* f, long long p, const P9& s
     f[5][p] = s.ar; f[6][p] = s.at; f[7][p] = s.az;
 }
 
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ void load9_guard(float* const* f, long long p, long long n, P9& s) {
+    if (p < n) {
+        s = load9(f, p);
+    } else {
+        s.r = -1.0f;
+    }
+}
+
 // One time step for every particle of one species.  A block owns whole
-// chunks of 4096 consecutive slots; the chunks of one XCD are contiguous so
-// neighbouring (cell-sorted) chunks share that XCD's L2.  Colliding
-// particles are compacted by wavefront ballots into an LDS queue and
-// processed by full waves; births are staged per chunk in slot order.
+// chunks of 4096 consecutive slots and each of its wavefronts a contiguous
+// slice of 1024 of them, processed 64 at a time with the next 64 already
+// in flight; the chunks of one XCD are contiguous so neighbouring
+// (cell-sorted) chunks share that XCD's L2.  Colliding particles are
+// compacted by wavefront ballots into a per-wavefront LDS queue and
+// processed 64 at a time by full wavefronts; births are staged per
+// (chunk, wavefront) in slot order.  The deposit goes to an LDS window (the
+// tile of the chunk's first particle plus halo) flushed once per chunk.
 __global__ __launch_bounds__(kBlock) void k_particles(PushArgs a) {
     __shared__ unsigned long long win[kWin * kWin];
-    __shared__ float qst[9][kQCap];
-    __shared__ unsigned int qslot[kQCap];
-    __shared__ int wave_cnt[kBlock / 64];
-    __shared__ int s_qn, s_nb;
+    __shared__ float qst[kWaves][9][kQW];
+    __shared__ unsigned int qslot[kWaves][kQW];
+    __shared__ int s_org[2];
     __shared__ unsigned long long s_abs[4];
     __shared__ unsigned int s_coll[4];
     __shared__ unsigned int s_fallback;
@@ -125,148 +144,158 @@ __global__ __launch_bounds__(kBlock) void k_particles(PushArgs a) {
     const int nx = 8;  // XCDs: consecutive block ids go round-robin over them
     const int xcd = blockIdx.x % nx, per = gridDim.x / nx, lb = blockIdx.x / nx;
     const long long c_begin = nch * xcd / nx, c_end = nch * (xcd + 1) / nx;
+    float* const* f = a.f;
+    unsigned int fallback = 0;
 
     for (int k = tid; k < kWin * kWin; k += kBlock) win[k] = 0ull;
     if (tid < 4) { s_abs[tid] = 0ull; s_coll[tid] = 0u; }
     if (tid == 0) s_fallback = 0u;
-    __syncthreads();
 
     for (long long chunk = c_begin + lb; chunk < c_end; chunk += per) {
         const long long base = chunk * kChunk;
-        // LDS window: the 16x16 tile of the chunk's first particle plus halo
-        int wi0 = -(1 << 28), wj0 = -(1 << 28);
-        {
-            Loc L0 = locate(a.f[0][base], a.f[1][base], g);
-            if (L0.inside && a.f[0][base] >= 0.0f) {
-                wi0 = ((L0.i >> kTileShift) << kTileShift) - kHalo;
-                wj0 = ((L0.j >> kTileShift) << kTileShift) - kHalo;
+        // LDS window origin: tile of the chunk's first live particle, plus halo
+        if (wave == 0) {
+            const long long p = base + lane;
+            bool ok = false;
+            Loc L;
+            if (p < n) {
+                const float r = f[0][p];
+                L = locate(r, f[1][p], g);
+                ok = (r >= 0.0f) && L.inside;
             }
+            const unsigned long long m = __ballot(ok);
+            const int first = m ? __ffsll((long long)m) - 1 : -1;
+            if (lane == first) {
+                s_org[0] = ((L.i >> kTileShift) << kTileShift) - kHalo;
+                s_org[1] = ((L.j >> kTileShift) << kTileShift) - kHalo;
+            }
+            if (first < 0 && lane == 0) { s_org[0] = -(1 << 28); s_org[1] = -(1 << 28); }
         }
-        if (tid == 0) { s_qn = 0; s_nb = 0; }
         __syncthreads();
+        const int wi0 = s_org[0], wj0 = s_org[1];
 
-        for (int it = 0; it < kItems; ++it) {
-            const long long p = base + (long long)it * kBlock + tid;
-            bool live = p < n;
-            bool coll = false;
-            P9 s;
-            if (live) {
-                s.r = a.f[0][p];
-                live = s.r >= 0.0f;
+        const long long sbase = base + (long long)wave * kSlice;
+        const long long stage_row = chunk * kWaves + wave;
+        int qn = 0, nb = 0;
+        float* qs = &qst[wave][0][0];
+        unsigned int* ql = qslot[wave];
+        P9 cur, nxt;
+        load9_guard(f, sbase + lane, n, cur);
+
+        auto run_queue = [&](int cnt) {
+            // lanes < cnt each take one deferred collider, in queue (slot) order
+            const bool has = lane < cnt;
+            int proc = -1;
+            float b6[6];
+            P9 c;
+            unsigned int slot = 0;
+            if (has) {
+                slot = ql[lane];
+                c.r = qs[0 * kQW + lane]; c.z = qs[1 * kQW + lane]; c.vr = qs[2 * kQW + lane];
+                c.vt = qs[3 * kQW + lane]; c.vz = qs[4 * kQW + lane]; c.ar = qs[5 * kQW + lane];
+                c.at = qs[6 * kQW + lane]; c.az = qs[7 * kQW + lane]; c.w = qs[8 * kQW + lane];
+                const uint4 x = draw(slot, a.step, kPurposeMcc, a.sp, 0, a.key0, a.key1);
+                proc = collide(a.sp, x, c.vr, c.vt, c.vz, a.m, slot, a.step, a.key0, a.key1, b6, &a.ctr->viol);
+                atomicAdd(&s_coll[proc], 1u);
             }
-            if (live) {
-                s = load9(a.f, p);
+            const bool born = has && proc == 2 && a.stage != nullptr;
+            const unsigned long long bm = __ballot(born);
+            if (born) {
+                const int idx = nb + __popcll(bm & lanemask_lt());
+                if (idx < kStageW) {
+                    Birth bb;
+                    bb.r = c.r; bb.z = c.z; bb.w = c.w;
+                    for (int k = 0; k < 6; ++k) bb.v[k] = b6[k];
+                    a.stage[stage_row * kStageW + idx] = bb;
+                } else {
+                    atomicMax(&a.ctr->err, 2);
+                }
+            }
+            nb += __popcll(bm);
+            if (has) {
+                d1_predict(c, a.dt);
+                const Loc L2 = locate(c.r, c.z, g);
+                if (absorb(g, L2, c.w, a.sign, s_abs, a.wallq)) {
+                    f[0][slot] = -1.0f;
+                } else {
+                    fallback += deposit(g, L2, c.w, win, wi0, wj0, a.dep);
+                    store8(f, slot, c);
+                }
+            }
+        };
+
+        for (int it = 0; it < kRounds; ++it) {
+            const long long p = sbase + (long long)it * 64 + lane;
+            if (it + 1 < kRounds) load9_guard(f, p + 64, n, nxt);
+            P9 s = cur;
+            bool coll = false;
+            if (s.r >= 0.0f) {
                 float Er, Ez;
                 gather_E(a.E, g, s.r, s.z, Er, Ez);
                 d1_correct(s, Er, Ez, a.qm, a.dt);
-                Loc L = locate(s.r, s.z, g);
+                const Loc L = locate(s.r, s.z, g);
                 if (absorb(g, L, s.w, a.sign, s_abs, a.wallq)) {
-                    a.f[0][p] = -1.0f;
-                    live = false;
+                    f[0][p] = -1.0f;
                 } else {
-                    uint4 x = draw((uint32_t)p, a.step, kPurposeMcc, a.sp, 0, a.key0, a.key1);
+                    const uint4 x = draw((uint32_t)p, a.step, kPurposeMcc, a.sp, 0, a.key0, a.key1);
                     coll = x.x < a.m.thresh;
                     if (!coll) {
                         d1_predict(s, a.dt);
-                        Loc L2 = locate(s.r, s.z, g);
+                        const Loc L2 = locate(s.r, s.z, g);
                         if (absorb(g, L2, s.w, a.sign, s_abs, a.wallq)) {
-                            a.f[0][p] = -1.0f;
+                            f[0][p] = -1.0f;
                         } else {
-                            deposit(g, L2, s.w, win, wi0, wj0, a.dep, &s_fallback);
-                            store8(a.f, p, s);
+                            fallback += deposit(g, L2, s.w, win, wi0, wj0, a.dep);
+                            store8(f, p, s);
                         }
                     }
                 }
             }
-            // ballot compaction of this round's colliders, in slot order
-            unsigned long long mask = __ballot(coll);
-            if (lane == 0) wave_cnt[wave] = __popcll(mask);
-            __syncthreads();
+            // ballot compaction of this round's colliders into the queue
+            const unsigned long long m = __ballot(coll);
             if (coll) {
-                int q = s_qn + __popcll(mask & lanemask_lt());
-                for (int w2 = 0; w2 < wave; ++w2) q += wave_cnt[w2];
-                qslot[q] = (unsigned int)p;
-                qst[0][q] = s.r; qst[1][q] = s.z; qst[2][q] = s.vr; qst[3][q] = s.vt; qst[4][q] = s.vz;
-                qst[5][q] = s.ar; qst[6][q] = s.at; qst[7][q] = s.az; qst[8][q] = s.w;
+                const int q = qn + __popcll(m & lanemask_lt());
+                ql[q] = (unsigned int)p;
+                qs[0 * kQW + q] = s.r; qs[1 * kQW + q] = s.z; qs[2 * kQW + q] = s.vr; qs[3 * kQW + q] = s.vt;
+                qs[4 * kQW + q] = s.vz; qs[5 * kQW + q] = s.ar; qs[6 * kQW + q] = s.at; qs[7 * kQW + q] = s.az;
+                qs[8 * kQW + q] = s.w;
             }
-            __syncthreads();
-            if (tid == 0) {
-                int t = 0;
-                for (int w2 = 0; w2 < kBlock / 64; ++w2) t += wave_cnt[w2];
-                s_qn += t;
-            }
-            __syncthreads();
-            const int qn = s_qn;
-            if (qn > kQCap - kBlock || it == kItems - 1) {
-                // process the queue with full waves
-                for (int b0 = 0; b0 < qn; b0 += kBlock) {
-                    const int q = b0 + tid;
-                    const bool has = q < qn;
-                    int proc = -1;
-                    float b6[6];
-                    P9 c;
-                    unsigned int slot = 0;
-                    if (has) {
-                        slot = qslot[q];
-                        c.r = qst[0][q]; c.z = qst[1][q]; c.vr = qst[2][q]; c.vt = qst[3][q]; c.vz = qst[4][q];
-                        c.ar = qst[5][q]; c.at = qst[6][q]; c.az = qst[7][q]; c.w = qst[8][q];
-                        uint4 x = draw(slot, a.step, kPurposeMcc, a.sp, 0, a.key0, a.key1);
-                        proc = collide(a.sp, x, c.vr, c.vt, c.vz, a.m, slot, a.step, a.key0, a.key1, b6,
-                                       &a.ctr->viol);
-                        atomicAdd(&s_coll[proc], 1u);
-                    }
-                    const bool born = has && proc == 2 && a.stage != nullptr;
-                    unsigned long long bm = __ballot(born);
-                    __syncthreads();
-                    if (lane == 0) wave_cnt[wave] = __popcll(bm);
-                    __syncthreads();
-                    if (born) {
-                        int idx = s_nb + __popcll(bm & lanemask_lt());
-                        for (int w2 = 0; w2 < wave; ++w2) idx += wave_cnt[w2];
-                        if (idx < kStageCap) {
-                            Birth bb;
-                            bb.r = c.r; bb.z = c.z; bb.w = c.w;
-                            for (int k = 0; k < 6; ++k) bb.v[k] = b6[k];
-                            a.stage[chunk * kStageCap + idx] = bb;
-                        } else {
-                            atomicMax(&a.ctr->err, 2);
-                        }
-                    }
-                    __syncthreads();
-                    if (tid == 0) {
-                        int t = 0;
-                        for (int w2 = 0; w2 < kBlock / 64; ++w2) t += wave_cnt[w2];
-                        s_nb += t;
-                    }
-                    if (has) {
-                        d1_predict(c, a.dt);
-                        Loc L2 = locate(c.r, c.z, g);
-                        if (absorb(g, L2, c.w, a.sign, s_abs, a.wallq)) {
-                            a.f[0][slot] = -1.0f;
-                        } else {
-                            deposit(g, L2, c.w, win, wi0, wj0, a.dep, &s_fallback);
-                            store8(a.f, slot, c);
-                        }
-                    }
+            qn += __popcll(m);
+            wave_sync();
+            if (qn >= 64) {
+                run_queue(64);
+                wave_sync();
+                // move the remaining qn - 64 (< 64) entries to the front
+                const int rest = qn - 64;
+                if (lane < rest) {
+                    float t[9];
+                    for (int k = 0; k < 9; ++k) t[k] = qs[k * kQW + 64 + lane];
+                    const unsigned int sl = ql[64 + lane];
+                    for (int k = 0; k < 9; ++k) qs[k * kQW + lane] = t[k];
+                    ql[lane] = sl;
                 }
-                __syncthreads();
-                if (tid == 0) s_qn = 0;
-                __syncthreads();
+                qn = rest;
+                wave_sync();
             }
+            cur = nxt;
         }
+        if (qn > 0) run_queue(qn);
+        if (lane == 0 && a.stage_cnt != nullptr) a.stage_cnt[stage_row] = min(nb, kStageW);
         // flush the window to the global grid and clear it
         __syncthreads();
         for (int k = tid; k < kWin * kWin; k += kBlock) {
-            unsigned long long v = win[k];
+            const unsigned long long v = win[k];
             if (v != 0ull) {
-                int gi = wi0 + k % kWin, gj = wj0 + k / kWin;
+                const int gi = wi0 + k % kWin, gj = wj0 + k / kWin;
                 if (gi >= 0 && gi <= g.nr && gj >= 0 && gj <= g.nz) atomicAdd(&a.dep[gj * g.w + gi], v);
                 win[k] = 0ull;
             }
         }
-        if (tid == 0 && a.stage_cnt != nullptr) a.stage_cnt[chunk] = min(s_nb, kStageCap);
         __syncthreads();
     }
+    for (int o = 32; o > 0; o >>= 1) fallback += __shfl_down(fallback, o);
+    if (lane == 0 && fallback) atomicAdd(&s_fallback, fallback);
+    __syncthreads();
     if (tid < 4) {
         if (s_abs[tid]) atomicAdd(&a.ctr->absorbed[a.sp][tid], s_abs[tid]);
         if (s_coll[tid]) atomicAdd(&a.ctr->coll[a.sp][tid], (unsigned long long)s_coll[tid]);
@@ -331,37 +360,58 @@ void launch_particles(pic_handle* h, int sp) {
 }
 
 // ---------------------------------------------------------------- births
-// One block: exclusive scan of the per-chunk birth counts of the electron
-// pass (slot order), capacity check, append bases.
-__global__ __launch_bounds__(1024) void k_birth_scan(DevCounters* c, const int* cnt, int* off, long long cap_e,
+// Births are appended in parent-slot order: the staged counts of the
+// (chunk, wavefront) rows are summed per segment of 1024 rows (coalesced),
+// the segment sums are scanned by one block (which also checks capacity and
+// sets the append bases), and the append kernel scans each segment locally.
+constexpr int kSegRows = 1024;
+
+__global__ __launch_bounds__(kSegRows) void k_birth_segsum(const DevCounters* c, const int* cnt, int* segsum) {
+    __shared__ int sh[kSegRows / 64];
+    const long long rows = (c->n_slots[0] + kChunk - 1) / kChunk * kWaves;
+    const long long nseg = (rows + kSegRows - 1) / kSegRows;
+    for (long long b = blockIdx.x; b < nseg; b += gridDim.x) {
+        const long long i = b * kSegRows + threadIdx.x;
+        int v = (i < rows) ? cnt[i] : 0;
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int t = 0;
+            for (int w = 0; w < kSegRows / 64; ++w) t += sh[w];
+            segsum[b] = t;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_birth_scan(DevCounters* c, const int* segsum, int* segoff, long long cap_e,
                                                      long long cap_i) {
     __shared__ long long s_part[1024];
-    __shared__ long long s_carry;
     const int tid = threadIdx.x;
-    const long long nch = (c->n_slots[0] + kChunk - 1) / kChunk;
-    if (tid == 0) s_carry = 0;
-    __syncthreads();
-    for (long long b0 = 0; b0 < nch; b0 += 1024) {
-        long long i = b0 + tid;
-        long long v = (i < nch) ? (long long)cnt[i] : 0;
+    const long long rows = (c->n_slots[0] + kChunk - 1) / kChunk * kWaves;
+    const long long nseg = (rows + kSegRows - 1) / kSegRows;
+    long long carry = 0;
+    for (long long b0 = 0; b0 < nseg; b0 += 1024) {
+        const long long i = b0 + tid;
+        const long long v = (i < nseg) ? segsum[i] : 0;
         s_part[tid] = v;
         __syncthreads();
         for (int o = 1; o < 1024; o <<= 1) {
-            long long t = (tid >= o) ? s_part[tid - o] : 0;
+            const long long t = (tid >= o) ? s_part[tid - o] : 0;
             __syncthreads();
             s_part[tid] += t;
             __syncthreads();
         }
-        if (i < nch) off[i] = (int)(s_carry + s_part[tid] - v);
-        __syncthreads();
-        if (tid == 0) s_carry += s_part[1023];
+        if (i < nseg) segoff[i] = (int)(carry + s_part[tid] - v);
+        carry += s_part[1023];
         __syncthreads();
     }
     if (tid == 0) {
-        long long B = s_carry;
+        long long B = carry;
         c->base[0] = c->n_slots[0];
         c->base[1] = c->n_slots[1];
-        c->nch_births = nch;
+        c->nch_births = rows;
         if (c->n_slots[0] + B > cap_e || c->n_slots[1] + B > cap_i) {
             atomicMax(&c->err, 2);
             B = 0;
@@ -383,7 +433,7 @@ struct BirthArgs {
     DevCounters* ctr;
     const Birth* stage;
     const int* cnt;
-    const int* off;
+    const int* segoff;
     float dt;
 };
 
@@ -441,30 +491,43 @@ __device__ __forceinline__ void place_newborn(const Geo& g, float* const* f, lon
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_birth_append(BirthArgs a) {
-    const long long nch = a.ctr->nch_births;
+__global__ __launch_bounds__(kSegRows) void k_birth_append(BirthArgs a) {
+    __shared__ int sh[kSegRows];
+    const long long rows = a.ctr->nch_births;
     if (a.ctr->births_step == 0) return;
     const long long be = a.ctr->base[0], bi = a.ctr->base[1];
-    for (long long chunk = blockIdx.x; chunk < nch; chunk += gridDim.x) {
-        int cnt = a.cnt[chunk];
-        if (cnt == 0) continue;
-        long long o = a.off[chunk];
-        for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
-            Birth b = a.stage[chunk * kStageCap + k];
+    const long long nseg = (rows + kSegRows - 1) / kSegRows;
+    for (long long b = blockIdx.x; b < nseg; b += gridDim.x) {
+        const long long row = b * kSegRows + threadIdx.x;
+        const int cnt = (row < rows) ? a.cnt[row] : 0;
+        sh[threadIdx.x] = cnt;
+        __syncthreads();
+        for (int o = 1; o < kSegRows; o <<= 1) {
+            const int t = ((int)threadIdx.x >= o) ? sh[threadIdx.x - o] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += t;
+            __syncthreads();
+        }
+        const long long o = (long long)a.segoff[b] + sh[threadIdx.x] - cnt;
+        __syncthreads();
+        for (int k = 0; k < cnt; ++k) {
+            const Birth bb = a.stage[row * kStageW + k];
             P9 e;
-            e.r = b.r; e.z = b.z; e.vr = b.v[0]; e.vt = b.v[1]; e.vz = b.v[2];
-            e.ar = 0.0f; e.at = 0.0f; e.az = 0.0f; e.w = b.w;
+            e.r = bb.r; e.z = bb.z; e.vr = bb.v[0]; e.vt = bb.v[1]; e.vz = bb.v[2];
+            e.ar = 0.0f; e.at = 0.0f; e.az = 0.0f; e.w = bb.w;
             place_newborn(a.g, a.fe, be + o + k, e, a.dt, 0, a.dep_e, a.wallq, a.ctr);
             P9 i = e;
-            i.vr = b.v[3]; i.vt = b.v[4]; i.vz = b.v[5];
+            i.vr = bb.v[3]; i.vt = bb.v[4]; i.vz = bb.v[5];
             place_newborn(a.g, a.fi, bi + o + k, i, a.dt, 1, a.dep_i, a.wallq, a.ctr);
         }
     }
 }
 
 void launch_births(pic_handle* h) {
-    hipLaunchKernelGGL(k_birth_scan, dim3(1), dim3(1024), 0, h->stream, h->ctr, h->stage_cnt, h->stage_off,
-                       (long long)h->cap[0], (long long)h->cap[1]);
+    hipLaunchKernelGGL(k_birth_segsum, dim3(256), dim3(kSegRows), 0, h->stream, (const DevCounters*)h->ctr,
+                       (const int*)h->stage_cnt, h->stage_off);
+    hipLaunchKernelGGL(k_birth_scan, dim3(1), dim3(1024), 0, h->stream, h->ctr, (const int*)h->stage_off,
+                       h->stage_segoff, (long long)h->cap[0], (long long)h->cap[1]);
     BirthArgs a;
     a.g = make_geo(h);
     for (int k = 0; k < 9; ++k) {
@@ -477,9 +540,9 @@ void launch_births(pic_handle* h) {
     a.ctr = h->ctr;
     a.stage = h->stage;
     a.cnt = h->stage_cnt;
-    a.off = h->stage_off;
+    a.segoff = h->stage_segoff;
     a.dt = (float)h->dt;
-    hipLaunchKernelGGL(k_birth_append, dim3(512), dim3(kBlock), 0, h->stream, a);
+    hipLaunchKernelGGL(k_birth_append, dim3(256), dim3(kSegRows), 0, h->stream, a);
 }
 
 // ------------------------------------------------------------------ loader

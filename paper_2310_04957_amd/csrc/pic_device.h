@@ -29,12 +29,13 @@ struct Geo {
 
 struct Loc {
     int inside, edge, i, j;
-    int64_t fr, fz;
+    uint32_t fr, fz;
 };
 
 // Fixed-point position q = floor((double)x * 2^F / dx): cell q >> F,
 // fraction q & (2^F - 1).  Outside when !(r < R), !(z > 0), !(z < Z) or
 // the cell index leaves the grid; `edge` then names the edge crossed.
+// Grids have at most 4096 cells a side, so q < 2^32.
 __device__ __forceinline__ Loc locate(float r, float z, const Geo& g) {
     Loc L;
     L.inside = 0; L.edge = 0; L.i = 0; L.j = 0; L.fr = 0; L.fz = 0;
@@ -42,14 +43,14 @@ __device__ __forceinline__ Loc locate(float r, float z, const Geo& g) {
     if (!(rd < g.R)) { L.edge = 0; return L; }
     if (!(zd > 0.0)) { L.edge = 1; return L; }
     if (!(zd < g.Z)) { L.edge = 2; return L; }
-    int64_t qr = (int64_t)floor(rd * g.Sr);
-    int64_t qz = (int64_t)floor(zd * g.Sz);
+    uint32_t qr = (uint32_t)floor(rd * g.Sr);
+    uint32_t qz = (uint32_t)floor(zd * g.Sz);
     int i = (int)(qr >> kFBits), j = (int)(qz >> kFBits);
     if (i >= g.nr) { L.edge = 0; return L; }
     if (j >= g.nz) { L.edge = 2; return L; }
     L.i = i; L.j = j;
-    L.fr = qr & ((1LL << kFBits) - 1);
-    L.fz = qz & ((1LL << kFBits) - 1);
+    L.fr = qr & ((1u << kFBits) - 1u);
+    L.fz = qz & ((1u << kFBits) - 1u);
     L.inside = 1;
     return L;
 }
@@ -62,11 +63,11 @@ __device__ __forceinline__ Loc locate(float r, float z, const Geo& g) {
 // (i+1,j+1); the four sum to floor(W 2^K) exactly.
 __device__ __forceinline__ void node_shares(const Loc& L, double W, const double* invd, int64_t c[4]) {
 #pragma clang fp contract(off)
-    int64_t nrr = 2LL * (int64_t)L.i * L.fr * (1LL << kFBits) + L.fr * L.fr;
+    const uint64_t nrr = (((uint64_t)(2u * (uint32_t)L.i) * (uint64_t)L.fr) << kFBits) + (uint64_t)L.fr * (uint64_t)L.fr;
     double wr = (double)nrr * invd[L.i];
     double wrb = 1.0 - wr;
     double wz = (double)L.fz * 0x1p-20;
-    double wzb = (double)((1LL << kFBits) - L.fz) * 0x1p-20;
+    double wzb = (double)((1u << kFBits) - L.fz) * 0x1p-20;
     double t;
     t = W * wr; t = t * wz; t = t * 0x1p32;
     int64_t c11 = (int64_t)floor(t);

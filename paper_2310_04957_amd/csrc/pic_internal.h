@@ -15,7 +15,9 @@ namespace pic {
 constexpr int kBlock = 256;           // threads per block for particle and sort kernels
 constexpr int kItems = 16;            // particles per thread per chunk
 constexpr int kChunk = kBlock * kItems;
+constexpr int kWaves = kBlock / 64;   // wavefronts per block of the particle kernel
 constexpr int kStageCap = 256;        // staged ionisation births per chunk
+constexpr int kStageW = kStageCap / kWaves;   // ... per (chunk, wavefront)
 constexpr int kMaxLevels = 16;
 constexpr int kMaxCoarse = 320;       // active nodes of the coarsest multigrid level
 constexpr int kRedBlocks = 1024;      // partial sums of a grid reduction
@@ -86,7 +88,7 @@ struct pic_handle {
     uint32_t* bsum;
     // births
     pic::Birth* stage;
-    int *stage_cnt, *stage_off;
+    int *stage_cnt, *stage_off, *stage_segoff;   // stage_off holds segment sums
     // deposits and grids
     unsigned long long* dep[2][2];  // [buffer][species]
     int dep_cur;

@@ -150,50 +150,72 @@ __device__ __forceinline__ unsigned long long lanemask_lt_s() {
     return (1ull << (threadIdx.x & 63)) - 1ull;
 }
 
-// stable scatter: element order inside a chunk is (item, thread); ranks
-// among equal digits come from 8 ballots per round
+// peers of a lane: the valid lanes of its wavefront holding the same digit
+__device__ __forceinline__ unsigned long long digit_peers(bool valid, uint32_t d) {
+    unsigned long long peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const unsigned long long m = __ballot((d >> b) & 1u);
+        peers &= ((d >> b) & 1u) ? m : ~m;
+    }
+    return peers;
+}
+
+// Stable scatter of one 8-bit digit.  Each wavefront owns a contiguous
+// quarter of the chunk and walks it twice: first counting its digits, then
+// (after one block-wide offset computation) placing every element at
+// chunk offset + earlier wavefronts' counts + its rank among equal digits
+// before it.  Ranks come from wavefront ballots, so the order is fixed.
 __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* kin, const uint32_t* vin, uint32_t* kout,
                                                     uint32_t* vout, const uint32_t* offs, const long long* n_slots,
                                                     int sp, int shift) {
-    __shared__ unsigned int run[256];
-    __shared__ unsigned int wcnt[kBlock / 64][256];
+    __shared__ unsigned int wcnt[kWaves][256];
+    __shared__ unsigned int wbase[kWaves][256];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    constexpr int slice = kChunk / kWaves;
     const long long n = n_slots[sp];
     const long long nch = (n + kChunk - 1) / kChunk;
     for (long long c = blockIdx.x; c < nch; c += gridDim.x) {
-        run[tid] = offs[(long long)tid * nch + c];
-        for (int w2 = 0; w2 < kBlock / 64; ++w2) wcnt[w2][tid] = 0u;
+        for (int w2 = 0; w2 < kWaves; ++w2) wcnt[w2][tid] = 0u;
         __syncthreads();
-        for (int it = 0; it < kItems; ++it) {
-            const long long p = c * kChunk + (long long)it * kBlock + tid;
+        const long long s0 = c * kChunk + (long long)wave * slice;
+        for (int it = 0; it < slice / 64; ++it) {
+            const long long p = s0 + it * 64 + lane;
             const bool valid = p < n;
-            uint32_t key = valid ? kin[p] : 0u;
-            uint32_t val = valid ? vin[p] : 0u;
-            uint32_t d = (key >> shift) & 0xFFu;
-            unsigned long long peers = __ballot(valid);
-#pragma unroll
-            for (int b = 0; b < 8; ++b) {
-                unsigned long long m = __ballot((d >> b) & 1u);
-                peers &= ((d >> b) & 1u) ? m : ~m;
-            }
-            const int rank = __popcll(peers & lanemask_lt_s());
-            if (valid && rank == 0) wcnt[wave][d] = (unsigned int)__popcll(peers);
-            __syncthreads();
-            if (valid) {
-                unsigned int pos = run[d] + rank;
-                for (int w2 = 0; w2 < wave; ++w2) pos += wcnt[w2][d];
-                kout[pos] = key;
-                vout[pos] = val;
-            }
-            __syncthreads();
-            unsigned int add = 0;
-            for (int w2 = 0; w2 < kBlock / 64; ++w2) {
-                add += wcnt[w2][tid];
-                wcnt[w2][tid] = 0u;
-            }
-            run[tid] += add;
-            __syncthreads();
+            const uint32_t d = valid ? (kin[p] >> shift) & 0xFFu : 0u;
+            const unsigned long long peers = digit_peers(valid, d);
+            if (valid && __popcll(peers & lanemask_lt_s()) == 0) wcnt[wave][d] += (unsigned int)__popcll(peers);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
         }
+        __syncthreads();
+        {
+            unsigned int run = offs[(long long)tid * nch + c];
+            for (int w2 = 0; w2 < kWaves; ++w2) {
+                wbase[w2][tid] = run;
+                run += wcnt[w2][tid];
+            }
+        }
+        __syncthreads();
+        for (int it = 0; it < slice / 64; ++it) {
+            const long long p = s0 + it * 64 + lane;
+            const bool valid = p < n;
+            const uint32_t key = valid ? kin[p] : 0u;
+            const uint32_t d = (key >> shift) & 0xFFu;
+            const unsigned long long peers = digit_peers(valid, d);
+            const int rank = __popcll(peers & lanemask_lt_s());
+            if (valid) {
+                const unsigned int pos = wbase[wave][d] + rank;
+                kout[pos] = key;
+                vout[pos] = vin[p];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            if (valid && rank == 0) wbase[wave][d] += (unsigned int)__popcll(peers);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
+        __syncthreads();
     }
 }
 

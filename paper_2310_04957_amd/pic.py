@@ -49,7 +49,8 @@ class Gas(C.Structure):
 class Run(C.Structure):
     _fields_ = [("n_e", C.c_int64), ("n_i", C.c_int64), ("cap_e", C.c_int64), ("cap_i", C.c_int64),
                 ("n0", C.c_double), ("Te_eV", C.c_double), ("Ti_eV", C.c_double),
-                ("steps_per_period", C.c_int32), ("sort_every", C.c_int32), ("seed", C.c_uint64),
+                ("steps_per_period", C.c_int32), ("sort_every", C.c_int32), ("sort_every_ion", C.c_int32),
+                ("seed", C.c_uint64),
                 ("load", C.c_int32), ("timing", C.c_int32)]
 
 
@@ -139,7 +140,8 @@ def make_config(w, load=True, timing=False, method=None, inner_tol=1e-4):
               "C_b", "R_b", "L_b"):
         setattr(cfg.circ, f, c[f])
     cfg.gas.p_Pa, cfg.gas.T_gas_K = gas["p_Pa"], gas["T_K"]
-    for f in ("n_e", "n_i", "cap_e", "cap_i", "n0", "Te_eV", "Ti_eV", "steps_per_period", "sort_every", "seed"):
+    for f in ("n_e", "n_i", "cap_e", "cap_i", "n0", "Te_eV", "Ti_eV", "steps_per_period", "sort_every",
+              "sort_every_ion", "seed"):
         setattr(cfg.run, f, run[f])
     cfg.run.load = 1 if load else 0
     cfg.run.timing = 1 if timing else 0
