@@ -51,7 +51,11 @@ enum {
 enum { PIC_VACUUM = 0, PIC_DIEL = 1, PIC_COND = 2 };                 /* region kinds */
 enum { PIC_GROUND = 0, PIC_POWERED = 1, PIC_NEUMANN = -1 };           /* conductor ids / edge bc */
 enum { PIC_IDEAL_SOURCE = 0, PIC_SERIES_RLC = 1, PIC_LMATCH = 2 };    /* circuits */
-enum { PIC_SOLVE_MGPCG_FP64 = 0, PIC_SOLVE_IR_MG = 1 };              /* field-solve methods */
+/* field-solve methods: FP64 MG-PCG; FP64 iterative refinement around an FP32
+   inner solve by MG-PCG, by flexible CG preconditioned with the U-net below
+   (MG-PCG takes over when the network fails), or by CG without a
+   preconditioner (the reference point of what the network gains) */
+enum { PIC_SOLVE_MGPCG_FP64 = 0, PIC_SOLVE_IR_MG = 1, PIC_SOLVE_IR_UNET = 2, PIC_SOLVE_IR_CG = 3 };
 
 /* A rectangle [r0,r1) x [z0,z1) in metres.  Each cell takes the last region
    that contains its centre.  kind PIC_COND uses cond_id (0 ground, 1 the
@@ -99,6 +103,8 @@ typedef struct {
     double tol;                 /* ||b - K phi||_2 / ||b||_2 at which a solve stops */
     int32_t max_iter;           /* Krylov iterations per solve */
     double inner_tol;           /* IR: relative tolerance of each FP32 inner solve */
+    int32_t unet_batch;         /* learned preconditioner: training batch capacity (0: no U-net) */
+    int32_t unet_pairs;         /* learned preconditioner: harvested (residual, error) pair slots */
 } pic_solver;
 
 typedef struct {
@@ -129,6 +135,7 @@ typedef struct {
     double ms_particles[2], ms_births, ms_sort, ms_field, ms_refresh; /* accumulated since last reset */
     int64_t timed_steps, deposit_fallback;
     int32_t error;              /* sticky error raised on the device (PIC_E_CAPACITY ...) */
+    int64_t unet_pairs, unet_fallbacks, unet_applications;
 } pic_diag_out;
 
 typedef struct {
@@ -197,6 +204,48 @@ int pic_solve_once(pic_handle* h, const double* Q, const double* chi, double U_E
 
 /* Set t, Q_E, U_E, circ[5], C_eq (9 doubles) -- for single-step parity. */
 int pic_set_state(pic_handle* h, const double* st9);
+
+/* ---- learned preconditioner (requires solver.unet_batch > 0; nr and nz
+   multiples of 16) ----
+   A 5-level, 32-channel U-net on the node image of nz rows (z) by nr
+   columns (r); the node row z = Z and column r = R must be conductors and
+   are left out.  Input channels per pixel: the residual scaled to unit RMS
+   over the unknown nodes, chi/(1+chi), and 1 on unknown nodes (0 on
+   conductors).  Output: the error K^-1 r of that residual, also at unit RMS;
+   it preconditions flexible CG (method PIC_SOLVE_IR_UNET), which does not
+   depend on a scalar factor of the preconditioner output.  MG-PCG takes over
+   a solve in which the output stops being a descent direction.
+   Parameters: one FP32 vector, per 3x3 convolution w[9][cout][cin] (tap
+   t = 3 (dy+1) + (dx+1), dy along z) then b[cout], in the order enc1a enc1b
+   ... enc4b mid5a mid5b dec4a dec4b ... dec1a dec1b, then the 1x1 output
+   w[32] and b[1].  BF16 weights and activations, FP32 accumulation; the
+   master weights and Adam moments stay FP32. */
+int pic_unet_num_params(pic_handle* h, int64_t* n);
+/* n must equal pic_unet_num_params; setting parameters also resets the Adam
+   moments and step count. */
+int pic_unet_set_params(pic_handle* h, const float* p, int64_t n);
+int pic_unet_get_params(pic_handle* h, float* p, int64_t n);
+/* Replace the solver settings (method, tol, max_iter, inner_tol); unet_batch
+   and unet_pairs must equal the values given to pic_init. */
+int pic_set_solver(pic_handle* h, const pic_solver* s);
+/* in3: [batch][nz][nr][3] FP32 input channels; out: [batch][nz][nr]. */
+int pic_unet_forward(pic_handle* h, const float* in3, int32_t batch, float* out);
+/* Gradient of the mean over mask of (out - target)^2 (mask, target:
+   [batch][nz][nr]) with respect to every parameter, and the loss. */
+int pic_unet_grads(pic_handle* h, const float* in3, const float* target, const float* mask, int32_t batch,
+                   float* grads, double* loss);
+/* During pic_step, store one (first residual, error removed) pair of the
+   field solve every `every` steps, both at unit RMS as above, in a ring of
+   solver.unet_pairs slots (every > 0 also harvests each pic_solve_once;
+   0 stops).  A solve that does not converge leaves no pair. */
+int pic_unet_harvest(pic_handle* h, int32_t every);
+/* Copy harvested pair `slot` (< min(pairs harvested, unet_pairs)): the
+   normalised residual, the normalised error, chi/(1+chi) and the mask, each
+   [nz][nr] FP32 (NULL skips one). */
+int pic_unet_get_pair(pic_handle* h, int32_t slot, float* r, float* e, float* chi, float* mask);
+/* Adam (lr, betas 0.9/0.999) on random batches of the harvested pairs;
+   loss_curve (or NULL) receives the loss of each step. */
+int pic_unet_train(pic_handle* h, int32_t steps, int32_t batch, double lr, uint64_t seed, double* loss_curve);
 
 #ifdef __cplusplus
 }

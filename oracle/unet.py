@@ -136,12 +136,16 @@ def loss_and_grad_out(out, target, mask):
     return (d * d).sum() / n, 2.0 * d / n
 
 
-def backward(p, cache, dout, levels=5):
-    """Gradients of every parameter given dL/d(out)."""
+def backward(p, cache, dout, levels=5, round_bf16=False):
+    """Gradients of every parameter given dL/d(out).  With round_bf16, every
+    stored activation gradient (the data gradients between layers) is rounded
+    to bfloat16, the storage precision of the GPU kernels; parameter
+    gradients stay exact sums."""
+    rnd = bf16 if round_bf16 else (lambda a: a)
     g = {}
     g["out.w"] = np.einsum("hw,hwc->c", dout, cache["last"])
     g["out.b"] = np.array([dout.sum()])
-    dh = dout[:, :, None] * p["out.w"][None, None, :]
+    dh = rnd(dout[:, :, None] * p["out.w"][None, None, :])
     C = p["out.w"].shape[0]
     dskips = {}
     for l in range(1, levels):
@@ -149,18 +153,21 @@ def backward(p, cache, dout, levels=5):
             name = f"dec{l}{s}"
             dpre = dh * (cache[name + ".out"] > 0)
             dh, g[name + ".w"], g[name + ".b"] = conv3x3_backward(cache[name + ".in"], p[name + ".w"], dpre)
+            dh = rnd(dh)
         dskips[l] = dh[:, :, C:]
-        dh = up2_backward(dh[:, :, :C])
+        dh = rnd(up2_backward(dh[:, :, :C]))
     for s in "ba":
         name = f"mid{levels}{s}"
         dpre = dh * (cache[name + ".out"] > 0)
         dh, g[name + ".w"], g[name + ".b"] = conv3x3_backward(cache[name + ".in"], p[name + ".w"], dpre)
+        dh = rnd(dh)
     for l in range(levels - 1, 0, -1):
-        dh = pool2_backward(dh) + dskips[l]
+        dh = rnd(pool2_backward(dh) + dskips[l])
         for s in "ba":
             name = f"enc{l}{s}"
             dpre = dh * (cache[name + ".out"] > 0)
             dh, g[name + ".w"], g[name + ".b"] = conv3x3_backward(cache[name + ".in"], p[name + ".w"], dpre)
+            dh = rnd(dh)
     return g
 
 
@@ -176,3 +183,27 @@ def adam_step(p, g, state, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
         mh = m / (1 - b1 ** t)
         vh = v / (1 - b2 ** t)
         p[k] = p[k] - lr * mh / (np.sqrt(vh) + eps)
+
+
+def flatten(p, levels=5):
+    """Parameters in the flat order of the GPU library: per 3x3 convolution
+    w[9][cout][cin] then b[cout], in forward order; then out.w, out.b."""
+    parts = []
+    for name, _, _ in layer_specs(p["out.w"].shape[0], p["enc1a.w"].shape[2], levels):
+        parts += [p[name + ".w"].ravel(), p[name + ".b"].ravel()]
+    parts += [p["out.w"].ravel(), p["out.b"].ravel()]
+    return np.concatenate(parts)
+
+
+def unflatten(v, C=32, cin=3, levels=5):
+    """Inverse of flatten."""
+    p, o = {}, 0
+    for name, ci, co in layer_specs(C, cin, levels):
+        p[name + ".w"] = np.asarray(v[o:o + 9 * co * ci], dtype=np.float64).reshape(9, co, ci)
+        o += 9 * co * ci
+        p[name + ".b"] = np.asarray(v[o:o + co], dtype=np.float64)
+        o += co
+    p["out.w"] = np.asarray(v[o:o + C], dtype=np.float64)
+    p["out.b"] = np.asarray(v[o + C:o + C + 1], dtype=np.float64)
+    assert o + C + 1 == len(v)
+    return p

@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libpic.so")
-SOURCES = ["api.hip", "particles.hip", "sort.hip", "field.hip"]
+SOURCES = ["api.hip", "particles.hip", "sort.hip", "field.hip", "unet.hip", "unet_kernels.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -51,9 +51,47 @@ int validate(const pic_config* c) {
     if (r.cap_e > 0xFFFFFFF0LL || r.cap_i > 0xFFFFFFF0LL || r.sort_every < 0 || r.sort_every_ion < 0)
         return PIC_E_CONFIG;
     if (!(c->gas.p_Pa >= 0) || !(c->gas.T_gas_K > 0) || !(r.n0 >= 0)) return PIC_E_CONFIG;
-    if (c->solver.method < 0 || c->solver.method > 1 || !(c->solver.tol > 0) || c->solver.max_iter < 1)
+    if (c->solver.method < 0 || c->solver.method > 3 || !(c->solver.tol > 0) || c->solver.max_iter < 1)
         return PIC_E_CONFIG;
+    const int ub = c->solver.unet_batch, up = c->solver.unet_pairs;
+    if (ub < 0 || ub > unet::kMaxBatch || up < 0 || up > unet::kMaxPairs) return PIC_E_CONFIG;
+    if (c->solver.method == PIC_SOLVE_IR_UNET && ub == 0) return PIC_E_CONFIG;
+    if (ub > 0 && ((g.nr % 16) || (g.nz % 16))) return PIC_E_CONFIG;
     return PIC_OK;
+}
+
+// the network sees nodes i < nr, j < nz: the rest must be conductors
+int unet_geometry_ok(const pic_handle* h) {
+    if (h->cfg.solver.unet_batch == 0) return PIC_OK;
+    for (int j = 0; j <= h->nz; ++j)
+        for (int i = 0; i <= h->nr; ++i)
+            if ((i == h->nr || j == h->nz) && h->h_node_kind[(size_t)j * h->w + i] < 0) return PIC_E_CONFIG;
+    return PIC_OK;
+}
+
+// He-normal initial weights from a splitmix64 stream (Box-Muller), zero biases
+uint64_t splitmix64(uint64_t& x) {
+    uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+double unit_open(uint64_t& x) { return ((double)(splitmix64(x) >> 11) + 0.5) * 0x1.0p-53; }
+
+std::vector<float> unet_initial_params(const unet::Net& n, uint64_t seed) {
+    std::vector<float> p((size_t)n.nparam, 0.0f);
+    uint64_t st = seed;
+    auto normal = [&]() {
+        const double u = unit_open(st), v = unit_open(st);
+        return std::sqrt(-2.0 * std::log(u)) * std::cos(2.0 * kPi * v);
+    };
+    for (int k = 0; k < unet::kConvs; ++k) {
+        const unet::Conv& c = n.conv[k];
+        const double sd = std::sqrt(2.0 / (9.0 * c.cin));
+        for (size_t e = 0; e < (size_t)9 * unet::kC * c.cin; ++e) p[c.woff + e] = (float)(sd * normal());
+    }
+    for (int e = 0; e < unet::kC; ++e) p[n.out_w + e] = (float)(std::sqrt(1.0 / unet::kC) * normal());
+    return p;
 }
 
 // cross sections for the electron null-collision bound (analytic argon
@@ -317,6 +355,14 @@ size_t layout(pic_handle* h, char* base) {
     h->lastU = c.take<double>(spp); h->lastI = c.take<double>(spp);
     h->ctr = c.take<DevCounters>(1);
     h->sc = c.take<DevScalars>(1);
+    h->unet_on = h->cfg.solver.unet_batch > 0;
+    if (h->unet_on) {
+        const int B = h->cfg.solver.unet_batch;
+        h->phi_old = c.take<double>(nn);
+        h->unet_stage = c.take<float>((size_t)B * h->nr * h->nz * 3);
+        c.off = (c.off + 255) & ~(size_t)255;
+        c.off += unet::layout(h->net, h->nz, h->nr, B, h->cfg.solver.unet_pairs, base ? base + c.off : nullptr);
+    }
     return c.off;
 }
 
@@ -465,7 +511,8 @@ int pic_workspace_size(const pic_config* cfg, size_t* bytes_out) {
     h->cfg = *cfg;
     derive(h);
     host_geometry(h);
-    rc = mg_plan(h);
+    rc = unet_geometry_ok(h);
+    if (rc == PIC_OK) rc = mg_plan(h);
     if (rc == PIC_OK) *bytes_out = layout(h, nullptr) + 256;
     delete h;
     return rc;
@@ -527,6 +574,18 @@ int pic_init(const pic_config* cfg, void* dev_workspace, size_t bytes, void* hip
     // the assembly above added the first deposit to the period sums: undo
     launch_zero_u64(h->psum[0], (size_t)h->nn, h->stream);
     launch_zero_u64(h->psum[1], (size_t)h->nn, h->stream);
+    if (h->unet_on) {
+        unet::Net& n = h->net;
+        const std::vector<float> p0 = unet_initial_params(n, cfg->run.seed);
+        if (hipMemcpyAsync(n.p, p0.data(), p0.size() * 4, hipMemcpyHostToDevice, h->stream) != hipSuccess) {
+            pic_free(h);
+            return PIC_E_HIP;
+        }
+        unet::pack_all(n, h->stream);
+        h->img_free = 0;
+        for (int j = 0; j < h->nz; ++j)
+            for (int i = 0; i < h->nr; ++i) h->img_free += h->h_node_kind[(size_t)j * h->w + i] < 0;
+    }
     rc = sync_err(h);
     if (rc) { pic_free(h); return rc; }
     *out = h;
@@ -546,7 +605,9 @@ int pic_step(pic_handle* h, int32_t nsteps) {
         launch_circuit(h);
         int32_t it = 0;
         double rel = 0.0;
+        h->harvest_now = h->harvest_every > 0 && h->step % h->harvest_every == 0;
         int rc = field_solve(h, h->phi, h->Q, &h->sc->U_E, c.solver.tol, c.solver.method, &it, &rel);
+        h->harvest_now = false;
         h->solver_iters = it;
         h->solver_relres = rel;
         if (rc != PIC_OK) return rc;
@@ -632,6 +693,9 @@ int pic_diag(pic_handle* h, pic_diag_out* out, const pic_diag_buffers* bufs) {
     out->timed_steps = h->timed_steps;
     out->deposit_fallback = (int64_t)ct.fallback;
     out->error = h->sticky_err;
+    out->unet_pairs = h->net.n_pairs;
+    out->unet_fallbacks = h->unet_fallbacks;
+    out->unet_applications = h->unet_apps;
     const int spp = h->cfg.run.steps_per_period;
     std::vector<double> U(spp), I(spp);
     if (hipMemcpy(U.data(), h->lastU, spp * 8, hipMemcpyDeviceToHost) != hipSuccess) return PIC_E_HIP;
@@ -800,7 +864,9 @@ int pic_solve_once(pic_handle* h, const double* Q, const double* chi, double U_E
     hipLaunchKernelGGL(k_set_U, dim3(1), dim3(1), 0, h->stream, h->sc, U_E);
     launch_faces(h);
     mg_rebuild(h);
+    h->harvest_now = h->harvest_every > 0;
     int rc = field_solve(h, h->phi, h->Q, &h->sc->U_E, tol, h->cfg.solver.method, iters, relres);
+    h->harvest_now = false;
     if (hipMemcpy(phi_inout, h->phi, nn * 8, hipMemcpyDeviceToHost) != hipSuccess) return PIC_E_HIP;
     return rc;
 }
@@ -810,6 +876,147 @@ int pic_set_state(pic_handle* h, const double* st9) {
     hipLaunchKernelGGL(k_set_state, dim3(1), dim3(1), 0, h->stream, h->sc, st9[0], st9[1], st9[2], st9[3], st9[4],
                        st9[5], st9[6], st9[7], st9[8]);
     return hipStreamSynchronize(h->stream) == hipSuccess ? PIC_OK : PIC_E_HIP;
+}
+
+int pic_set_solver(pic_handle* h, const pic_solver* sv) {
+    if (!h || !sv) return PIC_E_ARG;
+    pic_config c = h->cfg;
+    if (sv->unet_batch != c.solver.unet_batch || sv->unet_pairs != c.solver.unet_pairs) return PIC_E_CONFIG;
+    c.solver = *sv;
+    int rc = validate(&c);
+    if (rc) return rc;
+    h->cfg.solver = *sv;
+    return PIC_OK;
+}
+
+// ---- learned preconditioner
+
+int pic_unet_num_params(pic_handle* h, int64_t* n) {
+    if (!h || !n) return PIC_E_ARG;
+    if (!h->unet_on) return PIC_E_STATE;
+    *n = h->net.nparam;
+    return PIC_OK;
+}
+
+int pic_unet_set_params(pic_handle* h, const float* p, int64_t n) {
+    if (!h || !p) return PIC_E_ARG;
+    if (!h->unet_on) return PIC_E_STATE;
+    if (n != h->net.nparam) return PIC_E_ARG;
+    unet::Net& net = h->net;
+    HIP_OK(hipMemcpyAsync(net.p, p, (size_t)n * 4, hipMemcpyHostToDevice, h->stream));
+    // new weights start a new optimisation: Adam moments and step count reset
+    // (the moment arrays are padded to 256 bytes, so whole 8-byte words fit)
+    launch_zero_u64((unsigned long long*)net.m, ((size_t)n + 1) / 2, h->stream);
+    launch_zero_u64((unsigned long long*)net.v, ((size_t)n + 1) / 2, h->stream);
+    net.adam_t = 0;
+    unet::pack_all(net, h->stream);
+    HIP_OK(hipStreamSynchronize(h->stream));
+    return PIC_OK;
+}
+
+int pic_unet_get_params(pic_handle* h, float* p, int64_t n) {
+    if (!h || !p) return PIC_E_ARG;
+    if (!h->unet_on) return PIC_E_STATE;
+    if (n != h->net.nparam) return PIC_E_ARG;
+    HIP_OK(hipStreamSynchronize(h->stream));
+    HIP_OK(hipMemcpy(p, h->net.p, (size_t)n * 4, hipMemcpyDeviceToHost));
+    return PIC_OK;
+}
+
+static int unet_stage_inputs(pic_handle* h, const float* in3, int32_t batch) {
+    unet::Net& n = h->net;
+    const size_t npix = (size_t)batch * n.H * n.W;
+    HIP_OK(hipMemcpyAsync(h->unet_stage, in3, npix * 3 * 4, hipMemcpyHostToDevice, h->stream));
+    unet::input_from_f32(h->unet_stage, n.x0, npix, h->stream);
+    return PIC_OK;
+}
+
+int pic_unet_forward(pic_handle* h, const float* in3, int32_t batch, float* out) {
+    if (!h || !in3 || !out) return PIC_E_ARG;
+    if (!h->unet_on) return PIC_E_STATE;
+    if (batch < 1 || batch > h->net.B) return PIC_E_ARG;
+    int rc = unet_stage_inputs(h, in3, batch);
+    if (rc) return rc;
+    unet::forward(h->net, batch, h->stream);
+    HIP_OK(hipStreamSynchronize(h->stream));
+    HIP_OK(hipMemcpy(out, h->net.out, (size_t)batch * h->net.H * h->net.W * 4, hipMemcpyDeviceToHost));
+    return PIC_OK;
+}
+
+int pic_unet_grads(pic_handle* h, const float* in3, const float* target, const float* mask, int32_t batch,
+                   float* grads, double* loss) {
+    if (!h || !in3 || !target || !mask || !grads) return PIC_E_ARG;
+    if (!h->unet_on) return PIC_E_STATE;
+    unet::Net& n = h->net;
+    if (batch < 1 || batch > n.B) return PIC_E_ARG;
+    const size_t npix = (size_t)batch * n.H * n.W;
+    double cnt = 0.0;
+    for (size_t e = 0; e < npix; ++e) cnt += mask[e];
+    if (!(cnt > 0.0)) return PIC_E_ARG;
+    int rc = unet_stage_inputs(h, in3, batch);
+    if (rc) return rc;
+    HIP_OK(hipMemcpyAsync(n.target, target, npix * 4, hipMemcpyHostToDevice, h->stream));
+    HIP_OK(hipMemcpyAsync(n.mask, mask, npix * 4, hipMemcpyHostToDevice, h->stream));
+    unet::forward(n, batch, h->stream);
+    unet::backward(n, batch, (float)(1.0 / cnt), h->stream);
+    HIP_OK(hipStreamSynchronize(h->stream));
+    HIP_OK(hipMemcpy(grads, n.g, (size_t)n.nparam * 4, hipMemcpyDeviceToHost));
+    float l = 0.0f;
+    HIP_OK(hipMemcpy(&l, n.sums, 4, hipMemcpyDeviceToHost));
+    if (loss) *loss = l;
+    return PIC_OK;
+}
+
+int pic_unet_harvest(pic_handle* h, int32_t every) {
+    if (!h || every < 0) return PIC_E_ARG;
+    if (!h->unet_on) return PIC_E_STATE;
+    if (every > 0 && h->net.cap_pairs < 1) return PIC_E_CONFIG;
+    h->harvest_every = every;
+    return PIC_OK;
+}
+
+int pic_unet_get_pair(pic_handle* h, int32_t slot, float* r, float* e, float* chi, float* mask) {
+    if (!h) return PIC_E_ARG;
+    if (!h->unet_on) return PIC_E_STATE;
+    const unet::Net& n = h->net;
+    if (slot < 0 || slot >= std::min<int64_t>(n.n_pairs, n.cap_pairs)) return PIC_E_ARG;
+    HIP_OK(hipStreamSynchronize(h->stream));
+    const size_t img = (size_t)n.H * n.W;
+    if (r) HIP_OK(hipMemcpy(r, n.h_r + slot * img, img * 4, hipMemcpyDeviceToHost));
+    if (e) HIP_OK(hipMemcpy(e, n.h_e + slot * img, img * 4, hipMemcpyDeviceToHost));
+    if (chi) HIP_OK(hipMemcpy(chi, n.h_chi + slot * img, img * 4, hipMemcpyDeviceToHost));
+    if (mask) HIP_OK(hipMemcpy(mask, n.h_mask, img * 4, hipMemcpyDeviceToHost));
+    return PIC_OK;
+}
+
+int pic_unet_train(pic_handle* h, int32_t steps, int32_t batch, double lr, uint64_t seed, double* loss_curve) {
+    if (!h || steps < 0 || !(lr > 0)) return PIC_E_ARG;
+    if (!h->unet_on) return PIC_E_STATE;
+    unet::Net& n = h->net;
+    if (batch < 1 || batch > n.B) return PIC_E_ARG;
+    const int64_t avail = std::min<int64_t>(n.n_pairs, n.cap_pairs);
+    if (avail < 1 || h->img_free < 1) return PIC_E_STATE;
+    const float inv_n = (float)(1.0 / ((double)batch * (double)h->img_free));
+    uint64_t st = seed ^ 0x5DEECE66Dull;
+    std::vector<float> log(unet::kLossLog);
+    for (int32_t k = 0; k < steps; ++k) {
+        int idx[unet::kMaxBatch];
+        for (int b = 0; b < batch; ++b) idx[b] = (int)(splitmix64(st) % (uint64_t)avail);
+        unet::gather_batch(n, idx, batch, h->stream);
+        unet::forward(n, batch, h->stream);
+        unet::backward(n, batch, inv_n, h->stream);
+        unet::log_loss(n, k % unet::kLossLog, h->stream);
+        unet::adam_update(n, (float)lr, h->stream);
+        if ((k + 1) % unet::kLossLog == 0 || k + 1 == steps) {
+            HIP_OK(hipStreamSynchronize(h->stream));
+            const int m = k % unet::kLossLog + 1;
+            HIP_OK(hipMemcpy(log.data(), n.loss_log, (size_t)m * 4, hipMemcpyDeviceToHost));
+            if (loss_curve)
+                for (int e = 0; e < m; ++e) loss_curve[k + 1 - m + e] = log[e];
+        }
+    }
+    HIP_OK(hipStreamSynchronize(h->stream));
+    return PIC_OK;
 }
 
 }  // extern "C"

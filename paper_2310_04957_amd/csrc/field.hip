@@ -392,7 +392,47 @@ __global__ __launch_bounds__(256) void k_reduce(const double* part, DevScalars* 
     }
 }
 
-__global__ void k_begin_cg(DevScalars* s) { s->done = 0; s->iters = 0; }
+__global__ void k_begin_cg(DevScalars* s) { s->done = 0; s->iters = 0; s->fallback = 0; }
+
+// flexible CG: z.r and z.q of the new preconditioned residual in one pass
+__global__ __launch_bounds__(256) void k_dot2(const float* z, const float* r, const float* q, double* part,
+                                              const DevScalars* s, int nn) {
+    __shared__ double sh[4];
+    if (s->done) return;
+    double a = 0.0, b = 0.0;
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += gridDim.x * blockDim.x) {
+        a += (double)z[n] * (double)r[n];
+        b += (double)z[n] * (double)q[n];
+    }
+    double t1 = block_sum(a, sh);
+    double t2 = block_sum(b, sh);
+    if (threadIdx.x == 0) { part[blockIdx.x] = t1; part[kRedBlocks + blockIdx.x] = t2; }
+}
+
+// beta = -(z.q)/(p.q) keeps the new direction A-conjugate to the last one
+// (flexible CG with one stored direction); the preconditioner must keep
+// z.r > 0, else the solve is handed to multigrid
+__global__ __launch_bounds__(256) void k_reduce_fcg(const double* part, DevScalars* s) {
+    __shared__ double a[kRedBlocks], b[kRedBlocks];
+    if (s->done) return;
+    for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) { a[i] = part[i]; b[i] = part[kRedBlocks + i]; }
+    __syncthreads();
+    for (int o = kRedBlocks / 2; o > 0; o >>= 1) {
+        for (int i = threadIdx.x; i < o; i += blockDim.x) { a[i] += a[i + o]; b[i] += b[i + o]; }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const double zr = a[0], zq = b[0];
+    if (!(zr > 0.0) || !isfinite(zr) || !isfinite(zq)) { s->fallback = 1; s->done = 1; return; }
+    s->rz = zr;
+    s->beta = -zq / s->pq;
+}
+
+__global__ void k_fcg_start(DevScalars* s) {
+    if (!(s->rz > 0.0) || !isfinite(s->rz)) { s->fallback = 1; s->done = 1; }
+}
+
+__global__ void k_save_hscale(DevScalars* s) { s->hscale = s->scale; }
 
 // ------------------------------------------------------------- multigrid
 // level 0: damped Jacobi and residual on the 5-point operator
@@ -791,14 +831,22 @@ static void vcycle(pic_handle* h, int l, const T* b0, T* y0) {
 // preconditioned CG on the level-0 operator; r is overwritten, x receives
 // the correction.  Returns the iteration count.
 template <typename T>
-static int pcg(pic_handle* h, T* r, T* x, T* z, T* p, T* q, int max_iter, int* err) {
+static void precondition(pic_handle* h, int ident, const T* r, T* z) {
+    if (ident)
+        hipLaunchKernelGGL(k_copy<T>, grid_for(h->nn), dim3(256), 0, h->stream, z, r, (const DevScalars*)h->sc, h->nn);
+    else
+        vcycle<T>(h, 0, r, z);
+}
+
+template <typename T>
+static int pcg(pic_handle* h, T* r, T* x, T* z, T* p, T* q, int max_iter, int* err, int ident = 0) {
     using V = VecSet<T>;
     hipStream_t st = h->stream;
     const int nn = h->nn;
     DevScalars* s = h->sc;
     hipLaunchKernelGGL(k_begin_cg, dim3(1), dim3(1), 0, st, s);
     hipLaunchKernelGGL(k_fill<T>, grid_for(nn), dim3(256), 0, st, x, nn);
-    vcycle<T>(h, 0, r, z);
+    precondition<T>(h, ident, r, z);
     hipLaunchKernelGGL(k_copy<T>, grid_for(nn), dim3(256), 0, st, p, (const T*)z, s, nn);
     hipLaunchKernelGGL(k_dot<T>, dim3(kRedBlocks), dim3(256), 0, st, (const T*)r, (const T*)z, h->part, s, nn);
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, st, (const double*)h->part, s, 0);
@@ -810,7 +858,7 @@ static int pcg(pic_handle* h, T* r, T* x, T* z, T* p, T* q, int max_iter, int* e
         hipLaunchKernelGGL(k_update_xr<T>, dim3(kRedBlocks), dim3(256), 0, st, x, r, (const T*)p, (const T*)q,
                            h->part, s, nn);
         hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, st, (const double*)h->part, s, 2);
-        vcycle<T>(h, 0, r, z);
+        precondition<T>(h, ident, r, z);
         hipLaunchKernelGGL(k_dot<T>, dim3(kRedBlocks), dim3(256), 0, st, (const T*)r, (const T*)z, h->part, s, nn);
         hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, st, (const double*)h->part, s, 3);
         hipLaunchKernelGGL(k_update_p<T>, grid_for(nn), dim3(256), 0, st, p, (const T*)z, s, nn);
@@ -824,6 +872,62 @@ static int pcg(pic_handle* h, T* r, T* x, T* z, T* p, T* q, int max_iter, int* e
     if (hipStreamSynchronize(st) != hipSuccess) { *err = PIC_E_HIP; return it; }
     if (h->h_sc->nonfinite) *err = PIC_E_NONFINITE;
     return h->h_sc->iters;
+}
+
+// z = ||r|| UNet(r sqrt(n_free) / ||r||, chi / (1 + chi), mask) on the node
+// grid; rr points at r.r on the device
+static void unet_apply(pic_handle* h, const float* r, const double* rr, float* z) {
+    unet::Net& n = h->net;
+    unet::input_from_r32(n, r, rr, h->chi, h->node_kind, h->w, (double)h->img_free, h->stream);
+    unet::forward(n, 1, h->stream);
+    unet::out_to_z(n, rr, h->node_kind, z, h->w, h->nn, h->stream);
+    h->unet_apps++;
+}
+
+// Flexible CG (FP32) on the normalised residual with the network as the
+// preconditioner.  r is overwritten, x receives the correction.  Returns
+// the iteration count; sets DevScalars::fallback when the network output
+// stops being a descent direction.  The host reads the state after every
+// iteration: one network evaluation outweighs the read by far.
+static int fpcg(pic_handle* h, float* r, float* x, float* z, float* p, float* q, int max_iter, int* err) {
+    hipStream_t st = h->stream;
+    const int nn = h->nn;
+    DevScalars* s = h->sc;
+    hipLaunchKernelGGL(k_begin_cg, dim3(1), dim3(1), 0, st, s);
+    hipLaunchKernelGGL(k_fill<float>, grid_for(nn), dim3(256), 0, st, x, nn);
+    unet_apply(h, r, &s->one, z);    // r arrives with unit norm
+    hipLaunchKernelGGL(k_copy<float>, grid_for(nn), dim3(256), 0, st, p, (const float*)z, s, nn);
+    hipLaunchKernelGGL(k_dot<float>, dim3(kRedBlocks), dim3(256), 0, st, (const float*)r, (const float*)z, h->part, s,
+                       nn);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, st, (const double*)h->part, s, 0);
+    hipLaunchKernelGGL(k_fcg_start, dim3(1), dim3(1), 0, st, s);
+    for (int it = 0; it < max_iter; ++it) {
+        hipLaunchKernelGGL(k_spmv_dot<float>, dim3(kRedBlocks), dim3(256), 0, st, (const float*)h->ar32,
+                           (const float*)h->az32, (const int8_t*)h->node_kind, (const float*)p, q, h->part,
+                           (const DevScalars*)s, h->nr, h->nz);
+        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, st, (const double*)h->part, s, 1);
+        hipLaunchKernelGGL(k_update_xr<float>, dim3(kRedBlocks), dim3(256), 0, st, x, r, (const float*)p,
+                           (const float*)q, h->part, (const DevScalars*)s, nn);
+        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, st, (const double*)h->part, s, 2);
+        hipMemcpyAsync(h->h_sc, s, sizeof(DevScalars), hipMemcpyDeviceToHost, st);
+        if (hipStreamSynchronize(st) != hipSuccess) { *err = PIC_E_HIP; return it; }
+        if (h->h_sc->done) break;
+        unet_apply(h, r, &s->rr, z);
+        hipLaunchKernelGGL(k_dot2, dim3(kRedBlocks), dim3(256), 0, st, (const float*)z, (const float*)r,
+                           (const float*)q, h->part, (const DevScalars*)s, nn);
+        hipLaunchKernelGGL(k_reduce_fcg, dim3(1), dim3(256), 0, st, (const double*)h->part, s);
+        hipLaunchKernelGGL(k_update_p<float>, grid_for(nn), dim3(256), 0, st, p, (const float*)z,
+                           (const DevScalars*)s, nn);
+    }
+    hipMemcpyAsync(h->h_sc, s, sizeof(DevScalars), hipMemcpyDeviceToHost, st);
+    if (hipStreamSynchronize(st) != hipSuccess) { *err = PIC_E_HIP; return 0; }
+    if (h->h_sc->nonfinite) *err = PIC_E_NONFINITE;
+    if (!h->h_sc->done) h->h_sc->fallback = 1;   // out of iterations
+    return h->h_sc->iters;
+}
+
+__global__ __launch_bounds__(256) void k_copy64(double* dst, const double* src, int nn) {
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += gridDim.x * blockDim.x) dst[n] = src[n];
 }
 
 template <typename T>
@@ -849,6 +953,11 @@ int field_solve(pic_handle* h, double* phi, const double* Q, const double* Up, d
     const int nn = h->nn;
     const int fp64 = (method == PIC_SOLVE_MGPCG_FP64);
     const int max_outer = fp64 ? 4 : 30;
+    // a harvested solve stores its first residual and, once converged, the
+    // error phi - phi_old it removed (both normalised by ||r0||)
+    const bool harvest = h->harvest_now && h->unet_on && Q != nullptr;
+    const int slot = harvest ? (int)(h->net.n_pairs % std::max(h->net.cap_pairs, 1)) : 0;
+    bool harvested_r = false;
     int total = 0, outer = 0, err = 0;
     double rel = 0.0;
     for (;; ++outer) {
@@ -860,6 +969,12 @@ int field_solve(pic_handle* h, double* phi, const double* Q, const double* Up, d
         rel = h->h_sc->relres;
         if (h->h_sc->nonfinite) { err = PIC_E_NONFINITE; break; }
         if (rel <= tol || outer >= max_outer) break;
+        if (harvest && outer == 0 && h->net.cap_pairs > 0) {
+            hipLaunchKernelGGL(k_save_hscale, dim3(1), dim3(1), 0, st, h->sc);
+            hipLaunchKernelGGL(k_copy64, grid_for(nn), dim3(256), 0, st, h->phi_old, (const double*)phi, nn);
+            unet::harvest_r(h->net, slot, h->r64, &h->sc->hscale, h->chi, h->node_kind, h->w, (double)h->img_free, st);
+            harvested_r = true;
+        }
         if (fp64) {
             total += pcg<double>(h, h->r64, h->x64, h->z64, h->p64, h->q64, h->cfg.solver.max_iter, &err);
             hipLaunchKernelGGL(k_add_phi<double>, grid_for(nn), dim3(256), 0, st, phi, (const double*)h->x64,
@@ -869,13 +984,24 @@ int field_solve(pic_handle* h, double* phi, const double* Q, const double* Up, d
             hipLaunchKernelGGL(k_set_target, dim3(1), dim3(1), 0, st, h->sc, it * it);
             hipLaunchKernelGGL(k_scale_to<float>, grid_for(nn), dim3(256), 0, st, (const double*)h->r64, h->r32,
                                h->x32, (const DevScalars*)h->sc, nn);
-            total += pcg<float>(h, h->r32, h->x32, h->z32, h->p32, h->q32, h->cfg.solver.max_iter, &err);
+            if (method == PIC_SOLVE_IR_UNET) {
+                total += fpcg(h, h->r32, h->x32, h->z32, h->p32, h->q32, h->cfg.solver.max_iter, &err);
+                // the correction found so far is kept; multigrid finishes the solve
+                if (h->h_sc->fallback) { method = PIC_SOLVE_IR_MG; h->unet_fallbacks++; }
+            } else {
+                total += pcg<float>(h, h->r32, h->x32, h->z32, h->p32, h->q32, h->cfg.solver.max_iter, &err,
+                                    method == PIC_SOLVE_IR_CG ? 1 : 0);
+            }
             hipLaunchKernelGGL(k_add_phi<float>, grid_for(nn), dim3(256), 0, st, phi, (const float*)h->x32,
                                (const int8_t*)h->node_kind, (const DevScalars*)h->sc, nn, 1);
         }
         if (err) break;
     }
     hipLaunchKernelGGL(k_set_dirichlet, grid_for(nn), dim3(256), 0, st, phi, (const int8_t*)h->node_kind, Up, nn);
+    if (harvested_r && !err && rel <= tol) {
+        unet::harvest_e(h->net, slot, phi, h->phi_old, h->node_kind, h->w, (double)h->img_free, h->part, st);
+        h->net.n_pairs++;
+    }
     h->solver_outer = outer;
     if (iters_out) *iters_out = total;
     if (relres_out) *relres_out = rel;

@@ -9,6 +9,7 @@
 
 #include "../../include/pic.h"
 #include "pic_device.h"
+#include "unet.h"
 
 namespace pic {
 
@@ -44,7 +45,8 @@ struct DevScalars {
     double one;              // constant 1.0: Dirichlet value of the Laplace problem
     double powered_prev;     // integer powered-electrode charge at the last circuit step
     double bb, rr, rz, rz_new, pq, alpha, beta, target, scale, relres, rr0;
-    int done, iters, nonfinite, pad;
+    double hscale;           // 1/||r0|| of a harvested solve
+    int done, iters, nonfinite, fallback;
 };
 
 struct Level {
@@ -119,6 +121,14 @@ struct pic_handle {
     int64_t solver_iters, solver_outer;
     double solver_relres;
     int sticky_err;
+    // learned preconditioner
+    bool unet_on;
+    pic::unet::Net net;
+    float* unet_stage;      // host-provided inputs, [B][H][W][3]
+    double* phi_old;
+    int harvest_every;
+    bool harvest_now;
+    int64_t unet_fallbacks, unet_apps, img_free;
     // phase timing
     bool timing;
     std::vector<hipEvent_t> ev_pool;

@@ -1,0 +1,612 @@
+// unet_kernels.hip -- kernels of the learned preconditioner: a 5-level
+// convolutional U-net on the r-z node image (rows z, columns r) that
+// approximates the inverse of the finite-volume operator of Eq. (1) on a
+// normalised residual.  Activations are NHWC bfloat16; 3x3 convolutions run
+// as implicit GEMMs on gfx950 BF16 matrix cores (v_mfma_f32_32x32x16_bf16)
+// with FP32 accumulation; master weights and the Adam state are FP32.
+#include <hip/hip_runtime.h>
+
+#include "unet.h"
+
+namespace pic {
+namespace unet {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ float bf2f(bf16 v) {
+    return __uint_as_float(((unsigned)v.x) << 16);
+}
+__device__ __forceinline__ float bf2f(__bf16 v) {
+    return __uint_as_float(((unsigned)__builtin_bit_cast(unsigned short, v)) << 16);
+}
+__device__ __forceinline__ bf16 f2bf(float f) {
+    // round to nearest even (finite inputs)
+    unsigned u = __float_as_uint(f);
+    u = u + 0x7FFFu + ((u >> 16) & 1u);
+    bf16 r;
+    r.x = (unsigned short)(u >> 16);
+    return r;
+}
+__device__ __forceinline__ __bf16 f2raw(float f) { return __builtin_bit_cast(__bf16, f2bf(f).x); }
+__device__ __forceinline__ __bf16 raw(bf16 v) { return __builtin_bit_cast(__bf16, v.x); }
+
+// ------------------------------------------------------------- 3x3 conv
+// Y[b][y][x][n] = act(bias[n] + sum_t sum_c Wt[t][n][c] * Xin[b][y+dy_t][x+dx_t][c])
+// with zero padding, Xin = X (optionally multiplied by the ReLU mask
+// M > 0 of the layer whose gradient X is).  Tile: 16x16 output pixels per
+// block iteration, 4 wavefronts x 4 rows; each wavefront computes two
+// 32-pixel x 32-channel MFMA tiles per 32 output channels.
+template <int CIN, int COUT, bool RELU, bool MASK>
+__global__ __launch_bounds__(256) void k_conv3x3(const bf16* __restrict__ X, const bf16* __restrict__ Wt,
+                                                 const float* __restrict__ bias, const bf16* __restrict__ M,
+                                                 bf16* __restrict__ Y, int B, int H, int W) {
+    constexpr int CP = CIN + 8;           // padded channel stride in LDS (bank spread)
+    constexpr int NT = COUT / 32;
+    __shared__ __attribute__((aligned(16))) bf16 xs[18 * 18 * CP];
+    __shared__ __attribute__((aligned(16))) bf16 ws[9 * COUT * CP];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // weights once per block
+    for (int e = tid; e < 9 * COUT * (CIN / 8); e += 256) {
+        const int c8 = e % (CIN / 8), tn = e / (CIN / 8);
+        *(bf16x8*)&ws[tn * CP + c8 * 8] = *(const bf16x8*)&Wt[(size_t)tn * CIN + c8 * 8];
+    }
+    const int tx = (W + 15) / 16, ty = (H + 15) / 16;
+    const long long ntile = (long long)tx * ty * B;
+    for (long long tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+        const int b = (int)(tile / (tx * ty));
+        const int rem = (int)(tile % (tx * ty));
+        const int y0 = (rem / tx) * 16, x0 = (rem % tx) * 16;
+        __syncthreads();
+        // input tile with halo, zero outside the image
+        for (int e = tid; e < 18 * 18 * (CIN / 8); e += 256) {
+            const int c8 = e % (CIN / 8), pix = e / (CIN / 8);
+            const int yy = y0 - 1 + pix / 18, xx = x0 - 1 + pix % 18;
+            bf16x8 v = {};
+            if (yy >= 0 && yy < H && xx >= 0 && xx < W) {
+                const size_t g = (((size_t)b * H + yy) * W + xx) * CIN + c8 * 8;
+                v = *(const bf16x8*)&X[g];
+                if (MASK) {
+                    const bf16x8 m = *(const bf16x8*)&M[g];
+                    for (int k = 0; k < 8; ++k)
+                        if (!(bf2f(m[k]) > 0.0f)) v[k] = f2raw(0.0f);
+                }
+            }
+            *(bf16x8*)&xs[pix * CP + c8 * 8] = v;
+        }
+        __syncthreads();
+        f32x16 acc[2][NT];
+        for (int s = 0; s < 2; ++s)
+            for (int nt = 0; nt < NT; ++nt) acc[s][nt] = {};
+        const int kh = (lane >> 5) * 8;      // this lane's 8 channels of a 16-wide k step
+        const int m = lane & 31;             // this lane's pixel row of the A tile
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int dy = t / 3, dx = t % 3;   // halo coordinates: +1 offsets folded in
+#pragma unroll
+            for (int c0 = 0; c0 < CIN; c0 += 16) {
+                bf16x8 bfr[NT];
+                for (int nt = 0; nt < NT; ++nt)
+                    bfr[nt] = *(const bf16x8*)&ws[(t * COUT + nt * 32 + m) * CP + c0 + kh];
+                for (int s = 0; s < 2; ++s) {
+                    const int py = wave * 4 + s * 2 + m / 16, px = m % 16;
+                    const bf16x8 afr = *(const bf16x8*)&xs[((py + dy) * 18 + (px + dx)) * CP + c0 + kh];
+                    for (int nt = 0; nt < NT; ++nt)
+                        acc[s][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afr, bfr[nt], acc[s][nt], 0, 0, 0);
+                }
+            }
+        }
+        // D layout: lane holds column n = lane % 32, rows 8(r/4) + 4(lane/32) + r%4
+        for (int s = 0; s < 2; ++s)
+            for (int nt = 0; nt < NT; ++nt) {
+                const int n = nt * 32 + (lane & 31);
+                const float bb = bias ? bias[n] : 0.0f;
+                for (int r = 0; r < 16; ++r) {
+                    const int pm = 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
+                    const int py = y0 + wave * 4 + s * 2 + pm / 16, px = x0 + pm % 16;
+                    if (py < H && px < W) {
+                        float v = acc[s][nt][r] + bb;
+                        if (RELU) v = fmaxf(v, 0.0f);
+                        Y[(((size_t)b * H + py) * W + px) * COUT + n] = f2bf(v);
+                    }
+                }
+            }
+    }
+}
+
+// ------------------------------------------------------- weight gradient
+// dW[t][n][c] = sum_p Dm[p][n] * Xpad[p + off_t][c] and db[n] = sum_p Dm[p][n],
+// Dm = D * (Yout > 0).  GEMM with M = 32 output channels, N = CIN input
+// channels, K = pixels; wavefront w owns taps w, w+4, w+8.  Each block
+// accumulates over its tiles and writes one partial (reduced later in a
+// fixed order).
+template <int CIN>
+__global__ __launch_bounds__(256) void k_wgrad(const bf16* __restrict__ X, const bf16* __restrict__ D,
+                                               const bf16* __restrict__ Yout, float* __restrict__ part, int B, int H,
+                                               int W) {
+    constexpr int NT = (CIN + 31) / 32;
+    constexpr int CT = NT * 32;            // channels padded to whole N tiles
+    __shared__ __attribute__((aligned(16))) bf16 dT[32 * (256 + 8)];      // [n][pixel]
+    __shared__ __attribute__((aligned(16))) bf16 xT[CT * (18 * 18 + 8)];  // [c][halo pixel]
+    __shared__ float dbs[32];
+    constexpr int DS = 256 + 8, XS = 18 * 18 + 8;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    f32x16 acc[3][NT];
+    for (int k = 0; k < 3; ++k)
+        for (int nt = 0; nt < NT; ++nt) acc[k][nt] = {};
+    float dbacc = 0.0f;
+    const int tx = (W + 15) / 16, ty = (H + 15) / 16;
+    const long long ntile = (long long)tx * ty * B;
+    for (long long tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+        const int b = (int)(tile / (tx * ty));
+        const int rem = (int)(tile % (tx * ty));
+        const int y0 = (rem / tx) * 16, x0 = (rem % tx) * 16;
+        __syncthreads();
+        {   // masked output gradient, transposed: thread = pixel
+            const int py = y0 + tid / 16, px = x0 + tid % 16;
+            const bool in = py < H && px < W;
+            const size_t g = (((size_t)b * H + py) * W + px) * 32;
+            for (int n = 0; n < 32; ++n) {
+                float v = 0.0f;
+                if (in && bf2f(Yout[g + n]) > 0.0f) v = bf2f(D[g + n]);
+                dT[n * DS + tid] = f2bf(v);
+            }
+        }
+        for (int e = tid; e < 18 * 18; e += 256) {
+            const int yy = y0 - 1 + e / 18, xx = x0 - 1 + e % 18;
+            const bool in = yy >= 0 && yy < H && xx >= 0 && xx < W;
+            const size_t g = (((size_t)b * H + yy) * W + xx) * CIN;
+            for (int c = 0; c < CT; ++c) {
+                bf16 v;
+                v.x = 0;
+                if (in && c < CIN) v = X[g + c];
+                xT[c * XS + e] = v;
+            }
+        }
+        __syncthreads();
+        if (tid < 32) {
+            float s = 0.0f;
+            for (int p = 0; p < 256; ++p) s += bf2f(dT[tid * DS + p]);
+            dbacc += s;
+        }
+        const int kh = (lane >> 5) * 8, m = lane & 31;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int t = wave + 4 * k;
+            if (t <= 8) {
+            const int dy = t / 3, dx = t % 3;
+            for (int k0 = 0; k0 < 256; k0 += 16) {
+                // A[m = n_out][k = pixel], 8 consecutive pixels (same tile row)
+                const bf16x8 afr = *(const bf16x8*)&dT[m * DS + k0 + kh];
+                const int p0 = k0 + kh;                  // first of 8 pixels, all in row p0 / 16
+                const int hy = p0 / 16 + dy, hx = p0 % 16 + dx;
+                for (int nt = 0; nt < NT; ++nt) {
+                    const int c = nt * 32 + m;
+                    bf16x8 bfr;
+                    const bf16* src = &xT[c * XS + hy * 18 + hx];
+                    for (int q = 0; q < 8; ++q) bfr[q] = raw(src[q]);
+                    acc[k][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afr, bfr, acc[k][nt], 0, 0, 0);
+                }
+            }
+            }
+        }
+    }
+    // partial layout per block: [9][32][CIN] weights then [32] bias
+    float* out = part + (size_t)blockIdx.x * (9 * 32 * CIN + 32);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int t = wave + 4 * k;
+        if (t > 8) continue;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+            for (int r = 0; r < 16; ++r) {
+                const int n = 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
+                const int c = nt * 32 + (lane & 31);
+                if (c < CIN) out[(t * 32 + n) * CIN + c] = acc[k][nt][r];
+            }
+    }
+    if (tid < 32) out[9 * 32 * CIN + tid] = dbacc;
+}
+
+// sum of per-block partials, fixed order
+__global__ __launch_bounds__(256) void k_sum_parts(const float* part, int nblk, int len, float* out) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < len; i += gridDim.x * blockDim.x) {
+        float s = 0.0f;
+        for (int b = 0; b < nblk; ++b) s += part[(size_t)b * len + i];
+        out[i] = s;
+    }
+}
+
+// ---------------------------------------------- pooling, upsampling, concat
+__global__ __launch_bounds__(256) void k_pool(const bf16* X, bf16* Y, int B, int H, int W, int C) {
+    const int Ho = H / 2, Wo = W / 2;
+    const size_t n = (size_t)B * Ho * Wo * C;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        const int c = e % C;
+        const size_t q = e / C;
+        const int xo = q % Wo, yo = (q / Wo) % Ho, b = q / ((size_t)Wo * Ho);
+        const size_t g = (((size_t)b * H + 2 * yo) * W + 2 * xo) * C + c;
+        const float s = bf2f(X[g]) + bf2f(X[g + C]) + bf2f(X[g + (size_t)W * C]) + bf2f(X[g + (size_t)W * C + C]);
+        Y[e] = f2bf(0.25f * s);
+    }
+}
+
+// dX = pool^T(dY) + dS (the skip-path gradient), fine resolution
+__global__ __launch_bounds__(256) void k_pool_bwd_add(const bf16* dY, const bf16* dS, bf16* dX, int B, int H, int W,
+                                                      int C) {
+    const size_t n = (size_t)B * H * W * C;
+    const int Wo = W / 2, Ho = H / 2;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        const int c = e % C;
+        const size_t q = e / C;
+        const int x = q % W, y = (q / W) % H, b = q / ((size_t)W * H);
+        const float v = 0.25f * bf2f(dY[(((size_t)b * Ho + y / 2) * Wo + x / 2) * C + c]) + bf2f(dS[e]);
+        dX[e] = f2bf(v);
+    }
+}
+
+// Y = [up2(Xc), S]: 2C channels at the fine resolution
+__global__ __launch_bounds__(256) void k_up_concat(const bf16* Xc, const bf16* S, bf16* Y, int B, int H, int W, int C) {
+    const size_t n = (size_t)B * H * W * 2 * C;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        const int c = e % (2 * C);
+        const size_t q = e / (2 * C);
+        const int x = q % W, y = (q / W) % H, b = q / ((size_t)W * H);
+        Y[e] = (c < C) ? Xc[(((size_t)b * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c] : S[q * C + (c - C)];
+    }
+}
+
+// from the 2C-channel concat gradient: dXc = up^T(first C), dS = last C
+__global__ __launch_bounds__(256) void k_up_concat_bwd(const bf16* dY, bf16* dXc, bf16* dS, int B, int H, int W,
+                                                       int C) {
+    const int Ho = H / 2, Wo = W / 2;
+    const size_t nc = (size_t)B * Ho * Wo * C;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < nc; e += (size_t)gridDim.x * blockDim.x) {
+        const int c = e % C;
+        const size_t q = e / C;
+        const int xo = q % Wo, yo = (q / Wo) % Ho, b = q / ((size_t)Wo * Ho);
+        float s = 0.0f;
+        for (int d = 0; d < 4; ++d) {
+            const size_t p = ((size_t)b * H + 2 * yo + d / 2) * W + 2 * xo + d % 2;
+            s += bf2f(dY[p * 2 * C + c]);
+        }
+        dXc[e] = f2bf(s);
+    }
+    const size_t nf = (size_t)B * H * W * C;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < nf; e += (size_t)gridDim.x * blockDim.x) {
+        const size_t p = e / C;
+        const int c = e % C;
+        dS[e] = dY[p * 2 * C + C + c];
+    }
+}
+
+// ------------------------------------------------------------ output layer
+// out[p] = scale_b * (w . last[p] + b0) on unknown nodes (0 elsewhere)
+__global__ __launch_bounds__(256) void k_out(const bf16* last, const float* w, const float* b0, float* out, int B,
+                                             int HW, int C) {
+    const size_t n = (size_t)B * HW;
+    for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < n; p += (size_t)gridDim.x * blockDim.x) {
+        float s = b0[0];
+        for (int c = 0; c < C; ++c) s += w[c] * bf2f(last[p * C + c]);
+        out[p] = s;
+    }
+}
+
+// loss = mean over masked pixels of (out - target)^2; dz; dlast = w dz;
+// per-block partials of the loss, dw and db
+__global__ __launch_bounds__(256) void k_loss_out_bwd(const float* out, const float* target, const float* mask,
+                                                      const bf16* last, const float* w, bf16* dlast, float* part,
+                                                      int B, int HW, float inv_n) {
+    constexpr int C = kC;
+    __shared__ float sh[256];
+    float acc[C + 2];
+#pragma unroll
+    for (int k = 0; k < C + 2; ++k) acc[k] = 0.0f;
+    const size_t n = (size_t)B * HW;
+    for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < n; p += (size_t)gridDim.x * blockDim.x) {
+        const float mk = mask[p];
+        const float d = (out[p] - target[p]) * mk;
+        const float dz = 2.0f * d * inv_n;
+        acc[0] += d * d * inv_n;
+        acc[1] += dz;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const float x = bf2f(last[p * C + c]);
+            acc[2 + c] += x * dz;
+            dlast[p * C + c] = f2bf(w[c] * dz);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < C + 2; ++k) {
+        sh[threadIdx.x] = acc[k];
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) part[(size_t)blockIdx.x * (C + 2) + k] = sh[0];
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ Adam
+// master FP32 parameters p, gradients g, moments m, v; t is the step count
+__global__ __launch_bounds__(256) void k_adam(float* p, const float* g, float* m, float* v, int n, float lr, float b1,
+                                              float b2, float eps, float c1, float c2) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.0f - b1) * gi;
+        const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    }
+}
+
+// bfloat16 copies of one conv layer's weights: forward layout [t][co][cin_pad]
+// and, for the data gradient, [t'][ci][co] = W[8 - t'][co][ci]
+__global__ __launch_bounds__(256) void k_pack_conv(const float* w, int cin, int cin_pad, int cout, bf16* fwd,
+                                                   bf16* bwd) {
+    const int n = 9 * cout * cin_pad;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+        const int ci = e % cin_pad, co = (e / cin_pad) % cout, t = e / (cin_pad * cout);
+        fwd[e] = f2bf(ci < cin ? w[(t * cout + co) * cin + ci] : 0.0f);
+    }
+    if (!bwd) return;
+    const int nb = 9 * cin * cout;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nb; e += gridDim.x * blockDim.x) {
+        const int co = e % cout, ci = (e / cout) % cin, t = e / (cout * cin);
+        bwd[e] = f2bf(w[((8 - t) * cout + co) * cin + ci]);
+    }
+}
+
+// network input from a residual on the node grid (FP64), chi and node kinds:
+// channels [r * scale, chi / (1 + chi), 1 on unknown nodes], 16 padded
+__global__ __launch_bounds__(256) void k_input_from_grid(const double* r, double scale, const double* chi,
+                                                         const int8_t* nk, bf16* X, int H, int W, int w) {
+    const size_t n = (size_t)H * W;
+    for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < n; p += (size_t)gridDim.x * blockDim.x) {
+        const int y = p / W, x = p % W;
+        const int node = y * w + x;
+        const bool free = nk[node] < 0;
+        bf16x8 v0 = {}, v1 = {};
+        v0[0] = f2raw(free ? (float)(r[node] * scale) : 0.0f);
+        const float c = (float)chi[node];
+        v0[1] = f2raw(c / (1.0f + c));
+        v0[2] = f2raw(free ? 1.0f : 0.0f);
+        *(bf16x8*)&X[p * 16] = v0;
+        *(bf16x8*)&X[p * 16 + 8] = v1;
+    }
+}
+
+// network input from host-provided FP32 channels [H][W][3]
+__global__ __launch_bounds__(256) void k_input_from_f32(const float* in3, bf16* X, size_t npix) {
+    for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < npix; p += (size_t)gridDim.x * blockDim.x) {
+        bf16x8 v0 = {}, v1 = {};
+        v0[0] = f2raw(in3[p * 3]);
+        v0[1] = f2raw(in3[p * 3 + 1]);
+        v0[2] = f2raw(in3[p * 3 + 2]);
+        *(bf16x8*)&X[p * 16] = v0;
+        *(bf16x8*)&X[p * 16 + 8] = v1;
+    }
+}
+
+// training batch from harvested pairs: inputs [r, chi', mask], target e
+struct BatchIdx {
+    int idx[kMaxBatch];
+};
+__global__ __launch_bounds__(256) void k_gather_batch(BatchIdx bi, int B, const float* hr, const float* he,
+                                                      const float* hchi, const float* hmask, bf16* X, float* target,
+                                                      float* mask, size_t img) {
+    const size_t n = (size_t)B * img;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        const int b = (int)(e / img);
+        const size_t p = e % img;
+        const size_t src = (size_t)bi.idx[b] * img + p;
+        bf16x8 v0 = {}, v1 = {};
+        v0[0] = f2raw(hr[src]);
+        v0[1] = f2raw(hchi[src]);
+        v0[2] = f2raw(hmask[p]);
+        *(bf16x8*)&X[e * 16] = v0;
+        *(bf16x8*)&X[e * 16 + 8] = v1;
+        target[e] = he[src];
+        mask[e] = hmask[p];
+    }
+}
+
+// preconditioner input from an FP32 inner residual on the node grid,
+// scaled to unit RMS over the unknown nodes: r sqrt(n_free / (r.r))
+__global__ __launch_bounds__(256) void k_input_from_r32(const float* r, const double* rr, const double* chi,
+                                                        const int8_t* nk, bf16* X, int H, int W, int w,
+                                                        double n_free) {
+    const float sc = (float)sqrt(n_free / *rr);
+    const size_t n = (size_t)H * W;
+    for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < n; p += (size_t)gridDim.x * blockDim.x) {
+        const int node = (int)(p / W) * w + (int)(p % W);
+        const bool free = nk[node] < 0;
+        bf16x8 v0 = {}, v1 = {};
+        v0[0] = f2raw(free ? r[node] * sc : 0.0f);
+        const float c = (float)chi[node];
+        v0[1] = f2raw(c / (1.0f + c));
+        v0[2] = f2raw(free ? 1.0f : 0.0f);
+        *(bf16x8*)&X[p * 16] = v0;
+        *(bf16x8*)&X[p * 16 + 8] = v1;
+    }
+}
+
+// z = ||r|| * out on unknown nodes of the image, 0 elsewhere (flexible CG
+// is blind to a scalar factor on z; this one keeps z on the scale of r)
+__global__ __launch_bounds__(256) void k_out_to_z(const float* out, const double* rr, const int8_t* nk, float* z, int H,
+                                                  int W, int w, int nn) {
+    const float sc = (float)sqrt(*rr);
+    for (int node = blockIdx.x * blockDim.x + threadIdx.x; node < nn; node += gridDim.x * blockDim.x) {
+        const int i = node % w, j = node / w;
+        float v = 0.0f;
+        if (i < W && j < H && nk[node] < 0) v = sc * out[(size_t)j * W + i];
+        z[node] = v;
+    }
+}
+
+// harvest: the first residual of a solve at unit RMS (scale = 1/||r0||),
+// chi / (1 + chi) and the mask, into a pair slot
+__global__ __launch_bounds__(256) void k_harvest_r(const double* r64, const double* scale, const double* chi,
+                                                   const int8_t* nk, float* hr, float* hchi, float* hmask, int H,
+                                                   int W, int w, double root_n) {
+    const size_t n = (size_t)H * W;
+    const double sc = *scale * root_n;
+    for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < n; p += (size_t)gridDim.x * blockDim.x) {
+        const int node = (int)(p / W) * w + (int)(p % W);
+        const bool free = nk[node] < 0;
+        hr[p] = free ? (float)(r64[node] * sc) : 0.0f;
+        const double c = chi[node];
+        hchi[p] = (float)(c / (1.0 + c));
+        hmask[p] = free ? 1.0f : 0.0f;
+    }
+}
+
+// harvest: the error the solve removed, delta = phi - phi_old, first raw
+// with per-block partial sums of delta^2 ...
+__global__ __launch_bounds__(256) void k_harvest_e(const double* phi, const double* phi_old, const int8_t* nk,
+                                                   float* he, double* part, int H, int W, int w) {
+    __shared__ double sh[256];
+    const size_t n = (size_t)H * W;
+    double acc = 0.0;
+    for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < n; p += (size_t)gridDim.x * blockDim.x) {
+        const int node = (int)(p / W) * w + (int)(p % W);
+        const double d = nk[node] < 0 ? phi[node] - phi_old[node] : 0.0;
+        he[p] = (float)d;
+        acc += d * d;
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// ... then scaled to unit RMS over the unknown nodes (every block sums the
+// partials in the same order)
+__global__ __launch_bounds__(256) void k_norm_pair(float* he, const double* part, int nparts, size_t n, double n_free) {
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nparts; b += blockDim.x) acc += part[b];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    const double ss = sh[0];
+    const float sc = ss > 0.0 ? (float)sqrt(n_free / ss) : 0.0f;
+    for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < n; p += (size_t)gridDim.x * blockDim.x)
+        he[p] *= sc;
+}
+
+// --------------------------------------------------------------- launchers
+static dim3 tiles_grid(int B, int H, int W) {
+    const long long nt = (long long)((W + 15) / 16) * ((H + 15) / 16) * B;
+    return dim3((unsigned)std::min<long long>(nt, 2048));
+}
+
+void conv_fwd(int cin, const bf16* X, const bf16* Wt, const float* bias, bf16* Y, int B, int H, int W,
+              hipStream_t s) {
+    const dim3 g = tiles_grid(B, H, W);
+    if (cin == 16) hipLaunchKernelGGL((k_conv3x3<16, 32, true, false>), g, dim3(256), 0, s, X, Wt, bias, nullptr, Y, B, H, W);
+    else if (cin == 32) hipLaunchKernelGGL((k_conv3x3<32, 32, true, false>), g, dim3(256), 0, s, X, Wt, bias, nullptr, Y, B, H, W);
+    else hipLaunchKernelGGL((k_conv3x3<64, 32, true, false>), g, dim3(256), 0, s, X, Wt, bias, nullptr, Y, B, H, W);
+}
+
+void conv_dgrad(int cin_of_layer, const bf16* D, const bf16* Yout, const bf16* Wb, bf16* DX, int B, int H, int W,
+                hipStream_t s) {
+    const dim3 g = tiles_grid(B, H, W);
+    if (cin_of_layer == 32)
+        hipLaunchKernelGGL((k_conv3x3<32, 32, false, true>), g, dim3(256), 0, s, D, Wb, (const float*)nullptr, Yout, DX, B, H, W);
+    else
+        hipLaunchKernelGGL((k_conv3x3<32, 64, false, true>), g, dim3(256), 0, s, D, Wb, (const float*)nullptr, Yout, DX, B, H, W);
+}
+
+int conv_wgrad(int cin, const bf16* X, const bf16* D, const bf16* Yout, float* part, float* gw, int B, int H, int W,
+               hipStream_t s) {
+    const dim3 g = tiles_grid(B, H, W);
+    const int nb = (int)std::min<unsigned>(g.x, kWgradBlocks);
+    const int len = 9 * 32 * cin + 32;
+    if (cin == 16) hipLaunchKernelGGL((k_wgrad<16>), dim3(nb), dim3(256), 0, s, X, D, Yout, part, B, H, W);
+    else if (cin == 32) hipLaunchKernelGGL((k_wgrad<32>), dim3(nb), dim3(256), 0, s, X, D, Yout, part, B, H, W);
+    else hipLaunchKernelGGL((k_wgrad<64>), dim3(nb), dim3(256), 0, s, X, D, Yout, part, B, H, W);
+    hipLaunchKernelGGL(k_sum_parts, dim3((len + 255) / 256), dim3(256), 0, s, (const float*)part, nb, len, gw);
+    return nb;
+}
+
+static dim3 ew_grid(size_t n) { return dim3((unsigned)std::min<size_t>((n + 255) / 256, 4096)); }
+
+void pool(const bf16* X, bf16* Y, int B, int H, int W, int C, hipStream_t s) {
+    hipLaunchKernelGGL(k_pool, ew_grid((size_t)B * H * W * C / 4), dim3(256), 0, s, X, Y, B, H, W, C);
+}
+void pool_bwd_add(const bf16* dY, const bf16* dS, bf16* dX, int B, int H, int W, int C, hipStream_t s) {
+    hipLaunchKernelGGL(k_pool_bwd_add, ew_grid((size_t)B * H * W * C), dim3(256), 0, s, dY, dS, dX, B, H, W, C);
+}
+void up_concat(const bf16* Xc, const bf16* S, bf16* Y, int B, int H, int W, int C, hipStream_t s) {
+    hipLaunchKernelGGL(k_up_concat, ew_grid((size_t)B * H * W * 2 * C), dim3(256), 0, s, Xc, S, Y, B, H, W, C);
+}
+void up_concat_bwd(const bf16* dY, bf16* dXc, bf16* dS, int B, int H, int W, int C, hipStream_t s) {
+    hipLaunchKernelGGL(k_up_concat_bwd, ew_grid((size_t)B * H * W * C), dim3(256), 0, s, dY, dXc, dS, B, H, W, C);
+}
+void out_fwd(const bf16* last, const float* w, const float* b0, float* out, int B, int HW, int C, hipStream_t s) {
+    hipLaunchKernelGGL(k_out, ew_grid((size_t)B * HW), dim3(256), 0, s, last, w, b0, out, B, HW, C);
+}
+void loss_out_bwd(const float* out, const float* target, const float* mask, const bf16* last, const float* w,
+                  bf16* dlast, float* part, float* sums, int B, int HW, int C, float inv_n, hipStream_t s) {
+    hipLaunchKernelGGL(k_loss_out_bwd, dim3(kLossBlocks), dim3(256), 0, s, out, target, mask, last, w, dlast, part, B,
+                       HW, inv_n);
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, (const float*)part, kLossBlocks, C + 2, sums);
+}
+void adam(float* p, const float* g, float* m, float* v, int n, float lr, int t, hipStream_t s) {
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.0f - powf(b1, (float)t), c2 = 1.0f - powf(b2, (float)t);
+    hipLaunchKernelGGL(k_adam, ew_grid(n), dim3(256), 0, s, p, g, m, v, n, lr, b1, b2, 1e-8f, c1, c2);
+}
+void pack_conv(const float* w, int cin, int cin_pad, int cout, bf16* fwd, bf16* bwd, hipStream_t s) {
+    hipLaunchKernelGGL(k_pack_conv, dim3(64), dim3(256), 0, s, w, cin, cin_pad, cout, fwd, bwd);
+}
+void input_from_grid(const double* r, double scale, const double* chi, const int8_t* nk, bf16* X, int H, int W,
+                     int w, hipStream_t s) {
+    hipLaunchKernelGGL(k_input_from_grid, ew_grid((size_t)H * W), dim3(256), 0, s, r, scale, chi, nk, X, H, W, w);
+}
+void input_from_f32(const float* in3, bf16* X, size_t npix, hipStream_t s) {
+    hipLaunchKernelGGL(k_input_from_f32, ew_grid(npix), dim3(256), 0, s, in3, X, npix);
+}
+void gather_batch(const Net& n, const int* idx, int B, hipStream_t s) {
+    BatchIdx bi;
+    for (int b = 0; b < kMaxBatch; ++b) bi.idx[b] = b < B ? idx[b] : 0;
+    const size_t img = (size_t)n.H * n.W;
+    hipLaunchKernelGGL(k_gather_batch, ew_grid(B * img), dim3(256), 0, s, bi, B, (const float*)n.h_r,
+                       (const float*)n.h_e, (const float*)n.h_chi, (const float*)n.h_mask, n.x0, n.target, n.mask,
+                       img);
+}
+void input_from_r32(const Net& n, const float* r, const double* rr, const double* chi, const int8_t* nk, int w,
+                    double n_free, hipStream_t s) {
+    hipLaunchKernelGGL(k_input_from_r32, ew_grid((size_t)n.H * n.W), dim3(256), 0, s, r, rr, chi, nk, n.x0, n.H, n.W,
+                       w, n_free);
+}
+void out_to_z(const Net& n, const double* rr, const int8_t* nk, float* z, int w, int nn, hipStream_t s) {
+    hipLaunchKernelGGL(k_out_to_z, ew_grid(nn), dim3(256), 0, s, (const float*)n.out, rr, nk, z, n.H, n.W, w, nn);
+}
+void harvest_r(const Net& n, int slot, const double* r64, const double* scale, const double* chi, const int8_t* nk,
+               int w, double n_free, hipStream_t s) {
+    const size_t img = (size_t)n.H * n.W;
+    hipLaunchKernelGGL(k_harvest_r, ew_grid(img), dim3(256), 0, s, r64, scale, chi, nk, n.h_r + slot * img,
+                       n.h_chi + slot * img, n.h_mask, n.H, n.W, w, sqrt(n_free));
+}
+void harvest_e(const Net& n, int slot, const double* phi, const double* phi_old, const int8_t* nk, int w,
+               double n_free, double* part, hipStream_t s) {
+    const size_t img = (size_t)n.H * n.W;
+    const dim3 g((unsigned)std::min<size_t>((img + 255) / 256, kHarvestBlocks));
+    hipLaunchKernelGGL(k_harvest_e, g, dim3(256), 0, s, phi, phi_old, nk, n.h_e + slot * img, part, n.H, n.W, w);
+    hipLaunchKernelGGL(k_norm_pair, g, dim3(256), 0, s, n.h_e + slot * img, (const double*)part, (int)g.x, img,
+                       n_free);
+}
+
+}  // namespace unet
+}  // namespace pic

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libpic.so")
 ABI_VERSION = 1
 MAX_REGIONS = 32
 FIELDS = ("r", "z", "vr", "vt", "vz", "ar", "at", "az", "w")
+SOLVE_MGPCG_FP64, SOLVE_IR_MG, SOLVE_IR_UNET, SOLVE_IR_CG = 0, 1, 2, 3
 GRIDS = dict(DEP_E=0, DEP_I=1, PHI=2, ER=3, EZ=4, CHI=5, WALLQ=6, PHI_L=10, Q=11, AR=12, AZ=13)
 ERRORS = {0: "ok", -1: "PIC_E_CONFIG", -2: "PIC_E_CAPACITY", -3: "PIC_E_SOLVER", -4: "PIC_E_HIP",
           -5: "PIC_E_NONFINITE", -6: "PIC_E_STATE", -7: "PIC_E_ARG", -8: "PIC_E_NODEVICE"}
@@ -55,7 +56,8 @@ class Run(C.Structure):
 
 
 class Solver(C.Structure):
-    _fields_ = [("method", C.c_int32), ("tol", C.c_double), ("max_iter", C.c_int32), ("inner_tol", C.c_double)]
+    _fields_ = [("method", C.c_int32), ("tol", C.c_double), ("max_iter", C.c_int32), ("inner_tol", C.c_double),
+                ("unet_batch", C.c_int32), ("unet_pairs", C.c_int32)]
 
 
 class Config(C.Structure):
@@ -74,7 +76,8 @@ class Diag(C.Structure):
         ("harm_I_re", C.c_double * 6), ("harm_I_im", C.c_double * 6),
         ("ms_particles", C.c_double * 2), ("ms_births", C.c_double), ("ms_sort", C.c_double),
         ("ms_field", C.c_double), ("ms_refresh", C.c_double),
-        ("timed_steps", C.c_int64), ("deposit_fallback", C.c_int64), ("error", C.c_int32)]
+        ("timed_steps", C.c_int64), ("deposit_fallback", C.c_int64), ("error", C.c_int32),
+        ("unet_pairs", C.c_int64), ("unet_fallbacks", C.c_int64), ("unet_applications", C.c_int64)]
 
 
 class DiagBuffers(C.Structure):
@@ -109,6 +112,15 @@ def lib():
         L.pic_solve_once.argtypes = [P, P, P, C.c_double, C.c_double, P, C.POINTER(C.c_int32),
                                      C.POINTER(C.c_double)]
         L.pic_set_state.argtypes = [P, P]
+        L.pic_set_solver.argtypes = [P, C.POINTER(Solver)]
+        L.pic_unet_num_params.argtypes = [P, C.POINTER(C.c_int64)]
+        L.pic_unet_set_params.argtypes = [P, P, C.c_int64]
+        L.pic_unet_get_params.argtypes = [P, P, C.c_int64]
+        L.pic_unet_forward.argtypes = [P, P, C.c_int32, P]
+        L.pic_unet_grads.argtypes = [P, P, P, P, C.c_int32, P, C.POINTER(C.c_double)]
+        L.pic_unet_harvest.argtypes = [P, C.c_int32]
+        L.pic_unet_get_pair.argtypes = [P, C.c_int32, P, P, P, P]
+        L.pic_unet_train.argtypes = [P, C.c_int32, C.c_int32, C.c_double, C.c_uint64, P]
         _lib = L
     return _lib
 
@@ -122,7 +134,7 @@ def _check(rc, where):
         raise PicError(rc, where)
 
 
-def make_config(w, load=True, timing=False, method=None, inner_tol=1e-4):
+def make_config(w, load=True, timing=False, method=None, inner_tol=1e-4, unet_batch=0, unet_pairs=0):
     """Marshal a workload dict (pic_inputs.workloads) into pic_config."""
     g, c, gas, run, sol = w["geometry"], w["circuit"], w["gas"], w["run"], w["solver"]
     cfg = Config()
@@ -148,6 +160,8 @@ def make_config(w, load=True, timing=False, method=None, inner_tol=1e-4):
     cfg.solver.method = sol["method"] if method is None else method
     cfg.solver.tol, cfg.solver.max_iter = sol["tol"], sol["max_iter"]
     cfg.solver.inner_tol = inner_tol
+    cfg.solver.unet_batch = unet_batch
+    cfg.solver.unet_pairs = unet_pairs
     return cfg
 
 
@@ -160,12 +174,13 @@ def workspace_bytes(cfg):
 class Pic:
     """One simulation on the current HIP device and stream."""
 
-    def __init__(self, w, load=True, timing=False, method=None, inner_tol=1e-4, device="cuda:0"):
+    def __init__(self, w, load=True, timing=False, method=None, inner_tol=1e-4, device="cuda:0", unet_batch=0,
+                 unet_pairs=0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the HIP path has no CPU fallback")
         self.w = w
-        self.cfg = make_config(w, load, timing, method, inner_tol)
+        self.cfg = make_config(w, load, timing, method, inner_tol, unet_batch, unet_pairs)
         L = lib()
         nbytes = workspace_bytes(self.cfg)
         self.device = torch.device(device)
@@ -257,3 +272,62 @@ class Pic:
     def set_state(self, t, Q_E, U_E, circ, C_eq):
         st = np.array([t, Q_E, U_E] + list(circ) + [C_eq], dtype=np.float64)
         _check(lib().pic_set_state(self.h, _ptr(st)), "pic_set_state")
+
+    def set_solver(self, method=None, tol=None, max_iter=None, inner_tol=None):
+        s = Solver()
+        C.pointer(s)[0] = self.cfg.solver
+        if method is not None:
+            s.method = method
+        if tol is not None:
+            s.tol = tol
+        if max_iter is not None:
+            s.max_iter = max_iter
+        if inner_tol is not None:
+            s.inner_tol = inner_tol
+        _check(lib().pic_set_solver(self.h, C.byref(s)), "pic_set_solver")
+        self.cfg.solver = s
+
+    # ---- learned preconditioner (image: nz rows by nr columns)
+    def unet_num_params(self):
+        n = C.c_int64()
+        _check(lib().pic_unet_num_params(self.h, C.byref(n)), "pic_unet_num_params")
+        return n.value
+
+    def unet_set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        _check(lib().pic_unet_set_params(self.h, _ptr(p), p.size), "pic_unet_set_params")
+
+    def unet_params(self):
+        p = np.zeros(self.unet_num_params(), dtype=np.float32)
+        _check(lib().pic_unet_get_params(self.h, _ptr(p), p.size), "pic_unet_get_params")
+        return p
+
+    def unet_forward(self, in3):
+        in3 = np.ascontiguousarray(in3, dtype=np.float32)
+        B = in3.shape[0]
+        out = np.zeros((B, self.nz, self.nr), dtype=np.float32)
+        _check(lib().pic_unet_forward(self.h, _ptr(in3), B, _ptr(out)), "pic_unet_forward")
+        return out
+
+    def unet_grads(self, in3, target, mask):
+        in3 = np.ascontiguousarray(in3, dtype=np.float32)
+        target = np.ascontiguousarray(target, dtype=np.float32)
+        mask = np.ascontiguousarray(mask, dtype=np.float32)
+        g = np.zeros(self.unet_num_params(), dtype=np.float32)
+        loss = C.c_double()
+        _check(lib().pic_unet_grads(self.h, _ptr(in3), _ptr(target), _ptr(mask), in3.shape[0], _ptr(g),
+                                    C.byref(loss)), "pic_unet_grads")
+        return g, loss.value
+
+    def unet_harvest(self, every):
+        _check(lib().pic_unet_harvest(self.h, every), "pic_unet_harvest")
+
+    def unet_pair(self, slot):
+        a = [np.zeros((self.nz, self.nr), dtype=np.float32) for _ in range(4)]
+        _check(lib().pic_unet_get_pair(self.h, slot, *[_ptr(x) for x in a]), "pic_unet_get_pair")
+        return dict(zip(("r", "e", "chi", "mask"), a))
+
+    def unet_train(self, steps, batch, lr, seed=1):
+        curve = np.zeros(max(steps, 1))
+        _check(lib().pic_unet_train(self.h, steps, batch, lr, seed, _ptr(curve)), "pic_unet_train")
+        return curve[:steps]

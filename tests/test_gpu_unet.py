@@ -1,0 +1,231 @@
+"""GPU parity of the learned preconditioner (U-net) against the FP64 oracle in
+oracle/unet.py, through the C ABI, and its use inside flexible CG.
+
+The kernels store every activation (and every data gradient) in bfloat16 and
+accumulate in FP32.  The oracle can round its stored values the same way,
+but it accumulates in FP64, so near-ties round differently now and then, and
+each such one-ulp difference (2^-8 relative) feeds the next layers' rounding:
+over 18 layers the two roundings decorrelate to the size of the bfloat16
+storage effect itself.  The bar is therefore relative to that effect, which
+the oracle measures on the same input: the kernel's distance from the
+rounded oracle, and from the unrounded FP64 network, must stay within twice
+the rounded oracle's own distance from the unrounded network (plus 1e-3 for
+tensors the rounding barely touches).  A wrong tap, channel, transposition
+or missing term gives errors of order one.
+"""
+import numpy as np
+import pytest
+
+from oracle import unet as U
+from pic_inputs import workload
+from pic_inputs.workloads import SOLVE_IR_MG
+
+pytestmark = pytest.mark.gpu
+
+
+def _pic(w, **kw):
+    from paper_2310_04957_amd.pic import Pic
+    print(f"[gpu] init {w['geometry']['nr']}x{w['geometry']['nz']} {kw}", flush=True)
+    return Pic(w, **kw)
+
+
+def _gec(nr, nz, n=0, **run):
+    r = dict(n_e=n, n_i=n, cap_e=max(4 * n, 1), cap_i=max(4 * n, 1))
+    r.update(run)
+    w = workload("gec128x256", run=r)
+    w["geometry"]["nr"], w["geometry"]["nz"] = nr, nz
+    return w
+
+
+def _params(seed):
+    p = U.init_params(seed=seed)
+    rng = np.random.default_rng(seed + 100)
+    for k in p:
+        if k.endswith(".b"):
+            p[k] = rng.normal(0, 0.05, p[k].shape)
+    return U.flatten(p).astype(np.float32)
+
+
+def _as_gpu_sees(v):
+    """The parameters as the kernels use them: 3x3 weights in bfloat16,
+    biases and the 1x1 output layer in FP32."""
+    p = U.unflatten(v.astype(np.float64))
+    for k in p:
+        if k.endswith(".w") and not k.startswith("out"):
+            p[k] = U.bf16(p[k])
+    return p
+
+
+def _inputs(B, H, W, seed):
+    rng = np.random.default_rng(seed)
+    x = np.zeros((B, H, W, 3), np.float32)
+    x[..., 0] = rng.normal(size=(B, H, W))
+    x[..., 1] = rng.random((B, H, W))
+    x[..., 2] = (rng.random((B, H, W)) > 0.2).astype(np.float32)
+    x[..., 0] *= x[..., 2]
+    return x
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("shape", [(32, 64, 2), (128, 256, 1)])
+def test_forward_matches_oracle(shape):
+    nr, nz, B = shape        # image: nz rows by nr columns; 64x32 ends at 4x2 (ragged tiles)
+    g = _pic(_gec(nr, nz), load=False, method=SOLVE_IR_MG, unet_batch=B, unet_pairs=1)
+    v = _params(11)
+    assert g.unet_num_params() == v.size
+    g.unet_set_params(v)
+    assert np.array_equal(g.unet_params(), v)
+    x = _inputs(B, nz, nr, 12)
+    out = g.unet_forward(x)
+    p = _as_gpu_sees(v)
+    for b in range(B):
+        ref, _ = U.forward(p, U.bf16(x[b]), round_bf16=True)
+        exact, _ = U.forward(p, U.bf16(x[b]))
+        storage = _rel(ref, exact)
+        err, err_exact = _rel(out[b], ref), _rel(out[b], exact)
+        print(f"[gpu] forward {nz}x{nr} image {b}: rel L2 vs rounded oracle {err:.2e}, vs FP64 {err_exact:.2e}, "
+              f"bf16 storage effect {storage:.2e}", flush=True)
+        assert storage < 2e-2
+        assert err <= 2 * storage + 1e-3
+        assert err_exact <= 2 * storage + 1e-3
+    g.close()
+
+
+def test_gradients_match_oracle():
+    nr, nz, B = 32, 64, 2
+    g = _pic(_gec(nr, nz), load=False, method=SOLVE_IR_MG, unet_batch=B, unet_pairs=1)
+    v = _params(13)
+    g.unet_set_params(v)
+    x = _inputs(B, nz, nr, 14)
+    rng = np.random.default_rng(15)
+    target = rng.normal(size=(B, nz, nr)).astype(np.float32)
+    mask = x[..., 2].copy()
+    grads, loss = g.unet_grads(x, target, mask)
+    p = _as_gpu_sees(v)
+    n = float(mask.sum())
+
+    def oracle_grads(rounded):
+        loss_, acc = 0.0, None
+        for b in range(B):
+            out, cache = U.forward(p, U.bf16(x[b]), round_bf16=rounded)
+            d = (out - target[b]) * mask[b]
+            loss_ += float((d * d).sum()) / n
+            gb = U.backward(p, cache, 2.0 * d / n, round_bf16=rounded)
+            acc = gb if acc is None else {k: acc[k] + gb[k] for k in acc}
+        return loss_, acc
+
+    ref_loss, ref = oracle_grads(True)
+    _, exact = oracle_grads(False)
+    assert abs(loss - ref_loss) <= 1e-3 * ref_loss
+    gg = U.unflatten(grads.astype(np.float64))
+    for k in ref:
+        storage = _rel(ref[k], exact[k])
+        err, err_exact = _rel(gg[k], ref[k]), _rel(gg[k], exact[k])
+        print(f"[gpu] grad {k}: vs rounded oracle {err:.2e}, vs FP64 {err_exact:.2e}, storage effect {storage:.2e}",
+              flush=True)
+        assert storage < 1e-1, k
+        assert err <= 2 * storage + 1e-3, k
+        assert err_exact <= 2 * storage + 1e-3, k
+    g.close()
+
+
+def test_adam_step_matches_oracle():
+    """Training on one harvested pair: the parameters after one Adam step
+    equal the oracle's Adam step on the kernel's own gradient, to FP32."""
+    nr, nz = 32, 64
+    w = _gec(nr, nz, n=20000)
+    g = _pic(w, method=SOLVE_IR_MG, unet_batch=1, unet_pairs=2)
+    g.unet_harvest(1)
+    g.step(2)
+    assert g.diag().unet_pairs == 2
+    v = _params(16)
+    g.unet_set_params(v)                      # also resets Adam
+    curve = g.unet_train(1, 1, 1e-3, seed=3)  # batch of one from two pairs
+    after = g.unet_params()
+    assert np.isfinite(curve).all()
+    # the sampled pair is either slot; one of them reproduces the step
+    best = np.inf
+    for slot in (0, 1):
+        pr = g.unet_pair(slot)
+        xs = np.stack([pr["r"], pr["chi"], pr["mask"]], axis=-1)[None]
+        g.unet_set_params(v)
+        gs, _ = g.unet_grads(xs, pr["e"][None], pr["mask"][None])
+        pd = {"a": v.astype(np.float64)}
+        U.adam_step(pd, {"a": gs.astype(np.float64)}, {}, lr=1e-3)
+        best = min(best, float(np.max(np.abs(pd["a"] - after))))
+    assert best <= 2e-6, best
+    g.close()
+
+
+def test_harvested_pairs_are_residual_and_error():
+    """A harvested pair (r, e) satisfies K e ~ c r on the unknown nodes with
+    one scalar c > 0 (both are stored at unit RMS), where K is the operator
+    of the step's solve; r has unit RMS over the unknown nodes."""
+    nr, nz = 64, 128
+    w = _gec(nr, nz, n=40000)
+    g = _pic(w, method=SOLVE_IR_MG, unet_batch=1, unet_pairs=8)
+    g.unet_harvest(1)
+    g.step(3)
+    d = g.diag()
+    assert d.unet_pairs == 3
+    pr = g.unet_pair(2)              # the last step: AR/AZ still hold its operator
+    ar, az = g.grid("AR"), g.grid("AZ")
+    W = nr + 1
+    m = pr["mask"] > 0
+    nfree = int(m.sum())
+    assert abs(float((pr["r"][m].astype(np.float64) ** 2).mean()) - 1.0) < 1e-5
+    assert abs(float((pr["e"][m].astype(np.float64) ** 2).mean()) - 1.0) < 1e-5
+    e = np.zeros((nz + 1, nr + 1))
+    e[:nz, :nr] = np.where(m, pr["e"], 0.0)
+    a_r = ar.reshape(nz + 1, W)
+    a_z = az.reshape(nz + 1, W)
+    Ke = np.zeros_like(e)
+    Ke[:, :-1] += a_r[:, :-1] * (e[:, :-1] - e[:, 1:])
+    Ke[:, 1:] += a_r[:, :-1] * (e[:, 1:] - e[:, :-1])
+    Ke[:-1, :] += a_z[:-1, :] * (e[:-1, :] - e[1:, :])
+    Ke[1:, :] += a_z[:-1, :] * (e[1:, :] - e[:-1, :])
+    Ke = Ke[:nz, :nr][m]
+    r = pr["r"][m].astype(np.float64)
+    c = float(Ke @ r / (r @ r))
+    assert c > 0
+    res = np.linalg.norm(Ke - c * r) / np.linalg.norm(c * r)
+    print(f"[gpu] harvest: nfree {nfree}, |Ke - c r|/|c r| = {res:.2e}", flush=True)
+    assert res < 1e-2
+    g.close()
+
+
+def test_fpcg_converges_and_falls_back_to_multigrid():
+    from paper_2310_04957_amd.pic import SOLVE_IR_UNET
+    nr, nz = 64, 128
+    w = _gec(nr, nz, n=40000)
+    g = _pic(w, method=SOLVE_IR_UNET, unet_batch=1, unet_pairs=1)
+    g.step(3)
+    d = g.diag()
+    assert d.solver_relres <= w["solver"]["tol"]
+    assert d.unet_applications > 0
+    f0 = d.unet_fallbacks
+    # a network that outputs NaN: every solve still converges, through multigrid
+    v = np.full(g.unet_num_params(), np.nan, dtype=np.float32)
+    g.unet_set_params(v)
+    g.step(2)
+    d = g.diag()
+    assert d.solver_relres <= w["solver"]["tol"]
+    assert d.unet_fallbacks >= f0 + 2
+    g.close()
+
+
+def test_config_checks():
+    from paper_2310_04957_amd.pic import SOLVE_IR_UNET, PicError
+    with pytest.raises(PicError):       # U-net solve without a network
+        _pic(_gec(64, 128), load=False, method=SOLVE_IR_UNET, unet_batch=0)
+    g = _pic(_gec(64, 128), load=False, method=SOLVE_IR_MG, unet_batch=1, unet_pairs=0)
+    with pytest.raises(PicError):       # nothing harvested
+        g.unet_train(1, 1, 1e-3)
+    with pytest.raises(PicError):       # no pair slots
+        g.unet_harvest(1)
+    with pytest.raises(PicError):       # batch above capacity
+        g.unet_forward(np.zeros((2, 128, 64, 3), np.float32))
+    g.close()

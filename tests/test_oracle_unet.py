@@ -87,3 +87,32 @@ def test_parameter_count():
     p = U.init_params()
     n = sum(v.size for v in p.values())
     assert 150_000 < n < 250_000
+
+
+def test_bf16_storage_backward_stays_close_to_exact():
+    """Rounding the stored data gradients to bfloat16 perturbs each parameter
+    gradient by a few bfloat16 ulps at most (relative L2 per tensor)."""
+    rng = np.random.default_rng(5)
+    H, W, C = 32, 32, 8
+    p = U.init_params(C=C, seed=6)
+    x = U.bf16(rng.normal(size=(H, W, 3)))
+    mask = (rng.random((H, W)) > 0.2).astype(float)
+    target = rng.normal(size=(H, W))
+    out, cache = U.forward(p, x, round_bf16=True)
+    _, dout = U.loss_and_grad_out(out, target, mask)
+    g0 = U.backward(p, cache, dout)
+    g1 = U.backward(p, cache, dout, round_bf16=True)
+    for k in g0:
+        err = np.linalg.norm(g1[k] - g0[k]) / max(np.linalg.norm(g0[k]), 1e-30)
+        assert err < 2e-2, (k, err)
+    assert np.array_equal(g1["out.w"], g0["out.w"])
+
+
+def test_flatten_round_trip_and_count():
+    p = U.init_params(seed=7)
+    v = U.flatten(p)
+    q = U.unflatten(v)
+    assert all(np.array_equal(p[k], q[k]) for k in p)
+    # enc1a: 9*32*3 + 32 first, then enc1b starts
+    assert np.array_equal(v[:9 * 32 * 3], p["enc1a.w"].ravel())
+    assert np.array_equal(v[9 * 32 * 3:9 * 32 * 3 + 32], p["enc1a.b"])
