@@ -358,7 +358,7 @@ size_t layout(pic_handle* h, char* base) {
     h->unet_on = h->cfg.solver.unet_batch > 0;
     if (h->unet_on) {
         const int B = h->cfg.solver.unet_batch;
-        h->phi_old = c.take<double>(nn);
+        h->hx64 = c.take<double>(h->cfg.solver.unet_pairs > 0 ? (size_t)unet::kHarvestPerSolve * nn : 1);
         h->unet_stage = c.take<float>((size_t)B * h->nr * h->nz * 3);
         c.off = (c.off + 255) & ~(size_t)255;
         c.off += unet::layout(h->net, h->nz, h->nr, B, h->cfg.solver.unet_pairs, base ? base + c.off : nullptr);

@@ -432,8 +432,6 @@ __global__ void k_fcg_start(DevScalars* s) {
     if (!(s->rz > 0.0) || !isfinite(s->rz)) { s->fallback = 1; s->done = 1; }
 }
 
-__global__ void k_save_hscale(DevScalars* s) { s->hscale = s->scale; }
-
 // ------------------------------------------------------------- multigrid
 // level 0: damped Jacobi and residual on the 5-point operator
 template <typename T>
@@ -838,6 +836,30 @@ static void precondition(pic_handle* h, int ident, const T* r, T* z) {
         vcycle<T>(h, 0, r, z);
 }
 
+// harvest hook of an FP64 solve: iterate k, after the two damped-Jacobi
+// sweeps the learned preconditioner applies before the network, gives the
+// pair (r1 = r - K z1, e1 = x* - (x_k + z1)) with z1 the smoothed
+// correction; it is kept in pair slot (n_pairs + k) of the ring.  The
+// level-0 multigrid vectors are free between V-cycles and hold z1 and r1.
+template <typename T>
+static void harvest_iterate(pic_handle*, int, const T*, const T*) {}
+template <>
+void harvest_iterate<double>(pic_handle* h, int k, const double* r, const double* x) {
+    if (!h->harvesting || k >= h->harvest_limit) return;
+    Level& L = h->lv[0];
+    hipStream_t st = h->stream;
+    const DevScalars* s = h->sc;
+    hipLaunchKernelGGL(k_jac0<double>, grid_for(L.nn), dim3(256), 0, st, (const double*)h->ar, (const double*)h->az,
+                       (const int8_t*)h->node_kind, (const double*)L.x64, r, L.x64, s, L.nr, L.nz, 1);
+    hipLaunchKernelGGL(k_jac0<double>, grid_for(L.nn), dim3(256), 0, st, (const double*)h->ar, (const double*)h->az,
+                       (const int8_t*)h->node_kind, (const double*)L.x64, r, L.y64, s, L.nr, L.nz, 0);
+    hipLaunchKernelGGL(k_res0<double>, grid_for(L.nn), dim3(256), 0, st, (const double*)h->ar, (const double*)h->az,
+                       (const int8_t*)h->node_kind, (const double*)L.y64, r, L.res64, s, L.nr, L.nz);
+    const int slot = (int)((h->net.n_pairs + k) % h->net.cap_pairs);
+    unet::harvest_iter(h->net, slot, L.res64, x, L.y64, h->chi, h->node_kind, h->hx64 + (size_t)k * h->nn,
+                       &h->sc->done, h->w, h->nn, st);
+}
+
 template <typename T>
 static int pcg(pic_handle* h, T* r, T* x, T* z, T* p, T* q, int max_iter, int* err, int ident = 0) {
     using V = VecSet<T>;
@@ -846,6 +868,7 @@ static int pcg(pic_handle* h, T* r, T* x, T* z, T* p, T* q, int max_iter, int* e
     DevScalars* s = h->sc;
     hipLaunchKernelGGL(k_begin_cg, dim3(1), dim3(1), 0, st, s);
     hipLaunchKernelGGL(k_fill<T>, grid_for(nn), dim3(256), 0, st, x, nn);
+    harvest_iterate<T>(h, 0, r, x);
     precondition<T>(h, ident, r, z);
     hipLaunchKernelGGL(k_copy<T>, grid_for(nn), dim3(256), 0, st, p, (const T*)z, s, nn);
     hipLaunchKernelGGL(k_dot<T>, dim3(kRedBlocks), dim3(256), 0, st, (const T*)r, (const T*)z, h->part, s, nn);
@@ -857,6 +880,7 @@ static int pcg(pic_handle* h, T* r, T* x, T* z, T* p, T* q, int max_iter, int* e
         hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, st, (const double*)h->part, s, 1);
         hipLaunchKernelGGL(k_update_xr<T>, dim3(kRedBlocks), dim3(256), 0, st, x, r, (const T*)p, (const T*)q,
                            h->part, s, nn);
+        harvest_iterate<T>(h, it + 1, r, x);
         hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, st, (const double*)h->part, s, 2);
         precondition<T>(h, ident, r, z);
         hipLaunchKernelGGL(k_dot<T>, dim3(kRedBlocks), dim3(256), 0, st, (const T*)r, (const T*)z, h->part, s, nn);
@@ -874,13 +898,92 @@ static int pcg(pic_handle* h, T* r, T* x, T* z, T* p, T* q, int max_iter, int* e
     return h->h_sc->iters;
 }
 
-// z = ||r|| UNet(r sqrt(n_free) / ||r||, chi / (1 + chi), mask) on the node
-// grid; rr points at r.r on the device
-static void unet_apply(pic_handle* h, const float* r, const double* rr, float* z) {
+// learned preconditioner, one application z = P(r): two damped-Jacobi
+// sweeps, then the network's output v for the remaining residual res as a
+// one-dimensional Galerkin correction z += c v with c = (v.res)/(v.A v)
+// (c = 0 if v.A v is not positive), then two Jacobi sweeps again.  The
+// network supplies only a direction, so it is trained on unit-RMS pairs.
+__global__ __launch_bounds__(256) void k_spmv_dot2(const float* ar, const float* az, const int8_t* nk,
+                                                   const float* v, const float* res, float* q, double* part,
+                                                   const DevScalars* s, int nr, int nz) {
+    __shared__ double sh[4];
+    if (s->done) return;
+    const int w = nr + 1, nn = w * (nz + 1);
+    double a = 0.0, b = 0.0;
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += gridDim.x * blockDim.x) {
+        if (nk[n] >= 0) { q[n] = 0.0f; continue; }
+        float d;
+        const float av = apply0(ar, az, nk, v, n, n % w, n / w, nr, nz, w, d);
+        q[n] = av;
+        a += (double)v[n] * (double)av;
+        b += (double)v[n] * (double)res[n];
+    }
+    double t1 = block_sum(a, sh);
+    double t2 = block_sum(b, sh);
+    if (threadIdx.x == 0) { part[blockIdx.x] = t1; part[kRedBlocks + blockIdx.x] = t2; }
+}
+
+// what = 0: rr_net = sum of part; 1: c_net from (v.Av, v.res)
+__global__ __launch_bounds__(256) void k_reduce_net(const double* part, DevScalars* s, int what) {
+    __shared__ double a[kRedBlocks], b[kRedBlocks];
+    if (s->done) return;
+    for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) {
+        a[i] = part[i];
+        b[i] = what ? part[kRedBlocks + i] : 0.0;
+    }
+    __syncthreads();
+    for (int o = kRedBlocks / 2; o > 0; o >>= 1) {
+        for (int i = threadIdx.x; i < o; i += blockDim.x) { a[i] += a[i + o]; b[i] += b[i + o]; }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    if (what == 0) {
+        s->rr_net = a[0] > 0.0 ? a[0] : 1.0;
+    } else {
+        const double vav = a[0], vr = b[0];
+        s->c_net = (vav > 0.0 && isfinite(vav) && isfinite(vr)) ? vr / vav : 0.0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_axpy_net(float* z, const float* v, const DevScalars* s, int nn) {
+    if (s->done) return;
+    const float c = (float)s->c_net;
+    if (c == 0.0f) return;
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += gridDim.x * blockDim.x) z[n] += c * v[n];
+}
+
+static void unet_apply(pic_handle* h, const float* r, float* z) {
     unet::Net& n = h->net;
-    unet::input_from_r32(n, r, rr, h->chi, h->node_kind, h->w, (double)h->img_free, h->stream);
-    unet::forward(n, 1, h->stream);
-    unet::out_to_z(n, rr, h->node_kind, z, h->w, h->nn, h->stream);
+    Level& L = h->lv[0];
+    hipStream_t st = h->stream;
+    DevScalars* s = h->sc;
+    const float* ar = h->ar32;
+    const float* az = h->az32;
+    const int8_t* nk = h->node_kind;
+    const int nn = h->nn;
+    float* t = L.x32;      // scratch: smoother iterate, then the network direction v
+    float* res = L.res32;
+    float* q = L.y32;
+    hipLaunchKernelGGL(k_jac0<float>, grid_for(nn), dim3(256), 0, st, ar, az, nk, (const float*)t, r, t,
+                       (const DevScalars*)s, h->nr, h->nz, 1);
+    hipLaunchKernelGGL(k_jac0<float>, grid_for(nn), dim3(256), 0, st, ar, az, nk, (const float*)t, r, z,
+                       (const DevScalars*)s, h->nr, h->nz, 0);
+    hipLaunchKernelGGL(k_res0<float>, grid_for(nn), dim3(256), 0, st, ar, az, nk, (const float*)z, r, res,
+                       (const DevScalars*)s, h->nr, h->nz);
+    hipLaunchKernelGGL(k_dot<float>, dim3(kRedBlocks), dim3(256), 0, st, (const float*)res, (const float*)res, h->part,
+                       (const DevScalars*)s, nn);
+    hipLaunchKernelGGL(k_reduce_net, dim3(1), dim3(256), 0, st, (const double*)h->part, s, 0);
+    unet::input_from_r32(n, res, &s->rr_net, h->chi, nk, h->w, (double)h->img_free, st);
+    unet::forward(n, 1, st);
+    unet::out_to_z(n, &s->rr_net, nk, t, h->w, nn, st);
+    hipLaunchKernelGGL(k_spmv_dot2, dim3(kRedBlocks), dim3(256), 0, st, ar, az, nk, (const float*)t,
+                       (const float*)res, q, h->part, (const DevScalars*)s, h->nr, h->nz);
+    hipLaunchKernelGGL(k_reduce_net, dim3(1), dim3(256), 0, st, (const double*)h->part, s, 1);
+    hipLaunchKernelGGL(k_axpy_net, grid_for(nn), dim3(256), 0, st, z, (const float*)t, (const DevScalars*)s, nn);
+    hipLaunchKernelGGL(k_jac0<float>, grid_for(nn), dim3(256), 0, st, ar, az, nk, (const float*)z, r, t,
+                       (const DevScalars*)s, h->nr, h->nz, 0);
+    hipLaunchKernelGGL(k_jac0<float>, grid_for(nn), dim3(256), 0, st, ar, az, nk, (const float*)t, r, z,
+                       (const DevScalars*)s, h->nr, h->nz, 0);
     h->unet_apps++;
 }
 
@@ -895,7 +998,7 @@ static int fpcg(pic_handle* h, float* r, float* x, float* z, float* p, float* q,
     DevScalars* s = h->sc;
     hipLaunchKernelGGL(k_begin_cg, dim3(1), dim3(1), 0, st, s);
     hipLaunchKernelGGL(k_fill<float>, grid_for(nn), dim3(256), 0, st, x, nn);
-    unet_apply(h, r, &s->one, z);    // r arrives with unit norm
+    unet_apply(h, r, z);
     hipLaunchKernelGGL(k_copy<float>, grid_for(nn), dim3(256), 0, st, p, (const float*)z, s, nn);
     hipLaunchKernelGGL(k_dot<float>, dim3(kRedBlocks), dim3(256), 0, st, (const float*)r, (const float*)z, h->part, s,
                        nn);
@@ -912,7 +1015,7 @@ static int fpcg(pic_handle* h, float* r, float* x, float* z, float* p, float* q,
         hipMemcpyAsync(h->h_sc, s, sizeof(DevScalars), hipMemcpyDeviceToHost, st);
         if (hipStreamSynchronize(st) != hipSuccess) { *err = PIC_E_HIP; return it; }
         if (h->h_sc->done) break;
-        unet_apply(h, r, &s->rr, z);
+        unet_apply(h, r, z);
         hipLaunchKernelGGL(k_dot2, dim3(kRedBlocks), dim3(256), 0, st, (const float*)z, (const float*)r,
                            (const float*)q, h->part, (const DevScalars*)s, nn);
         hipLaunchKernelGGL(k_reduce_fcg, dim3(1), dim3(256), 0, st, (const double*)h->part, s);
@@ -924,10 +1027,6 @@ static int fpcg(pic_handle* h, float* r, float* x, float* z, float* p, float* q,
     if (h->h_sc->nonfinite) *err = PIC_E_NONFINITE;
     if (!h->h_sc->done) h->h_sc->fallback = 1;   // out of iterations
     return h->h_sc->iters;
-}
-
-__global__ __launch_bounds__(256) void k_copy64(double* dst, const double* src, int nn) {
-    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += gridDim.x * blockDim.x) dst[n] = src[n];
 }
 
 template <typename T>
@@ -951,13 +1050,13 @@ int field_solve(pic_handle* h, double* phi, const double* Q, const double* Up, d
                 int32_t* iters_out, double* relres_out) {
     hipStream_t st = h->stream;
     const int nn = h->nn;
+    // a harvested solve runs FP64 MG-PCG and keeps its first Krylov iterates
+    // (residual r_k, error x* - x_k of the first outer pass) as training pairs
+    const bool harvest = h->harvest_now && h->unet_on && Q != nullptr && h->net.cap_pairs > 0;
+    if (harvest) method = PIC_SOLVE_MGPCG_FP64;
     const int fp64 = (method == PIC_SOLVE_MGPCG_FP64);
     const int max_outer = fp64 ? 4 : 30;
-    // a harvested solve stores its first residual and, once converged, the
-    // error phi - phi_old it removed (both normalised by ||r0||)
-    const bool harvest = h->harvest_now && h->unet_on && Q != nullptr;
-    const int slot = harvest ? (int)(h->net.n_pairs % std::max(h->net.cap_pairs, 1)) : 0;
-    bool harvested_r = false;
+    int harvested = 0;
     int total = 0, outer = 0, err = 0;
     double rel = 0.0;
     for (;; ++outer) {
@@ -969,14 +1068,20 @@ int field_solve(pic_handle* h, double* phi, const double* Q, const double* Up, d
         rel = h->h_sc->relres;
         if (h->h_sc->nonfinite) { err = PIC_E_NONFINITE; break; }
         if (rel <= tol || outer >= max_outer) break;
-        if (harvest && outer == 0 && h->net.cap_pairs > 0) {
-            hipLaunchKernelGGL(k_save_hscale, dim3(1), dim3(1), 0, st, h->sc);
-            hipLaunchKernelGGL(k_copy64, grid_for(nn), dim3(256), 0, st, h->phi_old, (const double*)phi, nn);
-            unet::harvest_r(h->net, slot, h->r64, &h->sc->hscale, h->chi, h->node_kind, h->w, (double)h->img_free, st);
-            harvested_r = true;
-        }
         if (fp64) {
-            total += pcg<double>(h, h->r64, h->x64, h->z64, h->p64, h->q64, h->cfg.solver.max_iter, &err);
+            h->harvesting = harvest && outer == 0;
+            h->harvest_limit = std::min(unet::kHarvestPerSolve, h->net.cap_pairs);
+            const int its = pcg<double>(h, h->r64, h->x64, h->z64, h->p64, h->q64, h->cfg.solver.max_iter, &err);
+            total += its;
+            if (h->harvesting && !err && its > 0) {
+                // iterates 0 .. its-2: the last two are too close to x* for
+                // x* - x_k to be an accurate error
+                harvested = std::min(std::max(its - 1, 1), h->harvest_limit);
+                for (int k = 0; k < harvested; ++k)
+                    unet::pair_finish(h->net, (int)((h->net.n_pairs + k) % h->net.cap_pairs), h->x64,
+                                      h->hx64 + (size_t)k * nn, h->node_kind, h->w, (double)h->img_free, h->part, st);
+            }
+            h->harvesting = false;
             hipLaunchKernelGGL(k_add_phi<double>, grid_for(nn), dim3(256), 0, st, phi, (const double*)h->x64,
                                (const int8_t*)h->node_kind, (const DevScalars*)h->sc, nn, 0);
         } else {
@@ -998,10 +1103,7 @@ int field_solve(pic_handle* h, double* phi, const double* Q, const double* Up, d
         if (err) break;
     }
     hipLaunchKernelGGL(k_set_dirichlet, grid_for(nn), dim3(256), 0, st, phi, (const int8_t*)h->node_kind, Up, nn);
-    if (harvested_r && !err && rel <= tol) {
-        unet::harvest_e(h->net, slot, phi, h->phi_old, h->node_kind, h->w, (double)h->img_free, h->part, st);
-        h->net.n_pairs++;
-    }
+    if (harvested > 0 && !err && rel <= tol) h->net.n_pairs += harvested;
     h->solver_outer = outer;
     if (iters_out) *iters_out = total;
     if (relres_out) *relres_out = rel;

@@ -45,7 +45,7 @@ struct DevScalars {
     double one;              // constant 1.0: Dirichlet value of the Laplace problem
     double powered_prev;     // integer powered-electrode charge at the last circuit step
     double bb, rr, rz, rz_new, pq, alpha, beta, target, scale, relres, rr0;
-    double hscale;           // 1/||r0|| of a harvested solve
+    double rr_net, c_net;    // learned preconditioner: |res|^2 at the network, its Galerkin weight
     int done, iters, nonfinite, fallback;
 };
 
@@ -125,9 +125,9 @@ struct pic_handle {
     bool unet_on;
     pic::unet::Net net;
     float* unet_stage;      // host-provided inputs, [B][H][W][3]
-    double* phi_old;
-    int harvest_every;
-    bool harvest_now;
+    double* hx64;           // [kHarvestPerSolve][nn] Krylov iterates of a harvested solve
+    int harvest_every, harvest_limit;
+    bool harvest_now, harvesting;
     int64_t unet_fallbacks, unet_apps, img_free;
     // phase timing
     bool timing;

@@ -28,6 +28,7 @@ constexpr int kLossBlocks = 256;
 constexpr int kMaxBatch = 16;
 constexpr int kLossLog = 1024;
 constexpr int kHarvestBlocks = 1024;
+constexpr int kHarvestPerSolve = 16;   // Krylov iterates kept per harvested solve
 constexpr int kMaxPairs = 1 << 16;
 
 // launchers (unet_kernels.hip)
@@ -54,11 +55,13 @@ void gather_batch(const Net& n, const int* idx, int B, hipStream_t s);
 void input_from_r32(const Net& n, const float* r, const double* rr, const double* chi, const int8_t* nk, int w,
                     double n_free, hipStream_t s);
 void out_to_z(const Net& n, const double* rr, const int8_t* nk, float* z, int w, int nn, hipStream_t s);
-void harvest_r(const Net& n, int slot, const double* r64, const double* scale, const double* chi, const int8_t* nk,
-               int w, double n_free, hipStream_t s);
-// part: >= kHarvestBlocks doubles of scratch
-void harvest_e(const Net& n, int slot, const double* phi, const double* phi_old, const int8_t* nk, int w,
-               double n_free, double* part, hipStream_t s);
+// harvest of the Krylov iterates of an FP64 MG-PCG solve: residual r of the
+// approximation x + dx
+void harvest_iter(const Net& n, int slot, const double* r, const double* x, const double* dx, const double* chi,
+                  const int8_t* nk, double* xk, const int* done, int w, int nn, hipStream_t s);
+// part: >= 2 kHarvestBlocks doubles of scratch
+void pair_finish(const Net& n, int slot, const double* xs, const double* xk, const int8_t* nk, int w, double n_free,
+                 double* part, hipStream_t s);
 
 struct Conv {
     int cin, cin_pad;

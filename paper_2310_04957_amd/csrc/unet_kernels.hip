@@ -447,61 +447,83 @@ __global__ __launch_bounds__(256) void k_out_to_z(const float* out, const double
     }
 }
 
-// harvest: the first residual of a solve at unit RMS (scale = 1/||r0||),
-// chi / (1 + chi) and the mask, into a pair slot
-__global__ __launch_bounds__(256) void k_harvest_r(const double* r64, const double* scale, const double* chi,
-                                                   const int8_t* nk, float* hr, float* hchi, float* hmask, int H,
-                                                   int W, int w, double root_n) {
+// harvest, inside an FP64 MG-PCG solve: a residual (FP32, image layout,
+// not yet scaled), chi / (1 + chi), the mask, and the approximation x + dx it
+// belongs to (FP64, node layout) for the error computed once the solve is
+// done.  Skipped once the solve has converged (*done).
+__global__ __launch_bounds__(256) void k_harvest_iter(const double* r, const double* x, const double* dx,
+                                                      const double* chi, const int8_t* nk, float* hr, float* hchi,
+                                                      float* hmask, double* xk, const int* done, int H, int W, int w,
+                                                      int nn) {
+    if (*done) return;
     const size_t n = (size_t)H * W;
-    const double sc = *scale * root_n;
     for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < n; p += (size_t)gridDim.x * blockDim.x) {
         const int node = (int)(p / W) * w + (int)(p % W);
         const bool free = nk[node] < 0;
-        hr[p] = free ? (float)(r64[node] * sc) : 0.0f;
+        hr[p] = free ? (float)r[node] : 0.0f;
         const double c = chi[node];
         hchi[p] = (float)(c / (1.0 + c));
         hmask[p] = free ? 1.0f : 0.0f;
     }
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += gridDim.x * blockDim.x) xk[e] = x[e] + dx[e];
 }
 
-// harvest: the error the solve removed, delta = phi - phi_old, first raw
-// with per-block partial sums of delta^2 ...
-__global__ __launch_bounds__(256) void k_harvest_e(const double* phi, const double* phi_old, const int8_t* nk,
-                                                   float* he, double* part, int H, int W, int w) {
-    __shared__ double sh[256];
+// after the solve: the error of iterate k, e = x* - x_k (FP64 difference),
+// and per-block partial sums of e^2 and r^2
+__global__ __launch_bounds__(256) void k_pair_error(const double* xs, const double* xk, const int8_t* nk,
+                                                    const float* hr, float* he, double* part, int H, int W, int w) {
+    __shared__ double sa[256], sb[256];
     const size_t n = (size_t)H * W;
-    double acc = 0.0;
+    double a = 0.0, b = 0.0;
     for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < n; p += (size_t)gridDim.x * blockDim.x) {
         const int node = (int)(p / W) * w + (int)(p % W);
-        const double d = nk[node] < 0 ? phi[node] - phi_old[node] : 0.0;
+        const double d = nk[node] < 0 ? xs[node] - xk[node] : 0.0;
         he[p] = (float)d;
-        acc += d * d;
+        a += d * d;
+        b += (double)hr[p] * (double)hr[p];
     }
-    sh[threadIdx.x] = acc;
+    sa[threadIdx.x] = a;
+    sb[threadIdx.x] = b;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        if ((int)threadIdx.x < o) {
+            sa[threadIdx.x] += sa[threadIdx.x + o];
+            sb[threadIdx.x] += sb[threadIdx.x + o];
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = sa[0];
+        part[2 * blockIdx.x + 1] = sb[0];
+    }
 }
 
-// ... then scaled to unit RMS over the unknown nodes (every block sums the
-// partials in the same order)
-__global__ __launch_bounds__(256) void k_norm_pair(float* he, const double* part, int nparts, size_t n, double n_free) {
-    __shared__ double sh[256];
-    double acc = 0.0;
-    for (int b = threadIdx.x; b < nparts; b += blockDim.x) acc += part[b];
-    sh[threadIdx.x] = acc;
+// ... then both scaled to unit RMS over the unknown nodes (every block sums
+// the partials in the same order)
+__global__ __launch_bounds__(256) void k_pair_norm(float* hr, float* he, const double* part, int nparts, size_t n,
+                                                   double n_free) {
+    __shared__ double sa[256], sb[256];
+    double a = 0.0, b = 0.0;
+    for (int k = threadIdx.x; k < nparts; k += blockDim.x) {
+        a += part[2 * k];
+        b += part[2 * k + 1];
+    }
+    sa[threadIdx.x] = a;
+    sb[threadIdx.x] = b;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        if ((int)threadIdx.x < o) {
+            sa[threadIdx.x] += sa[threadIdx.x + o];
+            sb[threadIdx.x] += sb[threadIdx.x + o];
+        }
         __syncthreads();
     }
-    const double ss = sh[0];
-    const float sc = ss > 0.0 ? (float)sqrt(n_free / ss) : 0.0f;
-    for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < n; p += (size_t)gridDim.x * blockDim.x)
-        he[p] *= sc;
+    const float se = sa[0] > 0.0 ? (float)sqrt(n_free / sa[0]) : 0.0f;
+    const float sr = sb[0] > 0.0 ? (float)sqrt(n_free / sb[0]) : 0.0f;
+    for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < n; p += (size_t)gridDim.x * blockDim.x) {
+        he[p] *= se;
+        hr[p] *= sr;
+    }
 }
 
 // --------------------------------------------------------------- launchers
@@ -593,19 +615,20 @@ void input_from_r32(const Net& n, const float* r, const double* rr, const double
 void out_to_z(const Net& n, const double* rr, const int8_t* nk, float* z, int w, int nn, hipStream_t s) {
     hipLaunchKernelGGL(k_out_to_z, ew_grid(nn), dim3(256), 0, s, (const float*)n.out, rr, nk, z, n.H, n.W, w, nn);
 }
-void harvest_r(const Net& n, int slot, const double* r64, const double* scale, const double* chi, const int8_t* nk,
-               int w, double n_free, hipStream_t s) {
+void harvest_iter(const Net& n, int slot, const double* r, const double* x, const double* dx, const double* chi,
+                  const int8_t* nk, double* xk, const int* done, int w, int nn, hipStream_t s) {
     const size_t img = (size_t)n.H * n.W;
-    hipLaunchKernelGGL(k_harvest_r, ew_grid(img), dim3(256), 0, s, r64, scale, chi, nk, n.h_r + slot * img,
-                       n.h_chi + slot * img, n.h_mask, n.H, n.W, w, sqrt(n_free));
+    hipLaunchKernelGGL(k_harvest_iter, ew_grid(std::max<size_t>(img, nn)), dim3(256), 0, s, r, x, dx, chi, nk,
+                       n.h_r + slot * img, n.h_chi + slot * img, n.h_mask, xk, done, n.H, n.W, w, nn);
 }
-void harvest_e(const Net& n, int slot, const double* phi, const double* phi_old, const int8_t* nk, int w,
-               double n_free, double* part, hipStream_t s) {
+void pair_finish(const Net& n, int slot, const double* xs, const double* xk, const int8_t* nk, int w, double n_free,
+                 double* part, hipStream_t s) {
     const size_t img = (size_t)n.H * n.W;
     const dim3 g((unsigned)std::min<size_t>((img + 255) / 256, kHarvestBlocks));
-    hipLaunchKernelGGL(k_harvest_e, g, dim3(256), 0, s, phi, phi_old, nk, n.h_e + slot * img, part, n.H, n.W, w);
-    hipLaunchKernelGGL(k_norm_pair, g, dim3(256), 0, s, n.h_e + slot * img, (const double*)part, (int)g.x, img,
-                       n_free);
+    hipLaunchKernelGGL(k_pair_error, g, dim3(256), 0, s, xs, xk, nk, (const float*)(n.h_r + slot * img),
+                       n.h_e + slot * img, part, n.H, n.W, w);
+    hipLaunchKernelGGL(k_pair_norm, g, dim3(256), 0, s, n.h_r + slot * img, n.h_e + slot * img, (const double*)part,
+                       (int)g.x, img, n_free);
 }
 
 }  // namespace unet

@@ -140,7 +140,7 @@ def test_adam_step_matches_oracle():
     g = _pic(w, method=SOLVE_IR_MG, unet_batch=1, unet_pairs=2)
     g.unet_harvest(1)
     g.step(2)
-    assert g.diag().unet_pairs == 2
+    assert g.diag().unet_pairs >= 2          # the ring keeps the last two
     v = _params(16)
     g.unet_set_params(v)                      # also resets Adam
     curve = g.unet_train(1, 1, 1e-3, seed=3)  # batch of one from two pairs
@@ -161,43 +161,47 @@ def test_adam_step_matches_oracle():
 
 
 def test_harvested_pairs_are_residual_and_error():
-    """A harvested pair (r, e) satisfies K e ~ c r on the unknown nodes with
-    one scalar c > 0 (both are stored at unit RMS), where K is the operator
-    of the step's solve; r has unit RMS over the unknown nodes."""
+    """A harvested solve keeps its Krylov iterates: pair k holds the residual
+    r_k and the error e_k = x* - x_k, both at unit RMS over the unknown
+    nodes, so K e_k = c r_k with one scalar c > 0 up to the final residual
+    of the solve (K: the operator of that solve).  The first pair is the
+    residual of the warm start itself."""
     nr, nz = 64, 128
     w = _gec(nr, nz, n=40000)
-    g = _pic(w, method=SOLVE_IR_MG, unet_batch=1, unet_pairs=8)
+    g = _pic(w, method=SOLVE_IR_MG, unet_batch=1, unet_pairs=64)
+    g.step(2)
     g.unet_harvest(1)
-    g.step(3)
+    g.step(1)
     d = g.diag()
-    assert d.unet_pairs == 3
-    pr = g.unet_pair(2)              # the last step: AR/AZ still hold its operator
-    ar, az = g.grid("AR"), g.grid("AZ")
+    npairs = d.unet_pairs
+    assert 1 <= npairs <= min(16, max(d.solver_iters - 1, 1))
+    ar, az = g.grid("AR"), g.grid("AZ")     # still the operator of that solve
     W = nr + 1
-    m = pr["mask"] > 0
-    nfree = int(m.sum())
-    assert abs(float((pr["r"][m].astype(np.float64) ** 2).mean()) - 1.0) < 1e-5
-    assert abs(float((pr["e"][m].astype(np.float64) ** 2).mean()) - 1.0) < 1e-5
-    e = np.zeros((nz + 1, nr + 1))
-    e[:nz, :nr] = np.where(m, pr["e"], 0.0)
     a_r = ar.reshape(nz + 1, W)
     a_z = az.reshape(nz + 1, W)
-    Ke = np.zeros_like(e)
-    Ke[:, :-1] += a_r[:, :-1] * (e[:, :-1] - e[:, 1:])
-    Ke[:, 1:] += a_r[:, :-1] * (e[:, 1:] - e[:, :-1])
-    Ke[:-1, :] += a_z[:-1, :] * (e[:-1, :] - e[1:, :])
-    Ke[1:, :] += a_z[:-1, :] * (e[1:, :] - e[:-1, :])
-    Ke = Ke[:nz, :nr][m]
-    r = pr["r"][m].astype(np.float64)
-    c = float(Ke @ r / (r @ r))
-    assert c > 0
-    res = np.linalg.norm(Ke - c * r) / np.linalg.norm(c * r)
-    print(f"[gpu] harvest: nfree {nfree}, |Ke - c r|/|c r| = {res:.2e}", flush=True)
-    assert res < 1e-2
+    for k in range(npairs):
+        pr = g.unet_pair(k)
+        m = pr["mask"] > 0
+        assert abs(float((pr["r"][m].astype(np.float64) ** 2).mean()) - 1.0) < 1e-5
+        assert abs(float((pr["e"][m].astype(np.float64) ** 2).mean()) - 1.0) < 1e-5
+        e = np.zeros((nz + 1, nr + 1))
+        e[:nz, :nr] = np.where(m, pr["e"], 0.0)
+        Ke = np.zeros_like(e)
+        Ke[:, :-1] += a_r[:, :-1] * (e[:, :-1] - e[:, 1:])
+        Ke[:, 1:] += a_r[:, :-1] * (e[:, 1:] - e[:, :-1])
+        Ke[:-1, :] += a_z[:-1, :] * (e[:-1, :] - e[1:, :])
+        Ke[1:, :] += a_z[:-1, :] * (e[1:, :] - e[:-1, :])
+        Ke = Ke[:nz, :nr][m]
+        r = pr["r"][m].astype(np.float64)
+        c = float(Ke @ r / (r @ r))
+        res = np.linalg.norm(Ke - c * r) / np.linalg.norm(c * r)
+        print(f"[gpu] harvest pair {k}: |K e - c r|/|c r| = {res:.2e}", flush=True)
+        assert c > 0
+        assert res < (1e-3 if k == 0 else 0.3)
     g.close()
 
 
-def test_fpcg_converges_and_falls_back_to_multigrid():
+def test_fpcg_converges_rejects_bad_network_and_falls_back_to_multigrid():
     from paper_2310_04957_amd.pic import SOLVE_IR_UNET
     nr, nz = 64, 128
     w = _gec(nr, nz, n=40000)
@@ -206,10 +210,17 @@ def test_fpcg_converges_and_falls_back_to_multigrid():
     d = g.diag()
     assert d.solver_relres <= w["solver"]["tol"]
     assert d.unet_applications > 0
+    # a network that outputs NaN: its Galerkin weight is zero, the smoothing
+    # around it still preconditions, every solve converges
+    g.unet_set_params(np.full(g.unet_num_params(), np.nan, dtype=np.float32))
+    g.step(2)
+    d = g.diag()
+    assert d.solver_relres <= w["solver"]["tol"]
+    # one Krylov iteration per inner solve: flexible CG cannot finish and
+    # hands every solve over to multigrid (still converging through the
+    # outer refinement)
     f0 = d.unet_fallbacks
-    # a network that outputs NaN: every solve still converges, through multigrid
-    v = np.full(g.unet_num_params(), np.nan, dtype=np.float32)
-    g.unet_set_params(v)
+    g.set_solver(max_iter=1)
     g.step(2)
     d = g.diag()
     assert d.solver_relres <= w["solver"]["tol"]
@@ -228,4 +239,45 @@ def test_config_checks():
         g.unet_harvest(1)
     with pytest.raises(PicError):       # batch above capacity
         g.unet_forward(np.zeros((2, 128, 64, 3), np.float32))
+    g.close()
+
+
+def test_trained_network_gains_over_cg_without_it():
+    """What the learned part buys: on the same warm-started solves, flexible
+    CG with the trained network needs far fewer iterations than CG without a
+    preconditioner, and fewer than with the untrained network; every solve
+    reaches the FP64 tolerance.  MG-PCG is reported beside it."""
+    from paper_2310_04957_amd.pic import SOLVE_IR_CG, SOLVE_IR_MG, SOLVE_IR_UNET
+    nr, nz = 64, 128
+    w = _gec(nr, nz, n=40000)
+    g = _pic(w, method=SOLVE_IR_MG, unet_batch=8, unet_pairs=1024)
+    g.step(10)
+    g.unet_harvest(1)
+    g.step(60)
+    g.unet_harvest(0)
+    assert g.diag().unet_pairs >= 200
+    problems = []
+    for _ in range(3):
+        phi0 = g.grid("PHI")
+        g.step(1)
+        problems.append((g.grid("Q"), g.grid("CHI"), g.diag().U_E, phi0))
+    tol = w["solver"]["tol"]
+
+    def iters(method):
+        g.set_solver(method=method, max_iter=5000)
+        total = 0
+        for Q, chi, U, phi0 in problems:
+            _, it, rel, rc = g.solve_once(Q, chi, U, tol, phi0)
+            assert rc == 0 and rel <= tol, (method, rc, rel)
+            total += it
+        return total
+
+    cg, mg, untrained = iters(SOLVE_IR_CG), iters(SOLVE_IR_MG), iters(SOLVE_IR_UNET)
+    curve = g.unet_train(600, 8, 1e-3, seed=5)
+    trained = iters(SOLVE_IR_UNET)
+    print(f"[gpu] inner iterations over 3 solves: CG {cg}, U-net untrained {untrained}, trained {trained}, "
+          f"MG-PCG {mg}; loss {curve[:10].mean():.3f} -> {curve[-50:].mean():.3f}", flush=True)
+    assert curve[-50:].mean() < 0.5 * curve[:10].mean()
+    assert trained < untrained
+    assert 5 * trained < cg
     g.close()
