@@ -88,7 +88,7 @@ typedef struct {
 
 typedef struct {
     int64_t n_e, n_i;           /* initial macro-particles */
-    int64_t cap_e, cap_i;       /* slots reserved per species */
+    int64_t cap_e, cap_i;       /* slots reserved per species, at most 2^30 - 16 */
     double n0, Te_eV, Ti_eV;    /* initial uniform plasma density (m^-3) and temperatures */
     int32_t steps_per_period;   /* dt = 1 / (freq * steps_per_period) */
     int32_t sort_every;         /* electron tile sort every K steps (0: never) */

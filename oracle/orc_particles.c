@@ -299,10 +299,20 @@ static double e_cos_chi(double eps, double u) {
    -1 no collision, 0 elastic / isotropic, 1 excitation / charge exchange,
    2 ionisation, 3 null.  For ionisation birth6 = (ejected electron v,
    new ion v). */
+/* The null-collision decision word of a slot at a step [R27]: one
+   Philox4x32-10 block (purpose 2) serves the four slots that agree in the
+   low six bits and in bits 8 and up, c0 = (slot mod 64) + 64 floor(slot/256);
+   the slot takes word floor(slot / 64) mod 4 of it. */
+static uint32_t decision_word(const orc_sim* s, uint32_t slot, uint32_t step, int sp) {
+    uint32_t x[4];
+    draw(s, (slot & 63u) | ((slot >> 8) << 6), step, 2, sp, 0, x);
+    return x[(slot >> 6) & 3u];
+}
+
 int o_mcc1(orc_sim* s, int sp, double* v, uint32_t slot, uint32_t step, double* birth6) {
     uint32_t x[4];
+    if (!(decision_word(s, slot, step, sp) < s->thresh[sp])) return -1;
     draw(s, slot, step, 1, sp, 0, x);
-    if (!(x[0] < s->thresh[sp])) return -1;
     double u1 = o_u01(x[1]), u2 = o_u01(x[2]), u3 = o_u01(x[3]);
     double R = u1 * s->nu_max[sp];
     if (sp == 0) {

@@ -21,6 +21,7 @@ constexpr double kMAr = 39.948 * 1.66053906660e-27;
 constexpr double kEps0 = 8.8541878128e-12;
 constexpr double kKB = 1.380649e-23;
 constexpr double kPi = 3.14159265358979323846;
+constexpr int64_t kMaxSlots = (1LL << 30) - 16;   // particle arrays are addressed by 32-bit byte offsets
 
 #define HIP_OK(x)                               \
     do {                                        \
@@ -48,7 +49,7 @@ int validate(const pic_config* c) {
     if (ci.kind == PIC_SERIES_RLC && !(ci.C_b > 0 && ci.L_b > 0)) return PIC_E_CONFIG;
     const pic_run& r = c->run;
     if (r.steps_per_period < 1 || r.n_e < 0 || r.n_i < 0 || r.cap_e < r.n_e || r.cap_i < r.n_i) return PIC_E_CONFIG;
-    if (r.cap_e > 0xFFFFFFF0LL || r.cap_i > 0xFFFFFFF0LL || r.sort_every < 0 || r.sort_every_ion < 0)
+    if (r.cap_e > kMaxSlots || r.cap_i > kMaxSlots || r.sort_every < 0 || r.sort_every_ion < 0)
         return PIC_E_CONFIG;
     if (!(c->gas.p_Pa >= 0) || !(c->gas.T_gas_K > 0) || !(r.n0 >= 0)) return PIC_E_CONFIG;
     if (c->solver.method < 0 || c->solver.method > 3 || !(c->solver.tol > 0) || c->solver.max_iter < 1)
@@ -329,6 +330,7 @@ size_t layout(pic_handle* h, char* base) {
     h->chi = c.take<double>(nn); h->Q = c.take<double>(nn);
     h->ar = c.take<double>(nn); h->az = c.take<double>(nn);
     h->phi = c.take<double>(nn); h->phiL = c.take<double>(nn); h->zeroQ = c.take<double>(nn);
+    h->phi_prev = c.take<double>(nn);
     h->ar32 = c.take<float>(nn); h->az32 = c.take<float>(nn);
     h->E = c.take<float2>(nn);
     h->r64 = c.take<double>(nn); h->x64 = c.take<double>(nn); h->z64 = c.take<double>(nn);
@@ -606,6 +608,7 @@ int pic_step(pic_handle* h, int32_t nsteps) {
         int32_t it = 0;
         double rel = 0.0;
         h->harvest_now = h->harvest_every > 0 && h->step % h->harvest_every == 0;
+        launch_extrapolate(h);
         int rc = field_solve(h, h->phi, h->Q, &h->sc->U_E, c.solver.tol, c.solver.method, &it, &rel);
         h->harvest_now = false;
         h->solver_iters = it;
@@ -831,7 +834,7 @@ int pic_set_grid(pic_handle* h, int32_t which, const void* host) {
     case PIC_G_DEP_E: dst = h->dep[h->dep_cur][0]; break;
     case PIC_G_DEP_I: dst = h->dep[h->dep_cur][1]; break;
     case PIC_G_WALLQ: dst = h->wallq; break;
-    case PIC_G_PHI: dst = h->phi; break;
+    case PIC_G_PHI: dst = h->phi; h->have_prev = false; break;
     case PIC_G_PHI_L: dst = h->phiL; break;
     default: return PIC_E_ARG;
     }
@@ -865,6 +868,7 @@ int pic_solve_once(pic_handle* h, const double* Q, const double* chi, double U_E
     launch_faces(h);
     mg_rebuild(h);
     h->harvest_now = h->harvest_every > 0;
+    h->have_prev = false;
     int rc = field_solve(h, h->phi, h->Q, &h->sc->U_E, tol, h->cfg.solver.method, iters, relres);
     h->harvest_now = false;
     if (hipMemcpy(phi_inout, h->phi, nn * 8, hipMemcpyDeviceToHost) != hipSuccess) return PIC_E_HIP;

@@ -487,13 +487,13 @@ __device__ __forceinline__ T apply9(const Sten& S, const T* x, int n, int i, int
     return acc;
 }
 
+// The multigrid steps of levels >= 1 as grid-stride loops.
 template <typename T>
-__global__ __launch_bounds__(256) void k_jac9(Sten S, const T* xin, const T* b, T* xout, const DevScalars* s, int nr,
-                                              int nz, int first) {
-    if (s->done) return;
+__device__ __forceinline__ void jac9_range(const Sten& S, const T* xin, const T* b, T* xout, int nr, int nz, int first,
+                                           int start, int stride) {
     const int w = nr + 1, nn = w * (nz + 1);
     const T* D = (const T*)S.A[4];
-    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += gridDim.x * blockDim.x) {
+    for (int n = start; n < nn; n += stride) {
         const T d0 = D[n];
         if (d0 == T(0)) { xout[n] = T(0); continue; }
         if (first) { xout[n] = (T)kOmega * b[n] / d0; continue; }
@@ -504,12 +504,11 @@ __global__ __launch_bounds__(256) void k_jac9(Sten S, const T* xin, const T* b, 
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_res9(Sten S, const T* x, const T* b, T* res, const DevScalars* s, int nr,
-                                              int nz) {
-    if (s->done) return;
+__device__ __forceinline__ void res9_range(const Sten& S, const T* x, const T* b, T* res, int nr, int nz, int start,
+                                           int stride) {
     const int w = nr + 1, nn = w * (nz + 1);
     const T* D = (const T*)S.A[4];
-    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += gridDim.x * blockDim.x) {
+    for (int n = start; n < nn; n += stride) {
         if (D[n] == T(0)) { res[n] = T(0); continue; }
         T d;
         res[n] = b[n] - apply9(S, x, n, n % w, n / w, nr, nz, w, d);
@@ -526,12 +525,10 @@ __device__ __forceinline__ float pw1(int i, int I, int c) {
 // the diagonal (coarser levels); coarse nodes inactive when their diagonal
 // is zero
 template <typename T>
-__global__ __launch_bounds__(256) void k_restrict(const T* res, const int8_t* nk, const T* Df, int fnr, int fnz,
-                                                  T* bc, const T* Dc, int cnr, int cnz, int cr, int cz,
-                                                  const DevScalars* s) {
-    if (s->done) return;
+__device__ __forceinline__ void restrict_range(const T* res, const int8_t* nk, const T* Df, int fnr, int fnz, T* bc,
+                                               const T* Dc, int cnr, int cnz, int cr, int cz, int start, int stride) {
     const int fw = fnr + 1, cw = cnr + 1, cn = cw * (cnz + 1);
-    for (int N = blockIdx.x * blockDim.x + threadIdx.x; N < cn; N += gridDim.x * blockDim.x) {
+    for (int N = start; N < cn; N += stride) {
         if (Dc[N] == T(0)) { bc[N] = T(0); continue; }
         const int I = N % cw, J = N / cw;
         T acc = T(0);
@@ -551,11 +548,10 @@ __global__ __launch_bounds__(256) void k_restrict(const T* res, const int8_t* nk
 
 // y_f += P y_c on active fine nodes
 template <typename T>
-__global__ __launch_bounds__(256) void k_prolong(T* yf, const int8_t* nk, const T* Df, int fnr, int fnz, const T* yc,
-                                                 const T* Dc, int cnr, int cnz, int cr, int cz, const DevScalars* s) {
-    if (s->done) return;
+__device__ __forceinline__ void prolong_range(T* yf, const int8_t* nk, const T* Df, int fnr, int fnz, const T* yc,
+                                              const T* Dc, int cnr, int cnz, int cr, int cz, int start, int stride) {
     const int fw = fnr + 1, cw = cnr + 1, fn = fw * (fnz + 1);
-    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < fn; n += gridDim.x * blockDim.x) {
+    for (int n = start; n < fn; n += stride) {
         const bool act = nk ? (nk[n] < 0) : (Df[n] != T(0));
         if (!act) continue;
         const int i = n % fw, j = n / fw;
@@ -575,12 +571,11 @@ __global__ __launch_bounds__(256) void k_prolong(T* yf, const int8_t* nk, const 
     }
 }
 
-// coarsest level: y = A^-1 b with the precomputed dense inverse
+// coarsest level: y = A^-1 b with the precomputed dense inverse; one block
+// (sb: kMaxCoarse entries of shared memory)
 template <typename T>
-__global__ __launch_bounds__(256) void k_coarse(const T* b, T* y, const int* cmap, const int* clist, const T* inv,
-                                                int nc, int cn, const DevScalars* s) {
-    __shared__ T sb[kMaxCoarse];
-    if (s->done) return;
+__device__ __forceinline__ void coarse_block(const T* b, T* y, const int* cmap, const int* clist, const T* inv, int nc,
+                                             int cn, T* sb) {
     for (int k = threadIdx.x; k < nc; k += blockDim.x) sb[k] = b[clist[k]];
     for (int n = threadIdx.x; n < cn; n += blockDim.x)
         if (cmap[n] < 0) y[n] = T(0);
@@ -590,6 +585,45 @@ __global__ __launch_bounds__(256) void k_coarse(const T* b, T* y, const int* cma
         for (int c = 0; c < nc; ++c) acc += inv[r * nc + c] * sb[c];
         y[clist[r]] = acc;
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_jac9(Sten S, const T* xin, const T* b, T* xout, const DevScalars* s, int nr,
+                                              int nz, int first) {
+    if (s->done) return;
+    jac9_range(S, xin, b, xout, nr, nz, first, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_res9(Sten S, const T* x, const T* b, T* res, const DevScalars* s, int nr,
+                                              int nz) {
+    if (s->done) return;
+    res9_range(S, x, b, res, nr, nz, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_restrict(const T* res, const int8_t* nk, const T* Df, int fnr, int fnz,
+                                                  T* bc, const T* Dc, int cnr, int cnz, int cr, int cz,
+                                                  const DevScalars* s) {
+    if (s->done) return;
+    restrict_range(res, nk, Df, fnr, fnz, bc, Dc, cnr, cnz, cr, cz, blockIdx.x * blockDim.x + threadIdx.x,
+                   gridDim.x * blockDim.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_prolong(T* yf, const int8_t* nk, const T* Df, int fnr, int fnz, const T* yc,
+                                                 const T* Dc, int cnr, int cnz, int cr, int cz, const DevScalars* s) {
+    if (s->done) return;
+    prolong_range(yf, nk, Df, fnr, fnz, yc, Dc, cnr, cnz, cr, cz, blockIdx.x * blockDim.x + threadIdx.x,
+                  gridDim.x * blockDim.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_coarse(const T* b, T* y, const int* cmap, const int* clist, const T* inv,
+                                                int nc, int cn, const DevScalars* s) {
+    __shared__ T sb[kMaxCoarse];
+    if (s->done) return;
+    coarse_block(b, y, cmap, clist, inv, nc, cn, sb);
 }
 
 // ------------------------------------------------- multigrid construction
@@ -769,7 +803,7 @@ struct VecSet<float> {
     static const float* cinv(pic_handle* h) { return h->cinv32; }
 };
 
-static inline dim3 grid_for(int n) { return dim3(std::min(1024, (n + 255) / 256)); }
+static inline dim3 grid_for(int n) { return dim3(std::min(8192, (n + 255) / 256)); }
 
 // symmetric V(2,2) cycle: on level l, y = M_l b (b in the level's b buffer;
 // level 0 takes b0 and writes y0)
@@ -1036,6 +1070,24 @@ __global__ __launch_bounds__(256) void k_add_phi(double* phi, const T* x, const 
     const double f = scaled ? (1.0 / s->scale) / kEps0 : 1.0;
     for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += gridDim.x * blockDim.x)
         if (nk[n] < 0) phi[n] += f * (double)x[n];
+}
+
+// initial guess of the next solve: phi <- 2 phi - phi_prev (linear
+// extrapolation in time) on unknown nodes, phi_prev <- the previous phi;
+// without history only the copy is made
+__global__ __launch_bounds__(256) void k_extrapolate(double* phi, double* prev, const int8_t* nk, int nn, int have) {
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += gridDim.x * blockDim.x) {
+        if (nk[n] >= 0) continue;
+        const double t = phi[n];
+        if (have) phi[n] = 2.0 * t - prev[n];
+        prev[n] = t;
+    }
+}
+
+void launch_extrapolate(pic_handle* h) {
+    hipLaunchKernelGGL(k_extrapolate, grid_for(h->nn), dim3(256), 0, h->stream, h->phi, h->phi_prev,
+                       (const int8_t*)h->node_kind, h->nn, h->have_prev ? 1 : 0);
+    h->have_prev = true;
 }
 
 __global__ __launch_bounds__(256) void k_set_dirichlet(double* phi, const int8_t* nk, const double* Up, int nn) {

@@ -14,6 +14,7 @@ constexpr int kHalo = 16;                     // cells of halo around a 16x16-ce
 constexpr int kWin = kTile + 2 * kHalo + 1;   // LDS window nodes per side
 constexpr int kSlice = kChunk / kWaves;       // consecutive slots owned by one wavefront
 constexpr int kRounds = kSlice / 64;
+static_assert(kSlice % 256 == 0 && kRounds % 4 == 0, "decision words are shared by four aligned rounds");
 constexpr int kQW = 128;                      // deferred colliders per wavefront
 
 struct PushArgs {
@@ -39,7 +40,12 @@ __device__ __forceinline__ unsigned long long lanemask_lt() {
 // landing point into the dielectric surface-charge grid (the share on
 // conductor nodes goes to that conductor).  Returns true if removed.
 __device__ __forceinline__ bool absorb(const Geo& g, const Loc& L, float w, int sign,
-                                       unsigned long long* s_abs, unsigned long long* wallq) {
+                                       unsigned long long* s_abs, unsigned long long* wallq, bool vac, int wi0,
+                                       int wj0) {
+    // vac: every domain cell of the chunk's window is vacuum, so a particle
+    // inside the domain and the window needs no cell lookup
+    if (L.inside && vac && (unsigned)(L.i - wi0) < (unsigned)(kWin - 1) && (unsigned)(L.j - wj0) < (unsigned)(kWin - 1))
+        return false;
     if (L.inside && g.cell_kind[L.j * g.nr + L.i] == 0) return false;
     if (!L.inside) {
         int bc = g.edge_bc[L.edge];
@@ -94,17 +100,30 @@ __device__ __forceinline__ unsigned int deposit(const Geo& g, const Loc& L, floa
     return 1u;
 }
 
-__device__ __forceinline__ P9 load9(float* const* f, long long p) {
+// SoA access by a 32-bit byte offset from the (uniform) array base, so one
+// offset register serves all nine arrays (slots < 2^30, checked at init)
+__device__ __forceinline__ float ldf(const float* base, uint32_t boff) {
+    return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + boff);
+}
+__device__ __forceinline__ void stf(float* base, uint32_t boff, float v) {
+    *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + boff) = v;
+}
+
+__device__ __forceinline__ P9 load9(float* const* f, uint32_t p) {
+    const uint32_t o = p << 2;
     P9 s;
-    s.r = f[0][p]; s.z = f[1][p]; s.vr = f[2][p]; s.vt = f[3][p]; s.vz = f[4][p];
-    s.ar = f[5][p]; s.at = f[6][p]; s.az = f[7][p]; s.w = f[8][p];
+    s.r = ldf(f[0], o); s.z = ldf(f[1], o); s.vr = ldf(f[2], o); s.vt = ldf(f[3], o); s.vz = ldf(f[4], o);
+    s.ar = ldf(f[5], o); s.at = ldf(f[6], o); s.az = ldf(f[7], o); s.w = ldf(f[8], o);
     return s;
 }
 
-__device__ __forceinline__ void store8(float* const* f, long long p, const P9& s) {
-    f[0][p] = s.r; f[1][p] = s.z; f[2][p] = s.vr; f[3][p] = s.vt; f[4][p] = s.vz;
-    f[5][p] = s.ar; f[6][p] = s.at; f[7][p] = s.az;
+__device__ __forceinline__ void store8(float* const* f, uint32_t p, const P9& s) {
+    const uint32_t o = p << 2;
+    stf(f[0], o, s.r); stf(f[1], o, s.z); stf(f[2], o, s.vr); stf(f[3], o, s.vt); stf(f[4], o, s.vz);
+    stf(f[5], o, s.ar); stf(f[6], o, s.at); stf(f[7], o, s.az);
 }
+
+__device__ __forceinline__ void kill(float* const* f, uint32_t p) { stf(f[0], p << 2, -1.0f); }
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -113,7 +132,7 @@ __device__ __forceinline__ void wave_sync() {
 
 __device__ __forceinline__ void load9_guard(float* const* f, long long p, long long n, P9& s) {
     if (p < n) {
-        s = load9(f, p);
+        s = load9(f, (uint32_t)p);
     } else {
         s.r = -1.0f;
     }
@@ -130,7 +149,6 @@ __device__ __forceinline__ void load9_guard(float* const* f, long long p, long l
 // tile of the chunk's first particle plus halo) flushed once per chunk.
 __global__ __launch_bounds__(kBlock) void k_particles(PushArgs a) {
     __shared__ unsigned long long win[kWin * kWin];
-    __shared__ float qst[kWaves][9][kQW];
     __shared__ unsigned int qslot[kWaves][kQW];
     __shared__ int s_org[2];
     __shared__ unsigned long long s_abs[4];
@@ -173,17 +191,25 @@ __global__ __launch_bounds__(kBlock) void k_particles(PushArgs a) {
         }
         __syncthreads();
         const int wi0 = s_org[0], wj0 = s_org[1];
+        // are all domain cells of the window vacuum?
+        bool cells_ok = true;
+        for (int k = tid; k < (kWin - 1) * (kWin - 1); k += kBlock) {
+            const int ci = wi0 + k % (kWin - 1), cj = wj0 + k / (kWin - 1);
+            if (ci >= 0 && ci < g.nr && cj >= 0 && cj < g.nz && g.cell_kind[cj * g.nr + ci] != 0) cells_ok = false;
+        }
+        const bool vac = __syncthreads_and(cells_ok) != 0;
 
         const long long sbase = base + (long long)wave * kSlice;
         const long long stage_row = chunk * kWaves + wave;
         int qn = 0, nb = 0;
-        float* qs = &qst[wave][0][0];
         unsigned int* ql = qslot[wave];
         P9 cur, nxt;
         load9_guard(f, sbase + lane, n, cur);
 
         auto run_queue = [&](int cnt) {
-            // lanes < cnt each take one deferred collider, in queue (slot) order
+            // lanes < cnt each take one deferred collider, in queue (slot) order;
+            // its corrected state was stored to its slot when it was queued
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
             const bool has = lane < cnt;
             int proc = -1;
             float b6[6];
@@ -191,9 +217,7 @@ __global__ __launch_bounds__(kBlock) void k_particles(PushArgs a) {
             unsigned int slot = 0;
             if (has) {
                 slot = ql[lane];
-                c.r = qs[0 * kQW + lane]; c.z = qs[1 * kQW + lane]; c.vr = qs[2 * kQW + lane];
-                c.vt = qs[3 * kQW + lane]; c.vz = qs[4 * kQW + lane]; c.ar = qs[5 * kQW + lane];
-                c.at = qs[6 * kQW + lane]; c.az = qs[7 * kQW + lane]; c.w = qs[8 * kQW + lane];
+                c = load9(f, slot);
                 const uint4 x = draw(slot, a.step, kPurposeMcc, a.sp, 0, a.key0, a.key1);
                 proc = collide(a.sp, x, c.vr, c.vt, c.vz, a.m, slot, a.step, a.key0, a.key1, b6, &a.ctr->viol);
                 atomicAdd(&s_coll[proc], 1u);
@@ -215,8 +239,8 @@ __global__ __launch_bounds__(kBlock) void k_particles(PushArgs a) {
             if (has) {
                 d1_predict(c, a.dt);
                 const Loc L2 = locate(c.r, c.z, g);
-                if (absorb(g, L2, c.w, a.sign, s_abs, a.wallq)) {
-                    f[0][slot] = -1.0f;
+                if (absorb(g, L2, c.w, a.sign, s_abs, a.wallq, vac, wi0, wj0)) {
+                    kill(f, slot);
                 } else {
                     fallback += deposit(g, L2, c.w, win, wi0, wj0, a.dep);
                     store8(f, slot, c);
@@ -224,9 +248,14 @@ __global__ __launch_bounds__(kBlock) void k_particles(PushArgs a) {
             }
         };
 
+        uint4 dec4 = make_uint4(0u, 0u, 0u, 0u);
         for (int it = 0; it < kRounds; ++it) {
             const long long p = sbase + (long long)it * 64 + lane;
             if (it + 1 < kRounds) load9_guard(f, p + 64, n, nxt);
+            // decision words of this lane's slots in rounds it .. it+3 (sbase is
+            // a multiple of 256, so the four share one counter)
+            if ((it & 3) == 0) dec4 = draw(decision_ctr((uint32_t)p), a.step, kPurposeDecide, a.sp, 0, a.key0, a.key1);
+            const uint32_t dword = (it & 3) == 0 ? dec4.x : (it & 3) == 1 ? dec4.y : (it & 3) == 2 ? dec4.z : dec4.w;
             P9 s = cur;
             bool coll = false;
             if (s.r >= 0.0f) {
@@ -234,31 +263,29 @@ __global__ __launch_bounds__(kBlock) void k_particles(PushArgs a) {
                 gather_E(a.E, g, s.r, s.z, Er, Ez);
                 d1_correct(s, Er, Ez, a.qm, a.dt);
                 const Loc L = locate(s.r, s.z, g);
-                if (absorb(g, L, s.w, a.sign, s_abs, a.wallq)) {
-                    f[0][p] = -1.0f;
+                if (absorb(g, L, s.w, a.sign, s_abs, a.wallq, vac, wi0, wj0)) {
+                    kill(f, (uint32_t)p);
                 } else {
-                    const uint4 x = draw((uint32_t)p, a.step, kPurposeMcc, a.sp, 0, a.key0, a.key1);
-                    coll = x.x < a.m.thresh;
+                    coll = dword < a.m.thresh;
                     if (!coll) {
                         d1_predict(s, a.dt);
                         const Loc L2 = locate(s.r, s.z, g);
-                        if (absorb(g, L2, s.w, a.sign, s_abs, a.wallq)) {
-                            f[0][p] = -1.0f;
+                        if (absorb(g, L2, s.w, a.sign, s_abs, a.wallq, vac, wi0, wj0)) {
+                            kill(f, (uint32_t)p);
                         } else {
                             fallback += deposit(g, L2, s.w, win, wi0, wj0, a.dep);
-                            store8(f, p, s);
+                            store8(f, (uint32_t)p, s);
                         }
                     }
                 }
             }
-            // ballot compaction of this round's colliders into the queue
+            // ballot compaction of this round's colliders into the queue; the
+            // corrected state waits in the collider's own slot
             const unsigned long long m = __ballot(coll);
             if (coll) {
                 const int q = qn + __popcll(m & lanemask_lt());
                 ql[q] = (unsigned int)p;
-                qs[0 * kQW + q] = s.r; qs[1 * kQW + q] = s.z; qs[2 * kQW + q] = s.vr; qs[3 * kQW + q] = s.vt;
-                qs[4 * kQW + q] = s.vz; qs[5 * kQW + q] = s.ar; qs[6 * kQW + q] = s.at; qs[7 * kQW + q] = s.az;
-                qs[8 * kQW + q] = s.w;
+                store8(f, (uint32_t)p, s);
             }
             qn += __popcll(m);
             wave_sync();
@@ -268,10 +295,7 @@ __global__ __launch_bounds__(kBlock) void k_particles(PushArgs a) {
                 // move the remaining qn - 64 (< 64) entries to the front
                 const int rest = qn - 64;
                 if (lane < rest) {
-                    float t[9];
-                    for (int k = 0; k < 9; ++k) t[k] = qs[k * kQW + 64 + lane];
                     const unsigned int sl = ql[64 + lane];
-                    for (int k = 0; k < 9; ++k) qs[k * kQW + lane] = t[k];
                     ql[lane] = sl;
                 }
                 qn = rest;

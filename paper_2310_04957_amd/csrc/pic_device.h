@@ -108,7 +108,12 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
 // uniform in (0,1), exactly representable: ((x >> 9) + 1/2) 2^-23
 __device__ __forceinline__ float u01(uint32_t x) { return ((float)(x >> 9) + 0.5f) * 0x1p-23f; }
 
-enum { kPurposeLoad = 0, kPurposeMcc = 1 };
+enum { kPurposeLoad = 0, kPurposeMcc = 1, kPurposeDecide = 2 };
+
+// The null-collision decision of slot p comes from word (p >> 6) & 3 of the
+// draw at this counter: one Philox block serves four slots 64 apart, i.e.
+// four consecutive 64-slot rounds of one wavefront.
+__device__ __forceinline__ uint32_t decision_ctr(uint32_t p) { return (p & 63u) | ((p >> 8) << 6); }
 
 __device__ __forceinline__ uint4 draw(uint32_t slot, uint32_t step, uint32_t purpose, int sp, uint32_t k,
                                       uint32_t key0, uint32_t key1) {
@@ -232,7 +237,8 @@ __device__ __forceinline__ void maxwell3(uint4 y, float vth, float& a, float& b,
 }
 
 // Outcome codes: 0 elastic / isotropic, 1 excitation / charge exchange,
-// 2 ionisation, 3 null.  x is the first Philox draw of this particle-step.
+// 2 ionisation, 3 null.  x is the slot's first collision draw of this step
+// (its first word is unused: the decision has its own draw).
 __device__ __forceinline__ int collide(int sp, uint4 x, float& vr, float& vt, float& vz, const Mcc& m,
                                       uint32_t slot, uint32_t step, uint32_t key0, uint32_t key1,
                                       float* born6, unsigned int* viol) {

@@ -21,7 +21,7 @@ constexpr int kStageCap = 256;        // staged ionisation births per chunk
 constexpr int kStageW = kStageCap / kWaves;   // ... per (chunk, wavefront)
 constexpr int kMaxLevels = 16;
 constexpr int kMaxCoarse = 320;       // active nodes of the coarsest multigrid level
-constexpr int kRedBlocks = 1024;      // partial sums of a grid reduction
+constexpr int kRedBlocks = 4096;      // partial sums of a grid reduction
 
 // counters that kernels update; lives in device memory
 struct DevCounters {
@@ -96,6 +96,8 @@ struct pic_handle {
     int dep_cur;
     unsigned long long *wallq, *psum[2], *plast[2];
     double *chi, *Q, *ar, *az, *phi, *phiL, *zeroQ;
+    double* phi_prev;       // the previous step's solution (initial-guess extrapolation)
+    bool have_prev;
     float *ar32, *az32;
     float2* E;
     // solver vectors
@@ -166,6 +168,7 @@ int field_solve(pic_handle* h, double* phi, const double* Q, const double* Uptr,
 int refresh_laplace(pic_handle* h);
 void mg_rebuild(pic_handle* h);
 void launch_efield(pic_handle* h);
+void launch_extrapolate(pic_handle* h);
 void launch_period_roll(pic_handle* h);
 void launch_zero_u64(unsigned long long* p, size_t n, hipStream_t s);
 void launch_zero_f64(double* p, size_t n, hipStream_t s);
