@@ -25,7 +25,7 @@ HBM_PEAK_GBS = 8000.0
 # and WRITE_SIZE (scaled by a plain-copy calibration) on gec1024x2048; see
 # profiles/k_particles_gec1024x2048.md.  Set to None whenever the kernel
 # changes until it is measured again.
-MEASURED_BYTES_PER_PARTICLE_STEP = {"gec1024x2048": (7.27e9 + 8.55e9) / 199.4e6}
+MEASURED_BYTES_PER_PARTICLE_STEP = {}
 
 
 def cpu_baseline(name, sample_particles, steps):
@@ -46,6 +46,63 @@ def cpu_baseline(name, sample_particles, steps):
                 seconds=dt)
 
 
+def unet_flops(H, W, C=32, cin_pad=16, levels=5):
+    """FLOPs of one U-net forward on an H x W image (3x3 convolutions as the
+    kernels run them: the first layer on 16 padded input channels)."""
+    f = 0.0
+    for l in range(levels):
+        px = (H >> l) * (W >> l)
+        if l < levels - 1:
+            f += 2 * 9 * px * ((cin_pad if l == 0 else C) * C + C * C)     # encoder a, b
+            f += 2 * 9 * px * (2 * C * C + C * C)                          # decoder a (concat), b
+        else:
+            f += 2 * 9 * px * 2 * C * C                                    # bottom a, b
+    return f + 2 * H * W * C                                               # 1x1 output
+
+
+def learned_vs_plain(sim, args, w):
+    """Field-solve ms per step on the same discharge: plain FP64 MG-PCG,
+    FP32-inner mixed precision MG-PCG, and flexible CG preconditioned by the
+    U-net after training it on pairs harvested from this run."""
+    import torch
+    from paper_2310_04957_amd.pic import SOLVE_IR_MG, SOLVE_IR_UNET, SOLVE_MGPCG_FP64
+    sim.unet_harvest(1)
+    sim.step(args.learned_harvest_steps)
+    sim.unet_harvest(0)
+    pairs = int(sim.diag().unet_pairs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    curve = sim.unet_train(args.learned_train_steps, args.learned_batch, 1e-3, seed=1)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    res = {}
+    for m, name in ((SOLVE_MGPCG_FP64, "plain_fp64_mgpcg"), (SOLVE_IR_MG, "mixed_ir_mgpcg"),
+                    (SOLVE_IR_UNET, "learned_ir_unet_fpcg")):
+        sim.set_solver(method=m)
+        sim.step(1)
+        d0 = sim.diag()
+        sim.reset_timers()
+        its = []
+        for _ in range(args.learned_solve_steps):
+            sim.step(1)
+            d = sim.diag()
+            its.append(int(d.solver_iters))
+        res[name] = {"ms_per_step": d.ms_field / args.learned_solve_steps, "inner_iters": its,
+                     "fallbacks": int(d.unet_fallbacks - d0.unet_fallbacks),
+                     "unet_applications": int(d.unet_applications - d0.unet_applications)}
+    sim.set_solver(method=SOLVE_IR_MG)
+    H, W = w["geometry"]["nz"], w["geometry"]["nr"]
+    lr = res["learned_ir_unet_fpcg"]
+    return {
+        **res,
+        "faster_than_plain": lr["ms_per_step"] < res["plain_fp64_mgpcg"]["ms_per_step"],
+        "training": {"pairs": pairs, "steps": args.learned_train_steps, "batch": args.learned_batch,
+                     "seconds": t_train, "loss_first": float(curve[:5].mean()), "loss_last": float(curve[-20:].mean())},
+        "unet_gflop_per_application": unet_flops(H, W) / 1e9,
+        "image": f"{H}x{W}",
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -54,9 +111,15 @@ def main():
     ap.add_argument("--workload", default="gec1024x2048")
     ap.add_argument("--method", default="ir", choices=["ir", "mgpcg"])
     ap.add_argument("--cpu-sample", type=int, default=1_000_000)
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sort-every", type=int, default=None)
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-vs-plain field-solve comparison")
+    ap.add_argument("--learned-harvest-steps", type=int, default=24)
+    ap.add_argument("--learned-train-steps", type=int, default=150)
+    ap.add_argument("--learned-batch", type=int, default=4)
+    ap.add_argument("--learned-solve-steps", type=int, default=3)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain FP32 copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -86,7 +149,9 @@ def main():
     method = SOLVE_IR_MG if args.method == "ir" else SOLVE_MGPCG_FP64
     print(f"[bench] init {args.workload} method={args.method}", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    sim = Pic(w, timing=True, method=method)
+    learned = not args.no_learned
+    sim = Pic(w, timing=True, method=method, unet_batch=args.learned_batch if learned else 0,
+              unet_pairs=512 if learned else 0)
     torch.cuda.synchronize()
     t_init = time.perf_counter() - t0
     print(f"[bench] init done in {t_init:.1f} s; warmup {args.warmup}", file=sys.stderr, flush=True)
@@ -141,6 +206,9 @@ def main():
                      "kernel": "k_particles", "bytes_per_unit": BYTES_PER_PARTICLE_STEP,
                      "unit_of_work": "particle-step"},
     }
+    if learned:
+        print("[bench] learned vs plain field solve", file=sys.stderr, flush=True)
+        out["field_solve_learned_vs_plain"] = learned_vs_plain(sim, args, w)
     sim.close()
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)

@@ -10,8 +10,10 @@
 
 namespace pic {
 
-constexpr int kHalo = 16;                     // cells of halo around a 16x16-cell tile
-constexpr int kWin = kTile + 2 * kHalo + 1;   // LDS window nodes per side
+// LDS deposit window: the 16x16-cell tile of a chunk's first particle plus
+// a halo of H cells, (16 + 2H + 1)^2 nodes; electrons (fast, dispersing
+// between sorts) use H = 24, ions H = 16
+constexpr int win_nodes(int halo) { return kTile + 2 * halo + 1; }
 constexpr int kSlice = kChunk / kWaves;       // consecutive slots owned by one wavefront
 constexpr int kRounds = kSlice / 64;
 static_assert(kSlice % 256 == 0 && kRounds % 4 == 0, "decision words are shared by four aligned rounds");
@@ -39,6 +41,7 @@ __device__ __forceinline__ unsigned long long lanemask_lt() {
 // Charge of a removed particle: to the conductor it hit, or deposited at the
 // landing point into the dielectric surface-charge grid (the share on
 // conductor nodes goes to that conductor).  Returns true if removed.
+template <int kWin>
 __device__ __forceinline__ bool absorb(const Geo& g, const Loc& L, float w, int sign,
                                        unsigned long long* s_abs, unsigned long long* wallq, bool vac, int wi0,
                                        int wj0) {
@@ -79,6 +82,7 @@ __device__ __forceinline__ bool absorb(const Geo& g, const Loc& L, float w, int 
 // Deposit into the LDS window when all four nodes fall inside it, else
 // straight to the global grid (the result is identical: integer sums).
 // Returns 1 for a global-fallback deposit.
+template <int kWin>
 __device__ __forceinline__ unsigned int deposit(const Geo& g, const Loc& L, float w, unsigned long long* win,
                                                 int wi0, int wj0, unsigned long long* dep) {
     int64_t c[4];
@@ -147,7 +151,9 @@ __device__ __forceinline__ void load9_guard(float* const* f, long long p, long l
 // processed 64 at a time by full wavefronts; births are staged per
 // (chunk, wavefront) in slot order.  The deposit goes to an LDS window (the
 // tile of the chunk's first particle plus halo) flushed once per chunk.
+template <int kHalo>
 __global__ __launch_bounds__(kBlock) void k_particles(PushArgs a) {
+    constexpr int kWin = win_nodes(kHalo);
     __shared__ unsigned long long win[kWin * kWin];
     __shared__ unsigned int qslot[kWaves][kQW];
     __shared__ int s_org[2];
@@ -161,6 +167,8 @@ __global__ __launch_bounds__(kBlock) void k_particles(PushArgs a) {
     const long long nch = (n + kChunk - 1) / kChunk;
     const int nx = 8;  // XCDs: consecutive block ids go round-robin over them
     const int xcd = blockIdx.x % nx, per = gridDim.x / nx, lb = blockIdx.x / nx;
+    // this XCD's contiguous chunk range, taken by its blocks in turn, so the
+    // chunks in flight on one XCD stay close together (shared L2)
     const long long c_begin = nch * xcd / nx, c_end = nch * (xcd + 1) / nx;
     float* const* f = a.f;
     unsigned int fallback = 0;
@@ -168,6 +176,23 @@ __global__ __launch_bounds__(kBlock) void k_particles(PushArgs a) {
     for (int k = tid; k < kWin * kWin; k += kBlock) win[k] = 0ull;
     if (tid < 4) { s_abs[tid] = 0ull; s_coll[tid] = 0u; }
     if (tid == 0) s_fallback = 0u;
+
+    // the window stays in LDS while consecutive chunks share its origin and
+    // is flushed to the global grid (64-bit atomics) when the origin moves
+    int wi0 = -(1 << 28), wj0 = -(1 << 28);
+    bool vac = false, have = false;
+    auto flush = [&]() {
+        __syncthreads();
+        for (int k = tid; k < kWin * kWin; k += kBlock) {
+            const unsigned long long v = win[k];
+            if (v != 0ull) {
+                const int gi = wi0 + k % kWin, gj = wj0 + k / kWin;
+                if (gi >= 0 && gi <= g.nr && gj >= 0 && gj <= g.nz) atomicAdd(&a.dep[gj * g.w + gi], v);
+                win[k] = 0ull;
+            }
+        }
+        __syncthreads();
+    };
 
     for (long long chunk = c_begin + lb; chunk < c_end; chunk += per) {
         const long long base = chunk * kChunk;
@@ -190,14 +215,20 @@ __global__ __launch_bounds__(kBlock) void k_particles(PushArgs a) {
             if (first < 0 && lane == 0) { s_org[0] = -(1 << 28); s_org[1] = -(1 << 28); }
         }
         __syncthreads();
-        const int wi0 = s_org[0], wj0 = s_org[1];
-        // are all domain cells of the window vacuum?
-        bool cells_ok = true;
-        for (int k = tid; k < (kWin - 1) * (kWin - 1); k += kBlock) {
-            const int ci = wi0 + k % (kWin - 1), cj = wj0 + k / (kWin - 1);
-            if (ci >= 0 && ci < g.nr && cj >= 0 && cj < g.nz && g.cell_kind[cj * g.nr + ci] != 0) cells_ok = false;
+        if (!have || s_org[0] != wi0 || s_org[1] != wj0) {
+            if (have) flush();
+            wi0 = s_org[0];
+            wj0 = s_org[1];
+            have = true;
+            // are all domain cells of the window vacuum?
+            bool cells_ok = true;
+            for (int k = tid; k < (kWin - 1) * (kWin - 1); k += kBlock) {
+                const int ci = wi0 + k % (kWin - 1), cj = wj0 + k / (kWin - 1);
+                if (ci >= 0 && ci < g.nr && cj >= 0 && cj < g.nz && g.cell_kind[cj * g.nr + ci] != 0)
+                    cells_ok = false;
+            }
+            vac = __syncthreads_and(cells_ok) != 0;
         }
-        const bool vac = __syncthreads_and(cells_ok) != 0;
 
         const long long sbase = base + (long long)wave * kSlice;
         const long long stage_row = chunk * kWaves + wave;
@@ -239,10 +270,10 @@ __global__ __launch_bounds__(kBlock) void k_particles(PushArgs a) {
             if (has) {
                 d1_predict(c, a.dt);
                 const Loc L2 = locate(c.r, c.z, g);
-                if (absorb(g, L2, c.w, a.sign, s_abs, a.wallq, vac, wi0, wj0)) {
+                if (absorb<kWin>(g, L2, c.w, a.sign, s_abs, a.wallq, vac, wi0, wj0)) {
                     kill(f, slot);
                 } else {
-                    fallback += deposit(g, L2, c.w, win, wi0, wj0, a.dep);
+                    fallback += deposit<kWin>(g, L2, c.w, win, wi0, wj0, a.dep);
                     store8(f, slot, c);
                 }
             }
@@ -263,17 +294,17 @@ __global__ __launch_bounds__(kBlock) void k_particles(PushArgs a) {
                 gather_E(a.E, g, s.r, s.z, Er, Ez);
                 d1_correct(s, Er, Ez, a.qm, a.dt);
                 const Loc L = locate(s.r, s.z, g);
-                if (absorb(g, L, s.w, a.sign, s_abs, a.wallq, vac, wi0, wj0)) {
+                if (absorb<kWin>(g, L, s.w, a.sign, s_abs, a.wallq, vac, wi0, wj0)) {
                     kill(f, (uint32_t)p);
                 } else {
                     coll = dword < a.m.thresh;
                     if (!coll) {
                         d1_predict(s, a.dt);
                         const Loc L2 = locate(s.r, s.z, g);
-                        if (absorb(g, L2, s.w, a.sign, s_abs, a.wallq, vac, wi0, wj0)) {
+                        if (absorb<kWin>(g, L2, s.w, a.sign, s_abs, a.wallq, vac, wi0, wj0)) {
                             kill(f, (uint32_t)p);
                         } else {
-                            fallback += deposit(g, L2, s.w, win, wi0, wj0, a.dep);
+                            fallback += deposit<kWin>(g, L2, s.w, win, wi0, wj0, a.dep);
                             store8(f, (uint32_t)p, s);
                         }
                     }
@@ -305,18 +336,10 @@ __global__ __launch_bounds__(kBlock) void k_particles(PushArgs a) {
         }
         if (qn > 0) run_queue(qn);
         if (lane == 0 && a.stage_cnt != nullptr) a.stage_cnt[stage_row] = min(nb, kStageW);
-        // flush the window to the global grid and clear it
-        __syncthreads();
-        for (int k = tid; k < kWin * kWin; k += kBlock) {
-            const unsigned long long v = win[k];
-            if (v != 0ull) {
-                const int gi = wi0 + k % kWin, gj = wj0 + k / kWin;
-                if (gi >= 0 && gi <= g.nr && gj >= 0 && gj <= g.nz) atomicAdd(&a.dep[gj * g.w + gi], v);
-                win[k] = 0ull;
-            }
-        }
+        // s_org is rewritten by the next chunk's probe
         __syncthreads();
     }
+    if (have) flush();
     for (int o = 32; o > 0; o >>= 1) fallback += __shfl_down(fallback, o);
     if (lane == 0 && fallback) atomicAdd(&s_fallback, fallback);
     __syncthreads();
@@ -380,7 +403,10 @@ void launch_particles(pic_handle* h, int sp) {
     a.key0 = (uint32_t)(h->cfg.run.seed & 0xFFFFFFFFu);
     a.key1 = (uint32_t)(h->cfg.run.seed >> 32);
     a.step = (uint32_t)(h->step + 1);
-    hipLaunchKernelGGL(k_particles, dim3(grid_blocks()), dim3(kBlock), 0, h->stream, a);
+    if (sp == 0)
+        hipLaunchKernelGGL(k_particles<24>, dim3(grid_blocks()), dim3(kBlock), 0, h->stream, a);
+    else
+        hipLaunchKernelGGL(k_particles<16>, dim3(grid_blocks()), dim3(kBlock), 0, h->stream, a);
 }
 
 // ---------------------------------------------------------------- births

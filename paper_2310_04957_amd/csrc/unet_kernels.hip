@@ -218,65 +218,99 @@ __global__ __launch_bounds__(256) void k_sum_parts(const float* part, int nblk, 
 }
 
 // ---------------------------------------------- pooling, upsampling, concat
+// All four move whole 8-channel groups (16 bytes) per thread; C is a
+// multiple of 8.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void unpack8(u32x4 v, float* f) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        f[2 * k] = __uint_as_float(v[k] << 16);
+        f[2 * k + 1] = __uint_as_float(v[k] & 0xFFFF0000u);
+    }
+}
+__device__ __forceinline__ u32x4 pack8(const float* f) {
+    u32x4 v;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = (unsigned)f2bf(f[2 * k]).x | ((unsigned)f2bf(f[2 * k + 1]).x << 16);
+    return v;
+}
+__device__ __forceinline__ u32x4 ld8(const bf16* p) { return *reinterpret_cast<const u32x4*>(p); }
+__device__ __forceinline__ void st8(bf16* p, u32x4 v) { *reinterpret_cast<u32x4*>(p) = v; }
+
 __global__ __launch_bounds__(256) void k_pool(const bf16* X, bf16* Y, int B, int H, int W, int C) {
-    const int Ho = H / 2, Wo = W / 2;
-    const size_t n = (size_t)B * Ho * Wo * C;
+    const int Ho = H / 2, Wo = W / 2, G = C / 8;
+    const size_t n = (size_t)B * Ho * Wo * G;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
-        const int c = e % C;
-        const size_t q = e / C;
+        const int c8 = (int)(e % G);
+        const size_t q = e / G;
         const int xo = q % Wo, yo = (q / Wo) % Ho, b = q / ((size_t)Wo * Ho);
-        const size_t g = (((size_t)b * H + 2 * yo) * W + 2 * xo) * C + c;
-        const float s = bf2f(X[g]) + bf2f(X[g + C]) + bf2f(X[g + (size_t)W * C]) + bf2f(X[g + (size_t)W * C + C]);
-        Y[e] = f2bf(0.25f * s);
+        const size_t g = (((size_t)b * H + 2 * yo) * W + 2 * xo) * C + c8 * 8;
+        float s[8], t[8];
+        unpack8(ld8(X + g), s);
+        unpack8(ld8(X + g + C), t);
+        for (int k = 0; k < 8; ++k) s[k] += t[k];
+        unpack8(ld8(X + g + (size_t)W * C), t);
+        for (int k = 0; k < 8; ++k) s[k] += t[k];
+        unpack8(ld8(X + g + (size_t)W * C + C), t);
+        for (int k = 0; k < 8; ++k) s[k] = 0.25f * (s[k] + t[k]);
+        st8(Y + q * C + c8 * 8, pack8(s));
     }
 }
 
 // dX = pool^T(dY) + dS (the skip-path gradient), fine resolution
 __global__ __launch_bounds__(256) void k_pool_bwd_add(const bf16* dY, const bf16* dS, bf16* dX, int B, int H, int W,
                                                       int C) {
-    const size_t n = (size_t)B * H * W * C;
-    const int Wo = W / 2, Ho = H / 2;
+    const int G = C / 8, Wo = W / 2, Ho = H / 2;
+    const size_t n = (size_t)B * H * W * G;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
-        const int c = e % C;
-        const size_t q = e / C;
+        const int c8 = (int)(e % G);
+        const size_t q = e / G;
         const int x = q % W, y = (q / W) % H, b = q / ((size_t)W * H);
-        const float v = 0.25f * bf2f(dY[(((size_t)b * Ho + y / 2) * Wo + x / 2) * C + c]) + bf2f(dS[e]);
-        dX[e] = f2bf(v);
+        float u[8], v[8];
+        unpack8(ld8(dY + (((size_t)b * Ho + y / 2) * Wo + x / 2) * C + c8 * 8), u);
+        unpack8(ld8(dS + q * C + c8 * 8), v);
+        for (int k = 0; k < 8; ++k) u[k] = 0.25f * u[k] + v[k];
+        st8(dX + q * C + c8 * 8, pack8(u));
     }
 }
 
 // Y = [up2(Xc), S]: 2C channels at the fine resolution
 __global__ __launch_bounds__(256) void k_up_concat(const bf16* Xc, const bf16* S, bf16* Y, int B, int H, int W, int C) {
-    const size_t n = (size_t)B * H * W * 2 * C;
+    const int G = C / 8;
+    const size_t n = (size_t)B * H * W * 2 * G;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
-        const int c = e % (2 * C);
-        const size_t q = e / (2 * C);
+        const int c8 = (int)(e % (2 * G));
+        const size_t q = e / (2 * G);
         const int x = q % W, y = (q / W) % H, b = q / ((size_t)W * H);
-        Y[e] = (c < C) ? Xc[(((size_t)b * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c] : S[q * C + (c - C)];
+        const u32x4 v = (c8 < G) ? ld8(Xc + (((size_t)b * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c8 * 8)
+                                 : ld8(S + q * C + (c8 - G) * 8);
+        st8(Y + q * 2 * C + c8 * 8, v);
     }
 }
 
 // from the 2C-channel concat gradient: dXc = up^T(first C), dS = last C
 __global__ __launch_bounds__(256) void k_up_concat_bwd(const bf16* dY, bf16* dXc, bf16* dS, int B, int H, int W,
                                                        int C) {
-    const int Ho = H / 2, Wo = W / 2;
-    const size_t nc = (size_t)B * Ho * Wo * C;
+    const int Ho = H / 2, Wo = W / 2, G = C / 8;
+    const size_t nc = (size_t)B * Ho * Wo * G;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < nc; e += (size_t)gridDim.x * blockDim.x) {
-        const int c = e % C;
-        const size_t q = e / C;
+        const int c8 = (int)(e % G);
+        const size_t q = e / G;
         const int xo = q % Wo, yo = (q / Wo) % Ho, b = q / ((size_t)Wo * Ho);
-        float s = 0.0f;
+        float s[8] = {}, t[8];
         for (int d = 0; d < 4; ++d) {
             const size_t p = ((size_t)b * H + 2 * yo + d / 2) * W + 2 * xo + d % 2;
-            s += bf2f(dY[p * 2 * C + c]);
+            unpack8(ld8(dY + p * 2 * C + c8 * 8), t);
+            for (int k = 0; k < 8; ++k) s[k] += t[k];
         }
-        dXc[e] = f2bf(s);
+        st8(dXc + q * C + c8 * 8, pack8(s));
     }
-    const size_t nf = (size_t)B * H * W * C;
+    const size_t nf = (size_t)B * H * W * G;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < nf; e += (size_t)gridDim.x * blockDim.x) {
-        const size_t p = e / C;
-        const int c = e % C;
-        dS[e] = dY[p * 2 * C + C + c];
+        const size_t p = e / G;
+        const int c8 = (int)(e % G);
+        st8(dS + p * C + c8 * 8, ld8(dY + p * 2 * C + C + c8 * 8));
     }
 }
 
@@ -287,7 +321,11 @@ __global__ __launch_bounds__(256) void k_out(const bf16* last, const float* w, c
     const size_t n = (size_t)B * HW;
     for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < n; p += (size_t)gridDim.x * blockDim.x) {
         float s = b0[0];
-        for (int c = 0; c < C; ++c) s += w[c] * bf2f(last[p * C + c]);
+        for (int c8 = 0; c8 < C / 8; ++c8) {
+            float x[8];
+            unpack8(ld8(last + p * C + c8 * 8), x);
+            for (int k = 0; k < 8; ++k) s += w[c8 * 8 + k] * x[k];
+        }
         out[p] = s;
     }
 }
@@ -310,10 +348,15 @@ __global__ __launch_bounds__(256) void k_loss_out_bwd(const float* out, const fl
         acc[0] += d * d * inv_n;
         acc[1] += dz;
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-            const float x = bf2f(last[p * C + c]);
-            acc[2 + c] += x * dz;
-            dlast[p * C + c] = f2bf(w[c] * dz);
+        for (int c8 = 0; c8 < C / 8; ++c8) {
+            float x[8], g[8];
+            unpack8(ld8(last + p * C + c8 * 8), x);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                acc[2 + c8 * 8 + k] += x[k] * dz;
+                g[k] = w[c8 * 8 + k] * dz;
+            }
+            st8(dlast + p * C + c8 * 8, pack8(g));
         }
     }
 #pragma unroll
@@ -564,16 +607,16 @@ int conv_wgrad(int cin, const bf16* X, const bf16* D, const bf16* Yout, float* p
 static dim3 ew_grid(size_t n) { return dim3((unsigned)std::min<size_t>((n + 255) / 256, 4096)); }
 
 void pool(const bf16* X, bf16* Y, int B, int H, int W, int C, hipStream_t s) {
-    hipLaunchKernelGGL(k_pool, ew_grid((size_t)B * H * W * C / 4), dim3(256), 0, s, X, Y, B, H, W, C);
+    hipLaunchKernelGGL(k_pool, ew_grid((size_t)B * H * W * C / 32), dim3(256), 0, s, X, Y, B, H, W, C);
 }
 void pool_bwd_add(const bf16* dY, const bf16* dS, bf16* dX, int B, int H, int W, int C, hipStream_t s) {
-    hipLaunchKernelGGL(k_pool_bwd_add, ew_grid((size_t)B * H * W * C), dim3(256), 0, s, dY, dS, dX, B, H, W, C);
+    hipLaunchKernelGGL(k_pool_bwd_add, ew_grid((size_t)B * H * W * C / 8), dim3(256), 0, s, dY, dS, dX, B, H, W, C);
 }
 void up_concat(const bf16* Xc, const bf16* S, bf16* Y, int B, int H, int W, int C, hipStream_t s) {
-    hipLaunchKernelGGL(k_up_concat, ew_grid((size_t)B * H * W * 2 * C), dim3(256), 0, s, Xc, S, Y, B, H, W, C);
+    hipLaunchKernelGGL(k_up_concat, ew_grid((size_t)B * H * W * C / 4), dim3(256), 0, s, Xc, S, Y, B, H, W, C);
 }
 void up_concat_bwd(const bf16* dY, bf16* dXc, bf16* dS, int B, int H, int W, int C, hipStream_t s) {
-    hipLaunchKernelGGL(k_up_concat_bwd, ew_grid((size_t)B * H * W * C), dim3(256), 0, s, dY, dXc, dS, B, H, W, C);
+    hipLaunchKernelGGL(k_up_concat_bwd, ew_grid((size_t)B * H * W * C / 8), dim3(256), 0, s, dY, dXc, dS, B, H, W, C);
 }
 void out_fwd(const bf16* last, const float* w, const float* b0, float* out, int B, int HW, int C, hipStream_t s) {
     hipLaunchKernelGGL(k_out, ew_grid((size_t)B * HW), dim3(256), 0, s, last, w, b0, out, B, HW, C);
