@@ -313,6 +313,7 @@ size_t layout(pic_handle* h, char* base) {
         h->keys[b] = c.take<uint32_t>(capmax);
         h->idx[b] = c.take<uint32_t>(capmax);
     }
+    for (int sp = 0; sp < 2; ++sp) h->perm[sp] = c.take<uint32_t>((size_t)std::max<int64_t>(h->cap[sp], 1));
     const size_t mch = (size_t)h->max_chunks;
     h->hist = c.take<uint32_t>(256 * mch);
     h->bsum = c.take<uint32_t>((256 * mch + 4095) / 4096 + 1);
@@ -630,9 +631,10 @@ int pic_step(pic_handle* h, int32_t nsteps) {
         const bool se = c.run.sort_every > 0 && h->step % c.run.sort_every == 0;
         const bool si = c.run.sort_every_ion > 0 && h->step % c.run.sort_every_ion == 0;
         if (se || si) {
+            // deferred: the particles move during the next particle step
             ev_record(h, -1, &b3);
-            if (se) launch_sort(h, 0);
-            if (si) launch_sort(h, 1);
+            if (se) launch_sort(h, 0, true);
+            if (si) launch_sort(h, 1, true);
             ev_record(h, 3, &b3);
         }
         if (h->step % spp == 0) {
@@ -661,6 +663,8 @@ int pic_reset_timers(pic_handle* h) {
 
 int pic_diag(pic_handle* h, pic_diag_out* out, const pic_diag_buffers* bufs) {
     if (!h || !out) return PIC_E_ARG;
+    materialize(h, 0);
+    materialize(h, 1);
     int rc = sync_err(h);
     if (rc) return rc;
     ev_collect(h);
@@ -762,6 +766,7 @@ const char* pic_strerror(int code) {
 
 int pic_get_particles(pic_handle* h, int32_t species, float* host9, int64_t* n) {
     if (!h || !host9 || !n || species < 0 || species > 1) return PIC_E_ARG;
+    materialize(h, species);
     int rc = sync_err(h);
     if (rc) return rc;
     const int64_t m = h->h_ctr->n_slots[species];
@@ -776,6 +781,7 @@ int pic_get_particles(pic_handle* h, int32_t species, float* host9, int64_t* n) 
 
 int pic_set_particles(pic_handle* h, int32_t species, const float* host9, int64_t n) {
     if (!h || (!host9 && n > 0) || species < 0 || species > 1 || n < 0 || n > h->cap[species]) return PIC_E_ARG;
+    h->pending[species] = false;   // the new particles replace the old, sorted or not
     if (hipStreamSynchronize(h->stream) != hipSuccess) return PIC_E_HIP;
     for (int k = 0; k < 9; ++k)
         if (n > 0 && hipMemcpy(h->buf[species][h->cur[species]].f[k], host9 + (size_t)k * n, (size_t)n * 4,
@@ -793,6 +799,8 @@ int pic_set_particles(pic_handle* h, int32_t species, const float* host9, int64_
 
 int pic_redeposit(pic_handle* h) {
     if (!h) return PIC_E_ARG;
+    materialize(h, 0);
+    materialize(h, 1);
     launch_redeposit(h);
     return hipStreamSynchronize(h->stream) == hipSuccess ? PIC_OK : PIC_E_HIP;
 }
@@ -849,7 +857,7 @@ int pic_sort_now(pic_handle* h, int32_t species, int64_t* perm_out) {
     if (perm_out) {
         const int64_t n = h->h_ctr->n_slots[species];
         std::vector<uint32_t> p((size_t)std::max<int64_t>(n, 1));
-        if (n > 0 && hipMemcpy(p.data(), h->idx[h->sort_src_last], (size_t)n * 4, hipMemcpyDeviceToHost) != hipSuccess)
+        if (n > 0 && hipMemcpy(p.data(), h->perm[species], (size_t)n * 4, hipMemcpyDeviceToHost) != hipSuccess)
             return PIC_E_HIP;
         for (int64_t k = 0; k < n; ++k) perm_out[k] = p[k];
     }

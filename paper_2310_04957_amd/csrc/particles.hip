@@ -22,7 +22,9 @@ constexpr int kQW = 128;                      // deferred colliders per wavefron
 struct PushArgs {
     Geo g;
     Mcc m;
-    float* f[9];
+    float* f[9];                 // particles written here (read here too unless perm is set)
+    const float* src[9];         // with perm: slot p reads src at perm[p] (a deferred sort)
+    const uint32_t* perm;
     const float2* E;
     unsigned long long* dep;
     unsigned long long* wallq;
@@ -142,6 +144,22 @@ __device__ __forceinline__ void load9_guard(float* const* f, long long p, long l
     }
 }
 
+// slot p of this step: in place, or through the permutation of a deferred sort
+__device__ __forceinline__ void load_slot(float* const* f, const float* const* src, const uint32_t* perm, long long p,
+                                          long long n, P9& s) {
+    if (p < n) {
+        s = perm ? load9(const_cast<float* const*>(src), perm[p]) : load9(f, (uint32_t)p);
+    } else {
+        s.r = -1.0f;
+    }
+}
+
+// after a deferred sort the weight moves to the new buffer too
+__device__ __forceinline__ void store_slot(float* const* f, uint32_t p, const P9& s, bool moved) {
+    store8(f, p, s);
+    if (moved) stf(f[8], p << 2, s.w);
+}
+
 // One time step for every particle of one species.  A block owns whole
 // chunks of 4096 consecutive slots and each of its wavefronts a contiguous
 // slice of 1024 of them, processed 64 at a time with the next 64 already
@@ -171,6 +189,7 @@ __global__ __launch_bounds__(kBlock) void k_particles(PushArgs a) {
     // chunks in flight on one XCD stay close together (shared L2)
     const long long c_begin = nch * xcd / nx, c_end = nch * (xcd + 1) / nx;
     float* const* f = a.f;
+    const bool moved = a.perm != nullptr;
     unsigned int fallback = 0;
 
     for (int k = tid; k < kWin * kWin; k += kBlock) win[k] = 0ull;
@@ -202,8 +221,10 @@ __global__ __launch_bounds__(kBlock) void k_particles(PushArgs a) {
             bool ok = false;
             Loc L;
             if (p < n) {
-                const float r = f[0][p];
-                L = locate(r, f[1][p], g);
+                const uint32_t q = a.perm ? a.perm[p] : (uint32_t)p;
+                const float* const* rz = a.perm ? a.src : const_cast<const float* const*>(f);
+                const float r = rz[0][q];
+                L = locate(r, rz[1][q], g);
                 ok = (r >= 0.0f) && L.inside;
             }
             const unsigned long long m = __ballot(ok);
@@ -235,7 +256,7 @@ __global__ __launch_bounds__(kBlock) void k_particles(PushArgs a) {
         int qn = 0, nb = 0;
         unsigned int* ql = qslot[wave];
         P9 cur, nxt;
-        load9_guard(f, sbase + lane, n, cur);
+        load_slot(f, a.src, a.perm, sbase + lane, n, cur);
 
         auto run_queue = [&](int cnt) {
             // lanes < cnt each take one deferred collider, in queue (slot) order;
@@ -274,7 +295,7 @@ __global__ __launch_bounds__(kBlock) void k_particles(PushArgs a) {
                     kill(f, slot);
                 } else {
                     fallback += deposit<kWin>(g, L2, c.w, win, wi0, wj0, a.dep);
-                    store8(f, slot, c);
+                    store_slot(f, slot, c, moved);
                 }
             }
         };
@@ -282,7 +303,7 @@ __global__ __launch_bounds__(kBlock) void k_particles(PushArgs a) {
         uint4 dec4 = make_uint4(0u, 0u, 0u, 0u);
         for (int it = 0; it < kRounds; ++it) {
             const long long p = sbase + (long long)it * 64 + lane;
-            if (it + 1 < kRounds) load9_guard(f, p + 64, n, nxt);
+            if (it + 1 < kRounds) load_slot(f, a.src, a.perm, p + 64, n, nxt);
             // decision words of this lane's slots in rounds it .. it+3 (sbase is
             // a multiple of 256, so the four share one counter)
             if ((it & 3) == 0) dec4 = draw(decision_ctr((uint32_t)p), a.step, kPurposeDecide, a.sp, 0, a.key0, a.key1);
@@ -305,7 +326,7 @@ __global__ __launch_bounds__(kBlock) void k_particles(PushArgs a) {
                             kill(f, (uint32_t)p);
                         } else {
                             fallback += deposit<kWin>(g, L2, s.w, win, wi0, wj0, a.dep);
-                            store8(f, (uint32_t)p, s);
+                            store_slot(f, (uint32_t)p, s, moved);
                         }
                     }
                 }
@@ -316,7 +337,7 @@ __global__ __launch_bounds__(kBlock) void k_particles(PushArgs a) {
             if (coll) {
                 const int q = qn + __popcll(m & lanemask_lt());
                 ql[q] = (unsigned int)p;
-                store8(f, (uint32_t)p, s);
+                store_slot(f, (uint32_t)p, s, moved);
             }
             qn += __popcll(m);
             wave_sync();
@@ -389,7 +410,14 @@ void launch_particles(pic_handle* h, int sp) {
     PushArgs a;
     a.g = make_geo(h);
     a.m = make_mcc(h, sp);
-    for (int k = 0; k < 9; ++k) a.f[k] = h->buf[sp][h->cur[sp]].f[k];
+    // a deferred sort is applied on the way: read through the permutation,
+    // write the other buffer
+    const bool moved = h->pending[sp];
+    for (int k = 0; k < 9; ++k) {
+        a.src[k] = h->buf[sp][h->cur[sp]].f[k];
+        a.f[k] = h->buf[sp][moved ? 1 - h->cur[sp] : h->cur[sp]].f[k];
+    }
+    a.perm = moved ? h->perm[sp] : nullptr;
     a.E = h->E;
     a.dep = h->dep[h->dep_cur][sp];
     a.wallq = h->wallq;
@@ -407,6 +435,10 @@ void launch_particles(pic_handle* h, int sp) {
         hipLaunchKernelGGL(k_particles<24>, dim3(grid_blocks()), dim3(kBlock), 0, h->stream, a);
     else
         hipLaunchKernelGGL(k_particles<16>, dim3(grid_blocks()), dim3(kBlock), 0, h->stream, a);
+    if (moved) {
+        h->cur[sp] = 1 - h->cur[sp];
+        h->pending[sp] = false;
+    }
 }
 
 // ---------------------------------------------------------------- births

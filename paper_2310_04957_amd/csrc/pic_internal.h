@@ -84,8 +84,9 @@ struct pic_handle {
     // particles: two buffers per species for the sort
     pic::Species buf[2][2];
     int cur[2];
-    int sort_src_last;
     uint32_t *keys[2], *idx[2];
+    uint32_t* perm[2];        // per species: the permutation of the last sort
+    bool pending[2];          // a sort whose particle movement is still to be applied
     uint32_t* hist;
     uint32_t* bsum;
     // births
@@ -157,7 +158,8 @@ void launch_births(pic_handle* h);
 void launch_count_alive(pic_handle* h, long long* out2);
 
 // sort
-void launch_sort(pic_handle* h, int sp);
+void launch_sort(pic_handle* h, int sp, bool deferred = false);
+void materialize(pic_handle* h, int sp);
 
 // field
 void launch_assemble(pic_handle* h);

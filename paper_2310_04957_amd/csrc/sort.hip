@@ -223,13 +223,12 @@ struct GatherArgs {
     const float* src[9];
     float* dst[9];
     const uint32_t* idx;
-    long long* n_slots;
-    const unsigned int* dead;
+    const long long* n_slots;
     int sp;
 };
 
 __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a) {
-    const long long n = a.n_slots[a.sp] - (long long)a.dead[a.sp];
+    const long long n = a.n_slots[a.sp];
     for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n;
          q += (long long)gridDim.x * blockDim.x) {
         const uint32_t o = a.idx[q];
@@ -245,8 +244,9 @@ __global__ void k_finish_sort(long long* n_slots, unsigned int* dead, int sp) {
 
 __global__ void k_zero_u32(unsigned int* p) { *p = 0u; }
 
-void launch_sort(pic_handle* h, int sp) {
+void launch_sort(pic_handle* h, int sp, bool deferred) {
     hipStream_t st = h->stream;
+    materialize(h, sp);   // a sort reads the particles as they stand
     const long long* ns = (const long long*)h->ctr->n_slots;
     unsigned int* dead = &h->ctr->dead[0];
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, dead + sp);
@@ -264,25 +264,36 @@ void launch_sort(pic_handle* h, int sp) {
     hipLaunchKernelGGL(k_keys, dim3(2048), dim3(kBlock), 0, st, ka);
     int src = 0;
     for (int shift = 0; shift < h->key_bits; shift += 8) {
+        // the last pass writes the permutation to the species' own buffer
+        const bool last = shift + 8 >= h->key_bits;
         hipLaunchKernelGGL(k_hist, dim3(2048), dim3(kBlock), 0, st, h->keys[src], ns, sp, shift, h->hist);
         hipLaunchKernelGGL(k_scan_reduce, dim3(2048), dim3(kBlock), 0, st, h->hist, ns, sp, h->bsum);
         hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, h->bsum, ns, sp);
         hipLaunchKernelGGL(k_scan_down, dim3(2048), dim3(kBlock), 0, st, h->hist, h->bsum, ns, sp);
         hipLaunchKernelGGL(k_scatter, dim3(2048), dim3(kBlock), 0, st, h->keys[src], h->idx[src], h->keys[1 - src],
-                           h->idx[1 - src], h->hist, ns, sp, shift);
+                           last ? h->perm[sp] : h->idx[1 - src], h->hist, ns, sp, shift);
         src = 1 - src;
     }
+    hipLaunchKernelGGL(k_finish_sort, dim3(1), dim3(1), 0, st, h->ctr->n_slots, dead, sp);
+    // the particles move with the next particle step (deferred) or now
+    h->pending[sp] = true;
+    if (!deferred) materialize(h, sp);
+}
+
+// apply a deferred sort: gather the current buffer through the permutation
+// into the other one (the slot count is already that of the sorted view)
+void materialize(pic_handle* h, int sp) {
+    if (!h->pending[sp]) return;
     GatherArgs ga;
+    const Species& S = h->buf[sp][h->cur[sp]];
     Species& D = h->buf[sp][1 - h->cur[sp]];
     for (int k = 0; k < 9; ++k) { ga.src[k] = S.f[k]; ga.dst[k] = D.f[k]; }
-    ga.idx = h->idx[src];
+    ga.idx = h->perm[sp];
     ga.n_slots = h->ctr->n_slots;
-    ga.dead = dead;
     ga.sp = sp;
-    hipLaunchKernelGGL(k_gather, dim3(2048), dim3(kBlock), 0, st, ga);
-    hipLaunchKernelGGL(k_finish_sort, dim3(1), dim3(1), 0, st, h->ctr->n_slots, dead, sp);
+    hipLaunchKernelGGL(k_gather, dim3(2048), dim3(kBlock), 0, h->stream, ga);
     h->cur[sp] = 1 - h->cur[sp];
-    h->sort_src_last = src;
+    h->pending[sp] = false;
 }
 
 }  // namespace pic
