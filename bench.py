@@ -173,7 +173,14 @@ def main():
     n_mean = 0.5 * (n_start + n_end)
     ps = n_mean * args.steps
     ms_part = d.ms_particles[0] + d.ms_particles[1]
-    part_bytes = BYTES_PER_PARTICLE_STEP * ps
+    # a step right after a sort also reads the permutation (4 B) and writes w
+    # (4 B) for that species (the sort at the end of step s moves the
+    # particles during step s + 1)
+    def sorted_steps(every):
+        return sum(1 for s_ in range(args.warmup, args.warmup + args.steps) if every > 0 and s_ > 0 and s_ % every == 0)
+    extra = 8.0 * (d0.n_alive[0] * sorted_steps(w["run"]["sort_every"]) +
+                   d0.n_alive[1] * sorted_steps(w["run"]["sort_every_ion"]))
+    part_bytes = BYTES_PER_PARTICLE_STEP * ps + extra
     achieved = part_bytes / (ms_part * 1e-3) / 1e9 if ms_part > 0 else 0.0
     out = {
         "metric": "particle-steps/s (push+deposit+MCC) + field-solve ms/step, learned vs plain PCG",
@@ -204,6 +211,7 @@ def main():
                      "traffic_unit": "GB per launch (HBM, rocprofv3 counters)",
                      "algorithmic_gb_per_launch": part_bytes / (2 * args.steps) / 1e9,
                      "kernel": "k_particles", "bytes_per_unit": BYTES_PER_PARTICLE_STEP,
+                     "bytes_after_sort": "+8 per particle on the step after its species' sort",
                      "unit_of_work": "particle-step"},
     }
     if learned:
