@@ -49,7 +49,7 @@ class Diag(C.Structure):
                 ("numax_violations", C.c_int64), ("solver_iters", C.c_int64),
                 ("solver_relres", C.c_double),
                 ("harm_U_re", C.c_double * 6), ("harm_U_im", C.c_double * 6),
-                ("harm_I_re", C.c_double * 6), ("harm_I_im", C.c_double * 6)]
+                ("harm_I_re", C.c_double * 6), ("harm_I_im", C.c_double * 6), ("elec", C.c_double * 12)]
 
 
 _lib = None
@@ -90,7 +90,8 @@ def lib():
         L.orc_philox4x32.argtypes = [P, P, P]
         L.orc_philox4x64.argtypes = [P, P, P]
         L.orc_xsec_e.argtypes = [C.c_double, P]
-        L.orc_circuit_vacuum.argtypes = [C.POINTER(Config), C.c_double, C.c_int64, P, P]
+        L.orc_circuit_vacuum.argtypes = [C.POINTER(Config), C.c_double, C.c_int64, P, P, P]
+        L.orc_reflection.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, P]
         _lib = L
     return _lib
 
@@ -283,9 +284,28 @@ def xsec_e(eps):
     return o
 
 
-def circuit_vacuum(w, C_eq, nsteps):
+ELEC = ("Z_ccp_re", "Z_ccp_im", "Z_load_re", "Z_load_im", "gamma", "P_source", "P_Rs", "P_IMN", "P_stray",
+        "P_ccp", "P_forward", "P_ref")
+
+
+def elec_dict(a):
+    """The 12 electrical-characterisation numbers as a dict (Eqs. 11-14)."""
+    return dict(zip(ELEC, [float(v) for v in a]))
+
+
+def reflection(Z_load, R_s, P_source, P_Rs):
+    """|Gamma| (Eq. 12), P_forward and P_ref (Eq. 14)."""
+    out = np.zeros(3)
+    lib().orc_reflection(Z_load.real, Z_load.imag, R_s, P_source, P_Rs, _ptr(out))
+    return tuple(float(v) for v in out)
+
+
+def circuit_vacuum(w, C_eq, nsteps, chars=False):
+    """The circuit alone with a fixed C_eq: U_E and I series, and with
+    chars the electrical characterisation of the last period."""
     cfg = make_config(w, load=False)
     U = np.zeros(nsteps)
     I = np.zeros(nsteps)
-    lib().orc_circuit_vacuum(C.byref(cfg), C_eq, nsteps, _ptr(U), _ptr(I))
-    return U, I
+    e = np.zeros(12)
+    lib().orc_circuit_vacuum(C.byref(cfg), C_eq, nsteps, _ptr(U), _ptr(I), _ptr(e))
+    return (U, I, elec_dict(e)) if chars else (U, I)

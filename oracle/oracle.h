@@ -69,6 +69,9 @@ typedef struct {
     int64_t solver_iters;
     double solver_relres;
     double harm_U_re[6], harm_U_im[6], harm_I_re[6], harm_I_im[6];
+    /* last complete period (Eqs. 11-14): Z_ccp re/im, Z_load re/im, |Gamma|,
+       P_source, P_Rs, P_IMN, P_stray, P_ccp, P_forward, P_ref */
+    double elec[12];
 } orc_diag;
 
 typedef struct orc_sim orc_sim;
@@ -114,7 +117,14 @@ int orc_mcc(orc_sim* s, int32_t species, int64_t n, double* v3, uint32_t slot0, 
 void orc_philox4x32(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 void orc_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
 void orc_xsec_e(double eps_eV, double out3[3]);
-int orc_circuit_vacuum(const orc_config* cfg, double C_eq, int64_t nsteps, double* U_out, double* I_out);
+/* |Gamma| (Eq. 12), forward and reflected power (Eq. 14) of a load Z_load
+   against R_s: out3 = |Gamma|, P_forward, P_ref */
+void orc_reflection(double z_re, double z_im, double R_s, double P_source, double P_Rs, double* out3);
+
+/* the circuit alone with a fixed C_eq and no plasma; chars (or NULL): the
+   electrical characterisation of the last period, as orc_diag.elec */
+int orc_circuit_vacuum(const orc_config* cfg, double C_eq, int64_t nsteps, double* U_out, double* I_out,
+                       double* chars);
 
 #ifdef __cplusplus
 }

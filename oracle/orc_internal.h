@@ -52,10 +52,15 @@ struct orc_sim {
     /* diagnostics */
     int64_t step, periods_done, born, coll[2][4], viol;
     double *serU, *serI, *lastU, *lastI;
+    double *serVin, *serI1, *lastVin, *lastI1;   /* source-side voltage and current per step */
+    double energy[5], last_energy[5];            /* element energies of the current / last period */
     int64_t solver_iters;
     double solver_relres;
     int have_last;
 };
+
+void o_characterise(const orc_config* c, const double* U, const double* I, const double* Vin, const double* I1,
+                    const double* energy, double* chars);
 
 /* field (orc_field.c) */
 int o_geometry(orc_sim* s);

@@ -37,14 +37,40 @@ static void circ_rhs(const orc_config* c, double C_eq, double t, const double* y
     }
 }
 
+/* Instantaneous powers of the circuit elements for state y at time t
+   (Eq. 13 integrands) [R30]: 0 delivered by the source, 1 lost in R_s,
+   2 lost in the matching network (R_m) or in the series branch (R_b),
+   3 lost in the stray branch, 4 delivered to the plasma load U_E I_ccp. */
+static void circ_powers(const orc_config* c, double C_eq, double t, const double* y, double Q_P, double* p) {
+    double U_E = (y[5] - Q_P) / C_eq;
+    double Us = c->U_amp * sin(2.0 * O_PI * c->freq * t) + c->U_dc;
+    for (int k = 0; k < 5; k++) p[k] = 0.0;
+    if (c->circ_kind == 2) {
+        double I1 = (Us - (y[0] - y[1]) / c->C_m1) / c->R_s;
+        p[0] = Us * I1;
+        p[1] = c->R_s * I1 * I1;
+        p[2] = c->R_m * y[2] * y[2];
+        p[3] = c->R_stray * y[4] * y[4];
+        p[4] = U_E * (y[2] - y[4]);
+    } else if (c->circ_kind == 1) {
+        p[0] = Us * y[1];
+        p[2] = c->R_b * y[1] * y[1];
+        p[4] = U_E * y[1];
+    }
+}
+
 /* [R17] classical RK4 with `substeps` substeps per PIC step; I_conv and Q_P
-   are held over the step.  Returns the step-averaged circuit current. */
+   are held over the step.  Returns the step-averaged circuit current.  With
+   e5, adds each element's energy over the step (trapezoid rule on the
+   substep end points). */
 static double circ_integrate(const orc_config* c, double dt, double C_eq, double t0, double Q_P, double I_conv,
-                             double* y) {
+                             double* y, double* e5) {
     int M = c->substeps > 0 ? c->substeps : 1;
     double h = dt / M;
     int qi = (c->circ_kind == 2) ? 3 : 0;
     double q0 = y[qi];
+    double pa[5], pb[5];
+    if (e5) circ_powers(c, C_eq, t0, y, Q_P, pa);
     for (int m = 0; m < M; m++) {
         double t = t0 + m * h;
         double k1[6], k2[6], k3[6], k4[6], yt[6];
@@ -56,8 +82,22 @@ static double circ_integrate(const orc_config* c, double dt, double C_eq, double
         for (int k = 0; k < 6; k++) yt[k] = y[k] + h * k3[k];
         circ_rhs(c, C_eq, t + h, yt, Q_P, I_conv, k4);
         for (int k = 0; k < 6; k++) y[k] += h / 6.0 * (k1[k] + 2.0 * k2[k] + 2.0 * k3[k] + k4[k]);
+        if (e5) {
+            circ_powers(c, C_eq, t + h, y, Q_P, pb);
+            for (int k = 0; k < 5; k++) {
+                e5[k] += 0.5 * h * (pa[k] + pb[k]);
+                pa[k] = pb[k];
+            }
+        }
     }
     return (y[qi] - q0) / dt;
+}
+
+/* Source-side samples of a step for the load impedance: the voltage at the
+   matching network's input (across C_m1) or the source voltage, at t1. */
+static double circ_vin(const orc_config* c, double t1, const double* y) {
+    if (c->circ_kind == 2) return (y[0] - y[1]) / c->C_m1;
+    return c->U_amp * sin(2.0 * O_PI * c->freq * t1) + c->U_dc;
 }
 
 static double powered_count(const orc_sim* s) {
@@ -73,6 +113,7 @@ static double induced_charge(const orc_sim* s) {
 
 void o_circuit_advance(orc_sim* s) {
     double unit = O_QE * s->w_unit * ldexp(1.0, -O_KBITS);
+    int k = (int)(s->step % s->cfg.steps_per_period);
     double pc = powered_count(s);
     double I_conv = (pc - (double)s->cnt_prev_pow) * unit / s->dt;
     s->cnt_prev_pow = (int64_t)pc;
@@ -80,33 +121,62 @@ void o_circuit_advance(orc_sim* s) {
     double t1 = s->t + s->dt;
     const orc_config* c = &s->cfg;
     if (c->circ_kind == 0) {
+        double U0 = s->U_E;
         double U = c->U_amp * sin(2.0 * O_PI * c->freq * t1) + c->U_dc;
         double QE = s->C_eq * U + s->Q_P;
         s->I_ccp = (QE - s->Q_E) / s->dt - I_conv;
         s->Q_E = QE;
         s->U_E = U;
+        /* the source is the electrode: the mean voltage over the step times
+           the step-averaged current */
+        double e = s->dt * 0.5 * (U0 + U) * s->I_ccp;
+        s->energy[0] += e;
+        s->energy[4] += e;
+        s->serVin[k] = U;
+        s->serI1[k] = s->I_ccp;
     } else {
         double y[6];
-        for (int k = 0; k < 5; k++) y[k] = s->circ[k];
+        for (int q = 0; q < 5; q++) y[q] = s->circ[q];
         y[5] = s->Q_E;
-        s->I_ccp = circ_integrate(c, s->dt, s->C_eq, s->t, s->Q_P, I_conv, y);
-        for (int k = 0; k < 5; k++) s->circ[k] = y[k];
+        double q1 = y[0];
+        s->I_ccp = circ_integrate(c, s->dt, s->C_eq, s->t, s->Q_P, I_conv, y, s->energy);
+        for (int q = 0; q < 5; q++) s->circ[q] = y[q];
         s->Q_E = y[5];
         s->U_E = (s->Q_E - s->Q_P) / s->C_eq;
+        s->serVin[k] = circ_vin(c, t1, y);
+        s->serI1[k] = (c->circ_kind == 2) ? (y[0] - q1) / s->dt : s->I_ccp;
     }
     s->t = t1;
 }
 
-int orc_circuit_vacuum(const orc_config* cfg, double C_eq, int64_t nsteps, double* U_out, double* I_out) {
+int orc_circuit_vacuum(const orc_config* cfg, double C_eq, int64_t nsteps, double* U_out, double* I_out,
+                       double* chars) {
     double dt = 1.0 / (cfg->freq * cfg->steps_per_period);
+    int spp = cfg->steps_per_period;
     double y[6] = {0, 0, 0, 0, 0, 0};
-    double t = 0.0;
+    double t = 0.0, e[5] = {0, 0, 0, 0, 0};
+    double* vin = calloc((size_t)spp, sizeof(double));
+    double* i1 = calloc((size_t)spp, sizeof(double));
+    double* uu = calloc((size_t)spp, sizeof(double));
+    double* ii = calloc((size_t)spp, sizeof(double));
+    if (!vin || !i1 || !uu || !ii) { free(vin); free(i1); free(uu); free(ii); return -1; }
     for (int64_t n = 0; n < nsteps; n++) {
-        double I = circ_integrate(cfg, dt, C_eq, t, 0.0, 0.0, y);
+        int last_period = n >= nsteps - spp;
+        double q1 = y[0];
+        double I = circ_integrate(cfg, dt, C_eq, t, 0.0, 0.0, y, last_period ? e : NULL);
         t += dt;
         U_out[n] = y[5] / C_eq;
         I_out[n] = I;
+        if (last_period) {
+            int k = (int)(n - (nsteps - spp));
+            uu[k] = U_out[n];
+            ii[k] = I;
+            vin[k] = circ_vin(cfg, t, y);
+            i1[k] = (cfg->circ_kind == 2) ? (y[0] - q1) / dt : I;
+        }
     }
+    if (chars && nsteps >= spp) o_characterise(cfg, uu, ii, vin, i1, e, chars);
+    free(vin); free(i1); free(uu); free(ii);
     return 0;
 }
 
@@ -280,6 +350,9 @@ static int step1(orc_sim* s) {
         o_laplace(s);
         memcpy(s->lastU, s->serU, sizeof(double) * spp);
         memcpy(s->lastI, s->serI, sizeof(double) * spp);
+        memcpy(s->lastVin, s->serVin, sizeof(double) * spp);
+        memcpy(s->lastI1, s->serI1, sizeof(double) * spp);
+        for (int q = 0; q < 5; q++) { s->last_energy[q] = s->energy[q]; s->energy[q] = 0.0; }
         for (int sp = 0; sp < 2; sp++) {
             memcpy(s->plast[sp], s->psum[sp], sizeof(int64_t) * s->nn);
             memset(s->psum[sp], 0, sizeof(int64_t) * s->nn);
@@ -334,6 +407,10 @@ int orc_create(const orc_config* cfg, orc_sim** out) {
     int spp = cfg->steps_per_period;
     s->serU = calloc(spp, sizeof(double));
     s->serI = calloc(spp, sizeof(double));
+    s->serVin = calloc(spp, sizeof(double));
+    s->serI1 = calloc(spp, sizeof(double));
+    s->lastVin = calloc(spp, sizeof(double));
+    s->lastI1 = calloc(spp, sizeof(double));
     s->lastU = calloc(spp, sizeof(double));
     s->lastI = calloc(spp, sizeof(double));
     /* particles: the load fixes w_unit; with load = 0 the slots stay empty */
@@ -392,6 +469,7 @@ void orc_destroy(orc_sim* s) {
     free(s->phi); free(s->phiL); free(s->Er); free(s->Ez); free(s->chi); free(s->Q);
     free(s->ar); free(s->az);
     free(s->serU); free(s->serI); free(s->lastU); free(s->lastI);
+    free(s->serVin); free(s->serI1); free(s->lastVin); free(s->lastI1);
     free(s);
 }
 
@@ -411,6 +489,62 @@ static void harmonics(const double* x, int N, double* re, double* im) {
         re[k] = a * sc;
         im[k] = b * sc;
     }
+}
+
+/* Electrical characterisation of one RF period (Sec. 3, Eqs. 11-14)
+   [R30].  Voltages are sampled at the end of each step, currents are step
+   averages: the fundamental of a step average equals that of the sample at
+   the step end times sinc(pi/N) exp(-i pi/N), which is divided out.
+   chars: Z_ccp (re, im), Z_load (re, im), |Gamma|, P_source, P_Rs, P_IMN,
+   P_stray, P_ccp, P_forward, P_ref. */
+void o_characterise(const orc_config* c, const double* U, const double* I, const double* Vin, const double* I1,
+                    const double* energy, double* chars) {
+    int N = c->steps_per_period;
+    double hu[2][6], hi[2][6], hv[2][6], h1[2][6];
+    harmonics(U, N, hu[0], hu[1]);
+    harmonics(I, N, hi[0], hi[1]);
+    harmonics(Vin, N, hv[0], hv[1]);
+    harmonics(I1, N, h1[0], h1[1]);
+    double x = O_PI / N, sinc = sin(x) / x;
+    double fr = sinc * cos(-x), fi = sinc * sin(-x);   /* sinc(pi/N) e^{-i pi/N} */
+    /* complex a / (b / f) = a f / b */
+    double zc[2], zl[2];
+    {
+        double nr = hu[0][1] * fr - hu[1][1] * fi, ni = hu[0][1] * fi + hu[1][1] * fr;
+        double dd = hi[0][1] * hi[0][1] + hi[1][1] * hi[1][1];
+        zc[0] = (nr * hi[0][1] + ni * hi[1][1]) / dd;
+        zc[1] = (ni * hi[0][1] - nr * hi[1][1]) / dd;
+    }
+    {
+        double nr = hv[0][1] * fr - hv[1][1] * fi, ni = hv[0][1] * fi + hv[1][1] * fr;
+        double dd = h1[0][1] * h1[0][1] + h1[1][1] * h1[1][1];
+        zl[0] = (nr * h1[0][1] + ni * h1[1][1]) / dd;
+        zl[1] = (ni * h1[0][1] - nr * h1[1][1]) / dd;
+    }
+    const double T = 1.0 / c->freq;   /* one RF period */
+    double P[5];
+    for (int k = 0; k < 5; k++) P[k] = energy[k] / T;
+    chars[0] = zc[0]; chars[1] = zc[1]; chars[2] = zl[0]; chars[3] = zl[1];
+    for (int k = 0; k < 5; k++) chars[5 + k] = P[k];
+    double gp[3];
+    orc_reflection(zl[0], zl[1], c->circ_kind == 2 ? c->R_s : 0.0, P[0], P[1], gp);
+    chars[4] = gp[0];
+    chars[10] = gp[1];
+    chars[11] = gp[2];
+}
+
+/* Eq. 12 and Eq. 14: |Gamma| of a load Z against the source resistance R_s
+   (0 when there is none), the forward power into the matching network (the
+   source's power less its internal loss) and the reflected power. */
+void orc_reflection(double z_re, double z_im, double R_s, double P_source, double P_Rs, double* out3) {
+    double gam = 0.0;
+    if (R_s > 0.0) {
+        double ar = z_re - R_s, br = z_re + R_s;
+        gam = sqrt((ar * ar + z_im * z_im) / (br * br + z_im * z_im));
+    }
+    out3[0] = gam;
+    out3[1] = P_source - P_Rs;
+    out3[2] = out3[1] * gam * gam;
 }
 
 int orc_diag_get(orc_sim* s, orc_diag* d) {
@@ -436,6 +570,7 @@ int orc_diag_get(orc_sim* s, orc_diag* d) {
     if (s->have_last) {
         harmonics(s->lastU, s->cfg.steps_per_period, d->harm_U_re, d->harm_U_im);
         harmonics(s->lastI, s->cfg.steps_per_period, d->harm_I_re, d->harm_I_im);
+        o_characterise(&s->cfg, s->lastU, s->lastI, s->lastVin, s->lastI1, s->last_energy, d->elec);
     }
     return 0;
 }

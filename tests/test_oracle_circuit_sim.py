@@ -171,3 +171,84 @@ def test_runs_are_deterministic_and_sorted():
     keys = a.tile_keys(pa["r"], pa["z"])
     assert np.all(np.diff(keys.astype(np.int64)) >= 0)      # just sorted at step 10
     assert np.all(pa["r"] >= 0)                               # dead slots dropped
+
+
+def test_reflection_and_reflected_power_reproduce_table1():
+    """Eq. 12 and Eq. 14 as the oracle reads them (Gamma against Z_s = R_s;
+    forward power = source power less the R_s loss) reproduce the paper's
+    Table 1 from its own Z_load and powers, to the table's printed digits;
+    the table's element powers also add up to P_source."""
+    t = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_table1.json")))
+    for k in range(5):
+        Z = complex(*t["Z_load_ohm"][k])
+        g, pf, pr = O.reflection(Z, t["R_s_ohm"], t["P_source_W"][k], t["P_Rs_W"][k])
+        assert abs(g - t["gamma_abs"][k]) <= 0.0006, (k, g)
+        # P_ref is printed to 1e-4 W; |Gamma| enters squared from rounded Z
+        assert abs(pr - t["P_ref_W"][k]) <= 0.0006, (k, pr)
+        parts = t["P_Rs_W"][k] + t["P_IMN_W"][k] + t["P_stray_W"][k] + t["P_ccp_W"][k]
+        assert abs(parts - t["P_source_W"][k]) <= 2e-4
+
+
+def _vacuum_phasors(gold, om):
+    Zc = lambda C: 1 / (1j * om * C)
+    Ceq, Cm1, Cm2 = gold["C_eq_vacuum_F"], gold["C_m1_F"], gold["C_m2_F"]
+    Zst = gold["R_stray_ohm"] + 1j * om * 0.01e-6 + Zc(gold["C_stray_F"])
+    Zp = 1 / (1 / Zc(Ceq) + 1 / Zst)
+    Zser = gold["R_m_ohm"] + 1j * om * gold["L_m_H"] + Zc(Cm2) + Zp
+    Zin = 1 / (1 / Zser + 1 / Zc(Cm1))
+    Us = gold["U_source_amplitude_V"] * -1j          # 77 sin(w t)
+    I1 = Us / (gold["R_s_ohm"] + Zin)
+    Vin = Us - gold["R_s_ohm"] * I1
+    I2 = Vin / Zser
+    Vccp = I2 * Zp
+    return dict(Zc=Zc(Ceq), Zin=Zin, Us=Us, I1=I1, I2=I2, Vccp=Vccp, Iccp=Vccp / Zc(Ceq), Ist=Vccp / Zst)
+
+
+def test_vacuum_characterisation_matches_phasor_solution():
+    """Eqs. 11-14 on the paper's matched vacuum circuit (Sec. 3 values)
+    against its phasor solution: Z_ccp = 1/(j w C_eq), Z_load = Z_in, |Gamma|,
+    each element's power R |I|^2 / 2, the source power, power balance, and
+    P_ref = P_forward |Gamma|^2.  A purely capacitive load absorbs nothing."""
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_vacuum_matching.json")))
+    w = workload("pp32x24", circuit=dict(kind=CIRC_LMATCH, U_amp=gold["U_source_amplitude_V"],
+                                         C_m1=gold["C_m1_F"], C_m2=gold["C_m2_F"], L_m=gold["L_m_H"],
+                                         R_m=gold["R_m_ohm"], R_s=gold["R_s_ohm"], C_stray=gold["C_stray_F"],
+                                         R_stray=gold["R_stray_ohm"]),
+                 run=dict(steps_per_period=400))
+    _, _, e = O.circuit_vacuum(w, gold["C_eq_vacuum_F"], 400 * 400, chars=True)
+    ph = _vacuum_phasors(gold, 2 * math.pi * 13.56e6)
+    Zccp = complex(e["Z_ccp_re"], e["Z_ccp_im"])
+    Zload = complex(e["Z_load_re"], e["Z_load_im"])
+    assert abs(Zccp - ph["Zc"]) <= 1e-5 * abs(ph["Zc"])
+    assert abs(Zload - ph["Zin"]) <= 1e-5 * abs(ph["Zin"])
+    assert abs(e["gamma"] - abs((ph["Zin"] - 50) / (ph["Zin"] + 50))) <= 1e-6
+    Psrc = 0.5 * (ph["Us"] * ph["I1"].conjugate()).real
+    assert abs(e["P_source"] - Psrc) <= 1e-5 * Psrc
+    assert abs(e["P_Rs"] - 0.5 * 50 * abs(ph["I1"]) ** 2) <= 1e-5 * Psrc
+    assert abs(e["P_IMN"] - 0.5 * gold["R_m_ohm"] * abs(ph["I2"]) ** 2) <= 1e-5 * Psrc
+    assert abs(e["P_stray"] - 0.5 * gold["R_stray_ohm"] * abs(ph["Ist"]) ** 2) <= 1e-5 * Psrc
+    assert abs(e["P_ccp"]) <= 1e-6 * Psrc
+    assert abs(e["P_source"] - e["P_Rs"] - e["P_IMN"] - e["P_stray"] - e["P_ccp"]) <= 1e-6 * Psrc
+    assert e["P_forward"] == pytest.approx(e["P_source"] - e["P_Rs"], rel=1e-14)
+    assert e["P_ref"] == pytest.approx(e["P_forward"] * e["gamma"] ** 2, rel=1e-12)
+    # the paper's "100 V" electrode amplitude at 77 V drive, and its current
+    assert abs(abs(ph["Vccp"]) - 100.0) <= 0.5
+    assert abs(abs(ph["Iccp"]) - 2 * math.pi * 13.56e6 * gold["C_eq_vacuum_F"] * abs(ph["Vccp"])) <= 1e-9
+
+
+def test_series_rlc_characterisation_matches_phasor_solution():
+    """Circuit I (Eq. 9) in vacuum: Z_ccp, the load the source sees (series
+    branch plus C_eq), the R_b loss and the source power."""
+    Ceq = 892.07e-12
+    w = workload("pp32x24", circuit=dict(kind=CIRC_SERIES_RLC, U_amp=100.0), run=dict(steps_per_period=400))
+    _, _, e = O.circuit_vacuum(w, Ceq, 200 * 400, chars=True)
+    om = 2 * math.pi * 13.56e6
+    Zb = 0.5 + 1j * om * 0.01e-6 + 1 / (1j * om * 5e-9)
+    Zl = 1 / (1j * om * Ceq)
+    I = 100.0 * -1j / (Zb + Zl)
+    assert abs(complex(e["Z_ccp_re"], e["Z_ccp_im"]) - Zl) <= 1e-5 * abs(Zl)
+    assert abs(complex(e["Z_load_re"], e["Z_load_im"]) - (Zb + Zl)) <= 1e-5 * abs(Zb + Zl)
+    Pb = 0.5 * 0.5 * abs(I) ** 2
+    assert abs(e["P_IMN"] - Pb) <= 1e-5 * Pb
+    assert abs(e["P_source"] - Pb) <= 1e-5 * Pb
+    assert e["gamma"] == 0.0
