@@ -136,6 +136,14 @@ typedef struct {
     int64_t timed_steps, deposit_fallback;
     int32_t error;              /* sticky error raised on the device (PIC_E_CAPACITY ...) */
     int64_t unet_pairs, unet_fallbacks, unet_applications;
+    /* last complete RF period (Sec. 3, Eqs. 11-14): CCP and load impedances
+       at the fundamental (ohm), |Gamma| against R_s (circuit II only), and
+       period-averaged powers (W) of the source, R_s, the matching network's
+       R_m (circuit II) or the series branch's R_b (circuit I), the stray
+       branch, the plasma load; the forward power into the matching network
+       and the reflected power */
+    double Z_ccp_re, Z_ccp_im, Z_load_re, Z_load_im, gamma_abs;
+    double P_source, P_Rs, P_imn, P_stray, P_ccp, P_forward, P_ref;
 } pic_diag_out;
 
 typedef struct {

@@ -28,7 +28,7 @@ def run(w, steps):
         n_e=o.grid("NE_AVG"), n_i=o.grid("NI_AVG"), vol=o.grid("VOL"),
         harm_U=np.array(d.harm_U_re[:]) + 1j * np.array(d.harm_U_im[:]),
         harm_I=np.array(d.harm_I_re[:]) + 1j * np.array(d.harm_I_im[:]),
-        n_alive=np.array(d.n_alive[:]), periods_done=np.array(d.periods_done))
+        n_alive=np.array(d.n_alive[:]), periods_done=np.array(d.periods_done), elec=np.array(d.elec[:]))
 
 
 def ensemble(w, steps, seeds, workers=8):

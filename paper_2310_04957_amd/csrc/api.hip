@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -356,6 +357,8 @@ size_t layout(pic_handle* h, char* base) {
     const size_t spp = (size_t)h->cfg.run.steps_per_period;
     h->serU = c.take<double>(spp); h->serI = c.take<double>(spp);
     h->lastU = c.take<double>(spp); h->lastI = c.take<double>(spp);
+    h->serVin = c.take<double>(spp); h->serI1 = c.take<double>(spp);
+    h->lastVin = c.take<double>(spp); h->lastI1 = c.take<double>(spp);
     h->ctr = c.take<DevCounters>(1);
     h->sc = c.take<DevScalars>(1);
     h->unet_on = h->cfg.solver.unet_batch > 0;
@@ -492,6 +495,50 @@ int load_plasma(pic_handle* h) {
     }
     HIP_OK(hipStreamSynchronize(h->stream));
     return PIC_OK;
+}
+
+// fundamental (k = 1) of N samples: X_1 = (2/N) sum x_n e^{-2 pi i n / N}
+void fundamental(const std::vector<double>& x, double* re, double* im) {
+    const int N = (int)x.size();
+    double a = 0.0, b = 0.0;
+    for (int n = 0; n < N; ++n) {
+        const double ph = 2.0 * kPi * (double)n / (double)N;
+        a += x[n] * std::cos(ph);
+        b -= x[n] * std::sin(ph);
+    }
+    *re = a * 2.0 / N;
+    *im = b * 2.0 / N;
+}
+
+// Electrical characterisation of the last RF period (Sec. 3, Eqs. 11-14).
+// Voltages are samples at step ends, currents step averages, whose
+// fundamental carries sinc(pi/N) e^{-i pi/N} relative to an end sample;
+// impedances divide it out.  Powers are the period-averaged element energies.
+void characterise(const pic_handle* h, const std::vector<double>& U, const std::vector<double>& I,
+                  const std::vector<double>& Vin, const std::vector<double>& I1, const double* energy,
+                  pic_diag_out* out) {
+    const int N = (int)U.size();
+    const double x = kPi / N, sinc = std::sin(x) / x;
+    const std::complex<double> bias = std::polar(sinc, -x);
+    double ur, ui, ir, ii, vr, vi, jr, ji;
+    fundamental(U, &ur, &ui);
+    fundamental(I, &ir, &ii);
+    fundamental(Vin, &vr, &vi);
+    fundamental(I1, &jr, &ji);
+    const std::complex<double> zc = std::complex<double>(ur, ui) * bias / std::complex<double>(ir, ii);
+    const std::complex<double> zl = std::complex<double>(vr, vi) * bias / std::complex<double>(jr, ji);
+    out->Z_ccp_re = zc.real(); out->Z_ccp_im = zc.imag();
+    out->Z_load_re = zl.real(); out->Z_load_im = zl.imag();
+    const double T = 1.0 / h->cfg.circ.freq;
+    out->P_source = energy[0] / T;
+    out->P_Rs = energy[1] / T;
+    out->P_imn = energy[2] / T;
+    out->P_stray = energy[3] / T;
+    out->P_ccp = energy[4] / T;
+    const double Rs = h->cfg.circ.kind == PIC_LMATCH ? h->cfg.circ.R_s : 0.0;
+    out->gamma_abs = Rs > 0.0 ? std::abs((zl - Rs) / (zl + Rs)) : 0.0;
+    out->P_forward = out->P_source - out->P_Rs;
+    out->P_ref = out->P_forward * out->gamma_abs * out->gamma_abs;
 }
 
 int sync_err(pic_handle* h) {
@@ -708,6 +755,10 @@ int pic_diag(pic_handle* h, pic_diag_out* out, const pic_diag_buffers* bufs) {
     if (hipMemcpy(U.data(), h->lastU, spp * 8, hipMemcpyDeviceToHost) != hipSuccess) return PIC_E_HIP;
     if (hipMemcpy(I.data(), h->lastI, spp * 8, hipMemcpyDeviceToHost) != hipSuccess) return PIC_E_HIP;
     if (h->have_last) {
+        std::vector<double> V(spp), J(spp);
+        if (hipMemcpy(V.data(), h->lastVin, spp * 8, hipMemcpyDeviceToHost) != hipSuccess) return PIC_E_HIP;
+        if (hipMemcpy(J.data(), h->lastI1, spp * 8, hipMemcpyDeviceToHost) != hipSuccess) return PIC_E_HIP;
+        characterise(h, U, I, V, J, sc.last_energy, out);
         for (int k = 0; k < 6; ++k) {
             double a = 0, b = 0, c = 0, d = 0;
             for (int n = 0; n < spp; ++n) {

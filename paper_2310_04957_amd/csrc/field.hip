@@ -125,7 +125,7 @@ struct CircArgs {
     DevScalars* sc;
     const DevCounters* ctr;
     const double* part;
-    double *serU, *serI;
+    double *serU, *serI, *serVin, *serI1;
     int k, kind, substeps;
     double dt, qunit, freq, U_amp, U_dc, R_s, C_m1, C_m2, L_m, R_m, C_stray, L_stray, R_stray, C_b, R_b, L_b;
 };
@@ -152,6 +152,27 @@ __device__ void circ_f(const CircArgs& a, double C_eq, double Q_P, double I_conv
     }
 }
 
+// Element powers at state y, time t (the integrands of Eq. 13): source,
+// R_s, matching network R_m (or series-branch R_b), stray branch, plasma
+// load U_E I_ccp.
+__device__ void circ_p(const CircArgs& a, double C_eq, double Q_P, double t, const double* y, double* p) {
+    const double U_E = (y[5] - Q_P) / C_eq;
+    const double Us = a.U_amp * sin(2.0 * 3.14159265358979323846 * a.freq * t) + a.U_dc;
+    p[0] = p[1] = p[2] = p[3] = p[4] = 0.0;
+    if (a.kind == PIC_LMATCH) {
+        const double I1 = (Us - (y[0] - y[1]) / a.C_m1) / a.R_s;
+        p[0] = Us * I1;
+        p[1] = a.R_s * I1 * I1;
+        p[2] = a.R_m * y[2] * y[2];
+        p[3] = a.R_stray * y[4] * y[4];
+        p[4] = U_E * (y[2] - y[4]);
+    } else if (a.kind == PIC_SERIES_RLC) {
+        p[0] = Us * y[1];
+        p[2] = a.R_b * y[1] * y[1];
+        p[4] = U_E * y[1];
+    }
+}
+
 __global__ __launch_bounds__(256) void k_circuit(CircArgs a) {
     __shared__ double sh[kRedBlocks];
     for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) sh[i] = a.part[i];
@@ -169,19 +190,28 @@ __global__ __launch_bounds__(256) void k_circuit(CircArgs a) {
     s->Q_P = Q_P;
     const double t0 = s->t, t1 = t0 + a.dt;
     if (a.kind == PIC_IDEAL_SOURCE) {
+        const double U0 = s->U_E;
         const double U = a.U_amp * sin(2.0 * 3.14159265358979323846 * a.freq * t1) + a.U_dc;
         const double QE = s->C_eq * U + Q_P;
         s->I_ccp = (QE - s->Q_E) / a.dt - I_conv;
         s->Q_E = QE;
         s->U_E = U;
+        // the source drives the electrode directly
+        const double e = a.dt * 0.5 * (U0 + U) * s->I_ccp;
+        s->energy[0] += e;
+        s->energy[4] += e;
+        a.serVin[a.k] = U;
+        a.serI1[a.k] = s->I_ccp;
     } else {
         double y[6];
         for (int k = 0; k < 5; ++k) y[k] = s->circ[k];
         y[5] = s->Q_E;
         const int qi = (a.kind == PIC_LMATCH) ? 3 : 0;
-        const double q0 = y[qi];
+        const double q0 = y[qi], q1 = y[0];
         const int M = a.substeps > 0 ? a.substeps : 1;
         const double hh = a.dt / M;
+        double pa[5], pb[5];
+        circ_p(a, s->C_eq, Q_P, t0, y, pa);
         for (int m = 0; m < M; ++m) {
             const double t = t0 + m * hh;
             double k1[6], k2[6], k3[6], k4[6], yt[6];
@@ -193,8 +223,23 @@ __global__ __launch_bounds__(256) void k_circuit(CircArgs a) {
             for (int k = 0; k < 6; ++k) yt[k] = y[k] + hh * k3[k];
             circ_f(a, s->C_eq, Q_P, I_conv, t + hh, yt, k4);
             for (int k = 0; k < 6; ++k) y[k] += hh / 6.0 * (k1[k] + 2.0 * k2[k] + 2.0 * k3[k] + k4[k]);
+            // element energies: trapezoid rule over the substep
+            circ_p(a, s->C_eq, Q_P, t + hh, y, pb);
+            for (int k = 0; k < 5; ++k) {
+                s->energy[k] += 0.5 * hh * (pa[k] + pb[k]);
+                pa[k] = pb[k];
+            }
         }
         s->I_ccp = (y[qi] - q0) / a.dt;
+        // source-side samples: the matching network's input voltage (across
+        // C_m1) and the source current, or the source voltage and I_b
+        if (a.kind == PIC_LMATCH) {
+            a.serVin[a.k] = (y[0] - y[1]) / a.C_m1;
+            a.serI1[a.k] = (y[0] - q1) / a.dt;
+        } else {
+            a.serVin[a.k] = a.U_amp * sin(2.0 * 3.14159265358979323846 * a.freq * t1) + a.U_dc;
+            a.serI1[a.k] = s->I_ccp;
+        }
         for (int k = 0; k < 5; ++k) s->circ[k] = y[k];
         s->Q_E = y[5];
         s->U_E = (y[5] - Q_P) / s->C_eq;
@@ -208,6 +253,7 @@ void launch_circuit(pic_handle* h) {
     CircArgs a;
     const pic_circuit& c = h->cfg.circ;
     a.sc = h->sc; a.ctr = h->ctr; a.part = h->part; a.serU = h->serU; a.serI = h->serI;
+    a.serVin = h->serVin; a.serI1 = h->serI1;
     a.k = (int)(h->step % h->cfg.run.steps_per_period);
     a.kind = c.kind; a.substeps = c.substeps;
     a.dt = h->dt; a.qunit = h->qunit;
@@ -1228,23 +1274,36 @@ void launch_efield(pic_handle* h) {
                        1.0 / h->dr, 1.0 / h->dz);
 }
 
-__global__ __launch_bounds__(256) void k_period_roll(unsigned long long* pe, unsigned long long* pi,
-                                                     unsigned long long* le, unsigned long long* li, const double* sU,
-                                                     const double* sI, double* lU, double* lI, int nn, int spp) {
-    const int total = nn > spp ? nn : spp;
+struct RollArgs {
+    unsigned long long *pe, *pi, *le, *li;
+    const double *sU, *sI, *sV, *s1;
+    double *lU, *lI, *lV, *l1;
+    DevScalars* sc;
+    int nn, spp;
+};
+
+__global__ __launch_bounds__(256) void k_period_roll(RollArgs a) {
+    const int total = a.nn > a.spp ? a.nn : a.spp;
     for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < total; n += gridDim.x * blockDim.x) {
-        if (n < nn) {
-            le[n] = pe[n]; li[n] = pi[n];
-            pe[n] = 0ull; pi[n] = 0ull;
+        if (n < a.nn) {
+            a.le[n] = a.pe[n]; a.li[n] = a.pi[n];
+            a.pe[n] = 0ull; a.pi[n] = 0ull;
         }
-        if (n < spp) { lU[n] = sU[n]; lI[n] = sI[n]; }
+        if (n < a.spp) { a.lU[n] = a.sU[n]; a.lI[n] = a.sI[n]; a.lV[n] = a.sV[n]; a.l1[n] = a.s1[n]; }
+    }
+    if (blockIdx.x == 0 && threadIdx.x < 5) {
+        a.sc->last_energy[threadIdx.x] = a.sc->energy[threadIdx.x];
+        a.sc->energy[threadIdx.x] = 0.0;
     }
 }
 
 void launch_period_roll(pic_handle* h) {
-    hipLaunchKernelGGL(k_period_roll, dim3(1024), dim3(256), 0, h->stream, h->psum[0], h->psum[1], h->plast[0],
-                       h->plast[1], (const double*)h->serU, (const double*)h->serI, h->lastU, h->lastI, h->nn,
-                       h->cfg.run.steps_per_period);
+    RollArgs a;
+    a.pe = h->psum[0]; a.pi = h->psum[1]; a.le = h->plast[0]; a.li = h->plast[1];
+    a.sU = h->serU; a.sI = h->serI; a.sV = h->serVin; a.s1 = h->serI1;
+    a.lU = h->lastU; a.lI = h->lastI; a.lV = h->lastVin; a.l1 = h->lastI1;
+    a.sc = h->sc; a.nn = h->nn; a.spp = h->cfg.run.steps_per_period;
+    hipLaunchKernelGGL(k_period_roll, dim3(1024), dim3(256), 0, h->stream, a);
 }
 
 }  // namespace pic

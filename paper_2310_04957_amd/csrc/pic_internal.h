@@ -46,6 +46,8 @@ struct DevScalars {
     double powered_prev;     // integer powered-electrode charge at the last circuit step
     double bb, rr, rz, rz_new, pq, alpha, beta, target, scale, relres, rr0;
     double rr_net, c_net;    // learned preconditioner: |res|^2 at the network, its Galerkin weight
+    double energy[5];        // circuit element energies of the running RF period
+    double last_energy[5];   // ... of the last complete one
     int done, iters, nonfinite, fallback;
 };
 
@@ -113,6 +115,7 @@ struct pic_handle {
     float* cinv32;
     // time series
     double *serU, *serI, *lastU, *lastI;
+    double *serVin, *serI1, *lastVin, *lastI1;   // source-side voltage and current per step
     // device counters / scalars and their pinned host mirrors
     pic::DevCounters* ctr;
     pic::DevScalars* sc;

@@ -77,7 +77,9 @@ class Diag(C.Structure):
         ("ms_particles", C.c_double * 2), ("ms_births", C.c_double), ("ms_sort", C.c_double),
         ("ms_field", C.c_double), ("ms_refresh", C.c_double),
         ("timed_steps", C.c_int64), ("deposit_fallback", C.c_int64), ("error", C.c_int32),
-        ("unet_pairs", C.c_int64), ("unet_fallbacks", C.c_int64), ("unet_applications", C.c_int64)]
+        ("unet_pairs", C.c_int64), ("unet_fallbacks", C.c_int64), ("unet_applications", C.c_int64)] + [
+        (f, C.c_double) for f in ("Z_ccp_re", "Z_ccp_im", "Z_load_re", "Z_load_im", "gamma_abs", "P_source",
+                                  "P_Rs", "P_imn", "P_stray", "P_ccp", "P_forward", "P_ref")]
 
 
 class DiagBuffers(C.Structure):

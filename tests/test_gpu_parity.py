@@ -191,3 +191,31 @@ def test_one_step_matches_oracle_given_identical_state():
         assert dg.coll[sp][0] + dg.coll[sp][1] + dg.coll[sp][2] + dg.coll[sp][3] == \
             do.coll[sp][0] + do.coll[sp][1] + do.coll[sp][2] + do.coll[sp][3]
     g.close()
+
+
+@pytest.mark.parametrize("kind", ["lmatch", "series"])
+def test_electrical_characterisation_matches_oracle(kind):
+    """Eqs. 11-14 over the last RF period without plasma (deterministic FP64
+    circuit on both sides): impedances, |Gamma| and element powers agree
+    to 1e-7 relative (C_eq itself agrees to 1e-9)."""
+    from pic_inputs.workloads import CIRC_LMATCH, CIRC_SERIES_RLC
+    circ = dict(kind=CIRC_LMATCH, U_amp=77.0, C_m1=2335.51e-12, C_m2=215.62e-12) if kind == "lmatch" else \
+        dict(kind=CIRC_SERIES_RLC, U_amp=100.0)
+    w = workload("pp32x24", circuit=circ, run=dict(n_e=0, n_i=0, cap_e=1, cap_i=1, steps_per_period=200))
+    g = _pic(w, load=False)
+    o = O.Oracle(w, load=False)
+    g.step(400)
+    o.step(400)
+    d = g.diag()
+    e = O.elec_dict(o.diag().elec)
+    assert d.periods_done == 2
+    pairs = [("Z_ccp_re", "Z_ccp_re"), ("Z_ccp_im", "Z_ccp_im"), ("Z_load_re", "Z_load_re"),
+             ("Z_load_im", "Z_load_im"), ("gamma_abs", "gamma"), ("P_source", "P_source"), ("P_Rs", "P_Rs"),
+             ("P_imn", "P_IMN"), ("P_stray", "P_stray"), ("P_ccp", "P_ccp"), ("P_forward", "P_forward"),
+             ("P_ref", "P_ref")]
+    scale = {"Z": max(abs(complex(e["Z_ccp_re"], e["Z_ccp_im"])), abs(complex(e["Z_load_re"], e["Z_load_im"]))),
+             "P": max(abs(e["P_source"]), 1e-30), "g": 1.0}
+    for a, b in pairs:
+        sc = scale["Z" if a.startswith("Z") else ("g" if a.startswith("gamma") else "P")]
+        assert abs(getattr(d, a) - e[b]) <= 1e-7 * sc, (a, getattr(d, a), e[b])
+    g.close()

@@ -6,7 +6,8 @@ ways within a few hundred steps, after which the GPU run is one more sample
 of the discharge.  So the GPU run (seed 1) is compared with an ensemble of
 oracle runs that differ only in the seed.  For every compared quantity q
 (period-averaged electron and ion inventories, 4x4-node block inventories,
-harmonics 1..5 of the electrode current and voltage):
+harmonics 1..5 of the electrode current and voltage, the CCP and load
+impedances and the source and plasma powers of Eqs. 11-14):
 
     |q_gpu - mean(q_oracle)| <= max(1% of |mean(q_oracle)|, 3 sigma sqrt(1 + 1/S))
 
@@ -35,7 +36,9 @@ def _gpu_run(w, steps):
     out = dict(n_e=grids["n_e"], n_i=grids["n_i"],
                harm_U=np.array(d.harm_U_re[:]) + 1j * np.array(d.harm_U_im[:]),
                harm_I=np.array(d.harm_I_re[:]) + 1j * np.array(d.harm_I_im[:]),
-               periods_done=d.periods_done)
+               periods_done=d.periods_done,
+               elec=np.array([d.Z_ccp_re, d.Z_ccp_im, d.Z_load_re, d.Z_load_im, d.gamma_abs, d.P_source, d.P_Rs,
+                              d.P_imn, d.P_stray, d.P_ccp, d.P_forward, d.P_ref]))
     g.close()
     return out
 
@@ -73,6 +76,9 @@ def _compare(w, steps):
                [_blocks(e[sp], vol, nr, nz) for e in ens], max_frac_out=0.1)
     for h in ("harm_I", "harm_U"):
         _check(f"{h} 1..5", gpu[h][1:6], [e[h][1:6] for e in ens], max_frac_out=0.2)
+    # electrical characterisation (Eqs. 11-14): Z_ccp, Z_load, source and plasma power
+    pick = [0, 1, 2, 3, 5, 9]
+    _check("Z_ccp, Z_load, P_source, P_ccp", gpu["elec"][pick], [e["elec"][pick] for e in ens], max_frac_out=0.2)
 
 
 @pytest.mark.timeout(600)
