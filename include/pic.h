@@ -213,6 +213,15 @@ int pic_solve_once(pic_handle* h, const double* Q, const double* chi, double U_E
 /* Set t, Q_E, U_E, circ[5], C_eq (9 doubles) -- for single-step parity. */
 int pic_set_state(pic_handle* h, const double* st9);
 
+/* Energy moment of a species at its stored (predicted) positions and
+   explicit velocities v* (the state between steps): N and E node grids
+   (int64, nr+1 by nz+1, host buffers) of the deposit's integer weight
+   shares c_k (units 2^-32 of a weight) and of c_k floor(16 eps), eps the
+   particle's kinetic energy in eV (capped at 2^20 / 16 eV).  Mean energy
+   per node E / (16 N) eV, electron temperature two thirds of it (Sec. 3,
+   the T_e maps).  Exact integer sums: bit-identical to any order. */
+int pic_moments(pic_handle* h, int32_t species, int64_t* N, int64_t* E);
+
 /* ---- learned preconditioner (requires solver.unet_batch > 0; nr and nz
    multiples of 16) ----
    A 5-level, 32-channel U-net on the node image of nz rows (z) by nr

@@ -91,6 +91,7 @@ def lib():
         L.orc_philox4x64.argtypes = [P, P, P]
         L.orc_xsec_e.argtypes = [C.c_double, P]
         L.orc_circuit_vacuum.argtypes = [C.POINTER(Config), C.c_double, C.c_int64, P, P, P]
+        L.orc_moments.argtypes = [P, C.c_int, P, P]
         L.orc_reflection.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, P]
         _lib = L
     return _lib
@@ -224,6 +225,13 @@ class Oracle:
         g = np.zeros(self.nn, dtype=np.int64)
         lib().orc_deposit(self.h, len(r), _ptr(r), _ptr(z), _ptr(w), _ptr(g))
         return g
+
+    def moments(self, sp):
+        """(N, E) int64 node grids: weight shares and shares x floor(16 eps/eV)."""
+        N = np.zeros(self.nn, dtype=np.int64)
+        E = np.zeros(self.nn, dtype=np.int64)
+        lib().orc_moments(self.h, sp, _ptr(N), _ptr(E))
+        return N, E
 
     def tile_keys(self, r, z):
         r = np.ascontiguousarray(r, dtype=np.float64)

@@ -108,6 +108,10 @@ int orc_solve_q(orc_sim* s, const double* Q, const double* chi, double U_E, doub
 double orc_refresh_laplace(orc_sim* s); /* recompute phi_L and C_eq with the current chi */
 double orc_ceq_flux(orc_sim* s);         /* C_eq as the flux out of the electrode */
 int orc_deposit(orc_sim* s, int64_t n, const double* r, const double* z, const double* w, int64_t* grid);
+/* energy moment of species sp: node sums of the integer weight shares (N)
+   and of shares times floor(16 kinetic energy / eV) (E); mean energy
+   E / (16 N) eV */
+int orc_moments(orc_sim* s, int sp, int64_t* N, int64_t* E);
 int orc_tile_keys(orc_sim* s, int64_t n, const double* r, const double* z, uint32_t* keys);
 int orc_stable_perm(int64_t n, const uint32_t* keys, int64_t* perm);
 int orc_predict(orc_sim* s, int64_t n, double* p9);

@@ -685,6 +685,38 @@ int orc_deposit(orc_sim* s, int64_t n, const double* r, const double* z, const d
     return 0;
 }
 
+/* Energy moment of species sp at the stored (predicted) positions and
+   explicit velocities v* [R31]: per particle the kinetic energy
+   eps = (m / 2e)((v_r v_r + v_t v_t) + v_z v_z) in eV, quantised as
+   e_q = floor(16 eps) (capped at 2^20), and node sums N += c_k,
+   E += c_k e_q with the deposit's integer shares c_k.  Mean energy per
+   node E / (16 N) eV; temperature (2/3) of it. */
+int orc_moments(orc_sim* s, int sp, int64_t* N, int64_t* E) {
+    memset(N, 0, sizeof(int64_t) * s->nn);
+    memset(E, 0, sizeof(int64_t) * s->nn);
+    const o_parts* P = &s->p[sp];
+    const double half_m_over_e = 0.5 * s->mass[sp] / O_QE;
+    for (int64_t k = 0; k < P->n; k++) {
+        if (!(P->r[k] >= 0.0)) continue;
+        o_loc L = o_locate(s, P->r[k], P->z[k]);
+        if (!L.inside) continue;
+        int64_t c[4];
+        o_node_weights(s, &L, P->w[k], c);
+        double v2 = P->vr[k] * P->vr[k];
+        v2 = v2 + P->vt[k] * P->vt[k];
+        v2 = v2 + P->vz[k] * P->vz[k];
+        double eq = floor(half_m_over_e * v2 * 16.0);
+        int64_t q = eq < 1048576.0 ? (int64_t)eq : 1048576;
+        int nodes[4] = {L.j * (s->nr + 1) + L.i, L.j * (s->nr + 1) + L.i + 1, (L.j + 1) * (s->nr + 1) + L.i,
+                        (L.j + 1) * (s->nr + 1) + L.i + 1};
+        for (int m = 0; m < 4; m++) {
+            N[nodes[m]] += c[m];
+            E[nodes[m]] += c[m] * q;
+        }
+    }
+    return 0;
+}
+
 int orc_tile_keys(orc_sim* s, int64_t n, const double* r, const double* z, uint32_t* keys) {
     for (int64_t k = 0; k < n; k++) keys[k] = tile_key(s, r[k], z[k]);
     return 0;

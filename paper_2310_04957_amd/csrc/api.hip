@@ -941,6 +941,19 @@ int pic_set_state(pic_handle* h, const double* st9) {
     return hipStreamSynchronize(h->stream) == hipSuccess ? PIC_OK : PIC_E_HIP;
 }
 
+int pic_moments(pic_handle* h, int32_t species, int64_t* N, int64_t* E) {
+    if (!h || !N || !E || species < 0 || species > 1) return PIC_E_ARG;
+    materialize(h, species);
+    // the solver's FP64 work vectors are free between steps and hold the sums
+    unsigned long long* dN = reinterpret_cast<unsigned long long*>(h->x64);
+    unsigned long long* dE = reinterpret_cast<unsigned long long*>(h->z64);
+    launch_moments(h, species, dN, dE);
+    HIP_OK(hipStreamSynchronize(h->stream));
+    HIP_OK(hipMemcpy(N, dN, (size_t)h->nn * 8, hipMemcpyDeviceToHost));
+    HIP_OK(hipMemcpy(E, dE, (size_t)h->nn * 8, hipMemcpyDeviceToHost));
+    return PIC_OK;
+}
+
 int pic_set_solver(pic_handle* h, const pic_solver* sv) {
     if (!h || !sv) return PIC_E_ARG;
     pic_config c = h->cfg;

@@ -735,6 +735,15 @@ void launch_redeposit(pic_handle* h) {
     }
 }
 
+struct MomArgs {
+    Geo g;
+    const float* f[9];
+    const long long* n_slots;
+    int sp;
+    double half_m_over_e;
+    unsigned long long *N, *E;
+};
+
 __global__ __launch_bounds__(kBlock) void k_count_alive(const float* r, const long long* n_slots, int sp,
                                                         unsigned long long* out) {
     __shared__ unsigned int s_cnt;
@@ -748,6 +757,52 @@ __global__ __launch_bounds__(kBlock) void k_count_alive(const float* r, const lo
     atomicAdd(&s_cnt, c);
     __syncthreads();
     if (threadIdx.x == 0) atomicAdd(out, (unsigned long long)s_cnt);
+}
+
+// Energy moment of one species at the stored positions and velocities v*:
+// node sums of the deposit shares c_k and of c_k floor(16 eps / eV) with
+// eps = (m / 2e)((v_r^2 + v_t^2) + v_z^2) evaluated in FP64 (capped at 2^20).
+// Integer sums: order-independent.
+__global__ __launch_bounds__(kBlock) void k_moments(MomArgs a) {
+#pragma clang fp contract(off)
+    const long long n = a.n_slots[a.sp];
+    for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < n;
+         p += (long long)gridDim.x * blockDim.x) {
+        const float r = a.f[0][p];
+        if (!(r >= 0.0f)) continue;
+        const Loc L = locate(r, a.f[1][p], a.g);
+        if (!L.inside) continue;
+        int64_t c[4];
+        node_shares(L, (double)a.f[8][p], a.g.invd, c);
+        const double vr = a.f[2][p], vt = a.f[3][p], vz = a.f[4][p];
+        double v2 = vr * vr;
+        v2 = v2 + vt * vt;
+        v2 = v2 + vz * vz;
+        const double eq = floor(a.half_m_over_e * v2 * 16.0);
+        const long long q = eq < 1048576.0 ? (long long)eq : 1048576ll;
+        const int n00 = L.j * a.g.w + L.i;
+        const int nodes[4] = {n00, n00 + 1, n00 + a.g.w, n00 + a.g.w + 1};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            atomicAdd(&a.N[nodes[k]], (unsigned long long)c[k]);
+            atomicAdd(&a.E[nodes[k]], (unsigned long long)(c[k] * q));
+        }
+    }
+}
+
+void launch_moments(pic_handle* h, int sp, unsigned long long* N, unsigned long long* E) {
+    MomArgs a;
+    a.g = make_geo(h);
+    for (int k = 0; k < 9; ++k) a.f[k] = h->buf[sp][h->cur[sp]].f[k];
+    a.n_slots = (const long long*)h->ctr->n_slots;
+    a.sp = sp;
+    const double QE = 1.602176634e-19, ME = 9.1093837015e-31, MAR = 39.948 * 1.66053906660e-27;
+    a.half_m_over_e = 0.5 * (sp == 0 ? ME : MAR) / QE;
+    a.N = N;
+    a.E = E;
+    launch_zero_u64(N, (size_t)h->nn, h->stream);
+    launch_zero_u64(E, (size_t)h->nn, h->stream);
+    hipLaunchKernelGGL(k_moments, dim3(2048), dim3(kBlock), 0, h->stream, a);
 }
 
 void launch_count_alive(pic_handle* h, long long* out2) {

@@ -159,6 +159,7 @@ void launch_redeposit(pic_handle* h);
 void launch_particles(pic_handle* h, int sp);
 void launch_births(pic_handle* h);
 void launch_count_alive(pic_handle* h, long long* out2);
+void launch_moments(pic_handle* h, int sp, unsigned long long* N, unsigned long long* E);
 
 // sort
 void launch_sort(pic_handle* h, int sp, bool deferred = false);

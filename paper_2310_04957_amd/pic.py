@@ -115,6 +115,7 @@ def lib():
                                      C.POINTER(C.c_double)]
         L.pic_set_state.argtypes = [P, P]
         L.pic_set_solver.argtypes = [P, C.POINTER(Solver)]
+        L.pic_moments.argtypes = [P, C.c_int32, P, P]
         L.pic_unet_num_params.argtypes = [P, C.POINTER(C.c_int64)]
         L.pic_unet_set_params.argtypes = [P, P, C.c_int64]
         L.pic_unet_get_params.argtypes = [P, P, C.c_int64]
@@ -274,6 +275,13 @@ class Pic:
     def set_state(self, t, Q_E, U_E, circ, C_eq):
         st = np.array([t, Q_E, U_E] + list(circ) + [C_eq], dtype=np.float64)
         _check(lib().pic_set_state(self.h, _ptr(st)), "pic_set_state")
+
+    def moments(self, sp):
+        """(N, E) int64 node grids; mean energy E / (16 N) eV."""
+        N = np.zeros(self.nn, dtype=np.int64)
+        E = np.zeros(self.nn, dtype=np.int64)
+        _check(lib().pic_moments(self.h, sp, _ptr(N), _ptr(E)), "pic_moments")
+        return N, E
 
     def set_solver(self, method=None, tol=None, max_iter=None, inner_tol=None):
         s = Solver()

@@ -219,3 +219,23 @@ def test_electrical_characterisation_matches_oracle(kind):
         sc = scale["Z" if a.startswith("Z") else ("g" if a.startswith("gamma") else "P")]
         assert abs(getattr(d, a) - e[b]) <= 1e-7 * sc, (a, getattr(d, a), e[b])
     g.close()
+
+
+@pytest.mark.parametrize("sp", [0, 1])
+def test_energy_moments_bit_exact(sp):
+    """Energy moments (T_e maps): integer node sums of the weight shares and
+    of shares x floor(16 eps / eV) equal the oracle's bit for bit."""
+    w = _small_gec(n=0, cap_e=70000, cap_i=70000)
+    g = w["geometry"]
+    gp = _pic(w, load=False)
+    o = O.Oracle(w, load=False)
+    vmax = 3e6 if sp == 0 else 3e3
+    p = random_particles(65537, g["R"], g["Z"], seed=31 + sp, vmax=vmax, dead_frac=0.02)
+    gp.set_particles(sp, p)
+    o.set_particles(sp, _f64(p))
+    N, E = gp.moments(sp)
+    No, Eo = o.moments(sp)
+    assert np.array_equal(N, No)
+    assert np.array_equal(E, Eo)
+    assert E.sum() > 0
+    gp.close()

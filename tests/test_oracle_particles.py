@@ -192,3 +192,31 @@ def test_tile_keys_and_stable_sort_against_numpy():
     expect = np.where(alive, (j >> 4) * 4 + (i >> 4), 0xFFFFFFFF).astype(np.uint32)
     assert np.array_equal(keys, expect)
     assert np.array_equal(O.stable_perm(keys), np.argsort(keys, kind="stable"))
+
+
+def test_energy_moments_single_particle_and_maxwellian():
+    """Energy moment (R31): one particle puts c_k floor(16 eps) on its four
+    nodes (eps = m v^2 / 2e from its stored velocity); a Maxwellian load at
+    T has mean energy 3T/2 within its statistical error."""
+    import math
+    w = workload("pp32x24", run=dict(n_e=0, n_i=0, cap_e=10, cap_i=10))
+    o = O.Oracle(w, load=False)
+    me, qe = 9.1093837015e-31, 1.602176634e-19
+    v = (3.0e5, -1.0e5, 2.0e5)
+    p = {f: np.zeros(1) for f in ("r", "z", "vr", "vt", "vz", "ar", "at", "az", "w")}
+    p["r"][0], p["z"][0], p["w"][0] = 0.013, 0.007, 0.75
+    p["vr"][0], p["vt"][0], p["vz"][0] = v
+    o.set_particles(0, p)
+    N, E = o.moments(0)
+    eps = 0.5 * me / qe * ((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2])
+    q = math.floor(eps * 16.0)
+    dep = o.deposit(p["r"], p["z"], p["w"])
+    assert np.array_equal(N, dep)
+    assert np.array_equal(E, dep * q)
+    # Maxwellian at 2 eV: <eps> = 3 eV
+    w2 = workload("pp32x24", run=dict(n_e=20000, n_i=0, cap_e=20000, cap_i=10, Te_eV=2.0))
+    o2 = O.Oracle(w2)
+    N2, E2 = o2.moments(0)
+    mean = E2.sum() / (16.0 * N2.sum())
+    # floor(16 eps) loses 1/32 eV on average; 20k particles: sigma ~ 3 eV sqrt(2/3 / 20000)
+    assert abs(mean + 1.0 / 32 - 3.0) < 4 * 3.0 * math.sqrt(2.0 / 3.0 / 20000), mean
