@@ -385,7 +385,10 @@ void ev_record(pic_handle* h, int phase, hipEvent_t* begin) {
         e = h->ev_pool.back();
         h->ev_pool.pop_back();
     }
-    hipEventRecord(e, h->stream);
+    if (hipEventRecord(e, h->stream) != hipSuccess) {
+        h->ev_pool.push_back(e);
+        return;
+    }
     if (phase < 0) {
         *begin = e;
     } else {
@@ -732,7 +735,8 @@ int pic_diag(pic_handle* h, pic_diag_out* out, const pic_diag_buffers* bufs) {
         }
     }
     long long alive[2] = {0, 0};
-    launch_count_alive(h, alive);
+    rc = launch_count_alive(h, alive);
+    if (rc) return rc;
     out->n_alive[0] = alive[0];
     out->n_alive[1] = alive[1];
     out->step = h->step;
@@ -791,11 +795,12 @@ int pic_diag(pic_handle* h, pic_diag_out* out, const pic_diag_buffers* bufs) {
 
 int pic_free(pic_handle* h) {
     if (!h) return PIC_E_ARG;
-    hipStreamSynchronize(h->stream);
+    // teardown: errors here cannot be acted on, the handle goes away regardless
+    (void)hipStreamSynchronize(h->stream);
     ev_collect(h);
-    for (hipEvent_t e : h->ev_pool) hipEventDestroy(e);
-    if (h->h_sc) hipHostFree(h->h_sc);
-    if (h->h_ctr) hipHostFree(h->h_ctr);
+    for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+    if (h->h_sc) (void)hipHostFree(h->h_sc);
+    if (h->h_ctr) (void)hipHostFree(h->h_ctr);
     delete h;
     return PIC_OK;
 }

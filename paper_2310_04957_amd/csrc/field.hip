@@ -851,6 +851,12 @@ struct VecSet<float> {
 
 static inline dim3 grid_for(int n) { return dim3(std::min(8192, (n + 255) / 256)); }
 
+// copy the device scalars to their pinned host mirror and wait for them
+static bool read_scalars(pic_handle* h) {
+    return hipMemcpyAsync(h->h_sc, h->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, h->stream) == hipSuccess &&
+           hipStreamSynchronize(h->stream) == hipSuccess;
+}
+
 // symmetric V(2,2) cycle: on level l, y = M_l b (b in the level's b buffer;
 // level 0 takes b0 and writes y0)
 template <typename T>
@@ -967,13 +973,11 @@ static int pcg(pic_handle* h, T* r, T* x, T* z, T* p, T* q, int max_iter, int* e
         hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, st, (const double*)h->part, s, 3);
         hipLaunchKernelGGL(k_update_p<T>, grid_for(nn), dim3(256), 0, st, p, (const T*)z, s, nn);
         if ((it + 1) % kCheckEvery == 0 || it + 1 == max_iter) {
-            hipMemcpyAsync(h->h_sc, s, sizeof(DevScalars), hipMemcpyDeviceToHost, st);
-            if (hipStreamSynchronize(st) != hipSuccess) { *err = PIC_E_HIP; return it; }
+            if (!read_scalars(h)) { *err = PIC_E_HIP; return it; }
             if (h->h_sc->done) break;
         }
     }
-    hipMemcpyAsync(h->h_sc, s, sizeof(DevScalars), hipMemcpyDeviceToHost, st);
-    if (hipStreamSynchronize(st) != hipSuccess) { *err = PIC_E_HIP; return it; }
+    if (!read_scalars(h)) { *err = PIC_E_HIP; return it; }
     if (h->h_sc->nonfinite) *err = PIC_E_NONFINITE;
     return h->h_sc->iters;
 }
@@ -1092,8 +1096,7 @@ static int fpcg(pic_handle* h, float* r, float* x, float* z, float* p, float* q,
         hipLaunchKernelGGL(k_update_xr<float>, dim3(kRedBlocks), dim3(256), 0, st, x, r, (const float*)p,
                            (const float*)q, h->part, (const DevScalars*)s, nn);
         hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, st, (const double*)h->part, s, 2);
-        hipMemcpyAsync(h->h_sc, s, sizeof(DevScalars), hipMemcpyDeviceToHost, st);
-        if (hipStreamSynchronize(st) != hipSuccess) { *err = PIC_E_HIP; return it; }
+        if (!read_scalars(h)) { *err = PIC_E_HIP; return it; }
         if (h->h_sc->done) break;
         unet_apply(h, r, z);
         hipLaunchKernelGGL(k_dot2, dim3(kRedBlocks), dim3(256), 0, st, (const float*)z, (const float*)r,
@@ -1102,8 +1105,7 @@ static int fpcg(pic_handle* h, float* r, float* x, float* z, float* p, float* q,
         hipLaunchKernelGGL(k_update_p<float>, grid_for(nn), dim3(256), 0, st, p, (const float*)z,
                            (const DevScalars*)s, nn);
     }
-    hipMemcpyAsync(h->h_sc, s, sizeof(DevScalars), hipMemcpyDeviceToHost, st);
-    if (hipStreamSynchronize(st) != hipSuccess) { *err = PIC_E_HIP; return 0; }
+    if (!read_scalars(h)) { *err = PIC_E_HIP; return 0; }
     if (h->h_sc->nonfinite) *err = PIC_E_NONFINITE;
     if (!h->h_sc->done) h->h_sc->fallback = 1;   // out of iterations
     return h->h_sc->iters;
@@ -1161,8 +1163,7 @@ int field_solve(pic_handle* h, double* phi, const double* Q, const double* Up, d
         hipLaunchKernelGGL(k_resid64, dim3(kRedBlocks), dim3(256), 0, st, (const double*)h->ar, (const double*)h->az,
                            (const int8_t*)h->node_kind, Q, (const double*)phi, Up, h->r64, h->part, h->nr, h->nz);
         hipLaunchKernelGGL(k_reduce_resid, dim3(1), dim3(256), 0, st, (const double*)h->part, h->sc, tol, fp64);
-        hipMemcpyAsync(h->h_sc, h->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, st);
-        if (hipStreamSynchronize(st) != hipSuccess) return PIC_E_HIP;
+        if (!read_scalars(h)) return PIC_E_HIP;
         rel = h->h_sc->relres;
         if (h->h_sc->nonfinite) { err = PIC_E_NONFINITE; break; }
         if (rel <= tol || outer >= max_outer) break;

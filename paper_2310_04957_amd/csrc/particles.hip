@@ -805,15 +805,17 @@ void launch_moments(pic_handle* h, int sp, unsigned long long* N, unsigned long 
     hipLaunchKernelGGL(k_moments, dim3(2048), dim3(kBlock), 0, h->stream, a);
 }
 
-void launch_count_alive(pic_handle* h, long long* out2) {
+int launch_count_alive(pic_handle* h, long long* out2) {
     // uses the pad words of the device counters as scratch
     unsigned long long* d = (unsigned long long*)&h->ctr->pad[0];
     launch_zero_u64(d, 2, h->stream);
     for (int sp = 0; sp < 2; ++sp)
         hipLaunchKernelGGL(k_count_alive, dim3(512), dim3(kBlock), 0, h->stream, h->buf[sp][h->cur[sp]].f[0],
                            (const long long*)h->ctr->n_slots, sp, d + sp);
-    hipMemcpyAsync(out2, d, 2 * sizeof(long long), hipMemcpyDeviceToHost, h->stream);
-    hipStreamSynchronize(h->stream);
+    if (hipMemcpyAsync(out2, d, 2 * sizeof(long long), hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess)
+        return PIC_E_HIP;
+    return PIC_OK;
 }
 
 }  // namespace pic

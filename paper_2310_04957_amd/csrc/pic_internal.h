@@ -158,7 +158,7 @@ void launch_predict_deposit(pic_handle* h, int sp);
 void launch_redeposit(pic_handle* h);
 void launch_particles(pic_handle* h, int sp);
 void launch_births(pic_handle* h);
-void launch_count_alive(pic_handle* h, long long* out2);
+int launch_count_alive(pic_handle* h, long long* out2);
 void launch_moments(pic_handle* h, int sp, unsigned long long* N, unsigned long long* E);
 
 // sort
