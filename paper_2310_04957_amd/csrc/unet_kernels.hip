@@ -36,7 +36,39 @@ __device__ __forceinline__ __bf16 raw(bf16 v) { return __builtin_bit_cast(__bf16
 // with zero padding, Xin = X (optionally multiplied by the ReLU mask
 // M > 0 of the layer whose gradient X is).  Tile: 16x16 output pixels per
 // block iteration, 4 wavefronts x 4 rows; each wavefront computes two
-// 32-pixel x 32-channel MFMA tiles per 32 output channels.
+// 32-pixel x 32-channel MFMA tiles per 32 output channels.  The next
+// tile's input (with its halo) is loaded into registers while the current
+// one is multiplied out of LDS.
+template <int CIN>
+struct TileRegs {
+    static constexpr int kChunks = (18 * 18 * (CIN / 8) + 255) / 256;   // 8-channel groups per thread
+    bf16x8 v[kChunks];
+};
+
+template <int CIN, bool MASK>
+__device__ __forceinline__ void load_tile(const bf16* __restrict__ X, const bf16* __restrict__ M, int b, int y0,
+                                          int x0, int H, int W, int tid, TileRegs<CIN>& t) {
+#pragma unroll
+    for (int q = 0; q < TileRegs<CIN>::kChunks; ++q) {
+        const int e = tid + q * 256;
+        bf16x8 v = {};
+        if (e < 18 * 18 * (CIN / 8)) {
+            const int c8 = e % (CIN / 8), pix = e / (CIN / 8);
+            const int yy = y0 - 1 + pix / 18, xx = x0 - 1 + pix % 18;
+            if (yy >= 0 && yy < H && xx >= 0 && xx < W) {
+                const size_t g = (((size_t)b * H + yy) * W + xx) * CIN + c8 * 8;
+                v = *(const bf16x8*)&X[g];
+                if (MASK) {
+                    const bf16x8 m = *(const bf16x8*)&M[g];
+                    for (int k = 0; k < 8; ++k)
+                        if (!(bf2f(m[k]) > 0.0f)) v[k] = f2raw(0.0f);
+                }
+            }
+        }
+        t.v[q] = v;
+    }
+}
+
 template <int CIN, int COUT, bool RELU, bool MASK>
 __global__ __launch_bounds__(256) void k_conv3x3(const bf16* __restrict__ X, const bf16* __restrict__ Wt,
                                                  const float* __restrict__ bias, const bf16* __restrict__ M,
@@ -53,28 +85,31 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16* __restrict__ X, con
     }
     const int tx = (W + 15) / 16, ty = (H + 15) / 16;
     const long long ntile = (long long)tx * ty * B;
+    TileRegs<CIN> next;
+    if ((long long)blockIdx.x < ntile) {
+        const long long tile = blockIdx.x;
+        const int b = (int)(tile / (tx * ty)), rem = (int)(tile % (tx * ty));
+        load_tile<CIN, MASK>(X, M, b, (rem / tx) * 16, (rem % tx) * 16, H, W, tid, next);
+    }
     for (long long tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
         const int b = (int)(tile / (tx * ty));
         const int rem = (int)(tile % (tx * ty));
         const int y0 = (rem / tx) * 16, x0 = (rem % tx) * 16;
-        __syncthreads();
-        // input tile with halo, zero outside the image
-        for (int e = tid; e < 18 * 18 * (CIN / 8); e += 256) {
-            const int c8 = e % (CIN / 8), pix = e / (CIN / 8);
-            const int yy = y0 - 1 + pix / 18, xx = x0 - 1 + pix % 18;
-            bf16x8 v = {};
-            if (yy >= 0 && yy < H && xx >= 0 && xx < W) {
-                const size_t g = (((size_t)b * H + yy) * W + xx) * CIN + c8 * 8;
-                v = *(const bf16x8*)&X[g];
-                if (MASK) {
-                    const bf16x8 m = *(const bf16x8*)&M[g];
-                    for (int k = 0; k < 8; ++k)
-                        if (!(bf2f(m[k]) > 0.0f)) v[k] = f2raw(0.0f);
-                }
+        __syncthreads();   // the previous tile's MFMAs are done with xs
+#pragma unroll
+        for (int q = 0; q < TileRegs<CIN>::kChunks; ++q) {
+            const int e = tid + q * 256;
+            if (e < 18 * 18 * (CIN / 8)) {
+                const int c8 = e % (CIN / 8), pix = e / (CIN / 8);
+                *(bf16x8*)&xs[pix * CP + c8 * 8] = next.v[q];
             }
-            *(bf16x8*)&xs[pix * CP + c8 * 8] = v;
         }
         __syncthreads();
+        const long long nt2 = tile + gridDim.x;
+        if (nt2 < ntile) {
+            const int b2 = (int)(nt2 / (tx * ty)), rem2 = (int)(nt2 % (tx * ty));
+            load_tile<CIN, MASK>(X, M, b2, (rem2 / tx) * 16, (rem2 % tx) * 16, H, W, tid, next);
+        }
         f32x16 acc[2][NT];
         for (int s = 0; s < 2; ++s)
             for (int nt = 0; nt < NT; ++nt) acc[s][nt] = {};
