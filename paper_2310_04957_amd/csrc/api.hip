@@ -125,6 +125,7 @@ void derive(pic_handle* h) {
     h->cap[1] = c.run.cap_i;
     int64_t capmax = std::max<int64_t>(std::max(h->cap[0], h->cap[1]), 1);
     h->max_chunks = (capmax + kChunk - 1) / kChunk;
+    h->max_rows = stage_rows(capmax);
     // null-collision constants (Vahedi & Surendra 1995)
     h->n_gas = c.gas.p_Pa / (kKB * c.gas.T_gas_K);
     const int N = 2000000;
@@ -318,10 +319,11 @@ size_t layout(pic_handle* h, char* base) {
     const size_t mch = (size_t)h->max_chunks;
     h->hist = c.take<uint32_t>(256 * mch);
     h->bsum = c.take<uint32_t>((256 * mch + 4095) / 4096 + 1);
-    h->stage = c.take<Birth>(mch * kStageCap);
-    h->stage_cnt = c.take<int>(mch * kWaves);
-    h->stage_off = c.take<int>(mch * kWaves / 1024 + 2);
-    h->stage_segoff = c.take<int>(mch * kWaves / 1024 + 2);
+    const size_t mrows = (size_t)h->max_rows;
+    h->stage = c.take<Birth>(mrows * kStageW);
+    h->stage_cnt = c.take<int>(mrows);
+    h->stage_off = c.take<int>(mrows / 1024 + 2);
+    h->stage_segoff = c.take<int>(mrows / 1024 + 2);
     for (int b = 0; b < 2; ++b)
         for (int sp = 0; sp < 2; ++sp) h->dep[b][sp] = c.take<unsigned long long>(nn);
     h->wallq = c.take<unsigned long long>(nn);

@@ -14,7 +14,6 @@ namespace pic {
 // a halo of H cells, (16 + 2H + 1)^2 nodes; electrons (fast, dispersing
 // between sorts) use H = 24, ions H = 16
 constexpr int win_nodes(int halo) { return kTile + 2 * halo + 1; }
-constexpr int kSlice = kChunk / kWaves;       // consecutive slots owned by one wavefront
 constexpr int kRounds = kSlice / 64;
 static_assert(kSlice % 256 == 0 && kRounds % 4 == 0, "decision words are shared by four aligned rounds");
 constexpr int kQW = 128;                      // deferred colliders per wavefront
@@ -43,29 +42,40 @@ __device__ __forceinline__ unsigned long long lanemask_lt() {
 // Charge of a removed particle: to the conductor it hit, or deposited at the
 // landing point into the dielectric surface-charge grid (the share on
 // conductor nodes goes to that conductor).  Returns true if removed.
+// Cell kinds come from the window's LDS copy s_ck when the cell lies in it.
 template <int kWin>
 __device__ __forceinline__ bool absorb(const Geo& g, const Loc& L, float w, int sign,
                                        unsigned long long* s_abs, unsigned long long* wallq, bool vac, int wi0,
-                                       int wj0) {
-    // vac: every domain cell of the chunk's window is vacuum, so a particle
-    // inside the domain and the window needs no cell lookup
-    if (L.inside && vac && (unsigned)(L.i - wi0) < (unsigned)(kWin - 1) && (unsigned)(L.j - wj0) < (unsigned)(kWin - 1))
-        return false;
-    if (L.inside && g.cell_kind[L.j * g.nr + L.i] == 0) return false;
+                                       int wj0, const uint8_t* s_ck) {
     if (!L.inside) {
         int bc = g.edge_bc[L.edge];
         int slot = bc >= 0 ? (bc < 2 ? bc : 0) : 2;
         atomicAdd(&s_abs[slot], (unsigned long long)total_share((double)w));
         return true;
     }
-    int ck = g.cell_kind[L.j * g.nr + L.i];
+    const int li = L.i - wi0, lj = L.j - wj0;
+    const bool inw = (unsigned)li < (unsigned)(kWin - 1) && (unsigned)lj < (unsigned)(kWin - 1);
+    // vac: every domain cell of the window is vacuum
+    if (inw && vac) return false;
+    // the LDS read (index clamped into the window) is replaced from the
+    // global grid for a cell outside the window
+    int ck = s_ck[min(max(lj, 0), kWin - 2) * (kWin - 1) + min(max(li, 0), kWin - 2)];
+    // (as the aligned 32-bit word holding the byte, inside the grid's
+    // 256-byte-padded buffer, which also keeps the compiler from merging
+    // the two reads into one generic-address load)
+    if (!inw) {
+        const uint32_t c = (uint32_t)(L.j * g.nr + L.i);
+        const uint32_t wd = *reinterpret_cast<const uint32_t*>(g.cell_kind + (c & ~3u));
+        ck = (int)((wd >> (8u * (c & 3u))) & 0xFFu);
+    }
+    if (ck == 0) return false;
     if (ck >= 2) {
         int id = ck - 2;
         atomicAdd(&s_abs[id < 2 ? id : 0], (unsigned long long)total_share((double)w));
         return true;
     }
     int64_t c[4];
-    node_shares(L, (double)w, g.invd, c);
+    node_shares(L, (double)w, g.invd[L.i], c);
     int n00 = L.j * g.w + L.i;
     int nodes[4] = {n00, n00 + 1, n00 + g.w, n00 + g.w + 1};
 #pragma unroll
@@ -84,13 +94,15 @@ __device__ __forceinline__ bool absorb(const Geo& g, const Loc& L, float w, int 
 // Deposit into the LDS window when all four nodes fall inside it, else
 // straight to the global grid (the result is identical: integer sums).
 // Returns 1 for a global-fallback deposit.
+// The radial factor of the particle's column comes from the window's LDS
+// copy s_invd (columns wi0 ... wi0 + kWin - 1) in the first case.
 template <int kWin>
 __device__ __forceinline__ unsigned int deposit(const Geo& g, const Loc& L, float w, unsigned long long* win,
-                                                int wi0, int wj0, unsigned long long* dep) {
+                                                const double* s_invd, int wi0, int wj0, unsigned long long* dep) {
     int64_t c[4];
-    node_shares(L, (double)w, g.invd, c);
     const int li = L.i - wi0, lj = L.j - wj0;
     if (li >= 0 && li + 1 < kWin && lj >= 0 && lj + 1 < kWin) {
+        node_shares(L, (double)w, s_invd[li], c);
         const int b = lj * kWin + li;
         atomicAdd(&win[b], (unsigned long long)c[0]);
         atomicAdd(&win[b + 1], (unsigned long long)c[1]);
@@ -98,6 +110,7 @@ __device__ __forceinline__ unsigned int deposit(const Geo& g, const Loc& L, floa
         atomicAdd(&win[b + kWin + 1], (unsigned long long)c[3]);
         return 0u;
     }
+    node_shares(L, (double)w, g.invd[L.i], c);
     const int n00 = L.j * g.w + L.i;
     atomicAdd(&dep[n00], (unsigned long long)c[0]);
     atomicAdd(&dep[n00 + 1], (unsigned long long)c[1]);
@@ -136,22 +149,15 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
-__device__ __forceinline__ void load9_guard(float* const* f, long long p, long long n, P9& s) {
-    if (p < n) {
-        s = load9(f, (uint32_t)p);
-    } else {
-        s.r = -1.0f;
-    }
-}
-
-// slot p of this step: in place, or through the permutation of a deferred sort
-__device__ __forceinline__ void load_slot(float* const* f, const float* const* src, const uint32_t* perm, long long p,
-                                          long long n, P9& s) {
-    if (p < n) {
-        s = perm ? load9(const_cast<float* const*>(src), perm[p]) : load9(f, (uint32_t)p);
-    } else {
-        s.r = -1.0f;
-    }
+// slot p of this step: in place, or through the permutation of a deferred
+// sort.  Unconditional (no branch, so the loads stay where they are
+// issued): a slot beyond the last, n - 1, is read in its place and the
+// caller ignores it.  Needs n >= 1.
+template <bool kMoved>
+__device__ __forceinline__ P9 load_slot(float* const* f, const float* const* src, const uint32_t* perm, long long p,
+                                        long long n) {
+    const uint32_t q = (uint32_t)(p < n ? p : n - 1);
+    return kMoved ? load9(const_cast<float* const*>(src), perm[q]) : load9(f, q);
 }
 
 // after a deferred sort the weight moves to the new buffer too
@@ -160,20 +166,26 @@ __device__ __forceinline__ void store_slot(float* const* f, uint32_t p, const P9
     if (moved) stf(f[8], p << 2, s.w);
 }
 
-// One time step for every particle of one species.  A block owns whole
-// chunks of 4096 consecutive slots and each of its wavefronts a contiguous
-// slice of 1024 of them, processed 64 at a time with the next 64 already
-// in flight; the chunks of one XCD are contiguous so neighbouring
-// (cell-sorted) chunks share that XCD's L2.  Colliding particles are
-// compacted by wavefront ballots into a per-wavefront LDS queue and
-// processed 64 at a time by full wavefronts; births are staged per
-// (chunk, wavefront) in slot order.  The deposit goes to an LDS window (the
-// tile of the chunk's first particle plus halo) flushed once per chunk.
-template <int kHalo>
-__global__ __launch_bounds__(kBlock) void k_particles(PushArgs a) {
+// One time step for every particle of one species.  A block of eight
+// wavefronts owns whole chunks of 8192 consecutive slots and each of its
+// wavefronts a contiguous slice of 1024 of them, processed 64 at a time
+// with the next 64 already in flight; the chunks of one XCD are contiguous
+// so neighbouring (cell-sorted) chunks share that XCD's L2.  Colliding
+// particles are compacted by wavefront ballots into a per-wavefront LDS
+// queue and processed 64 at a time by full wavefronts; births are staged
+// per slice in slot order.  A window (the tile of the chunk's first
+// particle plus halo) lives in LDS: E at its nodes, the radial factors of
+// its columns and the kinds of its cells are read there, and the deposit
+// goes there, flushed when the window moves.  So the only global traffic
+// of a particle inside the window is its own state.
+template <int kHalo, bool kMoved>
+__global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_particles(PushArgs a) {
     constexpr int kWin = win_nodes(kHalo);
     __shared__ unsigned long long win[kWin * kWin];
-    __shared__ unsigned int qslot[kWaves][kQW];
+    __shared__ float2 ewin[kWin * kWin];
+    __shared__ double s_invd[kWin];
+    __shared__ uint8_t s_ck[(kWin - 1) * (kWin - 1)];
+    __shared__ unsigned int qslot[kPushWaves][kQW];
     __shared__ int s_org[2];
     __shared__ unsigned long long s_abs[4];
     __shared__ unsigned int s_coll[4];
@@ -182,17 +194,17 @@ __global__ __launch_bounds__(kBlock) void k_particles(PushArgs a) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const Geo& g = a.g;
     const long long n = a.ctr->n_slots[a.sp];
-    const long long nch = (n + kChunk - 1) / kChunk;
+    const long long nch = (n + kPushChunk - 1) / kPushChunk;
     const int nx = 8;  // XCDs: consecutive block ids go round-robin over them
     const int xcd = blockIdx.x % nx, per = gridDim.x / nx, lb = blockIdx.x / nx;
     // this XCD's contiguous chunk range, taken by its blocks in turn, so the
     // chunks in flight on one XCD stay close together (shared L2)
     const long long c_begin = nch * xcd / nx, c_end = nch * (xcd + 1) / nx;
     float* const* f = a.f;
-    const bool moved = a.perm != nullptr;
+    constexpr bool moved = kMoved;
     unsigned int fallback = 0;
 
-    for (int k = tid; k < kWin * kWin; k += kBlock) win[k] = 0ull;
+    for (int k = tid; k < kWin * kWin; k += kPushBlock) win[k] = 0ull;
     if (tid < 4) { s_abs[tid] = 0ull; s_coll[tid] = 0u; }
     if (tid == 0) s_fallback = 0u;
 
@@ -202,7 +214,7 @@ __global__ __launch_bounds__(kBlock) void k_particles(PushArgs a) {
     bool vac = false, have = false;
     auto flush = [&]() {
         __syncthreads();
-        for (int k = tid; k < kWin * kWin; k += kBlock) {
+        for (int k = tid; k < kWin * kWin; k += kPushBlock) {
             const unsigned long long v = win[k];
             if (v != 0ull) {
                 const int gi = wi0 + k % kWin, gj = wj0 + k / kWin;
@@ -214,15 +226,15 @@ __global__ __launch_bounds__(kBlock) void k_particles(PushArgs a) {
     };
 
     for (long long chunk = c_begin + lb; chunk < c_end; chunk += per) {
-        const long long base = chunk * kChunk;
+        const long long base = chunk * kPushChunk;
         // LDS window origin: tile of the chunk's first live particle, plus halo
         if (wave == 0) {
             const long long p = base + lane;
             bool ok = false;
             Loc L;
             if (p < n) {
-                const uint32_t q = a.perm ? a.perm[p] : (uint32_t)p;
-                const float* const* rz = a.perm ? a.src : const_cast<const float* const*>(f);
+                const uint32_t q = kMoved ? a.perm[p] : (uint32_t)p;
+                const float* const* rz = kMoved ? a.src : const_cast<const float* const*>(f);
                 const float r = rz[0][q];
                 L = locate(r, rz[1][q], g);
                 ok = (r >= 0.0f) && L.inside;
@@ -241,22 +253,33 @@ __global__ __launch_bounds__(kBlock) void k_particles(PushArgs a) {
             wi0 = s_org[0];
             wj0 = s_org[1];
             have = true;
-            // are all domain cells of the window vacuum?
+            // the window's copies of E, of the radial factors and of the
+            // cell kinds (zero outside the domain); are all its domain
+            // cells vacuum?
+            for (int k = tid; k < kWin * kWin; k += kPushBlock) {
+                const int gi = wi0 + k % kWin, gj = wj0 + k / kWin;
+                ewin[k] = (gi >= 0 && gi <= g.nr && gj >= 0 && gj <= g.nz) ? a.E[gj * g.w + gi]
+                                                                           : make_float2(0.0f, 0.0f);
+            }
+            for (int k = tid; k < kWin; k += kPushBlock) {
+                const int gi = wi0 + k;
+                s_invd[k] = (gi >= 0 && gi < g.nr) ? g.invd[gi] : 0.0;
+            }
             bool cells_ok = true;
-            for (int k = tid; k < (kWin - 1) * (kWin - 1); k += kBlock) {
+            for (int k = tid; k < (kWin - 1) * (kWin - 1); k += kPushBlock) {
                 const int ci = wi0 + k % (kWin - 1), cj = wj0 + k / (kWin - 1);
-                if (ci >= 0 && ci < g.nr && cj >= 0 && cj < g.nz && g.cell_kind[cj * g.nr + ci] != 0)
-                    cells_ok = false;
+                const uint8_t ck = (ci >= 0 && ci < g.nr && cj >= 0 && cj < g.nz) ? g.cell_kind[cj * g.nr + ci] : 0;
+                s_ck[k] = ck;
+                if (ck != 0) cells_ok = false;
             }
             vac = __syncthreads_and(cells_ok) != 0;
         }
 
         const long long sbase = base + (long long)wave * kSlice;
-        const long long stage_row = chunk * kWaves + wave;
+        const long long stage_row = chunk * kPushWaves + wave;
         int qn = 0, nb = 0;
         unsigned int* ql = qslot[wave];
-        P9 cur, nxt;
-        load_slot(f, a.src, a.perm, sbase + lane, n, cur);
+        P9 cur = load_slot<kMoved>(f, a.src, a.perm, sbase + lane, n);
 
         auto run_queue = [&](int cnt) {
             // lanes < cnt each take one deferred collider, in queue (slot) order;
@@ -291,10 +314,10 @@ __global__ __launch_bounds__(kBlock) void k_particles(PushArgs a) {
             if (has) {
                 d1_predict(c, a.dt);
                 const Loc L2 = locate(c.r, c.z, g);
-                if (absorb<kWin>(g, L2, c.w, a.sign, s_abs, a.wallq, vac, wi0, wj0)) {
+                if (absorb<kWin>(g, L2, c.w, a.sign, s_abs, a.wallq, vac, wi0, wj0, s_ck)) {
                     kill(f, slot);
                 } else {
-                    fallback += deposit<kWin>(g, L2, c.w, win, wi0, wj0, a.dep);
+                    fallback += deposit<kWin>(g, L2, c.w, win, s_invd, wi0, wj0, a.dep);
                     store_slot(f, slot, c, moved);
                 }
             }
@@ -303,29 +326,43 @@ __global__ __launch_bounds__(kBlock) void k_particles(PushArgs a) {
         uint4 dec4 = make_uint4(0u, 0u, 0u, 0u);
         for (int it = 0; it < kRounds; ++it) {
             const long long p = sbase + (long long)it * 64 + lane;
-            if (it + 1 < kRounds) load_slot(f, a.src, a.perm, p + 64, n, nxt);
+            // the next round's state is requested first and pinned here by a
+            // scheduling barrier, so its latency hides behind this round
+            const P9 nxt = load_slot<kMoved>(f, a.src, a.perm, it + 1 < kRounds ? p + 64 : p, n);
+            __builtin_amdgcn_sched_barrier(0);
             // decision words of this lane's slots in rounds it .. it+3 (sbase is
             // a multiple of 256, so the four share one counter)
             if ((it & 3) == 0) dec4 = draw(decision_ctr((uint32_t)p), a.step, kPurposeDecide, a.sp, 0, a.key0, a.key1);
             const uint32_t dword = (it & 3) == 0 ? dec4.x : (it & 3) == 1 ? dec4.y : (it & 3) == 2 ? dec4.z : dec4.w;
             P9 s = cur;
             bool coll = false;
-            if (s.r >= 0.0f) {
+            if (p < n && s.r >= 0.0f) {
                 float Er, Ez;
-                gather_E(a.E, g, s.r, s.z, Er, Ez);
+                const EW ew = e_weights(g, s.r, s.z);
+                const int eli = ew.i - wi0, elj = ew.j - wj0;
+                {
+                    // read in the window (clamped into it), then replaced
+                    // from the global grid for a cell outside the window
+                    const int b = min(max(elj, 0), kWin - 2) * kWin + min(max(eli, 0), kWin - 2);
+                    e_combine(ew, ewin[b], ewin[b + 1], ewin[b + kWin], ewin[b + kWin + 1], Er, Ez);
+                }
+                if (!((unsigned)eli < (unsigned)(kWin - 1) && (unsigned)elj < (unsigned)(kWin - 1))) {
+                    const int n00 = ew.j * g.w + ew.i;
+                    e_combine(ew, a.E[n00], a.E[n00 + 1], a.E[n00 + g.w], a.E[n00 + g.w + 1], Er, Ez);
+                }
                 d1_correct(s, Er, Ez, a.qm, a.dt);
                 const Loc L = locate(s.r, s.z, g);
-                if (absorb<kWin>(g, L, s.w, a.sign, s_abs, a.wallq, vac, wi0, wj0)) {
+                if (absorb<kWin>(g, L, s.w, a.sign, s_abs, a.wallq, vac, wi0, wj0, s_ck)) {
                     kill(f, (uint32_t)p);
                 } else {
                     coll = dword < a.m.thresh;
                     if (!coll) {
                         d1_predict(s, a.dt);
                         const Loc L2 = locate(s.r, s.z, g);
-                        if (absorb<kWin>(g, L2, s.w, a.sign, s_abs, a.wallq, vac, wi0, wj0)) {
+                        if (absorb<kWin>(g, L2, s.w, a.sign, s_abs, a.wallq, vac, wi0, wj0, s_ck)) {
                             kill(f, (uint32_t)p);
                         } else {
-                            fallback += deposit<kWin>(g, L2, s.w, win, wi0, wj0, a.dep);
+                            fallback += deposit<kWin>(g, L2, s.w, win, s_invd, wi0, wj0, a.dep);
                             store_slot(f, (uint32_t)p, s, moved);
                         }
                     }
@@ -372,8 +409,9 @@ __global__ __launch_bounds__(kBlock) void k_particles(PushArgs a) {
 }
 
 static int grid_blocks() {
-    // persistent-style grid: 8 XCDs x 32 CUs x 4 blocks, a multiple of 8
-    return 1024;
+    // persistent-style grid: 8 XCDs x 32 CUs x 2 blocks of 8 wavefronts, a
+    // multiple of 8
+    return 512;
 }
 
 static Geo make_geo(pic_handle* h) {
@@ -431,10 +469,13 @@ void launch_particles(pic_handle* h, int sp) {
     a.key0 = (uint32_t)(h->cfg.run.seed & 0xFFFFFFFFu);
     a.key1 = (uint32_t)(h->cfg.run.seed >> 32);
     a.step = (uint32_t)(h->step + 1);
-    if (sp == 0)
-        hipLaunchKernelGGL(k_particles<24>, dim3(grid_blocks()), dim3(kBlock), 0, h->stream, a);
-    else
-        hipLaunchKernelGGL(k_particles<16>, dim3(grid_blocks()), dim3(kBlock), 0, h->stream, a);
+    if (sp == 0) {
+        if (moved) hipLaunchKernelGGL((k_particles<24, true>), dim3(grid_blocks()), dim3(kPushBlock), 0, h->stream, a);
+        else hipLaunchKernelGGL((k_particles<24, false>), dim3(grid_blocks()), dim3(kPushBlock), 0, h->stream, a);
+    } else {
+        if (moved) hipLaunchKernelGGL((k_particles<16, true>), dim3(grid_blocks()), dim3(kPushBlock), 0, h->stream, a);
+        else hipLaunchKernelGGL((k_particles<16, false>), dim3(grid_blocks()), dim3(kPushBlock), 0, h->stream, a);
+    }
     if (moved) {
         h->cur[sp] = 1 - h->cur[sp];
         h->pending[sp] = false;
@@ -450,7 +491,7 @@ constexpr int kSegRows = 1024;
 
 __global__ __launch_bounds__(kSegRows) void k_birth_segsum(const DevCounters* c, const int* cnt, int* segsum) {
     __shared__ int sh[kSegRows / 64];
-    const long long rows = (c->n_slots[0] + kChunk - 1) / kChunk * kWaves;
+    const long long rows = stage_rows(c->n_slots[0]);
     const long long nseg = (rows + kSegRows - 1) / kSegRows;
     for (long long b = blockIdx.x; b < nseg; b += gridDim.x) {
         const long long i = b * kSegRows + threadIdx.x;
@@ -471,7 +512,7 @@ __global__ __launch_bounds__(1024) void k_birth_scan(DevCounters* c, const int* 
                                                      long long cap_i) {
     __shared__ long long s_part[1024];
     const int tid = threadIdx.x;
-    const long long rows = (c->n_slots[0] + kChunk - 1) / kChunk * kWaves;
+    const long long rows = stage_rows(c->n_slots[0]);
     const long long nseg = (rows + kSegRows - 1) / kSegRows;
     long long carry = 0;
     for (long long b0 = 0; b0 < nseg; b0 += 1024) {
@@ -542,7 +583,7 @@ __device__ __forceinline__ void place_newborn(const Geo& g, float* const* f, lon
                     loc[(ck - 2) < 2 ? ck - 2 : 0] += (unsigned long long)total_share((double)s.w);
                 } else {
                     int64_t c[4];
-                    node_shares(L, (double)s.w, g.invd, c);
+                    node_shares(L, (double)s.w, g.invd[L.i], c);
                     int n00 = L.j * g.w + L.i;
                     int nodes[4] = {n00, n00 + 1, n00 + g.w, n00 + g.w + 1};
                     for (int k = 0; k < 4; ++k) {
@@ -564,7 +605,7 @@ __device__ __forceinline__ void place_newborn(const Geo& g, float* const* f, lon
     f[5][slot] = s.ar; f[6][slot] = s.at; f[7][slot] = s.az; f[8][slot] = s.w;
     if (!removed) {
         int64_t c[4];
-        node_shares(L, (double)s.w, g.invd, c);
+        node_shares(L, (double)s.w, g.invd[L.i], c);
         int n00 = L.j * g.w + L.i;
         atomicAdd(&dep[n00], (unsigned long long)c[0]);
         atomicAdd(&dep[n00 + 1], (unsigned long long)c[1]);
@@ -703,7 +744,7 @@ __global__ __launch_bounds__(kBlock) void k_predict_deposit(PDArgs a) {
             Loc L = locate(s.r, s.z, a.g);
             if (!L.inside) continue;
             int64_t c[4];
-            node_shares(L, (double)s.w, a.g.invd, c);
+            node_shares(L, (double)s.w, a.g.invd[L.i], c);
             int n00 = L.j * a.g.w + L.i;
             atomicAdd(&a.dep[n00], (unsigned long long)c[0]);
             atomicAdd(&a.dep[n00 + 1], (unsigned long long)c[1]);
@@ -773,7 +814,7 @@ __global__ __launch_bounds__(kBlock) void k_moments(MomArgs a) {
         const Loc L = locate(r, a.f[1][p], a.g);
         if (!L.inside) continue;
         int64_t c[4];
-        node_shares(L, (double)a.f[8][p], a.g.invd, c);
+        node_shares(L, (double)a.f[8][p], a.g.invd[L.i], c);
         const double vr = a.f[2][p], vt = a.f[3][p], vz = a.f[4][p];
         double v2 = vr * vr;
         v2 = v2 + vt * vt;

@@ -36,22 +36,22 @@ struct Loc {
 // fraction q & (2^F - 1).  Outside when !(r < R), !(z > 0), !(z < Z) or
 // the cell index leaves the grid; `edge` then names the edge crossed.
 // Grids have at most 4096 cells a side, so q < 2^32.
+// Written without branches: the products are clamped into the range of the
+// conversion, which changes nothing for a position inside the domain.
 __device__ __forceinline__ Loc locate(float r, float z, const Geo& g) {
+    const double rd = (double)r, zd = (double)z;
+    const bool okr = rd < g.R, okz0 = zd > 0.0, okz1 = zd < g.Z;
+    const uint32_t qr = (uint32_t)floor(fmin(fmax(rd * g.Sr, 0.0), 4294967295.0));
+    const uint32_t qz = (uint32_t)floor(fmin(fmax(zd * g.Sz, 0.0), 4294967295.0));
+    const int i = (int)(qr >> kFBits), j = (int)(qz >> kFBits);
+    const bool oki = i < g.nr, okj = j < g.nz;
     Loc L;
-    L.inside = 0; L.edge = 0; L.i = 0; L.j = 0; L.fr = 0; L.fz = 0;
-    double rd = (double)r, zd = (double)z;
-    if (!(rd < g.R)) { L.edge = 0; return L; }
-    if (!(zd > 0.0)) { L.edge = 1; return L; }
-    if (!(zd < g.Z)) { L.edge = 2; return L; }
-    uint32_t qr = (uint32_t)floor(rd * g.Sr);
-    uint32_t qz = (uint32_t)floor(zd * g.Sz);
-    int i = (int)(qr >> kFBits), j = (int)(qz >> kFBits);
-    if (i >= g.nr) { L.edge = 0; return L; }
-    if (j >= g.nz) { L.edge = 2; return L; }
-    L.i = i; L.j = j;
-    L.fr = qr & ((1u << kFBits) - 1u);
-    L.fz = qz & ((1u << kFBits) - 1u);
-    L.inside = 1;
+    L.inside = (okr && okz0 && okz1 && oki && okj) ? 1 : 0;
+    L.edge = !okr ? 0 : !okz0 ? 1 : !okz1 ? 2 : !oki ? 0 : 2;
+    L.i = L.inside ? i : 0;
+    L.j = L.inside ? j : 0;
+    L.fr = L.inside ? (qr & ((1u << kFBits) - 1u)) : 0u;
+    L.fz = L.inside ? (qz & ((1u << kFBits) - 1u)) : 0u;
     return L;
 }
 
@@ -61,10 +61,11 @@ __device__ __forceinline__ Loc locate(float r, float z, const Geo& g) {
 // linear.  Every product is rounded separately (no contraction), so the
 // result is the same on any IEEE machine.  Order: (i,j) (i+1,j) (i,j+1)
 // (i+1,j+1); the four sum to floor(W 2^K) exactly.
-__device__ __forceinline__ void node_shares(const Loc& L, double W, const double* invd, int64_t c[4]) {
+// invd_i = 2^-2F / (2i + 1) for the particle's column i.
+__device__ __forceinline__ void node_shares(const Loc& L, double W, double invd_i, int64_t c[4]) {
 #pragma clang fp contract(off)
     const uint64_t nrr = (((uint64_t)(2u * (uint32_t)L.i) * (uint64_t)L.fr) << kFBits) + (uint64_t)L.fr * (uint64_t)L.fr;
-    double wr = (double)nrr * invd[L.i];
+    double wr = (double)nrr * invd_i;
     double wrb = 1.0 - wr;
     double wz = (double)L.fz * 0x1p-20;
     double wzb = (double)((1u << kFBits) - L.fz) * 0x1p-20;
@@ -92,6 +93,9 @@ __device__ __forceinline__ int64_t total_share(double W) {
 // ---------------------------------------------------------------- Philox
 // Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11).
 __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+    // opaque to loop-invariant motion: the twenty round keys are rebuilt
+    // with scalar adds at every call instead of occupying scalar registers
+    asm volatile("" : "+s"(k0), "+s"(k1));
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
         uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c.x;
@@ -153,10 +157,13 @@ __device__ __forceinline__ void d1_predict(P9& p, float dt) {
     float h = 0.5f * dt;
     float vr = p.vr + h * p.ar, vt = p.vt + h * p.at, vz = p.vz + h * p.az;
     float X = p.r + dt * vr, Y = dt * vt;
-    float rn = sqrtf(X * X + Y * Y);
-    float c = 1.0f, s = 0.0f;
-    if (rn > 0.0f) {
-        float inv = 1.0f / rn;
+    // |(X, Y)| and the rotation from one reciprocal square root; below
+    // 2^-50 m the particle is taken to sit on the axis
+    const float rr = X * X + Y * Y;
+    float rn = 0.0f, c = 1.0f, s = 0.0f;
+    if (rr > 0x1p-100f) {
+        const float inv = __builtin_amdgcn_rsqf(rr);
+        rn = rr * inv;
         c = X * inv;
         s = Y * inv;
     }
@@ -170,21 +177,42 @@ __device__ __forceinline__ void d1_predict(P9& p, float dt) {
     p.at = -s * ar + c * at;
 }
 
-// E at a position with the cylindrical-volume weights (FP32).
+// Gather of E at a position with the cylindrical-volume weights (FP32):
+// the cell (i, j) and the weights of its nodes (i,j) (i+1,j) (i,j+1)
+// (i+1,j+1).
+struct EW {
+    int i, j;
+    float a0, a1, a2, a3;
+};
+
+__device__ __forceinline__ EW e_weights(const Geo& g, float r, float z) {
+    EW e;
+    const float x = r * g.inv_dr, y = z * g.inv_dz;
+    e.i = min(max((int)x, 0), g.nr - 1);
+    e.j = min(max((int)y, 0), g.nz - 1);
+    const float f = fminf(fmaxf(x - (float)e.i, 0.0f), 1.0f);
+    const float gz = fminf(fmaxf(y - (float)e.j, 0.0f), 1.0f);
+    const float fi = (float)e.i;
+    const float wr = f * (2.0f * fi + f) * __builtin_amdgcn_rcpf(2.0f * fi + 1.0f);
+    e.a0 = (1.0f - wr) * (1.0f - gz);
+    e.a1 = wr * (1.0f - gz);
+    e.a2 = (1.0f - wr) * gz;
+    e.a3 = wr * gz;
+    return e;
+}
+
+__device__ __forceinline__ void e_combine(const EW& e, float2 e00, float2 e10, float2 e01, float2 e11, float& Er,
+                                          float& Ez) {
+    Er = e.a0 * e00.x + e.a1 * e10.x + e.a2 * e01.x + e.a3 * e11.x;
+    Ez = e.a0 * e00.y + e.a1 * e10.y + e.a2 * e01.y + e.a3 * e11.y;
+}
+
+// E from the global node grid
 __device__ __forceinline__ void gather_E(const float2* __restrict__ E, const Geo& g, float r, float z,
                                          float& Er, float& Ez) {
-    float x = r * g.inv_dr, y = z * g.inv_dz;
-    int i = min(max((int)x, 0), g.nr - 1);
-    int j = min(max((int)y, 0), g.nz - 1);
-    float f = fminf(fmaxf(x - (float)i, 0.0f), 1.0f);
-    float gz = fminf(fmaxf(y - (float)j, 0.0f), 1.0f);
-    float fi = (float)i;
-    float wr = f * (2.0f * fi + f) / (2.0f * fi + 1.0f);
-    int n00 = j * g.w + i;
-    float2 e00 = E[n00], e10 = E[n00 + 1], e01 = E[n00 + g.w], e11 = E[n00 + g.w + 1];
-    float a0 = (1.0f - wr) * (1.0f - gz), a1 = wr * (1.0f - gz), a2 = (1.0f - wr) * gz, a3 = wr * gz;
-    Er = a0 * e00.x + a1 * e10.x + a2 * e01.x + a3 * e11.x;
-    Ez = a0 * e00.y + a1 * e10.y + a2 * e01.y + a3 * e11.y;
+    const EW e = e_weights(g, r, z);
+    const int n00 = e.j * g.w + e.i;
+    e_combine(e, E[n00], E[n00 + 1], E[n00 + g.w], E[n00 + g.w + 1], Er, Ez);
 }
 
 // --------------------------------------------------------------- MCC (FP32)

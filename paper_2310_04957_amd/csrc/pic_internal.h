@@ -13,12 +13,21 @@
 
 namespace pic {
 
-constexpr int kBlock = 256;           // threads per block for particle and sort kernels
-constexpr int kItems = 16;            // particles per thread per chunk
+constexpr int kBlock = 256;           // threads per block for sort and helper kernels
+constexpr int kItems = 16;            // particles per thread per sort chunk
 constexpr int kChunk = kBlock * kItems;
-constexpr int kWaves = kBlock / 64;   // wavefronts per block of the particle kernel
-constexpr int kStageCap = 256;        // staged ionisation births per chunk
-constexpr int kStageW = kStageCap / kWaves;   // ... per (chunk, wavefront)
+constexpr int kWaves = kBlock / 64;   // wavefronts per block of the sort kernels
+// the particle kernel: a block of kPushWaves wavefronts owns chunks of
+// kPushChunk consecutive slots, each wavefront a slice of kSlice of them
+constexpr int kPushWaves = 8;
+constexpr int kPushBlock = 64 * kPushWaves;
+constexpr int kSlice = 1024;
+constexpr int kPushChunk = kSlice * kPushWaves;
+constexpr int kStageW = 64;           // staged ionisation births per slice (one row per slice)
+// rows of the birth staging area for n slots (whole chunks)
+__host__ __device__ constexpr long long stage_rows(long long n) {
+    return (n + kPushChunk - 1) / kPushChunk * kPushWaves;
+}
 constexpr int kMaxLevels = 16;
 constexpr int kMaxCoarse = 320;       // active nodes of the coarsest multigrid level
 constexpr int kRedBlocks = 4096;      // partial sums of a grid reduction
@@ -76,6 +85,7 @@ struct pic_handle {
     uint32_t thresh[2];
     int64_t cap[2];
     int64_t max_chunks;
+    int64_t max_rows;             // birth staging rows
     // geometry (device)
     uint8_t* cell_kind;
     int8_t* node_kind;
