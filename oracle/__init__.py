@@ -36,7 +36,7 @@ class Config(C.Structure):
                 ("n0", C.c_double), ("Te_eV", C.c_double), ("Ti_eV", C.c_double),
                 ("steps_per_period", C.c_int32), ("sort_every", C.c_int32), ("sort_every_ion", C.c_int32),
                 ("seed", C.c_uint64), ("tol", C.c_double), ("max_iter", C.c_int32),
-                ("load", C.c_int32)]
+                ("load", C.c_int32), ("weights", C.c_int32), ("split", C.c_int32)]
 
 
 class Diag(C.Structure):
@@ -49,7 +49,8 @@ class Diag(C.Structure):
                 ("numax_violations", C.c_int64), ("solver_iters", C.c_int64),
                 ("solver_relres", C.c_double),
                 ("harm_U_re", C.c_double * 6), ("harm_U_im", C.c_double * 6),
-                ("harm_I_re", C.c_double * 6), ("harm_I_im", C.c_double * 6), ("elec", C.c_double * 12)]
+                ("harm_I_re", C.c_double * 6), ("harm_I_im", C.c_double * 6), ("elec", C.c_double * 12),
+                ("split_added", C.c_int64 * 2)]
 
 
 _lib = None
@@ -93,6 +94,9 @@ def lib():
         L.orc_circuit_vacuum.argtypes = [C.POINTER(Config), C.c_double, C.c_int64, P, P, P]
         L.orc_moments.argtypes = [P, C.c_int, P, P]
         L.orc_reflection.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, P]
+        L.orc_split_now.argtypes = [P, C.c_int32, C.POINTER(C.c_int64)]
+        L.orc_split_target.argtypes = [P, C.c_int32, C.c_int32]
+        L.orc_split_target.restype = C.c_double
         _lib = L
     return _lib
 
@@ -125,6 +129,8 @@ def make_config(w, load=True):
         setattr(cfg, f, run[f])
     cfg.tol, cfg.max_iter = sol["tol"], sol["max_iter"]
     cfg.load = 1 if load else 0
+    cfg.weights = run.get("weights", 0)
+    cfg.split = run.get("split", 0)
     return cfg
 
 
@@ -232,6 +238,18 @@ class Oracle:
         E = np.zeros(self.nn, dtype=np.int64)
         lib().orc_moments(self.h, sp, _ptr(N), _ptr(E))
         return N, E
+
+    def split_now(self, sp):
+        """One splitting pass over species sp (reading R32); returns the copies added."""
+        added = C.c_int64()
+        rc = lib().orc_split_now(self.h, sp, C.byref(added))
+        if rc != 0:
+            raise RuntimeError(f"orc_split_now failed ({rc})")
+        return added.value
+
+    def split_target(self, sp, i):
+        """Reference weight of cell column i (units of w_unit), reading R32."""
+        return lib().orc_split_target(self.h, sp, i)
 
     def tile_keys(self, r, z):
         r = np.ascontiguousarray(r, dtype=np.float64)

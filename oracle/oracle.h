@@ -55,6 +55,9 @@ typedef struct {
     double tol;
     int32_t max_iter;
     int32_t load; /* 1: Maxwellian uniform load at creation, 0: no particles */
+    /* [R32] weights: 0 equal; 1 per cell volume (equal count per vacuum cell).
+       split: 1 splits heavy particles at every tile sort of their species */
+    int32_t weights, split;
 } orc_config;
 
 typedef struct {
@@ -72,6 +75,7 @@ typedef struct {
     /* last complete period (Eqs. 11-14): Z_ccp re/im, Z_load re/im, |Gamma|,
        P_source, P_Rs, P_IMN, P_stray, P_ccp, P_forward, P_ref */
     double elec[12];
+    int64_t split_added[2]; /* particles added by splitting since creation */
 } orc_diag;
 
 typedef struct orc_sim orc_sim;
@@ -101,6 +105,10 @@ int orc_redeposit(orc_sim* s);
 int orc_get_grid(orc_sim* s, int32_t which, void* out);
 int orc_set_grid(orc_sim* s, int32_t which, const void* in);
 int orc_set_state(orc_sim* s, const double* st); /* t, Q_E, U_E, circ[5], C_eq */
+/* [R32] one splitting pass over a species now; *added = copies appended */
+int orc_split_now(orc_sim* s, int32_t species, int64_t* added);
+/* [R32] reference weight of a particle in cell column i (units of w_unit) */
+double orc_split_target(orc_sim* s, int32_t species, int32_t i);
 
 /* pure pieces, for pins */
 int orc_solve_q(orc_sim* s, const double* Q, const double* chi, double U_E, double tol,

@@ -42,6 +42,9 @@ struct orc_sim {
     double qm[2], mass[2];
     int sign[2];
     double w_unit, n_gas, nu_max[2], vth_gas;
+    double vvac, wref[2];   /* vacuum volume; loading weight of each species */
+    int nvac;               /* vacuum cells */
+    int64_t split_added[2];
     uint32_t thresh[2];
     /* grids */
     int64_t *dep[2], *wallq, *psum[2], *plast[2];
@@ -74,6 +77,7 @@ void o_efield(orc_sim* s);
 /* particles (orc_particles.c) */
 typedef struct { int inside, edge; int64_t qr, qz; int i, j; int64_t fr, fz; } o_loc;
 o_loc o_locate(const orc_sim* s, double r, double z);
+double o_split_target(const orc_sim* s, int sp, int i);
 void o_deposit_one(const orc_sim* s, double r, double z, double W, int64_t* grid);
 void o_node_weights(const orc_sim* s, const o_loc* L, double W, int64_t c[4]);
 void o_philox4x32(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);

@@ -393,6 +393,15 @@ int o_mcc1(orc_sim* s, int sp, double* v, uint32_t slot, uint32_t step, double* 
     return 3;
 }
 
+/* [R32] Reference weight in cell column i: the species' loading weight
+   times the column's cell volume over the mean vacuum-cell volume, so that
+   particles of this weight fill every cell with the same count. */
+double o_split_target(const orc_sim* s, int sp, int i) {
+    double r0 = i * s->dr, r1 = (i + 1) * s->dr;
+    double vi = O_PI * (r1 * r1 - r0 * r0) * s->dz;
+    return s->wref[sp] * vi * (double)s->nvac / s->vvac;
+}
+
 /* --------------------------------------------------------------- loader */
 /* Uniform plasma (Sec. 3, first paragraph): particles uniform in volume over
    the vacuum cells (cell chosen by inverse CDF of cell volume, then r^2 and
@@ -424,11 +433,19 @@ int o_load(orc_sim* s) {
             uint32_t x[4], y[4];
             draw(s, (uint32_t)k, 0, 0, sp, 0, x);
             draw(s, (uint32_t)k, 0, 0, sp, 1, y);
-            double target = o_u01(x[0]) * vvac;
-            int lo = 0, hi = nv - 1; /* first c with cdf[c] > target */
-            while (lo < hi) {
-                int mid = (lo + hi) / 2;
-                if (cdf[mid] > target) hi = mid; else lo = mid + 1;
+            int lo;
+            if (s->cfg.weights == 1) {
+                /* [R32] every vacuum cell equally likely, weight by cell volume */
+                lo = (int)floor(o_u01(x[0]) * (double)nv);
+                if (lo > nv - 1) lo = nv - 1;
+            } else {
+                double target = o_u01(x[0]) * vvac;
+                lo = 0; /* first c with cdf[c] > target */
+                int hi = nv - 1;
+                while (lo < hi) {
+                    int mid = (lo + hi) / 2;
+                    if (cdf[mid] > target) hi = mid; else lo = mid + 1;
+                }
             }
             int ci = cell[lo] % nr, cj = cell[lo] / nr;
             double r0 = ci * s->dr, r1 = (ci + 1) * s->dr;
@@ -441,7 +458,7 @@ int o_load(orc_sim* s) {
             P->vt[k] = vth * a * sin(b);
             P->vz[k] = vth * c * cos(e);
             P->ar[k] = P->at[k] = P->az[k] = 0.0; /* [R8] */
-            P->w[k] = W;
+            P->w[k] = (s->cfg.weights == 1) ? o_split_target(s, sp, ci) : W;
         }
         P->n = n;
     }

@@ -255,6 +255,49 @@ static void sort_species(orc_sim* s, int sp) {
     free(perm);
 }
 
+/* [R32] Particle splitting.  A live particle inside the domain whose weight
+   w (compared in single precision) is at least 2^m times the reference
+   weight of its cell column is replaced by k = 2^m identical particles of
+   weight w / k, m at most 3: the parent keeps its slot with weight w / k and
+   the k - 1 copies follow the last slot, in parent order.  Position,
+   velocity and averaged acceleration are copied, so charge, momentum and
+   kinetic energy are unchanged exactly (k is a power of two). */
+static int split_doublings(float w, float t) {
+    int m = 0;
+    while (m < 3 && w >= t * (float)(2 << m)) m++;
+    return m;
+}
+
+static int split_of(orc_sim* s, int sp, int64_t k) {
+    const o_parts* P = &s->p[sp];
+    if (!(P->r[k] >= 0.0)) return 0;
+    o_loc L = o_locate(s, P->r[k], P->z[k]);
+    if (!L.inside) return 0;
+    return split_doublings((float)P->w[k], (float)o_split_target(s, sp, L.i));
+}
+
+/* nothing changes when the copies would not fit (returns -2) */
+static int split_species(orc_sim* s, int sp, int64_t* added) {
+    o_parts* P = &s->p[sp];
+    int64_t n = P->n, m = n, total = 0;
+    double st[9];
+    for (int64_t k = 0; k < n; k++) total += (1 << split_of(s, sp, k)) - 1;
+    if (n + total > P->cap) return -2;
+    for (int64_t k = 0; k < n; k++) {
+        int d = split_of(s, sp, k);
+        if (d == 0) continue;
+        int kk = 1 << d;
+        get1(P, k, st);
+        st[8] = st[8] / kk;
+        put1(P, k, st);
+        for (int c = 1; c < kk; c++) put1(P, m++, st);
+    }
+    P->n = m;
+    s->split_added[sp] += m - n;
+    if (added) *added = m - n;
+    return 0;
+}
+
 /* ------------------------------------------------------------------ step */
 typedef struct { double r, z, W, v[6]; } o_birth;
 
@@ -344,8 +387,14 @@ static int step1(orc_sim* s) {
     free(births);
     if (rc) return rc;
     s->step++;
-    if (s->cfg.sort_every > 0 && s->step % s->cfg.sort_every == 0) sort_species(s, 0);
-    if (s->cfg.sort_every_ion > 0 && s->step % s->cfg.sort_every_ion == 0) sort_species(s, 1);
+    for (int sp = 0; sp < 2; sp++) {
+        int every = sp == 0 ? s->cfg.sort_every : s->cfg.sort_every_ion;
+        if (every > 0 && s->step % every == 0) {
+            /* [R32] splitting runs at the species' tile sort, before it */
+            if (s->cfg.split && split_species(s, sp, NULL)) return -2;
+            sort_species(s, sp);
+        }
+    }
     if (s->step % spp == 0) {
         o_laplace(s);
         memcpy(s->lastU, s->serU, sizeof(double) * spp);
@@ -419,13 +468,21 @@ int orc_create(const orc_config* cfg, orc_sim** out) {
     /* w_unit from the requested counts even when nothing is loaded */
     {
         double vv = 0.0;
+        int nv = 0;
         for (int j = 0; j < s->nz; j++)
             for (int i = 0; i < s->nr; i++)
                 if (s->cell_kind[j * s->nr + i] == 0) {
                     double r0 = i * s->dr, r1 = (i + 1) * s->dr;
                     vv += O_PI * (r1 * r1 - r0 * r0) * s->dz;
+                    nv++;
                 }
         s->w_unit = cfg->n0 * vv / (double)(cfg->n_e > 0 ? cfg->n_e : 1);
+        /* loading weight of each species from the requested counts [R32] */
+        s->vvac = vv;
+        s->nvac = nv;
+        int64_t nreq[2] = {cfg->n_e, cfg->n_i};
+        for (int sp = 0; sp < 2; sp++)
+            s->wref[sp] = (nreq[sp] > 0) ? (cfg->n0 * vv / (double)nreq[sp]) / s->w_unit : 1.0;
     }
     int rc = o_load(s);
     s->cfg = save;
@@ -547,6 +604,13 @@ void orc_reflection(double z_re, double z_im, double R_s, double P_source, doubl
     out3[2] = out3[1] * gam * gam;
 }
 
+int orc_split_now(orc_sim* s, int32_t sp, int64_t* added) {
+    if (sp < 0 || sp > 1) return -1;
+    return split_species(s, sp, added);
+}
+
+double orc_split_target(orc_sim* s, int32_t sp, int32_t i) { return o_split_target(s, sp, i); }
+
 int orc_diag_get(orc_sim* s, orc_diag* d) {
     memset(d, 0, sizeof(*d));
     d->t = s->t; d->U_E = s->U_E; d->Q_E = s->Q_E; d->C_eq = s->C_eq; d->Q_P = s->Q_P;
@@ -564,6 +628,8 @@ int orc_diag_get(orc_sim* s, orc_diag* d) {
         for (int c = 0; c < 4; c++) d->coll[sp][c] = s->coll[sp][c];
     }
     d->born = s->born;
+    d->split_added[0] = s->split_added[0];
+    d->split_added[1] = s->split_added[1];
     d->numax_violations = s->viol;
     d->solver_iters = s->solver_iters;
     d->solver_relres = s->solver_relres;
