@@ -103,6 +103,26 @@ def learned_vs_plain(sim, args, w):
     }
 
 
+def split_pass(sim):
+    """One particle-splitting pass per species on the discharge as it stands
+    (equal loading weights: particles near the axis are heavier than the
+    reference weight of their column), timed by the wall clock around the
+    synchronous call."""
+    res = {}
+    for sp, name in ((0, "e"), (1, "i")):
+        n0 = sim.diag().n_slots[sp]
+        t0 = time.perf_counter()
+        try:
+            added = sim.split_now(sp)
+        except Exception as e:  # the copies do not fit: reported, nothing changed
+            res[name] = {"error": str(e)}
+            continue
+        ms = 1e3 * (time.perf_counter() - t0)
+        res[name] = {"ms": ms, "slots": int(n0), "copies": int(added),
+                     "slots_per_s": n0 / (ms * 1e-3) if ms > 0 else None}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -120,6 +140,8 @@ def main():
     ap.add_argument("--learned-train-steps", type=int, default=150)
     ap.add_argument("--learned-batch", type=int, default=4)
     ap.add_argument("--learned-solve-steps", type=int, default=3)
+    ap.add_argument("--no-split-pass", action="store_true",
+                    help="skip timing one particle-splitting pass per species after the run")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain FP32 copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -217,6 +239,9 @@ def main():
     if learned:
         print("[bench] learned vs plain field solve", file=sys.stderr, flush=True)
         out["field_solve_learned_vs_plain"] = learned_vs_plain(sim, args, w)
+    if not args.no_split_pass:
+        print("[bench] particle-splitting pass", file=sys.stderr, flush=True)
+        out["split_pass"] = split_pass(sim)
     sim.close()
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)

@@ -56,6 +56,7 @@ enum { PIC_IDEAL_SOURCE = 0, PIC_SERIES_RLC = 1, PIC_LMATCH = 2 };    /* circuit
    (MG-PCG takes over when the network fails), or by CG without a
    preconditioner (the reference point of what the network gains) */
 enum { PIC_SOLVE_MGPCG_FP64 = 0, PIC_SOLVE_IR_MG = 1, PIC_SOLVE_IR_UNET = 2, PIC_SOLVE_IR_CG = 3 };
+enum { PIC_WEIGHTS_EQUAL = 0, PIC_WEIGHTS_CELL = 1 };                /* initial macro-particle weights */
 
 /* A rectangle [r0,r1) x [z0,z1) in metres.  Each cell takes the last region
    that contains its centre.  kind PIC_COND uses cond_id (0 ground, 1 the
@@ -96,6 +97,16 @@ typedef struct {
     uint64_t seed;              /* Philox key */
     int32_t load;               /* 1: load the Maxwellian plasma at init; 0: start empty */
     int32_t timing;             /* 1: time each phase with HIP events (pic_diag reports ms) */
+    /* Unequal weights and particle splitting (Sec. 3, particle splitting
+       against on-axis heating).  weights: PIC_WEIGHTS_EQUAL loads equal
+       weights uniformly in volume; PIC_WEIGHTS_CELL loads every vacuum cell
+       with the same expected count, each particle weighted by the volume of
+       its cell over the mean vacuum-cell volume (the reference weight of
+       the cell's column).  split = 1: at every tile sort of a species, a
+       particle whose weight is at least 2^m reference weights of its
+       column is first replaced by 2^m identical particles (m <= 3). */
+    int32_t weights;
+    int32_t split;
 } pic_run;
 
 typedef struct {
@@ -144,6 +155,7 @@ typedef struct {
        and the reflected power */
     double Z_ccp_re, Z_ccp_im, Z_load_re, Z_load_im, gamma_abs;
     double P_source, P_Rs, P_imn, P_stray, P_ccp, P_forward, P_ref;
+    int64_t split_added[2];     /* particles added by splitting since init, per species */
 } pic_diag_out;
 
 typedef struct {
@@ -203,6 +215,19 @@ int pic_redeposit(pic_handle* h);
 /* Tile sort of one species now (stable, dead slots dropped); perm_out (or
    NULL) receives, for each new slot, the old slot it came from. */
 int pic_sort_now(pic_handle* h, int32_t species, int64_t* perm_out);
+
+/* One particle-splitting pass over a species now (Sec. 3, particle
+   splitting): a live particle inside the domain in cell column i whose
+   weight w is at least 2 w_ref(i) becomes k = 2^m particles of weight w/k
+   (m the largest with w >= 2^m w_ref(i), at most 3; compared in FP32) with
+   the same position, velocity and averaged acceleration.  w_ref(i) = W_s
+   V_i / V_mean: W_s the species' loading weight (units of w_unit), V_i the
+   cell volume of column i, V_mean the mean vacuum-cell volume.  The parent
+   keeps its slot; the k - 1 copies follow the last slot in parent-slot
+   order.  *added (or NULL) receives the number of copies.  Returns
+   PIC_E_CAPACITY when the copies do not fit: no particle changes, and the
+   handle keeps the capacity error that pic_diag reports. */
+int pic_split_now(pic_handle* h, int32_t species, int64_t* added);
 
 /* One solve of Eq. (1) on given node charges Q (C) and susceptibility chi
    with the driven electrode at U_E; phi_inout is the warm start and the

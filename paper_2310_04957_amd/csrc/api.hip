@@ -50,6 +50,7 @@ int validate(const pic_config* c) {
     if (ci.kind == PIC_SERIES_RLC && !(ci.C_b > 0 && ci.L_b > 0)) return PIC_E_CONFIG;
     const pic_run& r = c->run;
     if (r.steps_per_period < 1 || r.n_e < 0 || r.n_i < 0 || r.cap_e < r.n_e || r.cap_i < r.n_i) return PIC_E_CONFIG;
+    if (r.weights < PIC_WEIGHTS_EQUAL || r.weights > PIC_WEIGHTS_CELL || r.split < 0 || r.split > 1) return PIC_E_CONFIG;
     if (r.cap_e > kMaxSlots || r.cap_i > kMaxSlots || r.sort_every < 0 || r.sort_every_ion < 0)
         return PIC_E_CONFIG;
     if (!(c->gas.p_Pa >= 0) || !(c->gas.T_gas_K > 0) || !(r.n0 >= 0)) return PIC_E_CONFIG;
@@ -307,6 +308,7 @@ size_t layout(pic_handle* h, char* base) {
     h->gr = c.take<double>(nn);
     h->gz = c.take<double>(nn);
     h->invd = c.take<double>((size_t)h->nr);
+    for (int sp = 0; sp < 2; ++sp) h->wtcol[sp] = c.take<float>((size_t)h->nr);
     size_t capmax = (size_t)std::max<int64_t>(std::max(h->cap[0], h->cap[1]), 1);
     for (int sp = 0; sp < 2; ++sp)
         for (int b = 0; b < 2; ++b)
@@ -319,6 +321,7 @@ size_t layout(pic_handle* h, char* base) {
     const size_t mch = (size_t)h->max_chunks;
     h->hist = c.take<uint32_t>(256 * mch);
     h->bsum = c.take<uint32_t>((256 * mch + 4095) / 4096 + 1);
+    h->split_off = c.take<long long>(mch + 1);
     const size_t mrows = (size_t)h->max_rows;
     h->stage = c.take<Birth>(mrows * kStageW);
     h->stage_cnt = c.take<int>(mrows);
@@ -479,6 +482,23 @@ int load_plasma(pic_handle* h) {
         }
     const double vvac = acc;
     h->w_unit = r.n0 * vvac / (double)(r.n_e > 0 ? r.n_e : 1);
+    // reference weight of each cell column (splitting, unequal-weight load):
+    // loading weight x column cell volume / mean vacuum-cell volume
+    {
+        const int64_t nreq[2] = {r.n_e, r.n_i};
+        const double nv = (double)cdf.size();
+        for (int sp = 0; sp < 2; ++sp) {
+            const double wref = nreq[sp] > 0 ? (r.n0 * vvac / (double)nreq[sp]) / h->w_unit : 1.0;
+            std::vector<float> wt((size_t)h->nr);
+            for (int i = 0; i < h->nr; ++i) {
+                const double r0 = i * h->dr, r1 = (i + 1) * h->dr;
+                const double vi = kPi * (r1 * r1 - r0 * r0) * h->dz;
+                wt[(size_t)i] = (float)(wref * vi * nv / vvac);
+            }
+            HIP_OK(hipMemcpyAsync(h->wtcol[sp], wt.data(), wt.size() * 4, hipMemcpyHostToDevice, h->stream));
+        }
+        HIP_OK(hipStreamSynchronize(h->stream));
+    }
     h->qunit = kQE * h->w_unit * std::ldexp(1.0, -kKBits);
     const double base = 0.5 * h->dt * h->dt * kQE * kQE * h->w_unit * std::ldexp(1.0, -kKBits) / kEps0;
     h->chi_c[0] = base / kME;
@@ -685,7 +705,10 @@ int pic_step(pic_handle* h, int32_t nsteps) {
         if (se || si) {
             // deferred: the particles move during the next particle step
             ev_record(h, -1, &b3);
+            // particle splitting runs at a species' tile sort, before it
+            if (se && c.run.split) launch_split(h, 0);
             if (se) launch_sort(h, 0, true);
+            if (si && c.run.split) launch_split(h, 1);
             if (si) launch_sort(h, 1, true);
             ev_record(h, 3, &b3);
         }
@@ -756,6 +779,8 @@ int pic_diag(pic_handle* h, pic_diag_out* out, const pic_diag_buffers* bufs) {
     out->unet_pairs = h->net.n_pairs;
     out->unet_fallbacks = h->unet_fallbacks;
     out->unet_applications = h->unet_apps;
+    out->split_added[0] = ct.split_added[0];
+    out->split_added[1] = ct.split_added[1];
     const int spp = h->cfg.run.steps_per_period;
     std::vector<double> U(spp), I(spp);
     if (hipMemcpy(U.data(), h->lastU, spp * 8, hipMemcpyDeviceToHost) != hipSuccess) return PIC_E_HIP;
@@ -919,6 +944,17 @@ int pic_sort_now(pic_handle* h, int32_t species, int64_t* perm_out) {
             return PIC_E_HIP;
         for (int64_t k = 0; k < n; ++k) perm_out[k] = p[k];
     }
+    return PIC_OK;
+}
+
+int pic_split_now(pic_handle* h, int32_t species, int64_t* added) {
+    if (!h || species < 0 || species > 1) return PIC_E_ARG;
+    launch_split(h, species);
+    int rc = sync_err(h);
+    if (rc) return rc;
+    const long long t = h->h_ctr->split_total;
+    if (t < 0) return PIC_E_CAPACITY;
+    if (added) *added = t;
     return PIC_OK;
 }
 

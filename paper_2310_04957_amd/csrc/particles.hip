@@ -679,20 +679,29 @@ struct LoadArgs {
     float W, vth;
     int sp;
     uint32_t key0, key1;
+    int weights;              // PIC_WEIGHTS_CELL: cell uniform over vacuum cells, weight wt[column]
+    const float* wt;
 };
 
 // Uniform plasma (Sec. 3, first paragraph): a vacuum cell by inverse CDF of
-// cell volume, r^2 and z uniform inside it, Maxwellian velocity.
+// cell volume (equal weights) or uniformly over the vacuum cells with the
+// weight of the cell's column (unequal weights), r^2 and z uniform inside
+// it, Maxwellian velocity.
 __global__ __launch_bounds__(kBlock) void k_load(LoadArgs a) {
     for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < a.n;
          p += (long long)gridDim.x * blockDim.x) {
         uint4 x = draw((uint32_t)p, 0u, kPurposeLoad, a.sp, 0, a.key0, a.key1);
         uint4 y = draw((uint32_t)p, 0u, kPurposeLoad, a.sp, 1, a.key0, a.key1);
-        double target = (double)u01(x.x) * a.vvac;
-        int lo = 0, hi = a.nv - 1;
-        while (lo < hi) {
-            int mid = (lo + hi) >> 1;
-            if (a.cdf[mid] > target) hi = mid; else lo = mid + 1;
+        int lo = 0;
+        if (a.weights == PIC_WEIGHTS_CELL) {
+            lo = min((int)floor((double)u01(x.x) * (double)a.nv), a.nv - 1);
+        } else {
+            const double target = (double)u01(x.x) * a.vvac;
+            int hi = a.nv - 1;
+            while (lo < hi) {
+                int mid = (lo + hi) >> 1;
+                if (a.cdf[mid] > target) hi = mid; else lo = mid + 1;
+            }
         }
         int c = a.cell[lo];
         int ci = c % a.nr, cj = c / a.nr;
@@ -704,7 +713,7 @@ __global__ __launch_bounds__(kBlock) void k_load(LoadArgs a) {
         a.f[0][p] = (float)r; a.f[1][p] = (float)z;
         a.f[2][p] = vr; a.f[3][p] = vt; a.f[4][p] = vz;
         a.f[5][p] = 0.0f; a.f[6][p] = 0.0f; a.f[7][p] = 0.0f;
-        a.f[8][p] = a.W;
+        a.f[8][p] = a.weights == PIC_WEIGHTS_CELL ? a.wt[ci] : a.W;
     }
 }
 
@@ -717,6 +726,8 @@ void launch_load(pic_handle* h, int sp, const double* cdf, const int* cell, int 
     a.n = n; a.W = W; a.vth = vth; a.sp = sp;
     a.key0 = (uint32_t)(h->cfg.run.seed & 0xFFFFFFFFu);
     a.key1 = (uint32_t)(h->cfg.run.seed >> 32);
+    a.weights = h->cfg.run.weights;
+    a.wt = h->wtcol[sp];
     if (n > 0) hipLaunchKernelGGL(k_load, dim3(2048), dim3(kBlock), 0, h->stream, a);
 }
 

@@ -45,6 +45,8 @@ struct DevCounters {
     long long base[2];
     long long nch_births;
     unsigned int dead[2];
+    long long split_total;        // copies of the current splitting pass (-1: they do not fit)
+    long long split_added[2];     // copies since init, per species
     long long pad[4];
 };
 
@@ -101,6 +103,10 @@ struct pic_handle {
     bool pending[2];          // a sort whose particle movement is still to be applied
     uint32_t* hist;
     uint32_t* bsum;
+    // particle splitting: reference weight per cell column, per species;
+    // per-chunk copy counts and offsets of a pass
+    float* wtcol[2];
+    long long* split_off;
     // births
     pic::Birth* stage;
     int *stage_cnt, *stage_off, *stage_segoff;   // stage_off holds segment sums
@@ -173,6 +179,7 @@ void launch_moments(pic_handle* h, int sp, unsigned long long* N, unsigned long 
 
 // sort
 void launch_sort(pic_handle* h, int sp, bool deferred = false);
+void launch_split(pic_handle* h, int sp);
 void materialize(pic_handle* h, int sp);
 
 // field

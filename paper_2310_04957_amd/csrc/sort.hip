@@ -296,4 +296,161 @@ void materialize(pic_handle* h, int sp) {
     h->pending[sp] = false;
 }
 
+// ---------------------------------------------------- particle splitting
+// (Sec. 3, particle splitting against on-axis heating.)  A live particle
+// inside the domain whose weight is at least 2^m reference weights of its
+// cell column (m <= 3, compared in FP32) becomes 2^m identical particles of
+// a 2^m-th of the weight: the parent keeps its slot, the copies follow the
+// last slot in parent-slot order.  Three passes over the chunks of kChunk
+// slots: count, one exclusive scan of the chunk counts, write (the count is
+// recomputed, so no per-slot storage); order comes from block scans, never
+// from atomics, so the result is deterministic.
+struct SplitArgs {
+    Geo g;
+    float* f[9];
+    const float* wt;          // reference weight per cell column
+    DevCounters* ctr;
+    long long* off;           // per chunk: copies, then their exclusive offsets
+    long long cap;
+    int sp;
+};
+
+__device__ __forceinline__ int split_doublings(float w, float t) {
+    int m = 0;
+    while (m < 3 && w >= t * (float)(2 << m)) ++m;
+    return m;
+}
+
+__device__ __forceinline__ int split_m(const SplitArgs& a, long long p) {
+    const float r = a.f[0][p];
+    if (!(r >= 0.0f)) return 0;
+    const Loc L = locate(r, a.f[1][p], a.g);
+    if (!L.inside) return 0;
+    return split_doublings(a.f[8][p], a.wt[L.i]);
+}
+
+// exclusive scan of v over the block (kBlock threads); *total gets the sum
+__device__ __forceinline__ int block_exscan(int v, int* sh, int* total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) sh[wave] = x;
+    __syncthreads();
+    int before = 0, all = 0;
+    for (int w2 = 0; w2 < kBlock / 64; ++w2) {
+        if (w2 < wave) before += sh[w2];
+        all += sh[w2];
+    }
+    __syncthreads();
+    *total = all;
+    return before + x - v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_split_count(SplitArgs a) {
+    __shared__ int sh[kBlock / 64];
+    const long long n = a.ctr->n_slots[a.sp];
+    const long long nch = (n + kChunk - 1) / kChunk;
+    for (long long c = blockIdx.x; c < nch; c += gridDim.x) {
+        int cnt = 0;
+        for (int it = 0; it < kItems; ++it) {
+            const long long p = c * kChunk + (long long)it * kBlock + threadIdx.x;
+            if (p < n) cnt += (1 << split_m(a, p)) - 1;
+        }
+        int total;
+        block_exscan(cnt, sh, &total);
+        if (threadIdx.x == 0) a.off[c] = total;
+    }
+}
+
+// one block: chunk counts -> exclusive offsets; the pass is cancelled
+// (split_total = -1, capacity error) when the copies do not fit
+__global__ __launch_bounds__(1024) void k_split_scan(SplitArgs a) {
+    __shared__ long long sh[1024];
+    const long long n = a.ctr->n_slots[a.sp];
+    const long long nch = (n + kChunk - 1) / kChunk;
+    const long long per = (nch + 1023) / 1024;
+    const long long b0 = threadIdx.x * per, b1 = min(nch, b0 + per);
+    long long s = 0;
+    for (long long c = b0; c < b1; ++c) s += a.off[c];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const long long y = threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += y;
+        __syncthreads();
+    }
+    long long run = sh[threadIdx.x] - s;
+    for (long long c = b0; c < b1; ++c) {
+        const long long v = a.off[c];
+        a.off[c] = run;
+        run += v;
+    }
+    if (threadIdx.x == 1023) {
+        const long long total = sh[1023];
+        if (n + total > a.cap) {
+            a.ctr->split_total = -1;
+            atomicMax(&a.ctr->err, 2);
+        } else {
+            a.ctr->split_total = total;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_split_write(SplitArgs a) {
+    __shared__ int sh[kBlock / 64];
+    if (a.ctr->split_total <= 0) return;
+    const long long n = a.ctr->n_slots[a.sp];
+    const long long nch = (n + kChunk - 1) / kChunk;
+    for (long long c = blockIdx.x; c < nch; c += gridDim.x) {
+        long long out = n + a.off[c];
+        for (int it = 0; it < kItems; ++it) {
+            const long long p = c * kChunk + (long long)it * kBlock + threadIdx.x;
+            const int m = (p < n) ? split_m(a, p) : 0;
+            const int e = (1 << m) - 1;
+            int total;
+            const int ex = block_exscan(e, sh, &total);
+            if (e > 0) {
+                float v[9];
+                for (int k = 0; k < 9; ++k) v[k] = a.f[k][p];
+                v[8] = v[8] / (float)(1 << m);
+                a.f[8][p] = v[8];
+                for (int q = 0; q < e; ++q)
+                    for (int k = 0; k < 9; ++k) a.f[k][out + ex + q] = v[k];
+            }
+            out += total;
+        }
+    }
+}
+
+__global__ void k_split_commit(DevCounters* c, int sp) {
+    if (c->split_total > 0) {
+        c->n_slots[sp] += c->split_total;
+        c->split_added[sp] += c->split_total;
+    }
+}
+
+void launch_split(pic_handle* h, int sp) {
+    materialize(h, sp);
+    SplitArgs a;
+    a.g.nr = h->nr; a.g.nz = h->nz; a.g.w = h->w;
+    a.g.R = h->cfg.geom.R; a.g.Z = h->cfg.geom.Z; a.g.Sr = h->Sr; a.g.Sz = h->Sz;
+    a.g.inv_dr = (float)(1.0 / h->dr); a.g.inv_dz = (float)(1.0 / h->dz);
+    a.g.invd = h->invd; a.g.cell_kind = h->cell_kind; a.g.node_kind = h->node_kind;
+    for (int k = 0; k < 3; ++k) a.g.edge_bc[k] = h->cfg.geom.edge_bc[k];
+    for (int k = 0; k < 9; ++k) a.f[k] = h->buf[sp][h->cur[sp]].f[k];
+    a.wt = h->wtcol[sp];
+    a.ctr = h->ctr;
+    a.off = h->split_off;
+    a.cap = h->cap[sp];
+    a.sp = sp;
+    hipLaunchKernelGGL(k_split_count, dim3(2048), dim3(kBlock), 0, h->stream, a);
+    hipLaunchKernelGGL(k_split_scan, dim3(1), dim3(1024), 0, h->stream, a);
+    hipLaunchKernelGGL(k_split_write, dim3(2048), dim3(kBlock), 0, h->stream, a);
+    hipLaunchKernelGGL(k_split_commit, dim3(1), dim3(1), 0, h->stream, h->ctr, sp);
+}
+
 }  // namespace pic

@@ -16,6 +16,7 @@ ABI_VERSION = 1
 MAX_REGIONS = 32
 FIELDS = ("r", "z", "vr", "vt", "vz", "ar", "at", "az", "w")
 SOLVE_MGPCG_FP64, SOLVE_IR_MG, SOLVE_IR_UNET, SOLVE_IR_CG = 0, 1, 2, 3
+WEIGHTS_EQUAL, WEIGHTS_CELL = 0, 1
 GRIDS = dict(DEP_E=0, DEP_I=1, PHI=2, ER=3, EZ=4, CHI=5, WALLQ=6, PHI_L=10, Q=11, AR=12, AZ=13)
 ERRORS = {0: "ok", -1: "PIC_E_CONFIG", -2: "PIC_E_CAPACITY", -3: "PIC_E_SOLVER", -4: "PIC_E_HIP",
           -5: "PIC_E_NONFINITE", -6: "PIC_E_STATE", -7: "PIC_E_ARG", -8: "PIC_E_NODEVICE"}
@@ -52,7 +53,7 @@ class Run(C.Structure):
                 ("n0", C.c_double), ("Te_eV", C.c_double), ("Ti_eV", C.c_double),
                 ("steps_per_period", C.c_int32), ("sort_every", C.c_int32), ("sort_every_ion", C.c_int32),
                 ("seed", C.c_uint64),
-                ("load", C.c_int32), ("timing", C.c_int32)]
+                ("load", C.c_int32), ("timing", C.c_int32), ("weights", C.c_int32), ("split", C.c_int32)]
 
 
 class Solver(C.Structure):
@@ -79,7 +80,8 @@ class Diag(C.Structure):
         ("timed_steps", C.c_int64), ("deposit_fallback", C.c_int64), ("error", C.c_int32),
         ("unet_pairs", C.c_int64), ("unet_fallbacks", C.c_int64), ("unet_applications", C.c_int64)] + [
         (f, C.c_double) for f in ("Z_ccp_re", "Z_ccp_im", "Z_load_re", "Z_load_im", "gamma_abs", "P_source",
-                                  "P_Rs", "P_imn", "P_stray", "P_ccp", "P_forward", "P_ref")]
+                                  "P_Rs", "P_imn", "P_stray", "P_ccp", "P_forward", "P_ref")] + [
+        ("split_added", C.c_int64 * 2)]
 
 
 class DiagBuffers(C.Structure):
@@ -111,6 +113,7 @@ def lib():
         L.pic_set_grid.argtypes = [P, C.c_int32, P]
         L.pic_redeposit.argtypes = [P]
         L.pic_sort_now.argtypes = [P, C.c_int32, P]
+        L.pic_split_now.argtypes = [P, C.c_int32, C.POINTER(C.c_int64)]
         L.pic_solve_once.argtypes = [P, P, P, C.c_double, C.c_double, P, C.POINTER(C.c_int32),
                                      C.POINTER(C.c_double)]
         L.pic_set_state.argtypes = [P, P]
@@ -160,6 +163,8 @@ def make_config(w, load=True, timing=False, method=None, inner_tol=1e-4, unet_ba
         setattr(cfg.run, f, run[f])
     cfg.run.load = 1 if load else 0
     cfg.run.timing = 1 if timing else 0
+    cfg.run.weights = run.get("weights", 0)
+    cfg.run.split = run.get("split", 0)
     cfg.solver.method = sol["method"] if method is None else method
     cfg.solver.tol, cfg.solver.max_iter = sol["tol"], sol["max_iter"]
     cfg.solver.inner_tol = inner_tol
@@ -262,6 +267,12 @@ class Pic:
         perm = np.zeros(max(self.cap[sp], 1), dtype=np.int64)
         _check(lib().pic_sort_now(self.h, sp, _ptr(perm)), "pic_sort_now")
         return perm
+
+    def split_now(self, sp):
+        """One particle-splitting pass over species sp; returns the copies added."""
+        added = C.c_int64()
+        _check(lib().pic_split_now(self.h, sp, C.byref(added)), "pic_split_now")
+        return added.value
 
     def solve_once(self, Q, chi, U_E, tol, phi0=None):
         Q = np.ascontiguousarray(Q, dtype=np.float64)

@@ -239,3 +239,69 @@ def test_energy_moments_bit_exact(sp):
     assert np.array_equal(E, Eo)
     assert E.sum() > 0
     gp.close()
+
+
+@pytest.mark.parametrize("sp", [0, 1])
+def test_split_bit_exact(sp):
+    """Particle splitting (Sec. 3): the same copies, weights and slot order as
+    the oracle, bit for bit, over several chunks with a ragged tail, dead
+    slots and particles outside the domain."""
+    w = _small_gec(n=0, cap_e=120000, cap_i=120000)
+    w["run"]["n_e"], w["run"]["n_i"] = 20000, 10000   # the loading weights (not loaded)
+    g = w["geometry"]
+    gp = _pic(w, load=False)
+    o = O.Oracle(w, load=False)
+    p = random_particles(30001, g["R"], g["Z"], seed=41 + sp, wmin=0.01, wmax=8.0, dead_frac=0.03)
+    p["z"][::97] = np.float32(g["Z"] * 1.01)          # outside: never split
+    gp.set_particles(sp, p)
+    o.set_particles(sp, _f64(p))
+    ag = gp.split_now(sp)
+    ao = o.split_now(sp)
+    assert ag == ao and ag > 1000
+    qg, qo = gp.particles(sp), o.particles(sp)
+    for f in qg:
+        oo = qo[f].astype(np.float32)
+        assert np.array_equal(oo.astype(np.float64), qo[f]), f   # oracle values are FP32 values
+        assert np.array_equal(qg[f].view(np.uint32), oo.view(np.uint32)), f
+    assert gp.diag().split_added[sp] == ag
+    gp.close()
+
+
+def test_cell_weighted_load_matches_oracle():
+    """Unequal-weight load: same cells, positions to FP32 rounding, weights
+    the FP32 of the oracle's."""
+    w = workload("pp32x24", run=dict(weights=1))
+    g = _pic(w)
+    o = O.Oracle(w)
+    for sp in (0, 1):
+        pg, po = g.particles(sp), o.particles(sp)
+        assert len(pg["r"]) == len(po["r"])
+        alive = (pg["r"] >= 0) & (po["r"] >= 0)
+        assert (alive == (po["r"] >= 0)).mean() > 0.999
+        for f in ("r", "z", "vr", "vt", "vz"):
+            a, b = pg[f][alive].astype(np.float64), po[f][alive]
+            assert np.max(np.abs(a - b)) <= 2e-6 * (np.max(np.abs(b)) + 1e-30), f
+        assert np.array_equal(pg["w"][alive], po["w"][alive].astype(np.float32))
+    g.close()
+
+
+def test_step_splits_at_the_sort_and_keeps_the_charge():
+    """Two identical GPU runs, one with splitting: at the first electron
+    sort the split run has split_added more electrons and the same total
+    weight (as exact sums of FP32 weights)."""
+    from fractions import Fraction
+    w = workload("pp32x24", run=dict(n_e=8000, n_i=8000, cap_e=60000, cap_i=60000, sort_every=3,
+                                     sort_every_ion=3))
+    wa = workload("pp32x24", run=dict(w["run"], split=1))
+    a, b = _pic(wa), _pic(w)
+    a.step(3)
+    b.step(3)
+    da, db = a.diag(), b.diag()
+    assert da.split_added[0] > 0
+    assert da.n_alive[0] == db.n_alive[0] + da.split_added[0]
+    pa, pb = a.particles(0), b.particles(0)
+    sa = sum(Fraction(float(x)) for x in pa["w"][pa["r"] >= 0])
+    sb = sum(Fraction(float(x)) for x in pb["w"][pb["r"] >= 0])
+    assert sa == sb
+    a.close()
+    b.close()
