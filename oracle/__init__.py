@@ -15,11 +15,18 @@ FIELDS = ("r", "z", "vr", "vt", "vz", "ar", "at", "az", "w")
 G = dict(DEP_E=0, DEP_I=1, PHI=2, ER=3, EZ=4, CHI=5, WALLQ=6, NODE_KIND=7, CELL_KIND=8,
          VOL=9, PHI_L=10, Q=11, AR=12, AZ=13, NE_AVG=14, NI_AVG=15)
 MAX_REGIONS = 32
+MAX_EL = 4
+CIRC_FIELDS = ("freq", "U_amp", "U_dc", "R_s", "C_m1", "C_m2", "L_m", "R_m", "C_stray", "L_stray", "R_stray",
+               "C_b", "R_b", "L_b")
 
 
 class Region(C.Structure):
     _fields_ = [("r0", C.c_double), ("r1", C.c_double), ("z0", C.c_double), ("z1", C.c_double),
                 ("kind", C.c_int32), ("cond_id", C.c_int32), ("eps_r", C.c_double)]
+
+
+class Circ(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("substeps", C.c_int32)] + [(f, C.c_double) for f in CIRC_FIELDS]
 
 
 class Config(C.Structure):
@@ -36,7 +43,8 @@ class Config(C.Structure):
                 ("n0", C.c_double), ("Te_eV", C.c_double), ("Ti_eV", C.c_double),
                 ("steps_per_period", C.c_int32), ("sort_every", C.c_int32), ("sort_every_ion", C.c_int32),
                 ("seed", C.c_uint64), ("tol", C.c_double), ("max_iter", C.c_int32),
-                ("load", C.c_int32), ("weights", C.c_int32), ("split", C.c_int32)]
+                ("load", C.c_int32), ("weights", C.c_int32), ("split", C.c_int32),
+                ("n_el", C.c_int32), ("circ_el", Circ * (MAX_EL - 1))]
 
 
 class Diag(C.Structure):
@@ -50,7 +58,13 @@ class Diag(C.Structure):
                 ("solver_relres", C.c_double),
                 ("harm_U_re", C.c_double * 6), ("harm_U_im", C.c_double * 6),
                 ("harm_I_re", C.c_double * 6), ("harm_I_im", C.c_double * 6), ("elec", C.c_double * 12),
-                ("split_added", C.c_int64 * 2)]
+                ("split_added", C.c_int64 * 2),
+                ("n_el", C.c_int32), ("U_el", C.c_double * MAX_EL), ("Q_el", C.c_double * MAX_EL),
+                ("QP_el", C.c_double * MAX_EL), ("I_el", C.c_double * MAX_EL),
+                ("C_el", C.c_double * (MAX_EL * MAX_EL)),
+                ("hU_re", (C.c_double * 6) * MAX_EL), ("hU_im", (C.c_double * 6) * MAX_EL),
+                ("hI_re", (C.c_double * 6) * MAX_EL), ("hI_im", (C.c_double * 6) * MAX_EL),
+                ("absorbed_el", (C.c_int64 * MAX_EL) * 2)]
 
 
 _lib = None
@@ -95,6 +109,8 @@ def lib():
         L.orc_moments.argtypes = [P, C.c_int, P, P]
         L.orc_reflection.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, P]
         L.orc_split_now.argtypes = [P, C.c_int32, C.POINTER(C.c_int64)]
+        L.orc_solve_qv.argtypes = [P, P, P, P, C.c_double, P, C.POINTER(C.c_int32), C.POINTER(C.c_double)]
+        L.orc_get_phiL.argtypes = [P, C.c_int32, P]
         L.orc_split_target.argtypes = [P, C.c_int32, C.c_int32]
         L.orc_split_target.restype = C.c_double
         _lib = L
@@ -131,6 +147,14 @@ def make_config(w, load=True):
     cfg.load = 1 if load else 0
     cfg.weights = run.get("weights", 0)
     cfg.split = run.get("split", 0)
+    more = w.get("circuits_more", [])
+    if len(more) > MAX_EL - 1:
+        raise ValueError("too many driven electrodes")
+    cfg.n_el = 1 + len(more)
+    for e, ce in enumerate(more):
+        cfg.circ_el[e].kind, cfg.circ_el[e].substeps = ce["kind"], ce["substeps"]
+        for f in CIRC_FIELDS:
+            setattr(cfg.circ_el[e], f, ce[f])
     return cfg
 
 
@@ -217,6 +241,31 @@ class Oracle:
         rel = C.c_double()
         rc = lib().orc_solve_q(self.h, _ptr(Q), _ptr(chi), U_E, tol, _ptr(phi), C.byref(it), C.byref(rel))
         return phi, it.value, rel.value, rc
+
+    def solve_qv(self, Q, chi, U, tol=1e-12, phi0=None):
+        """One solve with driven electrode e at U[e - 1] (reading R33)."""
+        Q = np.ascontiguousarray(Q, dtype=np.float64)
+        chi = np.ascontiguousarray(chi, dtype=np.float64)
+        Uv = np.zeros(MAX_EL)
+        Uv[:len(U)] = U
+        phi = np.zeros(self.nn) if phi0 is None else np.array(phi0, dtype=np.float64)
+        it = C.c_int32()
+        rel = C.c_double()
+        rc = lib().orc_solve_qv(self.h, _ptr(Q), _ptr(chi), _ptr(Uv), tol, _ptr(phi), C.byref(it), C.byref(rel))
+        return phi, it.value, rel.value, rc
+
+    def phi_laplace(self, e):
+        """Laplace solution of driven electrode e (1-based) at 1 V, the others grounded."""
+        a = np.zeros(self.nn)
+        if lib().orc_get_phiL(self.h, e, _ptr(a)) != 0:
+            raise ValueError(e)
+        return a
+
+    def capacitance(self):
+        """n_el x n_el capacitance matrix (reading R33)."""
+        d = self.diag()
+        m = d.n_el
+        return np.array(d.C_el[:]).reshape(MAX_EL, MAX_EL)[:m, :m]
 
     def refresh_laplace(self):
         return lib().orc_refresh_laplace(self.h)

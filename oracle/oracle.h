@@ -26,6 +26,7 @@ extern "C" {
 
 #define ORC_MAX_REGIONS 32
 #define ORC_NCNT 4 /* absorption counter slots: 0 ground, 1 powered, 2 lost (Neumann edge), 3 dielectric */
+#define ORC_MAX_EL 4 /* driven electrodes: conductor ids 1 .. ORC_MAX_EL */
 
 typedef struct {
     double r0, r1, z0, z1;
@@ -33,6 +34,12 @@ typedef struct {
     int32_t cond_id; /* 0 ground, 1 RF-driven electrode */
     double eps_r;
 } orc_region;
+
+/* the external circuit of one driven electrode (fields as in orc_config) */
+typedef struct {
+    int32_t kind, substeps;
+    double freq, U_amp, U_dc, R_s, C_m1, C_m2, L_m, R_m, C_stray, L_stray, R_stray, C_b, R_b, L_b;
+} orc_circ;
 
 typedef struct {
     /* geometry: cells nr x nz on [0,R] x [0,Z] */
@@ -58,6 +65,10 @@ typedef struct {
     /* [R32] weights: 0 equal; 1 per cell volume (equal count per vacuum cell).
        split: 1 splits heavy particles at every tile sort of their species */
     int32_t weights, split;
+    /* [R33] driven electrodes 1 .. n_el (0 counts as 1): electrode 1 uses
+       the circuit above, electrode e >= 2 circ_el[e - 2] */
+    int32_t n_el;
+    orc_circ circ_el[ORC_MAX_EL - 1];
 } orc_config;
 
 typedef struct {
@@ -76,6 +87,15 @@ typedef struct {
        P_source, P_Rs, P_IMN, P_stray, P_ccp, P_forward, P_ref */
     double elec[12];
     int64_t split_added[2]; /* particles added by splitting since creation */
+    /* [R33] per driven electrode e = 1 .. n_el (index e - 1): voltage,
+       charge, induced charge, circuit current, capacitance matrix (row-major
+       ORC_MAX_EL x ORC_MAX_EL), harmonics 0..5 of the last period, charge
+       absorbed per species (units 2^-32 w_unit) */
+    int32_t n_el;
+    double U_el[ORC_MAX_EL], Q_el[ORC_MAX_EL], QP_el[ORC_MAX_EL], I_el[ORC_MAX_EL];
+    double C_el[ORC_MAX_EL * ORC_MAX_EL];
+    double hU_re[ORC_MAX_EL][6], hU_im[ORC_MAX_EL][6], hI_re[ORC_MAX_EL][6], hI_im[ORC_MAX_EL][6];
+    int64_t absorbed_el[2][ORC_MAX_EL];
 } orc_diag;
 
 typedef struct orc_sim orc_sim;
@@ -107,6 +127,11 @@ int orc_set_grid(orc_sim* s, int32_t which, const void* in);
 int orc_set_state(orc_sim* s, const double* st); /* t, Q_E, U_E, circ[5], C_eq */
 /* [R32] one splitting pass over a species now; *added = copies appended */
 int orc_split_now(orc_sim* s, int32_t species, int64_t* added);
+/* [R33] one solve with the driven electrodes at U[0 .. n_el-1] */
+int orc_solve_qv(orc_sim* s, const double* Q, const double* chi, const double* U, double tol,
+                 double* phi_inout, int32_t* iters, double* relres);
+/* [R33] Laplace solution of driven electrode e (1-based) at 1 V, others 0 */
+int orc_get_phiL(orc_sim* s, int32_t e, double* out);
 /* [R32] reference weight of a particle in cell column i (units of w_unit) */
 double orc_split_target(orc_sim* s, int32_t species, int32_t i);
 

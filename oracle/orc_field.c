@@ -393,14 +393,14 @@ static void full_residual(const orc_sim* s, const double* ar, const double* az, 
 }
 
 /* Solve Eq. (1) in finite-volume form, K phi = Q on the unknown nodes, with
-   phi = U_E on the driven electrode and 0 on grounded conductors (Sec. 2:
+   phi = U[e - 1] on driven electrode e and 0 on grounded conductors (Sec. 2:
    metals are equipotential boundaries).  Stops at ||b - K phi|| <= tol ||b||
    [R20].  phi is the warm start on entry. */
-int o_solve(orc_sim* s, const double* ar, const double* az, const double* Q, double U_E, double tol,
+int o_solve(orc_sim* s, const double* ar, const double* az, const double* Q, const double* U, double tol,
             double* phi, int* iters, double* relres) {
     int nn = s->nn;
     for (int n = 0; n < nn; n++)
-        if (s->node_kind[n] >= 0) phi[n] = (s->node_kind[n] == 1) ? U_E : 0.0;
+        if (s->node_kind[n] >= 0) phi[n] = (s->node_kind[n] >= 1) ? U[s->node_kind[n] - 1] : 0.0;
     double* r = calloc(nn, sizeof(double));
     double* z = calloc(nn, sizeof(double));
     double* p = calloc(nn, sizeof(double));
@@ -458,25 +458,37 @@ int o_solve(orc_sim* s, const double* ar, const double* az, const double* Q, dou
 /* Equivalent capacitance by the energy method (Eqs. 6-7): phi_L solves the
    Laplace problem with the driven electrode at 1 V and every other conductor
    grounded; 1/2 C_eq U^2 = integral of 1/2 eps |E|^2, which in the
-   finite-volume form is sum over edges of a (d phi_L)^2.  [R21] the operator
+   finite-volume form is sum over edges of a (d phi_L)^2.  [R33] with several
+   driven electrodes, one Laplace solution per electrode and the capacitance
+   matrix C_ef = sum over edges of a (d phi_Le)(d phi_Lf), the bilinear form
+   of the same energy (C_ee is each electrode's C_eq).  [R21] the operator
    includes the current chi (vacuum at start), refreshed once per RF period
-   (Sec. 2, text after Eq. 4). */
+   (Sec. 2, text after Eq. 4).  Returns C_11. */
 double o_laplace(orc_sim* s) {
     double* zero = calloc(s->nn, sizeof(double));
     int it;
     double rel;
-    o_solve(s, s->ar, s->az, zero, 1.0, 1e-13, s->phiL, &it, &rel);
+    for (int e = 0; e < s->n_el; e++) {
+        double U[ORC_MAX_EL] = {0.0};
+        U[e] = 1.0;
+        o_solve(s, s->ar, s->az, zero, U, 1e-13, s->phiL[e], &it, &rel);
+    }
     free(zero);
     int nr = s->nr, nz = s->nz, w = nr + 1;
-    double C = 0.0;
-    for (int j = 0; j <= nz; j++)
-        for (int i = 0; i <= nr; i++) {
-            int n = j * w + i;
-            if (i < nr) { double d = s->phiL[n] - s->phiL[n + 1]; C += s->ar[n] * d * d; }
-            if (j < nz) { double d = s->phiL[n] - s->phiL[n + w]; C += s->az[n] * d * d; }
+    for (int e = 0; e < s->n_el; e++)
+        for (int f = e; f < s->n_el; f++) {
+            const double *a = s->phiL[e], *b = s->phiL[f];
+            double C = 0.0;
+            for (int j = 0; j <= nz; j++)
+                for (int i = 0; i <= nr; i++) {
+                    int n = j * w + i;
+                    if (i < nr) { double d = a[n] - a[n + 1], g = b[n] - b[n + 1]; C += s->ar[n] * d * g; }
+                    if (j < nz) { double d = a[n] - a[n + w], g = b[n] - b[n + w]; C += s->az[n] * d * g; }
+                }
+            s->Cm[e][f] = C;
+            s->Cm[f][e] = C;
         }
-    s->C_eq = C;
-    return C;
+    return s->Cm[0][0];
 }
 
 double orc_ceq_flux(orc_sim* s) {
@@ -486,10 +498,11 @@ double orc_ceq_flux(orc_sim* s) {
         for (int i = 0; i <= nr; i++) {
             int n = j * w + i;
             if (s->node_kind[n] != 1) continue;
-            if (i > 0) F += s->ar[n - 1] * (s->phiL[n] - s->phiL[n - 1]);
-            if (i < nr) F += s->ar[n] * (s->phiL[n] - s->phiL[n + 1]);
-            if (j > 0) F += s->az[n - w] * (s->phiL[n] - s->phiL[n - w]);
-            if (j < nz) F += s->az[n] * (s->phiL[n] - s->phiL[n + w]);
+            const double* L = s->phiL[0];
+            if (i > 0) F += s->ar[n - 1] * (L[n] - L[n - 1]);
+            if (i < nr) F += s->ar[n] * (L[n] - L[n + 1]);
+            if (j > 0) F += s->az[n - w] * (L[n] - L[n - w]);
+            if (j < nz) F += s->az[n] * (L[n] - L[n + w]);
         }
     return F;
 }

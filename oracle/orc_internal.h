@@ -48,13 +48,19 @@ struct orc_sim {
     uint32_t thresh[2];
     /* grids */
     int64_t *dep[2], *wallq, *psum[2], *plast[2];
-    double *phi, *phiL, *Er, *Ez, *chi, *Q, *ar, *az;
-    /* circuit and electrode */
-    double t, Q_E, U_E, C_eq, Q_P, I_ccp, circ[5];
-    int64_t cnt[2][ORC_NCNT], cnt_prev_pow;
+    double *phi, *Er, *Ez, *chi, *Q, *ar, *az;
+    /* driven electrodes e = 0 .. n_el-1 (conductor id e + 1) [R33]: Laplace
+       solutions, capacitance matrix, charges, voltages, induced charges,
+       circuit currents and states */
+    int n_el;
+    double* phiL[ORC_MAX_EL];
+    double Cm[ORC_MAX_EL][ORC_MAX_EL];
+    double t, Q_E[ORC_MAX_EL], U_E[ORC_MAX_EL], Q_P[ORC_MAX_EL], I_ccp[ORC_MAX_EL], circ[ORC_MAX_EL][5];
+    /* absorption counters: slot_of(conductor id); 2 lost, 3 dielectric */
+    int64_t cnt[2][8], cnt_prev[ORC_MAX_EL];
     /* diagnostics */
     int64_t step, periods_done, born, coll[2][4], viol;
-    double *serU, *serI, *lastU, *lastI;
+    double *serU[ORC_MAX_EL], *serI[ORC_MAX_EL], *lastU[ORC_MAX_EL], *lastI[ORC_MAX_EL];
     double *serVin, *serI1, *lastVin, *lastI1;   /* source-side voltage and current per step */
     double energy[5], last_energy[5];            /* element energies of the current / last period */
     int64_t solver_iters;
@@ -69,8 +75,10 @@ void o_characterise(const orc_config* c, const double* U, const double* I, const
 int o_geometry(orc_sim* s);
 void o_assemble(orc_sim* s);
 void o_faces_from_chi(orc_sim* s, const double* chi, double* ar, double* az);
-int o_solve(orc_sim* s, const double* ar, const double* az, const double* Q, double U_E, double tol,
+int o_solve(orc_sim* s, const double* ar, const double* az, const double* Q, const double* U, double tol,
             double* phi, int* iters, double* relres);
+/* absorption counter slot of conductor id: 0 ground, 1 electrode 1, 4 + (id - 2) electrodes >= 2 */
+static inline int o_slot_of(int id) { return id <= 1 ? id : 2 + id; }
 double o_laplace(orc_sim* s);
 void o_efield(orc_sim* s);
 

@@ -146,7 +146,7 @@ int o_absorb_check(orc_sim* s, int sp, double r, double z, double W) {
     int64_t tot = (int64_t)floor(W * ldexp(1.0, O_KBITS));
     if (!L.inside) {
         int bc = s->cfg.edge_bc[L.edge];
-        int slot = (bc >= 0) ? (bc < 2 ? bc : 0) : 2;
+        int slot = (bc >= 0) ? o_slot_of(bc) : 2;
         s->cnt[sp][slot] += tot;
         return 1;
     }
@@ -154,7 +154,7 @@ int o_absorb_check(orc_sim* s, int sp, double r, double z, double W) {
     if (ck == 0) return 0;
     if (ck >= 2) {
         int id = ck - 2;
-        s->cnt[sp][id < 2 ? id : 0] += tot;
+        s->cnt[sp][o_slot_of(id)] += tot;
         return 1;
     }
     int64_t c[4];
@@ -162,7 +162,7 @@ int o_absorb_check(orc_sim* s, int sp, double r, double z, double W) {
     int nodes[4] = {NODE(L.i, L.j), NODE(L.i + 1, L.j), NODE(L.i, L.j + 1), NODE(L.i + 1, L.j + 1)};
     for (int k = 0; k < 4; k++) {
         int nk = s->node_kind[nodes[k]];
-        if (nk >= 0) s->cnt[sp][nk < 2 ? nk : 0] += c[k];
+        if (nk >= 0) s->cnt[sp][o_slot_of(nk)] += c[k];
         else {
             s->wallq[nodes[k]] += s->sign[sp] * c[k];
             s->cnt[sp][3] += c[k];

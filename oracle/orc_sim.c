@@ -11,18 +11,27 @@
 #include <string.h>
 
 /* ---------------------------------------------------------------- circuit */
+/* the external circuit of driven electrode e (0-based) [R33] */
+static orc_circ circ_of(const orc_config* c, int e) {
+    if (e > 0) return c->circ_el[e - 1];
+    orc_circ k;
+    k.kind = c->circ_kind; k.substeps = c->substeps;
+    k.freq = c->freq; k.U_amp = c->U_amp; k.U_dc = c->U_dc; k.R_s = c->R_s;
+    k.C_m1 = c->C_m1; k.C_m2 = c->C_m2; k.L_m = c->L_m; k.R_m = c->R_m;
+    k.C_stray = c->C_stray; k.L_stray = c->L_stray; k.R_stray = c->R_stray;
+    k.C_b = c->C_b; k.R_b = c->R_b; k.L_b = c->L_b;
+    return k;
+}
+
+static double source_v(const orc_circ* c, double t) { return c->U_amp * sin(2.0 * O_PI * c->freq * t) + c->U_dc; }
+
 /* State y: L-match (Eq. 10) y0..y4 = Q1, Q2, I2, Q_ccp, I_stray;
    series RLC (Eq. 9) y0, y1 = Q_b, I_b; y5 = Q_E, the electrode charge of
-   Eq. (8), dQ_E/dt = I_ccp + I_conv.  [R16] the electrode voltage is
-   U_E = (Q_E - Q_P)/C_eq, where Q_P = -sum phi_L Q is the charge the space
-   charge induces on the electrode (Green reciprocity); in vacuum this is
-   Eq. (5). */
-static void circ_rhs(const orc_config* c, double C_eq, double t, const double* y, double Q_P, double I_conv,
-                     double* dy) {
-    double U_E = (y[5] - Q_P) / C_eq;
-    double Us = c->U_amp * sin(2.0 * O_PI * c->freq * t) + c->U_dc;
+   Eq. (8), dQ_E/dt = I_ccp + I_conv, for the electrode voltage U_E. */
+static void circ_rhs(const orc_circ* c, double U_E, double t, const double* y, double I_conv, double* dy) {
+    double Us = source_v(c, t);
     for (int k = 0; k < 6; k++) dy[k] = 0.0;
-    if (c->circ_kind == 2) {
+    if (c->kind == 2) {
         double Um1 = (y[0] - y[1]) / c->C_m1;
         dy[0] = (Us - Um1) / c->R_s;
         dy[1] = y[2];
@@ -30,7 +39,7 @@ static void circ_rhs(const orc_config* c, double C_eq, double t, const double* y
         dy[3] = y[2] - y[4];
         dy[4] = (U_E - (y[1] - y[3]) / c->C_stray - y[4] * c->R_stray) / c->L_stray;
         dy[5] = (y[2] - y[4]) + I_conv;
-    } else if (c->circ_kind == 1) {
+    } else if (c->kind == 1) {
         dy[0] = y[1];
         dy[1] = (Us - U_E - y[0] / c->C_b - y[1] * c->R_b) / c->L_b;
         dy[5] = y[1] + I_conv;
@@ -41,110 +50,201 @@ static void circ_rhs(const orc_config* c, double C_eq, double t, const double* y
    (Eq. 13 integrands) [R30]: 0 delivered by the source, 1 lost in R_s,
    2 lost in the matching network (R_m) or in the series branch (R_b),
    3 lost in the stray branch, 4 delivered to the plasma load U_E I_ccp. */
-static void circ_powers(const orc_config* c, double C_eq, double t, const double* y, double Q_P, double* p) {
-    double U_E = (y[5] - Q_P) / C_eq;
-    double Us = c->U_amp * sin(2.0 * O_PI * c->freq * t) + c->U_dc;
+static void circ_powers(const orc_circ* c, double U_E, double t, const double* y, double* p) {
+    double Us = source_v(c, t);
     for (int k = 0; k < 5; k++) p[k] = 0.0;
-    if (c->circ_kind == 2) {
+    if (c->kind == 2) {
         double I1 = (Us - (y[0] - y[1]) / c->C_m1) / c->R_s;
         p[0] = Us * I1;
         p[1] = c->R_s * I1 * I1;
         p[2] = c->R_m * y[2] * y[2];
         p[3] = c->R_stray * y[4] * y[4];
         p[4] = U_E * (y[2] - y[4]);
-    } else if (c->circ_kind == 1) {
+    } else if (c->kind == 1) {
         p[0] = Us * y[1];
         p[2] = c->R_b * y[1] * y[1];
         p[4] = U_E * y[1];
     }
 }
 
-/* [R17] classical RK4 with `substeps` substeps per PIC step; I_conv and Q_P
-   are held over the step.  Returns the step-averaged circuit current.  With
-   e5, adds each element's energy over the step (trapezoid rule on the
-   substep end points). */
-static double circ_integrate(const orc_config* c, double dt, double C_eq, double t0, double Q_P, double I_conv,
-                             double* y, double* e5) {
-    int M = c->substeps > 0 ? c->substeps : 1;
+/* The driven electrodes' circuits, coupled through the capacitance matrix.
+   [R16] with one electrode U_E = (Q_E - Q_P)/C_eq, Q_P = -sum phi_L Q the
+   charge the space charge induces on it (Green reciprocity); in vacuum
+   Eq. (5).  [R33] with several: Q = C U + Q_P, so an ideal source fixes its
+   electrode's voltage and the others solve C_NN U_N = Q_N - Q_P,N - C_NK U_K. */
+typedef struct {
+    int M;
+    orc_circ c[ORC_MAX_EL];
+    double C[ORC_MAX_EL][ORC_MAX_EL];
+    double QP[ORC_MAX_EL], Iconv[ORC_MAX_EL];
+} o_circset;
+
+static void volts(const o_circset* cs, double t, double Y[][6], double* U) {
+    int N[ORC_MAX_EL], nN = 0;
+    for (int e = 0; e < cs->M; e++) {
+        if (cs->c[e].kind == 0) U[e] = source_v(&cs->c[e], t);
+        else N[nN++] = e;
+    }
+    if (nN == 0) return;
+    double A[ORC_MAX_EL][ORC_MAX_EL], b[ORC_MAX_EL];
+    for (int a = 0; a < nN; a++) {
+        int e = N[a];
+        b[a] = Y[e][5] - cs->QP[e];
+        for (int f = 0; f < cs->M; f++)
+            if (cs->c[f].kind == 0) b[a] -= cs->C[e][f] * U[f];
+        for (int q = 0; q < nN; q++) A[a][q] = cs->C[e][N[q]];
+    }
+    /* Gaussian elimination; A is symmetric positive definite */
+    for (int p = 0; p < nN; p++)
+        for (int a = p + 1; a < nN; a++) {
+            double m = A[a][p] / A[p][p];
+            for (int q = p; q < nN; q++) A[a][q] -= m * A[p][q];
+            b[a] -= m * b[p];
+        }
+    for (int a = nN - 1; a >= 0; a--) {
+        double x = b[a];
+        for (int q = a + 1; q < nN; q++) x -= A[a][q] * U[N[q]];
+        U[N[a]] = x / A[a][a];
+    }
+}
+
+/* [R17] classical RK4 of the coupled circuit states over one PIC step, the
+   largest substep count of the circuits; I_conv and Q_P are held over the
+   step.  Iavg: each circuit's step-averaged current.  With e5, adds the
+   element energies of electrode 1's circuit (trapezoid rule on the substep
+   end points). */
+static void circ_step(const o_circset* cs, double dt, double t0, double Y[][6], double* e5, double* Iavg) {
+    int M = 0, qi[ORC_MAX_EL];
+    double q0[ORC_MAX_EL];
+    for (int e = 0; e < cs->M; e++) {
+        qi[e] = (cs->c[e].kind == 2) ? 3 : 0;
+        q0[e] = Y[e][qi[e]];
+        if (cs->c[e].kind != 0) {
+            int ms = cs->c[e].substeps > 0 ? cs->c[e].substeps : 1;
+            if (ms > M) M = ms;
+        }
+    }
+    if (M == 0) return;
     double h = dt / M;
-    int qi = (c->circ_kind == 2) ? 3 : 0;
-    double q0 = y[qi];
-    double pa[5], pb[5];
-    if (e5) circ_powers(c, C_eq, t0, y, Q_P, pa);
+    double U[ORC_MAX_EL], pa[5], pb[5];
+    int pe = (e5 != NULL) && cs->c[0].kind != 0;
+    if (pe) {
+        volts(cs, t0, Y, U);
+        circ_powers(&cs->c[0], U[0], t0, Y[0], pa);
+    }
     for (int m = 0; m < M; m++) {
         double t = t0 + m * h;
-        double k1[6], k2[6], k3[6], k4[6], yt[6];
-        circ_rhs(c, C_eq, t, y, Q_P, I_conv, k1);
-        for (int k = 0; k < 6; k++) yt[k] = y[k] + 0.5 * h * k1[k];
-        circ_rhs(c, C_eq, t + 0.5 * h, yt, Q_P, I_conv, k2);
-        for (int k = 0; k < 6; k++) yt[k] = y[k] + 0.5 * h * k2[k];
-        circ_rhs(c, C_eq, t + 0.5 * h, yt, Q_P, I_conv, k3);
-        for (int k = 0; k < 6; k++) yt[k] = y[k] + h * k3[k];
-        circ_rhs(c, C_eq, t + h, yt, Q_P, I_conv, k4);
-        for (int k = 0; k < 6; k++) y[k] += h / 6.0 * (k1[k] + 2.0 * k2[k] + 2.0 * k3[k] + k4[k]);
-        if (e5) {
-            circ_powers(c, C_eq, t + h, y, Q_P, pb);
+        double k1[ORC_MAX_EL][6], k2[ORC_MAX_EL][6], k3[ORC_MAX_EL][6], k4[ORC_MAX_EL][6], yt[ORC_MAX_EL][6];
+        volts(cs, t, Y, U);
+        for (int e = 0; e < cs->M; e++) if (cs->c[e].kind) circ_rhs(&cs->c[e], U[e], t, Y[e], cs->Iconv[e], k1[e]);
+        for (int e = 0; e < cs->M; e++) for (int k = 0; k < 6; k++) yt[e][k] = Y[e][k] + 0.5 * h * k1[e][k];
+        volts(cs, t + 0.5 * h, yt, U);
+        for (int e = 0; e < cs->M; e++) if (cs->c[e].kind) circ_rhs(&cs->c[e], U[e], t + 0.5 * h, yt[e], cs->Iconv[e], k2[e]);
+        for (int e = 0; e < cs->M; e++) for (int k = 0; k < 6; k++) yt[e][k] = Y[e][k] + 0.5 * h * k2[e][k];
+        volts(cs, t + 0.5 * h, yt, U);
+        for (int e = 0; e < cs->M; e++) if (cs->c[e].kind) circ_rhs(&cs->c[e], U[e], t + 0.5 * h, yt[e], cs->Iconv[e], k3[e]);
+        for (int e = 0; e < cs->M; e++) for (int k = 0; k < 6; k++) yt[e][k] = Y[e][k] + h * k3[e][k];
+        volts(cs, t + h, yt, U);
+        for (int e = 0; e < cs->M; e++) if (cs->c[e].kind) circ_rhs(&cs->c[e], U[e], t + h, yt[e], cs->Iconv[e], k4[e]);
+        for (int e = 0; e < cs->M; e++)
+            if (cs->c[e].kind)
+                for (int k = 0; k < 6; k++) Y[e][k] += h / 6.0 * (k1[e][k] + 2.0 * k2[e][k] + 2.0 * k3[e][k] + k4[e][k]);
+        if (pe) {
+            volts(cs, t + h, Y, U);
+            circ_powers(&cs->c[0], U[0], t + h, Y[0], pb);
             for (int k = 0; k < 5; k++) {
                 e5[k] += 0.5 * h * (pa[k] + pb[k]);
                 pa[k] = pb[k];
             }
         }
     }
-    return (y[qi] - q0) / dt;
+    for (int e = 0; e < cs->M; e++)
+        if (cs->c[e].kind) Iavg[e] = (Y[e][qi[e]] - q0[e]) / dt;
 }
 
 /* Source-side samples of a step for the load impedance: the voltage at the
    matching network's input (across C_m1) or the source voltage, at t1. */
-static double circ_vin(const orc_config* c, double t1, const double* y) {
-    if (c->circ_kind == 2) return (y[0] - y[1]) / c->C_m1;
-    return c->U_amp * sin(2.0 * O_PI * c->freq * t1) + c->U_dc;
+static double circ_vin(const orc_circ* c, double t1, const double* y) {
+    if (c->kind == 2) return (y[0] - y[1]) / c->C_m1;
+    return source_v(c, t1);
 }
 
-static double powered_count(const orc_sim* s) {
-    return (double)(s->sign[1] * s->cnt[1][1] + s->sign[0] * s->cnt[0][1]);
+/* net charge absorbed by driven electrode e (units 2^-32 w_unit) */
+static double electrode_count(const orc_sim* s, int e) {
+    int slot = o_slot_of(e + 1);
+    return (double)(s->sign[1] * s->cnt[1][slot] + s->sign[0] * s->cnt[0][slot]);
 }
 
-static double induced_charge(const orc_sim* s) {
+static double induced_charge(const orc_sim* s, int e) {
     double qp = 0.0;
     for (int n = 0; n < s->nn; n++)
-        if (s->node_kind[n] < 0) qp -= s->phiL[n] * s->Q[n];
+        if (s->node_kind[n] < 0) qp -= s->phiL[e][n] * s->Q[n];
     return qp;
+}
+
+static void circset_of(const orc_sim* s, o_circset* cs) {
+    cs->M = s->n_el;
+    for (int e = 0; e < s->n_el; e++) {
+        cs->c[e] = circ_of(&s->cfg, e);
+        for (int f = 0; f < s->n_el; f++) cs->C[e][f] = s->Cm[e][f];
+        cs->QP[e] = 0.0;
+        cs->Iconv[e] = 0.0;
+    }
+}
+
+/* charge of an electrode held by an ideal source: Q = sum_f C_ef U_f + Q_P */
+static double held_charge(const o_circset* cs, int e, const double* U) {
+    double q = 0.0;
+    for (int f = 0; f < cs->M; f++) q += cs->C[e][f] * U[f];
+    return q + cs->QP[e];
 }
 
 void o_circuit_advance(orc_sim* s) {
     double unit = O_QE * s->w_unit * ldexp(1.0, -O_KBITS);
     int k = (int)(s->step % s->cfg.steps_per_period);
-    double pc = powered_count(s);
-    double I_conv = (pc - (double)s->cnt_prev_pow) * unit / s->dt;
-    s->cnt_prev_pow = (int64_t)pc;
-    s->Q_P = induced_charge(s);
+    o_circset cs;
+    circset_of(s, &cs);
+    for (int e = 0; e < s->n_el; e++) {
+        double pc = electrode_count(s, e);
+        cs.Iconv[e] = (pc - (double)s->cnt_prev[e]) * unit / s->dt;
+        s->cnt_prev[e] = (int64_t)pc;
+        cs.QP[e] = induced_charge(s, e);
+        s->Q_P[e] = cs.QP[e];
+    }
     double t1 = s->t + s->dt;
-    const orc_config* c = &s->cfg;
-    if (c->circ_kind == 0) {
-        double U0 = s->U_E;
-        double U = c->U_amp * sin(2.0 * O_PI * c->freq * t1) + c->U_dc;
-        double QE = s->C_eq * U + s->Q_P;
-        s->I_ccp = (QE - s->Q_E) / s->dt - I_conv;
-        s->Q_E = QE;
-        s->U_E = U;
+    double U0 = s->U_E[0];
+    double Y[ORC_MAX_EL][6], Iavg[ORC_MAX_EL], U[ORC_MAX_EL];
+    for (int e = 0; e < s->n_el; e++) {
+        for (int q = 0; q < 5; q++) Y[e][q] = s->circ[e][q];
+        Y[e][5] = s->Q_E[e];
+    }
+    double q1 = Y[0][0];
+    circ_step(&cs, s->dt, s->t, Y, s->energy, Iavg);
+    volts(&cs, t1, Y, U);
+    for (int e = 0; e < s->n_el; e++) {
+        if (cs.c[e].kind == 0) {
+            double QE = held_charge(&cs, e, U);
+            s->I_ccp[e] = (QE - s->Q_E[e]) / s->dt - cs.Iconv[e];
+            s->Q_E[e] = QE;
+        } else {
+            for (int q = 0; q < 5; q++) s->circ[e][q] = Y[e][q];
+            s->Q_E[e] = Y[e][5];
+            s->I_ccp[e] = Iavg[e];
+        }
+        s->U_E[e] = U[e];
+    }
+    /* electrode 1: source-side samples and, for an ideal source, energies */
+    if (cs.c[0].kind == 0) {
         /* the source is the electrode: the mean voltage over the step times
            the step-averaged current */
-        double e = s->dt * 0.5 * (U0 + U) * s->I_ccp;
+        double e = s->dt * 0.5 * (U0 + U[0]) * s->I_ccp[0];
         s->energy[0] += e;
         s->energy[4] += e;
-        s->serVin[k] = U;
-        s->serI1[k] = s->I_ccp;
+        s->serVin[k] = U[0];
+        s->serI1[k] = s->I_ccp[0];
     } else {
-        double y[6];
-        for (int q = 0; q < 5; q++) y[q] = s->circ[q];
-        y[5] = s->Q_E;
-        double q1 = y[0];
-        s->I_ccp = circ_integrate(c, s->dt, s->C_eq, s->t, s->Q_P, I_conv, y, s->energy);
-        for (int q = 0; q < 5; q++) s->circ[q] = y[q];
-        s->Q_E = y[5];
-        s->U_E = (s->Q_E - s->Q_P) / s->C_eq;
-        s->serVin[k] = circ_vin(c, t1, y);
-        s->serI1[k] = (c->circ_kind == 2) ? (y[0] - q1) / s->dt : s->I_ccp;
+        s->serVin[k] = circ_vin(&cs.c[0], t1, Y[0]);
+        s->serI1[k] = (cs.c[0].kind == 2) ? (Y[0][0] - q1) / s->dt : s->I_ccp[0];
     }
     s->t = t1;
 }
@@ -153,7 +253,13 @@ int orc_circuit_vacuum(const orc_config* cfg, double C_eq, int64_t nsteps, doubl
                        double* chars) {
     double dt = 1.0 / (cfg->freq * cfg->steps_per_period);
     int spp = cfg->steps_per_period;
-    double y[6] = {0, 0, 0, 0, 0, 0};
+    o_circset cs;
+    cs.M = 1;
+    cs.c[0] = circ_of(cfg, 0);
+    cs.C[0][0] = C_eq;
+    cs.QP[0] = 0.0;
+    cs.Iconv[0] = 0.0;
+    double Y[1][6] = {{0, 0, 0, 0, 0, 0}};
     double t = 0.0, e[5] = {0, 0, 0, 0, 0};
     double* vin = calloc((size_t)spp, sizeof(double));
     double* i1 = calloc((size_t)spp, sizeof(double));
@@ -162,17 +268,18 @@ int orc_circuit_vacuum(const orc_config* cfg, double C_eq, int64_t nsteps, doubl
     if (!vin || !i1 || !uu || !ii) { free(vin); free(i1); free(uu); free(ii); return -1; }
     for (int64_t n = 0; n < nsteps; n++) {
         int last_period = n >= nsteps - spp;
-        double q1 = y[0];
-        double I = circ_integrate(cfg, dt, C_eq, t, 0.0, 0.0, y, last_period ? e : NULL);
+        double q1 = Y[0][0];
+        double I = 0.0;
+        circ_step(&cs, dt, t, Y, last_period ? e : NULL, &I);
         t += dt;
-        U_out[n] = y[5] / C_eq;
+        U_out[n] = Y[0][5] / C_eq;
         I_out[n] = I;
         if (last_period) {
             int k = (int)(n - (nsteps - spp));
             uu[k] = U_out[n];
             ii[k] = I;
-            vin[k] = circ_vin(cfg, t, y);
-            i1[k] = (cfg->circ_kind == 2) ? (y[0] - q1) / dt : I;
+            vin[k] = circ_vin(&cs.c[0], t, Y[0]);
+            i1[k] = (cfg->circ_kind == 2) ? (Y[0][0] - q1) / dt : I;
         }
     }
     if (chars && nsteps >= spp) o_characterise(cfg, uu, ii, vin, i1, e, chars);
@@ -375,8 +482,10 @@ static int step1(orc_sim* s) {
     s->solver_relres = rel;
     if (rc) return rc;
     o_efield(s);
-    s->serU[k] = s->U_E;
-    s->serI[k] = s->I_ccp;
+    for (int e = 0; e < s->n_el; e++) {
+        s->serU[e][k] = s->U_E[e];
+        s->serI[e][k] = s->I_ccp[e];
+    }
     for (int sp = 0; sp < 2; sp++) memset(s->dep[sp], 0, sizeof(int64_t) * s->nn);
     uint32_t stepc = (uint32_t)(s->step + 1);
     o_birth* births = NULL;
@@ -397,8 +506,10 @@ static int step1(orc_sim* s) {
     }
     if (s->step % spp == 0) {
         o_laplace(s);
-        memcpy(s->lastU, s->serU, sizeof(double) * spp);
-        memcpy(s->lastI, s->serI, sizeof(double) * spp);
+        for (int e = 0; e < s->n_el; e++) {
+            memcpy(s->lastU[e], s->serU[e], sizeof(double) * spp);
+            memcpy(s->lastI[e], s->serI[e], sizeof(double) * spp);
+        }
         memcpy(s->lastVin, s->serVin, sizeof(double) * spp);
         memcpy(s->lastI1, s->serI1, sizeof(double) * spp);
         for (int q = 0; q < 5; q++) { s->last_energy[q] = s->energy[q]; s->energy[q] = 0.0; }
@@ -423,10 +534,12 @@ int orc_step(orc_sim* s, int32_t nsteps) {
 /* ------------------------------------------------------------ create/free */
 int orc_create(const orc_config* cfg, orc_sim** out) {
     if (cfg->nr < 2 || cfg->nz < 2 || cfg->R <= 0 || cfg->Z <= 0 || cfg->steps_per_period < 1 ||
-        cfg->n_regions < 0 || cfg->n_regions > ORC_MAX_REGIONS || cfg->freq <= 0)
+        cfg->n_regions < 0 || cfg->n_regions > ORC_MAX_REGIONS || cfg->freq <= 0 || cfg->n_el < 0 ||
+        cfg->n_el > ORC_MAX_EL)
         return -1;
     orc_sim* s = calloc(1, sizeof(orc_sim));
     s->cfg = *cfg;
+    s->n_el = cfg->n_el > 0 ? cfg->n_el : 1;
     s->nr = cfg->nr;
     s->nz = cfg->nz;
     s->nn = (cfg->nr + 1) * (cfg->nz + 1);
@@ -451,17 +564,20 @@ int orc_create(const orc_config* cfg, orc_sim** out) {
         s->plast[sp] = calloc(s->nn, sizeof(int64_t));
     }
     s->wallq = calloc(s->nn, sizeof(int64_t));
-    double** g[8] = {&s->phi, &s->phiL, &s->Er, &s->Ez, &s->chi, &s->Q, &s->ar, &s->az};
-    for (int k = 0; k < 8; k++) *g[k] = calloc(s->nn, sizeof(double));
+    double** g[7] = {&s->phi, &s->Er, &s->Ez, &s->chi, &s->Q, &s->ar, &s->az};
+    for (int k = 0; k < 7; k++) *g[k] = calloc(s->nn, sizeof(double));
     int spp = cfg->steps_per_period;
-    s->serU = calloc(spp, sizeof(double));
-    s->serI = calloc(spp, sizeof(double));
+    for (int e = 0; e < s->n_el; e++) {
+        s->phiL[e] = calloc(s->nn, sizeof(double));
+        s->serU[e] = calloc(spp, sizeof(double));
+        s->serI[e] = calloc(spp, sizeof(double));
+        s->lastU[e] = calloc(spp, sizeof(double));
+        s->lastI[e] = calloc(spp, sizeof(double));
+    }
     s->serVin = calloc(spp, sizeof(double));
     s->serI1 = calloc(spp, sizeof(double));
     s->lastVin = calloc(spp, sizeof(double));
     s->lastI1 = calloc(spp, sizeof(double));
-    s->lastU = calloc(spp, sizeof(double));
-    s->lastI = calloc(spp, sizeof(double));
     /* particles: the load fixes w_unit; with load = 0 the slots stay empty */
     orc_config save = s->cfg;
     if (!cfg->load) { s->cfg.n_e = 0; s->cfg.n_i = 0; }
@@ -506,10 +622,23 @@ int orc_create(const orc_config* cfg, orc_sim** out) {
     o_faces_from_chi(s, s->chi, s->ar, s->az);
     o_laplace(s);
     o_assemble(s);
-    s->Q_P = induced_charge(s);
-    s->U_E = (cfg->circ_kind == 0) ? cfg->U_dc : 0.0;
-    s->Q_E = s->C_eq * s->U_E + s->Q_P;
-    s->cnt_prev_pow = (int64_t)powered_count(s);
+    /* initial electrode voltages: an ideal source's DC value, else 0, with
+       the charge Q = C U + Q_P that holds them */
+    {
+        o_circset cs;
+        circset_of(s, &cs);
+        double U[ORC_MAX_EL];
+        for (int e = 0; e < s->n_el; e++) {
+            cs.QP[e] = induced_charge(s, e);
+            s->Q_P[e] = cs.QP[e];
+            U[e] = (cs.c[e].kind == 0) ? cs.c[e].U_dc : 0.0;
+            s->U_E[e] = U[e];
+        }
+        for (int e = 0; e < s->n_el; e++) {
+            s->Q_E[e] = held_charge(&cs, e, U);
+            s->cnt_prev[e] = (int64_t)electrode_count(s, e);
+        }
+    }
     *out = s;
     return 0;
 }
@@ -523,9 +652,11 @@ void orc_destroy(orc_sim* s) {
         free(s->dep[sp]); free(s->psum[sp]); free(s->plast[sp]);
     }
     free(s->wallq);
-    free(s->phi); free(s->phiL); free(s->Er); free(s->Ez); free(s->chi); free(s->Q);
+    free(s->phi); free(s->Er); free(s->Ez); free(s->chi); free(s->Q);
     free(s->ar); free(s->az);
-    free(s->serU); free(s->serI); free(s->lastU); free(s->lastI);
+    for (int e = 0; e < ORC_MAX_EL; e++) {
+        free(s->phiL[e]); free(s->serU[e]); free(s->serI[e]); free(s->lastU[e]); free(s->lastI[e]);
+    }
     free(s->serVin); free(s->serI1); free(s->lastVin); free(s->lastI1);
     free(s);
 }
@@ -613,8 +744,14 @@ double orc_split_target(orc_sim* s, int32_t sp, int32_t i) { return o_split_targ
 
 int orc_diag_get(orc_sim* s, orc_diag* d) {
     memset(d, 0, sizeof(*d));
-    d->t = s->t; d->U_E = s->U_E; d->Q_E = s->Q_E; d->C_eq = s->C_eq; d->Q_P = s->Q_P;
-    d->I_ccp = s->I_ccp; d->dt = s->dt; d->w_unit = s->w_unit; d->n_gas = s->n_gas;
+    d->t = s->t; d->U_E = s->U_E[0]; d->Q_E = s->Q_E[0]; d->C_eq = s->Cm[0][0]; d->Q_P = s->Q_P[0];
+    d->I_ccp = s->I_ccp[0]; d->dt = s->dt; d->w_unit = s->w_unit; d->n_gas = s->n_gas;
+    d->n_el = s->n_el;
+    for (int e = 0; e < s->n_el; e++) {
+        d->U_el[e] = s->U_E[e]; d->Q_el[e] = s->Q_E[e]; d->QP_el[e] = s->Q_P[e]; d->I_el[e] = s->I_ccp[e];
+        for (int f = 0; f < s->n_el; f++) d->C_el[e * ORC_MAX_EL + f] = s->Cm[e][f];
+        for (int sp = 0; sp < 2; sp++) d->absorbed_el[sp][e] = s->cnt[sp][o_slot_of(e + 1)];
+    }
     memcpy(d->circ, s->circ, sizeof(d->circ));
     d->nu_max[0] = s->nu_max[0]; d->nu_max[1] = s->nu_max[1];
     d->thresh[0] = s->thresh[0]; d->thresh[1] = s->thresh[1];
@@ -634,17 +771,21 @@ int orc_diag_get(orc_sim* s, orc_diag* d) {
     d->solver_iters = s->solver_iters;
     d->solver_relres = s->solver_relres;
     if (s->have_last) {
-        harmonics(s->lastU, s->cfg.steps_per_period, d->harm_U_re, d->harm_U_im);
-        harmonics(s->lastI, s->cfg.steps_per_period, d->harm_I_re, d->harm_I_im);
-        o_characterise(&s->cfg, s->lastU, s->lastI, s->lastVin, s->lastI1, s->last_energy, d->elec);
+        harmonics(s->lastU[0], s->cfg.steps_per_period, d->harm_U_re, d->harm_U_im);
+        harmonics(s->lastI[0], s->cfg.steps_per_period, d->harm_I_re, d->harm_I_im);
+        for (int e = 0; e < s->n_el; e++) {
+            harmonics(s->lastU[e], s->cfg.steps_per_period, d->hU_re[e], d->hU_im[e]);
+            harmonics(s->lastI[e], s->cfg.steps_per_period, d->hI_re[e], d->hI_im[e]);
+        }
+        o_characterise(&s->cfg, s->lastU[0], s->lastI[0], s->lastVin, s->lastI1, s->last_energy, d->elec);
     }
     return 0;
 }
 
 int orc_series(orc_sim* s, int32_t last, double* U_out, double* I_out) {
     int spp = s->cfg.steps_per_period;
-    memcpy(U_out, last ? s->lastU : s->serU, sizeof(double) * spp);
-    memcpy(I_out, last ? s->lastI : s->serI, sizeof(double) * spp);
+    memcpy(U_out, last ? s->lastU[0] : s->serU[0], sizeof(double) * spp);
+    memcpy(I_out, last ? s->lastI[0] : s->serI[0], sizeof(double) * spp);
     return 0;
 }
 
@@ -691,7 +832,7 @@ int orc_get_grid(orc_sim* s, int32_t which, void* out) {
     case ORC_G_NODE_KIND: memcpy(out, s->node_kind, nn * 4); return 0;
     case ORC_G_CELL_KIND: memcpy(out, s->cell_kind, nc * 4); return 0;
     case ORC_G_VOL: memcpy(out, s->vol, nn * 8); return 0;
-    case ORC_G_PHI_L: memcpy(out, s->phiL, nn * 8); return 0;
+    case ORC_G_PHI_L: memcpy(out, s->phiL[0], nn * 8); return 0;
     case ORC_G_Q: memcpy(out, s->Q, nn * 8); return 0;
     case ORC_G_AR: memcpy(out, s->ar, nn * 8); return 0;
     case ORC_G_AZ: memcpy(out, s->az, nn * 8); return 0;
@@ -714,32 +855,46 @@ int orc_set_grid(orc_sim* s, int32_t which, const void* in) {
     case ORC_G_DEP_I: memcpy(s->dep[1], in, nn * 8); return 0;
     case ORC_G_PHI: memcpy(s->phi, in, nn * 8); return 0;
     case ORC_G_WALLQ: memcpy(s->wallq, in, nn * 8); return 0;
-    case ORC_G_PHI_L: memcpy(s->phiL, in, nn * 8); return 0;
+    case ORC_G_PHI_L: memcpy(s->phiL[0], in, nn * 8); return 0;
     }
     return -1;
 }
 
 int orc_set_state(orc_sim* s, const double* st) {
-    s->t = st[0]; s->Q_E = st[1]; s->U_E = st[2];
-    for (int k = 0; k < 5; k++) s->circ[k] = st[3 + k];
-    s->C_eq = st[8];
+    s->t = st[0]; s->Q_E[0] = st[1]; s->U_E[0] = st[2];
+    for (int k = 0; k < 5; k++) s->circ[0][k] = st[3 + k];
+    s->Cm[0][0] = st[8];
     return 0;
 }
 
 /* ------------------------------------------------------------ pure pieces */
-int orc_solve_q(orc_sim* s, const double* Q, const double* chi, double U_E, double tol, double* phi_inout,
-                int32_t* iters, double* relres) {
+int orc_solve_qv(orc_sim* s, const double* Q, const double* chi, const double* U, double tol, double* phi_inout,
+                 int32_t* iters, double* relres) {
     double* ar = calloc(s->nn, sizeof(double));
     double* az = calloc(s->nn, sizeof(double));
     o_faces_from_chi(s, chi, ar, az);
     int it;
     double rel;
-    int rc = o_solve(s, ar, az, Q, U_E, tol, phi_inout, &it, &rel);
+    double Uv[ORC_MAX_EL] = {0.0};
+    for (int e = 0; e < s->n_el; e++) Uv[e] = U[e];
+    int rc = o_solve(s, ar, az, Q, Uv, tol, phi_inout, &it, &rel);
     if (iters) *iters = it;
     if (relres) *relres = rel;
     free(ar);
     free(az);
     return rc;
+}
+
+int orc_solve_q(orc_sim* s, const double* Q, const double* chi, double U_E, double tol, double* phi_inout,
+                int32_t* iters, double* relres) {
+    double U[ORC_MAX_EL] = {U_E, 0.0, 0.0, 0.0};
+    return orc_solve_qv(s, Q, chi, U, tol, phi_inout, iters, relres);
+}
+
+int orc_get_phiL(orc_sim* s, int32_t e, double* out) {
+    if (e < 1 || e > s->n_el) return -1;
+    memcpy(out, s->phiL[e - 1], sizeof(double) * s->nn);
+    return 0;
 }
 
 double orc_refresh_laplace(orc_sim* s) { return o_laplace(s); }

@@ -10,9 +10,11 @@ Pa, kelvin to eV) are input preparation, not part of the method.
 Geometry convention (shared by both implementations): a list of rectangles in
 metres ``(r0, r1, z0, z1, kind, cond_id, eps_r)``; a cell takes the last
 rectangle that contains its centre; ``kind`` is 0 vacuum, 1 dielectric,
-2 conductor; ``cond_id`` 0 is ground, 1 the RF-driven electrode.  ``edge_bc``
-gives the conductor id of the r=R, z=0 and z=Z domain edges, or -1 for a
-Neumann (symmetry) edge.  The r=0 edge is the axis.
+2 conductor; ``cond_id`` 0 is ground, 1 the RF-driven electrode (2, 3, 4
+further driven electrodes, whose circuits the optional list
+``circuits_more`` gives in order).  ``edge_bc`` gives the conductor id of
+the r=R, z=0 and z=Z domain edges, or -1 for a Neumann (symmetry) edge.  The
+r=0 edge is the axis.
 """
 import copy
 
@@ -30,6 +32,16 @@ SOLVE_MGPCG_FP64, SOLVE_IR_MG, SOLVE_IR_UNET = 0, 1, 2
 def parallel_plate_geometry(nr=32, nz=24, R=0.05, Z=0.0254):
     """Powered plate at z=0, grounded plate at z=Z and grounded wall at r=R."""
     return dict(nr=nr, nz=nz, R=R, Z=Z, regions=[],
+                edge_bc=[GROUND, POWERED, GROUND])
+
+
+def disk_electrode_geometry(nr=32, nz=24, R=0.05, Z=0.0254):
+    """Parallel plate with a second driven electrode: powered plate at z=0
+    (electrode 1), a disk electrode 2 of radius R/2 one cell thick, two cells
+    below the grounded top wall, grounded wall at r=R."""
+    dz = Z / nz
+    return dict(nr=nr, nz=nz, R=R, Z=Z,
+                regions=[(0.0, R / 2, Z - 3 * dz, Z - 2 * dz, COND, 2, 1.0)],
                 edge_bc=[GROUND, POWERED, GROUND])
 
 
@@ -82,6 +94,18 @@ WORKLOADS = {
     "pp32x24": dict(
         geometry=parallel_plate_geometry(),
         circuit=_circuit(CIRC_IDEAL, U_amp=100.0),
+        gas=dict(p_Pa=20 * MTORR_PA, T_K=300.0),
+        run=dict(n_e=20_000, n_i=20_000, cap_e=80_000, cap_i=80_000,
+                 n0=1e14, Te_eV=2.0, Ti_eV=0.026, steps_per_period=200,
+                 seed=1, sort_every=20, sort_every_ion=20, steps=2000),
+        solver=dict(method=SOLVE_MGPCG_FP64, tol=1e-8, max_iter=200),
+    ),
+    # Two driven electrodes (dual frequency): the plate at 13.56 MHz, a disk
+    # electrode at 27.12 MHz.
+    "pp32x24x2": dict(
+        geometry=disk_electrode_geometry(),
+        circuit=_circuit(CIRC_IDEAL, U_amp=100.0),
+        circuits_more=[_circuit(CIRC_IDEAL, freq=27.12e6, U_amp=50.0)],
         gas=dict(p_Pa=20 * MTORR_PA, T_K=300.0),
         run=dict(n_e=20_000, n_i=20_000, cap_e=80_000, cap_i=80_000,
                  n0=1e14, Te_eV=2.0, Ti_eV=0.026, steps_per_period=200,
