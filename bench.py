@@ -103,6 +103,36 @@ def learned_vs_plain(sim, args, w):
     }
 
 
+def electrodes_pass(args):
+    """Cost of a second driven electrode on the same grid without particles:
+    the lower GEC electrode driven (ideal, 2 MHz) besides the upper one.  One
+    RF period of steps each; field-solve ms per step and the once-per-period
+    refresh (one Laplace solve per electrode and the capacitance matrix)."""
+    import torch
+    from paper_2310_04957_amd.pic import Pic
+    from pic_inputs import workload
+    from pic_inputs.workloads import CIRC_IDEAL, _circuit, gec_geometry
+    w0 = workload(args.workload)
+    refine = w0["geometry"]["nr"] // 128
+    res = {"grid": f"{w0['geometry']['nr']}x{w0['geometry']['nz']}", "particles": 0}
+    for n_el in (1, 2):
+        w = workload(args.workload)
+        w["run"].update(n_e=0, n_i=0, cap_e=1, cap_i=1)
+        if n_el == 2:
+            w["geometry"] = gec_geometry(refine, driven_lower=True)
+            w["circuits_more"] = [_circuit(CIRC_IDEAL, freq=2e6, U_amp=100.0)]
+        sim = Pic(w, load=False, timing=True)
+        spp = w["run"]["steps_per_period"]
+        sim.reset_timers()
+        sim.step(spp)
+        torch.cuda.synchronize()
+        d = sim.diag()
+        res[str(n_el)] = {"field_ms_per_step": d.ms_field / spp, "refresh_ms": d.ms_refresh,
+                          "capacitance_pF": [[round(x * 1e12, 4) for x in row] for row in sim.capacitance()]}
+        sim.close()
+    return res
+
+
 def split_pass(sim):
     """One particle-splitting pass per species on the discharge as it stands
     (equal loading weights: particles near the axis are heavier than the
@@ -140,6 +170,8 @@ def main():
     ap.add_argument("--learned-train-steps", type=int, default=150)
     ap.add_argument("--learned-batch", type=int, default=4)
     ap.add_argument("--learned-solve-steps", type=int, default=3)
+    ap.add_argument("--no-electrodes-pass", action="store_true",
+                    help="skip timing the field solve and refresh with one and two driven electrodes")
     ap.add_argument("--no-split-pass", action="store_true",
                     help="skip timing one particle-splitting pass per species after the run")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -243,6 +275,9 @@ def main():
         print("[bench] particle-splitting pass", file=sys.stderr, flush=True)
         out["split_pass"] = split_pass(sim)
     sim.close()
+    if not args.no_electrodes_pass and args.workload.startswith("gec"):
+        print("[bench] driven electrodes", file=sys.stderr, flush=True)
+        out["electrodes_pass"] = electrodes_pass(args)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_sample, args.cpu_steps)

@@ -35,6 +35,7 @@ extern "C" {
 
 #define PIC_ABI_VERSION 1
 #define PIC_MAX_REGIONS 32
+#define PIC_MAX_ELECTRODES 4           /* driven electrodes: conductor ids 1 .. 4 */
 
 enum {
     PIC_OK = 0,
@@ -59,8 +60,8 @@ enum { PIC_SOLVE_MGPCG_FP64 = 0, PIC_SOLVE_IR_MG = 1, PIC_SOLVE_IR_UNET = 2, PIC
 enum { PIC_WEIGHTS_EQUAL = 0, PIC_WEIGHTS_CELL = 1 };                /* initial macro-particle weights */
 
 /* A rectangle [r0,r1) x [z0,z1) in metres.  Each cell takes the last region
-   that contains its centre.  kind PIC_COND uses cond_id (0 ground, 1 the
-   driven electrode); PIC_DIEL uses eps_r. */
+   that contains its centre.  kind PIC_COND uses cond_id (0 ground, 1 .. n_el
+   a driven electrode); PIC_DIEL uses eps_r. */
 typedef struct {
     double r0, r1, z0, z1;
     int32_t kind, cond_id;
@@ -125,6 +126,16 @@ typedef struct {
     pic_gas gas;
     pic_run run;
     pic_solver solver;
+    /* Several driven electrodes (Sec. 2: each metal electrode has its own
+       equivalent capacitance and circuit): conductor ids 1 .. n_el (0 means
+       1).  Electrode 1 uses circ, electrode e >= 2 circ_el[e - 2].  The
+       electrodes couple through the capacitance matrix C (the field-energy
+       bilinear form of their Laplace solutions): Q = C U + Q_P, so an ideal
+       source fixes its electrode's voltage and the other voltages follow
+       from their charges.  One time step's substep count is the largest of
+       the circuits'. */
+    int32_t n_el;
+    pic_circuit circ_el[PIC_MAX_ELECTRODES - 1];
 } pic_config;
 
 typedef struct pic_handle pic_handle;
@@ -156,6 +167,19 @@ typedef struct {
     double Z_ccp_re, Z_ccp_im, Z_load_re, Z_load_im, gamma_abs;
     double P_source, P_Rs, P_imn, P_stray, P_ccp, P_forward, P_ref;
     int64_t split_added[2];     /* particles added by splitting since init, per species */
+    /* per driven electrode e = 1 .. n_el at index e - 1: voltage, charge,
+       induced charge Q_P, circuit current, the capacitance matrix (row-major
+       PIC_MAX_ELECTRODES x PIC_MAX_ELECTRODES, F), harmonics 0..5 of voltage
+       and current over the last RF period of electrode 1's source, and the
+       charge absorbed per species (units 2^-32 w_unit).  U_E, Q_E, C_eq, Q_P,
+       I_ccp, the harmonics and the characterisation above are electrode 1's. */
+    int32_t n_el;
+    double U_el[PIC_MAX_ELECTRODES], Q_el[PIC_MAX_ELECTRODES], QP_el[PIC_MAX_ELECTRODES];
+    double I_el[PIC_MAX_ELECTRODES];
+    double C_el[PIC_MAX_ELECTRODES * PIC_MAX_ELECTRODES];
+    double hU_re[PIC_MAX_ELECTRODES][6], hU_im[PIC_MAX_ELECTRODES][6];
+    double hI_re[PIC_MAX_ELECTRODES][6], hI_im[PIC_MAX_ELECTRODES][6];
+    int64_t absorbed_el[2][PIC_MAX_ELECTRODES];
 } pic_diag_out;
 
 typedef struct {
@@ -203,7 +227,9 @@ enum {
     PIC_G_ER = 3, PIC_G_EZ = 4,       /* float, node electric field */
     PIC_G_CHI = 5,                    /* double */
     PIC_G_WALLQ = 6,                  /* int64 dielectric surface charge */
-    PIC_G_PHI_L = 10, PIC_G_Q = 11, PIC_G_AR = 12, PIC_G_AZ = 13 /* double */
+    PIC_G_PHI_L = 10, PIC_G_Q = 11, PIC_G_AR = 12, PIC_G_AZ = 13, /* double */
+    /* double: Laplace solutions of driven electrodes 2, 3, 4 (PHI_L is electrode 1's) */
+    PIC_G_PHI_L2 = 14, PIC_G_PHI_L3 = 15, PIC_G_PHI_L4 = 16
 };
 int pic_get_grid(pic_handle* h, int32_t which, void* host);
 int pic_set_grid(pic_handle* h, int32_t which, const void* host); /* DEP_E, DEP_I, WALLQ, PHI */
@@ -230,10 +256,15 @@ int pic_sort_now(pic_handle* h, int32_t species, int64_t* perm_out);
 int pic_split_now(pic_handle* h, int32_t species, int64_t* added);
 
 /* One solve of Eq. (1) on given node charges Q (C) and susceptibility chi
-   with the driven electrode at U_E; phi_inout is the warm start and the
-   result.  Uses the configured method; tol overrides the configured one. */
+   with driven electrode 1 at U_E (any others at 0 V); phi_inout is the warm
+   start and the result.  Uses the configured method; tol overrides the
+   configured one. */
 int pic_solve_once(pic_handle* h, const double* Q, const double* chi, double U_E, double tol,
                    double* phi_inout, int32_t* iters, double* relres);
+
+/* The same with driven electrode e at U[e - 1], e = 1 .. n_el (host array). */
+int pic_solve_once_el(pic_handle* h, const double* Q, const double* chi, const double* U, double tol,
+                      double* phi_inout, int32_t* iters, double* relres);
 
 /* Set t, Q_E, U_E, circ[5], C_eq (9 doubles) -- for single-step parity. */
 int pic_set_state(pic_handle* h, const double* st9);

@@ -34,20 +34,24 @@ int validate(const pic_config* c) {
     const pic_geometry& g = c->geom;
     if (g.nr < 4 || g.nz < 4 || (g.nr & 1) || (g.nz & 1) || g.nr > 4096 || g.nz > 4096) return PIC_E_CONFIG;
     if (!(g.R > 0) || !(g.Z > 0) || g.n_regions < 0 || g.n_regions > PIC_MAX_REGIONS) return PIC_E_CONFIG;
+    if (c->n_el < 0 || c->n_el > PIC_MAX_ELECTRODES) return PIC_E_CONFIG;
+    const int n_el = c->n_el > 0 ? c->n_el : 1;
     for (int k = 0; k < 3; ++k)
-        if (g.edge_bc[k] < -1 || g.edge_bc[k] > 1) return PIC_E_CONFIG;
+        if (g.edge_bc[k] < -1 || g.edge_bc[k] > n_el) return PIC_E_CONFIG;
     for (int k = 0; k < g.n_regions; ++k) {
         const pic_region& r = g.regions[k];
         if (r.kind < 0 || r.kind > 2) return PIC_E_CONFIG;
-        if (r.kind == PIC_COND && (r.cond_id < 0 || r.cond_id > 1)) return PIC_E_CONFIG;
+        if (r.kind == PIC_COND && (r.cond_id < 0 || r.cond_id > n_el)) return PIC_E_CONFIG;
         if (r.kind == PIC_DIEL && !(r.eps_r >= 1.0)) return PIC_E_CONFIG;
     }
-    const pic_circuit& ci = c->circ;
-    if (!(ci.freq > 0) || ci.kind < 0 || ci.kind > 2 || ci.substeps < 1) return PIC_E_CONFIG;
-    if (ci.kind == PIC_LMATCH && !(ci.C_m1 > 0 && ci.C_m2 > 0 && ci.L_m > 0 && ci.R_s > 0 && ci.C_stray > 0 &&
-                                   ci.L_stray > 0))
-        return PIC_E_CONFIG;
-    if (ci.kind == PIC_SERIES_RLC && !(ci.C_b > 0 && ci.L_b > 0)) return PIC_E_CONFIG;
+    for (int e = 0; e < n_el; ++e) {
+        const pic_circuit& ci = e == 0 ? c->circ : c->circ_el[e - 1];
+        if (!(ci.freq > 0) || ci.kind < 0 || ci.kind > 2 || ci.substeps < 1) return PIC_E_CONFIG;
+        if (ci.kind == PIC_LMATCH && !(ci.C_m1 > 0 && ci.C_m2 > 0 && ci.L_m > 0 && ci.R_s > 0 && ci.C_stray > 0 &&
+                                       ci.L_stray > 0))
+            return PIC_E_CONFIG;
+        if (ci.kind == PIC_SERIES_RLC && !(ci.C_b > 0 && ci.L_b > 0)) return PIC_E_CONFIG;
+    }
     const pic_run& r = c->run;
     if (r.steps_per_period < 1 || r.n_e < 0 || r.n_i < 0 || r.cap_e < r.n_e || r.cap_i < r.n_i) return PIC_E_CONFIG;
     if (r.weights < PIC_WEIGHTS_EQUAL || r.weights > PIC_WEIGHTS_CELL || r.split < 0 || r.split > 1) return PIC_E_CONFIG;
@@ -109,6 +113,7 @@ double sigma_total_e(double eps) {
 void derive(pic_handle* h) {
     const pic_config& c = h->cfg;
     h->nr = c.geom.nr; h->nz = c.geom.nz; h->w = h->nr + 1;
+    h->n_el = c.n_el > 0 ? c.n_el : 1;
     h->nn = (h->nr + 1) * (h->nz + 1);
     h->ncell = h->nr * h->nz;
     h->dr = c.geom.R / h->nr;
@@ -178,7 +183,9 @@ int host_geometry(pic_handle* h) {
     h->h_node_kind.assign((size_t)h->nn, -1);
     for (int j = 0; j <= nz; ++j)
         for (int i = 0; i <= nr; ++i) {
-            bool touch[2] = {false, false};
+            // conductor ids 0 .. kMaxEl (validated); the lowest id touching
+            // the node wins, so ground wins
+            bool touch[1 + kMaxEl] = {};
             for (int cj = j - 1; cj <= j; ++cj)
                 for (int ci = i - 1; ci <= i; ++ci) {
                     if (ci < 0 || cj < 0 || ci >= nr || cj >= nz) continue;
@@ -188,7 +195,10 @@ int host_geometry(pic_handle* h) {
             if (i == nr && g.edge_bc[0] >= 0) touch[g.edge_bc[0]] = true;
             if (j == 0 && g.edge_bc[1] >= 0) touch[g.edge_bc[1]] = true;
             if (j == nz && g.edge_bc[2] >= 0) touch[g.edge_bc[2]] = true;
-            h->h_node_kind[(size_t)j * w + i] = touch[0] ? 0 : (touch[1] ? 1 : -1);
+            int8_t kind = -1;
+            for (int k = kMaxEl; k >= 0; --k)
+                if (touch[k]) kind = (int8_t)k;
+            h->h_node_kind[(size_t)j * w + i] = kind;
         }
     // node volumes: half of each adjacent annulus (r^2 weights), half again on z edges
     h->h_vol.assign((size_t)h->nn, 0.0);
@@ -336,7 +346,8 @@ size_t layout(pic_handle* h, char* base) {
     }
     h->chi = c.take<double>(nn); h->Q = c.take<double>(nn);
     h->ar = c.take<double>(nn); h->az = c.take<double>(nn);
-    h->phi = c.take<double>(nn); h->phiL = c.take<double>(nn); h->zeroQ = c.take<double>(nn);
+    h->phi = c.take<double>(nn); h->zeroQ = c.take<double>(nn);
+    for (int e = 0; e < kMaxEl; ++e) h->phiL[e] = e < h->n_el ? c.take<double>(nn) : nullptr;
     h->phi_prev = c.take<double>(nn);
     h->ar32 = c.take<float>(nn); h->az32 = c.take<float>(nn);
     h->E = c.take<float2>(nn);
@@ -344,7 +355,7 @@ size_t layout(pic_handle* h, char* base) {
     h->p64 = c.take<double>(nn); h->q64 = c.take<double>(nn);
     h->r32 = c.take<float>(nn); h->x32 = c.take<float>(nn); h->z32 = c.take<float>(nn);
     h->p32 = c.take<float>(nn); h->q32 = c.take<float>(nn);
-    h->part = c.take<double>(2 * kRedBlocks);
+    h->part = c.take<double>(kMaxEl * kRedBlocks);
     for (int l = 0; l < h->nlev; ++l) {
         Level& L = h->lv[l];
         const size_t m = (size_t)L.nn;
@@ -360,8 +371,8 @@ size_t layout(pic_handle* h, char* base) {
     h->cinv64 = c.take<double>((size_t)kMaxCoarse * kMaxCoarse);
     h->cinv32 = c.take<float>((size_t)kMaxCoarse * kMaxCoarse);
     const size_t spp = (size_t)h->cfg.run.steps_per_period;
-    h->serU = c.take<double>(spp); h->serI = c.take<double>(spp);
-    h->lastU = c.take<double>(spp); h->lastI = c.take<double>(spp);
+    h->serU = c.take<double>(kMaxEl * spp); h->serI = c.take<double>(kMaxEl * spp);
+    h->lastU = c.take<double>(kMaxEl * spp); h->lastI = c.take<double>(kMaxEl * spp);
     h->serVin = c.take<double>(spp); h->serI1 = c.take<double>(spp);
     h->lastVin = c.take<double>(spp); h->lastI1 = c.take<double>(spp);
     h->ctr = c.take<DevCounters>(1);
@@ -411,20 +422,38 @@ void ev_collect(pic_handle* h) {
     h->ev_pending.clear();
 }
 
-__global__ void k_init_circuit(const double* part, DevScalars* s, const DevCounters* ctr, double U0) {
+struct InitCirc {
+    double U0[kMaxEl];
+    int n_el;
+};
+
+// initial electrode state: voltages U0 (an ideal source's DC value, else 0)
+// held by the charges Q = C U + Q_P
+__global__ void k_init_circuit(const double* part, DevScalars* s, const DevCounters* ctr, InitCirc ic) {
     __shared__ double a[kRedBlocks];
-    for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) a[i] = part[i];
-    __syncthreads();
-    for (int o = kRedBlocks / 2; o > 0; o >>= 1) {
-        for (int i = threadIdx.x; i < o; i += blockDim.x) a[i] += a[i + o];
+    __shared__ double qp[kMaxEl];
+    for (int e = 0; e < ic.n_el; ++e) {
+        for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) a[i] = part[e * kRedBlocks + i];
+        __syncthreads();
+        for (int o = kRedBlocks / 2; o > 0; o >>= 1) {
+            for (int i = threadIdx.x; i < o; i += blockDim.x) a[i] += a[i + o];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) qp[e] = a[0];
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        s->Q_P = a[0];
-        s->U_E = U0;
-        s->Q_E = s->C_eq * U0 + a[0];
-        s->powered_prev = (double)((long long)ctr->absorbed[1][1] - (long long)ctr->absorbed[0][1]);
-        s->one = 1.0;
+        for (int e = 0; e < ic.n_el; ++e) {
+            s->Q_P[e] = qp[e];
+            s->U_E[e] = ic.U0[e];
+        }
+        for (int e = 0; e < ic.n_el; ++e) {
+            double q = 0.0;
+            for (int f = 0; f < ic.n_el; ++f) q += s->Cm[e][f] * ic.U0[f];
+            s->Q_E[e] = q + qp[e];
+            const int sl = slot_of(e + 1);
+            s->el_prev[e] = (double)((long long)ctr->absorbed[1][sl] - (long long)ctr->absorbed[0][sl]);
+        }
     }
 }
 
@@ -435,14 +464,24 @@ __global__ void k_set_slots(DevCounters* c, long long ne, long long ni) {
 
 __global__ void k_set_state(DevScalars* s, double t, double QE, double UE, double c0, double c1, double c2, double c3,
                             double c4, double Ceq) {
-    s->t = t; s->Q_E = QE; s->U_E = UE;
-    s->circ[0] = c0; s->circ[1] = c1; s->circ[2] = c2; s->circ[3] = c3; s->circ[4] = c4;
-    s->C_eq = Ceq;
+    s->t = t; s->Q_E[0] = QE; s->U_E[0] = UE;
+    s->circ[0][0] = c0; s->circ[0][1] = c1; s->circ[0][2] = c2; s->circ[0][3] = c3; s->circ[0][4] = c4;
+    s->Cm[0][0] = Ceq;
 }
 
-__global__ void k_set_one(DevScalars* s) { s->one = 1.0; }
+// identity rows: the Dirichlet values of the electrodes' Laplace problems
+__global__ void k_set_units(DevScalars* s) {
+    for (int e = 0; e < kMaxEl; ++e)
+        for (int f = 0; f < kMaxEl; ++f) s->unit[e][f] = e == f ? 1.0 : 0.0;
+}
 
-__global__ void k_set_U(DevScalars* s, double U) { s->U_E = U; }
+struct Uvec {
+    double U[kMaxEl];
+};
+
+__global__ void k_set_U(DevScalars* s, Uvec u) {
+    for (int e = 0; e < kMaxEl; ++e) s->Uset[e] = u.U[e];
+}
 
 __global__ void k_set_cmap(int* cmap, const int* src, int n) {
     for (int i = threadIdx.x; i < n; i += blockDim.x) cmap[i] = src[i];
@@ -631,7 +670,7 @@ int pic_init(const pic_config* cfg, void* dev_workspace, size_t bytes, void* hip
     if (rc) { pic_free(h); return rc; }
     const int64_t n0[2] = {cfg->run.load ? cfg->run.n_e : 0, cfg->run.load ? cfg->run.n_i : 0};
     hipLaunchKernelGGL(k_set_slots, dim3(1), dim3(1), 0, h->stream, h->ctr, (long long)n0[0], (long long)n0[1]);
-    hipLaunchKernelGGL(k_set_one, dim3(1), dim3(1), 0, h->stream, h->sc);
+    hipLaunchKernelGGL(k_set_units, dim3(1), dim3(1), 0, h->stream, h->sc);
     h->dep_cur = 0;
     h->cur[0] = h->cur[1] = 0;
     // first prediction (a_bar = 0) and deposit; the loaded plasma starts tile-sorted
@@ -644,8 +683,17 @@ int pic_init(const pic_config* cfg, void* dev_workspace, size_t bytes, void* hip
     if (rc) { pic_free(h); return rc; }
     // initial electrode charge: U_E(0) with the induced charge of the load
     launch_assemble(h);
-    hipLaunchKernelGGL(k_init_circuit, dim3(1), dim3(256), 0, h->stream, (const double*)h->part, h->sc,
-                       (const DevCounters*)h->ctr, cfg->circ.kind == PIC_IDEAL_SOURCE ? cfg->circ.U_dc : 0.0);
+    {
+        InitCirc ic;
+        ic.n_el = h->n_el;
+        for (int e = 0; e < kMaxEl; ++e) ic.U0[e] = 0.0;
+        for (int e = 0; e < h->n_el; ++e) {
+            const pic_circuit& ce = e == 0 ? cfg->circ : cfg->circ_el[e - 1];
+            ic.U0[e] = ce.kind == PIC_IDEAL_SOURCE ? ce.U_dc : 0.0;
+        }
+        hipLaunchKernelGGL(k_init_circuit, dim3(1), dim3(256), 0, h->stream, (const double*)h->part, h->sc,
+                           (const DevCounters*)h->ctr, ic);
+    }
     // the assembly above added the first deposit to the period sums: undo
     launch_zero_u64(h->psum[0], (size_t)h->nn, h->stream);
     launch_zero_u64(h->psum[1], (size_t)h->nn, h->stream);
@@ -682,7 +730,7 @@ int pic_step(pic_handle* h, int32_t nsteps) {
         double rel = 0.0;
         h->harvest_now = h->harvest_every > 0 && h->step % h->harvest_every == 0;
         launch_extrapolate(h);
-        int rc = field_solve(h, h->phi, h->Q, &h->sc->U_E, c.solver.tol, c.solver.method, &it, &rel);
+        int rc = field_solve(h, h->phi, h->Q, h->sc->U_E, c.solver.tol, c.solver.method, &it, &rel);
         h->harvest_now = false;
         h->solver_iters = it;
         h->solver_relres = rel;
@@ -747,9 +795,15 @@ int pic_diag(pic_handle* h, pic_diag_out* out, const pic_diag_buffers* bufs) {
     if (hipMemcpy(&sc, h->sc, sizeof(sc), hipMemcpyDeviceToHost) != hipSuccess) return PIC_E_HIP;
     const DevCounters& ct = *h->h_ctr;
     std::memset(out, 0, sizeof(*out));
-    out->t = sc.t; out->U_E = sc.U_E; out->Q_E = sc.Q_E; out->C_eq = sc.C_eq; out->Q_P = sc.Q_P;
-    out->I_ccp = sc.I_ccp; out->dt = h->dt; out->w_unit = h->w_unit; out->n_gas = h->n_gas;
-    for (int k = 0; k < 5; ++k) out->circ[k] = sc.circ[k];
+    out->t = sc.t; out->U_E = sc.U_E[0]; out->Q_E = sc.Q_E[0]; out->C_eq = sc.Cm[0][0]; out->Q_P = sc.Q_P[0];
+    out->I_ccp = sc.I_ccp[0]; out->dt = h->dt; out->w_unit = h->w_unit; out->n_gas = h->n_gas;
+    for (int k = 0; k < 5; ++k) out->circ[k] = sc.circ[0][k];
+    out->n_el = h->n_el;
+    for (int e = 0; e < h->n_el; ++e) {
+        out->U_el[e] = sc.U_E[e]; out->Q_el[e] = sc.Q_E[e]; out->QP_el[e] = sc.Q_P[e]; out->I_el[e] = sc.I_ccp[e];
+        for (int f = 0; f < h->n_el; ++f) out->C_el[e * PIC_MAX_ELECTRODES + f] = sc.Cm[e][f];
+        for (int sp = 0; sp < 2; ++sp) out->absorbed_el[sp][e] = (int64_t)ct.absorbed[sp][slot_of(e + 1)];
+    }
     for (int sp = 0; sp < 2; ++sp) {
         out->nu_max[sp] = h->nu_max[sp];
         out->thresh[sp] = h->thresh[sp];
@@ -782,10 +836,25 @@ int pic_diag(pic_handle* h, pic_diag_out* out, const pic_diag_buffers* bufs) {
     out->split_added[0] = ct.split_added[0];
     out->split_added[1] = ct.split_added[1];
     const int spp = h->cfg.run.steps_per_period;
-    std::vector<double> U(spp), I(spp);
-    if (hipMemcpy(U.data(), h->lastU, spp * 8, hipMemcpyDeviceToHost) != hipSuccess) return PIC_E_HIP;
-    if (hipMemcpy(I.data(), h->lastI, spp * 8, hipMemcpyDeviceToHost) != hipSuccess) return PIC_E_HIP;
+    std::vector<double> UA((size_t)kMaxEl * spp), IA((size_t)kMaxEl * spp);
+    if (hipMemcpy(UA.data(), h->lastU, UA.size() * 8, hipMemcpyDeviceToHost) != hipSuccess) return PIC_E_HIP;
+    if (hipMemcpy(IA.data(), h->lastI, IA.size() * 8, hipMemcpyDeviceToHost) != hipSuccess) return PIC_E_HIP;
+    std::vector<double> U(UA.begin(), UA.begin() + spp), I(IA.begin(), IA.begin() + spp);
     if (h->have_last) {
+        // harmonics 0..5 of each electrode's voltage and current
+        for (int e = 0; e < h->n_el; ++e)
+            for (int k = 0; k < 6; ++k) {
+                double a = 0, b = 0, c = 0, d = 0;
+                for (int n = 0; n < spp; ++n) {
+                    const double ph = 2.0 * kPi * (double)k * (double)n / (double)spp;
+                    const double u = UA[(size_t)e * spp + n], i = IA[(size_t)e * spp + n];
+                    a += u * std::cos(ph); b -= u * std::sin(ph);
+                    c += i * std::cos(ph); d -= i * std::sin(ph);
+                }
+                const double s = (k == 0) ? 1.0 / spp : 2.0 / spp;
+                out->hU_re[e][k] = a * s; out->hU_im[e][k] = b * s;
+                out->hI_re[e][k] = c * s; out->hI_im[e][k] = d * s;
+            }
         std::vector<double> V(spp), J(spp);
         if (hipMemcpy(V.data(), h->lastVin, spp * 8, hipMemcpyDeviceToHost) != hipSuccess) return PIC_E_HIP;
         if (hipMemcpy(J.data(), h->lastI1, spp * 8, hipMemcpyDeviceToHost) != hipSuccess) return PIC_E_HIP;
@@ -900,7 +969,13 @@ int pic_get_grid(pic_handle* h, int32_t which, void* host) {
     case PIC_G_PHI: src = h->phi; break;
     case PIC_G_CHI: src = h->chi; break;
     case PIC_G_WALLQ: src = h->wallq; break;
-    case PIC_G_PHI_L: src = h->phiL; break;
+    case PIC_G_PHI_L: src = h->phiL[0]; break;
+    case PIC_G_PHI_L2:
+    case PIC_G_PHI_L3:
+    case PIC_G_PHI_L4:
+        if (which - PIC_G_PHI_L2 + 1 >= h->n_el) return PIC_E_ARG;
+        src = h->phiL[which - PIC_G_PHI_L2 + 1];
+        break;
     case PIC_G_Q: src = h->Q; break;
     case PIC_G_AR: src = h->ar; break;
     case PIC_G_AZ: src = h->az; break;
@@ -926,7 +1001,7 @@ int pic_set_grid(pic_handle* h, int32_t which, const void* host) {
     case PIC_G_DEP_I: dst = h->dep[h->dep_cur][1]; break;
     case PIC_G_WALLQ: dst = h->wallq; break;
     case PIC_G_PHI: dst = h->phi; h->have_prev = false; break;
-    case PIC_G_PHI_L: dst = h->phiL; break;
+    case PIC_G_PHI_L: dst = h->phiL[0]; break;
     default: return PIC_E_ARG;
     }
     return hipMemcpy(dst, host, (size_t)h->nn * 8, hipMemcpyHostToDevice) == hipSuccess ? PIC_OK : PIC_E_HIP;
@@ -958,23 +1033,31 @@ int pic_split_now(pic_handle* h, int32_t species, int64_t* added) {
     return PIC_OK;
 }
 
-int pic_solve_once(pic_handle* h, const double* Q, const double* chi, double U_E, double tol, double* phi_inout,
-                   int32_t* iters, double* relres) {
-    if (!h || !Q || !chi || !phi_inout) return PIC_E_ARG;
+int pic_solve_once_el(pic_handle* h, const double* Q, const double* chi, const double* U, double tol,
+                      double* phi_inout, int32_t* iters, double* relres) {
+    if (!h || !Q || !chi || !phi_inout || !U) return PIC_E_ARG;
     const size_t nn = (size_t)h->nn;
     if (hipMemcpyAsync(h->Q, Q, nn * 8, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
         hipMemcpyAsync(h->chi, chi, nn * 8, hipMemcpyHostToDevice, h->stream) != hipSuccess ||
         hipMemcpyAsync(h->phi, phi_inout, nn * 8, hipMemcpyHostToDevice, h->stream) != hipSuccess)
         return PIC_E_HIP;
-    hipLaunchKernelGGL(k_set_U, dim3(1), dim3(1), 0, h->stream, h->sc, U_E);
+    Uvec u;
+    for (int e = 0; e < kMaxEl; ++e) u.U[e] = e < h->n_el ? U[e] : 0.0;
+    hipLaunchKernelGGL(k_set_U, dim3(1), dim3(1), 0, h->stream, h->sc, u);
     launch_faces(h);
     mg_rebuild(h);
     h->harvest_now = h->harvest_every > 0;
     h->have_prev = false;
-    int rc = field_solve(h, h->phi, h->Q, &h->sc->U_E, tol, h->cfg.solver.method, iters, relres);
+    int rc = field_solve(h, h->phi, h->Q, h->sc->Uset, tol, h->cfg.solver.method, iters, relres);
     h->harvest_now = false;
     if (hipMemcpy(phi_inout, h->phi, nn * 8, hipMemcpyDeviceToHost) != hipSuccess) return PIC_E_HIP;
     return rc;
+}
+
+int pic_solve_once(pic_handle* h, const double* Q, const double* chi, double U_E, double tol, double* phi_inout,
+                   int32_t* iters, double* relres) {
+    double U[kMaxEl] = {U_E, 0.0, 0.0, 0.0};
+    return pic_solve_once_el(h, Q, chi, U, tol, phi_inout, iters, relres);
 }
 
 int pic_set_state(pic_handle* h, const double* st9) {

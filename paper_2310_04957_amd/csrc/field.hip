@@ -58,20 +58,22 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 struct AsmArgs {
     const unsigned long long *dep_e, *dep_i, *wallq;
     unsigned long long *next_e, *next_i, *psum_e, *psum_i;
-    const double *vol, *phiL;
+    const double* vol;
+    const double* phiL[kMaxEl];
     const int8_t* nk;
     double *chi, *Q, *part;
     double ce, ci, qunit;
-    int nn;
+    int nn, n_el;
 };
 
 // chi_n = 1/2 dt^2 sum_s (q_s^2/m_s) n_s / eps0 (the D1 linearised response),
 // Q_n = node charge of the predicted positions plus the dielectric surface
 // charge; also the period sums, the clearing of the next deposit buffer and
-// the partial sums of Q_P = -sum phi_L Q.
+// the partial sums of Q_P = -sum phi_L Q for each driven electrode
+// (part[e kRedBlocks + block]).
 __global__ __launch_bounds__(256) void k_assemble(AsmArgs a) {
     __shared__ double sh[4];
-    double qp = 0.0;
+    double qp[kMaxEl] = {0.0, 0.0, 0.0, 0.0};
     for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < a.nn; n += gridDim.x * blockDim.x) {
         long long Ne = (long long)a.dep_e[n], Ni = (long long)a.dep_i[n];
         long long W = (long long)a.wallq[n];
@@ -82,10 +84,13 @@ __global__ __launch_bounds__(256) void k_assemble(AsmArgs a) {
         a.psum_i[n] += (unsigned long long)Ni;
         a.next_e[n] = 0ull;
         a.next_i[n] = 0ull;
-        if (a.nk[n] < 0) qp -= a.phiL[n] * q;
+        if (a.nk[n] < 0)
+            for (int e = 0; e < a.n_el; ++e) qp[e] -= a.phiL[e][n] * q;
     }
-    double t = block_sum(qp, sh);
-    if (threadIdx.x == 0) a.part[blockIdx.x] = t;
+    for (int e = 0; e < a.n_el; ++e) {
+        double t = block_sum(qp[e], sh);
+        if (threadIdx.x == 0) a.part[e * kRedBlocks + blockIdx.x] = t;
+    }
 }
 
 void launch_assemble(pic_handle* h) {
@@ -94,7 +99,9 @@ void launch_assemble(pic_handle* h) {
     a.dep_e = h->dep[c][0]; a.dep_i = h->dep[c][1]; a.wallq = h->wallq;
     a.next_e = h->dep[o][0]; a.next_i = h->dep[o][1];
     a.psum_e = h->psum[0]; a.psum_i = h->psum[1];
-    a.vol = h->vol; a.phiL = h->phiL; a.nk = h->node_kind;
+    a.vol = h->vol; a.nk = h->node_kind;
+    a.n_el = h->n_el;
+    for (int e = 0; e < kMaxEl; ++e) a.phiL[e] = h->phiL[e];
     a.chi = h->chi; a.Q = h->Q; a.part = h->part;
     a.ce = h->chi_c[0]; a.ci = h->chi_c[1]; a.qunit = h->qunit; a.nn = h->nn;
     hipLaunchKernelGGL(k_assemble, dim3(kRedBlocks), dim3(256), 0, h->stream, a);
@@ -121,21 +128,29 @@ void launch_faces(pic_handle* h) {
 }
 
 // ---------------------------------------------------------------- circuit
+struct CircEl {
+    int kind, substeps;
+    double freq, U_amp, U_dc, R_s, C_m1, C_m2, L_m, R_m, C_stray, L_stray, R_stray, C_b, R_b, L_b;
+};
+
 struct CircArgs {
     DevScalars* sc;
     const DevCounters* ctr;
     const double* part;
-    double *serU, *serI, *serVin, *serI1;
-    int k, kind, substeps;
-    double dt, qunit, freq, U_amp, U_dc, R_s, C_m1, C_m2, L_m, R_m, C_stray, L_stray, R_stray, C_b, R_b, L_b;
+    double *serU, *serI, *serVin, *serI1;   // serU, serI: kMaxEl blocks of spp
+    int k, spp, n_el;
+    double dt, qunit;
+    CircEl ce[kMaxEl];
 };
 
+__device__ __forceinline__ double source_v(const CircEl& c, double t) {
+    return c.U_amp * sin(2.0 * 3.14159265358979323846 * c.freq * t) + c.U_dc;
+}
+
 // y: L-match (Eq. 10) Q1, Q2, I2, Q_ccp, I_stray; series RLC (Eq. 9) Q_b, I_b;
-// y[5] the electrode charge of Eq. (8).  U_E = (Q_E - Q_P)/C_eq.
-__device__ void circ_f(const CircArgs& a, double C_eq, double Q_P, double I_conv, double t, const double* y,
-                       double* dy) {
-    const double U_E = (y[5] - Q_P) / C_eq;
-    const double Us = a.U_amp * sin(2.0 * 3.14159265358979323846 * a.freq * t) + a.U_dc;
+// y[5] the electrode charge of Eq. (8); U_E the electrode voltage.
+__device__ void circ_f(const CircEl& a, double U_E, double I_conv, double t, const double* y, double* dy) {
+    const double Us = source_v(a, t);
     for (int k = 0; k < 6; ++k) dy[k] = 0.0;
     if (a.kind == PIC_LMATCH) {
         const double Um1 = (y[0] - y[1]) / a.C_m1;
@@ -152,13 +167,11 @@ __device__ void circ_f(const CircArgs& a, double C_eq, double Q_P, double I_conv
     }
 }
 
-// Element powers at state y, time t (the integrands of Eq. 13): source,
-// R_s, matching network R_m (or series-branch R_b), stray branch, plasma
-// load U_E I_ccp.
-__device__ void circ_p(const CircArgs& a, double C_eq, double Q_P, double t, const double* y, double* p) {
-    const double U_E = (y[5] - Q_P) / C_eq;
-    const double Us = a.U_amp * sin(2.0 * 3.14159265358979323846 * a.freq * t) + a.U_dc;
-    p[0] = p[1] = p[2] = p[3] = p[4] = 0.0;
+// element powers (Eq. 13 integrands): source, R_s, R_m or R_b, stray, load
+// U_E I_ccp.
+__device__ void circ_p(const CircEl& a, double U_E, double t, const double* y, double* p) {
+    const double Us = source_v(a, t);
+    for (int k = 0; k < 5; ++k) p[k] = 0.0;
     if (a.kind == PIC_LMATCH) {
         const double I1 = (Us - (y[0] - y[1]) / a.C_m1) / a.R_s;
         p[0] = Us * I1;
@@ -173,98 +186,186 @@ __device__ void circ_p(const CircArgs& a, double C_eq, double Q_P, double t, con
     }
 }
 
+// Electrode voltages at time t for circuit states Y: Q = C U + Q_P, so an
+// ideal source fixes its electrode's voltage and the other electrodes solve
+// C_NN U_N = Q_N - Q_P,N - C_NK U_K (Gaussian elimination on the symmetric
+// positive definite block; one electrode: U = (Q - Q_P) / C_eq).
+__device__ void volts(const CircArgs& a, const double (*C)[kMaxEl], const double* QP, double t,
+                      const double (*Y)[6], double* U) {
+    int N[kMaxEl], nN = 0;
+    for (int e = 0; e < a.n_el; ++e) {
+        if (a.ce[e].kind == PIC_IDEAL_SOURCE) U[e] = source_v(a.ce[e], t);
+        else N[nN++] = e;
+    }
+    if (nN == 0) return;
+    double A[kMaxEl][kMaxEl], b[kMaxEl];
+    for (int r = 0; r < nN; ++r) {
+        const int e = N[r];
+        b[r] = Y[e][5] - QP[e];
+        for (int f = 0; f < a.n_el; ++f)
+            if (a.ce[f].kind == PIC_IDEAL_SOURCE) b[r] -= C[e][f] * U[f];
+        for (int q = 0; q < nN; ++q) A[r][q] = C[e][N[q]];
+    }
+    for (int p = 0; p < nN; ++p)
+        for (int r = p + 1; r < nN; ++r) {
+            const double m = A[r][p] / A[p][p];
+            for (int q = p; q < nN; ++q) A[r][q] -= m * A[p][q];
+            b[r] -= m * b[p];
+        }
+    for (int r = nN - 1; r >= 0; --r) {
+        double x = b[r];
+        for (int q = r + 1; q < nN; ++q) x -= A[r][q] * U[N[q]];
+        U[N[r]] = x / A[r][r];
+    }
+}
+
+// One circuit step (Sec. 2, Eqs. 8-10): the induced charges Q_P from the
+// assembly's partial sums, the convective currents from the absorbed-charge
+// counters, then RK4 of all circuits together (substeps: the largest of the
+// circuits'), electrode 1's element energies by the trapezoid rule, and the
+// voltage series.  One block; thread 0 integrates.
 __global__ __launch_bounds__(256) void k_circuit(CircArgs a) {
     __shared__ double sh[kRedBlocks];
-    for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) sh[i] = a.part[i];
-    __syncthreads();
-    for (int o = kRedBlocks / 2; o > 0; o >>= 1) {
-        for (int i = threadIdx.x; i < o; i += blockDim.x) sh[i] += sh[i + o];
+    __shared__ double sQP[kMaxEl];
+    for (int e = 0; e < a.n_el; ++e) {
+        for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) sh[i] = a.part[e * kRedBlocks + i];
+        __syncthreads();
+        for (int o = kRedBlocks / 2; o > 0; o >>= 1) {
+            for (int i = threadIdx.x; i < o; i += blockDim.x) sh[i] += sh[i + o];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) sQP[e] = sh[0];
         __syncthreads();
     }
     if (threadIdx.x != 0) return;
     DevScalars* s = a.sc;
-    const double Q_P = sh[0];
-    const long long pc = (long long)a.ctr->absorbed[1][1] - (long long)a.ctr->absorbed[0][1];
-    const double I_conv = ((double)pc - s->powered_prev) * a.qunit / a.dt;
-    s->powered_prev = (double)pc;
-    s->Q_P = Q_P;
+    double QP[kMaxEl], Iconv[kMaxEl];
+    for (int e = 0; e < a.n_el; ++e) {
+        const int sl = slot_of(e + 1);
+        const long long pc = (long long)a.ctr->absorbed[1][sl] - (long long)a.ctr->absorbed[0][sl];
+        Iconv[e] = ((double)pc - s->el_prev[e]) * a.qunit / a.dt;
+        s->el_prev[e] = (double)pc;
+        QP[e] = sQP[e];
+        s->Q_P[e] = QP[e];
+    }
     const double t0 = s->t, t1 = t0 + a.dt;
-    if (a.kind == PIC_IDEAL_SOURCE) {
-        const double U0 = s->U_E;
-        const double U = a.U_amp * sin(2.0 * 3.14159265358979323846 * a.freq * t1) + a.U_dc;
-        const double QE = s->C_eq * U + Q_P;
-        s->I_ccp = (QE - s->Q_E) / a.dt - I_conv;
-        s->Q_E = QE;
-        s->U_E = U;
-        // the source drives the electrode directly
-        const double e = a.dt * 0.5 * (U0 + U) * s->I_ccp;
-        s->energy[0] += e;
-        s->energy[4] += e;
-        a.serVin[a.k] = U;
-        a.serI1[a.k] = s->I_ccp;
-    } else {
-        double y[6];
-        for (int k = 0; k < 5; ++k) y[k] = s->circ[k];
-        y[5] = s->Q_E;
-        const int qi = (a.kind == PIC_LMATCH) ? 3 : 0;
-        const double q0 = y[qi], q1 = y[0];
-        const int M = a.substeps > 0 ? a.substeps : 1;
+    const double U0 = s->U_E[0];
+    double Y[kMaxEl][6], U[kMaxEl], q0[kMaxEl];
+    int qi[kMaxEl];
+    int M = 0;
+    for (int e = 0; e < a.n_el; ++e) {
+        for (int k = 0; k < 5; ++k) Y[e][k] = s->circ[e][k];
+        Y[e][5] = s->Q_E[e];
+        qi[e] = (a.ce[e].kind == PIC_LMATCH) ? 3 : 0;
+        q0[e] = Y[e][qi[e]];
+        if (a.ce[e].kind != PIC_IDEAL_SOURCE) {
+            const int ms = a.ce[e].substeps > 0 ? a.ce[e].substeps : 1;
+            if (ms > M) M = ms;
+        }
+    }
+    const double q1 = Y[0][0];
+    if (M > 0) {
         const double hh = a.dt / M;
+        const bool pe = a.ce[0].kind != PIC_IDEAL_SOURCE;
         double pa[5], pb[5];
-        circ_p(a, s->C_eq, Q_P, t0, y, pa);
+        if (pe) {
+            volts(a, s->Cm, QP, t0, Y, U);
+            circ_p(a.ce[0], U[0], t0, Y[0], pa);
+        }
         for (int m = 0; m < M; ++m) {
             const double t = t0 + m * hh;
-            double k1[6], k2[6], k3[6], k4[6], yt[6];
-            circ_f(a, s->C_eq, Q_P, I_conv, t, y, k1);
-            for (int k = 0; k < 6; ++k) yt[k] = y[k] + 0.5 * hh * k1[k];
-            circ_f(a, s->C_eq, Q_P, I_conv, t + 0.5 * hh, yt, k2);
-            for (int k = 0; k < 6; ++k) yt[k] = y[k] + 0.5 * hh * k2[k];
-            circ_f(a, s->C_eq, Q_P, I_conv, t + 0.5 * hh, yt, k3);
-            for (int k = 0; k < 6; ++k) yt[k] = y[k] + hh * k3[k];
-            circ_f(a, s->C_eq, Q_P, I_conv, t + hh, yt, k4);
-            for (int k = 0; k < 6; ++k) y[k] += hh / 6.0 * (k1[k] + 2.0 * k2[k] + 2.0 * k3[k] + k4[k]);
-            // element energies: trapezoid rule over the substep
-            circ_p(a, s->C_eq, Q_P, t + hh, y, pb);
-            for (int k = 0; k < 5; ++k) {
-                s->energy[k] += 0.5 * hh * (pa[k] + pb[k]);
-                pa[k] = pb[k];
+            double k1[kMaxEl][6], k2[kMaxEl][6], k3[kMaxEl][6], k4[kMaxEl][6], yt[kMaxEl][6];
+            volts(a, s->Cm, QP, t, Y, U);
+            for (int e = 0; e < a.n_el; ++e) if (a.ce[e].kind) circ_f(a.ce[e], U[e], Iconv[e], t, Y[e], k1[e]);
+            for (int e = 0; e < a.n_el; ++e) for (int k = 0; k < 6; ++k) yt[e][k] = Y[e][k] + 0.5 * hh * k1[e][k];
+            volts(a, s->Cm, QP, t + 0.5 * hh, yt, U);
+            for (int e = 0; e < a.n_el; ++e)
+                if (a.ce[e].kind) circ_f(a.ce[e], U[e], Iconv[e], t + 0.5 * hh, yt[e], k2[e]);
+            for (int e = 0; e < a.n_el; ++e) for (int k = 0; k < 6; ++k) yt[e][k] = Y[e][k] + 0.5 * hh * k2[e][k];
+            volts(a, s->Cm, QP, t + 0.5 * hh, yt, U);
+            for (int e = 0; e < a.n_el; ++e)
+                if (a.ce[e].kind) circ_f(a.ce[e], U[e], Iconv[e], t + 0.5 * hh, yt[e], k3[e]);
+            for (int e = 0; e < a.n_el; ++e) for (int k = 0; k < 6; ++k) yt[e][k] = Y[e][k] + hh * k3[e][k];
+            volts(a, s->Cm, QP, t + hh, yt, U);
+            for (int e = 0; e < a.n_el; ++e) if (a.ce[e].kind) circ_f(a.ce[e], U[e], Iconv[e], t + hh, yt[e], k4[e]);
+            for (int e = 0; e < a.n_el; ++e)
+                if (a.ce[e].kind)
+                    for (int k = 0; k < 6; ++k)
+                        Y[e][k] += hh / 6.0 * (k1[e][k] + 2.0 * k2[e][k] + 2.0 * k3[e][k] + k4[e][k]);
+            if (pe) {
+                volts(a, s->Cm, QP, t + hh, Y, U);
+                circ_p(a.ce[0], U[0], t + hh, Y[0], pb);
+                for (int k = 0; k < 5; ++k) {
+                    s->energy[k] += 0.5 * hh * (pa[k] + pb[k]);
+                    pa[k] = pb[k];
+                }
             }
         }
-        s->I_ccp = (y[qi] - q0) / a.dt;
-        // source-side samples: the matching network's input voltage (across
-        // C_m1) and the source current, or the source voltage and I_b
-        if (a.kind == PIC_LMATCH) {
-            a.serVin[a.k] = (y[0] - y[1]) / a.C_m1;
-            a.serI1[a.k] = (y[0] - q1) / a.dt;
+    }
+    volts(a, s->Cm, QP, t1, Y, U);
+    for (int e = 0; e < a.n_el; ++e) {
+        if (a.ce[e].kind == PIC_IDEAL_SOURCE) {
+            // the charge that holds the source voltage: Q = C U + Q_P
+            double q = 0.0;
+            for (int f = 0; f < a.n_el; ++f) q += s->Cm[e][f] * U[f];
+            q += QP[e];
+            s->I_ccp[e] = (q - s->Q_E[e]) / a.dt - Iconv[e];
+            s->Q_E[e] = q;
         } else {
-            a.serVin[a.k] = a.U_amp * sin(2.0 * 3.14159265358979323846 * a.freq * t1) + a.U_dc;
-            a.serI1[a.k] = s->I_ccp;
+            for (int k = 0; k < 5; ++k) s->circ[e][k] = Y[e][k];
+            s->Q_E[e] = Y[e][5];
+            s->I_ccp[e] = (Y[e][qi[e]] - q0[e]) / a.dt;
         }
-        for (int k = 0; k < 5; ++k) s->circ[k] = y[k];
-        s->Q_E = y[5];
-        s->U_E = (y[5] - Q_P) / s->C_eq;
+        s->U_E[e] = U[e];
+    }
+    // electrode 1: source-side samples (the matching network's input voltage
+    // across C_m1 and the source current, or the source voltage and I_b) and,
+    // for an ideal source, its energy
+    const CircEl& c0 = a.ce[0];
+    if (c0.kind == PIC_IDEAL_SOURCE) {
+        const double e = a.dt * 0.5 * (U0 + U[0]) * s->I_ccp[0];
+        s->energy[0] += e;
+        s->energy[4] += e;
+        a.serVin[a.k] = U[0];
+        a.serI1[a.k] = s->I_ccp[0];
+    } else if (c0.kind == PIC_LMATCH) {
+        a.serVin[a.k] = (Y[0][0] - Y[0][1]) / c0.C_m1;
+        a.serI1[a.k] = (Y[0][0] - q1) / a.dt;
+    } else {
+        a.serVin[a.k] = source_v(c0, t1);
+        a.serI1[a.k] = s->I_ccp[0];
     }
     s->t = t1;
-    a.serU[a.k] = s->U_E;
-    a.serI[a.k] = s->I_ccp;
+    for (int e = 0; e < a.n_el; ++e) {
+        a.serU[e * a.spp + a.k] = s->U_E[e];
+        a.serI[e * a.spp + a.k] = s->I_ccp[e];
+    }
+}
+
+static CircEl circ_el(const pic_circuit& c) {
+    CircEl e;
+    e.kind = c.kind; e.substeps = c.substeps;
+    e.freq = c.freq; e.U_amp = c.U_amp; e.U_dc = c.U_dc; e.R_s = c.R_s; e.C_m1 = c.C_m1; e.C_m2 = c.C_m2;
+    e.L_m = c.L_m; e.R_m = c.R_m; e.C_stray = c.C_stray; e.L_stray = c.L_stray; e.R_stray = c.R_stray;
+    e.C_b = c.C_b; e.R_b = c.R_b; e.L_b = c.L_b;
+    return e;
 }
 
 void launch_circuit(pic_handle* h) {
     CircArgs a;
-    const pic_circuit& c = h->cfg.circ;
     a.sc = h->sc; a.ctr = h->ctr; a.part = h->part; a.serU = h->serU; a.serI = h->serI;
     a.serVin = h->serVin; a.serI1 = h->serI1;
-    a.k = (int)(h->step % h->cfg.run.steps_per_period);
-    a.kind = c.kind; a.substeps = c.substeps;
+    a.spp = h->cfg.run.steps_per_period;
+    a.k = (int)(h->step % a.spp);
     a.dt = h->dt; a.qunit = h->qunit;
-    a.freq = c.freq; a.U_amp = c.U_amp; a.U_dc = c.U_dc; a.R_s = c.R_s; a.C_m1 = c.C_m1; a.C_m2 = c.C_m2;
-    a.L_m = c.L_m; a.R_m = c.R_m; a.C_stray = c.C_stray; a.L_stray = c.L_stray; a.R_stray = c.R_stray;
-    a.C_b = c.C_b; a.R_b = c.R_b; a.L_b = c.L_b;
+    a.n_el = h->n_el;
+    for (int e = 0; e < h->n_el; ++e) a.ce[e] = circ_el(e == 0 ? h->cfg.circ : h->cfg.circ_el[e - 1]);
     hipLaunchKernelGGL(k_circuit, dim3(1), dim3(256), 0, h->stream, a);
 }
 
 // ---------------------------------------------------------- FP64 residual
-__device__ __forceinline__ double dir_val(int8_t k, double U) { return k == 1 ? U : 0.0; }
+// Dirichlet value of a conductor node: U[e - 1] on driven electrode e, 0 on ground
+__device__ __forceinline__ double dir_val(int8_t k, const double* U) { return k >= 1 ? U[k - 1] : 0.0; }
 
 // r = Q - K phi on unknown nodes, Dirichlet neighbours at their conductor
 // value; partial sums of r.r and of b.b (b = Q + Dirichlet lift)
@@ -273,7 +374,8 @@ __global__ __launch_bounds__(256) void k_resid64(const double* ar, const double*
                                                  double* part, int nr, int nz) {
     __shared__ double sh[4];
     const int w = nr + 1, nn = w * (nz + 1);
-    const double U = *Up;
+    double U[kMaxEl];
+    for (int e = 0; e < kMaxEl; ++e) U[e] = Up[e];
     double rr = 0.0, bb = 0.0;
     for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += gridDim.x * blockDim.x) {
         const int8_t k0 = nk[n];
@@ -1139,9 +1241,8 @@ void launch_extrapolate(pic_handle* h) {
 }
 
 __global__ __launch_bounds__(256) void k_set_dirichlet(double* phi, const int8_t* nk, const double* Up, int nn) {
-    const double U = *Up;
     for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += gridDim.x * blockDim.x)
-        if (nk[n] >= 0) phi[n] = nk[n] == 1 ? U : 0.0;
+        if (nk[n] >= 0) phi[n] = nk[n] >= 1 ? Up[nk[n] - 1] : 0.0;
 }
 
 __global__ void k_set_target(DevScalars* s, double v) { s->target = v; }
@@ -1211,21 +1312,22 @@ int field_solve(pic_handle* h, double* phi, const double* Q, const double* Up, d
 }
 
 // ---------------------------------------------------- Laplace and C_eq
-__global__ __launch_bounds__(256) void k_ceq_part(const double* ar, const double* az, const double* f, double* part,
-                                                  int nr, int nz) {
+// partial sums of the energy bilinear form sum over edges a (d f)(d g)
+__global__ __launch_bounds__(256) void k_ceq_part(const double* ar, const double* az, const double* f,
+                                                  const double* g, double* part, int nr, int nz) {
     __shared__ double sh[4];
     const int w = nr + 1, nn = w * (nz + 1);
     double acc = 0.0;
     for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += gridDim.x * blockDim.x) {
         const int i = n % w, j = n / w;
-        if (i < nr) { double d = f[n] - f[n + 1]; acc += ar[n] * d * d; }
-        if (j < nz) { double d = f[n] - f[n + w]; acc += az[n] * d * d; }
+        if (i < nr) { double d = f[n] - f[n + 1], d2 = g[n] - g[n + 1]; acc += ar[n] * d * d2; }
+        if (j < nz) { double d = f[n] - f[n + w], d2 = g[n] - g[n + w]; acc += az[n] * d * d2; }
     }
     double t = block_sum(acc, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
-__global__ __launch_bounds__(256) void k_ceq_final(const double* part, DevScalars* s) {
+__global__ __launch_bounds__(256) void k_ceq_final(const double* part, DevScalars* s, int e, int f) {
     __shared__ double a[kRedBlocks];
     for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) a[i] = part[i];
     __syncthreads();
@@ -1233,21 +1335,32 @@ __global__ __launch_bounds__(256) void k_ceq_final(const double* part, DevScalar
         for (int i = threadIdx.x; i < o; i += blockDim.x) a[i] += a[i + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0) s->C_eq = a[0];
+    if (threadIdx.x == 0) {
+        s->Cm[e][f] = a[0];
+        s->Cm[f][e] = a[0];
+    }
 }
 
 // Once per RF period (Sec. 2, text after Eq. 4): rebuild the multigrid
-// hierarchy for the current operator, solve the Laplace problem with the
-// driven electrode at 1 V, and C_eq = sum over edges of a (d phi_L)^2.
+// hierarchy for the current operator, solve the Laplace problem of each
+// driven electrode (it at 1 V, every other conductor at 0), and the
+// capacitance matrix C_ef = sum over edges of a (d phi_Le)(d phi_Lf), the
+// field energy's bilinear form (C_11 = C_eq of Eqs. 6-7).
 int refresh_laplace(pic_handle* h) {
     mg_rebuild(h);
-    int32_t it;
-    double rel;
-    int rc = field_solve(h, h->phiL, nullptr, &h->sc->one, 1e-12, PIC_SOLVE_MGPCG_FP64, &it, &rel);
-    if (rc != PIC_OK && rc != PIC_E_SOLVER) return rc;
-    hipLaunchKernelGGL(k_ceq_part, dim3(kRedBlocks), dim3(256), 0, h->stream, (const double*)h->ar,
-                       (const double*)h->az, (const double*)h->phiL, h->part, h->nr, h->nz);
-    hipLaunchKernelGGL(k_ceq_final, dim3(1), dim3(256), 0, h->stream, (const double*)h->part, h->sc);
+    for (int e = 0; e < h->n_el; ++e) {
+        int32_t it;
+        double rel;
+        int rc = field_solve(h, h->phiL[e], nullptr, h->sc->unit[e], 1e-12, PIC_SOLVE_MGPCG_FP64, &it, &rel);
+        if (rc != PIC_OK && rc != PIC_E_SOLVER) return rc;
+    }
+    for (int e = 0; e < h->n_el; ++e)
+        for (int f = e; f < h->n_el; ++f) {
+            hipLaunchKernelGGL(k_ceq_part, dim3(kRedBlocks), dim3(256), 0, h->stream, (const double*)h->ar,
+                               (const double*)h->az, (const double*)h->phiL[e], (const double*)h->phiL[f], h->part,
+                               h->nr, h->nz);
+            hipLaunchKernelGGL(k_ceq_final, dim3(1), dim3(256), 0, h->stream, (const double*)h->part, h->sc, e, f);
+        }
     return PIC_OK;
 }
 
@@ -1290,7 +1403,14 @@ __global__ __launch_bounds__(256) void k_period_roll(RollArgs a) {
             a.le[n] = a.pe[n]; a.li[n] = a.pi[n];
             a.pe[n] = 0ull; a.pi[n] = 0ull;
         }
-        if (n < a.spp) { a.lU[n] = a.sU[n]; a.lI[n] = a.sI[n]; a.lV[n] = a.sV[n]; a.l1[n] = a.s1[n]; }
+        if (n < a.spp) {
+            for (int e = 0; e < kMaxEl; ++e) {
+                a.lU[e * a.spp + n] = a.sU[e * a.spp + n];
+                a.lI[e * a.spp + n] = a.sI[e * a.spp + n];
+            }
+            a.lV[n] = a.sV[n];
+            a.l1[n] = a.s1[n];
+        }
     }
     if (blockIdx.x == 0 && threadIdx.x < 5) {
         a.sc->last_energy[threadIdx.x] = a.sc->energy[threadIdx.x];

@@ -49,7 +49,7 @@ __device__ __forceinline__ bool absorb(const Geo& g, const Loc& L, float w, int 
                                        int wj0, const uint8_t* s_ck) {
     if (!L.inside) {
         int bc = g.edge_bc[L.edge];
-        int slot = bc >= 0 ? (bc < 2 ? bc : 0) : 2;
+        int slot = bc >= 0 ? slot_of(bc) : 2;
         atomicAdd(&s_abs[slot], (unsigned long long)total_share((double)w));
         return true;
     }
@@ -71,7 +71,7 @@ __device__ __forceinline__ bool absorb(const Geo& g, const Loc& L, float w, int 
     if (ck == 0) return false;
     if (ck >= 2) {
         int id = ck - 2;
-        atomicAdd(&s_abs[id < 2 ? id : 0], (unsigned long long)total_share((double)w));
+        atomicAdd(&s_abs[slot_of(id)], (unsigned long long)total_share((double)w));
         return true;
     }
     int64_t c[4];
@@ -82,7 +82,7 @@ __device__ __forceinline__ bool absorb(const Geo& g, const Loc& L, float w, int 
     for (int k = 0; k < 4; ++k) {
         int nk = g.node_kind[nodes[k]];
         if (nk >= 0) {
-            atomicAdd(&s_abs[nk < 2 ? nk : 0], (unsigned long long)c[k]);
+            atomicAdd(&s_abs[slot_of(nk)], (unsigned long long)c[k]);
         } else {
             atomicAdd(&wallq[nodes[k]], (unsigned long long)(sign * c[k]));
             atomicAdd(&s_abs[3], (unsigned long long)c[k]);
@@ -187,7 +187,7 @@ __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4)))
     __shared__ uint8_t s_ck[(kWin - 1) * (kWin - 1)];
     __shared__ unsigned int qslot[kPushWaves][kQW];
     __shared__ int s_org[2];
-    __shared__ unsigned long long s_abs[4];
+    __shared__ unsigned long long s_abs[kSlots];
     __shared__ unsigned int s_coll[4];
     __shared__ unsigned int s_fallback;
 
@@ -205,7 +205,8 @@ __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4)))
     unsigned int fallback = 0;
 
     for (int k = tid; k < kWin * kWin; k += kPushBlock) win[k] = 0ull;
-    if (tid < 4) { s_abs[tid] = 0ull; s_coll[tid] = 0u; }
+    if (tid < kSlots) s_abs[tid] = 0ull;
+    if (tid < 4) s_coll[tid] = 0u;
     if (tid == 0) s_fallback = 0u;
 
     // the window stays in LDS while consecutive chunks share its origin and
@@ -401,10 +402,8 @@ __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4)))
     for (int o = 32; o > 0; o >>= 1) fallback += __shfl_down(fallback, o);
     if (lane == 0 && fallback) atomicAdd(&s_fallback, fallback);
     __syncthreads();
-    if (tid < 4) {
-        if (s_abs[tid]) atomicAdd(&a.ctr->absorbed[a.sp][tid], s_abs[tid]);
-        if (s_coll[tid]) atomicAdd(&a.ctr->coll[a.sp][tid], (unsigned long long)s_coll[tid]);
-    }
+    if (tid < kSlots && s_abs[tid]) atomicAdd(&a.ctr->absorbed[a.sp][tid], s_abs[tid]);
+    if (tid < 4 && s_coll[tid]) atomicAdd(&a.ctr->coll[a.sp][tid], (unsigned long long)s_coll[tid]);
     if (tid == 0 && s_fallback) atomicAdd(&a.ctr->fallback, (unsigned long long)s_fallback);
 }
 
@@ -568,7 +567,7 @@ __device__ __forceinline__ void place_newborn(const Geo& g, float* const* f, lon
     Loc L = locate(s.r, s.z, g);
     bool removed;
     {
-        unsigned long long loc[4] = {0ull, 0ull, 0ull, 0ull};
+        unsigned long long loc[kSlots] = {0ull, 0ull, 0ull, 0ull, 0ull, 0ull, 0ull, 0ull};
         // absorption accounting straight to the global counters (rare)
         if (L.inside && g.cell_kind[L.j * g.nr + L.i] == 0) {
             removed = false;
@@ -576,11 +575,11 @@ __device__ __forceinline__ void place_newborn(const Geo& g, float* const* f, lon
             removed = true;
             if (!L.inside) {
                 int bc = g.edge_bc[L.edge];
-                loc[bc >= 0 ? (bc < 2 ? bc : 0) : 2] += (unsigned long long)total_share((double)s.w);
+                loc[bc >= 0 ? slot_of(bc) : 2] += (unsigned long long)total_share((double)s.w);
             } else {
                 int ck = g.cell_kind[L.j * g.nr + L.i];
                 if (ck >= 2) {
-                    loc[(ck - 2) < 2 ? ck - 2 : 0] += (unsigned long long)total_share((double)s.w);
+                    loc[slot_of(ck - 2)] += (unsigned long long)total_share((double)s.w);
                 } else {
                     int64_t c[4];
                     node_shares(L, (double)s.w, g.invd[L.i], c);
@@ -588,7 +587,7 @@ __device__ __forceinline__ void place_newborn(const Geo& g, float* const* f, lon
                     int nodes[4] = {n00, n00 + 1, n00 + g.w, n00 + g.w + 1};
                     for (int k = 0; k < 4; ++k) {
                         int nk = g.node_kind[nodes[k]];
-                        if (nk >= 0) loc[nk < 2 ? nk : 0] += (unsigned long long)c[k];
+                        if (nk >= 0) loc[slot_of(nk)] += (unsigned long long)c[k];
                         else {
                             atomicAdd(&wallq[nodes[k]], (unsigned long long)((sp == 0 ? -1 : 1) * c[k]));
                             loc[3] += (unsigned long long)c[k];
@@ -596,7 +595,7 @@ __device__ __forceinline__ void place_newborn(const Geo& g, float* const* f, lon
                     }
                 }
             }
-            for (int k = 0; k < 4; ++k)
+            for (int k = 0; k < kSlots; ++k)
                 if (loc[k]) atomicAdd(&ctr->absorbed[sp][k], loc[k]);
         }
     }

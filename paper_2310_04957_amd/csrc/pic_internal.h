@@ -31,12 +31,17 @@ __host__ __device__ constexpr long long stage_rows(long long n) {
 constexpr int kMaxLevels = 16;
 constexpr int kMaxCoarse = 320;       // active nodes of the coarsest multigrid level
 constexpr int kRedBlocks = 4096;      // partial sums of a grid reduction
+constexpr int kMaxEl = PIC_MAX_ELECTRODES;   // driven electrodes
+// absorption counter slot of conductor id: 0 ground, 1 electrode 1, 2 lost
+// (Neumann edge), 3 dielectric, 4 .. 6 electrodes 2 .. 4
+__host__ __device__ constexpr int slot_of(int id) { return id <= 1 ? id : 2 + id; }
+constexpr int kSlots = 8;
 
 // counters that kernels update; lives in device memory
 struct DevCounters {
     long long n_slots[2];
     long long born;
-    unsigned long long absorbed[2][4];
+    unsigned long long absorbed[2][kSlots];
     unsigned long long coll[2][4];
     unsigned int viol;
     int err;
@@ -52,9 +57,15 @@ struct DevCounters {
 
 // FP64 scalars of the field solve and the circuit; device memory
 struct DevScalars {
-    double U_E, Q_E, Q_P, C_eq, t, I_ccp, circ[5];
-    double one;              // constant 1.0: Dirichlet value of the Laplace problem
-    double powered_prev;     // integer powered-electrode charge at the last circuit step
+    // driven electrodes e (index e - 1): voltage, charge, induced charge,
+    // circuit current and state, capacitance matrix (Cm[0][0] = C_eq of
+    // electrode 1), integer absorbed charge at the last circuit step
+    double U_E[kMaxEl], Q_E[kMaxEl], Q_P[kMaxEl], I_ccp[kMaxEl], circ[kMaxEl][5];
+    double Cm[kMaxEl][kMaxEl];
+    double el_prev[kMaxEl];
+    double unit[kMaxEl][kMaxEl];   // identity rows: Dirichlet values of the Laplace problems
+    double Uset[kMaxEl];           // Dirichlet values of pic_solve_once
+    double t;
     double bb, rr, rz, rz_new, pq, alpha, beta, target, scale, relres, rr0;
     double rr_net, c_net;    // learned preconditioner: |res|^2 at the network, its Galerkin weight
     double energy[5];        // circuit element energies of the running RF period
@@ -114,7 +125,9 @@ struct pic_handle {
     unsigned long long* dep[2][2];  // [buffer][species]
     int dep_cur;
     unsigned long long *wallq, *psum[2], *plast[2];
-    double *chi, *Q, *ar, *az, *phi, *phiL, *zeroQ;
+    double *chi, *Q, *ar, *az, *phi, *zeroQ;
+    int n_el;               // driven electrodes
+    double* phiL[pic::kMaxEl];  // Laplace solution of each driven electrode
     double* phi_prev;       // the previous step's solution (initial-guess extrapolation)
     bool have_prev;
     float *ar32, *az32;
@@ -130,7 +143,7 @@ struct pic_handle {
     double* cinv64;
     float* cinv32;
     // time series
-    double *serU, *serI, *lastU, *lastI;
+    double *serU, *serI, *lastU, *lastI;          // kMaxEl x steps_per_period each
     double *serVin, *serI1, *lastVin, *lastI1;   // source-side voltage and current per step
     // device counters / scalars and their pinned host mirrors
     pic::DevCounters* ctr;

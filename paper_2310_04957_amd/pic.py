@@ -17,7 +17,9 @@ MAX_REGIONS = 32
 FIELDS = ("r", "z", "vr", "vt", "vz", "ar", "at", "az", "w")
 SOLVE_MGPCG_FP64, SOLVE_IR_MG, SOLVE_IR_UNET, SOLVE_IR_CG = 0, 1, 2, 3
 WEIGHTS_EQUAL, WEIGHTS_CELL = 0, 1
-GRIDS = dict(DEP_E=0, DEP_I=1, PHI=2, ER=3, EZ=4, CHI=5, WALLQ=6, PHI_L=10, Q=11, AR=12, AZ=13)
+GRIDS = dict(DEP_E=0, DEP_I=1, PHI=2, ER=3, EZ=4, CHI=5, WALLQ=6, PHI_L=10, Q=11, AR=12, AZ=13,
+             PHI_L2=14, PHI_L3=15, PHI_L4=16)
+MAX_EL = 4
 ERRORS = {0: "ok", -1: "PIC_E_CONFIG", -2: "PIC_E_CAPACITY", -3: "PIC_E_SOLVER", -4: "PIC_E_HIP",
           -5: "PIC_E_NONFINITE", -6: "PIC_E_STATE", -7: "PIC_E_ARG", -8: "PIC_E_NODEVICE"}
 
@@ -63,7 +65,7 @@ class Solver(C.Structure):
 
 class Config(C.Structure):
     _fields_ = [("abi_version", C.c_int32), ("geom", Geometry), ("circ", Circuit), ("gas", Gas), ("run", Run),
-                ("solver", Solver)]
+                ("solver", Solver), ("n_el", C.c_int32), ("circ_el", Circuit * (MAX_EL - 1))]
 
 
 class Diag(C.Structure):
@@ -81,7 +83,12 @@ class Diag(C.Structure):
         ("unet_pairs", C.c_int64), ("unet_fallbacks", C.c_int64), ("unet_applications", C.c_int64)] + [
         (f, C.c_double) for f in ("Z_ccp_re", "Z_ccp_im", "Z_load_re", "Z_load_im", "gamma_abs", "P_source",
                                   "P_Rs", "P_imn", "P_stray", "P_ccp", "P_forward", "P_ref")] + [
-        ("split_added", C.c_int64 * 2)]
+        ("split_added", C.c_int64 * 2),
+        ("n_el", C.c_int32), ("U_el", C.c_double * MAX_EL), ("Q_el", C.c_double * MAX_EL),
+        ("QP_el", C.c_double * MAX_EL), ("I_el", C.c_double * MAX_EL), ("C_el", C.c_double * (MAX_EL * MAX_EL)),
+        ("hU_re", (C.c_double * 6) * MAX_EL), ("hU_im", (C.c_double * 6) * MAX_EL),
+        ("hI_re", (C.c_double * 6) * MAX_EL), ("hI_im", (C.c_double * 6) * MAX_EL),
+        ("absorbed_el", (C.c_int64 * MAX_EL) * 2)]
 
 
 class DiagBuffers(C.Structure):
@@ -114,6 +121,7 @@ def lib():
         L.pic_redeposit.argtypes = [P]
         L.pic_sort_now.argtypes = [P, C.c_int32, P]
         L.pic_split_now.argtypes = [P, C.c_int32, C.POINTER(C.c_int64)]
+        L.pic_solve_once_el.argtypes = [P, P, P, P, C.c_double, P, C.POINTER(C.c_int32), C.POINTER(C.c_double)]
         L.pic_solve_once.argtypes = [P, P, P, C.c_double, C.c_double, P, C.POINTER(C.c_int32),
                                      C.POINTER(C.c_double)]
         L.pic_set_state.argtypes = [P, P]
@@ -170,6 +178,15 @@ def make_config(w, load=True, timing=False, method=None, inner_tol=1e-4, unet_ba
     cfg.solver.inner_tol = inner_tol
     cfg.solver.unet_batch = unet_batch
     cfg.solver.unet_pairs = unet_pairs
+    more = w.get("circuits_more", [])
+    if len(more) > MAX_EL - 1:
+        raise ValueError("too many driven electrodes")
+    cfg.n_el = 1 + len(more)
+    for e, ce in enumerate(more):
+        cfg.circ_el[e].kind, cfg.circ_el[e].substeps = ce["kind"], ce["substeps"]
+        for f in ("freq", "U_amp", "U_dc", "R_s", "C_m1", "C_m2", "L_m", "R_m", "C_stray", "L_stray", "R_stray",
+                  "C_b", "R_b", "L_b"):
+            setattr(cfg.circ_el[e], f, ce[f])
     return cfg
 
 
@@ -282,6 +299,24 @@ class Pic:
         rel = C.c_double()
         rc = lib().pic_solve_once(self.h, _ptr(Q), _ptr(chi), U_E, tol, _ptr(phi), C.byref(it), C.byref(rel))
         return phi, it.value, rel.value, rc
+
+    def solve_once_el(self, Q, chi, U, tol, phi0=None):
+        """One solve with driven electrode e at U[e - 1]."""
+        Q = np.ascontiguousarray(Q, dtype=np.float64)
+        chi = np.ascontiguousarray(chi, dtype=np.float64)
+        Uv = np.zeros(MAX_EL)
+        Uv[:len(U)] = U
+        phi = np.zeros(self.nn) if phi0 is None else np.array(phi0, dtype=np.float64)
+        it = C.c_int32()
+        rel = C.c_double()
+        rc = lib().pic_solve_once_el(self.h, _ptr(Q), _ptr(chi), _ptr(Uv), tol, _ptr(phi), C.byref(it),
+                                     C.byref(rel))
+        return phi, it.value, rel.value, rc
+
+    def capacitance(self):
+        """n_el x n_el capacitance matrix of the driven electrodes (F)."""
+        d = self.diag()
+        return np.array(d.C_el[:]).reshape(MAX_EL, MAX_EL)[:d.n_el, :d.n_el]
 
     def set_state(self, t, Q_E, U_E, circ, C_eq):
         st = np.array([t, Q_E, U_E] + list(circ) + [C_eq], dtype=np.float64)

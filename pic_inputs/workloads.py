@@ -45,9 +45,11 @@ def disk_electrode_geometry(nr=32, nz=24, R=0.05, Z=0.0254):
                 edge_bc=[GROUND, POWERED, GROUND])
 
 
-def gec_geometry(refine=1):
+def gec_geometry(refine=1, driven_lower=False):
     """GEC-cell-shaped domain on a 128x256 base grid (refine=1), 512x1024
-    (refine=4) or 1024x2048 (refine=8).
+    (refine=4) or 1024x2048 (refine=8).  With driven_lower the lower
+    electrode is a second driven electrode (conductor id 2), lifted one base
+    cell off the grounded bottom wall.
 
     Domain r in [0, 10.16] cm, z in [0, 10.16] cm.  All features lie on
     base-grid edges (base cell 5.08/64 cm in r, 2.54/64 cm in z), so every
@@ -65,7 +67,8 @@ def gec_geometry(refine=1):
     regions = [
         (5.08 * cm, 5.715 * cm, 6.35 * cm, big, DIEL, -1, 4.0),       # ring
         (0.0, 5.715 * cm, 9.525 * cm, big, DIEL, -1, 4.0),            # cap
-        (0.0, 5.08 * cm, 0.0, 3.81 * cm, COND, GROUND, 1.0),          # lower electrode
+        (0.0, 5.08 * cm, 2.54 / 64 * cm if driven_lower else 0.0, 3.81 * cm, COND,
+         2 if driven_lower else GROUND, 1.0),                         # lower electrode
         (0.0, 5.08 * cm, 6.35 * cm, 9.525 * cm, COND, POWERED, 1.0),  # powered electrode
         (5.715 * cm, 6.35 * cm, 6.35 * cm, big, COND, GROUND, 1.0),   # shield
     ]
