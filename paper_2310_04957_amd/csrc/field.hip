@@ -1285,8 +1285,11 @@ int field_solve(pic_handle* h, double* phi, const double* Q, const double* Up, d
             hipLaunchKernelGGL(k_add_phi<double>, grid_for(nn), dim3(256), 0, st, phi, (const double*)h->x64,
                                (const int8_t*)h->node_kind, (const DevScalars*)h->sc, nn, 0);
         } else {
+            // the inner solve reduces its residual by inner_tol, or by no more
+            // than the outer tolerance still needs (with a factor 2 margin)
             const double it = h->cfg.solver.inner_tol > 0 ? h->cfg.solver.inner_tol : 1e-4;
-            hipLaunchKernelGGL(k_set_target, dim3(1), dim3(1), 0, st, h->sc, it * it);
+            const double want = std::max(it, 0.5 * tol / rel);
+            hipLaunchKernelGGL(k_set_target, dim3(1), dim3(1), 0, st, h->sc, want * want);
             hipLaunchKernelGGL(k_scale_to<float>, grid_for(nn), dim3(256), 0, st, (const double*)h->r64, h->r32,
                                h->x32, (const DevScalars*)h->sc, nn);
             if (method == PIC_SOLVE_IR_UNET) {
