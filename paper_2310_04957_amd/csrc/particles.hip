@@ -169,8 +169,7 @@ __device__ __forceinline__ void store_slot(float* const* f, uint32_t p, const P9
 // One time step for every particle of one species.  A block of eight
 // wavefronts owns whole chunks of 8192 consecutive slots and each of its
 // wavefronts a contiguous slice of 1024 of them, processed 64 at a time
-// with the next 64 already in flight; the chunks of one XCD are contiguous
-// so neighbouring (cell-sorted) chunks share that XCD's L2.  Colliding
+// with the next 64 already in flight.  Colliding
 // particles are compacted by wavefront ballots into a per-wavefront LDS
 // queue and processed 64 at a time by full wavefronts; births are staged
 // per slice in slot order.  A window (the tile of the chunk's first
@@ -195,11 +194,9 @@ __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4)))
     const Geo& g = a.g;
     const long long n = a.ctr->n_slots[a.sp];
     const long long nch = (n + kPushChunk - 1) / kPushChunk;
-    const int nx = 8;  // XCDs: consecutive block ids go round-robin over them
-    const int xcd = blockIdx.x % nx, per = gridDim.x / nx, lb = blockIdx.x / nx;
-    // this XCD's contiguous chunk range, taken by its blocks in turn, so the
-    // chunks in flight on one XCD stay close together (shared L2)
-    const long long c_begin = nch * xcd / nx, c_end = nch * (xcd + 1) / nx;
+    // chunks go round-robin over all blocks, so the chunks in flight form one
+    // narrow front sweeping the slot arrays (measured faster than one range
+    // per XCD, and much faster than one contiguous run per block)
     float* const* f = a.f;
     constexpr bool moved = kMoved;
     unsigned int fallback = 0;
@@ -226,7 +223,7 @@ __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4)))
         __syncthreads();
     };
 
-    for (long long chunk = c_begin + lb; chunk < c_end; chunk += per) {
+    for (long long chunk = blockIdx.x; chunk < nch; chunk += gridDim.x) {
         const long long base = chunk * kPushChunk;
         // LDS window origin: tile of the chunk's first live particle, plus halo
         if (wave == 0) {
