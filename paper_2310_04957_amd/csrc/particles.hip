@@ -194,9 +194,8 @@ __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4)))
     const Geo& g = a.g;
     const long long n = a.ctr->n_slots[a.sp];
     const long long nch = (n + kPushChunk - 1) / kPushChunk;
-    // chunks go round-robin over all blocks, so the chunks in flight form one
-    // narrow front sweeping the slot arrays (measured faster than one range
-    // per XCD, and much faster than one contiguous run per block)
+    // a block takes chunks blockIdx.x, + gridDim.x, ... (one chunk with the
+    // launch below)
     float* const* f = a.f;
     constexpr bool moved = kMoved;
     unsigned int fallback = 0;
@@ -404,10 +403,12 @@ __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4)))
     if (tid == 0 && s_fallback) atomicAdd(&a.ctr->fallback, (unsigned long long)s_fallback);
 }
 
-static int grid_blocks() {
-    // persistent-style grid: 8 XCDs x 32 CUs x 2 blocks of 8 wavefronts, a
-    // multiple of 8
-    return 512;
+// one block per chunk of the species' capacity (blocks past the last slot
+// exit at once): the hardware dispatches them in order, which keeps the
+// chunks in flight close together and balances uneven chunks (colliders,
+// window misses) better than a persistent grid
+static unsigned grid_blocks(const pic_handle* h, int sp) {
+    return (unsigned)std::max<int64_t>(1, (h->cap[sp] + kPushChunk - 1) / kPushChunk);
 }
 
 static Geo make_geo(pic_handle* h) {
@@ -466,11 +467,11 @@ void launch_particles(pic_handle* h, int sp) {
     a.key1 = (uint32_t)(h->cfg.run.seed >> 32);
     a.step = (uint32_t)(h->step + 1);
     if (sp == 0) {
-        if (moved) hipLaunchKernelGGL((k_particles<24, true>), dim3(grid_blocks()), dim3(kPushBlock), 0, h->stream, a);
-        else hipLaunchKernelGGL((k_particles<24, false>), dim3(grid_blocks()), dim3(kPushBlock), 0, h->stream, a);
+        if (moved) hipLaunchKernelGGL((k_particles<24, true>), dim3(grid_blocks(h, sp)), dim3(kPushBlock), 0, h->stream, a);
+        else hipLaunchKernelGGL((k_particles<24, false>), dim3(grid_blocks(h, sp)), dim3(kPushBlock), 0, h->stream, a);
     } else {
-        if (moved) hipLaunchKernelGGL((k_particles<16, true>), dim3(grid_blocks()), dim3(kPushBlock), 0, h->stream, a);
-        else hipLaunchKernelGGL((k_particles<16, false>), dim3(grid_blocks()), dim3(kPushBlock), 0, h->stream, a);
+        if (moved) hipLaunchKernelGGL((k_particles<16, true>), dim3(grid_blocks(h, sp)), dim3(kPushBlock), 0, h->stream, a);
+        else hipLaunchKernelGGL((k_particles<16, false>), dim3(grid_blocks(h, sp)), dim3(kPushBlock), 0, h->stream, a);
     }
     if (moved) {
         h->cur[sp] = 1 - h->cur[sp];
