@@ -188,34 +188,36 @@ __device__ void circ_p(const CircEl& a, double U_E, double t, const double* y, d
 
 // Electrode voltages at time t for circuit states Y: Q = C U + Q_P, so an
 // ideal source fixes its electrode's voltage and the other electrodes solve
-// C_NN U_N = Q_N - Q_P,N - C_NK U_K (Gaussian elimination on the symmetric
-// positive definite block; one electrode: U = (Q - Q_P) / C_eq).
-__device__ void volts(const CircArgs& a, const double (*C)[kMaxEl], const double* QP, double t,
-                      const double (*Y)[6], double* U) {
-    int N[kMaxEl], nN = 0;
-    for (int e = 0; e < a.n_el; ++e) {
-        if (a.ce[e].kind == PIC_IDEAL_SOURCE) U[e] = source_v(a.ce[e], t);
-        else N[nN++] = e;
+// C_NN U_N = Q_N - Q_P,N - C_NK U_K.  Gaussian elimination over all NE
+// electrodes with an ideal source's row replaced by U_e = U_s(t), which is
+// the same system (one electrode: U = (Q - Q_P) / C_eq); NE is a
+// compile-time count so every array stays in registers.
+template <int NE>
+__device__ __forceinline__ void volts(const CircArgs& a, const double (*C)[kMaxEl], const double* QP, double t,
+                                      const double (*Y)[6], double* U) {
+    double A[NE][NE], b[NE];
+#pragma unroll
+    for (int r = 0; r < NE; ++r) {
+        const bool ideal = a.ce[r].kind == PIC_IDEAL_SOURCE;
+        b[r] = ideal ? source_v(a.ce[r], t) : Y[r][5] - QP[r];
+#pragma unroll
+        for (int q = 0; q < NE; ++q) A[r][q] = ideal ? (r == q ? 1.0 : 0.0) : C[r][q];
     }
-    if (nN == 0) return;
-    double A[kMaxEl][kMaxEl], b[kMaxEl];
-    for (int r = 0; r < nN; ++r) {
-        const int e = N[r];
-        b[r] = Y[e][5] - QP[e];
-        for (int f = 0; f < a.n_el; ++f)
-            if (a.ce[f].kind == PIC_IDEAL_SOURCE) b[r] -= C[e][f] * U[f];
-        for (int q = 0; q < nN; ++q) A[r][q] = C[e][N[q]];
-    }
-    for (int p = 0; p < nN; ++p)
-        for (int r = p + 1; r < nN; ++r) {
+#pragma unroll
+    for (int p = 0; p < NE; ++p)
+#pragma unroll
+        for (int r = p + 1; r < NE; ++r) {
             const double m = A[r][p] / A[p][p];
-            for (int q = p; q < nN; ++q) A[r][q] -= m * A[p][q];
+#pragma unroll
+            for (int q = p; q < NE; ++q) A[r][q] -= m * A[p][q];
             b[r] -= m * b[p];
         }
-    for (int r = nN - 1; r >= 0; --r) {
+#pragma unroll
+    for (int r = NE - 1; r >= 0; --r) {
         double x = b[r];
-        for (int q = r + 1; q < nN; ++q) x -= A[r][q] * U[N[q]];
-        U[N[r]] = x / A[r][r];
+#pragma unroll
+        for (int q = r + 1; q < NE; ++q) x -= A[r][q] * U[q];
+        U[r] = x / A[r][r];
     }
 }
 
@@ -224,10 +226,12 @@ __device__ void volts(const CircArgs& a, const double (*C)[kMaxEl], const double
 // counters, then RK4 of all circuits together (substeps: the largest of the
 // circuits'), electrode 1's element energies by the trapezoid rule, and the
 // voltage series.  One block; thread 0 integrates.
+template <int NE>
 __global__ __launch_bounds__(256) void k_circuit(CircArgs a) {
     __shared__ double sh[kRedBlocks];
     __shared__ double sQP[kMaxEl];
-    for (int e = 0; e < a.n_el; ++e) {
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
         for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) sh[i] = a.part[e * kRedBlocks + i];
         __syncthreads();
         for (int o = kRedBlocks / 2; o > 0; o >>= 1) {
@@ -239,8 +243,9 @@ __global__ __launch_bounds__(256) void k_circuit(CircArgs a) {
     }
     if (threadIdx.x != 0) return;
     DevScalars* s = a.sc;
-    double QP[kMaxEl], Iconv[kMaxEl];
-    for (int e = 0; e < a.n_el; ++e) {
+    double QP[NE], Iconv[NE];
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
         const int sl = slot_of(e + 1);
         const long long pc = (long long)a.ctr->absorbed[1][sl] - (long long)a.ctr->absorbed[0][sl];
         Iconv[e] = ((double)pc - s->el_prev[e]) * a.qunit / a.dt;
@@ -250,14 +255,14 @@ __global__ __launch_bounds__(256) void k_circuit(CircArgs a) {
     }
     const double t0 = s->t, t1 = t0 + a.dt;
     const double U0 = s->U_E[0];
-    double Y[kMaxEl][6], U[kMaxEl], q0[kMaxEl];
-    int qi[kMaxEl];
+    double Y[NE][6], U[NE], q0[NE];
     int M = 0;
-    for (int e = 0; e < a.n_el; ++e) {
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+#pragma unroll
         for (int k = 0; k < 5; ++k) Y[e][k] = s->circ[e][k];
         Y[e][5] = s->Q_E[e];
-        qi[e] = (a.ce[e].kind == PIC_LMATCH) ? 3 : 0;
-        q0[e] = Y[e][qi[e]];
+        q0[e] = a.ce[e].kind == PIC_LMATCH ? Y[e][3] : Y[e][0];
         if (a.ce[e].kind != PIC_IDEAL_SOURCE) {
             const int ms = a.ce[e].substeps > 0 ? a.ce[e].substeps : 1;
             if (ms > M) M = ms;
@@ -269,32 +274,46 @@ __global__ __launch_bounds__(256) void k_circuit(CircArgs a) {
         const bool pe = a.ce[0].kind != PIC_IDEAL_SOURCE;
         double pa[5], pb[5];
         if (pe) {
-            volts(a, s->Cm, QP, t0, Y, U);
+            volts<NE>(a, s->Cm, QP, t0, Y, U);
             circ_p(a.ce[0], U[0], t0, Y[0], pa);
         }
         for (int m = 0; m < M; ++m) {
             const double t = t0 + m * hh;
-            double k1[kMaxEl][6], k2[kMaxEl][6], k3[kMaxEl][6], k4[kMaxEl][6], yt[kMaxEl][6];
-            volts(a, s->Cm, QP, t, Y, U);
-            for (int e = 0; e < a.n_el; ++e) if (a.ce[e].kind) circ_f(a.ce[e], U[e], Iconv[e], t, Y[e], k1[e]);
-            for (int e = 0; e < a.n_el; ++e) for (int k = 0; k < 6; ++k) yt[e][k] = Y[e][k] + 0.5 * hh * k1[e][k];
-            volts(a, s->Cm, QP, t + 0.5 * hh, yt, U);
-            for (int e = 0; e < a.n_el; ++e)
-                if (a.ce[e].kind) circ_f(a.ce[e], U[e], Iconv[e], t + 0.5 * hh, yt[e], k2[e]);
-            for (int e = 0; e < a.n_el; ++e) for (int k = 0; k < 6; ++k) yt[e][k] = Y[e][k] + 0.5 * hh * k2[e][k];
-            volts(a, s->Cm, QP, t + 0.5 * hh, yt, U);
-            for (int e = 0; e < a.n_el; ++e)
-                if (a.ce[e].kind) circ_f(a.ce[e], U[e], Iconv[e], t + 0.5 * hh, yt[e], k3[e]);
-            for (int e = 0; e < a.n_el; ++e) for (int k = 0; k < 6; ++k) yt[e][k] = Y[e][k] + hh * k3[e][k];
-            volts(a, s->Cm, QP, t + hh, yt, U);
-            for (int e = 0; e < a.n_el; ++e) if (a.ce[e].kind) circ_f(a.ce[e], U[e], Iconv[e], t + hh, yt[e], k4[e]);
-            for (int e = 0; e < a.n_el; ++e)
-                if (a.ce[e].kind)
+            double k1[NE][6], k2[NE][6], k3[NE][6], k4[NE][6], yt[NE][6];
+            volts<NE>(a, s->Cm, QP, t, Y, U);
+#pragma unroll
+            for (int e = 0; e < NE; ++e) circ_f(a.ce[e], U[e], Iconv[e], t, Y[e], k1[e]);
+#pragma unroll
+            for (int e = 0; e < NE; ++e)
+#pragma unroll
+                for (int k = 0; k < 6; ++k) yt[e][k] = Y[e][k] + 0.5 * hh * k1[e][k];
+            volts<NE>(a, s->Cm, QP, t + 0.5 * hh, yt, U);
+#pragma unroll
+            for (int e = 0; e < NE; ++e) circ_f(a.ce[e], U[e], Iconv[e], t + 0.5 * hh, yt[e], k2[e]);
+#pragma unroll
+            for (int e = 0; e < NE; ++e)
+#pragma unroll
+                for (int k = 0; k < 6; ++k) yt[e][k] = Y[e][k] + 0.5 * hh * k2[e][k];
+            volts<NE>(a, s->Cm, QP, t + 0.5 * hh, yt, U);
+#pragma unroll
+            for (int e = 0; e < NE; ++e) circ_f(a.ce[e], U[e], Iconv[e], t + 0.5 * hh, yt[e], k3[e]);
+#pragma unroll
+            for (int e = 0; e < NE; ++e)
+#pragma unroll
+                for (int k = 0; k < 6; ++k) yt[e][k] = Y[e][k] + hh * k3[e][k];
+            volts<NE>(a, s->Cm, QP, t + hh, yt, U);
+#pragma unroll
+            for (int e = 0; e < NE; ++e) circ_f(a.ce[e], U[e], Iconv[e], t + hh, yt[e], k4[e]);
+#pragma unroll
+            for (int e = 0; e < NE; ++e)
+                if (a.ce[e].kind != PIC_IDEAL_SOURCE)
+#pragma unroll
                     for (int k = 0; k < 6; ++k)
                         Y[e][k] += hh / 6.0 * (k1[e][k] + 2.0 * k2[e][k] + 2.0 * k3[e][k] + k4[e][k]);
             if (pe) {
-                volts(a, s->Cm, QP, t + hh, Y, U);
+                volts<NE>(a, s->Cm, QP, t + hh, Y, U);
                 circ_p(a.ce[0], U[0], t + hh, Y[0], pb);
+#pragma unroll
                 for (int k = 0; k < 5; ++k) {
                     s->energy[k] += 0.5 * hh * (pa[k] + pb[k]);
                     pa[k] = pb[k];
@@ -302,19 +321,22 @@ __global__ __launch_bounds__(256) void k_circuit(CircArgs a) {
             }
         }
     }
-    volts(a, s->Cm, QP, t1, Y, U);
-    for (int e = 0; e < a.n_el; ++e) {
+    volts<NE>(a, s->Cm, QP, t1, Y, U);
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
         if (a.ce[e].kind == PIC_IDEAL_SOURCE) {
             // the charge that holds the source voltage: Q = C U + Q_P
             double q = 0.0;
-            for (int f = 0; f < a.n_el; ++f) q += s->Cm[e][f] * U[f];
+#pragma unroll
+            for (int f = 0; f < NE; ++f) q += s->Cm[e][f] * U[f];
             q += QP[e];
             s->I_ccp[e] = (q - s->Q_E[e]) / a.dt - Iconv[e];
             s->Q_E[e] = q;
         } else {
+#pragma unroll
             for (int k = 0; k < 5; ++k) s->circ[e][k] = Y[e][k];
             s->Q_E[e] = Y[e][5];
-            s->I_ccp[e] = (Y[e][qi[e]] - q0[e]) / a.dt;
+            s->I_ccp[e] = ((a.ce[e].kind == PIC_LMATCH ? Y[e][3] : Y[e][0]) - q0[e]) / a.dt;
         }
         s->U_E[e] = U[e];
     }
@@ -336,7 +358,8 @@ __global__ __launch_bounds__(256) void k_circuit(CircArgs a) {
         a.serI1[a.k] = s->I_ccp[0];
     }
     s->t = t1;
-    for (int e = 0; e < a.n_el; ++e) {
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
         a.serU[e * a.spp + a.k] = s->U_E[e];
         a.serI[e * a.spp + a.k] = s->I_ccp[e];
     }
@@ -360,7 +383,12 @@ void launch_circuit(pic_handle* h) {
     a.dt = h->dt; a.qunit = h->qunit;
     a.n_el = h->n_el;
     for (int e = 0; e < h->n_el; ++e) a.ce[e] = circ_el(e == 0 ? h->cfg.circ : h->cfg.circ_el[e - 1]);
-    hipLaunchKernelGGL(k_circuit, dim3(1), dim3(256), 0, h->stream, a);
+    switch (h->n_el) {
+    case 1: hipLaunchKernelGGL(k_circuit<1>, dim3(1), dim3(256), 0, h->stream, a); break;
+    case 2: hipLaunchKernelGGL(k_circuit<2>, dim3(1), dim3(256), 0, h->stream, a); break;
+    case 3: hipLaunchKernelGGL(k_circuit<3>, dim3(1), dim3(256), 0, h->stream, a); break;
+    default: hipLaunchKernelGGL(k_circuit<4>, dim3(1), dim3(256), 0, h->stream, a); break;
+    }
 }
 
 // ---------------------------------------------------------- FP64 residual
