@@ -164,6 +164,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sort-every", type=int, default=None)
+    ap.add_argument("--inner-tol", type=float, default=1e-4,
+                    help="relative residual reduction of each FP32 inner solve of the field solve")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-vs-plain field-solve comparison")
     ap.add_argument("--learned-harvest-steps", type=int, default=24)
@@ -204,7 +206,7 @@ def main():
     print(f"[bench] init {args.workload} method={args.method}", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     learned = not args.no_learned
-    sim = Pic(w, timing=True, method=method, unet_batch=args.learned_batch if learned else 0,
+    sim = Pic(w, timing=True, method=method, inner_tol=args.inner_tol, unet_batch=args.learned_batch if learned else 0,
               unet_pairs=512 if learned else 0)
     torch.cuda.synchronize()
     t_init = time.perf_counter() - t0
