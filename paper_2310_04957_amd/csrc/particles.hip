@@ -10,9 +10,9 @@
 
 namespace pic {
 
-// LDS deposit window: the 16x16-cell tile of a chunk's first particle plus
-// a halo of H cells, (16 + 2H + 1)^2 nodes; electrons (fast, dispersing
-// between sorts) use H = 24, ions H = 16
+// LDS deposit window: the 16x16-cell tile of a particle from the middle of a
+// chunk plus a halo of H cells, (16 + 2H + 1)^2 nodes; electrons (fast,
+// dispersing between sorts) use H = 24, ions H = 16
 constexpr int win_nodes(int halo) { return kTile + 2 * halo + 1; }
 constexpr int kRounds = kSlice / 64;
 static_assert(kSlice % 256 == 0 && kRounds % 4 == 0, "decision words are shared by four aligned rounds");
@@ -224,21 +224,26 @@ __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4)))
 
     for (long long chunk = blockIdx.x; chunk < nch; chunk += gridDim.x) {
         const long long base = chunk * kPushChunk;
-        // LDS window origin: tile of the chunk's first live particle, plus halo
+        // LDS window origin: tile of a live particle from the middle of the
+        // chunk (else from its start), plus halo.  Sorted chunks that span
+        // several tiles then keep both ends inside the window.
         if (wave == 0) {
-            const long long p = base + lane;
-            bool ok = false;
-            Loc L;
-            if (p < n) {
+            const long long mid = max(base, base + min((long long)kPushChunk, n - base) / 2 - 32);
+            auto probe = [&](long long p, Loc& L) {
+                if (p >= n) return false;
                 const uint32_t q = kMoved ? a.perm[p] : (uint32_t)p;
                 const float* const* rz = kMoved ? a.src : const_cast<const float* const*>(f);
                 const float r = rz[0][q];
                 L = locate(r, rz[1][q], g);
-                ok = (r >= 0.0f) && L.inside;
-            }
-            const unsigned long long m = __ballot(ok);
+                return (r >= 0.0f) && L.inside;
+            };
+            Loc Lm, Lb;
+            const bool okm = probe(mid + lane, Lm), okb = probe(base + lane, Lb);
+            const unsigned long long mm = __ballot(okm), mb = __ballot(okb);
+            const unsigned long long m = mm ? mm : mb;
             const int first = m ? __ffsll((long long)m) - 1 : -1;
             if (lane == first) {
+                const Loc& L = mm ? Lm : Lb;
                 s_org[0] = ((L.i >> kTileShift) << kTileShift) - kHalo;
                 s_org[1] = ((L.j >> kTileShift) << kTileShift) - kHalo;
             }
