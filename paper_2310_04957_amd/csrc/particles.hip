@@ -142,8 +142,6 @@ __device__ __forceinline__ void store8(float* const* f, uint32_t p, const P9& s)
     stf(f[5], o, s.ar); stf(f[6], o, s.at); stf(f[7], o, s.az);
 }
 
-__device__ __forceinline__ void kill(float* const* f, uint32_t p) { stf(f[0], p << 2, -1.0f); }
-
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -316,12 +314,9 @@ __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4)))
             if (has) {
                 d1_predict(c, a.dt);
                 const Loc L2 = locate(c.r, c.z, g);
-                if (absorb<kWin>(g, L2, c.w, a.sign, s_abs, a.wallq, vac, wi0, wj0, s_ck)) {
-                    kill(f, slot);
-                } else {
-                    fallback += deposit<kWin>(g, L2, c.w, win, s_invd, wi0, wj0, a.dep);
-                    store_slot(f, slot, c, moved);
-                }
+                if (absorb<kWin>(g, L2, c.w, a.sign, s_abs, a.wallq, vac, wi0, wj0, s_ck)) c.r = -1.0f;
+                else fallback += deposit<kWin>(g, L2, c.w, win, s_invd, wi0, wj0, a.dep);
+                store_slot(f, slot, c, moved);
             }
         };
 
@@ -338,7 +333,8 @@ __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4)))
             const uint32_t dword = (it & 3) == 0 ? dec4.x : (it & 3) == 1 ? dec4.y : (it & 3) == 2 ? dec4.z : dec4.w;
             P9 s = cur;
             bool coll = false;
-            if (p < n && s.r >= 0.0f) {
+            const bool live = p < n && s.r >= 0.0f;
+            if (live) {
                 float Er, Ez;
                 const EW ew = e_weights(g, s.r, s.z);
                 const int eli = ew.i - wi0, elj = ew.j - wj0;
@@ -355,28 +351,29 @@ __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4)))
                 d1_correct(s, Er, Ez, a.qm, a.dt);
                 const Loc L = locate(s.r, s.z, g);
                 if (absorb<kWin>(g, L, s.w, a.sign, s_abs, a.wallq, vac, wi0, wj0, s_ck)) {
-                    kill(f, (uint32_t)p);
+                    s.r = -1.0f;
                 } else {
                     coll = dword < a.m.thresh;
                     if (!coll) {
                         d1_predict(s, a.dt);
                         const Loc L2 = locate(s.r, s.z, g);
                         if (absorb<kWin>(g, L2, s.w, a.sign, s_abs, a.wallq, vac, wi0, wj0, s_ck)) {
-                            kill(f, (uint32_t)p);
+                            s.r = -1.0f;
                         } else {
                             fallback += deposit<kWin>(g, L2, s.w, win, s_invd, wi0, wj0, a.dep);
-                            store_slot(f, (uint32_t)p, s, moved);
                         }
                     }
                 }
             }
-            // ballot compaction of this round's colliders into the queue; the
-            // corrected state waits in the collider's own slot
+            // one store per round for every live slot: the predicted state,
+            // r = -1 for a removed particle, the corrected state for a
+            // collider (it waits there for the queue)
+            if (live) store_slot(f, (uint32_t)p, s, moved);
+            // ballot compaction of this round's colliders into the queue
             const unsigned long long m = __ballot(coll);
             if (coll) {
                 const int q = qn + __popcll(m & lanemask_lt());
                 ql[q] = (unsigned int)p;
-                store_slot(f, (uint32_t)p, s, moved);
             }
             qn += __popcll(m);
             wave_sync();

@@ -234,11 +234,11 @@ __device__ __forceinline__ float e_cos_chi(float eps, float u) {
     return fminf(1.0f, fmaxf(-1.0f, c));
 }
 
-// turn unit vector d by polar angle chi (cos cchi) and azimuth phi
-__device__ __forceinline__ void rotate_dir(float& u, float& v, float& w, float cchi, float phi) {
+// turn unit vector d by polar angle chi (cos cchi) and azimuth 2 pi t
+__device__ __forceinline__ void rotate_dir(float& u, float& v, float& w, float cchi, float t) {
     float schi = sqrtf(fmaxf(0.0f, 1.0f - cchi * cchi));
     float sp, cp;
-    sincosf(phi, &sp, &cp);
+    sincospif(2.0f * t, &sp, &cp);
     float st = sqrtf(u * u + v * v);
     if (st > 1e-12f) {
         float inv = 1.0f / st;
@@ -254,11 +254,10 @@ __device__ __forceinline__ void rotate_dir(float& u, float& v, float& w, float c
 }
 
 __device__ __forceinline__ void maxwell3(uint4 y, float vth, float& a, float& b, float& c) {
-    const float two_pi = 6.28318530717958647692f;
     float m0 = sqrtf(-2.0f * logf(u01(y.x))), m1 = sqrtf(-2.0f * logf(u01(y.z)));
     float s0, c0, s1, c1;
-    sincosf(two_pi * u01(y.y), &s0, &c0);
-    sincosf(two_pi * u01(y.w), &s1, &c1);
+    sincospif(2.0f * u01(y.y), &s0, &c0);
+    sincospif(2.0f * u01(y.w), &s1, &c1);
     a = vth * m0 * c0;
     b = vth * m0 * s0;
     c = vth * m1 * c1;
@@ -270,7 +269,6 @@ __device__ __forceinline__ void maxwell3(uint4 y, float vth, float& a, float& b,
 __device__ __forceinline__ int collide(int sp, uint4 x, float& vr, float& vt, float& vz, const Mcc& m,
                                       uint32_t slot, uint32_t step, uint32_t key0, uint32_t key1,
                                       float* born6, unsigned int* viol) {
-    const float two_pi = 6.28318530717958647692f;
     float u1 = u01(x.y), u2 = u01(x.z), u3 = u01(x.w);
     float R = u1 * m.nu_max;
     if (sp == 0) {
@@ -284,38 +282,38 @@ __device__ __forceinline__ int collide(int sp, uint4 x, float& vr, float& vt, fl
         float n_el = k * el, n_ex = k * ex, n_io = k * io;
         float inv = 1.0f / vm;
         float du = vr * inv, dv = vt * inv, dw = vz * inv;
+        // the scattered electron of every process: scattering energy e_s
+        // (elastic: eps; excitation: eps - 11.5 eV; ionisation: what the
+        // ejected electron leaves), then one deflection for all three
+        int proc;
+        float e_s;
         if (R < n_el) {
-            float cc = e_cos_chi(eps, u2);
-            float e2 = eps * (1.0f - m.m_ratio2 * (1.0f - cc));
-            rotate_dir(du, dv, dw, cc, two_pi * u3);
-            float s = sqrtf(m.two_e_over_m * e2);
-            vr = s * du; vt = s * dv; vz = s * dw;
-            return 0;
-        }
-        if (R < n_el + n_ex) {
-            float e1 = eps - 11.5f;
-            float cc = e_cos_chi(e1, u2);
-            rotate_dir(du, dv, dw, cc, two_pi * u3);
-            float s = sqrtf(m.two_e_over_m * fmaxf(e1, 0.0f));
-            vr = s * du; vt = s * dv; vz = s * dw;
-            return 1;
-        }
-        if (R < n_el + n_ex + n_io) {
+            proc = 0;
+            e_s = eps;
+        } else if (R < n_el + n_ex) {
+            proc = 1;
+            e_s = eps - 11.5f;
+        } else if (R < n_el + n_ex + n_io) {
+            proc = 2;
             uint4 y = draw(slot, step, kPurposeMcc, sp, 1, key0, key1);
             uint4 z4 = draw(slot, step, kPurposeMcc, sp, 2, key0, key1);
             float e1 = eps - 15.76f;
             float eej = 10.0f * tanf(u01(y.x) * atanf(e1 * (1.0f / 20.0f)));
-            float esc = fmaxf(e1 - eej, 0.0f);
+            e_s = fmaxf(e1 - eej, 0.0f);
             float bu = du, bv = dv, bw = dw;
-            rotate_dir(du, dv, dw, e_cos_chi(esc, u2), two_pi * u3);
-            rotate_dir(bu, bv, bw, e_cos_chi(eej, u01(y.y)), two_pi * u01(y.z));
-            float s1 = sqrtf(m.two_e_over_m * esc), s2 = sqrtf(m.two_e_over_m * eej);
-            vr = s1 * du; vt = s1 * dv; vz = s1 * dw;
+            rotate_dir(bu, bv, bw, e_cos_chi(eej, u01(y.y)), u01(y.z));
+            float s2 = sqrtf(m.two_e_over_m * eej);
             born6[0] = s2 * bu; born6[1] = s2 * bv; born6[2] = s2 * bw;
             maxwell3(z4, m.vth_gas, born6[3], born6[4], born6[5]);
-            return 2;
+        } else {
+            return 3;
         }
-        return 3;
+        const float cc = e_cos_chi(e_s, u2);
+        const float e_out = proc == 0 ? eps * (1.0f - m.m_ratio2 * (1.0f - cc)) : fmaxf(e_s, 0.0f);
+        rotate_dir(du, dv, dw, cc, u3);
+        float s = sqrtf(m.two_e_over_m * e_out);
+        vr = s * du; vt = s * dv; vz = s * dw;
+        return proc;
     }
     // Ar+ on Ar: partner from the gas Maxwellian, relative velocity g
     uint4 y = draw(slot, step, kPurposeMcc, sp, 1, key0, key1);
@@ -335,7 +333,7 @@ __device__ __forceinline__ int collide(int sp, uint4 x, float& vr, float& vt, fl
         float cc = sqrtf(1.0f - u2);
         float inv = 1.0f / gm;
         float du = gr * inv, dv = gt * inv, dw = gz * inv;
-        rotate_dir(du, dv, dw, cc, two_pi * u3);
+        rotate_dir(du, dv, dw, cc, u3);
         float gp = gm * cc;
         vr = nr_ + gp * du; vt = nt_ + gp * dv; vz = nz_ + gp * dw;
         return 0;
