@@ -158,16 +158,18 @@ def test_loader_matches_oracle_load():
     g.close()
 
 
-@pytest.mark.parametrize("gas_factor", [1, 10, 40])
-def test_one_step_matches_oracle_given_identical_state(gas_factor):
+@pytest.mark.parametrize("gas_factor,vmax_e", [(1, 6e5), (10, 6e5), (40, 6e5), (1, 6e6)])
+def test_one_step_matches_oracle_given_identical_state(gas_factor, vmax_e):
     """gas_factor scales the pressure: at 10x (collision probability 0.57
     for electrons) and 40x (0.97) most rounds of 64 particles hold more
-    colliders than the kernel's per-wavefront collider queue."""
+    colliders than the kernel's per-wavefront collider queue.  Electrons up
+    to 6e6 m/s (about 100 eV) ionise: the births are appended in parent
+    order and compared slot by slot."""
     w = workload("pp32x24", run=dict(n_e=0, n_i=0, cap_e=40000, cap_i=40000, sort_every=0))
     w["gas"]["p_Pa"] *= gas_factor
     w["solver"]["tol"] = 1e-12
     gm = w["geometry"]
-    pe = random_particles(20000, gm["R"] * 0.98, gm["Z"], seed=41, vmax=6e5, amax=1e13, wmin=1.0, wmax=1.0,
+    pe = random_particles(20000, gm["R"] * 0.98, gm["Z"], seed=41, vmax=vmax_e, amax=1e13, wmin=1.0, wmax=1.0,
                           z_lo=0.002, z_hi=0.023)
     pi = random_particles(20000, gm["R"] * 0.98, gm["Z"], seed=42, vmax=3e3, amax=1e9, wmin=1.0, wmax=1.0,
                           z_lo=0.002, z_hi=0.023)
@@ -195,6 +197,9 @@ def test_one_step_matches_oracle_given_identical_state(gas_factor):
             assert np.mean(err > 1e-4) <= 2e-3, (sp, f)
         assert dg.coll[sp][0] + dg.coll[sp][1] + dg.coll[sp][2] + dg.coll[sp][3] == \
             do.coll[sp][0] + do.coll[sp][1] + do.coll[sp][2] + do.coll[sp][3]
+    if vmax_e > 1e6:
+        assert dg.born > 100 and dg.born == do.born
+    assert dg.error == 0
     g.close()
 
 
