@@ -802,6 +802,68 @@ __global__ __launch_bounds__(256) void k_coarse(const T* b, T* y, const int* cma
     coarse_block(b, y, cmap, clist, inv, nc, cn, sb);
 }
 
+// The coarse end of the V-cycle, from the first level of at most
+// kTailNodes nodes down to the dense solve, in one block: the same steps as
+// the kernels above, in the same order, each a block-stride loop followed
+// by a block barrier (on these small levels a kernel launch per step costs
+// more than the step).
+constexpr int kTailNodes = 2200;
+constexpr int kMaxTail = 8;
+template <typename T>
+struct TailLevel {
+    Sten S;
+    T *x, *y, *b, *res;
+    const T* D;
+    int nr, nz, cr, cz;
+};
+template <typename T>
+struct TailArgs {
+    TailLevel<T> L[kMaxTail];
+    int n;                        // levels; the last one is solved densely
+    const int* cmap;
+    const T* inv;
+    int nc;
+    const DevScalars* s;
+};
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_tail(TailArgs<T> a) {
+    __shared__ T sb[kMaxCoarse];
+    if (a.s->done) return;
+    const int t0 = threadIdx.x, st = blockDim.x;
+    const int last = a.n - 1;
+    for (int l = 0; l < last; ++l) {
+        const TailLevel<T>& L = a.L[l];
+        const TailLevel<T>& C = a.L[l + 1];
+        jac9_range(L.S, L.x, L.b, L.x, L.nr, L.nz, 1, t0, st);
+        __syncthreads();
+        jac9_range(L.S, L.x, L.b, L.y, L.nr, L.nz, 0, t0, st);
+        __syncthreads();
+        res9_range(L.S, L.y, L.b, L.res, L.nr, L.nz, t0, st);
+        __syncthreads();
+        restrict_range((const T*)L.res, (const int8_t*)nullptr, L.D, L.nr, L.nz, C.b, C.D, C.nr, C.nz, L.cr, L.cz, t0,
+                       st);
+        __syncthreads();
+    }
+    {
+        const TailLevel<T>& C = a.L[last];
+        const int cn = (C.nr + 1) * (C.nz + 1);
+        coarse_block((const T*)C.b, C.y, a.cmap, a.cmap + cn, a.inv, a.nc, cn, sb);
+        __syncthreads();
+    }
+    for (int l = last - 1; l >= 0; --l) {
+        const TailLevel<T>& L = a.L[l];
+        const TailLevel<T>& C = a.L[l + 1];
+        prolong_range(L.y, (const int8_t*)nullptr, L.D, L.nr, L.nz, (const T*)C.y, C.D, C.nr, C.nz, L.cr, L.cz, t0,
+                      st);
+        __syncthreads();
+        jac9_range(L.S, L.y, L.b, L.x, L.nr, L.nz, 0, t0, st);
+        __syncthreads();
+        jac9_range(L.S, L.x, L.b, L.y, L.nr, L.nz, 0, t0, st);
+        __syncthreads();
+    }
+}
+
 // ------------------------------------------------- multigrid construction
 // Galerkin product A_c = P^T A_f P, one coarse node per thread.  A coarse
 // node is active only if the fine node it injects into is active, which
@@ -998,6 +1060,24 @@ static void vcycle(pic_handle* h, int l, const T* b0, T* y0) {
     const T* b = (l == 0) ? b0 : V::b(L);
     T* y = (l == 0) ? y0 : V::y(L);
     T* x = V::x(L);
+    if (l >= 1 && l < h->nlev - 1 && L.nn <= kTailNodes && h->nlev - l <= kMaxTail) {
+        TailArgs<T> ta;
+        ta.n = h->nlev - l;
+        for (int k = 0; k < ta.n; ++k) {
+            Level& M = h->lv[l + k];
+            TailLevel<T>& t = ta.L[k];
+            t.S = V::sten(M);
+            t.x = V::x(M); t.y = V::y(M); t.b = V::b(M); t.res = V::res(M);
+            t.D = V::diag(M);
+            t.nr = M.nr; t.nz = M.nz; t.cr = M.cr; t.cz = M.cz;
+        }
+        ta.cmap = h->cmap;
+        ta.inv = V::cinv(h);
+        ta.nc = h->ncoarse;
+        ta.s = s;
+        hipLaunchKernelGGL(k_tail<T>, dim3(1), dim3(1024), 0, st, ta);
+        return;
+    }
     if (l == h->nlev - 1) {
         if (l == 0) {
             // single-level hierarchy: smoothing only
