@@ -133,6 +133,72 @@ def electrodes_pass(args):
     return res
 
 
+def precision_study(periods=4):
+    """The 512x1024 precision study: for each (pressure, source amplitude)
+    point, the same discharge (64M + 64M particles) run `periods` RF periods
+    with the FP32-inner IR solve (seed 1) and with all-FP64 MG-PCG (seeds 1
+    and 2).  The IR-vs-FP64 difference of the last period's averaged
+    densities and of the electrode current and voltage harmonics 1..5 is
+    reported beside the seed-to-seed difference of the FP64 runs (the
+    discharge's own statistical noise).  The push is FP32 in all three runs;
+    its error against an FP64 push is measured by the one-step and
+    statistical parity tests against the oracle."""
+    import numpy as np
+    import torch
+    from paper_2310_04957_amd.pic import Pic, SOLVE_IR_MG, SOLVE_MGPCG_FP64
+    from pic_inputs import workload
+    from pic_inputs.workloads import GEC512_SWEEP, MTORR_PA, _lmatch
+
+    def run(p_mtorr, U, method, seed):
+        w = workload("gec512x1024")
+        w["gas"]["p_Pa"] = p_mtorr * MTORR_PA
+        w["circuit"] = _lmatch(float(U))
+        w["run"]["seed"] = seed
+        spp = w["run"]["steps_per_period"]
+        print(f"[bench] precision study {p_mtorr} mTorr {U} V method {method} seed {seed}",
+              file=sys.stderr, flush=True)
+        sim = Pic(w, method=method, timing=True)
+        sim.reset_timers()
+        sim.step(periods * spp)
+        torch.cuda.synchronize()
+        d, g = sim.diag(grids=True)
+        out = dict(n_e=g["n_e"], n_i=g["n_i"],
+                   hI=np.array(d.harm_I_re[:]) + 1j * np.array(d.harm_I_im[:]),
+                   hU=np.array(d.harm_U_re[:]) + 1j * np.array(d.harm_U_im[:]),
+                   field_ms=d.ms_field / (periods * spp), nr=w["geometry"]["nr"], nz=w["geometry"]["nz"])
+        sim.close()
+        return out
+
+    def blocks(n, nr, nz, b=16):
+        a = n.reshape(nz + 1, nr + 1)
+        H, W = (nz + 1) // b * b, (nr + 1) // b * b
+        return a[:H, :W].reshape(H // b, b, W // b, b).sum(axis=(1, 3)).ravel()
+
+    def diff(a, b):
+        r = {}
+        for sp in ("n_e", "n_i"):
+            r[sp + "_total"] = abs(a[sp].sum() - b[sp].sum()) / b[sp].sum()
+            ba, bb = blocks(a[sp], a["nr"], a["nz"]), blocks(b[sp], b["nr"], b["nz"])
+            m = bb > 1e-3 * bb.max()
+            r[sp + "_16x16_blocks_rms"] = float(np.sqrt(np.mean(((ba[m] - bb[m]) / bb[m]) ** 2)))
+        for h in ("hI", "hU"):
+            r[h + "_1_5"] = [float(abs(a[h][k] - b[h][k]) / abs(b[h][k])) for k in range(1, 6)]
+        return {k: (round(v, 5) if isinstance(v, float) else [round(x, 5) for x in v]) for k, v in r.items()}
+
+    res = []
+    for p_mtorr, U in GEC512_SWEEP:
+        try:
+            ir = run(p_mtorr, U, SOLVE_IR_MG, 1)
+            f1 = run(p_mtorr, U, SOLVE_MGPCG_FP64, 1)
+            f2 = run(p_mtorr, U, SOLVE_MGPCG_FP64, 2)
+        except RuntimeError as e:
+            res.append({"p_mTorr": p_mtorr, "U_s": U, "error": str(e)})
+            continue
+        res.append({"p_mTorr": p_mtorr, "U_s": U, "ir_vs_fp64": diff(ir, f1), "fp64_seed2_vs_seed1": diff(f2, f1),
+                    "field_ms_per_step": {"ir": round(ir["field_ms"], 3), "fp64": round(f1["field_ms"], 3)}})
+    return {"grid": "512x1024", "particles": "64M + 64M", "periods": periods, "points": res}
+
+
 def split_pass(sim):
     """One particle-splitting pass per species on the discharge as it stands
     (equal loading weights: particles near the axis are heavier than the
@@ -172,6 +238,8 @@ def main():
     ap.add_argument("--learned-train-steps", type=int, default=150)
     ap.add_argument("--learned-batch", type=int, default=4)
     ap.add_argument("--learned-solve-steps", type=int, default=3)
+    ap.add_argument("--precision-study", action="store_true",
+                    help="also run the 512x1024 precision study (IR vs all-FP64 solve, seed noise floor)")
     ap.add_argument("--no-electrodes-pass", action="store_true",
                     help="skip timing the field solve and refresh with one and two driven electrodes")
     ap.add_argument("--no-split-pass", action="store_true",
@@ -280,6 +348,8 @@ def main():
     if not args.no_electrodes_pass and args.workload.startswith("gec"):
         print("[bench] driven electrodes", file=sys.stderr, flush=True)
         out["electrodes_pass"] = electrodes_pass(args)
+    if args.precision_study:
+        out["precision_study"] = precision_study()
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_sample, args.cpu_steps)
