@@ -18,7 +18,7 @@ namespace pic {
 
 constexpr double kEps0 = 8.8541878128e-12;
 constexpr double kOmega = 0.7;   // damped-Jacobi weight of the multigrid smoother
-constexpr int kCheckEvery = 4;   // Krylov iterations between host convergence reads
+constexpr int kCheckEvery = 4;   // Krylov iterations between host convergence reads (unguided)
 
 // ------------------------------------------------------------ small utils
 __global__ void k_fill_u64(unsigned long long* p, size_t n) {
@@ -1157,7 +1157,8 @@ void harvest_iterate<double>(pic_handle* h, int k, const double* r, const double
 }
 
 template <typename T>
-static int pcg(pic_handle* h, T* r, T* x, T* z, T* p, T* q, int max_iter, int* err, int ident = 0) {
+static int pcg(pic_handle* h, T* r, T* x, T* z, T* p, T* q, int max_iter, int* err, int ident = 0,
+               int first_check = kCheckEvery) {
     using V = VecSet<T>;
     hipStream_t st = h->stream;
     const int nn = h->nn;
@@ -1182,12 +1183,18 @@ static int pcg(pic_handle* h, T* r, T* x, T* z, T* p, T* q, int max_iter, int* e
         hipLaunchKernelGGL(k_dot<T>, dim3(kRedBlocks), dim3(256), 0, st, (const T*)r, (const T*)z, h->part, s, nn);
         hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, st, (const double*)h->part, s, 3);
         hipLaunchKernelGGL(k_update_p<T>, grid_for(nn), dim3(256), 0, st, p, (const T*)z, s, nn);
-        if ((it + 1) % kCheckEvery == 0 || it + 1 == max_iter) {
+        // the host reads the convergence flag first after first_check
+        // iterations (what the same solve needed last time), then after
+        // every iteration: iterations launched after convergence return at
+        // once but still cost their launches
+        if (it + 1 >= first_check || it + 1 == max_iter) {
             if (!read_scalars(h)) { *err = PIC_E_HIP; return it; }
             if (h->h_sc->done) break;
         }
     }
-    if (!read_scalars(h)) { *err = PIC_E_HIP; return it; }
+    // (the scalars were read after the last iteration launched, unless
+    // max_iter is 0)
+    if (it == 0 && !read_scalars(h)) { *err = PIC_E_HIP; return it; }
     if (h->h_sc->nonfinite) *err = PIC_E_NONFINITE;
     return h->h_sc->iters;
 }
@@ -1379,7 +1386,10 @@ int field_solve(pic_handle* h, double* phi, const double* Q, const double* Up, d
         if (fp64) {
             h->harvesting = harvest && outer == 0;
             h->harvest_limit = std::min(unet::kHarvestPerSolve, h->net.cap_pairs);
-            const int its = pcg<double>(h, h->r64, h->x64, h->z64, h->p64, h->q64, h->cfg.solver.max_iter, &err);
+            int& guess = h->cg_guess[1][std::min(outer, 3)];
+            const int its = pcg<double>(h, h->r64, h->x64, h->z64, h->p64, h->q64, h->cfg.solver.max_iter, &err, 0,
+                                        guess);
+            guess = std::max(1, its);
             total += its;
             if (h->harvesting && !err && its > 0) {
                 // iterates 0 .. its-2: the last two are too close to x* for
@@ -1405,8 +1415,11 @@ int field_solve(pic_handle* h, double* phi, const double* Q, const double* Up, d
                 // the correction found so far is kept; multigrid finishes the solve
                 if (h->h_sc->fallback) { method = PIC_SOLVE_IR_MG; h->unet_fallbacks++; }
             } else {
-                total += pcg<float>(h, h->r32, h->x32, h->z32, h->p32, h->q32, h->cfg.solver.max_iter, &err,
-                                    method == PIC_SOLVE_IR_CG ? 1 : 0);
+                int& guess = h->cg_guess[0][std::min(outer, 3)];
+                const int its = pcg<float>(h, h->r32, h->x32, h->z32, h->p32, h->q32, h->cfg.solver.max_iter, &err,
+                                           method == PIC_SOLVE_IR_CG ? 1 : 0, guess);
+                guess = std::max(1, its);
+                total += its;
             }
             hipLaunchKernelGGL(k_add_phi<float>, grid_for(nn), dim3(256), 0, st, phi, (const float*)h->x32,
                                (const int8_t*)h->node_kind, (const DevScalars*)h->sc, nn, 1);

@@ -154,6 +154,7 @@ struct pic_handle {
     int64_t step, periods_done;
     int have_last;
     int64_t solver_iters, solver_outer;
+    int cg_guess[2][4];           // Krylov iterations of the last solve, per precision and outer pass
     double solver_relres;
     int sticky_err;
     // learned preconditioner
