@@ -211,7 +211,8 @@ def split_pass(sim):
         try:
             added = sim.split_now(sp)
         except Exception as e:  # the copies do not fit: reported, nothing changed
-            res[name] = {"error": str(e)}
+            res[name] = {"error": str(e), "slots": int(n0), "capacity": int(sim.cap[sp]),
+                         "note": "the copies would not fit in the slot capacity; nothing was changed"}
             continue
         ms = 1e3 * (time.perf_counter() - t0)
         res[name] = {"ms": ms, "slots": int(n0), "copies": int(added),
@@ -222,7 +223,8 @@ def split_pass(sim):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=400,
+                    help="timed steps (default: one RF period of the workload)")
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="gec1024x2048")
     ap.add_argument("--method", default="ir", choices=["ir", "mgpcg"])
@@ -230,6 +232,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sort-every", type=int, default=None)
+    ap.add_argument("--sort-every-ion", type=int, default=None)
     ap.add_argument("--inner-tol", type=float, default=1e-4,
                     help="relative residual reduction of each FP32 inner solve of the field solve")
     ap.add_argument("--no-learned", action="store_true",
@@ -270,6 +273,8 @@ def main():
     w = workload(args.workload)
     if args.sort_every is not None:
         w["run"]["sort_every"] = args.sort_every
+    if args.sort_every_ion is not None:
+        w["run"]["sort_every_ion"] = args.sort_every_ion
     method = SOLVE_IR_MG if args.method == "ir" else SOLVE_MGPCG_FP64
     print(f"[bench] init {args.workload} method={args.method}", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
@@ -320,7 +325,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "grid": f"{w['geometry']['nr']}x{w['geometry']['nz']}",
-                   "particles": int(n_start), "solver": args.method, "sort_every": w["run"]["sort_every"], "steps_per_period": w["run"]["steps_per_period"]},
+                   "particles": int(n_start), "solver": args.method, "sort_every": w["run"]["sort_every"],
+                   "sort_every_ion": w["run"]["sort_every_ion"], "steps_per_period": w["run"]["steps_per_period"]},
         "particle_loop_particle_steps_per_s": ps / (ms_part * 1e-3) if ms_part > 0 else None,
         "field_solve_ms_per_step": d.ms_field / max(args.steps, 1),
         "phase_ms_per_step": {"particles_e": d.ms_particles[0] / args.steps, "particles_i": d.ms_particles[1] / args.steps,
