@@ -21,11 +21,9 @@ __device__ __forceinline__ float bf2f(__bf16 v) {
     return __uint_as_float(((unsigned)__builtin_bit_cast(unsigned short, v)) << 16);
 }
 __device__ __forceinline__ bf16 f2bf(float f) {
-    // round to nearest even (finite inputs)
-    unsigned u = __float_as_uint(f);
-    u = u + 0x7FFFu + ((u >> 16) & 1u);
+    // round to nearest even: one hardware conversion on gfx950
     bf16 r;
-    r.x = (unsigned short)(u >> 16);
+    r.x = __builtin_bit_cast(unsigned short, (__bf16)f);
     return r;
 }
 __device__ __forceinline__ __bf16 f2raw(float f) { return __builtin_bit_cast(__bf16, f2bf(f).x); }
@@ -131,21 +129,31 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16* __restrict__ X, con
                 }
             }
         }
-        // D layout: lane holds column n = lane % 32, rows 8(r/4) + 4(lane/32) + r%4
-        for (int s = 0; s < 2; ++s)
+        // D layout: lane holds column n = lane % 32, rows pm = 8(r/4) +
+        // 4(lane/32) + r%4, i.e. tile row pm/16 = (r >= 8) and column
+        // pm % 16 = 8((r/4) & 1) + 4(lane/32) + r%4.  One base address per
+        // lane and compile-time offsets; bounds are checked only on edge
+        // tiles; bf16 by the hardware's round-to-nearest-even conversion.
+        const bool full = y0 + 16 <= H && x0 + 16 <= W;
+        const int cx = 4 * (lane >> 5);
+        for (int s = 0; s < 2; ++s) {
+            const int py0 = y0 + wave * 4 + s * 2;
+            unsigned short* const Yb = reinterpret_cast<unsigned short*>(Y) +
+                                       (((size_t)b * H + py0) * W + x0 + cx) * COUT;
+            const size_t row = (size_t)W * COUT;
             for (int nt = 0; nt < NT; ++nt) {
                 const int n = nt * 32 + (lane & 31);
                 const float bb = bias ? bias[n] : 0.0f;
+#pragma unroll
                 for (int r = 0; r < 16; ++r) {
-                    const int pm = 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
-                    const int py = y0 + wave * 4 + s * 2 + pm / 16, px = x0 + pm % 16;
-                    if (py < H && px < W) {
-                        float v = acc[s][nt][r] + bb;
-                        if (RELU) v = fmaxf(v, 0.0f);
-                        Y[(((size_t)b * H + py) * W + px) * COUT + n] = f2bf(v);
-                    }
+                    const int dy = r >= 8 ? 1 : 0, dx = 8 * ((r / 4) & 1) + (r % 4);
+                    float v = acc[s][nt][r] + bb;
+                    if (RELU) v = fmaxf(v, 0.0f);
+                    const unsigned short hv = __builtin_bit_cast(unsigned short, (__bf16)v);
+                    if (full || (py0 + dy < H && x0 + cx + dx < W)) Yb[dy * row + dx * COUT + n] = hv;
                 }
             }
+        }
     }
 }
 
