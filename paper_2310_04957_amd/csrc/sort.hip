@@ -45,6 +45,10 @@ __global__ __launch_bounds__(kBlock) void k_keys(KeyArgs a) {
     if ((threadIdx.x & 63) == 0 && dead) atomicAdd(a.dead, dead);
 }
 
+// Digit counts per chunk.  Each thread counts kItems consecutive keys and
+// adds a run of equal digits with one LDS atomic: sorted or nearly sorted
+// keys (the usual case between two sorts) then cost about one atomic per
+// thread instead of one per key on the same few bins.
 __global__ __launch_bounds__(kBlock) void k_hist(const uint32_t* keys, const long long* n_slots, int sp, int shift,
                                                  uint32_t* hist) {
     __shared__ unsigned int h[256];
@@ -53,10 +57,33 @@ __global__ __launch_bounds__(kBlock) void k_hist(const uint32_t* keys, const lon
     for (long long c = blockIdx.x; c < nch; c += gridDim.x) {
         h[threadIdx.x] = 0u;
         __syncthreads();
-        for (int it = 0; it < kItems; ++it) {
-            long long p = c * kChunk + (long long)it * kBlock + threadIdx.x;
-            if (p < n) atomicAdd(&h[(keys[p] >> shift) & 0xFFu], 1u);
+        const long long p0 = c * kChunk + (long long)threadIdx.x * kItems;
+        uint32_t kv[kItems];
+        if (p0 + kItems <= n) {
+#pragma unroll
+            for (int q = 0; q < kItems / 4; ++q) {
+                const uint4 v = *reinterpret_cast<const uint4*>(keys + p0 + 4 * q);
+                kv[4 * q] = v.x; kv[4 * q + 1] = v.y; kv[4 * q + 2] = v.z; kv[4 * q + 3] = v.w;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < kItems; ++q) kv[q] = p0 + q < n ? keys[p0 + q] : 0u;
         }
+        const int cnt = (int)min((long long)kItems, max(0LL, n - p0));
+        uint32_t run_d = 0u, run_n = 0u;
+#pragma unroll
+        for (int q = 0; q < kItems; ++q) {
+            if (q < cnt) {
+                const uint32_t d = (kv[q] >> shift) & 0xFFu;
+                if (run_n != 0u && d != run_d) {
+                    atomicAdd(&h[run_d], run_n);
+                    run_n = 0u;
+                }
+                run_d = d;
+                ++run_n;
+            }
+        }
+        if (run_n != 0u) atomicAdd(&h[run_d], run_n);
         __syncthreads();
         hist[(long long)threadIdx.x * nch + c] = h[threadIdx.x];
         __syncthreads();
