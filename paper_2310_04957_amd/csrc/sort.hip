@@ -18,7 +18,6 @@ struct KeyArgs {
     const float* r;
     const float* z;
     uint32_t* keys;
-    uint32_t* idx;
     const long long* n_slots;
     unsigned int* dead;
     int sp, ntr;
@@ -38,7 +37,6 @@ __global__ __launch_bounds__(kBlock) void k_keys(KeyArgs a) {
         }
         dead += (key == a.dead_key);
         a.keys[p] = key;
-        a.idx[p] = (uint32_t)p;
     }
     // wave reduction then one atomic per wave
     for (int o = 32; o > 0; o >>= 1) dead += __shfl_down(dead, o);
@@ -234,7 +232,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* kin, const u
             if (valid) {
                 const unsigned int pos = wbase[wave][d] + rank;
                 kout[pos] = key;
-                vout[pos] = vin[p];
+                vout[pos] = vin ? vin[p] : (uint32_t)p;   // the first pass's values are the slots
             }
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
@@ -285,7 +283,7 @@ void launch_sort(pic_handle* h, int sp, bool deferred) {
     ka.g.invd = h->invd; ka.g.cell_kind = h->cell_kind; ka.g.node_kind = h->node_kind;
     for (int k = 0; k < 3; ++k) ka.g.edge_bc[k] = h->cfg.geom.edge_bc[k];
     ka.r = S.f[0]; ka.z = S.f[1];
-    ka.keys = h->keys[0]; ka.idx = h->idx[0];
+    ka.keys = h->keys[0];
     ka.n_slots = ns; ka.dead = dead + sp; ka.sp = sp; ka.ntr = h->ntr;
     ka.dead_key = (uint32_t)h->ntiles;   // one bucket past the last tile: sorts last
     hipLaunchKernelGGL(k_keys, dim3(2048), dim3(kBlock), 0, st, ka);
@@ -297,7 +295,8 @@ void launch_sort(pic_handle* h, int sp, bool deferred) {
         hipLaunchKernelGGL(k_scan_reduce, dim3(2048), dim3(kBlock), 0, st, h->hist, ns, sp, h->bsum);
         hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, h->bsum, ns, sp);
         hipLaunchKernelGGL(k_scan_down, dim3(2048), dim3(kBlock), 0, st, h->hist, h->bsum, ns, sp);
-        hipLaunchKernelGGL(k_scatter, dim3(2048), dim3(kBlock), 0, st, h->keys[src], h->idx[src], h->keys[1 - src],
+        hipLaunchKernelGGL(k_scatter, dim3(2048), dim3(kBlock), 0, st, h->keys[src], shift == 0 ? nullptr : h->idx[src],
+                           h->keys[1 - src],
                            last ? h->perm[sp] : h->idx[1 - src], h->hist, ns, sp, shift);
         src = 1 - src;
     }
