@@ -198,20 +198,43 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* kin, const u
     __shared__ unsigned int wbase[kWaves][256];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     constexpr int slice = kChunk / kWaves;
+    static_assert(slice == 64 * kItems, "a wavefront's slice is kItems keys per lane");
     const long long n = n_slots[sp];
     const long long nch = (n + kChunk - 1) / kChunk;
     for (long long c = blockIdx.x; c < nch; c += gridDim.x) {
         for (int w2 = 0; w2 < kWaves; ++w2) wcnt[w2][tid] = 0u;
         __syncthreads();
         const long long s0 = c * kChunk + (long long)wave * slice;
-        for (int it = 0; it < slice / 64; ++it) {
-            const long long p = s0 + it * 64 + lane;
-            const bool valid = p < n;
-            const uint32_t d = valid ? (kin[p] >> shift) & 0xFFu : 0u;
-            const unsigned long long peers = digit_peers(valid, d);
-            if (valid && __popcll(peers & lanemask_lt_s()) == 0) wcnt[wave][d] += (unsigned int)__popcll(peers);
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
+        // counts of the wavefront's slice: each lane counts kItems
+        // consecutive keys (slice = 64 kItems) by runs of equal digits
+        {
+            const long long p0 = s0 + (long long)lane * kItems;
+            uint32_t kv[kItems];
+            if (p0 + kItems <= n) {
+#pragma unroll
+                for (int q = 0; q < kItems / 4; ++q) {
+                    const uint4 v = *reinterpret_cast<const uint4*>(kin + p0 + 4 * q);
+                    kv[4 * q] = v.x; kv[4 * q + 1] = v.y; kv[4 * q + 2] = v.z; kv[4 * q + 3] = v.w;
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < kItems; ++q) kv[q] = p0 + q < n ? kin[p0 + q] : 0u;
+            }
+            const int cnt = (int)min((long long)kItems, max(0LL, n - p0));
+            uint32_t run_d = 0u, run_n = 0u;
+#pragma unroll
+            for (int q = 0; q < kItems; ++q) {
+                if (q < cnt) {
+                    const uint32_t d = (kv[q] >> shift) & 0xFFu;
+                    if (run_n != 0u && d != run_d) {
+                        atomicAdd(&wcnt[wave][run_d], run_n);
+                        run_n = 0u;
+                    }
+                    run_d = d;
+                    ++run_n;
+                }
+            }
+            if (run_n != 0u) atomicAdd(&wcnt[wave][run_d], run_n);
         }
         __syncthreads();
         {
