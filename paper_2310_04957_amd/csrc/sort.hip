@@ -245,17 +245,28 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* kin, const u
             }
         }
         __syncthreads();
+        // the slice's keys and values, all requested before the first is used
+        uint32_t kk[slice / 64], vv[slice / 64];
+#pragma unroll
         for (int it = 0; it < slice / 64; ++it) {
             const long long p = s0 + it * 64 + lane;
             const bool valid = p < n;
-            const uint32_t key = valid ? kin[p] : 0u;
+            kk[it] = valid ? kin[p] : 0u;
+            // the first pass's values are the slots
+            vv[it] = vin ? (valid ? vin[p] : 0u) : (uint32_t)p;
+        }
+#pragma unroll
+        for (int it = 0; it < slice / 64; ++it) {
+            const long long p = s0 + it * 64 + lane;
+            const bool valid = p < n;
+            const uint32_t key = kk[it];
             const uint32_t d = (key >> shift) & 0xFFu;
             const unsigned long long peers = digit_peers(valid, d);
             const int rank = __popcll(peers & lanemask_lt_s());
             if (valid) {
                 const unsigned int pos = wbase[wave][d] + rank;
                 kout[pos] = key;
-                vout[pos] = vin ? vin[p] : (uint32_t)p;   // the first pass's values are the slots
+                vout[pos] = vv[it];
             }
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
