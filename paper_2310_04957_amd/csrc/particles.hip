@@ -275,6 +275,15 @@ __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4)))
             vac = __syncthreads_and(cells_ok) != 0;
         }
 
+        // Cell-index range (in units of cells, FP32) whose positions are
+        // certainly inside the domain and whose cell, computed exactly, is
+        // certainly inside the window: one cell of margin on every side,
+        // far above the FP32 error of r / dr.  In a vacuum window a
+        // corrected position in this range is not absorbed, without the
+        // exact location.
+        const float fxlo = (float)(wi0 + 1), fxhi = (float)min(wi0 + kWin - 2, g.nr - 1);
+        const float fylo = (float)max(wj0 + 1, 1), fyhi = (float)min(wj0 + kWin - 2, g.nz - 1);
+
         const long long sbase = base + (long long)wave * kSlice;
         const long long stage_row = chunk * kPushWaves + wave;
         int qn = 0, nb = 0;
@@ -349,8 +358,13 @@ __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4)))
                     e_combine(ew, a.E[n00], a.E[n00 + 1], a.E[n00 + g.w], a.E[n00 + g.w + 1], Er, Ez);
                 }
                 d1_correct(s, Er, Ez, a.qm, a.dt);
-                const Loc L = locate(s.r, s.z, g);
-                if (absorb<kWin>(g, L, s.w, a.sign, s_abs, a.wallq, vac, wi0, wj0, s_ck)) {
+                const float cx = s.r * g.inv_dr, cy = s.z * g.inv_dz;
+                bool gone = false;
+                if (!(vac && cx >= fxlo && cx < fxhi && cy >= fylo && cy < fyhi)) {
+                    const Loc L = locate(s.r, s.z, g);
+                    gone = absorb<kWin>(g, L, s.w, a.sign, s_abs, a.wallq, vac, wi0, wj0, s_ck);
+                }
+                if (gone) {
                     s.r = -1.0f;
                 } else {
                     coll = dword < a.m.thresh;
