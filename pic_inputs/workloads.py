@@ -122,7 +122,7 @@ WORKLOADS = {
         gas=dict(p_Pa=10 * MTORR_PA, T_K=300.0),
         run=dict(n_e=4_000_000, n_i=4_000_000, cap_e=6_000_000, cap_i=6_000_000,
                  n0=1e14, Te_eV=30000 * KB_OVER_E, Ti_eV=300 * KB_OVER_E,
-                 steps_per_period=400, seed=1, sort_every=5, sort_every_ion=50, steps=8000),
+                 steps_per_period=400, seed=1, sort_every=4, sort_every_ion=20, steps=8000),
         solver=dict(method=SOLVE_MGPCG_FP64, tol=1e-8, max_iter=200),
     ),
     # Precision study, 512x1024, 64M + 64M (one sweep point: 20 mTorr, 150 V).
@@ -132,7 +132,7 @@ WORKLOADS = {
         gas=dict(p_Pa=20 * MTORR_PA, T_K=300.0),
         run=dict(n_e=64_000_000, n_i=64_000_000, cap_e=80_000_000, cap_i=80_000_000,
                  n0=1e14, Te_eV=30000 * KB_OVER_E, Ti_eV=300 * KB_OVER_E,
-                 steps_per_period=400, seed=1, sort_every=5, sort_every_ion=50, steps=1600),
+                 steps_per_period=400, seed=1, sort_every=4, sort_every_ion=20, steps=1600),
         solver=dict(method=SOLVE_IR_MG, tol=1e-8, max_iter=200),
     ),
     # Full scale, 1024x2048, 200M + 200M, 300 V with the matching network.
@@ -142,7 +142,7 @@ WORKLOADS = {
         gas=dict(p_Pa=10 * MTORR_PA, T_K=300.0),
         run=dict(n_e=200_000_000, n_i=200_000_000, cap_e=240_000_000, cap_i=240_000_000,
                  n0=1e14, Te_eV=30000 * KB_OVER_E, Ti_eV=300 * KB_OVER_E,
-                 steps_per_period=400, seed=1, sort_every=5, sort_every_ion=50, steps=20000),
+                 steps_per_period=400, seed=1, sort_every=4, sort_every_ion=20, steps=20000),
         solver=dict(method=SOLVE_IR_MG, tol=1e-8, max_iter=200),
     ),
 }
