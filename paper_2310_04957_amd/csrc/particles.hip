@@ -165,16 +165,17 @@ __device__ __forceinline__ void store_slot(float* const* f, uint32_t p, const P9
 }
 
 // One time step for every particle of one species.  A block of eight
-// wavefronts owns whole chunks of 8192 consecutive slots and each of its
+// wavefronts owns one chunk of 8192 consecutive slots and each of its
 // wavefronts a contiguous slice of 1024 of them, processed 64 at a time
-// with the next 64 already in flight.  Colliding
-// particles are compacted by wavefront ballots into a per-wavefront LDS
-// queue and processed 64 at a time by full wavefronts; births are staged
-// per slice in slot order.  A window (the tile of the chunk's first
-// particle plus halo) lives in LDS: E at its nodes, the radial factors of
-// its columns and the kinds of its cells are read there, and the deposit
-// goes there, flushed when the window moves.  So the only global traffic
-// of a particle inside the window is its own state.
+// with the next 64 already in flight; every live slot is stored once per
+// round.  Colliding particles are compacted by wavefront ballots into a
+// per-wavefront LDS queue of slots (the corrected state waits in the slot)
+// and processed 64 at a time, or at the end of the slice; births are
+// staged per slice in slot order.  A window (the tile of a particle from
+// the middle of the chunk plus halo) lives in LDS: E at its nodes, the
+// radial factors of its columns and the kinds of its cells are read there,
+// and the deposit goes there, flushed at the end.  So the only global
+// traffic of a particle inside the window is its own state.
 template <int kHalo, bool kMoved>
 __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_particles(PushArgs a) {
     constexpr int kWin = win_nodes(kHalo);
