@@ -84,15 +84,17 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16* __restrict__ X, con
     const int tx = (W + 15) / 16, ty = (H + 15) / 16;
     const long long ntile = (long long)tx * ty * B;
     TileRegs<CIN> next;
-    if ((long long)blockIdx.x < ntile) {
-        const long long tile = blockIdx.x;
-        const int b = (int)(tile / (tx * ty)), rem = (int)(tile % (tx * ty));
-        load_tile<CIN, MASK>(X, M, b, (rem / tx) * 16, (rem % tx) * 16, H, W, tid, next);
+    // tile indices fit in 32 bits (images of at most 2^31 16x16 tiles)
+    const unsigned txy = (unsigned)(tx * ty), utx = (unsigned)tx, nti = (unsigned)ntile;
+    if (blockIdx.x < nti) {
+        const unsigned tile = blockIdx.x;
+        const int b = (int)(tile / txy), rem = (int)(tile % txy);
+        load_tile<CIN, MASK>(X, M, b, (int)(rem / utx) * 16, (int)(rem % utx) * 16, H, W, tid, next);
     }
-    for (long long tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
-        const int b = (int)(tile / (tx * ty));
-        const int rem = (int)(tile % (tx * ty));
-        const int y0 = (rem / tx) * 16, x0 = (rem % tx) * 16;
+    for (unsigned tile = blockIdx.x; tile < nti; tile += gridDim.x) {
+        const int b = (int)(tile / txy);
+        const unsigned rem = tile % txy;
+        const int y0 = (int)(rem / utx) * 16, x0 = (int)(rem % utx) * 16;
         __syncthreads();   // the previous tile's MFMAs are done with xs
 #pragma unroll
         for (int q = 0; q < TileRegs<CIN>::kChunks; ++q) {
@@ -103,10 +105,11 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16* __restrict__ X, con
             }
         }
         __syncthreads();
-        const long long nt2 = tile + gridDim.x;
-        if (nt2 < ntile) {
-            const int b2 = (int)(nt2 / (tx * ty)), rem2 = (int)(nt2 % (tx * ty));
-            load_tile<CIN, MASK>(X, M, b2, (rem2 / tx) * 16, (rem2 % tx) * 16, H, W, tid, next);
+        const unsigned nt2 = tile + gridDim.x;
+        if (nt2 < nti) {
+            const int b2 = (int)(nt2 / txy);
+            const unsigned rem2 = nt2 % txy;
+            load_tile<CIN, MASK>(X, M, b2, (int)(rem2 / utx) * 16, (int)(rem2 % utx) * 16, H, W, tid, next);
         }
         f32x16 acc[2][NT];
         for (int s = 0; s < 2; ++s)
