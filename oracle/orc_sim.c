@@ -6,6 +6,7 @@
  * points used by the Python tests.
  */
 #include "orc_internal.h"
+#include <stdio.h>
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -342,8 +343,12 @@ int orc_stable_perm(int64_t n, const uint32_t* keys, int64_t* perm) {
 static void sort_species(orc_sim* s, int sp) {
     o_parts* P = &s->p[sp];
     int64_t n = P->n;
-    uint32_t* keys = malloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
+    uint32_t* keys = calloc((size_t)(n > 0 ? n : 1), sizeof(uint32_t));
     int64_t* perm = malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    if (!keys || !perm) {
+        fprintf(stderr, "oracle: out of memory in the tile sort\n");
+        abort();
+    }
     for (int64_t k = 0; k < n; k++) keys[k] = tile_key(s, P->r[k], P->z[k]);
     orc_stable_perm(n, keys, perm);
     o_parts Q;
