@@ -158,6 +158,49 @@ def test_loader_matches_oracle_load():
     g.close()
 
 
+def test_step_applying_a_sort_equals_sort_then_step():
+    """A deferred sort is applied by the next particle step, which reads each
+    new slot through the permutation; births of that step are appended in
+    parent-slot order.  Bit for bit the same as sorting at once and stepping
+    (every particle array, deposits, counters), with ionising electrons so
+    that births occur."""
+    w = workload("pp32x24", run=dict(n_e=0, n_i=0, cap_e=60000, cap_i=60000, sort_every=1, sort_every_ion=1))
+    w["solver"]["tol"] = 1e-12
+    gm = w["geometry"]
+    pe = random_particles(30000, gm["R"] * 0.98, gm["Z"], seed=51, vmax=6e6, amax=1e13, wmin=1.0, wmax=1.0,
+                          z_lo=0.002, z_hi=0.023, dead_frac=0.05)
+    pi = random_particles(30000, gm["R"] * 0.98, gm["Z"], seed=52, vmax=3e3, amax=1e9, wmin=1.0, wmax=1.0,
+                          z_lo=0.002, z_hi=0.023, dead_frac=0.05)
+    wb = workload("pp32x24", run=dict(w["run"], sort_every=0, sort_every_ion=0))
+    wb["solver"]["tol"] = 1e-12
+    ga = _pic(w, load=False)
+    gb = _pic(wb, load=False)
+    for g in (ga, gb):
+        g.set_particles(0, pe)
+        g.set_particles(1, pi)
+        g.redeposit()
+    ga.step(1)            # sorts both species at the end (applied by the next step)
+    gb.step(1)
+    gb.sort_now(0)
+    gb.sort_now(1)
+    ga.step(1)            # applies the sort; sorts again at the end
+    gb.step(1)
+    gb.sort_now(0)
+    gb.sort_now(1)
+    da, db = ga.diag(), gb.diag()
+    assert da.error == 0 and db.error == 0
+    assert da.born == db.born and da.born > 50
+    for sp in (0, 1):
+        a, b = ga.particles(sp), gb.particles(sp)
+        assert len(a["r"]) == len(b["r"])
+        for f in a:
+            assert np.array_equal(a[f].view(np.uint32), b[f].view(np.uint32)), (sp, f)
+    for name in ("DEP_E", "DEP_I", "WALLQ", "PHI"):
+        assert np.array_equal(ga.grid(name), gb.grid(name)), name
+    assert [list(x) for x in da.absorbed] == [list(x) for x in db.absorbed]
+    ga.close(); gb.close()
+
+
 @pytest.mark.parametrize("gas_factor,vmax_e", [(1, 6e5), (10, 6e5), (40, 6e5), (1, 6e6)])
 def test_one_step_matches_oracle_given_identical_state(gas_factor, vmax_e):
     """gas_factor scales the pressure: at 10x (collision probability 0.57
