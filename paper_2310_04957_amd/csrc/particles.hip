@@ -1,6 +1,6 @@
 // particles.hip -- the per-step particle loop on gfx950: field gather, D1
-// implicit correction, absorption, null-collision MCC with wavefront-ballot
-// compaction of colliders, D1 prediction and the fixed-point charge /
+// implicit correction, absorption, null-collision MCC on the colliding
+// lanes, D1 prediction and the fixed-point charge /
 // susceptibility deposit through an LDS window flushed with 64-bit integer
 // atomics (arXiv 2310.04957, Sec. 2: implicit push around Eq. 1, unequal
 // weights, collision paragraph).  Births are appended in parent order.
@@ -16,7 +16,6 @@ namespace pic {
 constexpr int win_nodes(int halo) { return kTile + 2 * halo + 1; }
 constexpr int kRounds = kSlice / 64;
 static_assert(kSlice % 256 == 0 && kRounds % 4 == 0, "decision words are shared by four aligned rounds");
-constexpr int kQW = 128;                      // deferred colliders per wavefront
 
 struct PushArgs {
     Geo g;
@@ -142,11 +141,6 @@ __device__ __forceinline__ void store8(float* const* f, uint32_t p, const P9& s)
     stf(f[5], o, s.ar); stf(f[6], o, s.at); stf(f[7], o, s.az);
 }
 
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
-
 // slot p of this step: in place, or through the permutation of a deferred
 // sort.  Unconditional (no branch, so the loads stay where they are
 // issued): a slot beyond the last, n - 1, is read in its place and the
@@ -168,10 +162,10 @@ __device__ __forceinline__ void store_slot(float* const* f, uint32_t p, const P9
 // wavefronts owns one chunk of 8192 consecutive slots and each of its
 // wavefronts a contiguous slice of 1024 of them, processed 64 at a time
 // with the next 64 already in flight; every live slot is stored once per
-// round.  Colliding particles are compacted by wavefront ballots into a
-// per-wavefront LDS queue of slots (the corrected state waits in the slot)
-// and processed 64 at a time, or at the end of the slice; births are
-// staged per slice in slot order.  A window (the tile of a particle from
+// round.  A colliding particle scatters in its own round, on its lane
+// alone (about one lane in thirty collides per step, and the kernel waits
+// on memory far more than on arithmetic), then is predicted and deposited
+// with the others; births are staged per slice in slot order.  A window (the tile of a particle from
 // the middle of the chunk plus halo) lives in LDS: E at its nodes, the
 // radial factors of its columns and the kinds of its cells are read there,
 // and the deposit goes there, flushed at the end.  So the only global
@@ -183,7 +177,6 @@ __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4)))
     __shared__ float2 ewin[kWin * kWin];
     __shared__ double s_invd[kWin];
     __shared__ uint8_t s_ck[(kWin - 1) * (kWin - 1)];
-    __shared__ unsigned int qslot[kPushWaves][kQW];
     __shared__ int s_org[2];
     __shared__ unsigned long long s_abs[kSlots];
     __shared__ unsigned int s_coll[4];
@@ -287,48 +280,8 @@ __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4)))
 
         const long long sbase = base + (long long)wave * kSlice;
         const long long stage_row = chunk * kPushWaves + wave;
-        int qn = 0, nb = 0;
-        unsigned int* ql = qslot[wave];
+        int nb = 0;
         P9 cur = load_slot<kMoved>(f, a.src, a.perm, sbase + lane, n);
-
-        auto run_queue = [&](int cnt) {
-            // lanes < cnt each take one deferred collider, in queue (slot) order;
-            // its corrected state was stored to its slot when it was queued
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-            const bool has = lane < cnt;
-            int proc = -1;
-            float b6[6];
-            P9 c;
-            unsigned int slot = 0;
-            if (has) {
-                slot = ql[lane];
-                c = load9(f, slot);
-                const uint4 x = draw(slot, a.step, kPurposeMcc, a.sp, 0, a.key0, a.key1);
-                proc = collide(a.sp, x, c.vr, c.vt, c.vz, a.m, slot, a.step, a.key0, a.key1, b6, &a.ctr->viol);
-                atomicAdd(&s_coll[proc], 1u);
-            }
-            const bool born = has && proc == 2 && a.stage != nullptr;
-            const unsigned long long bm = __ballot(born);
-            if (born) {
-                const int idx = nb + __popcll(bm & lanemask_lt());
-                if (idx < kStageW) {
-                    Birth bb;
-                    bb.r = c.r; bb.z = c.z; bb.w = c.w;
-                    for (int k = 0; k < 6; ++k) bb.v[k] = b6[k];
-                    a.stage[stage_row * kStageW + idx] = bb;
-                } else {
-                    atomicMax(&a.ctr->err, 2);
-                }
-            }
-            nb += __popcll(bm);
-            if (has) {
-                d1_predict(c, a.dt);
-                const Loc L2 = locate(c.r, c.z, g);
-                if (absorb<kWin>(g, L2, c.w, a.sign, s_abs, a.wallq, vac, wi0, wj0, s_ck)) c.r = -1.0f;
-                else fallback += deposit<kWin>(g, L2, c.w, win, s_invd, wi0, wj0, a.dep);
-                store_slot(f, slot, c, moved);
-            }
-        };
 
         uint4 dec4 = make_uint4(0u, 0u, 0u, 0u);
         for (int it = 0; it < kRounds; ++it) {
@@ -342,7 +295,8 @@ __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4)))
             if ((it & 3) == 0) dec4 = draw(decision_ctr((uint32_t)p), a.step, kPurposeDecide, a.sp, 0, a.key0, a.key1);
             const uint32_t dword = (it & 3) == 0 ? dec4.x : (it & 3) == 1 ? dec4.y : (it & 3) == 2 ? dec4.z : dec4.w;
             P9 s = cur;
-            bool coll = false;
+            bool born = false;
+            float b6[6], br = 0.0f, bz = 0.0f;
             const bool live = p < n && s.r >= 0.0f;
             if (live) {
                 float Er, Ez;
@@ -368,45 +322,46 @@ __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4)))
                 if (gone) {
                     s.r = -1.0f;
                 } else {
-                    coll = dword < a.m.thresh;
-                    if (!coll) {
-                        d1_predict(s, a.dt);
-                        const Loc L2 = locate(s.r, s.z, g);
-                        if (absorb<kWin>(g, L2, s.w, a.sign, s_abs, a.wallq, vac, wi0, wj0, s_ck)) {
-                            s.r = -1.0f;
-                        } else {
-                            fallback += deposit<kWin>(g, L2, s.w, win, s_invd, wi0, wj0, a.dep);
-                        }
+                    // a collider scatters at its corrected position (only
+                    // these lanes run the collision), then moves on with
+                    // the others
+                    if (dword < a.m.thresh) {
+                        const uint4 x = draw((uint32_t)p, a.step, kPurposeMcc, a.sp, 0, a.key0, a.key1);
+                        const int proc = collide(a.sp, x, s.vr, s.vt, s.vz, a.m, (uint32_t)p, a.step, a.key0, a.key1,
+                                                 b6, &a.ctr->viol);
+                        atomicAdd(&s_coll[proc], 1u);
+                        born = proc == 2 && a.stage != nullptr;
+                        br = s.r;
+                        bz = s.z;
+                    }
+                    d1_predict(s, a.dt);
+                    const Loc L2 = locate(s.r, s.z, g);
+                    if (absorb<kWin>(g, L2, s.w, a.sign, s_abs, a.wallq, vac, wi0, wj0, s_ck)) {
+                        s.r = -1.0f;
+                    } else {
+                        fallback += deposit<kWin>(g, L2, s.w, win, s_invd, wi0, wj0, a.dep);
                     }
                 }
             }
             // one store per round for every live slot: the predicted state,
-            // r = -1 for a removed particle, the corrected state for a
-            // collider (it waits there for the queue)
+            // or r = -1 for a removed particle
             if (live) store_slot(f, (uint32_t)p, s, moved);
-            // ballot compaction of this round's colliders into the queue
-            const unsigned long long m = __ballot(coll);
-            if (coll) {
-                const int q = qn + __popcll(m & lanemask_lt());
-                ql[q] = (unsigned int)p;
-            }
-            qn += __popcll(m);
-            wave_sync();
-            if (qn >= 64) {
-                run_queue(64);
-                wave_sync();
-                // move the remaining qn - 64 (< 64) entries to the front
-                const int rest = qn - 64;
-                if (lane < rest) {
-                    const unsigned int sl = ql[64 + lane];
-                    ql[lane] = sl;
+            // births of this round, staged in slot order
+            const unsigned long long bm = __ballot(born);
+            if (born) {
+                const int idx = nb + __popcll(bm & lanemask_lt());
+                if (idx < kStageW) {
+                    Birth bb;
+                    bb.r = br; bb.z = bz; bb.w = s.w;
+                    for (int k = 0; k < 6; ++k) bb.v[k] = b6[k];
+                    a.stage[stage_row * kStageW + idx] = bb;
+                } else {
+                    atomicMax(&a.ctr->err, 2);
                 }
-                qn = rest;
-                wave_sync();
             }
+            nb += __popcll(bm);
             cur = nxt;
         }
-        if (qn > 0) run_queue(qn);
         if (lane == 0 && a.stage_cnt != nullptr) a.stage_cnt[stage_row] = min(nb, kStageW);
         // s_org is rewritten by the next chunk's probe
         __syncthreads();
