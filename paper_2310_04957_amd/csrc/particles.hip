@@ -124,7 +124,7 @@ __device__ __forceinline__ float ldf(const float* base, uint32_t boff) {
     return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + boff);
 }
 __device__ __forceinline__ void stf(float* base, uint32_t boff, float v) {
-    *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + boff) = v;
+    __builtin_nontemporal_store(v, reinterpret_cast<float*>(reinterpret_cast<char*>(base) + boff));
 }
 
 __device__ __forceinline__ P9 load9(float* const* f, uint32_t p) {
