@@ -739,7 +739,10 @@ int pic_step(pic_handle* h, int32_t nsteps) {
         ev_record(h, 4, &b0);
         h->dep_cur = 1 - h->dep_cur;
         ev_record(h, -1, &b1);
-        launch_particles(h, 0);
+        // electrons write their sort keys when a sort ends this step (the
+        // key buffer is shared, so ions keep the key pass)
+        const bool se_next = c.run.sort_every > 0 && (h->step + 1) % c.run.sort_every == 0;
+        launch_particles(h, 0, se_next);
         ev_record(h, 0, &b1);
         ev_record(h, -1, &b1);
         launch_particles(h, 1);
@@ -755,7 +758,7 @@ int pic_step(pic_handle* h, int32_t nsteps) {
             ev_record(h, -1, &b3);
             // particle splitting runs at a species' tile sort, before it
             if (se && c.run.split) launch_split(h, 0);
-            if (se) launch_sort(h, 0, true);
+            if (se) launch_sort(h, 0, true, true);
             if (si && c.run.split) launch_split(h, 1);
             if (si) launch_sort(h, 1, true);
             ev_record(h, 3, &b3);

@@ -23,6 +23,9 @@ struct PushArgs {
     float* f[9];                 // particles written here (read here too unless perm is set)
     const float* src[9];         // with perm: slot p reads src at perm[p] (a deferred sort)
     const uint32_t* perm;
+    uint32_t* keys;              // non-null: write each slot's sort key (a sort follows this step)
+    uint32_t dead_key;
+    int ntr;
     const float2* E;
     unsigned long long* dep;
     unsigned long long* wallq;
@@ -170,7 +173,7 @@ __device__ __forceinline__ void store_slot(float* const* f, uint32_t p, const P9
 // radial factors of its columns and the kinds of its cells are read there,
 // and the deposit goes there, flushed at the end.  So the only global
 // traffic of a particle inside the window is its own state.
-template <int kHalo, bool kMoved>
+template <int kHalo, bool kMoved, bool kKeys>
 __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_particles(PushArgs a) {
     constexpr int kWin = win_nodes(kHalo);
     __shared__ unsigned long long win[kWin * kWin];
@@ -191,6 +194,7 @@ __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4)))
     float* const* f = a.f;
     constexpr bool moved = kMoved;
     unsigned int fallback = 0;
+    unsigned int ndead = 0;   // dead keys written (uniform in the wavefront)
 
     for (int k = tid; k < kWin * kWin; k += kPushBlock) win[k] = 0ull;
     if (tid < kSlots) s_abs[tid] = 0ull;
@@ -296,6 +300,7 @@ __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4)))
             const uint32_t dword = (it & 3) == 0 ? dec4.x : (it & 3) == 1 ? dec4.y : (it & 3) == 2 ? dec4.z : dec4.w;
             P9 s = cur;
             bool born = false;
+            uint32_t key = a.dead_key;
             float b6[6], br = 0.0f, bz = 0.0f;
             const bool live = p < n && s.r >= 0.0f;
             if (live) {
@@ -340,12 +345,19 @@ __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4)))
                         s.r = -1.0f;
                     } else {
                         fallback += deposit<kWin>(g, L2, s.w, win, s_invd, wi0, wj0, a.dep);
+                        key = tile_key(L2, a.ntr);
                     }
                 }
             }
             // one store per round for every live slot: the predicted state,
             // or r = -1 for a removed particle
             if (live) store_slot(f, (uint32_t)p, s, moved);
+            // the key of the tile sort that follows: the tile of the predicted
+            // position, or the dead key (as the key pass computes it)
+            if (kKeys) {
+                if (p < n) a.keys[p] = key;
+                ndead += __popcll(__ballot(p < n && key == a.dead_key));
+            }
             // births of this round, staged in slot order
             const unsigned long long bm = __ballot(born);
             if (born) {
@@ -373,6 +385,10 @@ __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4)))
     if (tid < kSlots && s_abs[tid]) atomicAdd(&a.ctr->absorbed[a.sp][tid], s_abs[tid]);
     if (tid < 4 && s_coll[tid]) atomicAdd(&a.ctr->coll[a.sp][tid], (unsigned long long)s_coll[tid]);
     if (tid == 0 && s_fallback) atomicAdd(&a.ctr->fallback, (unsigned long long)s_fallback);
+    if (kKeys) {
+        if (lane == 0 && ndead) atomicAdd(&a.ctr->dead[a.sp], ndead);
+        if (blockIdx.x == 0 && tid == 0) a.ctr->n_keyed[a.sp] = n;
+    }
 }
 
 // one block per chunk of the species' capacity (blocks past the last slot
@@ -413,7 +429,7 @@ static float qm_of(int sp) {
     return (float)(sp == 0 ? -QE / ME : QE / MAR);
 }
 
-void launch_particles(pic_handle* h, int sp) {
+void launch_particles(pic_handle* h, int sp, bool emit_keys) {
     PushArgs a;
     a.g = make_geo(h);
     a.m = make_mcc(h, sp);
@@ -438,12 +454,22 @@ void launch_particles(pic_handle* h, int sp) {
     a.key0 = (uint32_t)(h->cfg.run.seed & 0xFFFFFFFFu);
     a.key1 = (uint32_t)(h->cfg.run.seed >> 32);
     a.step = (uint32_t)(h->step + 1);
+    a.keys = emit_keys && sp == 0 ? h->keys[0] : nullptr;
+    a.dead_key = (uint32_t)h->ntiles;
+    a.ntr = h->ntr;
+    const dim3 grid(grid_blocks(h, sp)), block(kPushBlock);
     if (sp == 0) {
-        if (moved) hipLaunchKernelGGL((k_particles<24, true>), dim3(grid_blocks(h, sp)), dim3(kPushBlock), 0, h->stream, a);
-        else hipLaunchKernelGGL((k_particles<24, false>), dim3(grid_blocks(h, sp)), dim3(kPushBlock), 0, h->stream, a);
+        if (emit_keys) {
+            if (moved) hipLaunchKernelGGL((k_particles<24, true, true>), grid, block, 0, h->stream, a);
+            else hipLaunchKernelGGL((k_particles<24, false, true>), grid, block, 0, h->stream, a);
+        } else {
+            if (moved) hipLaunchKernelGGL((k_particles<24, true, false>), grid, block, 0, h->stream, a);
+            else hipLaunchKernelGGL((k_particles<24, false, false>), grid, block, 0, h->stream, a);
+        }
     } else {
-        if (moved) hipLaunchKernelGGL((k_particles<16, true>), dim3(grid_blocks(h, sp)), dim3(kPushBlock), 0, h->stream, a);
-        else hipLaunchKernelGGL((k_particles<16, false>), dim3(grid_blocks(h, sp)), dim3(kPushBlock), 0, h->stream, a);
+        // (ions never write keys: the key buffer is shared by the species)
+        if (moved) hipLaunchKernelGGL((k_particles<16, true, false>), grid, block, 0, h->stream, a);
+        else hipLaunchKernelGGL((k_particles<16, false, false>), grid, block, 0, h->stream, a);
     }
     if (moved) {
         h->cur[sp] = 1 - h->cur[sp];

@@ -52,7 +52,8 @@ struct DevCounters {
     unsigned int dead[2];
     long long split_total;        // copies of the current splitting pass (-1: they do not fit)
     long long split_added[2];     // copies since init, per species
-    long long pad[4];
+    long long n_keyed[2];         // slots whose sort keys the last particle step wrote
+    long long pad[2];
 };
 
 // FP64 scalars of the field solve and the circuit; device memory
@@ -186,13 +187,13 @@ void launch_load(pic_handle* h, int sp, const double* cdf, const int* cell, int 
                  float W, float vth);
 void launch_predict_deposit(pic_handle* h, int sp);
 void launch_redeposit(pic_handle* h);
-void launch_particles(pic_handle* h, int sp);
+void launch_particles(pic_handle* h, int sp, bool emit_keys = false);
 void launch_births(pic_handle* h);
 int launch_count_alive(pic_handle* h, long long* out2);
 void launch_moments(pic_handle* h, int sp, unsigned long long* N, unsigned long long* E);
 
 // sort
-void launch_sort(pic_handle* h, int sp, bool deferred = false);
+void launch_sort(pic_handle* h, int sp, bool deferred = false, bool keyed = false);
 void launch_split(pic_handle* h, int sp);
 void materialize(pic_handle* h, int sp);
 

@@ -4,7 +4,9 @@
 // digit-major order, and a stable scatter whose in-chunk ranks come from
 // wavefront ballots (no atomics decide an order, so the permutation is
 // deterministic).  The nine particle arrays are then gathered into the
-// second buffer.
+// second buffer.  Electron keys usually come from the particle step just
+// before (it locates every particle anyway); the key pass then covers only
+// the slots appended after it.
 #include <hip/hip_runtime.h>
 
 #include "pic_internal.h"
@@ -19,6 +21,7 @@ struct KeyArgs {
     const float* z;
     uint32_t* keys;
     const long long* n_slots;
+    const long long* start;   // non-null: keys below *start are already written
     unsigned int* dead;
     int sp, ntr;
     uint32_t dead_key;
@@ -26,8 +29,9 @@ struct KeyArgs {
 
 __global__ __launch_bounds__(kBlock) void k_keys(KeyArgs a) {
     const long long n = a.n_slots[a.sp];
+    const long long p0 = a.start ? *a.start : 0;
     unsigned int dead = 0;
-    for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < n;
+    for (long long p = p0 + blockIdx.x * (long long)blockDim.x + threadIdx.x; p < n;
          p += (long long)gridDim.x * blockDim.x) {
         float r = a.r[p];
         uint32_t key = a.dead_key;
@@ -303,12 +307,15 @@ __global__ void k_finish_sort(long long* n_slots, unsigned int* dead, int sp) {
 
 __global__ void k_zero_u32(unsigned int* p) { *p = 0u; }
 
-void launch_sort(pic_handle* h, int sp, bool deferred) {
+// keyed: the particle step just before wrote the keys of its slots and
+// counted their dead ones (no sort is pending then); the key pass covers
+// the slots appended since (births, split copies)
+void launch_sort(pic_handle* h, int sp, bool deferred, bool keyed) {
     hipStream_t st = h->stream;
     materialize(h, sp);   // a sort reads the particles as they stand
     const long long* ns = (const long long*)h->ctr->n_slots;
     unsigned int* dead = &h->ctr->dead[0];
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, dead + sp);
+    if (!keyed) hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, dead + sp);
     Species& S = h->buf[sp][h->cur[sp]];
     KeyArgs ka;
     ka.g.nr = h->nr; ka.g.nz = h->nz; ka.g.w = h->w;
@@ -319,6 +326,7 @@ void launch_sort(pic_handle* h, int sp, bool deferred) {
     ka.r = S.f[0]; ka.z = S.f[1];
     ka.keys = h->keys[0];
     ka.n_slots = ns; ka.dead = dead + sp; ka.sp = sp; ka.ntr = h->ntr;
+    ka.start = keyed ? (const long long*)&h->ctr->n_keyed[sp] : nullptr;
     ka.dead_key = (uint32_t)h->ntiles;   // one bucket past the last tile: sorts last
     hipLaunchKernelGGL(k_keys, dim3(2048), dim3(kBlock), 0, st, ka);
     int src = 0;
