@@ -269,7 +269,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* kin, const u
             const int rank = __popcll(peers & lanemask_lt_s());
             if (valid) {
                 const unsigned int pos = wbase[wave][d] + rank;
-                kout[pos] = key;
+                if (kout != nullptr) kout[pos] = key;   // (the last pass keeps no keys)
                 vout[pos] = vv[it];
             }
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -338,7 +338,7 @@ void launch_sort(pic_handle* h, int sp, bool deferred, bool keyed) {
         hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, h->bsum, ns, sp);
         hipLaunchKernelGGL(k_scan_down, dim3(2048), dim3(kBlock), 0, st, h->hist, h->bsum, ns, sp);
         hipLaunchKernelGGL(k_scatter, dim3(2048), dim3(kBlock), 0, st, h->keys[src], shift == 0 ? nullptr : h->idx[src],
-                           h->keys[1 - src],
+                           last ? nullptr : h->keys[1 - src],
                            last ? h->perm[sp] : h->idx[1 - src], h->hist, ns, sp, shift);
         src = 1 - src;
     }
