@@ -25,7 +25,7 @@ HBM_PEAK_GBS = 8000.0
 # and WRITE_SIZE (scaled by a plain-copy calibration) on gec1024x2048; see
 # profiles/k_particles_gec1024x2048.md.  Set to None whenever the kernel
 # changes until it is measured again.
-MEASURED_BYTES_PER_PARTICLE_STEP = {"gec1024x2048": (19.0e9 + 15.5e9) / 393.6e6}
+MEASURED_BYTES_PER_PARTICLE_STEP = {"gec1024x2048": (14.30e9 + 13.96e9) / 393.6e6}
 
 
 def cpu_baseline(name, sample_particles, steps):
