@@ -201,6 +201,46 @@ def test_step_applying_a_sort_equals_sort_then_step():
     ga.close(); gb.close()
 
 
+def test_sort_keyed_by_the_step_orders_births_and_split_copies():
+    """The electron keys of a sort that ends a step come from that step's
+    particle kernel; the slots appended after it (births, then split copies)
+    get theirs from the key pass.  After such a sort, with ionising electrons
+    and splitting on: every slot below the count holds a live particle, the
+    tile keys (the oracle's) do not decrease, and the live count and total
+    weight are those before the sort plus the copies."""
+    from fractions import Fraction
+    w = workload("pp32x24", run=dict(n_e=0, n_i=0, cap_e=120000, cap_i=60000, sort_every=1, sort_every_ion=0,
+                                     split=1))
+    gm = w["geometry"]
+    pe = random_particles(30000, gm["R"] * 0.98, gm["Z"], seed=61, vmax=6e6, amax=1e13, wmin=1.0, wmax=3.0,
+                          z_lo=0.002, z_hi=0.023, dead_frac=0.05)
+    pi = random_particles(30000, gm["R"] * 0.98, gm["Z"], seed=62, vmax=3e3, amax=1e9, wmin=1.0, wmax=1.0,
+                          z_lo=0.002, z_hi=0.023, dead_frac=0.05)
+    wb = workload("pp32x24", run=dict(w["run"], sort_every=0, split=0))
+    ga, gb = _pic(w, load=False), _pic(wb, load=False)
+    for g in (ga, gb):
+        g.set_particles(0, pe)
+        g.set_particles(1, pi)
+        g.redeposit()
+    ga.step(1)
+    gb.step(1)
+    da, db = ga.diag(), gb.diag()
+    assert da.error == 0 and db.error == 0
+    assert da.born == db.born and da.born > 50
+    assert da.split_added[0] > 0
+    o = O.Oracle(w, load=False)
+    a, b = ga.particles(0), gb.particles(0)
+    assert np.all(a["r"] >= 0), "a dead slot below the count after the sort"
+    live_b = b["r"] >= 0
+    assert len(a["r"]) == int(live_b.sum()) + da.split_added[0]
+    keys = o.tile_keys(a["r"].astype(np.float64), a["z"].astype(np.float64))
+    assert np.all(np.diff(keys.astype(np.int64)) >= 0), "tile keys decrease"
+    sa = sum(Fraction(float(x)) for x in a["w"])
+    sb = sum(Fraction(float(x)) for x in b["w"][live_b])
+    assert sa == sb
+    ga.close(); gb.close()
+
+
 @pytest.mark.parametrize("gas_factor,vmax_e", [(1, 6e5), (10, 6e5), (40, 6e5), (1, 6e6)])
 def test_one_step_matches_oracle_given_identical_state(gas_factor, vmax_e):
     """gas_factor scales the pressure: at 10x (collision probability 0.57
