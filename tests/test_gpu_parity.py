@@ -244,10 +244,9 @@ def test_sort_keyed_by_the_step_orders_births_and_split_copies():
 @pytest.mark.parametrize("gas_factor,vmax_e", [(1, 6e5), (10, 6e5), (40, 6e5), (1, 6e6)])
 def test_one_step_matches_oracle_given_identical_state(gas_factor, vmax_e):
     """gas_factor scales the pressure: at 10x (collision probability 0.57
-    for electrons) and 40x (0.97) most rounds of 64 particles hold more
-    colliders than the kernel's per-wavefront collider queue.  Electrons up
-    to 6e6 m/s (about 100 eV) ionise: the births are appended in parent
-    order and compared slot by slot."""
+    for electrons) and 40x (0.97) most lanes of a round of 64 particles
+    collide.  Electrons up to 6e6 m/s (about 100 eV) ionise: the births are
+    appended in parent order and compared slot by slot."""
     w = workload("pp32x24", run=dict(n_e=0, n_i=0, cap_e=40000, cap_i=40000, sort_every=0))
     w["gas"]["p_Pa"] *= gas_factor
     w["solver"]["tol"] = 1e-12
