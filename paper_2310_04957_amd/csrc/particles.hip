@@ -626,18 +626,28 @@ __global__ __launch_bounds__(kSegRows) void k_birth_append(BirthArgs a) {
             sh[threadIdx.x] += t;
             __syncthreads();
         }
-        const long long o = (long long)a.segoff[b] + sh[threadIdx.x] - cnt;
-        __syncthreads();
-        for (int k = 0; k < cnt; ++k) {
-            const Birth bb = a.stage[row * kStageW + k];
+        // the segment's births, spread over the block: birth idx (in row
+        // order) belongs to the first row whose inclusive count exceeds idx
+        // and goes to slot base + segoff + idx
+        const int total = sh[kSegRows - 1];
+        const long long o0 = (long long)a.segoff[b];
+        for (int idx = threadIdx.x; idx < total; idx += kSegRows) {
+            int lo = 0, hi = kSegRows - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (sh[mid] > idx) hi = mid; else lo = mid + 1;
+            }
+            const int k = idx - (lo > 0 ? sh[lo - 1] : 0);
+            const Birth bb = a.stage[(b * kSegRows + lo) * kStageW + k];
             P9 e;
             e.r = bb.r; e.z = bb.z; e.vr = bb.v[0]; e.vt = bb.v[1]; e.vz = bb.v[2];
             e.ar = 0.0f; e.at = 0.0f; e.az = 0.0f; e.w = bb.w;
-            place_newborn(a.g, a.fe, be + o + k, e, a.dt, 0, a.dep_e, a.wallq, a.ctr);
+            place_newborn(a.g, a.fe, be + o0 + idx, e, a.dt, 0, a.dep_e, a.wallq, a.ctr);
             P9 i = e;
             i.vr = bb.v[3]; i.vt = bb.v[4]; i.vz = bb.v[5];
-            place_newborn(a.g, a.fi, bi + o + k, i, a.dt, 1, a.dep_i, a.wallq, a.ctr);
+            place_newborn(a.g, a.fi, bi + o0 + idx, i, a.dt, 1, a.dep_i, a.wallq, a.ctr);
         }
+        __syncthreads();   // sh is rewritten by the next segment
     }
 }
 
