@@ -40,7 +40,10 @@ extern "C" {
 enum {
     PIC_OK = 0,
     PIC_E_CONFIG = -1,    /* invalid configuration (sizes, regions, circuit values) */
-    PIC_E_CAPACITY = -2,  /* births exceeded a species capacity; the births of that step were dropped */
+    PIC_E_CAPACITY = -2,  /* births exceeded a species capacity (or a slice's staging row): the births
+                             that did not fit were dropped in that step, pic_step returns this code at
+                             the next step, before moving any particle, and refuses every later call;
+                             a splitting pass that does not fit changes nothing and reports it too */
     PIC_E_SOLVER = -3,    /* field solve did not reach the tolerance within max_iter */
     PIC_E_HIP = -4,       /* a HIP runtime call failed */
     PIC_E_NONFINITE = -5, /* a non-finite value reached the field solve */
@@ -265,6 +268,20 @@ int pic_solve_once(pic_handle* h, const double* Q, const double* chi, double U_E
 /* The same with driven electrode e at U[e - 1], e = 1 .. n_el (host array). */
 int pic_solve_once_el(pic_handle* h, const double* Q, const double* chi, const double* U, double tol,
                       double* phi_inout, int32_t* iters, double* relres);
+
+/* Matching design (Sec. 3, first paragraph: the vacuum equivalent
+   capacitance gives the L-network's elements for a perfect match).  For
+   electrode 1's circuit II (PIC_LMATCH): the shunt C_m1 and series C_m2
+   for which the network, with its R_m and L_m, presents exactly R_s to the
+   source when loaded by the current C_eq in parallel with the stray branch
+   R_stray, L_stray, C_stray (Eq. 10).  Called right after pic_init, C_eq is
+   the vacuum one, as in the paper.  out2 (host, 2 doubles) receives C_m1
+   and C_m2 in farads; apply = 1 also makes them the circuit's elements for
+   the following steps (the circuit state is kept).  Synchronises the
+   stream.  PIC_E_CONFIG when the circuit is not PIC_LMATCH or no such
+   network exists (R_m + Re Z_load >= R_s, or a series reactance above
+   w L_m would be needed); nothing changes then. */
+int pic_match_design(pic_handle* h, int32_t apply, double* out2);
 
 /* Set t, Q_E, U_E, circ[5], C_eq (9 doubles) -- for single-step parity. */
 int pic_set_state(pic_handle* h, const double* st9);

@@ -113,6 +113,10 @@ def lib():
         L.orc_get_phiL.argtypes = [P, C.c_int32, P]
         L.orc_split_target.argtypes = [P, C.c_int32, C.c_int32]
         L.orc_split_target.restype = C.c_double
+        L.orc_match_design.argtypes = [C.POINTER(Config), C.c_double, P]
+        L.orc_assemble_now.argtypes = [P]
+        L.orc_efield_now.argtypes = [P]
+        L.orc_gather.argtypes = [P, C.c_int64, P, P, P, P]
         _lib = L
     return _lib
 
@@ -232,6 +236,23 @@ class Oracle:
     def set_state(self, t, Q_E, U_E, circ, C_eq):
         st = np.array([t, Q_E, U_E] + list(circ) + [C_eq], dtype=np.float64)
         lib().orc_set_state(self.h, _ptr(st))
+
+    def assemble_now(self):
+        """CHI and Q grids from the deposit grids as they stand (Eq. 1)."""
+        lib().orc_assemble_now(self.h)
+
+    def efield_now(self):
+        """ER and EZ grids from the PHI grid as it stands (reading R9)."""
+        lib().orc_efield_now(self.h)
+
+    def gather(self, r, z):
+        """(E_r, E_z) the particle step gathers at the given positions."""
+        r = np.ascontiguousarray(r, dtype=np.float64)
+        z = np.ascontiguousarray(z, dtype=np.float64)
+        Er = np.zeros(len(r))
+        Ez = np.zeros(len(r))
+        lib().orc_gather(self.h, len(r), _ptr(r), _ptr(z), _ptr(Er), _ptr(Ez))
+        return Er, Ez
 
     def solve_q(self, Q, chi, U_E, tol=1e-12, phi0=None):
         Q = np.ascontiguousarray(Q, dtype=np.float64)
@@ -373,6 +394,16 @@ def reflection(Z_load, R_s, P_source, P_Rs):
     out = np.zeros(3)
     lib().orc_reflection(Z_load.real, Z_load.imag, R_s, P_source, P_Rs, _ptr(out))
     return tuple(float(v) for v in out)
+
+
+def match_design(w, C_eq):
+    """(C_m1, C_m2) of the workload's L-network matching the load C_eq (Sec. 3)."""
+    cfg = make_config(w, load=False)
+    out = np.zeros(2)
+    rc = lib().orc_match_design(C.byref(cfg), C_eq, _ptr(out))
+    if rc != 0:
+        raise ValueError("no matching network for this load")
+    return float(out[0]), float(out[1])
 
 
 def circuit_vacuum(w, C_eq, nsteps, chars=False):

@@ -136,6 +136,9 @@ int orc_get_phiL(orc_sim* s, int32_t e, double* out);
 double orc_split_target(orc_sim* s, int32_t species, int32_t i);
 
 /* pure pieces, for pins */
+int orc_assemble_now(orc_sim* s);        /* CHI and Q grids from the deposits as they stand */
+int orc_efield_now(orc_sim* s);          /* ER and EZ grids from the PHI grid as it stands */
+int orc_gather(orc_sim* s, int64_t n, const double* r, const double* z, double* Er, double* Ez);
 int orc_solve_q(orc_sim* s, const double* Q, const double* chi, double U_E, double tol,
                 double* phi_inout, int32_t* iters, double* relres);
 double orc_refresh_laplace(orc_sim* s); /* recompute phi_L and C_eq with the current chi */
@@ -157,6 +160,11 @@ void orc_xsec_e(double eps_eV, double out3[3]);
 /* |Gamma| (Eq. 12), forward and reflected power (Eq. 14) of a load Z_load
    against R_s: out3 = |Gamma|, P_forward, P_ref */
 void orc_reflection(double z_re, double z_im, double R_s, double P_source, double P_Rs, double* out3);
+
+/* matching design (Sec. 3): C_m1, C_m2 of the L-network of cfg (its R_s,
+   R_m, L_m and stray branch) that match a load C_eq perfectly; out2 =
+   C_m1, C_m2.  -1 when no such network exists. */
+int orc_match_design(const orc_config* cfg, double C_eq, double* out2);
 
 /* the circuit alone with a fixed C_eq and no plasma; chars (or NULL): the
    electrical characterisation of the last period, as orc_diag.elec */

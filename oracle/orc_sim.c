@@ -740,6 +740,38 @@ void orc_reflection(double z_re, double z_im, double R_s, double P_source, doubl
     out3[2] = out3[1] * gam * gam;
 }
 
+/* Matching design from the equivalent capacitance (Sec. 3, first
+   paragraph: the vacuum C_eq gives the L-network's C_m1 and C_m2 for a
+   perfect match).  Load: C_eq in parallel with the stray branch
+   R_stray + j w L_stray + 1/(j w C_stray) (Eq. 10).  The network's input
+   admittance j w C_m1 + 1/Z_b, with Z_b = R_m + j w L_m + 1/(j w C_m2) +
+   Z_load = R_b + j X_b, equals 1/R_s when
+     R_b / (R_b^2 + X_b^2) = 1/R_s   and   w C_m1 = X_b / (R_b^2 + X_b^2),
+   i.e. X_b = +sqrt(R_b (R_s - R_b)) (C_m1 > 0), w C_m1 = X_b / (R_b R_s) and
+   1/(w C_m2) = w L_m + Im Z_load - X_b.  Returns -1 when no such network
+   exists (R_b >= R_s or a non-positive C_m2). */
+int orc_match_design(const orc_config* c, double C_eq, double* out2) {
+    double w = 2.0 * O_PI * c->freq;
+    /* Z_C = 1/(j w C_eq) = -j / (w C_eq) */
+    double zc_re = 0.0, zc_im = -1.0 / (w * C_eq);
+    double zs_re = c->R_stray, zs_im = w * c->L_stray - 1.0 / (w * c->C_stray);
+    /* parallel combination Z_C Z_s / (Z_C + Z_s) */
+    double num_re = zc_re * zs_re - zc_im * zs_im, num_im = zc_re * zs_im + zc_im * zs_re;
+    double den_re = zc_re + zs_re, den_im = zc_im + zs_im;
+    double dd = den_re * den_re + den_im * den_im;
+    double zl_re = (num_re * den_re + num_im * den_im) / dd;
+    double zl_im = (num_im * den_re - num_re * den_im) / dd;
+    double Rb = c->R_m + zl_re;
+    if (!(Rb > 0.0) || !(Rb < c->R_s)) return -1;
+    double Xb = sqrt(Rb * (c->R_s - Rb));
+    double Cm1 = Xb / (Rb * c->R_s) / w;
+    double xc2 = w * c->L_m + zl_im - Xb;
+    if (!(xc2 > 0.0)) return -1;
+    out2[0] = Cm1;
+    out2[1] = 1.0 / (w * xc2);
+    return 0;
+}
+
 int orc_split_now(orc_sim* s, int32_t sp, int64_t* added) {
     if (sp < 0 || sp > 1) return -1;
     return split_species(s, sp, added);
@@ -861,6 +893,8 @@ int orc_set_grid(orc_sim* s, int32_t which, const void* in) {
     case ORC_G_PHI: memcpy(s->phi, in, nn * 8); return 0;
     case ORC_G_WALLQ: memcpy(s->wallq, in, nn * 8); return 0;
     case ORC_G_PHI_L: memcpy(s->phiL[0], in, nn * 8); return 0;
+    case ORC_G_ER: memcpy(s->Er, in, nn * 8); return 0;
+    case ORC_G_EZ: memcpy(s->Ez, in, nn * 8); return 0;
     }
     return -1;
 }
@@ -873,6 +907,26 @@ int orc_set_state(orc_sim* s, const double* st) {
 }
 
 /* ------------------------------------------------------------ pure pieces */
+/* Eq. (1)'s susceptibility and right-hand side from the deposit grids as
+   they stand (the first step of every time step), without stepping. */
+int orc_assemble_now(orc_sim* s) {
+    o_assemble(s);
+    return 0;
+}
+
+/* E = -grad phi at the nodes from the potential grid as it stands [R9]. */
+int orc_efield_now(orc_sim* s) {
+    o_efield(s);
+    return 0;
+}
+
+/* The field the particle step gathers at n positions, from the node field
+   grids as they stand (0 outside the domain). */
+int orc_gather(orc_sim* s, int64_t n, const double* r, const double* z, double* Er, double* Ez) {
+    for (int64_t k = 0; k < n; k++) o_gather(s, r[k], z[k], &Er[k], &Ez[k]);
+    return 0;
+}
+
 int orc_solve_qv(orc_sim* s, const double* Q, const double* chi, const double* U, double tol, double* phi_inout,
                  int32_t* iters, double* relres) {
     double* ar = calloc(s->nn, sizeof(double));

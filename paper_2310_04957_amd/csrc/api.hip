@@ -608,7 +608,7 @@ void characterise(const pic_handle* h, const std::vector<double>& U, const std::
 int sync_err(pic_handle* h) {
     if (hipStreamSynchronize(h->stream) != hipSuccess) return PIC_E_HIP;
     if (hipMemcpy(h->h_ctr, h->ctr, sizeof(DevCounters), hipMemcpyDeviceToHost) != hipSuccess) return PIC_E_HIP;
-    if (h->h_ctr->err == 2) h->sticky_err = PIC_E_CAPACITY;
+    if (h->h_ctr->err != 0) h->sticky_err = PIC_E_CAPACITY;
     return PIC_OK;
 }
 
@@ -718,6 +718,7 @@ int pic_init(const pic_config* cfg, void* dev_workspace, size_t bytes, void* hip
 int pic_step(pic_handle* h, int32_t nsteps) {
     if (!h) return PIC_E_ARG;
     if (nsteps < 0) return PIC_E_ARG;
+    if (h->halted) return PIC_E_CAPACITY;
     const pic_config& c = h->cfg;
     const int spp = c.run.steps_per_period;
     for (int32_t k = 0; k < nsteps; ++k) {
@@ -735,6 +736,13 @@ int pic_step(pic_handle* h, int32_t nsteps) {
         h->solver_iters = it;
         h->solver_relres = rel;
         if (rc != PIC_OK) return rc;
+        // the solve's residual read waited for the previous step's births:
+        // if some did not fit, stop before this step moves any particle
+        if (h->h_sc->cap_err & kErrBirths) {
+            h->halted = true;
+            h->sticky_err = PIC_E_CAPACITY;
+            return PIC_E_CAPACITY;
+        }
         launch_efield(h);
         ev_record(h, 4, &b0);
         h->dep_cur = 1 - h->dep_cur;
@@ -1061,6 +1069,36 @@ int pic_solve_once(pic_handle* h, const double* Q, const double* chi, double U_E
                    int32_t* iters, double* relres) {
     double U[kMaxEl] = {U_E, 0.0, 0.0, 0.0};
     return pic_solve_once_el(h, Q, chi, U, tol, phi_inout, iters, relres);
+}
+
+int pic_match_design(pic_handle* h, int32_t apply, double* out2) {
+    if (!h || !out2) return PIC_E_ARG;
+    pic_circuit& c = h->cfg.circ;
+    if (c.kind != PIC_LMATCH) return PIC_E_CONFIG;
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return PIC_E_HIP;
+    double Ceq = 0.0;
+    if (hipMemcpy(&Ceq, &h->sc->Cm[0][0], sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) return PIC_E_HIP;
+    // load: C_eq in parallel with the stray branch; the network's input
+    // admittance j w C_m1 + 1/Z_b, Z_b = R_m + j w L_m + 1/(j w C_m2) + Z_load
+    // = R_b + j X_b, equals 1/R_s iff R_b/(R_b^2 + X_b^2) = 1/R_s and
+    // w C_m1 = X_b/(R_b^2 + X_b^2): X_b = sqrt(R_b (R_s - R_b)) > 0
+    using cd = std::complex<double>;
+    const double w = 2.0 * kPi * c.freq;
+    const cd zc = 1.0 / cd(0.0, w * Ceq);
+    const cd zs = cd(c.R_stray, w * c.L_stray) + 1.0 / cd(0.0, w * c.C_stray);
+    const cd zl = zc * zs / (zc + zs);
+    const double Rb = c.R_m + zl.real();
+    if (!(Ceq > 0.0) || !(Rb > 0.0) || !(Rb < c.R_s)) return PIC_E_CONFIG;
+    const double Xb = std::sqrt(Rb * (c.R_s - Rb));
+    const double xc2 = w * c.L_m + zl.imag() - Xb;   // reactance 1/(w C_m2) the series branch needs
+    if (!(xc2 > 0.0)) return PIC_E_CONFIG;
+    out2[0] = Xb / (Rb * c.R_s) / w;
+    out2[1] = 1.0 / (w * xc2);
+    if (apply) {
+        c.C_m1 = out2[0];
+        c.C_m2 = out2[1];
+    }
+    return PIC_OK;
 }
 
 int pic_set_state(pic_handle* h, const double* st9) {

@@ -431,7 +431,8 @@ __global__ __launch_bounds__(256) void k_resid64(const double* ar, const double*
 }
 
 // final sums; decides the outer convergence and the inner target
-__global__ __launch_bounds__(256) void k_reduce_resid(const double* part, DevScalars* s, double tol, int fp64) {
+__global__ __launch_bounds__(256) void k_reduce_resid(const double* part, DevScalars* s, const DevCounters* ctr,
+                                                      double tol, int fp64) {
     __shared__ double a[kRedBlocks], b[kRedBlocks];
     for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) { a[i] = part[2 * i]; b[i] = part[2 * i + 1]; }
     __syncthreads();
@@ -449,6 +450,7 @@ __global__ __launch_bounds__(256) void k_reduce_resid(const double* part, DevSca
         // inner target on r.r: FP64 -> the final tolerance (with margin),
         // FP32 on the normalised residual -> set by the caller
         s->target = fp64 ? 0.25 * tol * tol * bb : s->target;
+        s->cap_err = ctr->err;
     }
 }
 
@@ -1378,7 +1380,8 @@ int field_solve(pic_handle* h, double* phi, const double* Q, const double* Up, d
     for (;; ++outer) {
         hipLaunchKernelGGL(k_resid64, dim3(kRedBlocks), dim3(256), 0, st, (const double*)h->ar, (const double*)h->az,
                            (const int8_t*)h->node_kind, Q, (const double*)phi, Up, h->r64, h->part, h->nr, h->nz);
-        hipLaunchKernelGGL(k_reduce_resid, dim3(1), dim3(256), 0, st, (const double*)h->part, h->sc, tol, fp64);
+        hipLaunchKernelGGL(k_reduce_resid, dim3(1), dim3(256), 0, st, (const double*)h->part, h->sc,
+                           (const DevCounters*)h->ctr, tol, fp64);
         if (!read_scalars(h)) return PIC_E_HIP;
         rel = h->h_sc->relres;
         if (h->h_sc->nonfinite) { err = PIC_E_NONFINITE; break; }
@@ -1470,13 +1473,19 @@ __global__ __launch_bounds__(256) void k_ceq_final(const double* part, DevScalar
 // driven electrode (it at 1 V, every other conductor at 0), and the
 // capacitance matrix C_ef = sum over edges of a (d phi_Le)(d phi_Lf), the
 // field energy's bilinear form (C_11 = C_eq of Eqs. 6-7).
+constexpr double kLaplaceAccept = 1e-9;
+
 int refresh_laplace(pic_handle* h) {
     mg_rebuild(h);
     for (int e = 0; e < h->n_el; ++e) {
         int32_t it;
         double rel;
         int rc = field_solve(h, h->phiL[e], nullptr, h->sc->unit[e], 1e-12, PIC_SOLVE_MGPCG_FP64, &it, &rel);
-        if (rc != PIC_OK && rc != PIC_E_SOLVER) return rc;
+        // the solve asks for 1e-12 and accepts reaching 1e-9 within its
+        // iteration limit: C_eq is quadratic in phi_L, its error stays below
+        // 1e-9 relative; a Laplace solve that stops above that is an error
+        if (rc == PIC_E_SOLVER && rel <= kLaplaceAccept) rc = PIC_OK;
+        if (rc != PIC_OK) return rc;
     }
     for (int e = 0; e < h->n_el; ++e)
         for (int f = e; f < h->n_el; ++f) {

@@ -368,7 +368,7 @@ __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4)))
                     for (int k = 0; k < 6; ++k) bb.v[k] = b6[k];
                     a.stage[stage_row * kStageW + idx] = bb;
                 } else {
-                    atomicMax(&a.ctr->err, 2);
+                    atomicOr(&a.ctr->err, kErrBirths);
                 }
             }
             nb += __popcll(bm);
@@ -531,7 +531,7 @@ __global__ __launch_bounds__(1024) void k_birth_scan(DevCounters* c, const int* 
         c->base[1] = c->n_slots[1];
         c->nch_births = rows;
         if (c->n_slots[0] + B > cap_e || c->n_slots[1] + B > cap_i) {
-            atomicMax(&c->err, 2);
+            atomicOr(&c->err, kErrBirths);
             B = 0;
         }
         c->births_step = B;

@@ -36,6 +36,10 @@ constexpr int kMaxEl = PIC_MAX_ELECTRODES;   // driven electrodes
 // (Neumann edge), 3 dielectric, 4 .. 6 electrodes 2 .. 4
 __host__ __device__ constexpr int slot_of(int id) { return id <= 1 ? id : 2 + id; }
 constexpr int kSlots = 8;
+// bits of DevCounters::err: births that did not fit were dropped (the run
+// stops at the next step); a splitting pass did not fit and changed nothing
+constexpr int kErrBirths = 1;
+constexpr int kErrSplit = 2;
 
 // counters that kernels update; lives in device memory
 struct DevCounters {
@@ -72,6 +76,7 @@ struct DevScalars {
     double energy[5];        // circuit element energies of the running RF period
     double last_energy[5];   // ... of the last complete one
     int done, iters, nonfinite, fallback;
+    int cap_err;             // DevCounters::err as the last residual reduction saw it
 };
 
 struct Level {
@@ -158,6 +163,7 @@ struct pic_handle {
     int cg_guess[2][4];           // Krylov iterations of the last solve, per precision and outer pass
     double solver_relres;
     int sticky_err;
+    bool halted;                  // births were dropped: no further steps
     // learned preconditioner
     bool unet_on;
     pic::unet::Net net;

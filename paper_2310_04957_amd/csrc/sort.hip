@@ -461,7 +461,7 @@ __global__ __launch_bounds__(1024) void k_split_scan(SplitArgs a) {
         const long long total = sh[1023];
         if (n + total > a.cap) {
             a.ctr->split_total = -1;
-            atomicMax(&a.ctr->err, 2);
+            atomicOr(&a.ctr->err, kErrSplit);
         } else {
             a.ctr->split_total = total;
         }

@@ -125,6 +125,7 @@ def lib():
         L.pic_solve_once.argtypes = [P, P, P, C.c_double, C.c_double, P, C.POINTER(C.c_int32),
                                      C.POINTER(C.c_double)]
         L.pic_set_state.argtypes = [P, P]
+        L.pic_match_design.argtypes = [P, C.c_int32, P]
         L.pic_set_solver.argtypes = [P, C.POINTER(Solver)]
         L.pic_moments.argtypes = [P, C.c_int32, P, P]
         L.pic_unet_num_params.argtypes = [P, C.POINTER(C.c_int64)]
@@ -317,6 +318,12 @@ class Pic:
         """n_el x n_el capacitance matrix of the driven electrodes (F)."""
         d = self.diag()
         return np.array(d.C_el[:]).reshape(MAX_EL, MAX_EL)[:d.n_el, :d.n_el]
+
+    def match_design(self, apply=False):
+        """(C_m1, C_m2) of electrode 1's L-network matching the current C_eq (Sec. 3)."""
+        out = np.zeros(2)
+        _check(lib().pic_match_design(self.h, 1 if apply else 0, _ptr(out)), "pic_match_design")
+        return float(out[0]), float(out[1])
 
     def set_state(self, t, Q_E, U_E, circ, C_eq):
         st = np.array([t, Q_E, U_E] + list(circ) + [C_eq], dtype=np.float64)

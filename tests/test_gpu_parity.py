@@ -111,9 +111,13 @@ def test_sort_permutation_matches_stable_sort():
     g.close()
 
 
+@pytest.mark.parametrize("size", [(64, 128), (512, 1024), (1024, 2048)])
 @pytest.mark.parametrize("method", [SOLVE_MGPCG_FP64, SOLVE_IR_MG])
-def test_field_solve_matches_oracle(method):
-    w = _small_gec(n=0)
+def test_field_solve_matches_oracle(method, size):
+    """The GEC cell from a coarse grid up to the full 1024 x 2048 one, where
+    the multigrid hierarchy runs its fine levels over thousands of blocks
+    and its coarse levels in the fused tail kernel."""
+    w = _small_gec(nr=size[0], nz=size[1], n=0, cap_e=16, cap_i=16)
     g = _pic(w, load=False, method=method)
     o = O.Oracle(w, load=False)
     rng = np.random.default_rng(7)
@@ -397,3 +401,42 @@ def test_step_splits_at_the_sort_and_keeps_the_charge():
     assert sa == sb
     a.close()
     b.close()
+
+
+def test_births_across_staging_segments_match_oracle():
+    """More than a million electron slots (two segments of 1024 staging rows
+    of the birth scan) with ionising electrons, so one segment holds more
+    than 1024 births: the births are appended in parent-slot order, the same
+    slots as the oracle's, with the same states to FP32 rounding."""
+    n = 1_150_000
+    w = workload("pp32x24", run=dict(n_e=0, n_i=0, cap_e=n + 200000, cap_i=n + 200000, sort_every=0,
+                                     sort_every_ion=0))
+    w["solver"]["tol"] = 1e-12
+    gm = w["geometry"]
+    pe = random_particles(n, gm["R"] * 0.98, gm["Z"], seed=111, vmax=6e6, amax=0.0, wmin=1.0, wmax=1.0,
+                          z_lo=0.002, z_hi=0.023)
+    pi = random_particles(n, gm["R"] * 0.98, gm["Z"], seed=112, vmax=3e3, amax=0.0, wmin=1.0, wmax=1.0,
+                          z_lo=0.002, z_hi=0.023)
+    g = _pic(w, load=False)
+    o = O.Oracle(w, load=False)
+    for s in (g, o):
+        s.set_particles(0, pe)
+        s.set_particles(1, pi)
+        s.redeposit()
+    g.step(1)
+    o.step(1)
+    dg, do = g.diag(), o.diag()
+    assert dg.error == 0
+    print(f"[gpu] births {dg.born} (oracle {do.born})", flush=True)
+    assert dg.born == do.born and dg.born > 2048
+    for sp in (0, 1):
+        a, b = g.particles(sp), o.particles(sp)
+        assert len(a["r"]) == len(b["r"]) == n + dg.born
+        new = slice(n, n + dg.born)
+        both = (a["r"][new] >= 0) & (b["r"][new] >= 0)
+        assert both.mean() > 0.99
+        for f in ("r", "z", "vr", "vt", "vz", "w"):
+            x, y = a[f][new][both].astype(np.float64), b[f][new][both]
+            err = np.abs(x - y) / (np.abs(y) + np.max(np.abs(y)) * 1e-3)
+            assert np.mean(err > 1e-4) <= 1e-3, (sp, f)
+    g.close()

@@ -252,3 +252,33 @@ def test_series_rlc_characterisation_matches_phasor_solution():
     assert abs(e["P_IMN"] - Pb) <= 1e-5 * Pb
     assert abs(e["P_source"] - Pb) <= 1e-5 * Pb
     assert e["gamma"] == 0.0
+
+
+def test_matching_design_reproduces_the_paper_and_matches_in_time_domain():
+    # Sec. 3, first paragraph: the vacuum C_eq = 892.07 pF gives, by the
+    # authors' design method, C_m1 = 2335.51 pF and C_m2 = 215.62 pF for a
+    # perfect vacuum match (printed to 0.01 pF).  Independently of the
+    # design's closed form, the time-domain circuit with the designed
+    # elements must reflect nothing: |Gamma| of the simulated load, from the
+    # RK4 waveforms, at the level of its sampling error.
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                       "paper_vacuum_matching.json")))
+    base = dict(kind=CIRC_LMATCH, U_amp=gold["U_source_amplitude_V"], L_m=gold["L_m_H"],
+                R_m=gold["R_m_ohm"], R_s=gold["R_s_ohm"], C_stray=gold["C_stray_F"],
+                R_stray=gold["R_stray_ohm"])
+    w = workload("pp32x24", circuit=dict(base, C_m1=1e-9, C_m2=1e-10), run=dict(steps_per_period=400))
+    Cm1, Cm2 = O.match_design(w, gold["C_eq_vacuum_F"])
+    assert abs(Cm1 - gold["C_m1_F"]) <= 0.005e-12
+    assert abs(Cm2 - gold["C_m2_F"]) <= 0.005e-12
+    for Ceq in (gold["C_eq_vacuum_F"], 300e-12, 2000e-12):
+        Cm1, Cm2 = O.match_design(w, Ceq)
+        wm = workload("pp32x24", circuit=dict(base, C_m1=Cm1, C_m2=Cm2), run=dict(steps_per_period=400))
+        U, I, e = O.circuit_vacuum(wm, Ceq, 400 * 400, chars=True)
+        assert e["gamma"] < 1e-6, (Ceq, e["gamma"])
+        # a mis-designed network (C_m2 off by 1%) reflects measurably
+        wb = workload("pp32x24", circuit=dict(base, C_m1=Cm1, C_m2=1.01 * Cm2), run=dict(steps_per_period=400))
+        assert O.circuit_vacuum(wb, Ceq, 400 * 400, chars=True)[2]["gamma"] > 10 * e["gamma"]
+    # a load whose series resistance exceeds R_s cannot be matched by this network
+    wbad = workload("pp32x24", circuit=dict(base, R_m=60.0, C_m1=1e-9, C_m2=1e-10))
+    with pytest.raises(ValueError):
+        O.match_design(wbad, gold["C_eq_vacuum_F"])
