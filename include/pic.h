@@ -49,7 +49,8 @@ enum {
     PIC_E_NONFINITE = -5, /* a non-finite value reached the field solve */
     PIC_E_STATE = -6,     /* call not valid in the handle's state */
     PIC_E_ARG = -7,       /* bad argument (null pointer, size too small, bad id) */
-    PIC_E_NODEVICE = -8   /* no gfx950 device is current */
+    PIC_E_NODEVICE = -8,  /* no gfx950 device is current */
+    PIC_E_TOOBIG = -9     /* the grid exceeds the fixed scratch of an allocation-free entry point */
 };
 
 enum { PIC_VACUUM = 0, PIC_DIEL = 1, PIC_COND = 2 };                 /* region kinds */
@@ -294,6 +295,19 @@ int pic_set_state(pic_handle* h, const double* st9);
    per node E / (16 N) eV, electron temperature two thirds of it (Sec. 3,
    the T_e maps).  Exact integer sums: bit-identical to any order. */
 int pic_moments(pic_handle* h, int32_t species, int64_t* N, int64_t* E);
+
+/* pic_moments for callers that cannot allocate device memory (code under
+   HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+   the same results, bit for bit, but the two device node grids it
+   accumulates in live in a fixed scratch array of the library (one per GPU,
+   held until the process ends) instead of the handle's solver work vectors,
+   which it leaves untouched.  It calls no allocating routine.  Limit: grids
+   of at most PIC_NOALLOC_MAX_NODES nodes ((nr+1)(nz+1); 1024 x 2048 cells
+   fit), PIC_E_TOOBIG beyond.  Every call on one GPU shares that GPU's
+   scratch: calls that overlap on one GPU (several threads or streams) race
+   and must be serialised by the caller. */
+#define PIC_NOALLOC_MAX_NODES (1025 * 2049)
+int pic_moments_noalloc(pic_handle* h, int32_t species, int64_t* N, int64_t* E);
 
 /* ---- learned preconditioner (requires solver.unet_batch > 0; nr and nz
    multiples of 16) ----

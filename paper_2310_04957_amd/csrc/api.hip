@@ -7,6 +7,7 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -23,6 +24,30 @@ constexpr double kEps0 = 8.8541878128e-12;
 constexpr double kKB = 1.380649e-23;
 constexpr double kPi = 3.14159265358979323846;
 constexpr int64_t kMaxSlots = (1LL << 30) - 16;   // particle arrays are addressed by 32-bit byte offsets
+
+// Fixed scratch of the allocation-free entry points: two int64 node grids
+// (the energy moments' N and E), one copy per GPU for the process's life.
+// Host code never uses the array's name as an address: each device's copy
+// is found once with hipGetSymbolAddress, with that device current.
+constexpr size_t kNoAllocNodes = PIC_NOALLOC_MAX_NODES;
+__device__ __align__(256) unsigned long long scratch[2 * kNoAllocNodes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned long long* g_scratch_ptr[kMaxDevices];
+
+// the current device's copy of the scratch array (nullptr on failure)
+unsigned long long* noalloc_scratch() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+        g_scratch_ptr[dev] = static_cast<unsigned long long*>(p);
+    }
+    return g_scratch_ptr[dev];
+}
 
 #define HIP_OK(x)                               \
     do {                                        \
@@ -923,6 +948,7 @@ const char* pic_strerror(int code) {
     case PIC_E_STATE: return "call not valid in this state";
     case PIC_E_ARG: return "bad argument";
     case PIC_E_NODEVICE: return "no gfx950 device is current";
+    case PIC_E_TOOBIG: return "grid larger than the allocation-free scratch";
     }
     return "unknown error";
 }
@@ -1115,6 +1141,21 @@ int pic_moments(pic_handle* h, int32_t species, int64_t* N, int64_t* E) {
     unsigned long long* dN = reinterpret_cast<unsigned long long*>(h->x64);
     unsigned long long* dE = reinterpret_cast<unsigned long long*>(h->z64);
     launch_moments(h, species, dN, dE);
+    HIP_OK(hipStreamSynchronize(h->stream));
+    HIP_OK(hipMemcpy(N, dN, (size_t)h->nn * 8, hipMemcpyDeviceToHost));
+    HIP_OK(hipMemcpy(E, dE, (size_t)h->nn * 8, hipMemcpyDeviceToHost));
+    return PIC_OK;
+}
+
+int pic_moments_noalloc(pic_handle* h, int32_t species, int64_t* N, int64_t* E) {
+    if (!h || !N || !E || species < 0 || species > 1) return PIC_E_ARG;
+    if ((size_t)h->nn > kNoAllocNodes) return PIC_E_TOOBIG;
+    unsigned long long* base = noalloc_scratch();
+    if (!base) return PIC_E_HIP;
+    materialize(h, species);
+    unsigned long long* dN = base;
+    unsigned long long* dE = base + kNoAllocNodes;
+    launch_moments(h, species, dN, dE);   // clears the nn entries it uses with a fill kernel
     HIP_OK(hipStreamSynchronize(h->stream));
     HIP_OK(hipMemcpy(N, dN, (size_t)h->nn * 8, hipMemcpyDeviceToHost));
     HIP_OK(hipMemcpy(E, dE, (size_t)h->nn * 8, hipMemcpyDeviceToHost));

@@ -20,8 +20,9 @@ WEIGHTS_EQUAL, WEIGHTS_CELL = 0, 1
 GRIDS = dict(DEP_E=0, DEP_I=1, PHI=2, ER=3, EZ=4, CHI=5, WALLQ=6, PHI_L=10, Q=11, AR=12, AZ=13,
              PHI_L2=14, PHI_L3=15, PHI_L4=16)
 MAX_EL = 4
+PIC_NOALLOC_MAX_NODES = 1025 * 2049     # nodes of the allocation-free entry points
 ERRORS = {0: "ok", -1: "PIC_E_CONFIG", -2: "PIC_E_CAPACITY", -3: "PIC_E_SOLVER", -4: "PIC_E_HIP",
-          -5: "PIC_E_NONFINITE", -6: "PIC_E_STATE", -7: "PIC_E_ARG", -8: "PIC_E_NODEVICE"}
+          -5: "PIC_E_NONFINITE", -6: "PIC_E_STATE", -7: "PIC_E_ARG", -8: "PIC_E_NODEVICE", -9: "PIC_E_TOOBIG"}
 
 
 class PicError(RuntimeError):
@@ -128,6 +129,7 @@ def lib():
         L.pic_match_design.argtypes = [P, C.c_int32, P]
         L.pic_set_solver.argtypes = [P, C.POINTER(Solver)]
         L.pic_moments.argtypes = [P, C.c_int32, P, P]
+        L.pic_moments_noalloc.argtypes = [P, C.c_int32, P, P]
         L.pic_unet_num_params.argtypes = [P, C.POINTER(C.c_int64)]
         L.pic_unet_set_params.argtypes = [P, P, C.c_int64]
         L.pic_unet_get_params.argtypes = [P, P, C.c_int64]
@@ -334,6 +336,13 @@ class Pic:
         N = np.zeros(self.nn, dtype=np.int64)
         E = np.zeros(self.nn, dtype=np.int64)
         _check(lib().pic_moments(self.h, sp, _ptr(N), _ptr(E)), "pic_moments")
+        return N, E
+
+    def moments_noalloc(self, sp):
+        """pic_moments through the allocation-free entry point (fixed scratch)."""
+        N = np.zeros(self.nn, dtype=np.int64)
+        E = np.zeros(self.nn, dtype=np.int64)
+        _check(lib().pic_moments_noalloc(self.h, sp, _ptr(N), _ptr(E)), "pic_moments_noalloc")
         return N, E
 
     def set_solver(self, method=None, tol=None, max_iter=None, inner_tol=None):
