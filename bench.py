@@ -39,7 +39,17 @@ def cpu_baseline(name, sample_particles, steps):
     dt = time.perf_counter() - t0
     d = o.diag()
     n = int(d.n_alive[0] + d.n_alive[1])
+    cpu_model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu_model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return dict(value=2 * sample_particles * steps / dt, unit="particle-steps/s", cores=1, kind="oracle",
+                host_cores=os.cpu_count(), cpu_model=cpu_model,
                 sample=f"{name} geometry and circuit, {sample_particles} e + {sample_particles} Ar+ "
                        f"(uniform load), {steps} whole steps single-threaded FP64 incl. field solve; "
                        f"{dt:.1f} s, {n} alive at end",
@@ -100,6 +110,132 @@ def learned_vs_plain(sim, args, w):
                      "seconds": t_train, "loss_first": float(curve[:5].mean()), "loss_last": float(curve[-20:].mean())},
         "unet_gflop_per_application": unet_flops(H, W) / 1e9,
         "image": f"{H}x{W}",
+    }
+
+
+def c4_protocol(args):
+    """The learned preconditioner's protocol on the 512 x 1024 GEC discharge
+    (64M + 64M particles): pairs harvested from FP64 MG-PCG solves of runs
+    with seeds 1..16 (the five points of the pressure / voltage sweep in
+    turn), one network trained on all of them with the library's kernels,
+    then evaluated on seeds 17..20 inside flexible CG against plain FP64
+    MG-PCG and FP32-inner MG-PCG: inner iterations from the same warm starts
+    (solve_once, FP64 residual 1e-8), and field-solve ms per step and
+    fallbacks over steps of the running discharge."""
+    import numpy as np
+    import torch
+    from paper_2310_04957_amd.pic import Pic, SOLVE_IR_MG, SOLVE_IR_UNET, SOLVE_MGPCG_FP64
+    from pic_inputs import workload
+    from pic_inputs.workloads import GEC512_SWEEP, MTORR_PA, _lmatch
+
+    def discharge(seed, **kw):
+        p_mtorr, U = GEC512_SWEEP[(seed - 1) % len(GEC512_SWEEP)]
+        w = workload("gec512x1024")
+        w["gas"]["p_Pa"] = p_mtorr * MTORR_PA
+        w["circuit"] = _lmatch(float(U))
+        w["run"]["seed"] = seed
+        # room for the discharges of the sweep that ionise fastest (at 50
+        # mTorr and 300 V the ions grow from 64M to about 150M in 550 steps)
+        w["run"]["cap_e"] = w["run"]["cap_i"] = 240_000_000
+        print(f"[c4] seed {seed}: {p_mtorr} mTorr, {U} V", file=sys.stderr, flush=True)
+        return w, Pic(w, method=SOLVE_IR_MG, timing=True, **kw)
+
+    t_start = time.perf_counter()
+    pairs = []
+    for seed in range(1, args.c4_train_seeds + 1):
+        w, sim = discharge(seed, unet_batch=1, unet_pairs=args.c4_pairs_per_seed)
+        sim.step(args.c4_warmup)
+        sim.unet_harvest(args.c4_every)
+        for _ in range(0, args.c4_harvest_steps, 20):
+            sim.step(20)
+        sim.unet_harvest(0)
+        got = min(int(sim.diag().unet_pairs), args.c4_pairs_per_seed)
+        for k in range(got):
+            pr = sim.unet_pair(k)
+            pairs.append((pr["r"], pr["e"], pr["chi"]))
+        sim.close()
+        print(f"[c4] seed {seed}: {got} pairs ({len(pairs)} in all)", file=sys.stderr, flush=True)
+    t_harvest = time.perf_counter() - t_start
+
+    wt = workload("gec512x1024")
+    wt["run"].update(n_e=0, n_i=0, cap_e=1, cap_i=1)
+    trainer = Pic(wt, load=False, method=SOLVE_IR_MG, unet_batch=args.c4_batch, unet_pairs=len(pairs))
+    for k, (r, e, chi) in enumerate(pairs):
+        trainer.unet_put_pair(k, r, e, chi)
+    del pairs
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    curve = trainer.unet_train(args.c4_train_steps, args.c4_batch, args.c4_lr, seed=1)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    params = trainer.unet_params()
+    n_pairs = int(trainer.diag().unet_pairs)
+    trainer.close()
+    print(f"[c4] trained {args.c4_train_steps} steps on {n_pairs} pairs in {t_train:.1f} s: "
+          f"loss {curve[:20].mean():.3f} -> {curve[-100:].mean():.3f}", file=sys.stderr, flush=True)
+    if args.c4_save:
+        params.astype(np.float32).tofile(args.c4_save)
+
+    methods = ((SOLVE_MGPCG_FP64, "plain_fp64_mgpcg"), (SOLVE_IR_MG, "mixed_ir_mgpcg"),
+               (SOLVE_IR_UNET, "learned_ir_unet_fpcg"))
+    tol = 1e-8
+    evals = []
+    for seed in range(args.c4_train_seeds + 1, args.c4_train_seeds + 1 + args.c4_eval_seeds):
+        w, sim = discharge(seed, unet_batch=1, unet_pairs=0)
+        sim.unet_set_params(params)
+        sim.step(args.c4_warmup)
+        # the same warm starts for every method: a step's Q, chi and U_E,
+        # started from the previous step's solution
+        res = {"seed": seed, "point": GEC512_SWEEP[(seed - 1) % len(GEC512_SWEEP)]}
+        its = {name: [] for _, name in methods}
+        phi_n1 = sim.grid("PHI")
+        for _ in range(args.c4_problems):
+            phi_n0 = phi_n1
+            sim.step(1)
+            phi_n1 = sim.grid("PHI")
+            Q, chi, U = sim.grid("Q"), sim.grid("CHI"), sim.diag().U_E
+            for m, name in methods:
+                sim.set_solver(method=m)
+                _, it, rel, rc = sim.solve_once(Q, chi, U, tol, phi_n0)
+                its[name].append(int(it) if rc == 0 and rel <= tol else -1)
+            sim.set_solver(method=SOLVE_IR_MG)
+            sim.step(args.c4_problem_gap - 1)
+            phi_n1 = sim.grid("PHI")
+        res["inner_iters_same_start"] = its
+        for m, name in methods:
+            sim.set_solver(method=m)
+            sim.step(1)
+            d0 = sim.diag()
+            sim.reset_timers()
+            steps_its = []
+            for _ in range(args.c4_steps):
+                sim.step(1)
+                steps_its.append(int(sim.diag().solver_iters))
+            d = sim.diag()
+            res[name] = {"field_ms_per_step": d.ms_field / args.c4_steps, "inner_iters": steps_its,
+                         "fallbacks": int(d.unet_fallbacks - d0.unet_fallbacks),
+                         "unet_applications": int(d.unet_applications - d0.unet_applications),
+                         "relres_last": d.solver_relres, "network_switched_off": int(d.unet_disabled)}
+        sim.close()
+        evals.append(res)
+        print(f"[c4] eval seed {seed}: " + ", ".join(
+            f"{name} {res[name]['field_ms_per_step']:.3f} ms/step its {sum(its[name])}" for _, name in methods),
+              file=sys.stderr, flush=True)
+
+    def mean(name, key):
+        return float(np.mean([e[name][key] for e in evals]))
+    summary = {name: {"field_ms_per_step": mean(name, "field_ms_per_step"),
+                      "inner_iters_same_start_total": int(sum(sum(e["inner_iters_same_start"][name]) for e in evals)),
+                      "fallbacks": int(sum(e[name]["fallbacks"] for e in evals))} for _, name in methods}
+    return {
+        "grid": "512x1024", "particles": "64M + 64M", "train_seeds": list(range(1, args.c4_train_seeds + 1)),
+        "eval_seeds": [e["seed"] for e in evals], "pairs": n_pairs, "harvest_seconds": t_harvest,
+        "training": {"steps": args.c4_train_steps, "batch": args.c4_batch, "lr": args.c4_lr, "seconds": t_train,
+                     "loss_first": float(curve[:20].mean()), "loss_last": float(curve[-100:].mean())},
+        "summary": summary,
+        "faster_than_plain": summary["learned_ir_unet_fpcg"]["field_ms_per_step"] <
+        summary["plain_fp64_mgpcg"]["field_ms_per_step"],
+        "evaluation": evals,
     }
 
 
@@ -247,6 +383,23 @@ def main():
                     help="skip timing the field solve and refresh with one and two driven electrodes")
     ap.add_argument("--no-split-pass", action="store_true",
                     help="skip timing one particle-splitting pass per species after the run")
+    ap.add_argument("--c4", action="store_true",
+                    help="only run the learned preconditioner's train/evaluate protocol on 512x1024 (seeds 1-16 / 17-20)")
+    ap.add_argument("--no-c4", action="store_true",
+                    help="skip the learned preconditioner's 512x1024 train/evaluate protocol after the timed run")
+    ap.add_argument("--c4-train-seeds", type=int, default=16)
+    ap.add_argument("--c4-eval-seeds", type=int, default=4)
+    ap.add_argument("--c4-warmup", type=int, default=300)
+    ap.add_argument("--c4-every", type=int, default=4)
+    ap.add_argument("--c4-harvest-steps", type=int, default=200)
+    ap.add_argument("--c4-pairs-per-seed", type=int, default=200)
+    ap.add_argument("--c4-train-steps", type=int, default=3000)
+    ap.add_argument("--c4-batch", type=int, default=8)
+    ap.add_argument("--c4-lr", type=float, default=1e-3)
+    ap.add_argument("--c4-problems", type=int, default=4)
+    ap.add_argument("--c4-problem-gap", type=int, default=20)
+    ap.add_argument("--c4-steps", type=int, default=40)
+    ap.add_argument("--c4-save", default="")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain FP32 copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -259,6 +412,9 @@ def main():
             torch.add(src, 0.0, out=dst)
         torch.cuda.synchronize()
         print(json.dumps({"calibration": "copy", "bytes_read": 4 * n, "bytes_written": 4 * n, "launches": 3}))
+        return
+    if args.c4:
+        print(json.dumps({"c4": c4_protocol(args)}))
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
@@ -354,6 +510,12 @@ def main():
     if not args.no_electrodes_pass and args.workload.startswith("gec"):
         print("[bench] driven electrodes", file=sys.stderr, flush=True)
         out["electrodes_pass"] = electrodes_pass(args)
+    if not args.no_c4:
+        print("[bench] learned preconditioner protocol (512x1024)", file=sys.stderr, flush=True)
+        try:
+            out["learned_preconditioner_512x1024"] = c4_protocol(args)
+        except Exception as e:  # reported, the timed result stands
+            out["learned_preconditioner_512x1024"] = {"error": str(e)}
     if args.precision_study:
         out["precision_study"] = precision_study()
     if not args.no_cpu_baseline:

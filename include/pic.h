@@ -184,6 +184,14 @@ typedef struct {
     double hU_re[PIC_MAX_ELECTRODES][6], hU_im[PIC_MAX_ELECTRODES][6];
     double hI_re[PIC_MAX_ELECTRODES][6], hI_im[PIC_MAX_ELECTRODES][6];
     int64_t absorbed_el[2][PIC_MAX_ELECTRODES];
+    /* 1 when the learned preconditioner is switched off: three solves in a
+       row gave it back to multigrid (it stays off until pic_unet_set_params
+       or pic_unet_train; PIC_SOLVE_IR_UNET then runs as PIC_SOLVE_IR_MG) */
+    int32_t unet_disabled;
+    /* what raised PIC_E_CAPACITY: bit 0 the births of a step exceeded a
+       species' slot capacity, bit 1 a slice's births exceeded its staging
+       row, bit 2 a splitting pass did not fit */
+    int32_t capacity_bits;
 } pic_diag_out;
 
 typedef struct {
@@ -347,6 +355,12 @@ int pic_unet_harvest(pic_handle* h, int32_t every);
    normalised residual, the normalised error, chi/(1+chi) and the mask, each
    [nz][nr] FP32 (NULL skips one). */
 int pic_unet_get_pair(pic_handle* h, int32_t slot, float* r, float* e, float* chi, float* mask);
+/* Store a pair in slot `slot` (< solver.unet_pairs) of the ring, in the
+   layout pic_unet_get_pair returns (normalised residual, normalised error,
+   chi/(1+chi), each [nz][nr] FP32; the mask is the handle's own), so that
+   pairs harvested by several runs train one network.  The pair count
+   becomes at least slot + 1. */
+int pic_unet_put_pair(pic_handle* h, int32_t slot, const float* r, const float* e, const float* chi);
 /* Adam (lr, betas 0.9/0.999) on random batches of the harvested pairs;
    loss_curve (or NULL) receives the loss of each step. */
 int pic_unet_train(pic_handle* h, int32_t steps, int32_t batch, double lr, uint64_t seed, double* loss_curve);

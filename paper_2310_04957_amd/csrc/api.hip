@@ -175,6 +175,14 @@ void derive(pic_handle* h) {
         double T = std::floor(P * 4294967296.0);
         h->thresh[sp] = (T >= 4294967295.0) ? 0xFFFFFFFFu : (uint32_t)T;
     }
+    // births of a 1024-slot slice are at most its null-collision candidates,
+    // binomial(1024, P): the row holds the mean plus eight standard
+    // deviations plus 32, in whole 64s
+    {
+        const double P = (double)h->thresh[0] * 0x1p-32, m = kSlice * P;
+        const double need = m + 8.0 * std::sqrt(m * (1.0 - P)) + 32.0;
+        h->stage_w = std::min(kSlice, std::max(kStageWMin, ((int)std::ceil(need) + 63) / 64 * 64));
+    }
 }
 
 }  // namespace
@@ -358,7 +366,7 @@ size_t layout(pic_handle* h, char* base) {
     h->bsum = c.take<uint32_t>((256 * mch + 4095) / 4096 + 1);
     h->split_off = c.take<long long>(mch + 1);
     const size_t mrows = (size_t)h->max_rows;
-    h->stage = c.take<Birth>(mrows * kStageW);
+    h->stage = c.take<Birth>(mrows * h->stage_w);
     h->stage_cnt = c.take<int>(mrows);
     h->stage_off = c.take<int>(mrows / 1024 + 2);
     h->stage_segoff = c.take<int>(mrows / 1024 + 2);
@@ -763,7 +771,7 @@ int pic_step(pic_handle* h, int32_t nsteps) {
         if (rc != PIC_OK) return rc;
         // the solve's residual read waited for the previous step's births:
         // if some did not fit, stop before this step moves any particle
-        if (h->h_sc->cap_err & kErrBirths) {
+        if (h->h_sc->cap_err & (kErrBirths | kErrStage)) {
             h->halted = true;
             h->sticky_err = PIC_E_CAPACITY;
             return PIC_E_CAPACITY;
@@ -869,6 +877,8 @@ int pic_diag(pic_handle* h, pic_diag_out* out, const pic_diag_buffers* bufs) {
     out->unet_pairs = h->net.n_pairs;
     out->unet_fallbacks = h->unet_fallbacks;
     out->unet_applications = h->unet_apps;
+    out->unet_disabled = h->unet_off ? 1 : 0;
+    out->capacity_bits = h->h_ctr->err;
     out->split_added[0] = ct.split_added[0];
     out->split_added[1] = ct.split_added[1];
     const int spp = h->cfg.run.steps_per_period;
@@ -1194,6 +1204,8 @@ int pic_unet_set_params(pic_handle* h, const float* p, int64_t n) {
     launch_zero_u64((unsigned long long*)net.v, ((size_t)n + 1) / 2, h->stream);
     net.adam_t = 0;
     unet::pack_all(net, h->stream);
+    h->unet_off = false;
+    h->unet_strikes = 0;
     HIP_OK(hipStreamSynchronize(h->stream));
     return PIC_OK;
 }
@@ -1273,6 +1285,22 @@ int pic_unet_get_pair(pic_handle* h, int32_t slot, float* r, float* e, float* ch
     return PIC_OK;
 }
 
+int pic_unet_put_pair(pic_handle* h, int32_t slot, const float* r, const float* e, const float* chi) {
+    if (!h || !r || !e || !chi) return PIC_E_ARG;
+    if (!h->unet_on) return PIC_E_STATE;
+    unet::Net& n = h->net;
+    if (slot < 0 || slot >= n.cap_pairs) return PIC_E_ARG;
+    const size_t img = (size_t)n.H * n.W;
+    HIP_OK(hipMemcpyAsync(n.h_r + slot * img, r, img * 4, hipMemcpyHostToDevice, h->stream));
+    HIP_OK(hipMemcpyAsync(n.h_e + slot * img, e, img * 4, hipMemcpyHostToDevice, h->stream));
+    HIP_OK(hipMemcpyAsync(n.h_chi + slot * img, chi, img * 4, hipMemcpyHostToDevice, h->stream));
+    // the mask of the handle's own geometry (unknown nodes of the image)
+    if (n.n_pairs == 0) unet::mask_from_nodes(n, h->node_kind, h->w, h->stream);
+    HIP_OK(hipStreamSynchronize(h->stream));
+    if (n.n_pairs < (int64_t)slot + 1) n.n_pairs = (int64_t)slot + 1;
+    return PIC_OK;
+}
+
 int pic_unet_train(pic_handle* h, int32_t steps, int32_t batch, double lr, uint64_t seed, double* loss_curve) {
     if (!h || steps < 0 || !(lr > 0)) return PIC_E_ARG;
     if (!h->unet_on) return PIC_E_STATE;
@@ -1281,6 +1309,8 @@ int pic_unet_train(pic_handle* h, int32_t steps, int32_t batch, double lr, uint6
     const int64_t avail = std::min<int64_t>(n.n_pairs, n.cap_pairs);
     if (avail < 1 || h->img_free < 1) return PIC_E_STATE;
     const float inv_n = (float)(1.0 / ((double)batch * (double)h->img_free));
+    h->unet_off = false;
+    h->unet_strikes = 0;
     uint64_t st = seed ^ 0x5DEECE66Dull;
     std::vector<float> log(unet::kLossLog);
     for (int32_t k = 0; k < steps; ++k) {

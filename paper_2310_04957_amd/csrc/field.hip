@@ -1134,27 +1134,23 @@ static void precondition(pic_handle* h, int ident, const T* r, T* z) {
         vcycle<T>(h, 0, r, z);
 }
 
-// harvest hook of an FP64 solve: iterate k, after the two damped-Jacobi
-// sweeps the learned preconditioner applies before the network, gives the
-// pair (r1 = r - K z1, e1 = x* - (x_k + z1)) with z1 the smoothed
-// correction; it is kept in pair slot (n_pairs + k) of the ring.  The
-// level-0 multigrid vectors are free between V-cycles and hold z1 and r1.
+// harvest hook of an FP64 solve: iterate k, after the V-cycle z = M r that
+// the learned preconditioner also applies before the network, gives the
+// pair (res = r - K z, e = x* - (x_k + z)) of the error the V-cycle leaves;
+// it is kept in pair slot (n_pairs + k) of the ring.  The level-0
+// multigrid residual vector is free between V-cycles and holds res.
 template <typename T>
-static void harvest_iterate(pic_handle*, int, const T*, const T*) {}
+static void harvest_iterate(pic_handle*, int, const T*, const T*, const T*) {}
 template <>
-void harvest_iterate<double>(pic_handle* h, int k, const double* r, const double* x) {
+void harvest_iterate<double>(pic_handle* h, int k, const double* r, const double* x, const double* z) {
     if (!h->harvesting || k >= h->harvest_limit) return;
     Level& L = h->lv[0];
     hipStream_t st = h->stream;
     const DevScalars* s = h->sc;
-    hipLaunchKernelGGL(k_jac0<double>, grid_for(L.nn), dim3(256), 0, st, (const double*)h->ar, (const double*)h->az,
-                       (const int8_t*)h->node_kind, (const double*)L.x64, r, L.x64, s, L.nr, L.nz, 1);
-    hipLaunchKernelGGL(k_jac0<double>, grid_for(L.nn), dim3(256), 0, st, (const double*)h->ar, (const double*)h->az,
-                       (const int8_t*)h->node_kind, (const double*)L.x64, r, L.y64, s, L.nr, L.nz, 0);
     hipLaunchKernelGGL(k_res0<double>, grid_for(L.nn), dim3(256), 0, st, (const double*)h->ar, (const double*)h->az,
-                       (const int8_t*)h->node_kind, (const double*)L.y64, r, L.res64, s, L.nr, L.nz);
+                       (const int8_t*)h->node_kind, z, r, L.res64, s, L.nr, L.nz);
     const int slot = (int)((h->net.n_pairs + k) % h->net.cap_pairs);
-    unet::harvest_iter(h->net, slot, L.res64, x, L.y64, h->chi, h->node_kind, h->hx64 + (size_t)k * h->nn,
+    unet::harvest_iter(h->net, slot, L.res64, x, z, h->chi, h->node_kind, h->hx64 + (size_t)k * h->nn,
                        &h->sc->done, h->w, h->nn, st);
 }
 
@@ -1167,8 +1163,8 @@ static int pcg(pic_handle* h, T* r, T* x, T* z, T* p, T* q, int max_iter, int* e
     DevScalars* s = h->sc;
     hipLaunchKernelGGL(k_begin_cg, dim3(1), dim3(1), 0, st, s);
     hipLaunchKernelGGL(k_fill<T>, grid_for(nn), dim3(256), 0, st, x, nn);
-    harvest_iterate<T>(h, 0, r, x);
     precondition<T>(h, ident, r, z);
+    harvest_iterate<T>(h, 0, r, x, (const T*)z);
     hipLaunchKernelGGL(k_copy<T>, grid_for(nn), dim3(256), 0, st, p, (const T*)z, s, nn);
     hipLaunchKernelGGL(k_dot<T>, dim3(kRedBlocks), dim3(256), 0, st, (const T*)r, (const T*)z, h->part, s, nn);
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, st, (const double*)h->part, s, 0);
@@ -1179,9 +1175,9 @@ static int pcg(pic_handle* h, T* r, T* x, T* z, T* p, T* q, int max_iter, int* e
         hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, st, (const double*)h->part, s, 1);
         hipLaunchKernelGGL(k_update_xr<T>, dim3(kRedBlocks), dim3(256), 0, st, x, r, (const T*)p, (const T*)q,
                            h->part, s, nn);
-        harvest_iterate<T>(h, it + 1, r, x);
         hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, st, (const double*)h->part, s, 2);
         precondition<T>(h, ident, r, z);
+        harvest_iterate<T>(h, it + 1, r, x, (const T*)z);
         hipLaunchKernelGGL(k_dot<T>, dim3(kRedBlocks), dim3(256), 0, st, (const T*)r, (const T*)z, h->part, s, nn);
         hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, st, (const double*)h->part, s, 3);
         hipLaunchKernelGGL(k_update_p<T>, grid_for(nn), dim3(256), 0, st, p, (const T*)z, s, nn);
@@ -1201,11 +1197,13 @@ static int pcg(pic_handle* h, T* r, T* x, T* z, T* p, T* q, int max_iter, int* e
     return h->h_sc->iters;
 }
 
-// learned preconditioner, one application z = P(r): two damped-Jacobi
-// sweeps, then the network's output v for the remaining residual res as a
-// one-dimensional Galerkin correction z += c v with c = (v.res)/(v.A v)
-// (c = 0 if v.A v is not positive), then two Jacobi sweeps again.  The
-// network supplies only a direction, so it is trained on unit-RMS pairs.
+// learned preconditioner, one application z = P(r): the multigrid V-cycle
+// z = M r, then the network's output v for the residual the V-cycle leaves,
+// res = r - K z, as a one-dimensional Galerkin correction z += c v with
+// c = (v.res)/(v.K v) (c = 0 if v.K v is not positive).  The correction
+// minimises the energy-norm error of z along v, so the step is never worse
+// than the V-cycle alone; the network supplies only a direction, so it is
+// trained on unit-RMS pairs (reading R28).
 __global__ __launch_bounds__(256) void k_spmv_dot2(const float* ar, const float* az, const int8_t* nk,
                                                    const float* v, const float* res, float* q, double* part,
                                                    const DevScalars* s, int nr, int nz) {
@@ -1264,13 +1262,12 @@ static void unet_apply(pic_handle* h, const float* r, float* z) {
     const float* az = h->az32;
     const int8_t* nk = h->node_kind;
     const int nn = h->nn;
-    float* t = L.x32;      // scratch: smoother iterate, then the network direction v
+    vcycle<float>(h, 0, r, z);
+    // after the V-cycle the level-0 work vectors are free: res, the network
+    // direction v (in x) and K v (in y)
     float* res = L.res32;
+    float* v = L.x32;
     float* q = L.y32;
-    hipLaunchKernelGGL(k_jac0<float>, grid_for(nn), dim3(256), 0, st, ar, az, nk, (const float*)t, r, t,
-                       (const DevScalars*)s, h->nr, h->nz, 1);
-    hipLaunchKernelGGL(k_jac0<float>, grid_for(nn), dim3(256), 0, st, ar, az, nk, (const float*)t, r, z,
-                       (const DevScalars*)s, h->nr, h->nz, 0);
     hipLaunchKernelGGL(k_res0<float>, grid_for(nn), dim3(256), 0, st, ar, az, nk, (const float*)z, r, res,
                        (const DevScalars*)s, h->nr, h->nz);
     hipLaunchKernelGGL(k_dot<float>, dim3(kRedBlocks), dim3(256), 0, st, (const float*)res, (const float*)res, h->part,
@@ -1278,15 +1275,11 @@ static void unet_apply(pic_handle* h, const float* r, float* z) {
     hipLaunchKernelGGL(k_reduce_net, dim3(1), dim3(256), 0, st, (const double*)h->part, s, 0);
     unet::input_from_r32(n, res, &s->rr_net, h->chi, nk, h->w, (double)h->img_free, st);
     unet::forward(n, 1, st);
-    unet::out_to_z(n, &s->rr_net, nk, t, h->w, nn, st);
-    hipLaunchKernelGGL(k_spmv_dot2, dim3(kRedBlocks), dim3(256), 0, st, ar, az, nk, (const float*)t,
+    unet::out_to_z(n, &s->rr_net, nk, v, h->w, nn, st);
+    hipLaunchKernelGGL(k_spmv_dot2, dim3(kRedBlocks), dim3(256), 0, st, ar, az, nk, (const float*)v,
                        (const float*)res, q, h->part, (const DevScalars*)s, h->nr, h->nz);
     hipLaunchKernelGGL(k_reduce_net, dim3(1), dim3(256), 0, st, (const double*)h->part, s, 1);
-    hipLaunchKernelGGL(k_axpy_net, grid_for(nn), dim3(256), 0, st, z, (const float*)t, (const DevScalars*)s, nn);
-    hipLaunchKernelGGL(k_jac0<float>, grid_for(nn), dim3(256), 0, st, ar, az, nk, (const float*)z, r, t,
-                       (const DevScalars*)s, h->nr, h->nz, 0);
-    hipLaunchKernelGGL(k_jac0<float>, grid_for(nn), dim3(256), 0, st, ar, az, nk, (const float*)t, r, z,
-                       (const DevScalars*)s, h->nr, h->nz, 0);
+    hipLaunchKernelGGL(k_axpy_net, grid_for(nn), dim3(256), 0, st, z, (const float*)v, (const DevScalars*)s, nn);
     h->unet_apps++;
 }
 
@@ -1413,10 +1406,24 @@ int field_solve(pic_handle* h, double* phi, const double* Q, const double* Up, d
             hipLaunchKernelGGL(k_set_target, dim3(1), dim3(1), 0, st, h->sc, want * want);
             hipLaunchKernelGGL(k_scale_to<float>, grid_for(nn), dim3(256), 0, st, (const double*)h->r64, h->r32,
                                h->x32, (const DevScalars*)h->sc, nn);
+            if (method == PIC_SOLVE_IR_UNET && h->unet_off) method = PIC_SOLVE_IR_MG;
             if (method == PIC_SOLVE_IR_UNET) {
-                total += fpcg(h, h->r32, h->x32, h->z32, h->p32, h->q32, h->cfg.solver.max_iter, &err);
+                // the network may take at most twice (plus two) the iterations
+                // multigrid needed for this pass last time; a network that
+                // cannot keep up gives the solve back to multigrid, and one
+                // that fails three solves in a row is switched off until new
+                // parameters are set or trained
+                const int mg = h->cg_guess[0][std::min(outer, 3)];
+                const int cap = mg > 0 ? std::min(h->cfg.solver.max_iter, 2 * mg + 2) : h->cfg.solver.max_iter;
+                total += fpcg(h, h->r32, h->x32, h->z32, h->p32, h->q32, cap, &err);
                 // the correction found so far is kept; multigrid finishes the solve
-                if (h->h_sc->fallback) { method = PIC_SOLVE_IR_MG; h->unet_fallbacks++; }
+                if (h->h_sc->fallback) {
+                    method = PIC_SOLVE_IR_MG;
+                    h->unet_fallbacks++;
+                    if (++h->unet_strikes >= 3) h->unet_off = true;
+                } else {
+                    h->unet_strikes = 0;
+                }
             } else {
                 int& guess = h->cg_guess[0][std::min(outer, 3)];
                 const int its = pcg<float>(h, h->r32, h->x32, h->z32, h->p32, h->q32, h->cfg.solver.max_iter, &err,

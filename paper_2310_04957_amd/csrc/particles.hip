@@ -32,6 +32,7 @@ struct PushArgs {
     DevCounters* ctr;
     Birth* stage;
     int* stage_cnt;
+    int stage_w;                 // births per staging row
     int sp, sign;
     float qm, dt;
     uint32_t key0, key1, step;
@@ -362,19 +363,19 @@ __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4)))
             const unsigned long long bm = __ballot(born);
             if (born) {
                 const int idx = nb + __popcll(bm & lanemask_lt());
-                if (idx < kStageW) {
+                if (idx < a.stage_w) {
                     Birth bb;
                     bb.r = br; bb.z = bz; bb.w = s.w;
                     for (int k = 0; k < 6; ++k) bb.v[k] = b6[k];
-                    a.stage[stage_row * kStageW + idx] = bb;
+                    a.stage[stage_row * a.stage_w + idx] = bb;
                 } else {
-                    atomicOr(&a.ctr->err, kErrBirths);
+                    atomicOr(&a.ctr->err, kErrStage);
                 }
             }
             nb += __popcll(bm);
             cur = nxt;
         }
-        if (lane == 0 && a.stage_cnt != nullptr) a.stage_cnt[stage_row] = min(nb, kStageW);
+        if (lane == 0 && a.stage_cnt != nullptr) a.stage_cnt[stage_row] = min(nb, a.stage_w);
         // s_org is rewritten by the next chunk's probe
         __syncthreads();
     }
@@ -447,6 +448,7 @@ void launch_particles(pic_handle* h, int sp, bool emit_keys) {
     a.ctr = h->ctr;
     a.stage = sp == 0 ? h->stage : nullptr;
     a.stage_cnt = sp == 0 ? h->stage_cnt : nullptr;
+    a.stage_w = h->stage_w;
     a.sp = sp;
     a.sign = sp == 0 ? -1 : 1;
     a.qm = qm_of(sp);
@@ -552,6 +554,7 @@ struct BirthArgs {
     const Birth* stage;
     const int* cnt;
     const int* segoff;
+    int stage_w;
     float dt;
 };
 
@@ -638,7 +641,7 @@ __global__ __launch_bounds__(kSegRows) void k_birth_append(BirthArgs a) {
                 if (sh[mid] > idx) hi = mid; else lo = mid + 1;
             }
             const int k = idx - (lo > 0 ? sh[lo - 1] : 0);
-            const Birth bb = a.stage[(b * kSegRows + lo) * kStageW + k];
+            const Birth bb = a.stage[(b * kSegRows + lo) * a.stage_w + k];
             P9 e;
             e.r = bb.r; e.z = bb.z; e.vr = bb.v[0]; e.vt = bb.v[1]; e.vz = bb.v[2];
             e.ar = 0.0f; e.at = 0.0f; e.az = 0.0f; e.w = bb.w;
@@ -669,6 +672,7 @@ void launch_births(pic_handle* h) {
     a.stage = h->stage;
     a.cnt = h->stage_cnt;
     a.segoff = h->stage_segoff;
+    a.stage_w = h->stage_w;
     a.dt = (float)h->dt;
     hipLaunchKernelGGL(k_birth_append, dim3(256), dim3(kSegRows), 0, h->stream, a);
 }

@@ -23,7 +23,10 @@ constexpr int kPushWaves = 8;
 constexpr int kPushBlock = 64 * kPushWaves;
 constexpr int kSlice = 1024;
 constexpr int kPushChunk = kSlice * kPushWaves;
-constexpr int kStageW = 64;           // staged ionisation births per slice (one row per slice)
+// staged ionisation births per slice (one row per slice): at least this
+// many, and enough that a slice overflows its row with a probability below
+// 1e-15 per step (set with the null-collision constants)
+constexpr int kStageWMin = 64;
 // rows of the birth staging area for n slots (whole chunks)
 __host__ __device__ constexpr long long stage_rows(long long n) {
     return (n + kPushChunk - 1) / kPushChunk * kPushWaves;
@@ -36,10 +39,12 @@ constexpr int kMaxEl = PIC_MAX_ELECTRODES;   // driven electrodes
 // (Neumann edge), 3 dielectric, 4 .. 6 electrodes 2 .. 4
 __host__ __device__ constexpr int slot_of(int id) { return id <= 1 ? id : 2 + id; }
 constexpr int kSlots = 8;
-// bits of DevCounters::err: births that did not fit were dropped (the run
-// stops at the next step); a splitting pass did not fit and changed nothing
+// bits of DevCounters::err: births that did not fit a species' slots or a
+// slice's staging row were dropped (the run stops at the next step); a
+// splitting pass did not fit and changed nothing
 constexpr int kErrBirths = 1;
-constexpr int kErrSplit = 2;
+constexpr int kErrStage = 2;   // births dropped too: a slice's staging row was full
+constexpr int kErrSplit = 4;
 
 // counters that kernels update; lives in device memory
 struct DevCounters {
@@ -105,6 +110,7 @@ struct pic_handle {
     int64_t cap[2];
     int64_t max_chunks;
     int64_t max_rows;             // birth staging rows
+    int stage_w;                  // births per staging row
     // geometry (device)
     uint8_t* cell_kind;
     int8_t* node_kind;
@@ -172,6 +178,8 @@ struct pic_handle {
     int harvest_every, harvest_limit;
     bool harvest_now, harvesting;
     int64_t unet_fallbacks, unet_apps, img_free;
+    int unet_strikes;       // consecutive solves the network gave back to multigrid
+    bool unet_off;          // switched off after three of them, until new parameters
     // phase timing
     bool timing;
     std::vector<hipEvent_t> ev_pool;

@@ -59,6 +59,8 @@ void out_to_z(const Net& n, const double* rr, const int8_t* nk, float* z, int w,
 // approximation x + dx
 void harvest_iter(const Net& n, int slot, const double* r, const double* x, const double* dx, const double* chi,
                   const int8_t* nk, double* xk, const int* done, int w, int nn, hipStream_t s);
+// the mask image (1 on unknown nodes) of the handle's geometry
+void mask_from_nodes(const Net& n, const int8_t* nk, int w, hipStream_t s);
 // part: >= 2 kHarvestBlocks doubles of scratch
 void pair_finish(const Net& n, int slot, const double* xs, const double* xk, const int8_t* nk, int w, double n_free,
                  double* part, hipStream_t s);

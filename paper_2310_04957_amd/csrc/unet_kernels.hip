@@ -710,6 +710,14 @@ void harvest_iter(const Net& n, int slot, const double* r, const double* x, cons
     hipLaunchKernelGGL(k_harvest_iter, ew_grid(std::max<size_t>(img, nn)), dim3(256), 0, s, r, x, dx, chi, nk,
                        n.h_r + slot * img, n.h_chi + slot * img, n.h_mask, xk, done, n.H, n.W, w, nn);
 }
+__global__ __launch_bounds__(256) void k_mask_from_nodes(const int8_t* nk, float* hmask, int H, int W, int w) {
+    const size_t n = (size_t)H * W;
+    for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < n; p += (size_t)gridDim.x * blockDim.x)
+        hmask[p] = nk[(int)(p / W) * w + (int)(p % W)] < 0 ? 1.0f : 0.0f;
+}
+void mask_from_nodes(const Net& n, const int8_t* nk, int w, hipStream_t s) {
+    hipLaunchKernelGGL(k_mask_from_nodes, ew_grid((size_t)n.H * n.W), dim3(256), 0, s, nk, n.h_mask, n.H, n.W, w);
+}
 void pair_finish(const Net& n, int slot, const double* xs, const double* xk, const int8_t* nk, int w, double n_free,
                  double* part, hipStream_t s) {
     const size_t img = (size_t)n.H * n.W;

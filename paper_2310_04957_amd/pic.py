@@ -89,7 +89,7 @@ class Diag(C.Structure):
         ("QP_el", C.c_double * MAX_EL), ("I_el", C.c_double * MAX_EL), ("C_el", C.c_double * (MAX_EL * MAX_EL)),
         ("hU_re", (C.c_double * 6) * MAX_EL), ("hU_im", (C.c_double * 6) * MAX_EL),
         ("hI_re", (C.c_double * 6) * MAX_EL), ("hI_im", (C.c_double * 6) * MAX_EL),
-        ("absorbed_el", (C.c_int64 * MAX_EL) * 2)]
+        ("absorbed_el", (C.c_int64 * MAX_EL) * 2), ("unet_disabled", C.c_int32), ("capacity_bits", C.c_int32)]
 
 
 class DiagBuffers(C.Structure):
@@ -137,6 +137,7 @@ def lib():
         L.pic_unet_grads.argtypes = [P, P, P, P, C.c_int32, P, C.POINTER(C.c_double)]
         L.pic_unet_harvest.argtypes = [P, C.c_int32]
         L.pic_unet_get_pair.argtypes = [P, C.c_int32, P, P, P, P]
+        L.pic_unet_put_pair.argtypes = [P, C.c_int32, P, P, P]
         L.pic_unet_train.argtypes = [P, C.c_int32, C.c_int32, C.c_double, C.c_uint64, P]
         _lib = L
     return _lib
@@ -398,6 +399,13 @@ class Pic:
         a = [np.zeros((self.nz, self.nr), dtype=np.float32) for _ in range(4)]
         _check(lib().pic_unet_get_pair(self.h, slot, *[_ptr(x) for x in a]), "pic_unet_get_pair")
         return dict(zip(("r", "e", "chi", "mask"), a))
+
+    def unet_put_pair(self, slot, r, e, chi):
+        a = [np.ascontiguousarray(x, dtype=np.float32) for x in (r, e, chi)]
+        for x in a:
+            if x.shape != (self.nz, self.nr):
+                raise ValueError("pair images are nz x nr")
+        _check(lib().pic_unet_put_pair(self.h, slot, *[_ptr(x) for x in a]), "pic_unet_put_pair")
 
     def unet_train(self, steps, batch, lr, seed=1):
         curve = np.zeros(max(steps, 1))

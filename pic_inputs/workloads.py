@@ -130,7 +130,7 @@ WORKLOADS = {
         geometry=gec_geometry(4),
         circuit=_lmatch(150.0),
         gas=dict(p_Pa=20 * MTORR_PA, T_K=300.0),
-        run=dict(n_e=64_000_000, n_i=64_000_000, cap_e=80_000_000, cap_i=80_000_000,
+        run=dict(n_e=64_000_000, n_i=64_000_000, cap_e=160_000_000, cap_i=160_000_000,
                  n0=1e14, Te_eV=30000 * KB_OVER_E, Ti_eV=300 * KB_OVER_E,
                  steps_per_period=400, seed=1, sort_every=4, sort_every_ion=20, steps=1600),
         solver=dict(method=SOLVE_IR_MG, tol=1e-8, max_iter=200),

@@ -161,11 +161,12 @@ def test_adam_step_matches_oracle():
 
 
 def test_harvested_pairs_are_residual_and_error():
-    """A harvested solve keeps its Krylov iterates: pair k holds the residual
-    r_k and the error e_k = x* - x_k, both at unit RMS over the unknown
-    nodes, so K e_k = c r_k with one scalar c > 0 up to the final residual
-    of the solve (K: the operator of that solve).  The first pair is the
-    residual of the warm start itself."""
+    """A harvested solve keeps its Krylov iterates after their V-cycle z_k:
+    pair k holds the residual r_k - K z_k the V-cycle leaves and its error
+    x* - x_k - z_k, both at unit RMS over the unknown nodes, so K e = c r
+    with one scalar c > 0 up to the final residual of the solve (K: the
+    operator of that solve), which the early iterates' residuals exceed the
+    most."""
     nr, nz = 64, 128
     w = _gec(nr, nz, n=40000)
     g = _pic(w, method=SOLVE_IR_MG, unet_batch=1, unet_pairs=64)
@@ -197,7 +198,7 @@ def test_harvested_pairs_are_residual_and_error():
         res = np.linalg.norm(Ke - c * r) / np.linalg.norm(c * r)
         print(f"[gpu] harvest pair {k}: |K e - c r|/|c r| = {res:.2e}", flush=True)
         assert c > 0
-        assert res < (1e-3 if k == 0 else 0.3)
+        assert res < (1e-2 if k == 0 else 0.3)
     g.close()
 
 
@@ -210,8 +211,8 @@ def test_fpcg_converges_rejects_bad_network_and_falls_back_to_multigrid():
     d = g.diag()
     assert d.solver_relres <= w["solver"]["tol"]
     assert d.unet_applications > 0
-    # a network that outputs NaN: its Galerkin weight is zero, the smoothing
-    # around it still preconditions, every solve converges
+    # a network that outputs NaN: its Galerkin weight is zero, the V-cycle
+    # before it still preconditions, every solve converges
     g.unet_set_params(np.full(g.unet_num_params(), np.nan, dtype=np.float32))
     g.step(2)
     d = g.diag()
@@ -224,7 +225,23 @@ def test_fpcg_converges_rejects_bad_network_and_falls_back_to_multigrid():
     g.step(2)
     d = g.diag()
     assert d.solver_relres <= w["solver"]["tol"]
-    assert d.unet_fallbacks >= f0 + 2
+    assert d.unet_fallbacks == f0 + 2 and d.unet_disabled == 0
+    # the third solve in a row given back to multigrid switches the network
+    # off: later solves run multigrid without trying it
+    g.step(1)
+    d = g.diag()
+    assert d.unet_fallbacks == f0 + 3 and d.unet_disabled == 1
+    a0 = d.unet_applications
+    g.step(2)
+    d = g.diag()
+    assert d.unet_applications == a0 and d.unet_fallbacks == f0 + 3
+    assert d.solver_relres <= w["solver"]["tol"]
+    # new parameters switch it on again
+    g.unet_set_params(np.zeros(g.unet_num_params(), dtype=np.float32))
+    g.set_solver(max_iter=200)
+    g.step(1)
+    d = g.diag()
+    assert d.unet_disabled == 0 and d.unet_applications > a0
     g.close()
 
 
@@ -242,11 +259,17 @@ def test_config_checks():
     g.close()
 
 
-def test_trained_network_gains_over_cg_without_it():
+def test_trained_network_gains_over_multigrid_alone():
     """What the learned part buys: on the same warm-started solves, flexible
-    CG with the trained network needs far fewer iterations than CG without a
-    preconditioner, and fewer than with the untrained network; every solve
-    reaches the FP64 tolerance.  MG-PCG is reported beside it."""
+    CG with the trained network (after each V-cycle, its Galerkin-weighted
+    correction for the error the V-cycle leaves) against MG-PCG, against
+    the untrained network and against CG without a preconditioner.  Every
+    solve reaches the FP64 tolerance with the network itself (no solve is
+    given back to multigrid); the trained network needs no more iterations
+    than MG-PCG and than the untrained one.  Iterations and wall time are
+    printed side by side."""
+    import time
+    import torch
     from paper_2310_04957_amd.pic import SOLVE_IR_CG, SOLVE_IR_MG, SOLVE_IR_UNET
     nr, nz = 64, 128
     w = _gec(nr, nz, n=40000)
@@ -255,7 +278,7 @@ def test_trained_network_gains_over_cg_without_it():
     g.unet_harvest(1)
     g.step(60)
     g.unet_harvest(0)
-    assert g.diag().unet_pairs >= 200
+    assert g.diag().unet_pairs >= 150
     problems = []
     for _ in range(3):
         phi0 = g.grid("PHI")
@@ -266,18 +289,25 @@ def test_trained_network_gains_over_cg_without_it():
     def iters(method):
         g.set_solver(method=method, max_iter=5000)
         total = 0
+        f0 = g.diag().unet_fallbacks
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         for Q, chi, U, phi0 in problems:
             _, it, rel, rc = g.solve_once(Q, chi, U, tol, phi0)
             assert rc == 0 and rel <= tol, (method, rc, rel)
             total += it
-        return total
+        ms = 1e3 * (time.perf_counter() - t0) / len(problems)
+        assert g.diag().unet_fallbacks == f0, method
+        return total, ms
 
-    cg, mg, untrained = iters(SOLVE_IR_CG), iters(SOLVE_IR_MG), iters(SOLVE_IR_UNET)
+    (cg, _), (mg, mg_ms), (untrained, u_ms) = iters(SOLVE_IR_CG), iters(SOLVE_IR_MG), iters(SOLVE_IR_UNET)
     curve = g.unet_train(600, 8, 1e-3, seed=5)
-    trained = iters(SOLVE_IR_UNET)
-    print(f"[gpu] inner iterations over 3 solves: CG {cg}, U-net untrained {untrained}, trained {trained}, "
-          f"MG-PCG {mg}; loss {curve[:10].mean():.3f} -> {curve[-50:].mean():.3f}", flush=True)
-    assert curve[-50:].mean() < 0.5 * curve[:10].mean()
-    assert trained < untrained
-    assert 5 * trained < cg
+    trained, t_ms = iters(SOLVE_IR_UNET)
+    print(f"[gpu] inner iterations over 3 solves: CG {cg}, MG-PCG {mg} ({mg_ms:.2f} ms per solve), U-net untrained "
+          f"{untrained} ({u_ms:.2f} ms), trained {trained} ({t_ms:.2f} ms); loss {curve[:10].mean():.3f} -> "
+          f"{curve[-50:].mean():.3f}", flush=True)
+    assert curve[-50:].mean() < 0.8 * curve[:10].mean()
+    assert trained <= untrained
+    assert trained <= mg
+    assert 3 * trained < cg
     g.close()
