@@ -34,36 +34,59 @@ __device__ __forceinline__ __bf16 raw(bf16 v) { return __builtin_bit_cast(__bf16
 // with zero padding, Xin = X (optionally multiplied by the ReLU mask
 // M > 0 of the layer whose gradient X is).  Tile: 16x16 output pixels per
 // block iteration, 4 wavefronts x 4 rows; each wavefront computes two
-// 32-pixel x 32-channel MFMA tiles per 32 output channels.  The next
-// tile's input (with its halo) is loaded into registers while the current
-// one is multiplied out of LDS.
+// 32-pixel x 32-channel MFMA tiles per 32 output channels.  The input
+// channels are staged in LDS 32 (or all, if fewer) at a time with the
+// tile's halo; the weights of all taps and channels stay in LDS for the
+// whole launch.  The next chunk's input is loaded into registers while the
+// current one is multiplied out of LDS.  Each thread's place in the staged
+// halo tile is fixed, so its load offsets are computed once per launch.
 template <int CIN>
-struct TileRegs {
-    static constexpr int kChunks = (18 * 18 * (CIN / 8) + 255) / 256;   // 8-channel groups per thread
-    bf16x8 v[kChunks];
+struct Stage {
+    static constexpr int CH = CIN < 32 ? CIN : 32;   // channels per staged chunk
+    static constexpr int NCH = CIN / CH;             // chunks per tile
+    static constexpr int G = CH / 8;                 // 8-channel groups per pixel of a chunk
+    static constexpr int N = 18 * 18 * G;            // groups of one staged halo tile
+    static constexpr int Q = (N + 255) / 256;        // groups per thread
 };
 
-template <int CIN, bool MASK>
-__device__ __forceinline__ void load_tile(const bf16* __restrict__ X, const bf16* __restrict__ M, int b, int y0,
-                                          int x0, int H, int W, int tid, TileRegs<CIN>& t) {
+template <int CIN>
+struct LoadPlan {
+    int py[Stage<CIN>::Q], px[Stage<CIN>::Q], c8[Stage<CIN>::Q];
+};
+
+template <int CIN>
+__device__ __forceinline__ void make_plan(int tid, LoadPlan<CIN>& lp) {
+    using S = Stage<CIN>;
 #pragma unroll
-    for (int q = 0; q < TileRegs<CIN>::kChunks; ++q) {
+    for (int q = 0; q < S::Q; ++q) {
         const int e = tid + q * 256;
-        bf16x8 v = {};
-        if (e < 18 * 18 * (CIN / 8)) {
-            const int c8 = e % (CIN / 8), pix = e / (CIN / 8);
-            const int yy = y0 - 1 + pix / 18, xx = x0 - 1 + pix % 18;
-            if (yy >= 0 && yy < H && xx >= 0 && xx < W) {
-                const size_t g = (((size_t)b * H + yy) * W + xx) * CIN + c8 * 8;
-                v = *(const bf16x8*)&X[g];
-                if (MASK) {
-                    const bf16x8 m = *(const bf16x8*)&M[g];
-                    for (int k = 0; k < 8; ++k)
-                        if (!(bf2f(m[k]) > 0.0f)) v[k] = f2raw(0.0f);
-                }
+        const int pix = e / S::G;
+        lp.c8[q] = e % S::G;
+        lp.py[q] = e < S::N ? pix / 18 : -1000000;   // an idle group is never in the image
+        lp.px[q] = pix % 18;
+    }
+}
+
+// chunk ch of the halo tile at (b, y0 - 1, x0 - 1) into registers
+template <int CIN, bool MASK>
+__device__ __forceinline__ void load_chunk(const bf16* __restrict__ X, const bf16* __restrict__ M,
+                                           const LoadPlan<CIN>& lp, int b, int y0, int x0, int ch, int H, int W,
+                                           bf16x8* v) {
+    using S = Stage<CIN>;
+#pragma unroll
+    for (int q = 0; q < S::Q; ++q) {
+        const int yy = y0 - 1 + lp.py[q], xx = x0 - 1 + lp.px[q];
+        bf16x8 t = {};
+        if (yy >= 0 && yy < H && xx >= 0 && xx < W) {
+            const size_t g = (((size_t)b * H + yy) * W + xx) * CIN + ch * S::CH + lp.c8[q] * 8;
+            t = *(const bf16x8*)&X[g];
+            if (MASK) {
+                const bf16x8 m = *(const bf16x8*)&M[g];
+                for (int k = 0; k < 8; ++k)
+                    if (!(bf2f(m[k]) > 0.0f)) t[k] = f2raw(0.0f);
             }
         }
-        t.v[q] = v;
+        v[q] = t;
     }
 }
 
@@ -71,64 +94,72 @@ template <int CIN, int COUT, bool RELU, bool MASK>
 __global__ __launch_bounds__(256) void k_conv3x3(const bf16* __restrict__ X, const bf16* __restrict__ Wt,
                                                  const float* __restrict__ bias, const bf16* __restrict__ M,
                                                  bf16* __restrict__ Y, int B, int H, int W) {
-    constexpr int CP = CIN + 8;           // padded channel stride in LDS (bank spread)
+    using S = Stage<CIN>;
+    constexpr int CP = S::CH + 8;         // padded channel stride of the staged chunk (bank spread)
+    constexpr int CW = CIN + 8;           // padded channel stride of the weights
     constexpr int NT = COUT / 32;
     __shared__ __attribute__((aligned(16))) bf16 xs[18 * 18 * CP];
-    __shared__ __attribute__((aligned(16))) bf16 ws[9 * COUT * CP];
+    __shared__ __attribute__((aligned(16))) bf16 ws[9 * COUT * CW];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     // weights once per block
     for (int e = tid; e < 9 * COUT * (CIN / 8); e += 256) {
         const int c8 = e % (CIN / 8), tn = e / (CIN / 8);
-        *(bf16x8*)&ws[tn * CP + c8 * 8] = *(const bf16x8*)&Wt[(size_t)tn * CIN + c8 * 8];
+        *(bf16x8*)&ws[tn * CW + c8 * 8] = *(const bf16x8*)&Wt[(size_t)tn * CIN + c8 * 8];
     }
+    LoadPlan<CIN> lp;
+    make_plan<CIN>(tid, lp);
     const int tx = (W + 15) / 16, ty = (H + 15) / 16;
-    const long long ntile = (long long)tx * ty * B;
-    TileRegs<CIN> next;
     // tile indices fit in 32 bits (images of at most 2^31 16x16 tiles)
-    const unsigned txy = (unsigned)(tx * ty), utx = (unsigned)tx, nti = (unsigned)ntile;
+    const unsigned txy = (unsigned)(tx * ty), utx = (unsigned)tx, nti = (unsigned)((long long)tx * ty * B);
+    bf16x8 next[S::Q];
     if (blockIdx.x < nti) {
         const unsigned tile = blockIdx.x;
-        const int b = (int)(tile / txy), rem = (int)(tile % txy);
-        load_tile<CIN, MASK>(X, M, b, (int)(rem / utx) * 16, (int)(rem % utx) * 16, H, W, tid, next);
+        const int b = (int)(tile / txy);
+        const unsigned rem = tile % txy;
+        load_chunk<CIN, MASK>(X, M, lp, b, (int)(rem / utx) * 16, (int)(rem % utx) * 16, 0, H, W, next);
     }
+    const int kh = (lane >> 5) * 8;      // this lane's 8 channels of a 16-wide k step
+    const int m = lane & 31;             // this lane's pixel row of the A tile / output channel of B
     for (unsigned tile = blockIdx.x; tile < nti; tile += gridDim.x) {
         const int b = (int)(tile / txy);
         const unsigned rem = tile % txy;
         const int y0 = (int)(rem / utx) * 16, x0 = (int)(rem % utx) * 16;
-        __syncthreads();   // the previous tile's MFMAs are done with xs
-#pragma unroll
-        for (int q = 0; q < TileRegs<CIN>::kChunks; ++q) {
-            const int e = tid + q * 256;
-            if (e < 18 * 18 * (CIN / 8)) {
-                const int c8 = e % (CIN / 8), pix = e / (CIN / 8);
-                *(bf16x8*)&xs[pix * CP + c8 * 8] = next.v[q];
-            }
-        }
-        __syncthreads();
-        const unsigned nt2 = tile + gridDim.x;
-        if (nt2 < nti) {
-            const int b2 = (int)(nt2 / txy);
-            const unsigned rem2 = nt2 % txy;
-            load_tile<CIN, MASK>(X, M, b2, (int)(rem2 / utx) * 16, (int)(rem2 % utx) * 16, H, W, tid, next);
-        }
         f32x16 acc[2][NT];
         for (int s = 0; s < 2; ++s)
             for (int nt = 0; nt < NT; ++nt) acc[s][nt] = {};
-        const int kh = (lane >> 5) * 8;      // this lane's 8 channels of a 16-wide k step
-        const int m = lane & 31;             // this lane's pixel row of the A tile
 #pragma unroll
-        for (int t = 0; t < 9; ++t) {
-            const int dy = t / 3, dx = t % 3;   // halo coordinates: +1 offsets folded in
+        for (int ch = 0; ch < S::NCH; ++ch) {
+            __syncthreads();   // the previous chunk's MFMAs are done with xs
 #pragma unroll
-            for (int c0 = 0; c0 < CIN; c0 += 16) {
-                bf16x8 bfr[NT];
-                for (int nt = 0; nt < NT; ++nt)
-                    bfr[nt] = *(const bf16x8*)&ws[(t * COUT + nt * 32 + m) * CP + c0 + kh];
-                for (int s = 0; s < 2; ++s) {
-                    const int py = wave * 4 + s * 2 + m / 16, px = m % 16;
-                    const bf16x8 afr = *(const bf16x8*)&xs[((py + dy) * 18 + (px + dx)) * CP + c0 + kh];
+            for (int q = 0; q < S::Q; ++q)
+                if (lp.py[q] >= 0) *(bf16x8*)&xs[(lp.py[q] * 18 + lp.px[q]) * CP + lp.c8[q] * 8] = next[q];
+            __syncthreads();
+            // the next chunk of this tile, else the first of the next tile
+            if (ch + 1 < S::NCH) {
+                load_chunk<CIN, MASK>(X, M, lp, b, y0, x0, ch + 1, H, W, next);
+            } else {
+                const unsigned nt2 = tile + gridDim.x;
+                if (nt2 < nti) {
+                    const int b2 = (int)(nt2 / txy);
+                    const unsigned rem2 = nt2 % txy;
+                    load_chunk<CIN, MASK>(X, M, lp, b2, (int)(rem2 / utx) * 16, (int)(rem2 % utx) * 16, 0, H, W,
+                                          next);
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                const int dy = t / 3, dx = t % 3;   // halo coordinates: +1 offsets folded in
+#pragma unroll
+                for (int c0 = 0; c0 < S::CH; c0 += 16) {
+                    bf16x8 bfr[NT];
                     for (int nt = 0; nt < NT; ++nt)
-                        acc[s][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afr, bfr[nt], acc[s][nt], 0, 0, 0);
+                        bfr[nt] = *(const bf16x8*)&ws[(t * COUT + nt * 32 + m) * CW + ch * S::CH + c0 + kh];
+                    for (int s = 0; s < 2; ++s) {
+                        const int py = wave * 4 + s * 2 + m / 16, px = m % 16;
+                        const bf16x8 afr = *(const bf16x8*)&xs[((py + dy) * 18 + (px + dx)) * CP + c0 + kh];
+                        for (int nt = 0; nt < NT; ++nt)
+                            acc[s][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afr, bfr[nt], acc[s][nt], 0, 0, 0);
+                    }
                 }
             }
         }
