@@ -283,8 +283,8 @@ int upload_geometry(pic_handle* h) {
 
 // Level sizes: coarsen in z only while cells are much wider in r (strong
 // axial coupling), in r only in the opposite case, else in both; stop at
-// <= 300 nodes.  A grid too small to coarsen gets one identity level so the
-// coarse solve is exact.
+// kCoarsestNodes nodes or fewer.  A grid too small to coarsen gets one
+// identity level so the coarse solve is exact.
 int mg_plan(pic_handle* h) {
     int nr = h->nr, nz = h->nz;
     double dr = h->dr, dz = h->dz;
@@ -292,7 +292,7 @@ int mg_plan(pic_handle* h) {
     h->lv[0].nr = nr; h->lv[0].nz = nz;
     for (;;) {
         const long nn = (long)(nr + 1) * (nz + 1);
-        if (nn <= 300 || l + 1 >= kMaxLevels) break;
+        if (nn <= kCoarsestNodes || l + 1 >= kMaxLevels) break;
         const bool can_r = (nr % 2 == 0) && nr >= 4, can_z = (nz % 2 == 0) && nz >= 4;
         int cr = 1, cz = 1;
         if (dr > 1.5 * dz) { if (can_z) cz = 2; else if (can_r) cr = 2; }

@@ -651,33 +651,35 @@ struct Sten {
     const void* A[9];
 };
 
-template <typename T>
-__device__ __forceinline__ T apply9(const Sten& S, const T* x, int n, int i, int j, int nr, int nz, int w, T& d) {
-    T acc = T(0);
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        const int di = k % 3 - 1, dj = k / 3 - 1;
-        const int i2 = i + di, j2 = j + dj;
-        if (i2 < 0 || j2 < 0 || i2 > nr || j2 > nz) continue;
-        acc += ((const T*)S.A[k])[n] * x[n + dj * w + di];
-    }
-    d = ((const T*)S.A[4])[n];
-    return acc;
-}
-
-// The multigrid steps of levels >= 1 as grid-stride loops.
+// The passes of the levels >= 1 inside the tail kernel, as block-stride
+// loops.  Every load of a node's update is issued before any test on the
+// loaded values (a pass then costs one memory round trip per node); values
+// at inactive nodes are zero, and so are stencil entries towards them and
+// towards off-grid nodes.
 template <typename T>
 __device__ __forceinline__ void jac9_range(const Sten& S, const T* xin, const T* b, T* xout, int nr, int nz, int first,
                                            int start, int stride) {
     const int w = nr + 1, nn = w * (nz + 1);
     const T* D = (const T*)S.A[4];
     for (int n = start; n < nn; n += stride) {
-        const T d0 = D[n];
-        if (d0 == T(0)) { xout[n] = T(0); continue; }
-        if (first) { xout[n] = (T)kOmega * b[n] / d0; continue; }
-        T d;
-        T ax = apply9(S, xin, n, n % w, n / w, nr, nz, w, d);
-        xout[n] = xin[n] + (T)kOmega * (b[n] - ax) / d;
+        const T d0 = D[n], bn = b[n];
+        if (first) {
+            xout[n] = d0 == T(0) ? T(0) : (T)kOmega * bn / d0;
+            continue;
+        }
+        const int i = n % w, j = n / w;
+        T c[9], v[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const int i2 = i + k % 3 - 1, j2 = j + k / 3 - 1;
+            const bool ok = i2 >= 0 && j2 >= 0 && i2 <= nr && j2 <= nz;
+            c[k] = ok ? ((const T*)S.A[k])[n] : T(0);
+            v[k] = ok ? xin[n + (k / 3 - 1) * w + (k % 3 - 1)] : T(0);
+        }
+        T acc = T(0);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) acc += c[k] * v[k];
+        xout[n] = d0 == T(0) ? T(0) : v[4] + (T)kOmega * (bn - acc) / d0;
     }
 }
 
@@ -685,72 +687,98 @@ template <typename T>
 __device__ __forceinline__ void res9_range(const Sten& S, const T* x, const T* b, T* res, int nr, int nz, int start,
                                            int stride) {
     const int w = nr + 1, nn = w * (nz + 1);
-    const T* D = (const T*)S.A[4];
     for (int n = start; n < nn; n += stride) {
-        if (D[n] == T(0)) { res[n] = T(0); continue; }
-        T d;
-        res[n] = b[n] - apply9(S, x, n, n % w, n / w, nr, nz, w, d);
+        const int i = n % w, j = n / w;
+        const T bn = b[n];
+        T c[9], v[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const int i2 = i + k % 3 - 1, j2 = j + k / 3 - 1;
+            const bool ok = i2 >= 0 && j2 >= 0 && i2 <= nr && j2 <= nz;
+            c[k] = ok ? ((const T*)S.A[k])[n] : T(0);
+            v[k] = ok ? x[n + (k / 3 - 1) * w + (k % 3 - 1)] : T(0);
+        }
+        T acc = T(0);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) acc += c[k] * v[k];
+        res[n] = c[4] == T(0) ? T(0) : bn - acc;
     }
 }
 
+// bilinear prolongation weight of coarse node I for fine node i (coarsening
+// factor c), zero outside its support
 __device__ __forceinline__ float pw1(int i, int I, int c) {
     if (c == 1) return i == I ? 1.0f : 0.0f;
     int d = i - 2 * I;
     return d == 0 ? 1.0f : ((d == 1 || d == -1) ? 0.5f : 0.0f);
 }
 
-// b_c = P^T res_f; activity of fine nodes from the node kinds (level 0) or
-// the diagonal (coarser levels); coarse nodes inactive when their diagonal
-// is zero
+// prolongation weight of coarse node I for fine node i (coarsening factor
+// c, |i - c I| <= c - 1): 1 on the injected node, 1/2 beside it
+__device__ __forceinline__ float pwt(int i, int I, int c) { return i == c * I ? 1.0f : 0.5f; }
+
+// b_c = P^T res_f (the residual is zero on inactive fine nodes); coarse
+// nodes inactive when their diagonal is zero
 template <typename T>
-__device__ __forceinline__ void restrict_range(const T* res, const int8_t* nk, const T* Df, int fnr, int fnz, T* bc,
-                                               const T* Dc, int cnr, int cnz, int cr, int cz, int start, int stride) {
+__device__ __forceinline__ void restrict_range(const T* res, int fnr, int fnz, T* bc, const T* Dc, int cnr, int cnz,
+                                               int cr, int cz, int start, int stride) {
     const int fw = fnr + 1, cw = cnr + 1, cn = cw * (cnz + 1);
     for (int N = start; N < cn; N += stride) {
-        if (Dc[N] == T(0)) { bc[N] = T(0); continue; }
         const int I = N % cw, J = N / cw;
-        T acc = T(0);
-        for (int j = cz * J - (cz - 1); j <= cz * J + (cz - 1); ++j) {
-            if (j < 0 || j > fnz) continue;
-            for (int i = cr * I - (cr - 1); i <= cr * I + (cr - 1); ++i) {
-                if (i < 0 || i > fnr) continue;
-                const int nf = j * fw + i;
-                const bool act = nk ? (nk[nf] < 0) : (Df[nf] != T(0));
-                if (!act) continue;
-                acc += (T)(pw1(i, I, cr) * pw1(j, J, cz)) * res[nf];
+        const T dc = Dc[N];
+        T v[3][3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const int j = cz * J + a - 1, i = cr * I + q - 1;
+                const bool ok = a - 1 >= 1 - cz && a - 1 <= cz - 1 && q - 1 >= 1 - cr && q - 1 <= cr - 1 && i >= 0 &&
+                                j >= 0 && i <= fnr && j <= fnz;
+                v[a][q] = ok ? res[j * fw + i] : T(0);
             }
-        }
-        bc[N] = acc;
+        T acc = T(0);
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const int j = cz * J + a - 1, i = cr * I + q - 1;
+                if (a - 1 < 1 - cz || a - 1 > cz - 1 || q - 1 < 1 - cr || q - 1 > cr - 1) continue;
+                if (i < 0 || j < 0 || i > fnr || j > fnz) continue;
+                acc += (T)(pwt(i, I, cr) * pwt(j, J, cz)) * v[a][q];
+            }
+        bc[N] = dc == T(0) ? T(0) : acc;
     }
 }
 
-// y_f += P y_c on active fine nodes
+// y_f += P y_c on active fine nodes (the coarse correction is zero on
+// inactive coarse nodes)
 template <typename T>
-__device__ __forceinline__ void prolong_range(T* yf, const int8_t* nk, const T* Df, int fnr, int fnz, const T* yc,
-                                              const T* Dc, int cnr, int cnz, int cr, int cz, int start, int stride) {
+__device__ __forceinline__ void prolong_range(T* yf, const T* Df, int fnr, int fnz, const T* yc, int cnr, int cnz,
+                                              int cr, int cz, int start, int stride) {
     const int fw = fnr + 1, cw = cnr + 1, fn = fw * (fnz + 1);
     for (int n = start; n < fn; n += stride) {
-        const bool act = nk ? (nk[n] < 0) : (Df[n] != T(0));
-        if (!act) continue;
         const int i = n % fw, j = n / fw;
-        const int I0 = i / cr, J0 = j / cz;
-        T acc = T(0);
-        for (int J = J0 - 1; J <= J0 + 1; ++J) {
-            if (J < 0 || J > cnz) continue;
-            for (int I = I0 - 1; I <= I0 + 1; ++I) {
-                if (I < 0 || I > cnr) continue;
-                const int N = J * cw + I;
-                if (Dc[N] == T(0)) continue;
-                const float p = pw1(i, I, cr) * pw1(j, J, cz);
-                if (p != 0.0f) acc += (T)p * yc[N];
-            }
+        const int Ia = i / cr, Ib = (i + cr - 1) / cr, Ja = j / cz, Jb = (j + cz - 1) / cz;
+        const T df = Df[n];
+        const T y00 = yc[Ja * cw + Ia];
+        const T y01 = Ib <= cnr ? yc[Ja * cw + Ib] : T(0);
+        const T y10 = Jb <= cnz ? yc[Jb * cw + Ia] : T(0);
+        const T y11 = (Ib <= cnr && Jb <= cnz) ? yc[Jb * cw + Ib] : T(0);
+        const T wgt = (T)((Ia == Ib ? 1.0f : 0.5f) * (Ja == Jb ? 1.0f : 0.5f));
+        T acc = wgt * y00;
+        if (Ib != Ia) acc += wgt * y01;
+        if (Jb != Ja) {
+            acc += wgt * y10;
+            if (Ib != Ia) acc += wgt * y11;
         }
-        yf[n] += acc;
+        if (df != T(0)) yf[n] += acc;
     }
 }
 
-// coarsest level: y = A^-1 b with the precomputed dense inverse; one block
-// (sb: kMaxCoarse entries of shared memory)
+// coarsest level: y = A^-1 b with the precomputed dense inverse (stored
+// exactly symmetric); one block.  A wavefront takes a row: its lanes take
+// every 64th column and the row sum is a fixed butterfly over the lanes.
+// sb: kMaxCoarse entries of shared memory.
 template <typename T>
 __device__ __forceinline__ void coarse_block(const T* b, T* y, const int* cmap, const int* clist, const T* inv, int nc,
                                              int cn, T* sb) {
@@ -758,42 +786,14 @@ __device__ __forceinline__ void coarse_block(const T* b, T* y, const int* cmap, 
     for (int n = threadIdx.x; n < cn; n += blockDim.x)
         if (cmap[n] < 0) y[n] = T(0);
     __syncthreads();
-    for (int r = threadIdx.x; r < nc; r += blockDim.x) {
+    const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    for (int r = threadIdx.x >> 6; r < nc; r += nw) {
         T acc = T(0);
-        for (int c = 0; c < nc; ++c) acc += inv[r * nc + c] * sb[c];
-        y[clist[r]] = acc;
+        for (int c = lane; c < nc; c += 64) acc += inv[r * nc + c] * sb[c];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+        if (lane == 0) y[clist[r]] = acc;
     }
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_jac9(Sten S, const T* xin, const T* b, T* xout, const DevScalars* s, int nr,
-                                              int nz, int first) {
-    if (s->done) return;
-    jac9_range(S, xin, b, xout, nr, nz, first, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_res9(Sten S, const T* x, const T* b, T* res, const DevScalars* s, int nr,
-                                              int nz) {
-    if (s->done) return;
-    res9_range(S, x, b, res, nr, nz, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_restrict(const T* res, const int8_t* nk, const T* Df, int fnr, int fnz,
-                                                  T* bc, const T* Dc, int cnr, int cnz, int cr, int cz,
-                                                  const DevScalars* s) {
-    if (s->done) return;
-    restrict_range(res, nk, Df, fnr, fnz, bc, Dc, cnr, cnz, cr, cz, blockIdx.x * blockDim.x + threadIdx.x,
-                   gridDim.x * blockDim.x);
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_prolong(T* yf, const int8_t* nk, const T* Df, int fnr, int fnz, const T* yc,
-                                                 const T* Dc, int cnr, int cnz, int cr, int cz, const DevScalars* s) {
-    if (s->done) return;
-    prolong_range(yf, nk, Df, fnr, fnz, yc, Dc, cnr, cnz, cr, cz, blockIdx.x * blockDim.x + threadIdx.x,
-                  gridDim.x * blockDim.x);
 }
 
 template <typename T>
@@ -843,8 +843,7 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs<T> a) {
         __syncthreads();
         res9_range(L.S, L.y, L.b, L.res, L.nr, L.nz, t0, st);
         __syncthreads();
-        restrict_range((const T*)L.res, (const int8_t*)nullptr, L.D, L.nr, L.nz, C.b, C.D, C.nr, C.nz, L.cr, L.cz, t0,
-                       st);
+        restrict_range((const T*)L.res, L.nr, L.nz, C.b, C.D, C.nr, C.nz, L.cr, L.cz, t0, st);
         __syncthreads();
     }
     {
@@ -856,8 +855,7 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs<T> a) {
     for (int l = last - 1; l >= 0; --l) {
         const TailLevel<T>& L = a.L[l];
         const TailLevel<T>& C = a.L[l + 1];
-        prolong_range(L.y, (const int8_t*)nullptr, L.D, L.nr, L.nz, (const T*)C.y, C.D, C.nr, C.nz, L.cr, L.cz, t0,
-                      st);
+        prolong_range(L.y, L.D, L.nr, L.nz, (const T*)C.y, C.nr, C.nz, L.cr, L.cz, t0, st);
         __syncthreads();
         jac9_range(L.S, L.y, L.b, L.x, L.nr, L.nz, 0, t0, st);
         __syncthreads();
@@ -865,6 +863,342 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs<T> a) {
         __syncthreads();
     }
 }
+
+// ------------------------------------------- fused V-cycle level kernels
+// A level above the tail takes two launches per V-cycle: the down pass
+// (both pre-smoothing sweeps from a zero guess, the residual and its
+// restriction to the coarse right-hand side) and the up pass (prolongation
+// of the coarse correction and both post-smoothing sweeps).  A block owns a
+// tile of TS x TS fine nodes.  It first copies everything it reads (right-
+// hand side, stencil or face coefficients, node activity, the iterate and
+// the coarse correction), on the tile and the halo its sweeps need, into
+// LDS in one batch of independent loads, then runs the sweeps there: the
+// iterates on the halo are recomputed instead of exchanged.  Per node the
+// arithmetic is that of the one-sweep-per-launch steps above (jac0/jac9,
+// res0/res9, restrict, prolong).  Off-grid, conductor and inactive nodes
+// hold zero in LDS, and so do the face coefficients of faces that do not
+// exist, so the sums need no bounds tests (a zero term changes no sum).
+template <typename T>
+struct MgArgs {
+    Sten S;                      // levels >= 1
+    const T* ar;                 // level 0: face coefficients and node kinds
+    const T* az;
+    const int8_t* nk;
+    const T* b;                  // the level's right-hand side
+    const T* yin;                // up pass: the pre-smoothed iterate
+    T* yout;                     // down pass: the pre-smoothed iterate; up pass: the level's result
+    T* bc;                       // down pass: the coarse right-hand side
+    const T* yc;                 // up pass: the coarse correction (zero on inactive nodes)
+    const T* Dc;                 // down pass: coarse diagonal (zero: inactive)
+    int nr, nz, cnr, cnz, cr, cz, tiles_r;
+    const DevScalars* s;
+};
+
+// tile edge and threads per block: 32 x 32 nodes and 512 threads in FP32,
+// 16 x 16 and 256 in FP64 (whose LDS arrays and registers are twice as large)
+template <typename T>
+struct MgShape {
+    static constexpr int TS = sizeof(T) == 4 ? 32 : 16;
+    static constexpr int NT = sizeof(T) == 4 ? 512 : 256;
+};
+
+#define MG_FOR(U) _Pragma("unroll") for (int u_ = 0; u_ < (U); ++u_)
+
+// Down pass.  Local coordinates have the origin (i0 - 4, j0 - 4) and row
+// stride S = TS + 6; regions: faces [0, S) (level 0), first iterate and
+// right-hand side [1, S), smoothed iterate [2, S - 1), residual [3, S - 2),
+// owned nodes [4, S - 2).  The residual region is what the tile's coarse
+// nodes restrict from (one node left of the tile when coarsening by 2).
+// Each thread takes the same nodes of the smoothed-iterate region in the
+// second sweep and in the residual, so on levels >= 1 it keeps their
+// stencils in registers.
+template <typename T, bool L0>
+__global__ __launch_bounds__(MgShape<T>::NT) void k_mg_down(MgArgs<T> a) {
+    constexpr int TS = MgShape<T>::TS, NT = MgShape<T>::NT;
+    constexpr int S = TS + 6, N = S * S, U = (N + NT - 1) / NT;
+    constexpr int YW = TS + 3, NY = YW * YW, UY = (NY + NT - 1) / NT;
+    constexpr int UC = (TS * TS + NT - 1) / NT;
+    __shared__ T sf[2][L0 ? N : 1];              // level 0: face coefficients ar, az
+    __shared__ T sd[L0 ? 1 : N];                 // levels >= 1: diagonal
+    __shared__ T sb[N], sx[N], sy[N];            // sx holds the residual after the second sweep
+    __shared__ int8_t sk[L0 ? N : 1];
+    if (a.s->done) return;
+    const int w = a.nr + 1, cw = a.cnr + 1;
+    const int i0 = (blockIdx.x % a.tiles_r) * TS, j0 = (blockIdx.x / a.tiles_r) * TS;
+    const int oi = i0 - 4, oj = j0 - 4;
+    const int hr = a.cr - 1, hz = a.cz - 1;
+    const int CI = TS / a.cr, CJ = TS / a.cz, I0 = i0 / a.cr, J0 = j0 / a.cz;
+    T cf[UY][L0 ? 1 : 9];
+    T dc[UC];
+    // stage: everything the block reads, in one batch of loads
+    {
+        T vb[U], vf[U][L0 ? 2 : 1];
+        int8_t vk[U];
+        MG_FOR(U) {
+            const int t = threadIdx.x + u_ * NT;
+            const int li = t % S, lj = t / S, i = oi + li, j = oj + lj;
+            const bool in = t < N && i >= 0 && j >= 0 && i <= a.nr && j <= a.nz;
+            const bool px = in && li >= 1 && lj >= 1;
+            const int n = j * w + i;
+            vb[u_] = px ? a.b[n] : T(0);
+            if (L0) {
+                vk[u_] = px ? (int8_t)(a.nk[n] < 0) : (int8_t)0;
+                vf[u_][0] = (in && i < a.nr) ? a.ar[n] : T(0);
+                vf[u_][1] = (in && j < a.nz) ? a.az[n] : T(0);
+            } else {
+                vf[u_][0] = px ? ((const T*)a.S.A[4])[n] : T(0);
+            }
+        }
+        if (!L0) {
+            MG_FOR(UY) {
+                const int ty = threadIdx.x + u_ * NT;
+                const int i = oi + 2 + ty % YW, j = oj + 2 + ty / YW;
+                const bool in = ty < NY && i >= 0 && j >= 0 && i <= a.nr && j <= a.nz;
+                const int n = j * w + i;
+#pragma unroll
+                for (int k = 0; k < 9; ++k) cf[u_][k] = in ? ((const T*)a.S.A[k])[n] : T(0);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < UC; ++u) {
+            const int tc = threadIdx.x + u * NT;
+            const int I = I0 + tc % CI, J = J0 + tc / CI;
+            dc[u] = (tc < CI * CJ && I <= a.cnr && J <= a.cnz) ? a.Dc[J * cw + I] : T(0);
+        }
+        MG_FOR(U) {
+            const int t = threadIdx.x + u_ * NT;
+            if (t < N) {
+                sb[t] = vb[u_];
+                if (L0) {
+                    sk[t] = vk[u_];
+                    sf[0][t] = vf[u_][0];
+                    sf[1][t] = vf[u_][1];
+                } else {
+                    sd[t] = vf[u_][0];
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // level 0: (A v)(t) from the faces in LDS; d receives the diagonal
+    auto apply0s = [&](const T* v, int t, T& d) -> T {
+        const T fl = sf[0][t - 1], fr = sf[0][t], fd = sf[1][t - S], fu = sf[1][t];
+        T dd = T(0), off = T(0);
+        dd += fl; off += fl * v[t - 1];
+        dd += fr; off += fr * v[t + 1];
+        dd += fd; off += fd * v[t - S];
+        dd += fu; off += fu * v[t + S];
+        d = dd;
+        return dd * v[t] - off;
+    };
+    auto apply9r = [&](const T* v, int t, const T* c) -> T {
+        T acc = T(0);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) acc += c[k] * v[t + (k / 3 - 1) * S + (k % 3 - 1)];
+        return acc;
+    };
+    // first iterate x = w b / d
+    MG_FOR(U) {
+        const int t = threadIdx.x + u_ * NT;
+        const int li = t % S, lj = t / S;
+        if (t < N && li >= 1 && lj >= 1) {
+            T v = T(0);
+            if (L0) {
+                if (sk[t]) v = (T)kOmega * sb[t] / (sf[0][t - 1] + sf[0][t] + sf[1][t - S] + sf[1][t]);
+            } else {
+                if (sd[t] != T(0)) v = (T)kOmega * sb[t] / sd[t];
+            }
+            sx[t] = v;
+        }
+    }
+    __syncthreads();
+    // second sweep; the owned nodes go out
+    MG_FOR(UY) {
+        const int ty = threadIdx.x + u_ * NT;
+        const int li = 2 + ty % YW, lj = 2 + ty / YW, t = lj * S + li;
+        if (ty < NY) {
+            T v = T(0);
+            if (L0 ? sk[t] != 0 : sd[t] != T(0)) {
+                T d, ax;
+                if (L0) ax = apply0s(sx, t, d);
+                else { ax = apply9r(sx, t, cf[u_]); d = cf[u_][4]; }
+                v = sx[t] + (T)kOmega * (sb[t] - ax) / d;
+            }
+            sy[t] = v;
+            const int i = oi + li, j = oj + lj;
+            if (li >= 4 && lj >= 4 && li < S - 2 && lj < S - 2 && i <= a.nr && j <= a.nz) a.yout[j * w + i] = v;
+        }
+    }
+    __syncthreads();
+    // residual (into sx, whose first iterate is no longer read)
+    MG_FOR(UY) {
+        const int ty = threadIdx.x + u_ * NT;
+        const int li = 2 + ty % YW, lj = 2 + ty / YW, t = lj * S + li;
+        if (ty < NY && li >= 3 && lj >= 3 && li < S - 2 && lj < S - 2) {
+            T v = T(0);
+            if (L0 ? sk[t] != 0 : sd[t] != T(0)) {
+                T d;
+                v = sb[t] - (L0 ? apply0s(sy, t, d) : apply9r(sy, t, cf[u_]));
+            }
+            sx[t] = v;
+        }
+    }
+    __syncthreads();
+    // b_c = P^T res on the tile's coarse nodes
+#pragma unroll
+    for (int u = 0; u < UC; ++u) {
+        const int tc = threadIdx.x + u * NT;
+        const int I = I0 + tc % CI, J = J0 + tc / CI;
+        if (tc >= CI * CJ || I > a.cnr || J > a.cnz) continue;
+        T acc = T(0);
+        if (dc[u] != T(0)) {
+            for (int j = a.cz * J - hz; j <= a.cz * J + hz; ++j) {
+                if (j < 0 || j > a.nz) continue;
+                for (int i = a.cr * I - hr; i <= a.cr * I + hr; ++i) {
+                    if (i < 0 || i > a.nr) continue;
+                    acc += (T)(pwt(i, I, a.cr) * pwt(j, J, a.cz)) * sx[(j - oj) * S + (i - oi)];
+                }
+            }
+        }
+        a.bc[J * cw + I] = acc;
+    }
+}
+
+// Up pass.  Local coordinates have the origin (i0 - 2, j0 - 2) and row
+// stride S = TS + 4; regions: prolongated iterate [0, S), first
+// post-smoothing sweep [1, S - 1), owned nodes [2, S - 2).  The coarse
+// correction is staged on coarse nodes from (i0 - 2) / cr - 1.  Each thread
+// takes the same nodes of the sweep region in both sweeps and keeps their
+// right-hand side and stencil (level 0: face coefficients) in registers.
+template <typename T, bool L0>
+__global__ __launch_bounds__(MgShape<T>::NT) void k_mg_up(MgArgs<T> a) {
+    constexpr int TS = MgShape<T>::TS, NT = MgShape<T>::NT;
+    constexpr int S = TS + 4, N = S * S, U = (N + NT - 1) / NT;
+    constexpr int XW = TS + 2, NX = XW * XW, UX = (NX + NT - 1) / NT;
+    constexpr int CWM = TS + 7, NC = CWM * CWM, UC = (NC + NT - 1) / NT;   // coarsening by 1 is the widest
+    constexpr int NCF = L0 ? 4 : 9;
+    __shared__ T sp[N], sx[N], sc[NC];
+    __shared__ int8_t sk[N];                     // activity
+    if (a.s->done) return;
+    const int w = a.nr + 1, cw = a.cnr + 1;
+    const int i0 = (blockIdx.x % a.tiles_r) * TS, j0 = (blockIdx.x / a.tiles_r) * TS;
+    const int oi = i0 - 2, oj = j0 - 2;
+    const int ci = (i0 - 2) / a.cr - 1, cj = (j0 - 2) / a.cz - 1;    // exact: i0 - 2 is even
+    const int CW = (TS + 4) / a.cr + 3, CH = (TS + 4) / a.cz + 3;
+    T cf[UX][NCF], cb[UX];
+    {
+        T vy[U];
+        int8_t vk[U];
+        MG_FOR(U) {
+            const int t = threadIdx.x + u_ * NT;
+            const int li = t % S, lj = t / S, i = oi + li, j = oj + lj;
+            const bool in = t < N && i >= 0 && j >= 0 && i <= a.nr && j <= a.nz;
+            const int n = j * w + i;
+            vy[u_] = in ? a.yin[n] : T(0);
+            if (L0) vk[u_] = in ? (int8_t)(a.nk[n] < 0) : (int8_t)0;
+            else vk[u_] = (in && ((const T*)a.S.A[4])[n] != T(0)) ? (int8_t)1 : (int8_t)0;
+        }
+        MG_FOR(UX) {
+            const int tx = threadIdx.x + u_ * NT;
+            const int i = oi + 1 + tx % XW, j = oj + 1 + tx / XW;
+            const bool in = tx < NX && i >= 0 && j >= 0 && i <= a.nr && j <= a.nz;
+            const int n = j * w + i;
+            cb[u_] = in ? a.b[n] : T(0);
+            if (L0) {
+                cf[u_][0] = (in && i > 0) ? a.ar[n - 1] : T(0);
+                cf[u_][1] = (in && i < a.nr) ? a.ar[n] : T(0);
+                cf[u_][2] = (in && j > 0) ? a.az[n - w] : T(0);
+                cf[u_][3] = (in && j < a.nz) ? a.az[n] : T(0);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 9; ++k) cf[u_][k] = in ? ((const T*)a.S.A[k])[n] : T(0);
+            }
+        }
+        T vc[UC];
+#pragma unroll
+        for (int u = 0; u < UC; ++u) {
+            const int t = threadIdx.x + u * NT;
+            const int li = t % CWM, lj = t / CWM, I = ci + li, J = cj + lj;
+            const bool in = t < NC && li < CW && lj < CH && I >= 0 && J >= 0 && I <= a.cnr && J <= a.cnz;
+            vc[u] = in ? a.yc[J * cw + I] : T(0);
+        }
+        MG_FOR(U) {
+            const int t = threadIdx.x + u_ * NT;
+            if (t < N) { sp[t] = vy[u_]; sk[t] = vk[u_]; }
+        }
+#pragma unroll
+        for (int u = 0; u < UC; ++u) {
+            const int t = threadIdx.x + u * NT;
+            if (t < NC) sc[t] = vc[u];
+        }
+    }
+    __syncthreads();
+    // (A v)(t) with the stencil c of the node; d receives the diagonal
+    auto apply = [&](const T* v, int t, const T* c, T& d) -> T {
+        if (L0) {
+            T dd = T(0), off = T(0);
+            dd += c[0]; off += c[0] * v[t - 1];
+            dd += c[1]; off += c[1] * v[t + 1];
+            dd += c[2]; off += c[2] * v[t - S];
+            dd += c[3]; off += c[3] * v[t + S];
+            d = dd;
+            return dd * v[t] - off;
+        }
+        T acc = T(0);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) acc += c[k] * v[t + (k / 3 - 1) * S + (k % 3 - 1)];
+        d = c[4];
+        return acc;
+    };
+    // y += P y_c on active nodes (the coarse correction is zero on inactive
+    // coarse nodes)
+    MG_FOR(U) {
+        const int t = threadIdx.x + u_ * NT;
+        if (t < N && sk[t]) {
+            const int i = oi + t % S, j = oj + t / S;
+            const int Ia = i / a.cr, Ib = (i + a.cr - 1) / a.cr, Ja = j / a.cz, Jb = (j + a.cz - 1) / a.cz;
+            const float wa = Ia == Ib ? 1.0f : 0.5f, wb = Ja == Jb ? 1.0f : 0.5f;
+            const T* c0 = sc + (Ja - cj) * CWM - ci;
+            const T* c1 = sc + (Jb - cj) * CWM - ci;
+            T acc = (T)(wa * wb) * c0[Ia];
+            if (Ib != Ia) acc += (T)(wa * wb) * c0[Ib];
+            if (Jb != Ja) {
+                acc += (T)(wa * wb) * c1[Ia];
+                if (Ib != Ia) acc += (T)(wa * wb) * c1[Ib];
+            }
+            sp[t] += acc;
+        }
+    }
+    __syncthreads();
+    MG_FOR(UX) {
+        const int tx = threadIdx.x + u_ * NT;
+        const int t = (1 + tx / XW) * S + 1 + tx % XW;
+        if (tx < NX) {
+            T v = T(0);
+            if (sk[t]) {
+                T d;
+                const T ax = apply(sp, t, cf[u_], d);
+                v = sp[t] + (T)kOmega * (cb[u_] - ax) / d;
+            }
+            sx[t] = v;
+        }
+    }
+    __syncthreads();
+    MG_FOR(UX) {
+        const int tx = threadIdx.x + u_ * NT;
+        const int li = 1 + tx % XW, lj = 1 + tx / XW, t = lj * S + li, i = oi + li, j = oj + lj;
+        if (tx < NX && li >= 2 && lj >= 2 && li < S - 2 && lj < S - 2 && i <= a.nr && j <= a.nz) {
+            T v = T(0);
+            if (sk[t]) {
+                T d;
+                const T ax = apply(sx, t, cf[u_], d);
+                v = sx[t] + (T)kOmega * (cb[u_] - ax) / d;
+            }
+            a.yout[j * w + i] = v;
+        }
+    }
+}
+#undef MG_FOR
 
 // ------------------------------------------------- multigrid construction
 // Galerkin product A_c = P^T A_f P, one coarse node per thread.  A coarse
@@ -987,6 +1321,19 @@ __global__ __launch_bounds__(1024) void k_invert(double* M, int n) {
     }
 }
 
+// the inverse of a symmetric matrix, made exactly symmetric (the mean of
+// the two rounded triangles), one block
+__global__ __launch_bounds__(1024) void k_symmetrize(double* M, int n) {
+    for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+        const int r = t / n, c = t % n;
+        if (r < c) {
+            const double v = 0.5 * (M[r * n + c] + M[c * n + r]);
+            M[r * n + c] = v;
+            M[c * n + r] = v;
+        }
+    }
+}
+
 void mg_rebuild(pic_handle* h) {
     hipStream_t st = h->stream;
     for (int l = 0; l + 1 < h->nlev; ++l) {
@@ -1011,6 +1358,7 @@ void mg_rebuild(pic_handle* h) {
         }
         hipLaunchKernelGGL(k_coarse_dense, dim3(1), dim3(256), 0, st, S, h->cmap, h->cinv64, h->ncoarse, L.nr, L.nz);
         hipLaunchKernelGGL(k_invert, dim3(1), dim3(1024), 0, st, h->cinv64, h->ncoarse);
+        hipLaunchKernelGGL(k_symmetrize, dim3(1), dim3(1024), 0, st, h->cinv64, h->ncoarse);
         hipLaunchKernelGGL(k_to32, dim3(64), dim3(256), 0, st, (const double*)h->cinv64, h->cinv32,
                            h->ncoarse * h->ncoarse, kEps0);
     }
@@ -1092,36 +1440,32 @@ static void vcycle(pic_handle* h, int l, const T* b0, T* y0) {
         return;
     }
     Level& C = h->lv[l + 1];
-    if (l == 0) {
-        hipLaunchKernelGGL(k_jac0<T>, grid_for(L.nn), dim3(256), 0, st, V::ar(h), V::az(h), h->node_kind, x, b, x, s,
-                           L.nr, L.nz, 1);
-        hipLaunchKernelGGL(k_jac0<T>, grid_for(L.nn), dim3(256), 0, st, V::ar(h), V::az(h), h->node_kind, x, b, y, s,
-                           L.nr, L.nz, 0);
-        hipLaunchKernelGGL(k_res0<T>, grid_for(L.nn), dim3(256), 0, st, V::ar(h), V::az(h), h->node_kind, y, b,
-                           V::res(L), s, L.nr, L.nz);
-    } else {
-        Sten S = V::sten(L);
-        hipLaunchKernelGGL(k_jac9<T>, grid_for(L.nn), dim3(256), 0, st, S, x, b, x, s, L.nr, L.nz, 1);
-        hipLaunchKernelGGL(k_jac9<T>, grid_for(L.nn), dim3(256), 0, st, S, x, b, y, s, L.nr, L.nz, 0);
-        hipLaunchKernelGGL(k_res9<T>, grid_for(L.nn), dim3(256), 0, st, S, y, b, V::res(L), s, L.nr, L.nz);
-    }
-    const int8_t* nk = (l == 0) ? h->node_kind : nullptr;
-    const T* Df = (l == 0) ? nullptr : V::diag(L);
-    hipLaunchKernelGGL(k_restrict<T>, grid_for(C.nn), dim3(256), 0, st, (const T*)V::res(L), nk, Df, L.nr, L.nz,
-                       V::b(C), V::diag(C), C.nr, C.nz, L.cr, L.cz, s);
+    MgArgs<T> a;
+    a.S = V::sten(L);
+    a.ar = V::ar(h);
+    a.az = V::az(h);
+    a.nk = (l == 0) ? h->node_kind : nullptr;
+    a.b = b;
+    a.yin = nullptr;
+    a.yout = x;            // the pre-smoothed iterate
+    a.bc = V::b(C);
+    a.yc = nullptr;
+    a.Dc = V::diag(C);
+    a.nr = L.nr; a.nz = L.nz; a.cnr = C.nr; a.cnz = C.nz; a.cr = L.cr; a.cz = L.cz;
+    constexpr int ts = MgShape<T>::TS;
+    const dim3 nt(MgShape<T>::NT);
+    a.tiles_r = (L.nr + ts) / ts;
+    a.s = s;
+    const dim3 tiles(a.tiles_r * ((L.nz + ts) / ts));
+    if (l == 0) hipLaunchKernelGGL((k_mg_down<T, true>), tiles, nt, 0, st, a);
+    else hipLaunchKernelGGL((k_mg_down<T, false>), tiles, nt, 0, st, a);
     vcycle<T>(h, l + 1, nullptr, nullptr);
-    hipLaunchKernelGGL(k_prolong<T>, grid_for(L.nn), dim3(256), 0, st, y, nk, Df, L.nr, L.nz, (const T*)V::y(C),
-                       V::diag(C), C.nr, C.nz, L.cr, L.cz, s);
-    if (l == 0) {
-        hipLaunchKernelGGL(k_jac0<T>, grid_for(L.nn), dim3(256), 0, st, V::ar(h), V::az(h), h->node_kind, y, b, x, s,
-                           L.nr, L.nz, 0);
-        hipLaunchKernelGGL(k_jac0<T>, grid_for(L.nn), dim3(256), 0, st, V::ar(h), V::az(h), h->node_kind, x, b, y, s,
-                           L.nr, L.nz, 0);
-    } else {
-        Sten S = V::sten(L);
-        hipLaunchKernelGGL(k_jac9<T>, grid_for(L.nn), dim3(256), 0, st, S, y, b, x, s, L.nr, L.nz, 0);
-        hipLaunchKernelGGL(k_jac9<T>, grid_for(L.nn), dim3(256), 0, st, S, x, b, y, s, L.nr, L.nz, 0);
-    }
+    a.yin = x;
+    a.yout = y;
+    a.bc = nullptr;
+    a.yc = V::y(C);
+    if (l == 0) hipLaunchKernelGGL((k_mg_up<T, true>), tiles, nt, 0, st, a);
+    else hipLaunchKernelGGL((k_mg_up<T, false>), tiles, nt, 0, st, a);
 }
 
 // preconditioned CG on the level-0 operator; r is overwritten, x receives

@@ -33,6 +33,7 @@ __host__ __device__ constexpr long long stage_rows(long long n) {
 }
 constexpr int kMaxLevels = 16;
 constexpr int kMaxCoarse = 320;       // active nodes of the coarsest multigrid level
+constexpr int kCoarsestNodes = 100;   // coarsening stops at this many nodes (or when it cannot go on)
 constexpr int kRedBlocks = 4096;      // partial sums of a grid reduction
 constexpr int kMaxEl = PIC_MAX_ELECTRODES;   // driven electrodes
 // absorption counter slot of conductor id: 0 ground, 1 electrode 1, 2 lost
