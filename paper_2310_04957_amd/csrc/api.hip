@@ -382,6 +382,7 @@ size_t layout(pic_handle* h, char* base) {
     h->phi = c.take<double>(nn); h->zeroQ = c.take<double>(nn);
     for (int e = 0; e < kMaxEl; ++e) h->phiL[e] = e < h->n_el ? c.take<double>(nn) : nullptr;
     h->phi_prev = c.take<double>(nn);
+    h->phi_prev2 = c.take<double>(nn);
     h->ar32 = c.take<float>(nn); h->az32 = c.take<float>(nn);
     h->E = c.take<float2>(nn);
     h->r64 = c.take<double>(nn); h->x64 = c.take<double>(nn); h->z64 = c.take<double>(nn);
@@ -389,6 +390,10 @@ size_t layout(pic_handle* h, char* base) {
     h->r32 = c.take<float>(nn); h->x32 = c.take<float>(nn); h->z32 = c.take<float>(nn);
     h->p32 = c.take<float>(nn); h->q32 = c.take<float>(nn);
     h->part = c.take<double>(kMaxEl * kRedBlocks);
+    // partials of the fused CG: r.z and p.q (one per level-0 tile of the
+    // fused multigrid; 16-node tiles in FP64 are the most), r.r
+    h->cgpart_n = std::max(((h->nr + 16) / 16) * ((h->nz + 16) / 16), kCgBlocks);
+    h->cgpart = c.take<double>(3 * (size_t)h->cgpart_n);
     for (int l = 0; l < h->nlev; ++l) {
         Level& L = h->lv[l];
         const size_t m = (size_t)L.nn;
@@ -1047,7 +1052,7 @@ int pic_set_grid(pic_handle* h, int32_t which, const void* host) {
     case PIC_G_DEP_E: dst = h->dep[h->dep_cur][0]; break;
     case PIC_G_DEP_I: dst = h->dep[h->dep_cur][1]; break;
     case PIC_G_WALLQ: dst = h->wallq; break;
-    case PIC_G_PHI: dst = h->phi; h->have_prev = false; break;
+    case PIC_G_PHI: dst = h->phi; h->have_prev = 0; break;
     case PIC_G_PHI_L: dst = h->phiL[0]; break;
     default: return PIC_E_ARG;
     }
@@ -1094,7 +1099,7 @@ int pic_solve_once_el(pic_handle* h, const double* Q, const double* chi, const d
     launch_faces(h);
     mg_rebuild(h);
     h->harvest_now = h->harvest_every > 0;
-    h->have_prev = false;
+    h->have_prev = 0;
     int rc = field_solve(h, h->phi, h->Q, h->sc->Uset, tol, h->cfg.solver.method, iters, relres);
     h->harvest_now = false;
     if (hipMemcpy(phi_inout, h->phi, nn * 8, hipMemcpyDeviceToHost) != hipSuccess) return PIC_E_HIP;

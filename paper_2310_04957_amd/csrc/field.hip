@@ -54,6 +54,28 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
     return t;  // valid in thread 0
 }
 
+// block sum of a double returned to every thread (fixed order; up to 1024
+// threads, sh: 16 doubles)
+__device__ __forceinline__ double block_total(double v, double* sh) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w];
+    __syncthreads();
+    return t;
+}
+
+// sum of the n per-block partials a launch left, in every thread of the
+// block: the fused Krylov kernels reduce the partials of the launch before
+// them themselves instead of in a launch of their own (every block gets the
+// same sum, and only one launch computes each scalar)
+__device__ __forceinline__ double sum_partials(const double* p, int n, double* sh) {
+    double v = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) v += p[i];
+    return block_total(v, sh);
+}
+
 // --------------------------------------------------------------- assembly
 struct AsmArgs {
     const unsigned long long *dep_e, *dep_i, *wallq;
@@ -610,31 +632,41 @@ __global__ void k_fcg_start(DevScalars* s) {
     if (!(s->rz > 0.0) || !isfinite(s->rz)) { s->fallback = 1; s->done = 1; }
 }
 
-// ------------------------------------------------------------- multigrid
-// level 0: damped Jacobi and residual on the 5-point operator
+// Fused preconditioned CG (multigrid preconditioner).  One iteration is
+// k_cg_dir (with the multigrid kernels below), k_cg_step and the V-cycle:
+// k_cg_dir sums the r.z partials the last V-cycle left, forms the direction
+// p = z + beta p_old (beta = 0 on the first) into the other direction
+// buffer, q = K p and the p.q partials; k_cg_step sums those, alpha =
+// rz / pq, x += alpha p, r -= alpha q and the r.r partials, which the
+// V-cycle's first launch tests against the target.
+constexpr int kCgThreads = 512;
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_jac0(const T* ar, const T* az, const int8_t* nk, const T* xin, const T* b,
-                                              T* xout, const DevScalars* s, int nr, int nz, int first) {
+__global__ __launch_bounds__(kCgThreads) void k_cg_step(T* x, T* r, const T* p, const T* q, const double* pqp,
+                                                        int npq, double* rrp, DevScalars* s, int nn) {
+    __shared__ double sh[16];
     if (s->done) return;
-    const int w = nr + 1, nn = w * (nz + 1);
-    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += gridDim.x * blockDim.x) {
-        if (nk[n] >= 0) { xout[n] = T(0); continue; }
-        T d;
-        const int i = n % w, j = n / w;
-        if (first) {
-            T dd = T(0);
-            if (i > 0) dd += ar[n - 1];
-            if (i < nr) dd += ar[n];
-            if (j > 0) dd += az[n - w];
-            if (j < nz) dd += az[n];
-            xout[n] = (T)kOmega * b[n] / dd;
-        } else {
-            T ax = apply0(ar, az, nk, xin, n, i, j, nr, nz, w, d);
-            xout[n] = xin[n] + (T)kOmega * (b[n] - ax) / d;
-        }
+    const double pq = sum_partials(pqp, npq, sh);
+    if (!(pq > 0.0) || !isfinite(pq)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) { s->pq = pq; s->done = 1; s->nonfinite = !isfinite(pq); }
+        return;
     }
+    const double rz = s->rz_new, alpha = rz / pq;
+    const T al = (T)alpha;
+    double acc = 0.0;
+    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += gridDim.x * blockDim.x) {
+        x[n] += al * p[n];
+        const T rn = r[n] - al * q[n];
+        r[n] = rn;
+        acc += (double)rn * (double)rn;
+    }
+    const double t = block_total(acc, sh);
+    if (threadIdx.x == 0) rrp[blockIdx.x] = t;
+    if (blockIdx.x == 0 && threadIdx.x == 0) { s->pq = pq; s->alpha = alpha; s->rz = rz; }
 }
 
+// ------------------------------------------------------------- multigrid
+// level 0: residual on the 5-point operator
 template <typename T>
 __global__ __launch_bounds__(256) void k_res0(const T* ar, const T* az, const int8_t* nk, const T* x, const T* b,
                                               T* res, const DevScalars* s, int nr, int nz) {
@@ -864,6 +896,115 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs<T> a) {
     }
 }
 
+// The same tail with its levels resident in LDS: one launch stages the
+// stencils of the smoothed levels and the first level's right-hand side
+// (one batch of loads per level), every pass then reads and writes LDS
+// (the pass functions above take generic pointers), and only the first
+// level's result goes back to memory.  Layout in the dynamic LDS, per
+// smoothed level l from off[l]: A[0..8], b, x, y, res (nn_l each); the
+// coarsest level's b and y from off[last].  A tail level has at most
+// kTailNodes <= 3 x 1024 nodes.
+struct TailLds {
+    int off[kMaxTail];
+    int bytes;
+};
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_tail_lds(TailArgs<T> a, TailLds o) {
+    extern __shared__ unsigned char tail_dyn[];
+    __shared__ T sb[kMaxCoarse];
+    if (a.s->done) return;
+    T* lds = reinterpret_cast<T*>(tail_dyn);
+    const int t0 = threadIdx.x, st = blockDim.x;
+    const int last = a.n - 1;
+    for (int l = 0; l < last; ++l) {
+        const TailLevel<T>& G = a.L[l];
+        const int nn = (G.nr + 1) * (G.nz + 1);
+        T* base = lds + o.off[l];
+        T v[10][3];
+#pragma unroll
+        for (int k = 0; k < 10; ++k)
+#pragma unroll
+            for (int u = 0; u < 3; ++u) {
+                const int n = t0 + u * 1024;
+                const T* src = k < 9 ? (const T*)G.S.A[k] : (const T*)G.b;
+                v[k][u] = (n < nn && (k < 9 || l == 0)) ? src[n] : T(0);
+            }
+#pragma unroll
+        for (int k = 0; k < 10; ++k)
+#pragma unroll
+            for (int u = 0; u < 3; ++u) {
+                const int n = t0 + u * 1024;
+                if (n < nn && (k < 9 || l == 0)) base[k * nn + n] = v[k][u];
+            }
+    }
+    __syncthreads();
+    auto lev = [&](int l, Sten& S, T*& b, T*& x, T*& y, T*& res) {
+        const int nn = (a.L[l].nr + 1) * (a.L[l].nz + 1);
+        T* base = lds + o.off[l];
+        for (int k = 0; k < 9; ++k) S.A[k] = base + k * nn;
+        b = base + 9 * nn;
+        x = b + nn;
+        y = x + nn;
+        res = y + nn;
+    };
+    for (int l = 0; l < last; ++l) {
+        const TailLevel<T>& L = a.L[l];
+        const TailLevel<T>& C = a.L[l + 1];
+        Sten S;
+        T *b, *x, *y, *res;
+        lev(l, S, b, x, y, res);
+        T* bc;
+        const T* Dc;
+        if (l + 1 < last) {
+            Sten SC;
+            T *xc, *yc, *rc;
+            lev(l + 1, SC, bc, xc, yc, rc);
+            Dc = (const T*)SC.A[4];
+        } else {
+            bc = lds + o.off[last];
+            Dc = C.D;
+        }
+        jac9_range(S, (const T*)x, (const T*)b, x, L.nr, L.nz, 1, t0, st);
+        __syncthreads();
+        jac9_range(S, (const T*)x, (const T*)b, y, L.nr, L.nz, 0, t0, st);
+        __syncthreads();
+        res9_range(S, (const T*)y, (const T*)b, res, L.nr, L.nz, t0, st);
+        __syncthreads();
+        restrict_range((const T*)res, L.nr, L.nz, bc, Dc, C.nr, C.nz, L.cr, L.cz, t0, st);
+        __syncthreads();
+    }
+    {
+        const TailLevel<T>& C = a.L[last];
+        const int cn = (C.nr + 1) * (C.nz + 1);
+        T* bc = lds + o.off[last];
+        coarse_block((const T*)bc, bc + cn, a.cmap, a.cmap + cn, a.inv, a.nc, cn, sb);
+        __syncthreads();
+    }
+    for (int l = last - 1; l >= 0; --l) {
+        const TailLevel<T>& L = a.L[l];
+        const TailLevel<T>& C = a.L[l + 1];
+        Sten S;
+        T *b, *x, *y, *res;
+        lev(l, S, b, x, y, res);
+        const T* yc;
+        if (l + 1 < last) {
+            Sten SC;
+            T *bc2, *xc, *ycc, *rc;
+            lev(l + 1, SC, bc2, xc, ycc, rc);
+            yc = ycc;
+        } else {
+            yc = lds + o.off[last] + (C.nr + 1) * (C.nz + 1);
+        }
+        prolong_range(y, (const T*)S.A[4], L.nr, L.nz, yc, C.nr, C.nz, L.cr, L.cz, t0, st);
+        __syncthreads();
+        jac9_range(S, (const T*)y, (const T*)b, x, L.nr, L.nz, 0, t0, st);
+        __syncthreads();
+        jac9_range(S, (const T*)x, (const T*)b, l == 0 ? a.L[0].y : y, L.nr, L.nz, 0, t0, st);
+        __syncthreads();
+    }
+}
+
 // ------------------------------------------- fused V-cycle level kernels
 // A level above the tail takes two launches per V-cycle: the down pass
 // (both pre-smoothing sweeps from a zero guess, the residual and its
@@ -892,6 +1033,13 @@ struct MgArgs {
     const T* Dc;                 // down pass: coarse diagonal (zero: inactive)
     int nr, nz, cnr, cnz, cr, cz, tiles_r;
     const DevScalars* s;
+    // preconditioned CG (level 0 only; null when unused): the down pass
+    // first sums the r.r partials of the update before it and ends the
+    // solve at the target; the up pass leaves per-block partials of r.z
+    // (r = b, z = the result)
+    const double* chk;
+    int nchk;
+    double* rzp;
 };
 
 // tile edge and threads per block: 32 x 32 nodes and 512 threads in FP32,
@@ -923,6 +1071,20 @@ __global__ __launch_bounds__(MgShape<T>::NT) void k_mg_down(MgArgs<T> a) {
     __shared__ T sb[N], sx[N], sy[N];            // sx holds the residual after the second sweep
     __shared__ int8_t sk[L0 ? N : 1];
     if (a.s->done) return;
+    if (L0 && a.chk) {
+        // r.r of the new residual against the target (every block decides
+        // alike; block 0 records it)
+        __shared__ double sh[16];
+        const double rr = sum_partials(a.chk, a.nchk, sh);
+        const bool fin = isfinite(rr), done = !fin || rr <= a.s->target;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            DevScalars* sw = const_cast<DevScalars*>(a.s);
+            sw->rr = rr;
+            sw->iters += 1;
+            if (done) { sw->done = 1; sw->nonfinite = !fin; }
+        }
+        if (done) return;
+    }
     const int w = a.nr + 1, cw = a.cnr + 1;
     const int i0 = (blockIdx.x % a.tiles_r) * TS, j0 = (blockIdx.x / a.tiles_r) * TS;
     const int oi = i0 - 4, oj = j0 - 4;
@@ -1184,6 +1346,7 @@ __global__ __launch_bounds__(MgShape<T>::NT) void k_mg_up(MgArgs<T> a) {
         }
     }
     __syncthreads();
+    double rz = 0.0;
     MG_FOR(UX) {
         const int tx = threadIdx.x + u_ * NT;
         const int li = 1 + tx % XW, lj = 1 + tx / XW, t = lj * S + li, i = oi + li, j = oj + lj;
@@ -1195,9 +1358,91 @@ __global__ __launch_bounds__(MgShape<T>::NT) void k_mg_up(MgArgs<T> a) {
                 v = sx[t] + (T)kOmega * (cb[u_] - ax) / d;
             }
             a.yout[j * w + i] = v;
+            rz += (double)cb[u_] * (double)v;
         }
     }
+    if (L0 && a.rzp) {
+        __shared__ double sh[16];
+        const double t = block_total(rz, sh);
+        if (threadIdx.x == 0) a.rzp[blockIdx.x] = t;
+    }
 }
+// First kernel of a fused CG iteration, on the multigrid's level-0 tiles:
+// the direction p = z + beta p_old (beta = rz / rz_old from the r.z partials
+// of the last V-cycle; p = z on the first iteration) on the tile and one
+// node around it in LDS, then q = K p, p and q on the tile, and the
+// tile's partial of p.q.
+template <typename T>
+__global__ __launch_bounds__(MgShape<T>::NT) void k_cg_dir(const T* ar, const T* az, const int8_t* nk, const T* z,
+                                                           const T* pold, T* p, T* q, const double* rzp, int nrz,
+                                                           double* pqp, DevScalars* s, int first, int nr, int nz,
+                                                           int tiles_r) {
+    constexpr int TS = MgShape<T>::TS, NT = MgShape<T>::NT;
+    constexpr int S = TS + 2, N = S * S, U = (N + NT - 1) / NT, UO = (TS * TS + NT - 1) / NT;
+    __shared__ T sp[N];
+    __shared__ double sh[16];
+    if (s->done) return;
+    const double rz = sum_partials(rzp, nrz, sh);
+    if (first && !(rz > 0.0)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) { s->rz_new = rz; s->done = 1; }
+        return;
+    }
+    const T be = first ? T(0) : (T)(rz / s->rz);
+    const int w = nr + 1;
+    const int i0 = (blockIdx.x % tiles_r) * TS, j0 = (blockIdx.x / tiles_r) * TS;
+    const int oi = i0 - 1, oj = j0 - 1;
+    T vz[U], vp[U];
+    MG_FOR(U) {
+        const int t = threadIdx.x + u_ * NT;
+        const int i = oi + t % S, j = oj + t / S;
+        const bool in = t < N && i >= 0 && j >= 0 && i <= nr && j <= nz;
+        vz[u_] = in ? z[j * w + i] : T(0);
+        vp[u_] = (in && !first) ? pold[j * w + i] : T(0);
+    }
+    T fl[UO], fr[UO], fd[UO], fu[UO];
+    int8_t k0[UO];
+    MG_FOR(UO) {
+        const int to = threadIdx.x + u_ * NT;
+        const int i = i0 + to % TS, j = j0 + to / TS, n = j * w + i;
+        const bool in = to < TS * TS && i <= nr && j <= nz;
+        k0[u_] = in ? nk[n] : (int8_t)1;
+        fl[u_] = (in && i > 0) ? ar[n - 1] : T(0);
+        fr[u_] = (in && i < nr) ? ar[n] : T(0);
+        fd[u_] = (in && j > 0) ? az[n - w] : T(0);
+        fu[u_] = (in && j < nz) ? az[n] : T(0);
+    }
+    MG_FOR(U) {
+        const int t = threadIdx.x + u_ * NT;
+        if (t < N) sp[t] = first ? vz[u_] : vz[u_] + be * vp[u_];
+    }
+    __syncthreads();
+    double acc = 0.0;
+    MG_FOR(UO) {
+        const int to = threadIdx.x + u_ * NT;
+        const int li = to % TS, lj = to / TS, i = i0 + li, j = j0 + lj, n = j * w + i;
+        if (to < TS * TS && i <= nr && j <= nz) {
+            const int t = (lj + 1) * S + li + 1;
+            const T p0 = sp[t];
+            T v = T(0);
+            if (k0[u_] < 0) {
+                // the 5-point operator; conductor neighbours hold zero
+                T d = T(0), off = T(0);
+                d += fl[u_]; off += fl[u_] * sp[t - 1];
+                d += fr[u_]; off += fr[u_] * sp[t + 1];
+                d += fd[u_]; off += fd[u_] * sp[t - S];
+                d += fu[u_]; off += fu[u_] * sp[t + S];
+                v = d * p0 - off;
+            }
+            p[n] = p0;
+            q[n] = v;
+            acc += (double)p0 * (double)v;
+        }
+    }
+    const double t = block_total(acc, sh);
+    if (threadIdx.x == 0) pqp[blockIdx.x] = t;
+    if (blockIdx.x == 0 && threadIdx.x == 0) s->rz_new = rz;
+}
+
 #undef MG_FOR
 
 // ------------------------------------------------- multigrid construction
@@ -1334,8 +1579,28 @@ __global__ __launch_bounds__(1024) void k_symmetrize(double* M, int n) {
     }
 }
 
+// largest dynamic LDS the resident tail may take: the device's limit per
+// block less the static arrays, once the kernels are allowed to use it
+static int tail_lds_limit() {
+    int dev = 0, lim = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return 0;
+    lim -= (int)(kMaxCoarse * sizeof(double)) + 1024;
+    if (lim <= 0 ||
+        hipFuncSetAttribute((const void*)k_tail_lds<float>, hipFuncAttributeMaxDynamicSharedMemorySize, lim) !=
+            hipSuccess ||
+        hipFuncSetAttribute((const void*)k_tail_lds<double>, hipFuncAttributeMaxDynamicSharedMemorySize, lim) !=
+            hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return lim;
+}
+
 void mg_rebuild(pic_handle* h) {
     hipStream_t st = h->stream;
+    if (h->tail_lds_max < 0) h->tail_lds_max = tail_lds_limit();
     for (int l = 0; l + 1 < h->nlev; ++l) {
         Level& F = h->lv[l];
         Level& C = h->lv[l + 1];
@@ -1400,9 +1665,17 @@ static bool read_scalars(pic_handle* h) {
 }
 
 // symmetric V(2,2) cycle: on level l, y = M_l b (b in the level's b buffer;
-// level 0 takes b0 and writes y0)
+// level 0 takes b0 and writes y0).  A preconditioned-CG caller passes a
+// hook at level 0: the r.r partials its first launch tests for convergence,
+// and where the up pass leaves the r.z partials (one per level-0 tile).
+struct CgHook {
+    const double* chk;
+    int nchk;
+    double* rzp;
+};
+
 template <typename T>
-static void vcycle(pic_handle* h, int l, const T* b0, T* y0) {
+static void vcycle(pic_handle* h, int l, const T* b0, T* y0, const CgHook* hook = nullptr) {
     using V = VecSet<T>;
     hipStream_t st = h->stream;
     Level& L = h->lv[l];
@@ -1425,16 +1698,24 @@ static void vcycle(pic_handle* h, int l, const T* b0, T* y0) {
         ta.inv = V::cinv(h);
         ta.nc = h->ncoarse;
         ta.s = s;
+        TailLds o;
+        int off = 0;
+        for (int k = 0; k < ta.n; ++k) {
+            o.off[k] = off;
+            const int nn = (ta.L[k].nr + 1) * (ta.L[k].nz + 1);
+            off += (k + 1 < ta.n ? 13 : 2) * nn;
+        }
+        o.bytes = off * (int)sizeof(T);
+        if (o.bytes <= h->tail_lds_max) {
+            hipLaunchKernelGGL(k_tail_lds<T>, dim3(1), dim3(1024), o.bytes, st, ta, o);
+            return;
+        }
         hipLaunchKernelGGL(k_tail<T>, dim3(1), dim3(1024), 0, st, ta);
         return;
     }
     if (l == h->nlev - 1) {
-        if (l == 0) {
-            // single-level hierarchy: smoothing only
-            hipLaunchKernelGGL(k_jac0<T>, grid_for(L.nn), dim3(256), 0, st, V::ar(h), V::az(h), h->node_kind, x, b, y,
-                               s, L.nr, L.nz, 1);
-            return;
-        }
+        // (level 0 always has a coarser level: a grid too small to coarsen
+        // gets an identity level)
         hipLaunchKernelGGL(k_coarse<T>, dim3(1), dim3(256), 0, st, b, y, h->cmap, h->cmap + L.nn, V::cinv(h),
                            h->ncoarse, L.nn, s);
         return;
@@ -1456,6 +1737,9 @@ static void vcycle(pic_handle* h, int l, const T* b0, T* y0) {
     const dim3 nt(MgShape<T>::NT);
     a.tiles_r = (L.nr + ts) / ts;
     a.s = s;
+    a.chk = (l == 0 && hook) ? hook->chk : nullptr;
+    a.nchk = (l == 0 && hook) ? hook->nchk : 0;
+    a.rzp = (l == 0 && hook) ? hook->rzp : nullptr;
     const dim3 tiles(a.tiles_r * ((L.nz + ts) / ts));
     if (l == 0) hipLaunchKernelGGL((k_mg_down<T, true>), tiles, nt, 0, st, a);
     else hipLaunchKernelGGL((k_mg_down<T, false>), tiles, nt, 0, st, a);
@@ -1464,6 +1748,7 @@ static void vcycle(pic_handle* h, int l, const T* b0, T* y0) {
     a.yout = y;
     a.bc = nullptr;
     a.yc = V::y(C);
+    a.chk = nullptr;
     if (l == 0) hipLaunchKernelGGL((k_mg_up<T, true>), tiles, nt, 0, st, a);
     else hipLaunchKernelGGL((k_mg_up<T, false>), tiles, nt, 0, st, a);
 }
@@ -1498,9 +1783,60 @@ void harvest_iterate<double>(pic_handle* h, int k, const double* r, const double
                        &h->sc->done, h->w, h->nn, st);
 }
 
+// preconditioned CG with the multigrid preconditioner in fused launches
+// (k_cg_dir, k_cg_step, V-cycle); r is overwritten, x receives the
+// correction.  The second direction buffer is the level-0 y vector, which
+// the V-cycle leaves unused.  Returns the iteration count.
+template <typename T>
+static int pcg_mg(pic_handle* h, T* r, T* x, T* z, T* p, T* q, int max_iter, int* err, int first_check,
+                  bool x_zero) {
+    using V = VecSet<T>;
+    hipStream_t st = h->stream;
+    const int nn = h->nn;
+    DevScalars* s = h->sc;
+    T* pb[2] = {p, V::y(h->lv[0])};
+    double* rzp = h->cgpart;
+    double* pqp = h->cgpart + h->cgpart_n;
+    double* rrp = pqp + h->cgpart_n;
+    const int tiles_r0 = (h->nr + MgShape<T>::TS) / MgShape<T>::TS;
+    const int tiles0 = tiles_r0 * ((h->nz + MgShape<T>::TS) / MgShape<T>::TS);
+    hipLaunchKernelGGL(k_begin_cg, dim3(1), dim3(1), 0, st, s);
+    if (!x_zero) hipLaunchKernelGGL(k_fill<T>, grid_for(nn), dim3(256), 0, st, x, nn);
+    CgHook hook{nullptr, 0, rzp};
+    vcycle<T>(h, 0, r, z, &hook);
+    harvest_iterate<T>(h, 0, r, x, (const T*)z);
+    int it = 0;
+    for (; it < max_iter; ++it) {
+        T* pn = pb[it & 1];
+        const T* po = pb[(it + 1) & 1];
+        hipLaunchKernelGGL(k_cg_dir<T>, dim3(tiles0), dim3(MgShape<T>::NT), 0, st, V::ar(h), V::az(h), h->node_kind,
+                           (const T*)z, po, pn, q, (const double*)rzp, tiles0, pqp, s, it == 0 ? 1 : 0, h->nr, h->nz,
+                           tiles_r0);
+        hipLaunchKernelGGL(k_cg_step<T>, dim3(kCgBlocks), dim3(kCgThreads), 0, st, x, r, (const T*)pn, (const T*)q,
+                           (const double*)pqp, tiles0, rrp, s, nn);
+        hook = CgHook{rrp, kCgBlocks, rzp};
+        vcycle<T>(h, 0, r, z, &hook);
+        harvest_iterate<T>(h, it + 1, r, x, (const T*)z);
+        // the host reads the convergence flag first after first_check
+        // iterations (what the same solve needed last time), then after
+        // every iteration: iterations launched after convergence return at
+        // once but still cost their launches
+        if (it + 1 >= first_check || it + 1 == max_iter) {
+            if (!read_scalars(h)) { *err = PIC_E_HIP; return it; }
+            if (h->h_sc->done) break;
+        }
+    }
+    if (it == 0 && !read_scalars(h)) { *err = PIC_E_HIP; return it; }
+    if (h->h_sc->nonfinite) *err = PIC_E_NONFINITE;
+    return h->h_sc->iters;
+}
+
+// preconditioned CG with separate launches for every vector operation and
+// reduction (the identity preconditioner: plain CG)
 template <typename T>
 static int pcg(pic_handle* h, T* r, T* x, T* z, T* p, T* q, int max_iter, int* err, int ident = 0,
-               int first_check = kCheckEvery) {
+               int first_check = kCheckEvery, bool x_zero = false) {
+    if (!ident) return pcg_mg<T>(h, r, x, z, p, q, max_iter, err, first_check, x_zero);
     using V = VecSet<T>;
     hipStream_t st = h->stream;
     const int nn = h->nn;
@@ -1676,22 +2012,26 @@ __global__ __launch_bounds__(256) void k_add_phi(double* phi, const T* x, const 
         if (nk[n] < 0) phi[n] += f * (double)x[n];
 }
 
-// initial guess of the next solve: phi <- 2 phi - phi_prev (linear
-// extrapolation in time) on unknown nodes, phi_prev <- the previous phi;
-// without history only the copy is made
-__global__ __launch_bounds__(256) void k_extrapolate(double* phi, double* prev, const int8_t* nk, int nn, int have) {
+// initial guess of the next solve on unknown nodes, extrapolated in time
+// from the last solutions: quadratic (3 phi - 3 phi_prev + phi_prev2) once
+// two earlier ones are known, linear (2 phi - phi_prev) with one, none
+// without; the history moves one step back
+__global__ __launch_bounds__(256) void k_extrapolate(double* phi, double* prev, double* prev2, const int8_t* nk, int nn,
+                                                     int have) {
     for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += gridDim.x * blockDim.x) {
         if (nk[n] >= 0) continue;
-        const double t = phi[n];
-        if (have) phi[n] = 2.0 * t - prev[n];
+        const double t = phi[n], p1 = prev[n];
+        if (have >= 2) phi[n] = 3.0 * (t - p1) + prev2[n];
+        else if (have == 1) phi[n] = 2.0 * t - p1;
+        prev2[n] = p1;
         prev[n] = t;
     }
 }
 
 void launch_extrapolate(pic_handle* h) {
-    hipLaunchKernelGGL(k_extrapolate, grid_for(h->nn), dim3(256), 0, h->stream, h->phi, h->phi_prev,
-                       (const int8_t*)h->node_kind, h->nn, h->have_prev ? 1 : 0);
-    h->have_prev = true;
+    hipLaunchKernelGGL(k_extrapolate, grid_for(h->nn), dim3(256), 0, h->stream, h->phi, h->phi_prev, h->phi_prev2,
+                       (const int8_t*)h->node_kind, h->nn, h->have_prev);
+    h->have_prev = std::min(h->have_prev + 1, 2);
 }
 
 __global__ __launch_bounds__(256) void k_set_dirichlet(double* phi, const int8_t* nk, const double* Up, int nn) {
@@ -1771,7 +2111,7 @@ int field_solve(pic_handle* h, double* phi, const double* Q, const double* Up, d
             } else {
                 int& guess = h->cg_guess[0][std::min(outer, 3)];
                 const int its = pcg<float>(h, h->r32, h->x32, h->z32, h->p32, h->q32, h->cfg.solver.max_iter, &err,
-                                           method == PIC_SOLVE_IR_CG ? 1 : 0, guess);
+                                           method == PIC_SOLVE_IR_CG ? 1 : 0, guess, true);
                 guess = std::max(1, its);
                 total += its;
             }

@@ -35,6 +35,7 @@ constexpr int kMaxLevels = 16;
 constexpr int kMaxCoarse = 320;       // active nodes of the coarsest multigrid level
 constexpr int kCoarsestNodes = 100;   // coarsening stops at this many nodes (or when it cannot go on)
 constexpr int kRedBlocks = 4096;      // partial sums of a grid reduction
+constexpr int kCgBlocks = 512;        // blocks (and partial sums) of the fused CG vector kernels
 constexpr int kMaxEl = PIC_MAX_ELECTRODES;   // driven electrodes
 // absorption counter slot of conductor id: 0 ground, 1 electrode 1, 2 lost
 // (Neumann edge), 3 dielectric, 4 .. 6 electrodes 2 .. 4
@@ -142,13 +143,17 @@ struct pic_handle {
     int n_el;               // driven electrodes
     double* phiL[pic::kMaxEl];  // Laplace solution of each driven electrode
     double* phi_prev;       // the previous step's solution (initial-guess extrapolation)
-    bool have_prev;
+    double* phi_prev2;      // ... and the one before
+    int have_prev;          // solutions in the history (0 .. 2)
     float *ar32, *az32;
     float2* E;
     // solver vectors
     double *r64, *x64, *z64, *p64, *q64;
     float *r32, *x32, *z32, *p32, *q32;
     double* part;           // reduction partials
+    double* cgpart;         // fused CG partials: r.z (cgpart_n, one per level-0 multigrid tile), p.q, r.r
+    int cgpart_n;
+    int tail_lds_max = -1;  // dynamic LDS bytes the multigrid tail may use (-1: not yet asked)
     pic::Level lv[pic::kMaxLevels];
     int nlev;
     int* cmap;              // coarsest node -> dense index, -1 inactive
