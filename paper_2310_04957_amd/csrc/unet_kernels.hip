@@ -146,21 +146,35 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16* __restrict__ X, con
                                           next);
                 }
             }
-#pragma unroll
-            for (int t = 0; t < 9; ++t) {
+            // steps k = (tap, 16-channel slice); the fragments of step k + 1
+            // are read from LDS before the MFMAs of step k are issued (the
+            // scheduling barriers keep that order)
+            constexpr int KS = S::CH / 16, NK = 9 * KS;
+            auto frag = [&](int k, bf16x8* a, bf16x8* bq) {
+                const int t = k / KS, c0 = (k % KS) * 16;
                 const int dy = t / 3, dx = t % 3;   // halo coordinates: +1 offsets folded in
 #pragma unroll
-                for (int c0 = 0; c0 < S::CH; c0 += 16) {
-                    bf16x8 bfr[NT];
-                    for (int nt = 0; nt < NT; ++nt)
-                        bfr[nt] = *(const bf16x8*)&ws[(t * COUT + nt * 32 + m) * CW + ch * S::CH + c0 + kh];
-                    for (int s = 0; s < 2; ++s) {
-                        const int py = wave * 4 + s * 2 + m / 16, px = m % 16;
-                        const bf16x8 afr = *(const bf16x8*)&xs[((py + dy) * 18 + (px + dx)) * CP + c0 + kh];
-                        for (int nt = 0; nt < NT; ++nt)
-                            acc[s][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afr, bfr[nt], acc[s][nt], 0, 0, 0);
-                    }
+                for (int nt = 0; nt < NT; ++nt)
+                    bq[nt] = *(const bf16x8*)&ws[(t * COUT + nt * 32 + m) * CW + ch * S::CH + c0 + kh];
+#pragma unroll
+                for (int s = 0; s < 2; ++s) {
+                    const int py = wave * 4 + s * 2 + m / 16, px = m % 16;
+                    a[s] = *(const bf16x8*)&xs[((py + dy) * 18 + (px + dx)) * CP + c0 + kh];
                 }
+            };
+            bf16x8 afr[2][2], bfr[2][NT];
+            frag(0, afr[0], bfr[0]);
+#pragma unroll
+            for (int k = 0; k < NK; ++k) {
+                if (k + 1 < NK) frag(k + 1, afr[(k + 1) & 1], bfr[(k + 1) & 1]);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int s = 0; s < 2; ++s)
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt)
+                        acc[s][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afr[k & 1][s], bfr[k & 1][nt],
+                                                                              acc[s][nt], 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
         // D layout: lane holds column n = lane % 32, rows pm = 8(r/4) +
