@@ -33,7 +33,7 @@
 extern "C" {
 #endif
 
-#define PIC_ABI_VERSION 1
+#define PIC_ABI_VERSION 2
 #define PIC_MAX_REGIONS 32
 #define PIC_MAX_ELECTRODES 4           /* driven electrodes: conductor ids 1 .. 4 */
 
@@ -121,6 +121,12 @@ typedef struct {
     double inner_tol;           /* IR: relative tolerance of each FP32 inner solve */
     int32_t unet_batch;         /* learned preconditioner: training batch capacity (0: no U-net) */
     int32_t unet_pairs;         /* learned preconditioner: harvested (residual, error) pair slots */
+    int32_t graphs;             /* 1: each iteration of the multigrid-preconditioned CG (its two
+                                   vector launches and the V-cycle's launches) is replayed from a HIP
+                                   graph captured once per handle, so the host issues one launch per
+                                   iteration instead of ~15; 0: every kernel is launched on its own
+                                   (for callers that capture pic_step into graphs of their own).  The
+                                   results are the same bit for bit. */
 } pic_solver;
 
 typedef struct {

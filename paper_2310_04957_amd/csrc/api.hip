@@ -946,6 +946,10 @@ int pic_free(pic_handle* h) {
     (void)hipStreamSynchronize(h->stream);
     ev_collect(h);
     for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+    for (auto& g : h->cg_graph)
+        for (hipGraphExec_t e : g)
+            if (e) (void)hipGraphExecDestroy(e);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     if (h->h_sc) (void)hipHostFree(h->h_sc);
     if (h->h_ctr) (void)hipHostFree(h->h_ctr);
     delete h;

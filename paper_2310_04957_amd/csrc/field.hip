@@ -1010,7 +1010,7 @@ __global__ __launch_bounds__(1024) void k_tail_lds(TailArgs<T> a, TailLds o) {
 // (both pre-smoothing sweeps from a zero guess, the residual and its
 // restriction to the coarse right-hand side) and the up pass (prolongation
 // of the coarse correction and both post-smoothing sweeps).  A block owns a
-// tile of TS x TS fine nodes.  It first copies everything it reads (right-
+// tile of TX x TY fine nodes.  It first copies everything it reads (right-
 // hand side, stencil or face coefficients, node activity, the iterate and
 // the coarse correction), on the tile and the halo its sweeps need, into
 // LDS in one batch of independent loads, then runs the sweeps there: the
@@ -1042,30 +1042,53 @@ struct MgArgs {
     double* rzp;
 };
 
-// tile edge and threads per block: 32 x 32 nodes and 512 threads in FP32,
-// 16 x 16 and 256 in FP64 (whose LDS arrays and registers are twice as large)
+// tile shape and threads per block: 32 x 32 nodes and 512 threads in FP32,
+// 16 x 16 and 256 in FP64 (whose LDS arrays and registers are twice as
+// large).  The kernels take the tile's width and height as parameters;
+// 64 x 32 tiles (longer staged rows) measured no faster over a step.
 template <typename T>
 struct MgShape {
-    static constexpr int TS = sizeof(T) == 4 ? 32 : 16;
+    static constexpr int SQ = sizeof(T) == 4 ? 32 : 16;   // tile edge
     static constexpr int NT = sizeof(T) == 4 ? 512 : 256;
 };
 
 #define MG_FOR(U) _Pragma("unroll") for (int u_ = 0; u_ < (U); ++u_)
 
+// The stencil of node n = (i, j) on a level >= 1.  The Galerkin operator is
+// symmetric: the entry towards neighbour m = n + off_k equals the entry of m
+// back towards n, A_k[n] = A_{8-k}[m], so entries 0..3 are read from the
+// neighbours' entries 8..5 and only the arrays 4..8 are streamed (20 of 36
+// bytes per node; each level's operator is then exactly symmetric).
+// Entries towards nodes off the grid are zero.
+template <typename T>
+__device__ __forceinline__ void stencil_sym(const Sten& S, int n, int i, int j, int nr, int nz, int w, bool in,
+                                            T* c) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const int di = k % 3 - 1, dj = k / 3 - 1;
+        if (k >= 4) {
+            c[k] = in ? ((const T*)S.A[k])[n] : T(0);
+        } else {
+            const bool ok = in && i + di >= 0 && j + dj >= 0 && i + di <= nr && j + dj <= nz;
+            c[k] = ok ? ((const T*)S.A[8 - k])[n + dj * w + di] : T(0);
+        }
+    }
+}
+
 // Down pass.  Local coordinates have the origin (i0 - 4, j0 - 4) and row
-// stride S = TS + 6; regions: faces [0, S) (level 0), first iterate and
-// right-hand side [1, S), smoothed iterate [2, S - 1), residual [3, S - 2),
-// owned nodes [4, S - 2).  The residual region is what the tile's coarse
+// stride S = TX + 6 (SY = TY + 6 rows); regions, per coordinate: faces
+// [0, S) (level 0), first iterate and right-hand side [1, S), smoothed
+// iterate [2, S - 1), residual [3, S - 2), owned nodes [4, S - 2).  The residual region is what the tile's coarse
 // nodes restrict from (one node left of the tile when coarsening by 2).
 // Each thread takes the same nodes of the smoothed-iterate region in the
 // second sweep and in the residual, so on levels >= 1 it keeps their
 // stencils in registers.
-template <typename T, bool L0>
+template <typename T, bool L0, int TX, int TY>
 __global__ __launch_bounds__(MgShape<T>::NT) void k_mg_down(MgArgs<T> a) {
-    constexpr int TS = MgShape<T>::TS, NT = MgShape<T>::NT;
-    constexpr int S = TS + 6, N = S * S, U = (N + NT - 1) / NT;
-    constexpr int YW = TS + 3, NY = YW * YW, UY = (NY + NT - 1) / NT;
-    constexpr int UC = (TS * TS + NT - 1) / NT;
+    constexpr int NT = MgShape<T>::NT;
+    constexpr int S = TX + 6, SY = TY + 6, N = S * SY, U = (N + NT - 1) / NT;
+    constexpr int YW = TX + 3, NY = YW * (TY + 3), UY = (NY + NT - 1) / NT;
+    constexpr int UC = (TX * TY + NT - 1) / NT;
     __shared__ T sf[2][L0 ? N : 1];              // level 0: face coefficients ar, az
     __shared__ T sd[L0 ? 1 : N];                 // levels >= 1: diagonal
     __shared__ T sb[N], sx[N], sy[N];            // sx holds the residual after the second sweep
@@ -1086,10 +1109,10 @@ __global__ __launch_bounds__(MgShape<T>::NT) void k_mg_down(MgArgs<T> a) {
         if (done) return;
     }
     const int w = a.nr + 1, cw = a.cnr + 1;
-    const int i0 = (blockIdx.x % a.tiles_r) * TS, j0 = (blockIdx.x / a.tiles_r) * TS;
+    const int i0 = (blockIdx.x % a.tiles_r) * TX, j0 = (blockIdx.x / a.tiles_r) * TY;
     const int oi = i0 - 4, oj = j0 - 4;
     const int hr = a.cr - 1, hz = a.cz - 1;
-    const int CI = TS / a.cr, CJ = TS / a.cz, I0 = i0 / a.cr, J0 = j0 / a.cz;
+    const int CI = TX / a.cr, CJ = TY / a.cz, I0 = i0 / a.cr, J0 = j0 / a.cz;
     T cf[UY][L0 ? 1 : 9];
     T dc[UC];
     // stage: everything the block reads, in one batch of loads
@@ -1116,9 +1139,7 @@ __global__ __launch_bounds__(MgShape<T>::NT) void k_mg_down(MgArgs<T> a) {
                 const int ty = threadIdx.x + u_ * NT;
                 const int i = oi + 2 + ty % YW, j = oj + 2 + ty / YW;
                 const bool in = ty < NY && i >= 0 && j >= 0 && i <= a.nr && j <= a.nz;
-                const int n = j * w + i;
-#pragma unroll
-                for (int k = 0; k < 9; ++k) cf[u_][k] = in ? ((const T*)a.S.A[k])[n] : T(0);
+                stencil_sym<T>(a.S, j * w + i, i, j, a.nr, a.nz, w, in, cf[u_]);
             }
         }
 #pragma unroll
@@ -1188,7 +1209,7 @@ __global__ __launch_bounds__(MgShape<T>::NT) void k_mg_down(MgArgs<T> a) {
             }
             sy[t] = v;
             const int i = oi + li, j = oj + lj;
-            if (li >= 4 && lj >= 4 && li < S - 2 && lj < S - 2 && i <= a.nr && j <= a.nz) a.yout[j * w + i] = v;
+            if (li >= 4 && lj >= 4 && li < S - 2 && lj < SY - 2 && i <= a.nr && j <= a.nz) a.yout[j * w + i] = v;
         }
     }
     __syncthreads();
@@ -1196,7 +1217,7 @@ __global__ __launch_bounds__(MgShape<T>::NT) void k_mg_down(MgArgs<T> a) {
     MG_FOR(UY) {
         const int ty = threadIdx.x + u_ * NT;
         const int li = 2 + ty % YW, lj = 2 + ty / YW, t = lj * S + li;
-        if (ty < NY && li >= 3 && lj >= 3 && li < S - 2 && lj < S - 2) {
+        if (ty < NY && li >= 3 && lj >= 3 && li < S - 2 && lj < SY - 2) {
             T v = T(0);
             if (L0 ? sk[t] != 0 : sd[t] != T(0)) {
                 T d;
@@ -1227,26 +1248,27 @@ __global__ __launch_bounds__(MgShape<T>::NT) void k_mg_down(MgArgs<T> a) {
 }
 
 // Up pass.  Local coordinates have the origin (i0 - 2, j0 - 2) and row
-// stride S = TS + 4; regions: prolongated iterate [0, S), first
-// post-smoothing sweep [1, S - 1), owned nodes [2, S - 2).  The coarse
+// stride S = TX + 4 (SY = TY + 4 rows); regions, per coordinate:
+// prolongated iterate [0, S), first post-smoothing sweep [1, S - 1), owned
+// nodes [2, S - 2).  The coarse
 // correction is staged on coarse nodes from (i0 - 2) / cr - 1.  Each thread
 // takes the same nodes of the sweep region in both sweeps and keeps their
 // right-hand side and stencil (level 0: face coefficients) in registers.
-template <typename T, bool L0>
+template <typename T, bool L0, int TX, int TY>
 __global__ __launch_bounds__(MgShape<T>::NT) void k_mg_up(MgArgs<T> a) {
-    constexpr int TS = MgShape<T>::TS, NT = MgShape<T>::NT;
-    constexpr int S = TS + 4, N = S * S, U = (N + NT - 1) / NT;
-    constexpr int XW = TS + 2, NX = XW * XW, UX = (NX + NT - 1) / NT;
-    constexpr int CWM = TS + 7, NC = CWM * CWM, UC = (NC + NT - 1) / NT;   // coarsening by 1 is the widest
+    constexpr int NT = MgShape<T>::NT;
+    constexpr int S = TX + 4, SY = TY + 4, N = S * SY, U = (N + NT - 1) / NT;
+    constexpr int XW = TX + 2, NX = XW * (TY + 2), UX = (NX + NT - 1) / NT;
+    constexpr int CWM = TX + 7, NC = CWM * (TY + 7), UC = (NC + NT - 1) / NT;   // coarsening by 1 is the widest
     constexpr int NCF = L0 ? 4 : 9;
     __shared__ T sp[N], sx[N], sc[NC];
     __shared__ int8_t sk[N];                     // activity
     if (a.s->done) return;
     const int w = a.nr + 1, cw = a.cnr + 1;
-    const int i0 = (blockIdx.x % a.tiles_r) * TS, j0 = (blockIdx.x / a.tiles_r) * TS;
+    const int i0 = (blockIdx.x % a.tiles_r) * TX, j0 = (blockIdx.x / a.tiles_r) * TY;
     const int oi = i0 - 2, oj = j0 - 2;
     const int ci = (i0 - 2) / a.cr - 1, cj = (j0 - 2) / a.cz - 1;    // exact: i0 - 2 is even
-    const int CW = (TS + 4) / a.cr + 3, CH = (TS + 4) / a.cz + 3;
+    const int CW = (TX + 4) / a.cr + 3, CH = (TY + 4) / a.cz + 3;
     T cf[UX][NCF], cb[UX];
     {
         T vy[U];
@@ -1272,8 +1294,7 @@ __global__ __launch_bounds__(MgShape<T>::NT) void k_mg_up(MgArgs<T> a) {
                 cf[u_][2] = (in && j > 0) ? a.az[n - w] : T(0);
                 cf[u_][3] = (in && j < a.nz) ? a.az[n] : T(0);
             } else {
-#pragma unroll
-                for (int k = 0; k < 9; ++k) cf[u_][k] = in ? ((const T*)a.S.A[k])[n] : T(0);
+                stencil_sym<T>(a.S, n, i, j, a.nr, a.nz, w, in, cf[u_]);
             }
         }
         T vc[UC];
@@ -1350,7 +1371,7 @@ __global__ __launch_bounds__(MgShape<T>::NT) void k_mg_up(MgArgs<T> a) {
     MG_FOR(UX) {
         const int tx = threadIdx.x + u_ * NT;
         const int li = 1 + tx % XW, lj = 1 + tx / XW, t = lj * S + li, i = oi + li, j = oj + lj;
-        if (tx < NX && li >= 2 && lj >= 2 && li < S - 2 && lj < S - 2 && i <= a.nr && j <= a.nz) {
+        if (tx < NX && li >= 2 && lj >= 2 && li < S - 2 && lj < SY - 2 && i <= a.nr && j <= a.nz) {
             T v = T(0);
             if (sk[t]) {
                 T d;
@@ -1372,13 +1393,13 @@ __global__ __launch_bounds__(MgShape<T>::NT) void k_mg_up(MgArgs<T> a) {
 // of the last V-cycle; p = z on the first iteration) on the tile and one
 // node around it in LDS, then q = K p, p and q on the tile, and the
 // tile's partial of p.q.
-template <typename T>
+template <typename T, int TX, int TY>
 __global__ __launch_bounds__(MgShape<T>::NT) void k_cg_dir(const T* ar, const T* az, const int8_t* nk, const T* z,
                                                            const T* pold, T* p, T* q, const double* rzp, int nrz,
                                                            double* pqp, DevScalars* s, int first, int nr, int nz,
                                                            int tiles_r) {
-    constexpr int TS = MgShape<T>::TS, NT = MgShape<T>::NT;
-    constexpr int S = TS + 2, N = S * S, U = (N + NT - 1) / NT, UO = (TS * TS + NT - 1) / NT;
+    constexpr int NT = MgShape<T>::NT;
+    constexpr int S = TX + 2, N = S * (TY + 2), U = (N + NT - 1) / NT, UO = (TX * TY + NT - 1) / NT;
     __shared__ T sp[N];
     __shared__ double sh[16];
     if (s->done) return;
@@ -1389,7 +1410,7 @@ __global__ __launch_bounds__(MgShape<T>::NT) void k_cg_dir(const T* ar, const T*
     }
     const T be = first ? T(0) : (T)(rz / s->rz);
     const int w = nr + 1;
-    const int i0 = (blockIdx.x % tiles_r) * TS, j0 = (blockIdx.x / tiles_r) * TS;
+    const int i0 = (blockIdx.x % tiles_r) * TX, j0 = (blockIdx.x / tiles_r) * TY;
     const int oi = i0 - 1, oj = j0 - 1;
     T vz[U], vp[U];
     MG_FOR(U) {
@@ -1403,8 +1424,8 @@ __global__ __launch_bounds__(MgShape<T>::NT) void k_cg_dir(const T* ar, const T*
     int8_t k0[UO];
     MG_FOR(UO) {
         const int to = threadIdx.x + u_ * NT;
-        const int i = i0 + to % TS, j = j0 + to / TS, n = j * w + i;
-        const bool in = to < TS * TS && i <= nr && j <= nz;
+        const int i = i0 + to % TX, j = j0 + to / TX, n = j * w + i;
+        const bool in = to < TX * TY && i <= nr && j <= nz;
         k0[u_] = in ? nk[n] : (int8_t)1;
         fl[u_] = (in && i > 0) ? ar[n - 1] : T(0);
         fr[u_] = (in && i < nr) ? ar[n] : T(0);
@@ -1419,8 +1440,8 @@ __global__ __launch_bounds__(MgShape<T>::NT) void k_cg_dir(const T* ar, const T*
     double acc = 0.0;
     MG_FOR(UO) {
         const int to = threadIdx.x + u_ * NT;
-        const int li = to % TS, lj = to / TS, i = i0 + li, j = j0 + lj, n = j * w + i;
-        if (to < TS * TS && i <= nr && j <= nz) {
+        const int li = to % TX, lj = to / TX, i = i0 + li, j = j0 + lj, n = j * w + i;
+        if (to < TX * TY && i <= nr && j <= nz) {
             const int t = (lj + 1) * S + li + 1;
             const T p0 = sp[t];
             T v = T(0);
@@ -1733,24 +1754,24 @@ static void vcycle(pic_handle* h, int l, const T* b0, T* y0, const CgHook* hook 
     a.yc = nullptr;
     a.Dc = V::diag(C);
     a.nr = L.nr; a.nz = L.nz; a.cnr = C.nr; a.cnz = C.nz; a.cr = L.cr; a.cz = L.cz;
-    constexpr int ts = MgShape<T>::TS;
+    constexpr int SQ = MgShape<T>::SQ;
     const dim3 nt(MgShape<T>::NT);
-    a.tiles_r = (L.nr + ts) / ts;
+    a.tiles_r = (L.nr + SQ) / SQ;
     a.s = s;
     a.chk = (l == 0 && hook) ? hook->chk : nullptr;
     a.nchk = (l == 0 && hook) ? hook->nchk : 0;
     a.rzp = (l == 0 && hook) ? hook->rzp : nullptr;
-    const dim3 tiles(a.tiles_r * ((L.nz + ts) / ts));
-    if (l == 0) hipLaunchKernelGGL((k_mg_down<T, true>), tiles, nt, 0, st, a);
-    else hipLaunchKernelGGL((k_mg_down<T, false>), tiles, nt, 0, st, a);
+    const dim3 tiles(a.tiles_r * ((L.nz + SQ) / SQ));
+    if (l == 0) hipLaunchKernelGGL((k_mg_down<T, true, SQ, SQ>), tiles, nt, 0, st, a);
+    else hipLaunchKernelGGL((k_mg_down<T, false, SQ, SQ>), tiles, nt, 0, st, a);
     vcycle<T>(h, l + 1, nullptr, nullptr);
     a.yin = x;
     a.yout = y;
     a.bc = nullptr;
     a.yc = V::y(C);
     a.chk = nullptr;
-    if (l == 0) hipLaunchKernelGGL((k_mg_up<T, true>), tiles, nt, 0, st, a);
-    else hipLaunchKernelGGL((k_mg_up<T, false>), tiles, nt, 0, st, a);
+    if (l == 0) hipLaunchKernelGGL((k_mg_up<T, true, SQ, SQ>), tiles, nt, 0, st, a);
+    else hipLaunchKernelGGL((k_mg_up<T, false, SQ, SQ>), tiles, nt, 0, st, a);
 }
 
 // preconditioned CG on the level-0 operator; r is overwritten, x receives
@@ -1783,6 +1804,35 @@ void harvest_iterate<double>(pic_handle* h, int k, const double* r, const double
                        &h->sc->done, h->w, h->nn, st);
 }
 
+// Capture what `body` launches on the handle's stream into an executable
+// graph: the launches go to a private stream in capture mode (nothing
+// runs), which stands in for the handle's stream meanwhile.  False if the
+// runtime refuses any part; the caller then launches eagerly.
+template <class F>
+static bool capture_graph(pic_handle* h, hipGraphExec_t* out, F&& body) {
+    *out = nullptr;
+    if (!h->cap_stream && hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    hipStream_t keep = h->stream;
+    h->stream = h->cap_stream;
+    bool ok = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    hipGraph_t g = nullptr;
+    if (ok) {
+        body();
+        ok = hipStreamEndCapture(h->cap_stream, &g) == hipSuccess && g != nullptr;
+    }
+    h->stream = keep;
+    if (ok) ok = hipGraphInstantiate(out, g, nullptr, nullptr, 0) == hipSuccess;
+    if (g) (void)hipGraphDestroy(g);
+    if (!ok) {
+        *out = nullptr;
+        (void)hipGetLastError();
+    }
+    return ok;
+}
+
 // preconditioned CG with the multigrid preconditioner in fused launches
 // (k_cg_dir, k_cg_step, V-cycle); r is overwritten, x receives the
 // correction.  The second direction buffer is the level-0 y vector, which
@@ -1798,24 +1848,63 @@ static int pcg_mg(pic_handle* h, T* r, T* x, T* z, T* p, T* q, int max_iter, int
     double* rzp = h->cgpart;
     double* pqp = h->cgpart + h->cgpart_n;
     double* rrp = pqp + h->cgpart_n;
-    const int tiles_r0 = (h->nr + MgShape<T>::TS) / MgShape<T>::TS;
-    const int tiles0 = tiles_r0 * ((h->nz + MgShape<T>::TS) / MgShape<T>::TS);
-    hipLaunchKernelGGL(k_begin_cg, dim3(1), dim3(1), 0, st, s);
+    // r.z partials: one per level-0 tile of the V-cycle's up pass; p.q
+    // partials: one per tile of k_cg_dir (the same tiles)
+    constexpr int SQ = MgShape<T>::SQ;
+    const int tiles_r0 = (h->nr + SQ) / SQ;
+    const int tiles0 = tiles_r0 * ((h->nz + SQ) / SQ), nrz = tiles0;
     if (!x_zero) hipLaunchKernelGGL(k_fill<T>, grid_for(nn), dim3(256), 0, st, x, nn);
-    CgHook hook{nullptr, 0, rzp};
-    vcycle<T>(h, 0, r, z, &hook);
+    // the launches of the start and of iteration `it`, on h->stream
+    auto start = [&]() {
+        hipLaunchKernelGGL(k_begin_cg, dim3(1), dim3(1), 0, h->stream, s);
+        CgHook hook{nullptr, 0, rzp};
+        vcycle<T>(h, 0, r, z, &hook);
+    };
+    auto iteration = [&](int it) {
+        T* pn = pb[it & 1];
+        const T* po = pb[(it + 1) & 1];
+        hipLaunchKernelGGL((k_cg_dir<T, SQ, SQ>), dim3(tiles0), dim3(MgShape<T>::NT), 0, h->stream, V::ar(h), V::az(h),
+                           h->node_kind, (const T*)z, po, pn, q, (const double*)rzp, nrz, pqp, s, it == 0 ? 1 : 0,
+                           h->nr, h->nz, tiles_r0);
+        hipLaunchKernelGGL(k_cg_step<T>, dim3(kCgBlocks), dim3(kCgThreads), 0, h->stream, x, r, (const T*)pn,
+                           (const T*)q, (const double*)pqp, tiles0, rrp, s, nn);
+        CgHook hook{rrp, kCgBlocks, rzp};
+        vcycle<T>(h, 0, r, z, &hook);
+    };
+    // graphs: the launches only read the handle's fixed buffers, so the
+    // graphs captured at the first solve serve every later one (a harvested
+    // solve adds launches of its own and runs without them)
+    const int pi = sizeof(T) == 4 ? 0 : 1;
+    const bool want = h->cfg.solver.graphs != 0 && !h->harvesting;
+    if (want && !h->cg_graph_tried[pi]) {
+        h->cg_graph_tried[pi] = true;
+        hipGraphExec_t* g = h->cg_graph[pi];
+        bool ok = capture_graph(h, &g[0], start);
+        ok = ok && capture_graph(h, &g[1], [&] { iteration(0); });
+        ok = ok && capture_graph(h, &g[2], [&] { iteration(1); });
+        ok = ok && capture_graph(h, &g[3], [&] { iteration(2); });
+        if (!ok)
+            for (int v = 0; v < 4; ++v)
+                if (g[v]) { (void)hipGraphExecDestroy(g[v]); g[v] = nullptr; }
+        h->cg_graph_ok[pi] = ok;
+    }
+    const bool use = want && h->cg_graph_ok[pi];
+    if (use) {
+        if (hipGraphLaunch(h->cg_graph[pi][0], st) != hipSuccess) { *err = PIC_E_HIP; return 0; }
+    } else {
+        start();
+    }
     harvest_iterate<T>(h, 0, r, x, (const T*)z);
     int it = 0;
     for (; it < max_iter; ++it) {
-        T* pn = pb[it & 1];
-        const T* po = pb[(it + 1) & 1];
-        hipLaunchKernelGGL(k_cg_dir<T>, dim3(tiles0), dim3(MgShape<T>::NT), 0, st, V::ar(h), V::az(h), h->node_kind,
-                           (const T*)z, po, pn, q, (const double*)rzp, tiles0, pqp, s, it == 0 ? 1 : 0, h->nr, h->nz,
-                           tiles_r0);
-        hipLaunchKernelGGL(k_cg_step<T>, dim3(kCgBlocks), dim3(kCgThreads), 0, st, x, r, (const T*)pn, (const T*)q,
-                           (const double*)pqp, tiles0, rrp, s, nn);
-        hook = CgHook{rrp, kCgBlocks, rzp};
-        vcycle<T>(h, 0, r, z, &hook);
+        if (use) {
+            if (hipGraphLaunch(h->cg_graph[pi][it == 0 ? 1 : (it & 1) ? 2 : 3], st) != hipSuccess) {
+                *err = PIC_E_HIP;
+                return it;
+            }
+        } else {
+            iteration(it);
+        }
         harvest_iterate<T>(h, it + 1, r, x, (const T*)z);
         // the host reads the convergence flag first after first_check
         // iterations (what the same solve needed last time), then after

@@ -154,6 +154,14 @@ struct pic_handle {
     double* cgpart;         // fused CG partials: r.z (cgpart_n, one per level-0 multigrid tile), p.q, r.r
     int cgpart_n;
     int tail_lds_max = -1;  // dynamic LDS bytes the multigrid tail may use (-1: not yet asked)
+    // HIP graphs of the fused CG, per precision (0 FP32, 1 FP64): the start
+    // (k_begin_cg and the first V-cycle) and the iterations 0, odd, even
+    // (which differ in the direction buffers and the first-iteration flag);
+    // captured on a private stream at the first solve, replayed on `stream`
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t cg_graph[2][4] = {};
+    bool cg_graph_tried[2] = {false, false};
+    bool cg_graph_ok[2] = {false, false};
     pic::Level lv[pic::kMaxLevels];
     int nlev;
     int* cmap;              // coarsest node -> dense index, -1 inactive

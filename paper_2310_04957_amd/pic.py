@@ -12,7 +12,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpic.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 MAX_REGIONS = 32
 FIELDS = ("r", "z", "vr", "vt", "vz", "ar", "at", "az", "w")
 SOLVE_MGPCG_FP64, SOLVE_IR_MG, SOLVE_IR_UNET, SOLVE_IR_CG = 0, 1, 2, 3
@@ -61,7 +61,7 @@ class Run(C.Structure):
 
 class Solver(C.Structure):
     _fields_ = [("method", C.c_int32), ("tol", C.c_double), ("max_iter", C.c_int32), ("inner_tol", C.c_double),
-                ("unet_batch", C.c_int32), ("unet_pairs", C.c_int32)]
+                ("unet_batch", C.c_int32), ("unet_pairs", C.c_int32), ("graphs", C.c_int32)]
 
 
 class Config(C.Structure):
@@ -152,7 +152,8 @@ def _check(rc, where):
         raise PicError(rc, where)
 
 
-def make_config(w, load=True, timing=False, method=None, inner_tol=1e-4, unet_batch=0, unet_pairs=0):
+def make_config(w, load=True, timing=False, method=None, inner_tol=1e-4, unet_batch=0, unet_pairs=0,
+                graphs=False):
     """Marshal a workload dict (pic_inputs.workloads) into pic_config."""
     g, c, gas, run, sol = w["geometry"], w["circuit"], w["gas"], w["run"], w["solver"]
     cfg = Config()
@@ -182,6 +183,7 @@ def make_config(w, load=True, timing=False, method=None, inner_tol=1e-4, unet_ba
     cfg.solver.inner_tol = inner_tol
     cfg.solver.unet_batch = unet_batch
     cfg.solver.unet_pairs = unet_pairs
+    cfg.solver.graphs = 1 if graphs else 0
     more = w.get("circuits_more", [])
     if len(more) > MAX_EL - 1:
         raise ValueError("too many driven electrodes")
@@ -204,12 +206,12 @@ class Pic:
     """One simulation on the current HIP device and stream."""
 
     def __init__(self, w, load=True, timing=False, method=None, inner_tol=1e-4, device="cuda:0", unet_batch=0,
-                 unet_pairs=0):
+                 unet_pairs=0, graphs=False):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the HIP path has no CPU fallback")
         self.w = w
-        self.cfg = make_config(w, load, timing, method, inner_tol, unet_batch, unet_pairs)
+        self.cfg = make_config(w, load, timing, method, inner_tol, unet_batch, unet_pairs, graphs)
         L = lib()
         nbytes = workspace_bytes(self.cfg)
         self.device = torch.device(device)
@@ -346,9 +348,11 @@ class Pic:
         _check(lib().pic_moments_noalloc(self.h, sp, _ptr(N), _ptr(E)), "pic_moments_noalloc")
         return N, E
 
-    def set_solver(self, method=None, tol=None, max_iter=None, inner_tol=None):
+    def set_solver(self, method=None, tol=None, max_iter=None, inner_tol=None, graphs=None):
         s = Solver()
         C.pointer(s)[0] = self.cfg.solver
+        if graphs is not None:
+            s.graphs = 1 if graphs else 0
         if method is not None:
             s.method = method
         if tol is not None:
