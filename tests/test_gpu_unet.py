@@ -88,9 +88,12 @@ def test_forward_matches_oracle(shape):
         err, err_exact = _rel(out[b], ref), _rel(out[b], exact)
         print(f"[gpu] forward {nz}x{nr} image {b}: rel L2 vs rounded oracle {err:.2e}, vs FP64 {err_exact:.2e}, "
               f"bf16 storage effect {storage:.2e}", flush=True)
+        # the GPU and the rounded oracle store the same BF16 activations and
+        # differ only in the FP32 accumulation order, whose effect after
+        # rounding stays below the storage effect itself
         assert storage < 2e-2
-        assert err <= 2 * storage + 1e-3
-        assert err_exact <= 2 * storage + 1e-3
+        assert err <= storage + 1e-3
+        assert err_exact <= 1.2 * storage + 1e-3
     g.close()
 
 
@@ -126,9 +129,12 @@ def test_gradients_match_oracle():
         err, err_exact = _rel(gg[k], ref[k]), _rel(gg[k], exact[k])
         print(f"[gpu] grad {k}: vs rounded oracle {err:.2e}, vs FP64 {err_exact:.2e}, storage effect {storage:.2e}",
               flush=True)
-        assert storage < 1e-1, k
-        assert err <= 2 * storage + 1e-3, k
-        assert err_exact <= 2 * storage + 1e-3, k
+        # backward through BF16 activations: the storage effect grows with
+        # depth (to ~4e-2 at the middle of the network); the accumulation
+        # order moves the GPU by at most that much from the rounded oracle
+        assert storage < 5e-2, k
+        assert err <= 1.2 * storage + 1e-4, k
+        assert err_exact <= 1.6 * storage + 1e-4, k
     g.close()
 
 
