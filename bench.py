@@ -23,12 +23,11 @@ BYTES_PER_PARTICLE_STEP = 68.0   # read r z vr vt vz ar at az w, write all but w
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per particle-step of k_particles by the rocprofv3 FETCH_SIZE and
 # WRITE_SIZE counters (scaled by a plain-copy calibration: fetch x2, write
-# x1) over the first 9 steps after the load of gec1024x2048 (two electron
-# sort cycles, no ion sort): electrons 129.5 B (the step that applies a
-# sort fetches 50-61 GB, eight times a plain step), ions 69.8 B.  The
-# counters include lines served by the 256 MB last-level cache.  Set to
-# None whenever the kernel changes until it is measured again.
-MEASURED_BYTES_PER_PARTICLE_STEP = {"gec1024x2048": 99.4}
+# x1) over the first 9 steps after the load (two electron sort cycles, no
+# ion sort).  The counters include lines served by the 256 MB last-level
+# cache.  A workload is left out (traffic null) whenever the kernel changes,
+# until it is measured again.
+MEASURED_BYTES_PER_PARTICLE_STEP = {}
 
 
 def cpu_baseline(name, sample_particles, steps):

@@ -23,7 +23,7 @@ constexpr double kMAr = 39.948 * 1.66053906660e-27;
 constexpr double kEps0 = 8.8541878128e-12;
 constexpr double kKB = 1.380649e-23;
 constexpr double kPi = 3.14159265358979323846;
-constexpr int64_t kMaxSlots = (1LL << 30) - 16;   // particle arrays are addressed by 32-bit byte offsets
+constexpr int64_t kMaxSlots = (1LL << 30) - 16;   // slot indices and sort permutations are 32-bit
 
 // Fixed scratch of the allocation-free entry points: two int64 node grids
 // (the energy moments' N and E), one copy per GPU for the process's life.
@@ -354,8 +354,12 @@ size_t layout(pic_handle* h, char* base) {
     for (int sp = 0; sp < 2; ++sp) h->wtcol[sp] = c.take<float>((size_t)h->nr);
     size_t capmax = (size_t)std::max<int64_t>(std::max(h->cap[0], h->cap[1]), 1);
     for (int sp = 0; sp < 2; ++sp)
-        for (int b = 0; b < 2; ++b)
-            for (int k = 0; k < 9; ++k) h->buf[sp][b].f[k] = c.take<float>((size_t)std::max<int64_t>(h->cap[sp], 1));
+        for (int b = 0; b < 2; ++b) {
+            const size_t cs = (size_t)std::max<int64_t>(h->cap[sp], 1);
+            h->buf[sp][b].a = c.take<f32x4>(cs);
+            h->buf[sp][b].b = c.take<f32x4>(cs);
+            h->buf[sp][b].w = c.take<float>(cs);
+        }
     for (int b = 0; b < 2; ++b) {
         h->keys[b] = c.take<uint32_t>(capmax);
         h->idx[b] = c.take<uint32_t>(capmax);
@@ -978,11 +982,22 @@ int pic_get_particles(pic_handle* h, int32_t species, float* host9, int64_t* n) 
     int rc = sync_err(h);
     if (rc) return rc;
     const int64_t m = h->h_ctr->n_slots[species];
-    const int64_t cap = h->cap[species];
-    for (int k = 0; k < 9; ++k)
-        if (m > 0 && hipMemcpy(host9 + (size_t)k * cap, h->buf[species][h->cur[species]].f[k], (size_t)m * 4,
-                               hipMemcpyDeviceToHost) != hipSuccess)
-            return PIC_E_HIP;
+    const size_t cap = (size_t)h->cap[species];
+    const Species& S = h->buf[species][h->cur[species]];
+    if (m > 0) {
+        // the two vector groups through a host buffer, split into the
+        // caller's nine arrays
+        std::vector<float> g((size_t)m * 4);
+        for (int grp = 0; grp < 2; ++grp) {
+            if (hipMemcpy(g.data(), grp ? S.b : S.a, (size_t)m * 16, hipMemcpyDeviceToHost) != hipSuccess)
+                return PIC_E_HIP;
+            for (int k = 0; k < 4; ++k) {
+                float* out = host9 + (size_t)(4 * grp + k) * cap;
+                for (int64_t p = 0; p < m; ++p) out[p] = g[(size_t)p * 4 + k];
+            }
+        }
+        if (hipMemcpy(host9 + 8 * cap, S.w, (size_t)m * 4, hipMemcpyDeviceToHost) != hipSuccess) return PIC_E_HIP;
+    }
     *n = m;
     return PIC_OK;
 }
@@ -991,10 +1006,20 @@ int pic_set_particles(pic_handle* h, int32_t species, const float* host9, int64_
     if (!h || (!host9 && n > 0) || species < 0 || species > 1 || n < 0 || n > h->cap[species]) return PIC_E_ARG;
     h->pending[species] = false;   // the new particles replace the old, sorted or not
     if (hipStreamSynchronize(h->stream) != hipSuccess) return PIC_E_HIP;
-    for (int k = 0; k < 9; ++k)
-        if (n > 0 && hipMemcpy(h->buf[species][h->cur[species]].f[k], host9 + (size_t)k * n, (size_t)n * 4,
-                               hipMemcpyHostToDevice) != hipSuccess)
+    const Species& S = h->buf[species][h->cur[species]];
+    if (n > 0) {
+        std::vector<float> g((size_t)n * 4);
+        for (int grp = 0; grp < 2; ++grp) {
+            for (int k = 0; k < 4; ++k) {
+                const float* in = host9 + (size_t)(4 * grp + k) * n;
+                for (int64_t p = 0; p < n; ++p) g[(size_t)p * 4 + k] = in[p];
+            }
+            if (hipMemcpy(grp ? S.b : S.a, g.data(), (size_t)n * 16, hipMemcpyHostToDevice) != hipSuccess)
+                return PIC_E_HIP;
+        }
+        if (hipMemcpy(S.w, host9 + 8 * (size_t)n, (size_t)n * 4, hipMemcpyHostToDevice) != hipSuccess)
             return PIC_E_HIP;
+    }
     long long ns[2];
     DevCounters ct;
     if (hipMemcpy(&ct, h->ctr, sizeof(ct), hipMemcpyDeviceToHost) != hipSuccess) return PIC_E_HIP;

@@ -20,8 +20,8 @@ static_assert(kSlice % 256 == 0 && kRounds % 4 == 0, "decision words are shared 
 struct PushArgs {
     Geo g;
     Mcc m;
-    float* f[9];                 // particles written here (read here too unless perm is set)
-    const float* src[9];         // with perm: slot p reads src at perm[p] (a deferred sort)
+    Species f;                   // particles written here (read here too unless perm is set)
+    Species src;                 // with perm: slot p reads src at perm[p] (a deferred sort)
     const uint32_t* perm;
     uint32_t* keys;              // non-null: write each slot's sort key (a sort follows this step)
     uint32_t dead_key;
@@ -122,27 +122,11 @@ __device__ __forceinline__ unsigned int deposit(const Geo& g, const Loc& L, floa
     return 1u;
 }
 
-// SoA access by a 32-bit byte offset from the (uniform) array base, so one
-// offset register serves all nine arrays (slots < 2^30, checked at init)
-__device__ __forceinline__ float ldf(const float* base, uint32_t boff) {
-    return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + boff);
-}
-__device__ __forceinline__ void stf(float* base, uint32_t boff, float v) {
-    __builtin_nontemporal_store(v, reinterpret_cast<float*>(reinterpret_cast<char*>(base) + boff));
-}
-
-__device__ __forceinline__ P9 load9(float* const* f, uint32_t p) {
-    const uint32_t o = p << 2;
-    P9 s;
-    s.r = ldf(f[0], o); s.z = ldf(f[1], o); s.vr = ldf(f[2], o); s.vt = ldf(f[3], o); s.vz = ldf(f[4], o);
-    s.ar = ldf(f[5], o); s.at = ldf(f[6], o); s.az = ldf(f[7], o); s.w = ldf(f[8], o);
-    return s;
-}
-
-__device__ __forceinline__ void store8(float* const* f, uint32_t p, const P9& s) {
-    const uint32_t o = p << 2;
-    stf(f[0], o, s.r); stf(f[1], o, s.z); stf(f[2], o, s.vr); stf(f[3], o, s.vt); stf(f[4], o, s.vz);
-    stf(f[5], o, s.ar); stf(f[6], o, s.at); stf(f[7], o, s.az);
+// the step's store of the two vector groups (the weight does not change
+// within a step), streaming past the caches
+__device__ __forceinline__ void store8(const Species& f, uint32_t p, const P9& s) {
+    __builtin_nontemporal_store(group_a(s), &f.a[p]);
+    __builtin_nontemporal_store(group_b(s), &f.b[p]);
 }
 
 // slot p of this step: in place, or through the permutation of a deferred
@@ -150,16 +134,16 @@ __device__ __forceinline__ void store8(float* const* f, uint32_t p, const P9& s)
 // issued): a slot beyond the last, n - 1, is read in its place and the
 // caller ignores it.  Needs n >= 1.
 template <bool kMoved>
-__device__ __forceinline__ P9 load_slot(float* const* f, const float* const* src, const uint32_t* perm, long long p,
+__device__ __forceinline__ P9 load_slot(const Species& f, const Species& src, const uint32_t* perm, long long p,
                                         long long n) {
     const uint32_t q = (uint32_t)(p < n ? p : n - 1);
-    return kMoved ? load9(const_cast<float* const*>(src), perm[q]) : load9(f, q);
+    return kMoved ? load9(src, perm[q]) : load9(f, q);
 }
 
 // after a deferred sort the weight moves to the new buffer too
-__device__ __forceinline__ void store_slot(float* const* f, uint32_t p, const P9& s, bool moved) {
+__device__ __forceinline__ void store_slot(const Species& f, uint32_t p, const P9& s, bool moved) {
     store8(f, p, s);
-    if (moved) stf(f[8], p << 2, s.w);
+    if (moved) __builtin_nontemporal_store(s.w, &f.w[p]);
 }
 
 // One time step for every particle of one species.  A block of eight
@@ -192,7 +176,7 @@ __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4)))
     const long long nch = (n + kPushChunk - 1) / kPushChunk;
     // a block takes chunks blockIdx.x, + gridDim.x, ... (one chunk with the
     // launch below)
-    float* const* f = a.f;
+    const Species& f = a.f;
     constexpr bool moved = kMoved;
     unsigned int fallback = 0;
     unsigned int ndead = 0;   // dead keys written (uniform in the wavefront)
@@ -229,9 +213,9 @@ __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4)))
             auto probe = [&](long long p, Loc& L) {
                 if (p >= n) return false;
                 const uint32_t q = kMoved ? a.perm[p] : (uint32_t)p;
-                const float* const* rz = kMoved ? a.src : const_cast<const float* const*>(f);
-                const float r = rz[0][q];
-                L = locate(r, rz[1][q], g);
+                const f32x4 x = (kMoved ? a.src : f).a[q];
+                const float r = x.x;
+                L = locate(r, x.y, g);
                 return (r >= 0.0f) && L.inside;
             };
             Loc Lm, Lb;
@@ -437,10 +421,8 @@ void launch_particles(pic_handle* h, int sp, bool emit_keys) {
     // a deferred sort is applied on the way: read through the permutation,
     // write the other buffer
     const bool moved = h->pending[sp];
-    for (int k = 0; k < 9; ++k) {
-        a.src[k] = h->buf[sp][h->cur[sp]].f[k];
-        a.f[k] = h->buf[sp][moved ? 1 - h->cur[sp] : h->cur[sp]].f[k];
-    }
+    a.src = h->buf[sp][h->cur[sp]];
+    a.f = h->buf[sp][moved ? 1 - h->cur[sp] : h->cur[sp]];
     a.perm = moved ? h->perm[sp] : nullptr;
     a.E = h->E;
     a.dep = h->dep[h->dep_cur][sp];
@@ -545,8 +527,8 @@ __global__ __launch_bounds__(1024) void k_birth_scan(DevCounters* c, const int* 
 
 struct BirthArgs {
     Geo g;
-    float* fe[9];
-    float* fi[9];
+    Species fe;
+    Species fi;
     unsigned long long* dep_e;
     unsigned long long* dep_i;
     unsigned long long* wallq;
@@ -559,7 +541,7 @@ struct BirthArgs {
 };
 
 // Newborn electron and ion: a_bar = 0, predict, absorption, deposit.
-__device__ __forceinline__ void place_newborn(const Geo& g, float* const* f, long long slot, P9 s, float dt,
+__device__ __forceinline__ void place_newborn(const Geo& g, const Species& f, long long slot, P9 s, float dt,
                                               int sp, unsigned long long* dep, unsigned long long* wallq,
                                               DevCounters* ctr) {
     d1_predict(s, dt);
@@ -598,9 +580,8 @@ __device__ __forceinline__ void place_newborn(const Geo& g, float* const* f, lon
                 if (loc[k]) atomicAdd(&ctr->absorbed[sp][k], loc[k]);
         }
     }
-    f[0][slot] = removed ? -1.0f : s.r;
-    f[1][slot] = s.z; f[2][slot] = s.vr; f[3][slot] = s.vt; f[4][slot] = s.vz;
-    f[5][slot] = s.ar; f[6][slot] = s.at; f[7][slot] = s.az; f[8][slot] = s.w;
+    if (removed) s.r = -1.0f;
+    store9(f, (uint32_t)slot, s);
     if (!removed) {
         int64_t c[4];
         node_shares(L, (double)s.w, g.invd[L.i], c);
@@ -661,10 +642,8 @@ void launch_births(pic_handle* h) {
                        h->stage_segoff, (long long)h->cap[0], (long long)h->cap[1]);
     BirthArgs a;
     a.g = make_geo(h);
-    for (int k = 0; k < 9; ++k) {
-        a.fe[k] = h->buf[0][h->cur[0]].f[k];
-        a.fi[k] = h->buf[1][h->cur[1]].f[k];
-    }
+    a.fe = h->buf[0][h->cur[0]];
+    a.fi = h->buf[1][h->cur[1]];
     a.dep_e = h->dep[h->dep_cur][0];
     a.dep_i = h->dep[h->dep_cur][1];
     a.wallq = h->wallq;
@@ -679,7 +658,7 @@ void launch_births(pic_handle* h) {
 
 // ------------------------------------------------------------------ loader
 struct LoadArgs {
-    float* f[9];
+    Species f;
     const double* cdf;
     const int* cell;
     int nv, nr;
@@ -719,17 +698,19 @@ __global__ __launch_bounds__(kBlock) void k_load(LoadArgs a) {
         double z = (cj + (double)u01(x.z)) * a.dz;
         float vr, vt, vz;
         maxwell3(y, a.vth, vr, vt, vz);
-        a.f[0][p] = (float)r; a.f[1][p] = (float)z;
-        a.f[2][p] = vr; a.f[3][p] = vt; a.f[4][p] = vz;
-        a.f[5][p] = 0.0f; a.f[6][p] = 0.0f; a.f[7][p] = 0.0f;
-        a.f[8][p] = a.weights == PIC_WEIGHTS_CELL ? a.wt[ci] : a.W;
+        P9 s;
+        s.r = (float)r; s.z = (float)z;
+        s.vr = vr; s.vt = vt; s.vz = vz;
+        s.ar = 0.0f; s.at = 0.0f; s.az = 0.0f;
+        s.w = a.weights == PIC_WEIGHTS_CELL ? a.wt[ci] : a.W;
+        store9(a.f, (uint32_t)p, s);
     }
 }
 
 void launch_load(pic_handle* h, int sp, const double* cdf, const int* cell, int nv, double vvac, int64_t n,
                  float W, float vth) {
     LoadArgs a;
-    for (int k = 0; k < 9; ++k) a.f[k] = h->buf[sp][h->cur[sp]].f[k];
+    a.f = h->buf[sp][h->cur[sp]];
     a.cdf = cdf; a.cell = cell; a.nv = nv; a.nr = h->nr;
     a.vvac = vvac; a.dr = h->dr; a.dz = h->dz;
     a.n = n; a.W = W; a.vth = vth; a.sp = sp;
@@ -744,7 +725,7 @@ void launch_load(pic_handle* h, int sp, const double* cdf, const int* cell, int 
 // with predict = 0, a plain deposit of the stored positions.
 struct PDArgs {
     Geo g;
-    float* f[9];
+    Species f;
     unsigned long long* dep;
     unsigned long long* wallq;
     DevCounters* ctr;
@@ -756,7 +737,7 @@ __global__ __launch_bounds__(kBlock) void k_predict_deposit(PDArgs a) {
     const long long n = a.ctr->n_slots[a.sp];
     for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < n;
          p += (long long)gridDim.x * blockDim.x) {
-        P9 s = load9(a.f, p);
+        P9 s = load9(a.f, (uint32_t)p);
         if (!(s.r >= 0.0f)) continue;
         if (a.predict) {
             place_newborn(a.g, a.f, p, s, a.dt, a.sp, a.dep, a.wallq, a.ctr);
@@ -777,7 +758,7 @@ __global__ __launch_bounds__(kBlock) void k_predict_deposit(PDArgs a) {
 static void launch_pd(pic_handle* h, int sp, int predict) {
     PDArgs a;
     a.g = make_geo(h);
-    for (int k = 0; k < 9; ++k) a.f[k] = h->buf[sp][h->cur[sp]].f[k];
+    a.f = h->buf[sp][h->cur[sp]];
     a.dep = h->dep[h->dep_cur][sp];
     a.wallq = h->wallq;
     a.ctr = h->ctr;
@@ -798,14 +779,14 @@ void launch_redeposit(pic_handle* h) {
 
 struct MomArgs {
     Geo g;
-    const float* f[9];
+    Species f;
     const long long* n_slots;
     int sp;
     double half_m_over_e;
     unsigned long long *N, *E;
 };
 
-__global__ __launch_bounds__(kBlock) void k_count_alive(const float* r, const long long* n_slots, int sp,
+__global__ __launch_bounds__(kBlock) void k_count_alive(const f32x4* ra, const long long* n_slots, int sp,
                                                         unsigned long long* out) {
     __shared__ unsigned int s_cnt;
     if (threadIdx.x == 0) s_cnt = 0;
@@ -814,7 +795,7 @@ __global__ __launch_bounds__(kBlock) void k_count_alive(const float* r, const lo
     unsigned int c = 0;
     for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < n;
          p += (long long)gridDim.x * blockDim.x)
-        c += (r[p] >= 0.0f);
+        c += (ra[p].x >= 0.0f);
     atomicAdd(&s_cnt, c);
     __syncthreads();
     if (threadIdx.x == 0) atomicAdd(out, (unsigned long long)s_cnt);
@@ -829,13 +810,13 @@ __global__ __launch_bounds__(kBlock) void k_moments(MomArgs a) {
     const long long n = a.n_slots[a.sp];
     for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < n;
          p += (long long)gridDim.x * blockDim.x) {
-        const float r = a.f[0][p];
-        if (!(r >= 0.0f)) continue;
-        const Loc L = locate(r, a.f[1][p], a.g);
+        const P9 s = load9(a.f, (uint32_t)p);
+        if (!(s.r >= 0.0f)) continue;
+        const Loc L = locate(s.r, s.z, a.g);
         if (!L.inside) continue;
         int64_t c[4];
-        node_shares(L, (double)a.f[8][p], a.g.invd[L.i], c);
-        const double vr = a.f[2][p], vt = a.f[3][p], vz = a.f[4][p];
+        node_shares(L, (double)s.w, a.g.invd[L.i], c);
+        const double vr = s.vr, vt = s.vt, vz = s.vz;
         double v2 = vr * vr;
         v2 = v2 + vt * vt;
         v2 = v2 + vz * vz;
@@ -854,7 +835,7 @@ __global__ __launch_bounds__(kBlock) void k_moments(MomArgs a) {
 void launch_moments(pic_handle* h, int sp, unsigned long long* N, unsigned long long* E) {
     MomArgs a;
     a.g = make_geo(h);
-    for (int k = 0; k < 9; ++k) a.f[k] = h->buf[sp][h->cur[sp]].f[k];
+    a.f = h->buf[sp][h->cur[sp]];
     a.n_slots = (const long long*)h->ctr->n_slots;
     a.sp = sp;
     const double QE = 1.602176634e-19, ME = 9.1093837015e-31, MAR = 39.948 * 1.66053906660e-27;
@@ -871,7 +852,7 @@ int launch_count_alive(pic_handle* h, long long* out2) {
     unsigned long long* d = (unsigned long long*)&h->ctr->pad[0];
     launch_zero_u64(d, 2, h->stream);
     for (int sp = 0; sp < 2; ++sp)
-        hipLaunchKernelGGL(k_count_alive, dim3(512), dim3(kBlock), 0, h->stream, h->buf[sp][h->cur[sp]].f[0],
+        hipLaunchKernelGGL(k_count_alive, dim3(512), dim3(kBlock), 0, h->stream, (const f32x4*)h->buf[sp][h->cur[sp]].a,
                            (const long long*)h->ctr->n_slots, sp, d + sp);
     if (hipMemcpyAsync(out2, d, 2 * sizeof(long long), hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
         hipStreamSynchronize(h->stream) != hipSuccess)

@@ -132,6 +132,38 @@ struct P9 {
     float r, z, vr, vt, vz, ar, at, az, w;
 };
 
+// Storage of one species: 36 bytes a slot in three arrays, a = (r~, z~,
+// v*_r, v*_theta), b = (v*_z, a_bar_r, a_bar_theta, a_bar_z) and the
+// weight w.  A slot read out of order (a sort being applied, splitting)
+// touches three memory lines instead of nine; in-order reads and writes
+// are 16-byte vector accesses.  Slot indices are 32-bit.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+struct Species {
+    f32x4* a;
+    f32x4* b;
+    float* w;
+};
+
+__device__ __forceinline__ P9 load9(const Species& S, uint32_t p) {
+    const f32x4 x = S.a[p], y = S.b[p];
+    P9 s;
+    s.r = x.x; s.z = x.y; s.vr = x.z; s.vt = x.w;
+    s.vz = y.x; s.ar = y.y; s.at = y.z; s.az = y.w;
+    s.w = S.w[p];
+    return s;
+}
+
+__device__ __forceinline__ f32x4 group_a(const P9& s) { return f32x4{s.r, s.z, s.vr, s.vt}; }
+__device__ __forceinline__ f32x4 group_b(const P9& s) { return f32x4{s.vz, s.ar, s.at, s.az}; }
+
+// all nine values (the weight too)
+__device__ __forceinline__ void store9(const Species& S, uint32_t p, const P9& s) {
+    S.a[p] = group_a(s);
+    S.b[p] = group_b(s);
+    S.w[p] = s.w;
+}
+
 // correct: a = (q/m) E(x~); x = x~ + dt^2/2 a; v = v* + dt/2 a;
 // a_bar = (a_bar + a)/2; crossing the axis reflects r, v_r, v_t, a_r, a_t.
 __device__ __forceinline__ void d1_correct(P9& p, float Er, float Ez, float qm, float dt) {

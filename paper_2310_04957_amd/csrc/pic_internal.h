@@ -94,10 +94,6 @@ struct Level {
     float *x32, *y32, *b32, *res32;
 };
 
-struct Species {
-    float* f[9];                 // r z vr vt vz ar at az w
-};
-
 }  // namespace pic
 
 struct pic_handle {

@@ -17,8 +17,7 @@ constexpr int kSeg = 4096;   // elements per block of the scan kernels
 
 struct KeyArgs {
     Geo g;
-    const float* r;
-    const float* z;
+    const f32x4* rz;          // the particles' first vector group (r, z, ...)
     uint32_t* keys;
     const long long* n_slots;
     const long long* start;   // non-null: keys below *start are already written
@@ -33,10 +32,10 @@ __global__ __launch_bounds__(kBlock) void k_keys(KeyArgs a) {
     unsigned int dead = 0;
     for (long long p = p0 + blockIdx.x * (long long)blockDim.x + threadIdx.x; p < n;
          p += (long long)gridDim.x * blockDim.x) {
-        float r = a.r[p];
+        const f32x4 x = a.rz[p];
         uint32_t key = a.dead_key;
-        if (r >= 0.0f) {
-            Loc L = locate(r, a.z[p], a.g);
+        if (x.x >= 0.0f) {
+            Loc L = locate(x.x, x.y, a.g);
             if (L.inside) key = tile_key(L, a.ntr);
         }
         dead += (key == a.dead_key);
@@ -283,8 +282,8 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* kin, const u
 }
 
 struct GatherArgs {
-    const float* src[9];
-    float* dst[9];
+    Species src;
+    Species dst;
     const uint32_t* idx;
     const long long* n_slots;
     int sp;
@@ -294,9 +293,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a) {
     const long long n = a.n_slots[a.sp];
     for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n;
          q += (long long)gridDim.x * blockDim.x) {
-        const uint32_t o = a.idx[q];
-#pragma unroll
-        for (int k = 0; k < 9; ++k) a.dst[k][q] = a.src[k][o];
+        store9(a.dst, (uint32_t)q, load9(a.src, a.idx[q]));
     }
 }
 
@@ -323,7 +320,7 @@ void launch_sort(pic_handle* h, int sp, bool deferred, bool keyed) {
     ka.g.inv_dr = (float)(1.0 / h->dr); ka.g.inv_dz = (float)(1.0 / h->dz);
     ka.g.invd = h->invd; ka.g.cell_kind = h->cell_kind; ka.g.node_kind = h->node_kind;
     for (int k = 0; k < 3; ++k) ka.g.edge_bc[k] = h->cfg.geom.edge_bc[k];
-    ka.r = S.f[0]; ka.z = S.f[1];
+    ka.rz = S.a;
     ka.keys = h->keys[0];
     ka.n_slots = ns; ka.dead = dead + sp; ka.sp = sp; ka.ntr = h->ntr;
     ka.start = keyed ? (const long long*)&h->ctr->n_keyed[sp] : nullptr;
@@ -355,7 +352,8 @@ void materialize(pic_handle* h, int sp) {
     GatherArgs ga;
     const Species& S = h->buf[sp][h->cur[sp]];
     Species& D = h->buf[sp][1 - h->cur[sp]];
-    for (int k = 0; k < 9; ++k) { ga.src[k] = S.f[k]; ga.dst[k] = D.f[k]; }
+    ga.src = S;
+    ga.dst = D;
     ga.idx = h->perm[sp];
     ga.n_slots = h->ctr->n_slots;
     ga.sp = sp;
@@ -375,7 +373,7 @@ void materialize(pic_handle* h, int sp) {
 // from atomics, so the result is deterministic.
 struct SplitArgs {
     Geo g;
-    float* f[9];
+    Species f;
     const float* wt;          // reference weight per cell column
     DevCounters* ctr;
     long long* off;           // per chunk: copies, then their exclusive offsets
@@ -390,11 +388,11 @@ __device__ __forceinline__ int split_doublings(float w, float t) {
 }
 
 __device__ __forceinline__ int split_m(const SplitArgs& a, long long p) {
-    const float r = a.f[0][p];
-    if (!(r >= 0.0f)) return 0;
-    const Loc L = locate(r, a.f[1][p], a.g);
+    const f32x4 x = a.f.a[p];
+    if (!(x.x >= 0.0f)) return 0;
+    const Loc L = locate(x.x, x.y, a.g);
     if (!L.inside) return 0;
-    return split_doublings(a.f[8][p], a.wt[L.i]);
+    return split_doublings(a.f.w[p], a.wt[L.i]);
 }
 
 // exclusive scan of v over the block (kBlock threads); *total gets the sum
@@ -482,12 +480,10 @@ __global__ __launch_bounds__(kBlock) void k_split_write(SplitArgs a) {
             int total;
             const int ex = block_exscan(e, sh, &total);
             if (e > 0) {
-                float v[9];
-                for (int k = 0; k < 9; ++k) v[k] = a.f[k][p];
-                v[8] = v[8] / (float)(1 << m);
-                a.f[8][p] = v[8];
-                for (int q = 0; q < e; ++q)
-                    for (int k = 0; k < 9; ++k) a.f[k][out + ex + q] = v[k];
+                P9 v = load9(a.f, (uint32_t)p);
+                v.w = v.w / (float)(1 << m);
+                a.f.w[p] = v.w;
+                for (int q = 0; q < e; ++q) store9(a.f, (uint32_t)(out + ex + q), v);
             }
             out += total;
         }
@@ -509,7 +505,7 @@ void launch_split(pic_handle* h, int sp) {
     a.g.inv_dr = (float)(1.0 / h->dr); a.g.inv_dz = (float)(1.0 / h->dz);
     a.g.invd = h->invd; a.g.cell_kind = h->cell_kind; a.g.node_kind = h->node_kind;
     for (int k = 0; k < 3; ++k) a.g.edge_bc[k] = h->cfg.geom.edge_bc[k];
-    for (int k = 0; k < 9; ++k) a.f[k] = h->buf[sp][h->cur[sp]].f[k];
+    a.f = h->buf[sp][h->cur[sp]];
     a.wt = h->wtcol[sp];
     a.ctr = h->ctr;
     a.off = h->split_off;
