@@ -20,6 +20,17 @@ constexpr double kEps0 = 8.8541878128e-12;
 constexpr double kOmega = 0.7;   // damped-Jacobi weight of the multigrid smoother
 constexpr int kCheckEvery = 4;   // Krylov iterations between host convergence reads (unguided)
 
+// Tile (or node range) of a block in the tiled and stencil kernels.  The
+// hardware deals consecutive blocks round-robin to the eight XCDs, each with
+// its own L2; the tiles are handed to the XCDs in contiguous runs instead,
+// so that the halo lines neighbouring tiles share are fetched into one L2.
+// Partial sums stay indexed by tile, so the results do not change.  (A
+// bijection of 0 .. n-1: XCD x takes n/8 tiles, one more if x < n % 8.)
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+    const int q = n >> 3, r = n & 7, x = b & 7;
+    return x * q + min(x, r) + (b >> 3);
+}
+
 // ------------------------------------------------------------ small utils
 __global__ void k_fill_u64(unsigned long long* p, size_t n) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
@@ -277,6 +288,16 @@ __global__ __launch_bounds__(256) void k_circuit(CircArgs a) {
     }
     const double t0 = s->t, t1 = t0 + a.dt;
     const double U0 = s->U_E[0];
+    // the capacitance matrix and the energy sums in registers for the whole
+    // integration (the same operations in the same order as on the scalars,
+    // without a dependent memory access per stage)
+    double Cm[kMaxEl][kMaxEl], en[5];
+#pragma unroll
+    for (int e = 0; e < NE; ++e)
+#pragma unroll
+        for (int f = 0; f < NE; ++f) Cm[e][f] = s->Cm[e][f];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) en[k] = s->energy[k];
     double Y[NE][6], U[NE], q0[NE];
     int M = 0;
 #pragma unroll
@@ -296,34 +317,34 @@ __global__ __launch_bounds__(256) void k_circuit(CircArgs a) {
         const bool pe = a.ce[0].kind != PIC_IDEAL_SOURCE;
         double pa[5], pb[5];
         if (pe) {
-            volts<NE>(a, s->Cm, QP, t0, Y, U);
+            volts<NE>(a, Cm, QP, t0, Y, U);
             circ_p(a.ce[0], U[0], t0, Y[0], pa);
         }
         for (int m = 0; m < M; ++m) {
             const double t = t0 + m * hh;
             double k1[NE][6], k2[NE][6], k3[NE][6], k4[NE][6], yt[NE][6];
-            volts<NE>(a, s->Cm, QP, t, Y, U);
+            volts<NE>(a, Cm, QP, t, Y, U);
 #pragma unroll
             for (int e = 0; e < NE; ++e) circ_f(a.ce[e], U[e], Iconv[e], t, Y[e], k1[e]);
 #pragma unroll
             for (int e = 0; e < NE; ++e)
 #pragma unroll
                 for (int k = 0; k < 6; ++k) yt[e][k] = Y[e][k] + 0.5 * hh * k1[e][k];
-            volts<NE>(a, s->Cm, QP, t + 0.5 * hh, yt, U);
+            volts<NE>(a, Cm, QP, t + 0.5 * hh, yt, U);
 #pragma unroll
             for (int e = 0; e < NE; ++e) circ_f(a.ce[e], U[e], Iconv[e], t + 0.5 * hh, yt[e], k2[e]);
 #pragma unroll
             for (int e = 0; e < NE; ++e)
 #pragma unroll
                 for (int k = 0; k < 6; ++k) yt[e][k] = Y[e][k] + 0.5 * hh * k2[e][k];
-            volts<NE>(a, s->Cm, QP, t + 0.5 * hh, yt, U);
+            volts<NE>(a, Cm, QP, t + 0.5 * hh, yt, U);
 #pragma unroll
             for (int e = 0; e < NE; ++e) circ_f(a.ce[e], U[e], Iconv[e], t + 0.5 * hh, yt[e], k3[e]);
 #pragma unroll
             for (int e = 0; e < NE; ++e)
 #pragma unroll
                 for (int k = 0; k < 6; ++k) yt[e][k] = Y[e][k] + hh * k3[e][k];
-            volts<NE>(a, s->Cm, QP, t + hh, yt, U);
+            volts<NE>(a, Cm, QP, t + hh, yt, U);
 #pragma unroll
             for (int e = 0; e < NE; ++e) circ_f(a.ce[e], U[e], Iconv[e], t + hh, yt[e], k4[e]);
 #pragma unroll
@@ -333,24 +354,26 @@ __global__ __launch_bounds__(256) void k_circuit(CircArgs a) {
                     for (int k = 0; k < 6; ++k)
                         Y[e][k] += hh / 6.0 * (k1[e][k] + 2.0 * k2[e][k] + 2.0 * k3[e][k] + k4[e][k]);
             if (pe) {
-                volts<NE>(a, s->Cm, QP, t + hh, Y, U);
+                volts<NE>(a, Cm, QP, t + hh, Y, U);
                 circ_p(a.ce[0], U[0], t + hh, Y[0], pb);
 #pragma unroll
                 for (int k = 0; k < 5; ++k) {
-                    s->energy[k] += 0.5 * hh * (pa[k] + pb[k]);
+                    en[k] += 0.5 * hh * (pa[k] + pb[k]);
                     pa[k] = pb[k];
                 }
             }
         }
     }
-    volts<NE>(a, s->Cm, QP, t1, Y, U);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) s->energy[k] = en[k];
+    volts<NE>(a, Cm, QP, t1, Y, U);
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
         if (a.ce[e].kind == PIC_IDEAL_SOURCE) {
             // the charge that holds the source voltage: Q = C U + Q_P
             double q = 0.0;
 #pragma unroll
-            for (int f = 0; f < NE; ++f) q += s->Cm[e][f] * U[f];
+            for (int f = 0; f < NE; ++f) q += Cm[e][f] * U[f];
             q += QP[e];
             s->I_ccp[e] = (q - s->Q_E[e]) / a.dt - Iconv[e];
             s->Q_E[e] = q;
@@ -421,13 +444,15 @@ __device__ __forceinline__ double dir_val(int8_t k, const double* U) { return k 
 // value; partial sums of r.r and of b.b (b = Q + Dirichlet lift)
 __global__ __launch_bounds__(256) void k_resid64(const double* ar, const double* az, const int8_t* nk,
                                                  const double* Q, const double* phi, const double* Up, double* r,
-                                                 double* part, int nr, int nz) {
+                                                 double* part, int nr, int nz, const DevScalars* s) {
     __shared__ double sh[4];
+    if (s->outer_done) return;
     const int w = nr + 1, nn = w * (nz + 1);
     double U[kMaxEl];
     for (int e = 0; e < kMaxEl; ++e) U[e] = Up[e];
     double rr = 0.0, bb = 0.0;
-    for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += gridDim.x * blockDim.x) {
+    const int lb = xcd_tile(blockIdx.x, gridDim.x);
+    for (int n = lb * blockDim.x + threadIdx.x; n < nn; n += gridDim.x * blockDim.x) {
         const int8_t k0 = nk[n];
         if (k0 >= 0) { r[n] = 0.0; continue; }
         const int i = n % w, j = n / w;
@@ -449,13 +474,14 @@ __global__ __launch_bounds__(256) void k_resid64(const double* ar, const double*
     }
     double t1 = block_sum(rr, sh);
     double t2 = block_sum(bb, sh);
-    if (threadIdx.x == 0) { part[2 * blockIdx.x] = t1; part[2 * blockIdx.x + 1] = t2; }
+    if (threadIdx.x == 0) { part[2 * lb] = t1; part[2 * lb + 1] = t2; }
 }
 
 // final sums; decides the outer convergence and the inner target
 __global__ __launch_bounds__(256) void k_reduce_resid(const double* part, DevScalars* s, const DevCounters* ctr,
-                                                      double tol, int fp64) {
+                                                      double tol, int fp64, int dev, double inner_tol, int max_outer) {
     __shared__ double a[kRedBlocks], b[kRedBlocks];
+    if (s->outer_done) return;
     for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) { a[i] = part[2 * i]; b[i] = part[2 * i + 1]; }
     __syncthreads();
     for (int o = kRedBlocks / 2; o > 0; o >>= 1) {
@@ -473,12 +499,34 @@ __global__ __launch_bounds__(256) void k_reduce_resid(const double* part, DevSca
         // FP32 on the normalised residual -> set by the caller
         s->target = fp64 ? 0.25 * tol * tol * bb : s->target;
         s->cap_err = ctr->err;
+        if (dev) {
+            // the solve ends here, or the next FP32 pass reduces its residual
+            // by inner_tol, or by no more than the tolerance still needs
+            // (with a factor 2 margin)
+            const double rel = s->relres;
+            if (s->nonfinite || rel <= tol || s->outer >= max_outer) {
+                s->outer_done = 1;
+            } else {
+                const double want = fmax(inner_tol, 0.5 * tol / rel);
+                s->target = want * want;
+            }
+            s->outer += 1;
+        }
     }
+}
+
+// start and end of a field solve: no pass is finished and none counted yet
+__global__ void k_begin_solve(DevScalars* s) {
+    s->outer_done = 0;
+    s->outer = 0;
+    s->iters_total = 0;
+    for (int k = 0; k < 4; ++k) s->its_pass[k] = 0;
 }
 
 // ------------------------------------------------------ Krylov kernels (T)
 template <typename T>
 __global__ __launch_bounds__(256) void k_scale_to(const double* r64, T* r, T* x, const DevScalars* s, int nn) {
+    if (s->outer_done) return;
     const double sc = s->scale;
     for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += gridDim.x * blockDim.x) {
         r[n] = (T)(r64[n] * sc);
@@ -592,7 +640,8 @@ __global__ __launch_bounds__(256) void k_reduce(const double* part, DevScalars* 
     }
 }
 
-__global__ void k_begin_cg(DevScalars* s) { s->done = 0; s->iters = 0; s->fallback = 0; }
+// (a Krylov solve of a finished refinement starts as done)
+__global__ void k_begin_cg(DevScalars* s) { s->done = s->outer_done; s->iters = 0; s->fallback = 0; }
 
 // flexible CG: z.r and z.q of the new preconditioned residual in one pass
 __global__ __launch_bounds__(256) void k_dot2(const float* z, const float* r, const float* q, double* part,
@@ -1019,16 +1068,6 @@ __global__ __launch_bounds__(1024) void k_tail_lds(TailArgs<T> a, TailLds o) {
 // res0/res9, restrict, prolong).  Off-grid, conductor and inactive nodes
 // hold zero in LDS, and so do the face coefficients of faces that do not
 // exist, so the sums need no bounds tests (a zero term changes no sum).
-// Tile of a block in the tiled multigrid and Krylov kernels.  The hardware
-// deals consecutive blocks round-robin to the eight XCDs, each with its own
-// L2; tile rows are handed to the XCDs in contiguous runs instead, so that
-// the halo lines a tile shares with its neighbours are fetched into one L2.
-// (A bijection of 0 .. n-1: XCD x takes n/8 tiles, one more if x < n % 8.)
-__device__ __forceinline__ int xcd_tile(int b, int n) {
-    const int q = n >> 3, r = n & 7, x = b & 7;
-    return x * q + min(x, r) + (b >> 3);
-}
-
 template <typename T>
 struct MgArgs {
     Sten S;                      // levels >= 1
@@ -1852,7 +1891,7 @@ static bool capture_graph(pic_handle* h, hipGraphExec_t* out, F&& body) {
 // the V-cycle leaves unused.  Returns the iteration count.
 template <typename T>
 static int pcg_mg(pic_handle* h, T* r, T* x, T* z, T* p, T* q, int max_iter, int* err, int first_check,
-                  bool x_zero) {
+                  bool x_zero, bool host_check = true) {
     using V = VecSet<T>;
     hipStream_t st = h->stream;
     const int nn = h->nn;
@@ -1922,12 +1961,14 @@ static int pcg_mg(pic_handle* h, T* r, T* x, T* z, T* p, T* q, int max_iter, int
         // the host reads the convergence flag first after first_check
         // iterations (what the same solve needed last time), then after
         // every iteration: iterations launched after convergence return at
-        // once but still cost their launches
-        if (it + 1 >= first_check || it + 1 == max_iter) {
+        // once but still cost their launches.  Without host checks the
+        // max_iter iterations are launched and the device stops itself.
+        if (host_check && (it + 1 >= first_check || it + 1 == max_iter)) {
             if (!read_scalars(h)) { *err = PIC_E_HIP; return it; }
             if (h->h_sc->done) break;
         }
     }
+    if (!host_check) return 0;
     if (it == 0 && !read_scalars(h)) { *err = PIC_E_HIP; return it; }
     if (h->h_sc->nonfinite) *err = PIC_E_NONFINITE;
     return h->h_sc->iters;
@@ -1937,8 +1978,8 @@ static int pcg_mg(pic_handle* h, T* r, T* x, T* z, T* p, T* q, int max_iter, int
 // reduction (the identity preconditioner: plain CG)
 template <typename T>
 static int pcg(pic_handle* h, T* r, T* x, T* z, T* p, T* q, int max_iter, int* err, int ident = 0,
-               int first_check = kCheckEvery, bool x_zero = false) {
-    if (!ident) return pcg_mg<T>(h, r, x, z, p, q, max_iter, err, first_check, x_zero);
+               int first_check = kCheckEvery, bool x_zero = false, bool host_check = true) {
+    if (!ident) return pcg_mg<T>(h, r, x, z, p, q, max_iter, err, first_check, x_zero, host_check);
     using V = VecSet<T>;
     hipStream_t st = h->stream;
     const int nn = h->nn;
@@ -2106,9 +2147,15 @@ static int fpcg(pic_handle* h, float* r, float* x, float* z, float* p, float* q,
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_add_phi(double* phi, const T* x, const int8_t* nk, const DevScalars* s,
-                                                 int nn, int scaled) {
+__global__ __launch_bounds__(256) void k_add_phi(double* phi, const T* x, const int8_t* nk, DevScalars* s, int nn,
+                                                 int scaled) {
     // FP32 inner: x solves (K/eps0) x = r / ||r||, so K^-1 r = x ||r|| / eps0
+    if (s->outer_done) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        // the pass's Krylov iterations
+        s->its_pass[min(max(s->outer - 1, 0), 3)] = s->iters;
+        s->iters_total += s->iters;
+    }
     const double f = scaled ? (1.0 / s->scale) / kEps0 : 1.0;
     for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += gridDim.x * blockDim.x)
         if (nk[n] < 0) phi[n] += f * (double)x[n];
@@ -2136,7 +2183,10 @@ void launch_extrapolate(pic_handle* h) {
     h->have_prev = std::min(h->have_prev + 1, 2);
 }
 
-__global__ __launch_bounds__(256) void k_set_dirichlet(double* phi, const int8_t* nk, const double* Up, int nn) {
+__global__ __launch_bounds__(256) void k_set_dirichlet(double* phi, const int8_t* nk, const double* Up, int nn,
+                                                       DevScalars* s) {
+    // (the solve is over: later Krylov solves start unfinished)
+    if (blockIdx.x == 0 && threadIdx.x == 0) s->outer_done = 0;
     for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += gridDim.x * blockDim.x)
         if (nk[n] >= 0) phi[n] = nk[n] >= 1 ? Up[nk[n] - 1] : 0.0;
 }
@@ -2153,18 +2203,47 @@ int field_solve(pic_handle* h, double* phi, const double* Q, const double* Up, d
     if (harvest) method = PIC_SOLVE_MGPCG_FP64;
     const int fp64 = (method == PIC_SOLVE_MGPCG_FP64);
     const int max_outer = fp64 ? 4 : 30;
+    const double inner_tol = h->cfg.solver.inner_tol > 0 ? h->cfg.solver.inner_tol : 1e-4;
+    // FP32 multigrid refinement runs with its control on the device: each
+    // residual reduction ends the solve or sets the next pass's target, and
+    // every launch after the end returns at once.  The host launches, ahead
+    // of its first read, the passes the last solve needed, each with the
+    // Krylov iterations that pass took then (a pass cut short leaves more to
+    // the next), and continues pass by pass (reading after each) only if the
+    // solve is not finished.
+    const bool dev = method == PIC_SOLVE_IR_MG;
     int harvested = 0;
     int total = 0, outer = 0, err = 0;
     double rel = 0.0;
-    for (;; ++outer) {
+    hipLaunchKernelGGL(k_begin_solve, dim3(1), dim3(1), 0, st, h->sc);
+    auto residual = [&]() {
         hipLaunchKernelGGL(k_resid64, dim3(kRedBlocks), dim3(256), 0, st, (const double*)h->ar, (const double*)h->az,
-                           (const int8_t*)h->node_kind, Q, (const double*)phi, Up, h->r64, h->part, h->nr, h->nz);
+                           (const int8_t*)h->node_kind, Q, (const double*)phi, Up, h->r64, h->part, h->nr, h->nz,
+                           (const DevScalars*)h->sc);
         hipLaunchKernelGGL(k_reduce_resid, dim3(1), dim3(256), 0, st, (const double*)h->part, h->sc,
-                           (const DevCounters*)h->ctr, tol, fp64);
+                           (const DevCounters*)h->ctr, tol, fp64, dev ? 1 : 0, inner_tol, max_outer);
+    };
+    // one FP32 pass of refinement: scaled residual, inner solve, update
+    auto pass32 = [&](int max_iter, int first_check, bool host_check) {
+        hipLaunchKernelGGL(k_scale_to<float>, grid_for(nn), dim3(256), 0, st, (const double*)h->r64, h->r32, h->x32,
+                           (const DevScalars*)h->sc, nn);
+        const int its = pcg<float>(h, h->r32, h->x32, h->z32, h->p32, h->q32, max_iter, &err,
+                                   method == PIC_SOLVE_IR_CG ? 1 : 0, first_check, true, host_check);
+        hipLaunchKernelGGL(k_add_phi<float>, grid_for(nn), dim3(256), 0, st, phi, (const float*)h->x32,
+                           (const int8_t*)h->node_kind, h->sc, nn, 1);
+        return its;
+    };
+    const int spec = dev ? h->ir_passes : 0;
+    for (int k = 0; k < spec; ++k) {
+        residual();
+        pass32(std::min(h->cfg.solver.max_iter, h->cg_guess[0][std::min(k, 3)]), 0, false);
+    }
+    for (outer = spec;; ++outer) {
+        residual();
         if (!read_scalars(h)) return PIC_E_HIP;
         rel = h->h_sc->relres;
         if (h->h_sc->nonfinite) { err = PIC_E_NONFINITE; break; }
-        if (rel <= tol || outer >= max_outer) break;
+        if (dev ? h->h_sc->outer_done != 0 : (rel <= tol || outer >= max_outer)) break;
         if (fp64) {
             h->harvesting = harvest && outer == 0;
             h->harvest_limit = std::min(unet::kHarvestPerSolve, h->net.cap_pairs);
@@ -2183,17 +2262,19 @@ int field_solve(pic_handle* h, double* phi, const double* Q, const double* Up, d
             }
             h->harvesting = false;
             hipLaunchKernelGGL(k_add_phi<double>, grid_for(nn), dim3(256), 0, st, phi, (const double*)h->x64,
-                               (const int8_t*)h->node_kind, (const DevScalars*)h->sc, nn, 0);
+                               (const int8_t*)h->node_kind, h->sc, nn, 0);
+        } else if (dev) {
+            // (the reduction has set the target)
+            pass32(h->cfg.solver.max_iter, h->cg_guess[0][std::min(outer, 3)], true);
         } else {
             // the inner solve reduces its residual by inner_tol, or by no more
             // than the outer tolerance still needs (with a factor 2 margin)
-            const double it = h->cfg.solver.inner_tol > 0 ? h->cfg.solver.inner_tol : 1e-4;
-            const double want = std::max(it, 0.5 * tol / rel);
+            const double want = std::max(inner_tol, 0.5 * tol / rel);
             hipLaunchKernelGGL(k_set_target, dim3(1), dim3(1), 0, st, h->sc, want * want);
-            hipLaunchKernelGGL(k_scale_to<float>, grid_for(nn), dim3(256), 0, st, (const double*)h->r64, h->r32,
-                               h->x32, (const DevScalars*)h->sc, nn);
             if (method == PIC_SOLVE_IR_UNET && h->unet_off) method = PIC_SOLVE_IR_MG;
             if (method == PIC_SOLVE_IR_UNET) {
+                hipLaunchKernelGGL(k_scale_to<float>, grid_for(nn), dim3(256), 0, st, (const double*)h->r64, h->r32,
+                                   h->x32, (const DevScalars*)h->sc, nn);
                 // the network may take at most twice (plus two) the iterations
                 // multigrid needed for this pass last time; a network that
                 // cannot keep up gives the solve back to multigrid, and one
@@ -2210,19 +2291,28 @@ int field_solve(pic_handle* h, double* phi, const double* Q, const double* Up, d
                 } else {
                     h->unet_strikes = 0;
                 }
+                hipLaunchKernelGGL(k_add_phi<float>, grid_for(nn), dim3(256), 0, st, phi, (const float*)h->x32,
+                                   (const int8_t*)h->node_kind, h->sc, nn, 1);
             } else {
                 int& guess = h->cg_guess[0][std::min(outer, 3)];
-                const int its = pcg<float>(h, h->r32, h->x32, h->z32, h->p32, h->q32, h->cfg.solver.max_iter, &err,
-                                           method == PIC_SOLVE_IR_CG ? 1 : 0, guess, true);
+                const int its = pass32(h->cfg.solver.max_iter, guess, true);
                 guess = std::max(1, its);
                 total += its;
             }
-            hipLaunchKernelGGL(k_add_phi<float>, grid_for(nn), dim3(256), 0, st, phi, (const float*)h->x32,
-                               (const int8_t*)h->node_kind, (const DevScalars*)h->sc, nn, 1);
         }
         if (err) break;
     }
-    hipLaunchKernelGGL(k_set_dirichlet, grid_for(nn), dim3(256), 0, st, phi, (const int8_t*)h->node_kind, Up, nn);
+    if (dev) {
+        // what the device did: passes, iterations in all and per pass (the
+        // guesses of the next solve)
+        const DevScalars& hs = *h->h_sc;
+        outer = std::max(hs.outer - 1, 0);
+        total = hs.iters_total;
+        for (int k = 0; k < std::min(outer, 4); ++k) h->cg_guess[0][k] = std::max(1, hs.its_pass[k]);
+        h->ir_passes = err ? 0 : outer;
+    }
+    hipLaunchKernelGGL(k_set_dirichlet, grid_for(nn), dim3(256), 0, st, phi, (const int8_t*)h->node_kind, Up, nn,
+                       h->sc);
     if (harvested > 0 && !err && rel <= tol) h->net.n_pairs += harvested;
     h->solver_outer = outer;
     if (iters_out) *iters_out = total;

@@ -84,6 +84,10 @@ struct DevScalars {
     double last_energy[5];   // ... of the last complete one
     int done, iters, nonfinite, fallback;
     int cap_err;             // DevCounters::err as the last residual reduction saw it
+    // refinement with the control on the device: the solve is finished
+    // (every later launch of it returns at once), the residual reductions
+    // done, the Krylov iterations of each pass and in all
+    int outer_done, outer, its_pass[4], iters_total;
 };
 
 struct Level {
@@ -177,6 +181,7 @@ struct pic_handle {
     int have_last;
     int64_t solver_iters, solver_outer;
     int cg_guess[2][4];           // Krylov iterations of the last solve, per precision and outer pass
+    int ir_passes = 0;            // refinement passes of the last device-controlled solve (0: none yet)
     double solver_relres;
     int sticky_err;
     bool halted;                  // births were dropped: no further steps
