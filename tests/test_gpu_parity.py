@@ -135,6 +135,42 @@ def test_field_solve_matches_oracle(method, size):
     g.close()
 
 
+def test_device_controlled_refinement_continues_and_skips():
+    """FP32 refinement with its control on the device: the host launches,
+    ahead of its one read, the passes (and Krylov iterations) the last solve
+    needed.  A solve that needs more passes (a tighter tolerance) continues
+    pass by pass and reaches it; a solve that needs fewer leaves the extra
+    passes to return at once, which changes no bit of its result.  After it
+    an FP64 solve (host-controlled) starts unfinished and converges."""
+    w = _small_gec(nr=64, nz=128, n=0, cap_e=16, cap_i=16)
+    g = _pic(w, load=False, method=SOLVE_IR_MG)
+    o = O.Oracle(w, load=False)
+    rng = np.random.default_rng(11)
+    chi = rng.uniform(0, 3.0, o.nn)
+    Q = rng.normal(0, 3e-14, o.nn)
+    U = 77.0
+    ref, _, _, _ = o.solve_q(Q, chi, U, tol=1e-12)
+    scale = np.max(np.abs(ref))
+    phi1, it1, rel1, rc1 = g.solve_once(Q, chi, U, tol=1e-8)
+    d1 = g.diag()
+    assert rc1 == 0 and rel1 <= 1e-8
+    phi2, it2, rel2, rc2 = g.solve_once(Q, chi, U, tol=1e-12)
+    d2 = g.diag()
+    print(f"[gpu] passes {d1.solver_outer} -> {d2.solver_outer}, iters {it1} -> {it2}", flush=True)
+    assert rc2 == 0 and rel2 <= 1e-12
+    assert d2.solver_outer > d1.solver_outer
+    assert np.max(np.abs(phi2 - ref)) <= 1e-6 * scale
+    phi3, it3, rel3, rc3 = g.solve_once(Q, chi, U, tol=1e-8)
+    d3 = g.diag()
+    assert rc3 == 0 and d3.solver_outer == d1.solver_outer and it3 == it1 and rel3 == rel1
+    assert np.array_equal(phi3, phi1)
+    g.set_solver(method=SOLVE_MGPCG_FP64)
+    phi4, it4, rel4, rc4 = g.solve_once(Q, chi, U, tol=1e-12)
+    assert rc4 == 0 and rel4 <= 1e-12 and it4 > 0
+    assert np.max(np.abs(phi4 - ref)) <= 1e-6 * scale
+    g.close()
+
+
 def test_graph_replay_matches_eager_launches():
     """The fused CG's iterations replayed from HIP graphs (captured once per
     handle) give the same bits as the same kernels launched one by one: a
