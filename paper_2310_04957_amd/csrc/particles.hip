@@ -132,12 +132,21 @@ __device__ __forceinline__ void store8(const Species& f, uint32_t p, const P9& s
 // slot p of this step: in place, or through the permutation of a deferred
 // sort.  Unconditional (no branch, so the loads stay where they are
 // issued): a slot beyond the last, n - 1, is read in its place and the
-// caller ignores it.  Needs n >= 1.
+// caller ignores it.  Needs n >= 1.  In place the state is read once, in
+// order, so it streams past the caches (non-temporal), leaving them to the
+// grids; through a permutation the lines of the old order are picked
+// several times and stay cached.
 template <bool kMoved>
 __device__ __forceinline__ P9 load_slot(const Species& f, const Species& src, const uint32_t* perm, long long p,
                                         long long n) {
     const uint32_t q = (uint32_t)(p < n ? p : n - 1);
-    return kMoved ? load9(src, perm[q]) : load9(f, q);
+    if (kMoved) return load9(src, perm[q]);
+    const f32x4 x = __builtin_nontemporal_load(&f.a[q]), y = __builtin_nontemporal_load(&f.b[q]);
+    P9 s;
+    s.r = x.x; s.z = x.y; s.vr = x.z; s.vt = x.w;
+    s.vz = y.x; s.ar = y.y; s.at = y.z; s.az = y.w;
+    s.w = __builtin_nontemporal_load(&f.w[q]);
+    return s;
 }
 
 // after a deferred sort the weight moves to the new buffer too
