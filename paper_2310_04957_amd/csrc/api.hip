@@ -365,6 +365,7 @@ size_t layout(pic_handle* h, char* base) {
         h->idx[b] = c.take<uint32_t>(capmax);
     }
     for (int sp = 0; sp < 2; ++sp) h->perm[sp] = c.take<uint32_t>((size_t)std::max<int64_t>(h->cap[sp], 1));
+    h->keys_ion = c.take<uint32_t>((size_t)std::max<int64_t>(h->cap[1], 1));
     const size_t mch = (size_t)h->max_chunks;
     h->hist = c.take<uint32_t>(256 * mch);
     h->bsum = c.take<uint32_t>((256 * mch + 4095) / 4096 + 1);
@@ -789,13 +790,15 @@ int pic_step(pic_handle* h, int32_t nsteps) {
         ev_record(h, 4, &b0);
         h->dep_cur = 1 - h->dep_cur;
         ev_record(h, -1, &b1);
-        // electrons write their sort keys when a sort ends this step (the
-        // key buffer is shared, so ions keep the key pass)
+        // a species writes its sort keys in the particle step that its sort
+        // ends (the ions into a key buffer of their own: the electrons' sort
+        // runs first and uses the shared ones)
         const bool se_next = c.run.sort_every > 0 && (h->step + 1) % c.run.sort_every == 0;
+        const bool si_next = c.run.sort_every_ion > 0 && (h->step + 1) % c.run.sort_every_ion == 0;
         launch_particles(h, 0, se_next);
         ev_record(h, 0, &b1);
         ev_record(h, -1, &b1);
-        launch_particles(h, 1);
+        launch_particles(h, 1, si_next);
         ev_record(h, 1, &b1);
         ev_record(h, -1, &b2);
         launch_births(h);
@@ -810,7 +813,7 @@ int pic_step(pic_handle* h, int32_t nsteps) {
             if (se && c.run.split) launch_split(h, 0);
             if (se) launch_sort(h, 0, true, true);
             if (si && c.run.split) launch_split(h, 1);
-            if (si) launch_sort(h, 1, true);
+            if (si) launch_sort(h, 1, true, true);
             ev_record(h, 3, &b3);
         }
         if (h->step % spp == 0) {

@@ -447,7 +447,7 @@ void launch_particles(pic_handle* h, int sp, bool emit_keys) {
     a.key0 = (uint32_t)(h->cfg.run.seed & 0xFFFFFFFFu);
     a.key1 = (uint32_t)(h->cfg.run.seed >> 32);
     a.step = (uint32_t)(h->step + 1);
-    a.keys = emit_keys && sp == 0 ? h->keys[0] : nullptr;
+    a.keys = emit_keys ? (sp == 0 ? h->keys[0] : h->keys_ion) : nullptr;
     a.dead_key = (uint32_t)h->ntiles;
     a.ntr = h->ntr;
     const dim3 grid(grid_blocks(h, sp)), block(kPushBlock);
@@ -460,9 +460,13 @@ void launch_particles(pic_handle* h, int sp, bool emit_keys) {
             else hipLaunchKernelGGL((k_particles<24, false, false>), grid, block, 0, h->stream, a);
         }
     } else {
-        // (ions never write keys: the key buffer is shared by the species)
-        if (moved) hipLaunchKernelGGL((k_particles<16, true, false>), grid, block, 0, h->stream, a);
-        else hipLaunchKernelGGL((k_particles<16, false, false>), grid, block, 0, h->stream, a);
+        if (emit_keys) {
+            if (moved) hipLaunchKernelGGL((k_particles<16, true, true>), grid, block, 0, h->stream, a);
+            else hipLaunchKernelGGL((k_particles<16, false, true>), grid, block, 0, h->stream, a);
+        } else {
+            if (moved) hipLaunchKernelGGL((k_particles<16, true, false>), grid, block, 0, h->stream, a);
+            else hipLaunchKernelGGL((k_particles<16, false, false>), grid, block, 0, h->stream, a);
+        }
     }
     if (moved) {
         h->cur[sp] = 1 - h->cur[sp];

@@ -124,6 +124,7 @@ struct pic_handle {
     pic::Species buf[2][2];
     int cur[2];
     uint32_t *keys[2], *idx[2];
+    uint32_t* keys_ion;       // the ions' sort keys, written by the ion step before their sort
     uint32_t* perm[2];        // per species: the permutation of the last sort
     bool pending[2];          // a sort whose particle movement is still to be applied
     uint32_t* hist;

@@ -3,10 +3,10 @@
 // sort on 8-bit digits: per-chunk digit histograms, one exclusive scan in
 // digit-major order, and a stable scatter whose in-chunk ranks come from
 // wavefront ballots (no atomics decide an order, so the permutation is
-// deterministic).  The nine particle arrays are then gathered into the
-// second buffer.  Electron keys usually come from the particle step just
-// before (it locates every particle anyway); the key pass then covers only
-// the slots appended after it.
+// deterministic).  The particle arrays are then gathered through the
+// permutation, usually by the next particle step.  The keys usually come
+// from the species' particle step just before (it locates every particle
+// anyway); the key pass then covers only the slots appended after it.
 #include <hip/hip_runtime.h>
 
 #include "pic_internal.h"
@@ -321,7 +321,10 @@ void launch_sort(pic_handle* h, int sp, bool deferred, bool keyed) {
     ka.g.invd = h->invd; ka.g.cell_kind = h->cell_kind; ka.g.node_kind = h->node_kind;
     for (int k = 0; k < 3; ++k) ka.g.edge_bc[k] = h->cfg.geom.edge_bc[k];
     ka.rz = S.a;
-    ka.keys = h->keys[0];
+    // the species' keys: the electrons' in the first shared buffer, the ions'
+    // in their own (the radix passes then ping-pong with the second shared one)
+    uint32_t* kb[2] = {sp == 0 ? h->keys[0] : h->keys_ion, h->keys[1]};
+    ka.keys = kb[0];
     ka.n_slots = ns; ka.dead = dead + sp; ka.sp = sp; ka.ntr = h->ntr;
     ka.start = keyed ? (const long long*)&h->ctr->n_keyed[sp] : nullptr;
     ka.dead_key = (uint32_t)h->ntiles;   // one bucket past the last tile: sorts last
@@ -330,12 +333,12 @@ void launch_sort(pic_handle* h, int sp, bool deferred, bool keyed) {
     for (int shift = 0; shift < h->key_bits; shift += 8) {
         // the last pass writes the permutation to the species' own buffer
         const bool last = shift + 8 >= h->key_bits;
-        hipLaunchKernelGGL(k_hist, dim3(2048), dim3(kBlock), 0, st, h->keys[src], ns, sp, shift, h->hist);
+        hipLaunchKernelGGL(k_hist, dim3(2048), dim3(kBlock), 0, st, kb[src], ns, sp, shift, h->hist);
         hipLaunchKernelGGL(k_scan_reduce, dim3(2048), dim3(kBlock), 0, st, h->hist, ns, sp, h->bsum);
         hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, h->bsum, ns, sp);
         hipLaunchKernelGGL(k_scan_down, dim3(2048), dim3(kBlock), 0, st, h->hist, h->bsum, ns, sp);
-        hipLaunchKernelGGL(k_scatter, dim3(2048), dim3(kBlock), 0, st, h->keys[src], shift == 0 ? nullptr : h->idx[src],
-                           last ? nullptr : h->keys[1 - src],
+        hipLaunchKernelGGL(k_scatter, dim3(2048), dim3(kBlock), 0, st, kb[src], shift == 0 ? nullptr : h->idx[src],
+                           last ? nullptr : kb[1 - src],
                            last ? h->perm[sp] : h->idx[1 - src], h->hist, ns, sp, shift);
         src = 1 - src;
     }
