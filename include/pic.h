@@ -73,7 +73,7 @@ typedef struct {
 } pic_region;
 
 typedef struct {
-    int32_t nr, nz;             /* cells; both even, 4 <= n <= 4096 */
+    int32_t nr, nz;             /* cells; both even, 4 <= n <= 4096, at most 65535 tiles of 16 x 16 cells */
     double R, Z;                /* domain [0,R] x [0,Z], metres; r = 0 is the axis */
     int32_t n_regions;
     int32_t edge_bc[3];         /* r=R, z=0, z=Z edges: conductor id or PIC_NEUMANN */

@@ -58,6 +58,8 @@ int validate(const pic_config* c) {
     if (!c || c->abi_version != PIC_ABI_VERSION) return PIC_E_CONFIG;
     const pic_geometry& g = c->geom;
     if (g.nr < 4 || g.nz < 4 || (g.nr & 1) || (g.nz & 1) || g.nr > 4096 || g.nz > 4096) return PIC_E_CONFIG;
+    // 16-bit sort keys: the tiles and the dead key after them
+    if (((g.nr + kTile - 1) / kTile) * ((g.nz + kTile - 1) / kTile) > 65535) return PIC_E_CONFIG;
     if (!(g.R > 0) || !(g.Z > 0) || g.n_regions < 0 || g.n_regions > PIC_MAX_REGIONS) return PIC_E_CONFIG;
     if (c->n_el < 0 || c->n_el > PIC_MAX_ELECTRODES) return PIC_E_CONFIG;
     const int n_el = c->n_el > 0 ? c->n_el : 1;
@@ -361,11 +363,11 @@ size_t layout(pic_handle* h, char* base) {
             h->buf[sp][b].w = c.take<float>(cs);
         }
     for (int b = 0; b < 2; ++b) {
-        h->keys[b] = c.take<uint32_t>(capmax);
+        h->keys[b] = c.take<tkey_t>(capmax);
         h->idx[b] = c.take<uint32_t>(capmax);
     }
     for (int sp = 0; sp < 2; ++sp) h->perm[sp] = c.take<uint32_t>((size_t)std::max<int64_t>(h->cap[sp], 1));
-    h->keys_ion = c.take<uint32_t>((size_t)std::max<int64_t>(h->cap[1], 1));
+    h->keys_ion = c.take<tkey_t>((size_t)std::max<int64_t>(h->cap[1], 1));
     const size_t mch = (size_t)h->max_chunks;
     h->hist = c.take<uint32_t>(256 * mch);
     h->bsum = c.take<uint32_t>((256 * mch + 4095) / 4096 + 1);

@@ -23,7 +23,7 @@ struct PushArgs {
     Species f;                   // particles written here (read here too unless perm is set)
     Species src;                 // with perm: slot p reads src at perm[p] (a deferred sort)
     const uint32_t* perm;
-    uint32_t* keys;              // non-null: write each slot's sort key (a sort follows this step)
+    tkey_t* keys;                // non-null: write each slot's sort key (a sort follows this step)
     uint32_t dead_key;
     int ntr;
     const float2* E;
@@ -349,7 +349,7 @@ __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4)))
             // the key of the tile sort that follows: the tile of the predicted
             // position, or the dead key (as the key pass computes it)
             if (kKeys) {
-                if (p < n) a.keys[p] = key;
+                if (p < n) a.keys[p] = (tkey_t)key;
                 ndead += __popcll(__ballot(p < n && key == a.dead_key));
             }
             // births of this round, staged in slot order

@@ -13,6 +13,9 @@
 
 namespace pic {
 
+// tile sort key of a slot: its tile, or the tile count for a dead slot (at
+// most 65535 tiles, checked at init)
+typedef uint16_t tkey_t;
 constexpr int kBlock = 256;           // threads per block for sort and helper kernels
 constexpr int kItems = 16;            // particles per thread per sort chunk
 constexpr int kChunk = kBlock * kItems;
@@ -123,8 +126,9 @@ struct pic_handle {
     // particles: two buffers per species for the sort
     pic::Species buf[2][2];
     int cur[2];
-    uint32_t *keys[2], *idx[2];
-    uint32_t* keys_ion;       // the ions' sort keys, written by the ion step before their sort
+    pic::tkey_t* keys[2];
+    uint32_t* idx[2];
+    pic::tkey_t* keys_ion;    // the ions' sort keys, written by the ion step before their sort
     uint32_t* perm[2];        // per species: the permutation of the last sort
     bool pending[2];          // a sort whose particle movement is still to be applied
     uint32_t* hist;

@@ -18,7 +18,7 @@ constexpr int kSeg = 4096;   // elements per block of the scan kernels
 struct KeyArgs {
     Geo g;
     const f32x4* rz;          // the particles' first vector group (r, z, ...)
-    uint32_t* keys;
+    tkey_t* keys;
     const long long* n_slots;
     const long long* start;   // non-null: keys below *start are already written
     unsigned int* dead;
@@ -39,18 +39,24 @@ __global__ __launch_bounds__(kBlock) void k_keys(KeyArgs a) {
             if (L.inside) key = tile_key(L, a.ntr);
         }
         dead += (key == a.dead_key);
-        a.keys[p] = key;
+        a.keys[p] = (tkey_t)key;
     }
     // wave reduction then one atomic per wave
     for (int o = 32; o > 0; o >>= 1) dead += __shfl_down(dead, o);
     if ((threadIdx.x & 63) == 0 && dead) atomicAdd(a.dead, dead);
 }
 
+// eight 16-bit keys from one 16-byte load
+__device__ __forceinline__ void unpack8(const uint4 v, uint32_t* k) {
+    k[0] = v.x & 0xFFFFu; k[1] = v.x >> 16; k[2] = v.y & 0xFFFFu; k[3] = v.y >> 16;
+    k[4] = v.z & 0xFFFFu; k[5] = v.z >> 16; k[6] = v.w & 0xFFFFu; k[7] = v.w >> 16;
+}
+
 // Digit counts per chunk.  Each thread counts kItems consecutive keys and
 // adds a run of equal digits with one LDS atomic: sorted or nearly sorted
 // keys (the usual case between two sorts) then cost about one atomic per
 // thread instead of one per key on the same few bins.
-__global__ __launch_bounds__(kBlock) void k_hist(const uint32_t* keys, const long long* n_slots, int sp, int shift,
+__global__ __launch_bounds__(kBlock) void k_hist(const tkey_t* keys, const long long* n_slots, int sp, int shift,
                                                  uint32_t* hist) {
     __shared__ unsigned int h[256];
     const long long n = n_slots[sp];
@@ -62,10 +68,7 @@ __global__ __launch_bounds__(kBlock) void k_hist(const uint32_t* keys, const lon
         uint32_t kv[kItems];
         if (p0 + kItems <= n) {
 #pragma unroll
-            for (int q = 0; q < kItems / 4; ++q) {
-                const uint4 v = *reinterpret_cast<const uint4*>(keys + p0 + 4 * q);
-                kv[4 * q] = v.x; kv[4 * q + 1] = v.y; kv[4 * q + 2] = v.z; kv[4 * q + 3] = v.w;
-            }
+            for (int q = 0; q < kItems / 8; ++q) unpack8(*reinterpret_cast<const uint4*>(keys + p0 + 8 * q), kv + 8 * q);
         } else {
 #pragma unroll
             for (int q = 0; q < kItems; ++q) kv[q] = p0 + q < n ? keys[p0 + q] : 0u;
@@ -194,7 +197,7 @@ __device__ __forceinline__ unsigned long long digit_peers(bool valid, uint32_t d
 // (after one block-wide offset computation) placing every element at
 // chunk offset + earlier wavefronts' counts + its rank among equal digits
 // before it.  Ranks come from wavefront ballots, so the order is fixed.
-__global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* kin, const uint32_t* vin, uint32_t* kout,
+__global__ __launch_bounds__(kBlock) void k_scatter(const tkey_t* kin, const uint32_t* vin, tkey_t* kout,
                                                     uint32_t* vout, const uint32_t* offs, const long long* n_slots,
                                                     int sp, int shift) {
     __shared__ unsigned int wcnt[kWaves][256];
@@ -215,10 +218,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* kin, const u
             uint32_t kv[kItems];
             if (p0 + kItems <= n) {
 #pragma unroll
-                for (int q = 0; q < kItems / 4; ++q) {
-                    const uint4 v = *reinterpret_cast<const uint4*>(kin + p0 + 4 * q);
-                    kv[4 * q] = v.x; kv[4 * q + 1] = v.y; kv[4 * q + 2] = v.z; kv[4 * q + 3] = v.w;
-                }
+                for (int q = 0; q < kItems / 8; ++q) unpack8(*reinterpret_cast<const uint4*>(kin + p0 + 8 * q), kv + 8 * q);
             } else {
 #pragma unroll
                 for (int q = 0; q < kItems; ++q) kv[q] = p0 + q < n ? kin[p0 + q] : 0u;
@@ -268,7 +268,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* kin, const u
             const int rank = __popcll(peers & lanemask_lt_s());
             if (valid) {
                 const unsigned int pos = wbase[wave][d] + rank;
-                if (kout != nullptr) kout[pos] = key;   // (the last pass keeps no keys)
+                if (kout != nullptr) kout[pos] = (tkey_t)key;   // (the last pass keeps no keys)
                 vout[pos] = vv[it];
             }
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -323,7 +323,7 @@ void launch_sort(pic_handle* h, int sp, bool deferred, bool keyed) {
     ka.rz = S.a;
     // the species' keys: the electrons' in the first shared buffer, the ions'
     // in their own (the radix passes then ping-pong with the second shared one)
-    uint32_t* kb[2] = {sp == 0 ? h->keys[0] : h->keys_ion, h->keys[1]};
+    tkey_t* kb[2] = {sp == 0 ? h->keys[0] : h->keys_ion, h->keys[1]};
     ka.keys = kb[0];
     ka.n_slots = ns; ka.dead = dead + sp; ka.sp = sp; ka.ntr = h->ntr;
     ka.start = keyed ? (const long long*)&h->ctr->n_keyed[sp] : nullptr;

@@ -50,6 +50,13 @@ def test_workspace_size_and_config_errors(P):
         P.workspace_bytes(bad)
     assert e.value.code == -1
     bad = P.make_config(workload("pp32x24"))
+    bad.geom.nr, bad.geom.nz = 4096, 4096    # 256 x 256 tiles: more than 16-bit tile keys hold
+    with pytest.raises(P.PicError) as e:
+        P.workspace_bytes(bad)
+    assert e.value.code == -1
+    bad.geom.nz = 4064                        # 256 x 254 tiles
+    assert P.workspace_bytes(bad) > 0
+    bad = P.make_config(workload("pp32x24"))
     bad.abi_version = 99
     with pytest.raises(P.PicError):
         P.workspace_bytes(bad)
