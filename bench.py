@@ -402,6 +402,8 @@ def main():
     ap.add_argument("--c4-problem-gap", type=int, default=20)
     ap.add_argument("--c4-steps", type=int, default=40)
     ap.add_argument("--c4-save", default="")
+    ap.add_argument("--unet-forwards", type=int, default=0,
+                    help="only run this many U-net forwards (batch 1, no particles) on the workload's node image")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain FP32 copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -414,6 +416,29 @@ def main():
             torch.add(src, 0.0, out=dst)
         torch.cuda.synchronize()
         print(json.dumps({"calibration": "copy", "bytes_read": 4 * n, "bytes_written": 4 * n, "launches": 3}))
+        return
+    if args.unet_forwards:
+        # the learned preconditioner's forward pass alone, for the kernel
+        # trace and counters of its convolutions at full resolution
+        import numpy as np
+        import torch
+        from paper_2310_04957_amd.pic import Pic
+        from pic_inputs import workload
+        from pic_inputs.workloads import SOLVE_IR_MG
+        w = workload(args.workload, run={"n_e": 0, "n_i": 0, "cap_e": 16, "cap_i": 16})
+        g = Pic(w, load=False, method=SOLVE_IR_MG, unet_batch=1, unet_pairs=0)
+        nr, nz = w["geometry"]["nr"], w["geometry"]["nz"]
+        x = np.random.default_rng(1).normal(size=(1, nz, nr, 3)).astype(np.float32)
+        g.unet_forward(x)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.unet_forwards):
+            out = g.unet_forward(x)
+        wall = time.perf_counter() - t0
+        g.close()
+        print(json.dumps({"unet_forwards": args.unet_forwards, "image": [nz, nr],
+                          "ms_per_forward_with_copies": 1e3 * wall / args.unet_forwards,
+                          "mean_abs_out": float(np.abs(out).mean())}))
         return
     if args.c4:
         print(json.dumps({"c4": c4_protocol(args)}))

@@ -12,6 +12,7 @@ namespace pic {
 namespace unet {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));   // 8 bf16 moved as raw bits
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 __device__ __forceinline__ float bf2f(bf16 v) {
@@ -67,24 +68,34 @@ __device__ __forceinline__ void make_plan(int tid, LoadPlan<CIN>& lp) {
     }
 }
 
-// chunk ch of the halo tile at (b, y0 - 1, x0 - 1) into registers
+// keep each of the eight bf16 in t whose mask value in m is > 0 (the mask is
+// a ReLU output: never NaN)
+__device__ __forceinline__ void relu_mask(u32x4& t, const u32x4 m) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const unsigned lo = (m[k] << 16), hi = (m[k] & 0xffff0000u);
+        const unsigned keep = (__uint_as_float(lo) > 0.0f ? 0x0000ffffu : 0u) |
+                              (__uint_as_float(hi) > 0.0f ? 0xffff0000u : 0u);
+        t[k] &= keep;
+    }
+}
+
+// chunk ch of the halo tile at (b, y0 - 1, x0 - 1) into registers, as raw
+// bits (a bf16 vector type here costs a repacking per element on the way
+// to LDS)
 template <int CIN, bool MASK>
 __device__ __forceinline__ void load_chunk(const bf16* __restrict__ X, const bf16* __restrict__ M,
                                            const LoadPlan<CIN>& lp, int b, int y0, int x0, int ch, int H, int W,
-                                           bf16x8* v) {
+                                           u32x4* v) {
     using S = Stage<CIN>;
 #pragma unroll
     for (int q = 0; q < S::Q; ++q) {
         const int yy = y0 - 1 + lp.py[q], xx = x0 - 1 + lp.px[q];
-        bf16x8 t = {};
+        u32x4 t = {0u, 0u, 0u, 0u};
         if (yy >= 0 && yy < H && xx >= 0 && xx < W) {
             const size_t g = (((size_t)b * H + yy) * W + xx) * CIN + ch * S::CH + lp.c8[q] * 8;
-            t = *(const bf16x8*)&X[g];
-            if (MASK) {
-                const bf16x8 m = *(const bf16x8*)&M[g];
-                for (int k = 0; k < 8; ++k)
-                    if (!(bf2f(m[k]) > 0.0f)) t[k] = f2raw(0.0f);
-            }
+            t = *(const u32x4*)&X[g];
+            if (MASK) relu_mask(t, *(const u32x4*)&M[g]);
         }
         v[q] = t;
     }
@@ -104,22 +115,37 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16* __restrict__ X, con
     // weights once per block
     for (int e = tid; e < 9 * COUT * (CIN / 8); e += 256) {
         const int c8 = e % (CIN / 8), tn = e / (CIN / 8);
-        *(bf16x8*)&ws[tn * CW + c8 * 8] = *(const bf16x8*)&Wt[(size_t)tn * CIN + c8 * 8];
+        *(u32x4*)&ws[tn * CW + c8 * 8] = *(const u32x4*)&Wt[(size_t)tn * CIN + c8 * 8];
     }
     LoadPlan<CIN> lp;
     make_plan<CIN>(tid, lp);
+    const int kh = (lane >> 5) * 8;      // this lane's 8 channels of a 16-wide k step
+    const int m = lane & 31;             // this lane's pixel row of the A tile / output channel of B
+    // this lane's bias values, once per launch (a load inside the epilogue
+    // makes every store there wait for all earlier memory operations)
+    float bb[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) bb[nt] = bias ? bias[nt * 32 + m] : 0.0f;
     const int tx = (W + 15) / 16, ty = (H + 15) / 16;
     // tile indices fit in 32 bits (images of at most 2^31 16x16 tiles)
     const unsigned txy = (unsigned)(tx * ty), utx = (unsigned)tx, nti = (unsigned)((long long)tx * ty * B);
-    bf16x8 next[S::Q];
+    u32x4 next[S::Q];
+    // the staged chunk in registers into LDS, between barriers (every
+    // wavefront's MFMAs are done with the previous chunk)
+    auto stage = [&]() {
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < S::Q; ++q)
+            if (lp.py[q] >= 0) *(u32x4*)&xs[(lp.py[q] * 18 + lp.px[q]) * CP + lp.c8[q] * 8] = next[q];
+        __syncthreads();
+    };
     if (blockIdx.x < nti) {
         const unsigned tile = blockIdx.x;
         const int b = (int)(tile / txy);
         const unsigned rem = tile % txy;
         load_chunk<CIN, MASK>(X, M, lp, b, (int)(rem / utx) * 16, (int)(rem % utx) * 16, 0, H, W, next);
+        stage();
     }
-    const int kh = (lane >> 5) * 8;      // this lane's 8 channels of a 16-wide k step
-    const int m = lane & 31;             // this lane's pixel row of the A tile / output channel of B
     for (unsigned tile = blockIdx.x; tile < nti; tile += gridDim.x) {
         const int b = (int)(tile / txy);
         const unsigned rem = tile % txy;
@@ -129,11 +155,7 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16* __restrict__ X, con
             for (int nt = 0; nt < NT; ++nt) acc[s][nt] = {};
 #pragma unroll
         for (int ch = 0; ch < S::NCH; ++ch) {
-            __syncthreads();   // the previous chunk's MFMAs are done with xs
-#pragma unroll
-            for (int q = 0; q < S::Q; ++q)
-                if (lp.py[q] >= 0) *(bf16x8*)&xs[(lp.py[q] * 18 + lp.px[q]) * CP + lp.c8[q] * 8] = next[q];
-            __syncthreads();
+            if (ch > 0) stage();   // the first chunk is staged before the loop or the previous epilogue
             // the next chunk of this tile, else the first of the next tile
             if (ch + 1 < S::NCH) {
                 load_chunk<CIN, MASK>(X, M, lp, b, y0, x0, ch + 1, H, W, next);
@@ -177,29 +199,47 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16* __restrict__ X, con
                 __builtin_amdgcn_sched_barrier(0);
             }
         }
+        // the next tile's first chunk goes to LDS before this tile's results
+        // are stored: the wait for its loads then waits for no store
+        if (tile + gridDim.x < nti) stage();
         // D layout: lane holds column n = lane % 32, rows pm = 8(r/4) +
         // 4(lane/32) + r%4, i.e. tile row pm/16 = (r >= 8) and column
         // pm % 16 = 8((r/4) & 1) + 4(lane/32) + r%4.  One base address per
-        // lane and compile-time offsets; bounds are checked only on edge
-        // tiles; bf16 by the hardware's round-to-nearest-even conversion.
+        // lane and compile-time offsets; interior tiles store without any
+        // check (one branch for the whole tile), edge tiles check each
+        // value; bf16 by the hardware's round-to-nearest-even conversion.
         const bool full = y0 + 16 <= H && x0 + 16 <= W;
         const int cx = 4 * (lane >> 5);
-        for (int s = 0; s < 2; ++s) {
-            const int py0 = y0 + wave * 4 + s * 2;
-            unsigned short* const Yb = reinterpret_cast<unsigned short*>(Y) +
-                                       (((size_t)b * H + py0) * W + x0 + cx) * COUT;
-            const size_t row = (size_t)W * COUT;
-            for (int nt = 0; nt < NT; ++nt) {
-                const int n = nt * 32 + (lane & 31);
-                const float bb = bias ? bias[n] : 0.0f;
+        const size_t row = (size_t)W * COUT;
+        auto out = [&](int s, int nt, int r) {
+            float v = acc[s][nt][r] + bb[nt];
+            if (RELU) v = fmaxf(v, 0.0f);
+            return __builtin_bit_cast(unsigned short, (__bf16)v);
+        };
+        if (full) {
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int dy = r >= 8 ? 1 : 0, dx = 8 * ((r / 4) & 1) + (r % 4);
-                    float v = acc[s][nt][r] + bb;
-                    if (RELU) v = fmaxf(v, 0.0f);
-                    const unsigned short hv = __builtin_bit_cast(unsigned short, (__bf16)v);
-                    if (full || (py0 + dy < H && x0 + cx + dx < W)) Yb[dy * row + dx * COUT + n] = hv;
-                }
+            for (int s = 0; s < 2; ++s) {
+                unsigned short* const Yb = reinterpret_cast<unsigned short*>(Y) +
+                                           (((size_t)b * H + y0 + wave * 4 + s * 2) * W + x0 + cx) * COUT + m;
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const int dy = r >= 8 ? 1 : 0, dx = 8 * ((r / 4) & 1) + (r % 4);
+                        Yb[dy * row + dx * COUT + nt * 32] = out(s, nt, r);
+                    }
+            }
+        } else {
+            for (int s = 0; s < 2; ++s) {
+                const int py0 = y0 + wave * 4 + s * 2;
+                unsigned short* const Yb = reinterpret_cast<unsigned short*>(Y) +
+                                           (((size_t)b * H + py0) * W + x0 + cx) * COUT + m;
+                for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const int dy = r >= 8 ? 1 : 0, dx = 8 * ((r / 4) & 1) + (r % 4);
+                        if (py0 + dy < H && x0 + cx + dx < W) Yb[dy * row + dx * COUT + nt * 32] = out(s, nt, r);
+                    }
             }
         }
     }
