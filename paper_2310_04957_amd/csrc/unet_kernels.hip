@@ -247,105 +247,187 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16* __restrict__ X, con
 
 // ------------------------------------------------------- weight gradient
 // dW[t][n][c] = sum_p Dm[p][n] * Xpad[p + off_t][c] and db[n] = sum_p Dm[p][n],
-// Dm = D * (Yout > 0).  GEMM with M = 32 output channels, N = CIN input
-// channels, K = pixels; wavefront w owns taps w, w+4, w+8.  Each block
-// accumulates over its tiles and writes one partial (reduced later in a
-// fixed order).
+// Dm = D * (Yout > 0).  Per 16x16 tile and tap a GEMM with M = 32 output
+// channels, N = the input channels (padded to whole 32-channel tiles) and
+// K = the tile's 256 pixels.  Dm and the halo tile of X are staged
+// transposed in LDS (channel-major, two pixels per 32-bit word); the halo
+// rows are padded to 24 pixels, so that for one tile row and one tap row dy
+// a 16-byte and a 4-byte read give the B fragments of all three dx (dx = 1
+// by a 16-bit funnel shift).  Wavefront w takes all nine taps over the tile
+// rows w, w + 4, ... (with 64 input channels: channel tile w & 1 over the
+// rows w/2, w/2 + 2, ...).  At the end the wavefronts' sums are added in LDS
+// in a fixed order and each block writes one partial, reduced later in a
+// fixed order.
+__device__ __forceinline__ float bf_lo(unsigned w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf_hi(unsigned w) { return __uint_as_float(w & 0xffff0000u); }
+__device__ __forceinline__ bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
+
 template <int CIN>
 __global__ __launch_bounds__(256) void k_wgrad(const bf16* __restrict__ X, const bf16* __restrict__ D,
                                                const bf16* __restrict__ Yout, float* __restrict__ part, int B, int H,
                                                int W) {
     constexpr int NT = (CIN + 31) / 32;
     constexpr int CT = NT * 32;            // channels padded to whole N tiles
-    __shared__ __attribute__((aligned(16))) bf16 dT[32 * (256 + 8)];      // [n][pixel]
-    __shared__ __attribute__((aligned(16))) bf16 xT[CT * (18 * 18 + 8)];  // [c][halo pixel]
-    __shared__ float dbs[32];
-    constexpr int DS = 256 + 8, XS = 18 * 18 + 8;
+    constexpr int DS = 256 + 8;            // dT[n][pixel], pixel = 16 row + column
+    constexpr int HR = 24;                 // padded halo row
+    constexpr int XS = 18 * HR + 8;        // xT[c][halo row][halo column]
+    constexpr int RS = 4 / NT;             // tile-row stride of a wavefront
+    constexpr int NX = 18 * 9 * (CT / 8);  // X staging tasks: (halo row, column pair, 8-channel group)
+    constexpr int QX = (NX + 255) / 256;
+    constexpr int kStage = 32 * DS * 2 + CT * XS * 2;
+    constexpr int kRed = 9 * 32 * CT * 4;
+    __shared__ __attribute__((aligned(16))) unsigned char smem[kStage > kRed ? kStage : kRed];
+    __shared__ float dbred[4][16];
+    bf16* const dT = reinterpret_cast<bf16*>(smem);
+    bf16* const xT = dT + 32 * DS;
+    float* const red = reinterpret_cast<float*>(smem);   // after the last tile
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    f32x16 acc[3][NT];
-    for (int k = 0; k < 3; ++k)
-        for (int nt = 0; nt < NT; ++nt) acc[k][nt] = {};
-    float dbacc = 0.0f;
+    const int m = lane & 31, kh = (lane >> 5) * 8;
+    const int nt = NT == 1 ? 0 : (wave & 1);
+    const int row0 = NT == 1 ? wave : (wave >> 1);
+    f32x16 acc[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[t] = {};
+    // this thread's pixel pair (tile row prow, columns pcol, pcol + 1) and
+    // 16 channels of Dm, and its share of db
+    const int pp = tid & 127, dh = tid >> 7;
+    const int prow = pp >> 3, pcol = (pp & 7) * 2;
+    float dbp[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) dbp[j] = 0.0f;
     const int tx = (W + 15) / 16, ty = (H + 15) / 16;
     const long long ntile = (long long)tx * ty * B;
     for (long long tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
         const int b = (int)(tile / (tx * ty));
         const int rem = (int)(tile % (tx * ty));
         const int y0 = (rem / tx) * 16, x0 = (rem % tx) * 16;
-        __syncthreads();
-        {   // masked output gradient, transposed: thread = pixel
-            const int py = y0 + tid / 16, px = x0 + tid % 16;
-            const bool in = py < H && px < W;
-            const size_t g = (((size_t)b * H + py) * W + px) * 32;
-            for (int n = 0; n < 32; ++n) {
-                float v = 0.0f;
-                if (in && bf2f(Yout[g + n]) > 0.0f) v = bf2f(D[g + n]);
-                dT[n * DS + tid] = f2bf(v);
-            }
-        }
-        for (int e = tid; e < 18 * 18; e += 256) {
-            const int yy = y0 - 1 + e / 18, xx = x0 - 1 + e % 18;
-            const bool in = yy >= 0 && yy < H && xx >= 0 && xx < W;
-            const size_t g = (((size_t)b * H + yy) * W + xx) * CIN;
-            for (int c = 0; c < CT; ++c) {
-                bf16 v;
-                v.x = 0;
-                if (in && c < CIN) v = X[g + c];
-                xT[c * XS + e] = v;
-            }
-        }
-        __syncthreads();
-        if (tid < 32) {
-            float s = 0.0f;
-            for (int p = 0; p < 256; ++p) s += bf2f(dT[tid * DS + p]);
-            dbacc += s;
-        }
-        const int kh = (lane >> 5) * 8, m = lane & 31;
+        u32x4 dv[2][2], xv[QX][2];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const int t = wave + 4 * k;
-            if (t <= 8) {
-            const int dy = t / 3, dx = t % 3;
-            for (int k0 = 0; k0 < 256; k0 += 16) {
-                // A[m = n_out][k = pixel], 8 consecutive pixels (same tile row)
-                const bf16x8 afr = *(const bf16x8*)&dT[m * DS + k0 + kh];
-                const int p0 = k0 + kh;                  // first of 8 pixels, all in row p0 / 16
-                const int hy = p0 / 16 + dy, hx = p0 % 16 + dx;
-                for (int nt = 0; nt < NT; ++nt) {
-                    const int c = nt * 32 + m;
-                    bf16x8 bfr;
-                    const bf16* src = &xT[c * XS + hy * 18 + hx];
-                    for (int q = 0; q < 8; ++q) bfr[q] = raw(src[q]);
-                    acc[k][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afr, bfr, acc[k][nt], 0, 0, 0);
+        for (int k = 0; k < 2; ++k) {
+            const int py = y0 + prow, px = x0 + pcol + k;
+            dv[k][0] = dv[k][1] = u32x4{0u, 0u, 0u, 0u};
+            if (py < H && px < W) {
+                const size_t g = (((size_t)b * H + py) * W + px) * 32 + dh * 16;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    dv[k][h] = *(const u32x4*)&D[g + 8 * h];
+                    relu_mask(dv[k][h], *(const u32x4*)&Yout[g + 8 * h]);
                 }
             }
+        }
+#pragma unroll
+        for (int q = 0; q < QX; ++q) {
+            const int e = tid + 256 * q;
+            const int g8 = e % (CT / 8), cp = (e / (CT / 8)) % 9, hy = e / (CT / 8) / 9;
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int yy = y0 - 1 + hy, xx = x0 - 1 + 2 * cp + k;
+                xv[q][k] = u32x4{0u, 0u, 0u, 0u};
+                if (e < NX && g8 * 8 < CIN && yy >= 0 && yy < H && xx >= 0 && xx < W)
+                    xv[q][k] = *(const u32x4*)&X[(((size_t)b * H + yy) * W + xx) * CIN + g8 * 8];
+            }
+        }
+        __syncthreads();   // every wavefront is done with the previous tile's fragments
+        // word (channel, pixel pair): the first pixel in the low half
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const unsigned a = dv[0][h][i], c = dv[1][h][i];
+                const int j = h * 8 + 2 * i, n0 = dh * 16 + j;
+                *(unsigned*)&dT[n0 * DS + prow * 16 + pcol] = (a & 0xffffu) | (c << 16);
+                *(unsigned*)&dT[(n0 + 1) * DS + prow * 16 + pcol] = (a >> 16) | (c & 0xffff0000u);
+                dbp[j] += bf_lo(a) + bf_lo(c);
+                dbp[j + 1] += bf_hi(a) + bf_hi(c);
+            }
+#pragma unroll
+        for (int q = 0; q < QX; ++q) {
+            const int e = tid + 256 * q;
+            if (e < NX) {
+                const int g8 = e % (CT / 8), cp = (e / (CT / 8)) % 9, hy = e / (CT / 8) / 9;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const unsigned a = xv[q][0][i], c = xv[q][1][i];
+                    const int c0 = g8 * 8 + 2 * i;
+                    *(unsigned*)&xT[c0 * XS + hy * HR + 2 * cp] = (a & 0xffffu) | (c << 16);
+                    *(unsigned*)&xT[(c0 + 1) * XS + hy * HR + 2 * cp] = (a >> 16) | (c & 0xffff0000u);
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int r = 0; r < 16 / RS; ++r) {
+            const int ks = row0 + r * RS;   // tile row = k step of 16 pixels
+            const bf16x8 afr = as_bf16x8(*(const u32x4*)&dT[m * DS + ks * 16 + kh]);
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy) {
+                const bf16* src = &xT[(nt * 32 + m) * XS + (ks + dy) * HR + kh];
+                const u32x4 v = *(const u32x4*)src;
+                const unsigned v4 = *(const unsigned*)(src + 8);
+                const u32x4 s1 = {__builtin_amdgcn_alignbit(v[1], v[0], 16), __builtin_amdgcn_alignbit(v[2], v[1], 16),
+                                  __builtin_amdgcn_alignbit(v[3], v[2], 16), __builtin_amdgcn_alignbit(v4, v[3], 16)};
+                const u32x4 s2 = {v[1], v[2], v[3], v4};
+                acc[dy * 3 + 0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afr, as_bf16x8(v), acc[dy * 3 + 0], 0, 0, 0);
+                acc[dy * 3 + 1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afr, as_bf16x8(s1), acc[dy * 3 + 1], 0, 0, 0);
+                acc[dy * 3 + 2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afr, as_bf16x8(s2), acc[dy * 3 + 2], 0, 0, 0);
             }
         }
     }
-    // partial layout per block: [9][32][CIN] weights then [32] bias
-    float* out = part + (size_t)blockIdx.x * (9 * 32 * CIN + 32);
+    // the wavefronts' sums: the buffer cleared, then each wavefront adds its
+    // own, one wavefront at a time in wavefront order (a fixed order; the
+    // LDS atomic takes the accumulators as they are).  D layout: lane holds
+    // input channel nt 32 + lane % 32, output channels 8(r/4) + 4(lane/32) +
+    // r%4
+    __syncthreads();
+    for (int e = tid; e < 9 * 32 * CT; e += 256) red[e] = 0.0f;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const int t = wave + 4 * k;
-        if (t > 8) continue;
+    for (int w = 0; w < 4; ++w) {
+        __syncthreads();
+        if (wave == w) {
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt)
-            for (int r = 0; r < 16; ++r) {
-                const int n = 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
-                const int c = nt * 32 + (lane & 31);
-                if (c < CIN) out[(t * 32 + n) * CIN + c] = acc[k][nt][r];
-            }
+            for (int t = 0; t < 9; ++t)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int n = 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
+                    atomicAdd(&red[(t * 32 + n) * CT + nt * 32 + m], acc[t][r]);
+                }
+        }
     }
-    if (tid < 32) out[9 * 32 * CIN + tid] = dbacc;
+    // db: over the 64 lanes of a wavefront, then the two wavefronts of a
+    // channel half
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        float v = dbp[j];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if (lane == 0) dbred[wave][j] = v;
+    }
+    __syncthreads();
+    // partial layout per block: [9][32][CIN] weights then [32] bias
+    float* const out = part + (size_t)blockIdx.x * (9 * 32 * CIN + 32);
+    for (int e = tid; e < 9 * 32 * CIN; e += 256) out[e] = red[(e / CIN) * CT + e % CIN];
+    if (tid < 32) out[9 * 32 * CIN + tid] = dbred[2 * (tid >> 4)][tid & 15] + dbred[2 * (tid >> 4) + 1][tid & 15];
 }
 
-// sum of per-block partials, fixed order
+// sum of per-block partials in a fixed order: the 8 thread groups of a block
+// add the partials k, k + 8, ... of 32 consecutive elements, then the 8 sums
+// are added in order
 __global__ __launch_bounds__(256) void k_sum_parts(const float* part, int nblk, int len, float* out) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < len; i += gridDim.x * blockDim.x) {
-        float s = 0.0f;
-        for (int b = 0; b < nblk; ++b) s += part[(size_t)b * len + i];
-        out[i] = s;
+    __shared__ float sh[256];
+    const int k = threadIdx.x >> 5, i = blockIdx.x * 32 + (threadIdx.x & 31);
+    float s = 0.0f;
+    if (i < len)
+        for (int b = k; b < nblk; b += 8) s += part[(size_t)b * len + i];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x < 32 && i < len) {
+        float t = 0.0f;
+        for (int j = 0; j < 8; ++j) t += sh[j * 32 + threadIdx.x];
+        out[i] = t;
     }
+}
+
+static void sum_parts(const float* part, int nblk, int len, float* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_sum_parts, dim3((len + 31) / 32), dim3(256), 0, s, part, nblk, len, out);
 }
 
 // ---------------------------------------------- pooling, upsampling, concat
@@ -731,7 +813,7 @@ int conv_wgrad(int cin, const bf16* X, const bf16* D, const bf16* Yout, float* p
     if (cin == 16) hipLaunchKernelGGL((k_wgrad<16>), dim3(nb), dim3(256), 0, s, X, D, Yout, part, B, H, W);
     else if (cin == 32) hipLaunchKernelGGL((k_wgrad<32>), dim3(nb), dim3(256), 0, s, X, D, Yout, part, B, H, W);
     else hipLaunchKernelGGL((k_wgrad<64>), dim3(nb), dim3(256), 0, s, X, D, Yout, part, B, H, W);
-    hipLaunchKernelGGL(k_sum_parts, dim3((len + 255) / 256), dim3(256), 0, s, (const float*)part, nb, len, gw);
+    sum_parts(part, nb, len, gw, s);
     return nb;
 }
 
@@ -756,7 +838,7 @@ void loss_out_bwd(const float* out, const float* target, const float* mask, cons
                   bf16* dlast, float* part, float* sums, int B, int HW, int C, float inv_n, hipStream_t s) {
     hipLaunchKernelGGL(k_loss_out_bwd, dim3(kLossBlocks), dim3(256), 0, s, out, target, mask, last, w, dlast, part, B,
                        HW, inv_n);
-    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, (const float*)part, kLossBlocks, C + 2, sums);
+    sum_parts(part, kLossBlocks, C + 2, sums, s);
 }
 void adam(float* p, const float* g, float* m, float* v, int n, float lr, int t, hipStream_t s) {
     const float b1 = 0.9f, b2 = 0.999f;

@@ -97,8 +97,11 @@ def test_forward_matches_oracle(shape):
     g.close()
 
 
-def test_gradients_match_oracle():
-    nr, nz, B = 32, 64, 2
+# 272 x 512 has 544 tiles of 16 x 16 at full resolution: more than the
+# weight gradient's 512 blocks, so blocks accumulate more than one tile
+@pytest.mark.parametrize("shape", [(32, 64, 2), (272, 512, 1)])
+def test_gradients_match_oracle(shape):
+    nr, nz, B = shape
     g = _pic(_gec(nr, nz), load=False, method=SOLVE_IR_MG, unet_batch=B, unet_pairs=1)
     v = _params(13)
     g.unet_set_params(v)
@@ -127,8 +130,8 @@ def test_gradients_match_oracle():
     for k in ref:
         storage = _rel(ref[k], exact[k])
         err, err_exact = _rel(gg[k], ref[k]), _rel(gg[k], exact[k])
-        print(f"[gpu] grad {k}: vs rounded oracle {err:.2e}, vs FP64 {err_exact:.2e}, storage effect {storage:.2e}",
-              flush=True)
+        print(f"[gpu] grad {k} ({nz}x{nr}): vs rounded oracle {err:.2e}, vs FP64 {err_exact:.2e}, "
+              f"storage effect {storage:.2e}", flush=True)
         # backward through BF16 activations: the storage effect grows with
         # depth (to ~4e-2 at the middle of the network); the accumulation
         # order moves the GPU by at most that much from the rounded oracle
