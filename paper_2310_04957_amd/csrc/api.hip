@@ -368,6 +368,10 @@ size_t layout(pic_handle* h, char* base) {
     }
     for (int sp = 0; sp < 2; ++sp) h->perm[sp] = c.take<uint32_t>((size_t)std::max<int64_t>(h->cap[sp], 1));
     h->keys_ion = c.take<tkey_t>((size_t)std::max<int64_t>(h->cap[1], 1));
+    h->sink.a = c.take<f32x4>(64);
+    h->sink.b = c.take<f32x4>(64);
+    h->sink.w = c.take<float>(64);
+    h->ksink = c.take<tkey_t>(64);
     const size_t mch = (size_t)h->max_chunks;
     h->hist = c.take<uint32_t>(256 * mch);
     h->bsum = c.take<uint32_t>((256 * mch + 4095) / 4096 + 1);

@@ -24,6 +24,8 @@ struct PushArgs {
     Species src;                 // with perm: slot p reads src at perm[p] (a deferred sort)
     const uint32_t* perm;
     tkey_t* keys;                // non-null: write each slot's sort key (a sort follows this step)
+    Species sink;                // 64 slots written by the lanes past the last slot
+    tkey_t* ksink;               // 64 keys likewise
     uint32_t dead_key;
     int ntr;
     const float2* E;
@@ -42,6 +44,15 @@ __device__ __forceinline__ unsigned long long lanemask_lt() {
     return (1ull << (threadIdx.x & 63)) - 1ull;
 }
 
+// The radial factor 2^-2F / (2i + 1) of column i, as the grid's table holds
+// it (a correctly rounded FP64 division, bit for bit the table's value).
+// Computed, not read from the table, on the paths of particles outside the
+// LDS window: a load there would make its wait also wait for the next
+// round's state, which is in flight.
+__device__ __forceinline__ double radial_factor(int i) {
+    return __builtin_ldexp(1.0, -2 * kFBits) / (double)(2 * i + 1);
+}
+
 // Charge of a removed particle: to the conductor it hit, or deposited at the
 // landing point into the dielectric surface-charge grid (the share on
 // conductor nodes goes to that conductor).  Returns true if removed.
@@ -51,7 +62,9 @@ __device__ __forceinline__ bool absorb(const Geo& g, const Loc& L, float w, int 
                                        unsigned long long* s_abs, unsigned long long* wallq, bool vac, int wi0,
                                        int wj0, const uint8_t* s_ck) {
     if (!L.inside) {
-        int bc = g.edge_bc[L.edge];
+        // (a select of the three, not an indexed read of the argument block,
+        // which would be a vector memory load)
+        const int bc = L.edge == 0 ? g.edge_bc[0] : L.edge == 1 ? g.edge_bc[1] : g.edge_bc[2];
         int slot = bc >= 0 ? slot_of(bc) : 2;
         atomicAdd(&s_abs[slot], (unsigned long long)total_share((double)w));
         return true;
@@ -78,7 +91,7 @@ __device__ __forceinline__ bool absorb(const Geo& g, const Loc& L, float w, int 
         return true;
     }
     int64_t c[4];
-    node_shares(L, (double)w, g.invd[L.i], c);
+    node_shares(L, (double)w, radial_factor(L.i), c);
     int n00 = L.j * g.w + L.i;
     int nodes[4] = {n00, n00 + 1, n00 + g.w, n00 + g.w + 1};
 #pragma unroll
@@ -113,7 +126,7 @@ __device__ __forceinline__ unsigned int deposit(const Geo& g, const Loc& L, floa
         atomicAdd(&win[b + kWin + 1], (unsigned long long)c[3]);
         return 0u;
     }
-    node_shares(L, (double)w, g.invd[L.i], c);
+    node_shares(L, (double)w, radial_factor(L.i), c);
     const int n00 = L.j * g.w + L.i;
     atomicAdd(&dep[n00], (unsigned long long)c[0]);
     atomicAdd(&dep[n00 + 1], (unsigned long long)c[1]);
@@ -284,7 +297,24 @@ __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4)))
         uint4 dec4 = make_uint4(0u, 0u, 0u, 0u);
         for (int it = 0; it < kRounds; ++it) {
             const long long p = sbase + (long long)it * 64 + lane;
-            // the next round's state is requested first and pinned here by a
+            P9 s = cur;
+            const bool live = p < n && s.r >= 0.0f;
+            // E at the particle's position: its cell and weights, and for a
+            // cell outside the window the four nodes from the global grid,
+            // requested before the next round's state (waiting for them then
+            // does not wait for that state)
+            const EW ew = e_weights(g, s.r, s.z);
+            const int eli = ew.i - wi0, elj = ew.j - wj0;
+            const bool eout = live && !((unsigned)eli < (unsigned)(kWin - 1) && (unsigned)elj < (unsigned)(kWin - 1));
+            float2 eg[4];
+            if (eout) {
+                const int n00 = ew.j * g.w + ew.i;
+                eg[0] = a.E[n00];
+                eg[1] = a.E[n00 + 1];
+                eg[2] = a.E[n00 + g.w];
+                eg[3] = a.E[n00 + g.w + 1];
+            }
+            // the next round's state is requested here and pinned by a
             // scheduling barrier, so its latency hides behind this round
             const P9 nxt = load_slot<kMoved>(f, a.src, a.perm, it + 1 < kRounds ? p + 64 : p, n);
             __builtin_amdgcn_sched_barrier(0);
@@ -292,25 +322,18 @@ __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4)))
             // a multiple of 256, so the four share one counter)
             if ((it & 3) == 0) dec4 = draw(decision_ctr((uint32_t)p), a.step, kPurposeDecide, a.sp, 0, a.key0, a.key1);
             const uint32_t dword = (it & 3) == 0 ? dec4.x : (it & 3) == 1 ? dec4.y : (it & 3) == 2 ? dec4.z : dec4.w;
-            P9 s = cur;
             bool born = false;
             uint32_t key = a.dead_key;
             float b6[6], br = 0.0f, bz = 0.0f;
-            const bool live = p < n && s.r >= 0.0f;
             if (live) {
                 float Er, Ez;
-                const EW ew = e_weights(g, s.r, s.z);
-                const int eli = ew.i - wi0, elj = ew.j - wj0;
                 {
-                    // read in the window (clamped into it), then replaced
-                    // from the global grid for a cell outside the window
+                    // read in the window (clamped into it), then replaced by
+                    // the global grid's values for a cell outside the window
                     const int b = min(max(elj, 0), kWin - 2) * kWin + min(max(eli, 0), kWin - 2);
                     e_combine(ew, ewin[b], ewin[b + 1], ewin[b + kWin], ewin[b + kWin + 1], Er, Ez);
                 }
-                if (!((unsigned)eli < (unsigned)(kWin - 1) && (unsigned)elj < (unsigned)(kWin - 1))) {
-                    const int n00 = ew.j * g.w + ew.i;
-                    e_combine(ew, a.E[n00], a.E[n00 + 1], a.E[n00 + g.w], a.E[n00 + g.w + 1], Er, Ez);
-                }
+                if (eout) e_combine(ew, eg[0], eg[1], eg[2], eg[3], Er, Ez);
                 d1_correct(s, Er, Ez, a.qm, a.dt);
                 const float cx = s.r * g.inv_dr, cy = s.z * g.inv_dz;
                 bool gone = false;
@@ -343,14 +366,24 @@ __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4)))
                     }
                 }
             }
-            // one store per round for every live slot: the predicted state,
-            // or r = -1 for a removed particle
-            if (live) store_slot(f, (uint32_t)p, s, moved);
-            // the key of the tile sort that follows: the tile of the predicted
-            // position, or the dead key (as the key pass computes it)
-            if (kKeys) {
-                if (p < n) a.keys[p] = (tkey_t)key;
-                ndead += __popcll(__ballot(p < n && key == a.dead_key));
+            // one store per round for every slot: the predicted state, r = -1
+            // for a removed particle, a dead slot's state unchanged; a lane
+            // past the last slot writes the sink.  The stores are issued by
+            // every wavefront in every round, so the compiler counts them
+            // exactly: the wait for the next round's state above then lets
+            // them stay in flight.
+            {
+                const bool in = p < n;
+                const Species& dst = in ? f : a.sink;
+                const uint32_t q = in ? (uint32_t)p : (uint32_t)lane;
+                store_slot(dst, q, s, moved);
+                // the key of the tile sort that follows: the tile of the
+                // predicted position, or the dead key (as the key pass
+                // computes it)
+                if (kKeys) {
+                    (in ? a.keys : a.ksink)[q] = (tkey_t)key;
+                    ndead += __popcll(__ballot(in && key == a.dead_key));
+                }
             }
             // births of this round, staged in slot order
             const unsigned long long bm = __ballot(born);
@@ -448,6 +481,8 @@ void launch_particles(pic_handle* h, int sp, bool emit_keys) {
     a.key1 = (uint32_t)(h->cfg.run.seed >> 32);
     a.step = (uint32_t)(h->step + 1);
     a.keys = emit_keys ? (sp == 0 ? h->keys[0] : h->keys_ion) : nullptr;
+    a.sink = h->sink;
+    a.ksink = h->ksink;
     a.dead_key = (uint32_t)h->ntiles;
     a.ntr = h->ntr;
     const dim3 grid(grid_blocks(h, sp)), block(kPushBlock);

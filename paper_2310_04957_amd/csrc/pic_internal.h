@@ -129,6 +129,8 @@ struct pic_handle {
     pic::tkey_t* keys[2];
     uint32_t* idx[2];
     pic::tkey_t* keys_ion;    // the ions' sort keys, written by the ion step before their sort
+    pic::Species sink;               // 64 slots the particle kernel's lanes past the last slot write
+    pic::tkey_t* ksink;              // 64 keys likewise
     uint32_t* perm[2];        // per species: the permutation of the last sort
     bool pending[2];          // a sort whose particle movement is still to be applied
     uint32_t* hist;
