@@ -196,8 +196,9 @@ __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4)))
     const Geo& g = a.g;
     const long long n = a.ctr->n_slots[a.sp];
     const long long nch = (n + kPushChunk - 1) / kPushChunk;
-    // a block takes chunks blockIdx.x, + gridDim.x, ... (one chunk with the
-    // launch below)
+    // one block per chunk: the grid has ceil(capacity / chunk) blocks and
+    // n never exceeds the capacity (a single pass rather than a loop over
+    // chunks, so nothing of the setup below is kept live across one)
     const Species& f = a.f;
     constexpr bool moved = kMoved;
     unsigned int fallback = 0;
@@ -208,8 +209,7 @@ __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4)))
     if (tid < 4) s_coll[tid] = 0u;
     if (tid == 0) s_fallback = 0u;
 
-    // the window stays in LDS while consecutive chunks share its origin and
-    // is flushed to the global grid (64-bit atomics) when the origin moves
+    // the window's deposits go to the global grid (64-bit atomics) at the end
     int wi0 = -(1 << 28), wj0 = -(1 << 28);
     bool vac = false, have = false;
     auto flush = [&]() {
@@ -225,8 +225,13 @@ __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4)))
         __syncthreads();
     };
 
-    for (long long chunk = blockIdx.x; chunk < nch; chunk += gridDim.x) {
+    if (blockIdx.x < nch) {
+        const long long chunk = blockIdx.x;
         const long long base = chunk * kPushChunk;
+        // this wavefront's slice, whose first round is requested before the
+        // window is probed and filled (its latency overlaps theirs)
+        const long long sbase = base + (long long)wave * kSlice;
+        P9 cur = load_slot<kMoved>(f, a.src, a.perm, sbase + lane, n);
         // LDS window origin: tile of a live particle from the middle of the
         // chunk (else from its start), plus halo.  Sorted chunks that span
         // several tiles then keep both ends inside the window.
@@ -253,30 +258,47 @@ __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4)))
             if (first < 0 && lane == 0) { s_org[0] = -(1 << 28); s_org[1] = -(1 << 28); }
         }
         __syncthreads();
-        if (!have || s_org[0] != wi0 || s_org[1] != wj0) {
-            if (have) flush();
+        {
             wi0 = s_org[0];
             wj0 = s_org[1];
             have = true;
             // the window's copies of E, of the radial factors and of the
             // cell kinds (zero outside the domain); are all its domain
-            // cells vacuum?
-            for (int k = tid; k < kWin * kWin; k += kPushBlock) {
+            // cells vacuum?  A thread requests all its values before it
+            // stores the first, so their latencies overlap.
+            constexpr int kNE = (kWin * kWin + kPushBlock - 1) / kPushBlock;
+            constexpr int kNC = ((kWin - 1) * (kWin - 1) + kPushBlock - 1) / kPushBlock;
+            static_assert(kWin <= kPushBlock, "one radial factor per thread");
+            float2 ev[kNE];
+            uint32_t cv[kNC];
+            double dv = 0.0;
+#pragma unroll
+            for (int q = 0; q < kNE; ++q) {
+                const int k = tid + q * kPushBlock;
                 const int gi = wi0 + k % kWin, gj = wj0 + k / kWin;
-                ewin[k] = (gi >= 0 && gi <= g.nr && gj >= 0 && gj <= g.nz) ? a.E[gj * g.w + gi]
-                                                                           : make_float2(0.0f, 0.0f);
+                ev[q] = make_float2(0.0f, 0.0f);
+                if (k < kWin * kWin && gi >= 0 && gi <= g.nr && gj >= 0 && gj <= g.nz) ev[q] = a.E[gj * g.w + gi];
             }
-            for (int k = tid; k < kWin; k += kPushBlock) {
-                const int gi = wi0 + k;
-                s_invd[k] = (gi >= 0 && gi < g.nr) ? g.invd[gi] : 0.0;
-            }
-            bool cells_ok = true;
-            for (int k = tid; k < (kWin - 1) * (kWin - 1); k += kPushBlock) {
+#pragma unroll
+            for (int q = 0; q < kNC; ++q) {
+                const int k = tid + q * kPushBlock;
                 const int ci = wi0 + k % (kWin - 1), cj = wj0 + k / (kWin - 1);
-                const uint8_t ck = (ci >= 0 && ci < g.nr && cj >= 0 && cj < g.nz) ? g.cell_kind[cj * g.nr + ci] : 0;
-                s_ck[k] = ck;
-                if (ck != 0) cells_ok = false;
+                cv[q] = 0u;
+                if (k < (kWin - 1) * (kWin - 1) && ci >= 0 && ci < g.nr && cj >= 0 && cj < g.nz)
+                    cv[q] = g.cell_kind[cj * g.nr + ci];
             }
+            if (tid < kWin && wi0 + tid >= 0 && wi0 + tid < g.nr) dv = g.invd[wi0 + tid];
+#pragma unroll
+            for (int q = 0; q < kNE; ++q)
+                if (tid + q * kPushBlock < kWin * kWin) ewin[tid + q * kPushBlock] = ev[q];
+            if (tid < kWin) s_invd[tid] = dv;
+            bool cells_ok = true;
+#pragma unroll
+            for (int q = 0; q < kNC; ++q)
+                if (tid + q * kPushBlock < (kWin - 1) * (kWin - 1)) {
+                    s_ck[tid + q * kPushBlock] = (uint8_t)cv[q];
+                    if (cv[q] != 0u) cells_ok = false;
+                }
             vac = __syncthreads_and(cells_ok) != 0;
         }
 
@@ -289,10 +311,8 @@ __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4)))
         const float fxlo = (float)(wi0 + 1), fxhi = (float)min(wi0 + kWin - 2, g.nr - 1);
         const float fylo = (float)max(wj0 + 1, 1), fyhi = (float)min(wj0 + kWin - 2, g.nz - 1);
 
-        const long long sbase = base + (long long)wave * kSlice;
         const long long stage_row = chunk * kPushWaves + wave;
         int nb = 0;
-        P9 cur = load_slot<kMoved>(f, a.src, a.perm, sbase + lane, n);
 
         uint4 dec4 = make_uint4(0u, 0u, 0u, 0u);
         for (int it = 0; it < kRounds; ++it) {
@@ -402,8 +422,6 @@ __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4)))
             cur = nxt;
         }
         if (lane == 0 && a.stage_cnt != nullptr) a.stage_cnt[stage_row] = min(nb, a.stage_w);
-        // s_org is rewritten by the next chunk's probe
-        __syncthreads();
     }
     if (have) flush();
     for (int o = 32; o > 0; o >>= 1) fallback += __shfl_down(fallback, o);
