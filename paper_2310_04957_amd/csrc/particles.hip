@@ -135,13 +135,6 @@ __device__ __forceinline__ unsigned int deposit(const Geo& g, const Loc& L, floa
     return 1u;
 }
 
-// the step's store of the two vector groups (the weight does not change
-// within a step), streaming past the caches
-__device__ __forceinline__ void store8(const Species& f, uint32_t p, const P9& s) {
-    __builtin_nontemporal_store(group_a(s), &f.a[p]);
-    __builtin_nontemporal_store(group_b(s), &f.b[p]);
-}
-
 // slot p of this step: in place, or through the permutation of a deferred
 // sort.  Unconditional (no branch, so the loads stay where they are
 // issued): a slot beyond the last, n - 1, is read in its place and the
@@ -160,12 +153,6 @@ __device__ __forceinline__ P9 load_slot(const Species& f, const Species& src, co
     s.vz = y.x; s.ar = y.y; s.at = y.z; s.az = y.w;
     s.w = __builtin_nontemporal_load(&f.w[q]);
     return s;
-}
-
-// after a deferred sort the weight moves to the new buffer too
-__device__ __forceinline__ void store_slot(const Species& f, uint32_t p, const P9& s, bool moved) {
-    store8(f, p, s);
-    if (moved) __builtin_nontemporal_store(s.w, &f.w[p]);
 }
 
 // One time step for every particle of one species.  A block of eight
@@ -231,7 +218,17 @@ __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4)))
         // this wavefront's slice, whose first round is requested before the
         // window is probed and filled (its latency overlaps theirs)
         const long long sbase = base + (long long)wave * kSlice;
+        // this lane's slot in round r (after the last round the last one's,
+        // beyond the last slot the last slot: read and ignored)
+        auto slot_in = [&](int r) -> long long {
+            const long long q = sbase + (long long)min(r, kRounds - 1) * 64 + lane;
+            return q < n ? q : n - 1;
+        };
         P9 cur = load_slot<kMoved>(f, a.src, a.perm, sbase + lane, n);
+        // after a deferred sort: the permutation entry of the next round,
+        // requested a round ahead of the state it points to (waiting for it
+        // then waits for nothing issued since)
+        uint32_t pq_next = kMoved ? a.perm[slot_in(1)] : 0u;
         // LDS window origin: tile of a live particle from the middle of the
         // chunk (else from its start), plus halo.  Sorted chunks that span
         // several tiles then keep both ends inside the window.
@@ -336,7 +333,14 @@ __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4)))
             }
             // the next round's state is requested here and pinned by a
             // scheduling barrier, so its latency hides behind this round
-            const P9 nxt = load_slot<kMoved>(f, a.src, a.perm, it + 1 < kRounds ? p + 64 : p, n);
+            uint32_t pq_after = 0u;
+            P9 nxt;
+            if (kMoved) {
+                pq_after = a.perm[slot_in(it + 2)];
+                nxt = load9(a.src, pq_next);
+            } else {
+                nxt = load_slot<false>(f, a.src, a.perm, it + 1 < kRounds ? p + 64 : p, n);
+            }
             __builtin_amdgcn_sched_barrier(0);
             // decision words of this lane's slots in rounds it .. it+3 (sbase is
             // a multiple of 256, so the four share one counter)
@@ -394,14 +398,20 @@ __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4)))
             // them stay in flight.
             {
                 const bool in = p < n;
-                const Species& dst = in ? f : a.sink;
-                const uint32_t q = in ? (uint32_t)p : (uint32_t)lane;
-                store_slot(dst, q, s, moved);
+                // (a choice between two computed addresses: a choice between
+                // the arrays' pointers becomes a per-lane load of the pointer)
+                auto pick = [&](auto* base, auto* sink) {
+                    return reinterpret_cast<decltype(base)>(in ? reinterpret_cast<uintptr_t>(base + p)
+                                                               : reinterpret_cast<uintptr_t>(sink + lane));
+                };
+                __builtin_nontemporal_store(group_a(s), pick(f.a, a.sink.a));
+                __builtin_nontemporal_store(group_b(s), pick(f.b, a.sink.b));
+                if (moved) __builtin_nontemporal_store(s.w, pick(f.w, a.sink.w));
                 // the key of the tile sort that follows: the tile of the
                 // predicted position, or the dead key (as the key pass
                 // computes it)
                 if (kKeys) {
-                    (in ? a.keys : a.ksink)[q] = (tkey_t)key;
+                    *pick(a.keys, a.ksink) = (tkey_t)key;
                     ndead += __popcll(__ballot(in && key == a.dead_key));
                 }
             }
@@ -420,6 +430,7 @@ __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4)))
             }
             nb += __popcll(bm);
             cur = nxt;
+            pq_next = pq_after;
         }
         if (lane == 0 && a.stage_cnt != nullptr) a.stage_cnt[stage_row] = min(nb, a.stage_w);
     }
