@@ -183,11 +183,16 @@ __device__ __forceinline__ unsigned long long lanemask_lt_s() {
 
 // peers of a lane: the valid lanes of its wavefront holding the same digit
 __device__ __forceinline__ unsigned long long digit_peers(bool valid, uint32_t d) {
-    unsigned long long peers = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-        const unsigned long long m = __ballot((d >> b) & 1u);
-        peers &= ((d >> b) & 1u) ? m : ~m;
+    // one ballot per distinct digit present in the wavefront (a few: the
+    // keys are nearly sorted), taking the digits in the order of their
+    // first lane
+    unsigned long long left = __ballot(valid), peers = 0ull;
+    while (left) {
+        const uint32_t d0 = __builtin_amdgcn_readlane(d, __ffsll((long long)left) - 1);
+        const bool same = valid && d == d0;
+        const unsigned long long m = __ballot(same);
+        if (same) peers = m;
+        left &= ~m;
     }
     return peers;
 }
