@@ -27,7 +27,7 @@ HBM_PEAK_GBS = 8000.0
 # ion sort).  The counters include lines served by the 256 MB last-level
 # cache.  A workload is left out (traffic null) whenever the kernel changes,
 # until it is measured again.
-MEASURED_BYTES_PER_PARTICLE_STEP = {"gec1024x2048": 87.2}
+MEASURED_BYTES_PER_PARTICLE_STEP = {"gec1024x2048": 87.0}
 
 
 def cpu_baseline(name, sample_particles, steps):
