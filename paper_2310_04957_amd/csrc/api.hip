@@ -274,6 +274,18 @@ int upload_geometry(pic_handle* h) {
     for (int i = 0; i < h->nr; ++i) invd[i] = std::ldexp(1.0, -2 * kFBits) / (double)(2 * i + 1);
     hipStream_t s = h->stream;
     HIP_OK(hipMemcpyAsync(h->cell_kind, h->h_cell_kind.data(), h->h_cell_kind.size(), hipMemcpyHostToDevice, s));
+    // tiles whose cells are all vacuum (the particle kernel answers the
+    // absorption test of a cell outside its window from this bitmap)
+    std::vector<uint32_t> vt(kVacWords, 0u);
+    for (int t = 0; t < std::min(h->ntiles, 32 * kVacWords); ++t) {
+        const int ti = t % h->ntr, tj = t / h->ntr;
+        bool vac = true;
+        for (int j = tj * kTile; j < std::min((tj + 1) * kTile, h->nz) && vac; ++j)
+            for (int i = ti * kTile; i < std::min((ti + 1) * kTile, h->nr); ++i)
+                if (h->h_cell_kind[(size_t)j * h->nr + i] != 0) { vac = false; break; }
+        if (vac) vt[t >> 5] |= 1u << (t & 31);
+    }
+    HIP_OK(hipMemcpyAsync(h->vac_tiles, vt.data(), vt.size() * 4, hipMemcpyHostToDevice, s));
     HIP_OK(hipMemcpyAsync(h->node_kind, h->h_node_kind.data(), h->h_node_kind.size(), hipMemcpyHostToDevice, s));
     HIP_OK(hipMemcpyAsync(h->vol, h->h_vol.data(), h->h_vol.size() * 8, hipMemcpyHostToDevice, s));
     HIP_OK(hipMemcpyAsync(h->gr, h->h_gr.data(), h->h_gr.size() * 8, hipMemcpyHostToDevice, s));
@@ -348,6 +360,7 @@ size_t layout(pic_handle* h, char* base) {
     Carver c{base};
     const size_t nn = (size_t)h->nn, nc = (size_t)h->ncell;
     h->cell_kind = c.take<uint8_t>(nc);
+    h->vac_tiles = c.take<uint32_t>(kVacWords);
     h->node_kind = c.take<int8_t>(nn);
     h->vol = c.take<double>(nn);
     h->gr = c.take<double>(nn);

@@ -56,11 +56,13 @@ __device__ __forceinline__ double radial_factor(int i) {
 // Charge of a removed particle: to the conductor it hit, or deposited at the
 // landing point into the dielectric surface-charge grid (the share on
 // conductor nodes goes to that conductor).  Returns true if removed.
-// Cell kinds come from the window's LDS copy s_ck when the cell lies in it.
+// Cell kinds come from the window's LDS copy s_ck when the cell lies in it,
+// else from the LDS copy s_vt of the all-vacuum tile bitmap when that marks
+// the cell's tile, else from the global grid.
 template <int kWin>
 __device__ __forceinline__ bool absorb(const Geo& g, const Loc& L, float w, int sign,
                                        unsigned long long* s_abs, unsigned long long* wallq, bool vac, int wi0,
-                                       int wj0, const uint8_t* s_ck) {
+                                       int wj0, const uint8_t* s_ck, const uint32_t* s_vt) {
     if (!L.inside) {
         // (a select of the three, not an indexed read of the argument block,
         // which would be a vector memory load)
@@ -80,6 +82,10 @@ __device__ __forceinline__ bool absorb(const Geo& g, const Loc& L, float w, int 
     // 256-byte-padded buffer, which also keeps the compiler from merging
     // the two reads into one generic-address load)
     if (!inw) {
+        // a vacuum tile needs no global read (whose wait would also wait
+        // for the next round's state, in flight)
+        const int t = (L.j >> kTileShift) * g.ntr + (L.i >> kTileShift);
+        if (t < 32 * kVacWords && ((s_vt[t >> 5] >> (t & 31)) & 1u)) return false;
         const uint32_t c = (uint32_t)(L.j * g.nr + L.i);
         const uint32_t wd = *reinterpret_cast<const uint32_t*>(g.cell_kind + (c & ~3u));
         ck = (int)((wd >> (8u * (c & 3u))) & 0xFFu);
@@ -174,6 +180,7 @@ __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4)))
     __shared__ float2 ewin[kWin * kWin];
     __shared__ double s_invd[kWin];
     __shared__ uint8_t s_ck[(kWin - 1) * (kWin - 1)];
+    __shared__ uint32_t s_vt[kVacWords];
     __shared__ int s_org[2];
     __shared__ unsigned long long s_abs[kSlots];
     __shared__ unsigned int s_coll[4];
@@ -285,10 +292,13 @@ __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4)))
                     cv[q] = g.cell_kind[cj * g.nr + ci];
             }
             if (tid < kWin && wi0 + tid >= 0 && wi0 + tid < g.nr) dv = g.invd[wi0 + tid];
+            static_assert(kVacWords <= kPushBlock, "one bitmap word per thread");
+            const uint32_t vtw = tid < kVacWords ? g.vac_tiles[tid] : 0u;
 #pragma unroll
             for (int q = 0; q < kNE; ++q)
                 if (tid + q * kPushBlock < kWin * kWin) ewin[tid + q * kPushBlock] = ev[q];
             if (tid < kWin) s_invd[tid] = dv;
+            if (tid < kVacWords) s_vt[tid] = vtw;
             bool cells_ok = true;
 #pragma unroll
             for (int q = 0; q < kNC; ++q)
@@ -363,7 +373,7 @@ __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4)))
                 bool gone = false;
                 if (!(vac && cx >= fxlo && cx < fxhi && cy >= fylo && cy < fyhi)) {
                     const Loc L = locate(s.r, s.z, g);
-                    gone = absorb<kWin>(g, L, s.w, a.sign, s_abs, a.wallq, vac, wi0, wj0, s_ck);
+                    gone = absorb<kWin>(g, L, s.w, a.sign, s_abs, a.wallq, vac, wi0, wj0, s_ck, s_vt);
                 }
                 if (gone) {
                     s.r = -1.0f;
@@ -382,7 +392,7 @@ __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4)))
                     }
                     d1_predict(s, a.dt);
                     const Loc L2 = locate(s.r, s.z, g);
-                    if (absorb<kWin>(g, L2, s.w, a.sign, s_abs, a.wallq, vac, wi0, wj0, s_ck)) {
+                    if (absorb<kWin>(g, L2, s.w, a.sign, s_abs, a.wallq, vac, wi0, wj0, s_ck, s_vt)) {
                         s.r = -1.0f;
                     } else {
                         fallback += deposit<kWin>(g, L2, s.w, win, s_invd, wi0, wj0, a.dep);
@@ -462,6 +472,8 @@ static Geo make_geo(pic_handle* h) {
     g.inv_dr = (float)(1.0 / h->dr); g.inv_dz = (float)(1.0 / h->dz);
     g.invd = h->invd;
     g.cell_kind = h->cell_kind;
+    g.vac_tiles = h->vac_tiles;
+    g.ntr = h->ntr;
     g.node_kind = h->node_kind;
     for (int k = 0; k < 3; ++k) g.edge_bc[k] = h->cfg.geom.edge_bc[k];
     return g;

@@ -14,6 +14,7 @@ constexpr int kFBits = 20;        // fraction bits of a fixed-point position (pe
 constexpr int kKBits = 32;        // fraction bits of a deposited weight
 constexpr int kTileShift = 4;     // sort / LDS tiles of 16 x 16 cells
 constexpr int kTile = 1 << kTileShift;
+constexpr int kVacWords = 256;    // bitmap of all-vacuum tiles: the first 32 kVacWords tiles
 constexpr uint32_t kDeadKey = 0xFFFFFFFFu;
 
 // Geometry as the particle kernels see it.
@@ -23,6 +24,8 @@ struct Geo {
     float inv_dr, inv_dz;
     const double* invd;           // 2^-2F / (2i + 1), i < nr
     const uint8_t* cell_kind;     // 0 vacuum, 1 dielectric, 2 + id conductor
+    const uint32_t* vac_tiles;    // bit t: every cell of tile t is vacuum (tiles < 32 kVacWords)
+    int ntr;                      // tiles per row
     const int8_t* node_kind;      // -1 unknown, >= 0 conductor id
     int edge_bc[3];               // r=R, z=0, z=Z
 };

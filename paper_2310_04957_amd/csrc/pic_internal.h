@@ -118,6 +118,7 @@ struct pic_handle {
     int stage_w;                  // births per staging row
     // geometry (device)
     uint8_t* cell_kind;
+    uint32_t* vac_tiles;          // kVacWords words: bit t, every cell of tile t is vacuum
     int8_t* node_kind;
     double *vol, *gr, *gz, *invd;
     std::vector<int8_t> h_node_kind;
