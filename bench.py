@@ -444,7 +444,7 @@ def main():
         print(json.dumps({"c4": c4_protocol(args)}))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
+        print(json.dumps({"error": "the benchmark runs on one GPU; multi-GPU runs are not implemented",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 

@@ -115,7 +115,7 @@ def _gpu_mean(w, steps, periods, seeds):
 
 @pytest.mark.timeout(900)
 def test_parallel_plate_means_within_one_percent():
-    """The benchmark spec's bar, shown: eight GPU runs against eight oracle runs
+    """Ensemble agreement within 1%: eight GPU runs against eight oracle runs
     (seeds 1..8) of the 32x24 parallel-plate discharge with 200k + 200k
     particles, 2000 steps, densities and current harmonics averaged over the
     last five RF periods.  The ensemble means differ by at most 1%: the L2
