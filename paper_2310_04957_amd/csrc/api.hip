@@ -151,8 +151,23 @@ void derive(pic_handle* h) {
     h->ntr = (h->nr + kTile - 1) / kTile;
     h->ntz = (h->nz + kTile - 1) / kTile;
     h->ntiles = h->ntr * h->ntz;
+    // tile keys ty kmul + tx, the dead key ntz kmul after them: kmul the
+    // tiles per row rounded up to a power of two 2^row_bits when the tile
+    // column and the tile row (dead key included) each fit one 8-bit radix
+    // digit, so each pass sorts one coordinate (a wavefront of nearly sorted
+    // keys then holds few distinct digits); else the tiles per row, sorted in
+    // 8-bit digits.  The tile order, and so the sort, is the same.
+    int rb = 0;
+    while ((1 << rb) < h->ntr) ++rb;
+    if (rb >= 1 && rb <= 8 && h->ntz <= 255) {
+        h->kmul = 1 << rb;
+        h->row_bits = rb;
+    } else {
+        h->kmul = h->ntr;
+        h->row_bits = 0;
+    }
     int bits = 1;
-    while ((1u << bits) <= (unsigned)h->ntiles) ++bits;   // keys 0..ntiles (ntiles = dead)
+    while ((1u << bits) <= (unsigned)(h->ntz * h->kmul)) ++bits;   // keys 0 .. ntz kmul (dead)
     h->key_bits = bits;
     h->cap[0] = c.run.cap_e;
     h->cap[1] = c.run.cap_i;

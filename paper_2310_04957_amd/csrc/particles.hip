@@ -27,7 +27,7 @@ struct PushArgs {
     Species sink;                // 64 slots written by the lanes past the last slot
     tkey_t* ksink;               // 64 keys likewise
     uint32_t dead_key;
-    int ntr;
+    int kmul;                    // tile key multiplier
     const float2* E;
     unsigned long long* dep;
     unsigned long long* wallq;
@@ -397,7 +397,7 @@ __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4)))
                         s.r = -1.0f;
                     } else {
                         fallback += deposit<kWin>(g, L2, s.w, win, s_invd, wi0, wj0, a.dep);
-                        key = tile_key(L2, a.ntr);
+                        key = tile_key(L2, a.kmul);
                     }
                 }
             }
@@ -525,8 +525,8 @@ void launch_particles(pic_handle* h, int sp, bool emit_keys) {
     a.keys = emit_keys ? (sp == 0 ? h->keys[0] : h->keys_ion) : nullptr;
     a.sink = h->sink;
     a.ksink = h->ksink;
-    a.dead_key = (uint32_t)h->ntiles;
-    a.ntr = h->ntr;
+    a.dead_key = (uint32_t)(h->ntz * h->kmul);
+    a.kmul = h->kmul;
     const dim3 grid(grid_blocks(h, sp)), block(kPushBlock);
     if (sp == 0) {
         if (emit_keys) {

@@ -386,8 +386,10 @@ struct Birth {
     float r, z, w, v[6];
 };
 
-__device__ __forceinline__ uint32_t tile_key(const Loc& L, int ntr) {
-    return (uint32_t)((L.j >> kTileShift) * ntr + (L.i >> kTileShift));
+// sort key of a cell's tile: tile row times kmul plus tile column (kmul at
+// least the tiles per row, so keys follow the row-major tile order)
+__device__ __forceinline__ uint32_t tile_key(const Loc& L, int kmul) {
+    return (uint32_t)((L.j >> kTileShift) * kmul + (L.i >> kTileShift));
 }
 
 }  // namespace pic

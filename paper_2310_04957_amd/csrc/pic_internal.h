@@ -110,6 +110,7 @@ struct pic_handle {
     size_t ws_bytes;
     // derived constants
     int nr, nz, w, nn, ncell, ntr, ntz, ntiles, key_bits;
+    int kmul, row_bits;           // tile keys ty kmul + tx; row_bits > 0: kmul = 2^row_bits
     double dr, dz, dt, Sr, Sz, w_unit, n_gas, nu_max[2], vth_gas, qunit, chi_c[2];
     uint32_t thresh[2];
     int64_t cap[2];

@@ -22,7 +22,7 @@ struct KeyArgs {
     const long long* n_slots;
     const long long* start;   // non-null: keys below *start are already written
     unsigned int* dead;
-    int sp, ntr;
+    int sp, kmul;             // tile key multiplier
     uint32_t dead_key;
 };
 
@@ -36,7 +36,7 @@ __global__ __launch_bounds__(kBlock) void k_keys(KeyArgs a) {
         uint32_t key = a.dead_key;
         if (x.x >= 0.0f) {
             Loc L = locate(x.x, x.y, a.g);
-            if (L.inside) key = tile_key(L, a.ntr);
+            if (L.inside) key = tile_key(L, a.kmul);
         }
         dead += (key == a.dead_key);
         a.keys[p] = (tkey_t)key;
@@ -57,7 +57,7 @@ __device__ __forceinline__ void unpack8(const uint4 v, uint32_t* k) {
 // keys (the usual case between two sorts) then cost about one atomic per
 // thread instead of one per key on the same few bins.
 __global__ __launch_bounds__(kBlock) void k_hist(const tkey_t* keys, const long long* n_slots, int sp, int shift,
-                                                 uint32_t* hist) {
+                                                 uint32_t mask, uint32_t* hist) {
     __shared__ unsigned int h[256];
     const long long n = n_slots[sp];
     const long long nch = (n + kChunk - 1) / kChunk;
@@ -78,7 +78,7 @@ __global__ __launch_bounds__(kBlock) void k_hist(const tkey_t* keys, const long 
 #pragma unroll
         for (int q = 0; q < kItems; ++q) {
             if (q < cnt) {
-                const uint32_t d = (kv[q] >> shift) & 0xFFu;
+                const uint32_t d = (kv[q] >> shift) & mask;
                 if (run_n != 0u && d != run_d) {
                     atomicAdd(&h[run_d], run_n);
                     run_n = 0u;
@@ -204,7 +204,7 @@ __device__ __forceinline__ unsigned long long digit_peers(bool valid, uint32_t d
 // before it.  Ranks come from wavefront ballots, so the order is fixed.
 __global__ __launch_bounds__(kBlock) void k_scatter(const tkey_t* kin, const uint32_t* vin, tkey_t* kout,
                                                     uint32_t* vout, const uint32_t* offs, const long long* n_slots,
-                                                    int sp, int shift) {
+                                                    int sp, int shift, uint32_t mask) {
     __shared__ unsigned int wcnt[kWaves][256];
     __shared__ unsigned int wbase[kWaves][256];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -233,7 +233,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const tkey_t* kin, const uin
 #pragma unroll
             for (int q = 0; q < kItems; ++q) {
                 if (q < cnt) {
-                    const uint32_t d = (kv[q] >> shift) & 0xFFu;
+                    const uint32_t d = (kv[q] >> shift) & mask;
                     if (run_n != 0u && d != run_d) {
                         atomicAdd(&wcnt[wave][run_d], run_n);
                         run_n = 0u;
@@ -268,7 +268,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const tkey_t* kin, const uin
             const long long p = s0 + it * 64 + lane;
             const bool valid = p < n;
             const uint32_t key = kk[it];
-            const uint32_t d = (key >> shift) & 0xFFu;
+            const uint32_t d = (key >> shift) & mask;
             const unsigned long long peers = digit_peers(valid, d);
             const int rank = __popcll(peers & lanemask_lt_s());
             if (valid) {
@@ -330,21 +330,39 @@ void launch_sort(pic_handle* h, int sp, bool deferred, bool keyed) {
     // in their own (the radix passes then ping-pong with the second shared one)
     tkey_t* kb[2] = {sp == 0 ? h->keys[0] : h->keys_ion, h->keys[1]};
     ka.keys = kb[0];
-    ka.n_slots = ns; ka.dead = dead + sp; ka.sp = sp; ka.ntr = h->ntr;
+    ka.n_slots = ns; ka.dead = dead + sp; ka.sp = sp; ka.kmul = h->kmul;
     ka.start = keyed ? (const long long*)&h->ctr->n_keyed[sp] : nullptr;
-    ka.dead_key = (uint32_t)h->ntiles;   // one bucket past the last tile: sorts last
+    ka.dead_key = (uint32_t)(h->ntz * h->kmul);   // past the last tile's key: sorts last
     hipLaunchKernelGGL(k_keys, dim3(2048), dim3(kBlock), 0, st, ka);
+    // the passes' digits: the tile column, then the tile row (power-of-two
+    // key multiplier), else 8-bit digits
+    int pshift[3], pmask[3], np = 0;
+    if (h->row_bits > 0) {
+        pshift[0] = 0;
+        pmask[0] = (1 << h->row_bits) - 1;
+        pshift[1] = h->row_bits;
+        pmask[1] = 0xFF;
+        np = 2;
+    } else {
+        for (int sh = 0; sh < h->key_bits && np < 3; sh += 8) {
+            pshift[np] = sh;
+            pmask[np] = 0xFF;
+            ++np;
+        }
+    }
     int src = 0;
-    for (int shift = 0; shift < h->key_bits; shift += 8) {
+    for (int ip = 0; ip < np; ++ip) {
+        const int shift = pshift[ip];
+        const uint32_t mask = (uint32_t)pmask[ip];
         // the last pass writes the permutation to the species' own buffer
-        const bool last = shift + 8 >= h->key_bits;
-        hipLaunchKernelGGL(k_hist, dim3(2048), dim3(kBlock), 0, st, kb[src], ns, sp, shift, h->hist);
+        const bool last = ip + 1 == np;
+        hipLaunchKernelGGL(k_hist, dim3(2048), dim3(kBlock), 0, st, kb[src], ns, sp, shift, mask, h->hist);
         hipLaunchKernelGGL(k_scan_reduce, dim3(2048), dim3(kBlock), 0, st, h->hist, ns, sp, h->bsum);
         hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, h->bsum, ns, sp);
         hipLaunchKernelGGL(k_scan_down, dim3(2048), dim3(kBlock), 0, st, h->hist, h->bsum, ns, sp);
-        hipLaunchKernelGGL(k_scatter, dim3(2048), dim3(kBlock), 0, st, kb[src], shift == 0 ? nullptr : h->idx[src],
+        hipLaunchKernelGGL(k_scatter, dim3(2048), dim3(kBlock), 0, st, kb[src], ip == 0 ? nullptr : h->idx[src],
                            last ? nullptr : kb[1 - src],
-                           last ? h->perm[sp] : h->idx[1 - src], h->hist, ns, sp, shift);
+                           last ? h->perm[sp] : h->idx[1 - src], h->hist, ns, sp, shift, mask);
         src = 1 - src;
     }
     hipLaunchKernelGGL(k_finish_sort, dim3(1), dim3(1), 0, st, h->ctr->n_slots, dead, sp);
