@@ -91,8 +91,12 @@ def test_fused_step_deposit_and_charge_are_bit_exact():
     g.close(); g2.close()
 
 
-def test_sort_permutation_matches_stable_sort():
-    w = _small_gec(n=0, cap_e=50000, cap_i=50000)
+@pytest.mark.parametrize("nr", [64, 48, 16])
+def test_sort_permutation_matches_stable_sort(nr):
+    """Tile keys ty kmul + tx: 64 cells wide is 4 tiles per row (kmul = 4,
+    column and row digit passes), 48 is 3 (kmul = 4 > 3: keys skip a value
+    per row), 16 is one (kmul = 1, a single 8-bit digit pass)."""
+    w = _small_gec(nr=nr, n=0, cap_e=50000, cap_i=50000)
     gm = w["geometry"]
     g = _pic(w, load=False)
     o = O.Oracle(w, load=False)
