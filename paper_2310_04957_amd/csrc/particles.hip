@@ -235,7 +235,7 @@ __global__ __launch_bounds__(kPushBlock) __attribute__((amdgpu_waves_per_eu(4)))
         // after a deferred sort the permutation entries run two rounds
         // ahead: the entry of round r is requested in round r - 2, the state
         // it points to in round r - 1 (the wait for the entry then waits for
-        // nothing issued since); here the entry of round 1
+        // nothing issued since); here the entry of the second round (r = 1)
         uint32_t pq_next = kMoved ? a.perm[slot_in(1)] : 0u;
         // LDS window origin: tile of a live particle from the middle of the
         // chunk (else from its start), plus halo.  Sorted chunks that span
